@@ -1,0 +1,170 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws random numbers; it holds none of the method's
+arithmetic (no keys, boxes, ranges or distance tests).  Both the HIP path and
+the oracle consume the arrays it returns, byte for byte.
+
+Distributions:
+  * uniform points in [0,1)^2 (the paper's Uniform distribution, Sec. 3
+    "Data", rescaled from [0, 2^32) to [0,1));
+  * clustered points: a fraction ``frac`` (exactly floor(frac*n) points) from
+    an equal-weight mixture of ``k`` isotropic Gaussians with uniform centres
+    and standard deviation ``sigma``, the rest uniform, clamped to
+    [0, 1 - 2^-53] (the largest double below 1) and shuffled;
+  * query radii that aim at a given expected output size c: for a query at q
+    over n points of density f, delta = sqrt(c / (pi * n * f(q))), with c
+    log-uniform in [c_lo, c_hi].
+
+Generators are numpy PCG64 streams; every function takes an explicit seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+ONE_BELOW = float(np.nextafter(1.0, 0.0))   # 1 - 2^-53
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@dataclasses.dataclass(frozen=True)
+class Mixture:
+    """Clustered distribution: weight ``frac`` on k Gaussians, rest uniform."""
+    centres: np.ndarray      # (k, 2)
+    sigma: float
+    frac: float
+
+    def density(self, q: np.ndarray) -> np.ndarray:
+        """Analytic density of the (unclamped) mixture at the rows of q."""
+        q = np.asarray(q, np.float64)
+        k = self.centres.shape[0]
+        d2 = ((q[:, None, :] - self.centres[None, :, :]) ** 2).sum(-1)
+        g = np.exp(-d2 / (2.0 * self.sigma ** 2)) / (2.0 * math.pi * self.sigma ** 2)
+        return (1.0 - self.frac) + (self.frac / k) * g.sum(1)
+
+    def sample(self, n: int, rng: np.random.Generator) -> np.ndarray:
+        nc = (int(round(self.frac * 1000)) * n) // 1000   # floor(frac * n)
+        comp = rng.integers(0, self.centres.shape[0], nc)
+        pc = self.centres[comp] + self.sigma * rng.standard_normal((nc, 2))
+        pu = rng.random((n - nc, 2))
+        p = np.concatenate([pc, pu], axis=0)
+        np.clip(p, 0.0, ONE_BELOW, out=p)
+        return p[rng.permutation(n)]
+
+
+def uniform_points(n: int, seed: int) -> np.ndarray:
+    return _rng(seed).random((n, 2))
+
+
+def make_mixture(seed: int, k: int = 16, sigma: float = 0.01, frac: float = 0.8) -> Mixture:
+    return Mixture(centres=_rng(seed).random((k, 2)), sigma=sigma, frac=frac)
+
+
+def clustered_points(n: int, seed: int, mixture: Mixture) -> np.ndarray:
+    return mixture.sample(n, _rng(seed))
+
+
+def radius_for_count(c: float, n: int) -> float:
+    """delta with expected c reports per query over n uniform points."""
+    return math.sqrt(c / (math.pi * n))
+
+
+def loguniform(rng: np.random.Generator, lo: float, hi: float, size: int) -> np.ndarray:
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size))
+
+
+def density_radii(q: np.ndarray, n: int, seed: int, c_lo: float = 1.0, c_hi: float = 1000.0,
+                  mixture: Mixture | None = None) -> np.ndarray:
+    """delta per query such that the expected output is c ~ logU[c_lo, c_hi]
+    (density 1 when ``mixture`` is None)."""
+    rng = _rng(seed)
+    c = loguniform(rng, c_lo, c_hi, q.shape[0])
+    f = np.ones(q.shape[0]) if mixture is None else mixture.density(q)
+    return np.sqrt(c / (math.pi * n * f))
+
+
+# ---- named workloads --------------------------------------------------------
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    points: np.ndarray       # (n, 2) float64
+    queries: np.ndarray      # (m, 2) float64
+    delta: np.ndarray        # (m,) float64
+    curve: int               # 0 Z-order, 1 Hilbert
+
+
+def uniform_fixed_radius(n: int = 1 << 16, m: int = 10_000, curve: int = 0,
+                         expected: float = 10.0, seed: int = 1) -> Workload:
+    """Uniform points and queries, one radius giving ``expected`` reports."""
+    pts = uniform_points(n, 1000 + seed)
+    q = uniform_points(m, 2000 + seed)
+    d = np.full(m, radius_for_count(expected, n))
+    return Workload(f"uniform_n{n}_m{m}_fixed", pts, q, d, curve)
+
+
+def clustered_loguniform(n: int = 1 << 24, m: int = 1 << 20, curve: int = 1,
+                         seed: int = 2, c_lo: float = 1.0, c_hi: float = 1000.0) -> Workload:
+    """80% of the points from 16 Gaussians (sigma 0.01), 20% uniform; queries
+    from the same mixture; delta aimed at an output log-uniform in
+    [c_lo, c_hi]."""
+    mix = make_mixture(500 + seed)
+    pts = clustered_points(n, 1000 + seed, mix)
+    q = clustered_points(m, 2000 + seed, mix)
+    d = density_radii(q, n, 3000 + seed, c_lo, c_hi, mix)
+    return Workload(f"clustered_n{n}_m{m}_loguniform", pts, q, d, curve)
+
+
+def clustered_uniform_queries(n: int = 1 << 26, m: int = 1 << 22, curve: int = 0,
+                              seed: int = 3, expected: float = 10.0) -> Workload:
+    """Clustered points as above; uniform queries with one radius aimed at
+    ``expected`` reports at unit density."""
+    mix = make_mixture(500 + seed)
+    pts = clustered_points(n, 1000 + seed, mix)
+    q = uniform_points(m, 2000 + seed)
+    d = np.full(m, radius_for_count(expected, n))
+    return Workload(f"clustered_n{n}_m{m}_uniformq", pts, q, d, curve)
+
+
+@dataclasses.dataclass
+class BatchedWorkload:
+    name: str
+    points: np.ndarray       # (N, 2) concatenated
+    set_off: np.ndarray      # (S+1,) uint64
+    queries: np.ndarray      # (M, 2)
+    delta: np.ndarray        # (M,)
+    qset: np.ndarray         # (M,) uint32, queries grouped by set
+    curve: int
+
+
+def batched_uneven(n_sets: int = 256, log2_n: tuple = (10, 20), log2_m: tuple = (8, 16),
+                   curve: int = 0, seed: int = 4, c_lo: float = 1.0,
+                   c_hi: float = 1000.0) -> BatchedWorkload:
+    """Independent sets with sizes round(2^U[log2_n]) and query counts
+    round(2^U[log2_m]); each set uniform or clustered by a fair coin."""
+    rng = _rng(4000 + seed)
+    ns = np.rint(2.0 ** rng.uniform(*log2_n, n_sets)).astype(np.int64)
+    ms = np.rint(2.0 ** rng.uniform(*log2_m, n_sets)).astype(np.int64)
+    coin = rng.integers(0, 2, n_sets)
+    pts, qs, ds, qset = [], [], [], []
+    for s in range(n_sets):
+        if coin[s]:
+            mix = make_mixture(10_000 + 3 * s)
+            p = clustered_points(int(ns[s]), 10_001 + 3 * s, mix)
+            q = clustered_points(int(ms[s]), 10_002 + 3 * s, mix)
+        else:
+            mix = None
+            p = uniform_points(int(ns[s]), 10_001 + 3 * s)
+            q = uniform_points(int(ms[s]), 10_002 + 3 * s)
+        pts.append(p)
+        qs.append(q)
+        ds.append(density_radii(q, int(ns[s]), 20_000 + s, c_lo, c_hi, mix))
+        qset.append(np.full(int(ms[s]), s, np.uint32))
+    set_off = np.zeros(n_sets + 1, np.uint64)
+    set_off[1:] = np.cumsum(ns)
+    return BatchedWorkload(f"batched_{n_sets}sets", np.concatenate(pts), set_off,
+                           np.concatenate(qs), np.concatenate(ds), np.concatenate(qset), curve)
