@@ -208,6 +208,10 @@ def test_box_hand_values():
     assert oracle.box(0.0, 0.0, 0.0) == (0, 1, 0, 1)                  # clamped at 0
     assert oracle.box(5.0, 0.5, 1.0) is None                          # misses the domain
     assert oracle.box(-3.0, 0.5, 10.0) == (0, M32, 0, M32)
+    # Far query, huge radius: w = 1 + floor((|qx| + delta) 2^-19) = 129 quanta
+    # on the x axis; qx - delta = 1/2 + 2^-27 exactly.
+    qx = 2.0 ** 25 + 0.5 + 2.0 ** -27
+    assert oracle.box(qx, 0.5, 2.0 ** 25)[0] == 2 ** 31 + 32 - 129
 
 
 @pytest.mark.parametrize("bad", [(0.5, 0.5, -1e-9), (0.5, 0.5, float("nan")),
