@@ -1,0 +1,198 @@
+/*
+ * sfc.h -- C ABI of libsfc, exact distance reporting on MI355X (gfx950) by
+ * sorting points along a space-filling curve.
+ *
+ * Method: "Simpler is Faster: Practical Distance Reporting by Sorting Along a
+ * Space-Filling Curve" (arXiv 2508.19891).
+ *   - Problem (Sec. 2, Problem Statement): store a point set P; for a query
+ *     (q, delta) report every p in P with |p - q| <= delta (closed ball).
+ *   - Construction (Sec. 2.1, "Storing P twice"; Alg. 2; Def. 3): compute a
+ *     64-bit curve key per point (Z-order by bit interleaving, or Hilbert),
+ *     sort (key, id) pairs, keep the sorted keys beside the sorted points.
+ *   - Query (Alg. 1 with cells(Q) and the Observation): the bounding square of
+ *     the ball is covered by at most four quadtree cells of side in [s, 2s);
+ *     each cell is one contiguous key interval, located by search in the
+ *     sorted keys and scanned with the exact distance test.
+ *   - Dynamic setting (Sec. 2.1, "Dynamic implementation"): insertions and
+ *     deletions of points.
+ *
+ * Conventions shared by every entry point
+ *   - Coordinates are IEEE binary64 in [0,1)^2, stored interleaved
+ *     (x0, y0, x1, y1, ...).  Each axis maps to the 32-bit grid cell
+ *     floor(v * 2^32).
+ *   - The distance test is evaluated in binary64, round-to-nearest-even, with
+ *     no fused multiply-add, in this order:
+ *        dx = px-qx; dy = py-qy; t = dx*dx; u = dy*dy; s = t+u; r2 = d*d;
+ *        report iff s <= r2.
+ *   - Point ids are uint32: the index of the point in the build input, then
+ *     consecutive ids for inserted points.  At most 2^32 - 1 points.
+ *   - Pointers named "device" must be device memory of the current HIP device
+ *     (hipMalloc / torch CUDA tensors); "host" pointers are host memory.  The
+ *     caller owns every buffer it passes; the index owns its own arrays.
+ *   - All work is ordered on the stream given in sfc_options.  Calls that
+ *     return a count to the host synchronise that stream before returning.
+ *   - Out-parameters are written only when the call returns SFC_OK, unless an
+ *     entry point says otherwise.  No C++ exception crosses this interface.
+ *   - A handle must not be used by two calls at once.  Distinct handles are
+ *     independent.
+ */
+#ifndef SFC_H_
+#define SFC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfc_index sfc_index; /* opaque; owns its device arrays */
+
+typedef enum {
+  SFC_OK = 0,
+  SFC_ERR_INVALID = -1,  /* NULL pointer, size out of range, bad option, or a
+                            query with delta < 0 or a non-finite value */
+  SFC_ERR_DOMAIN = -2,   /* a point coordinate outside [0,1) (or NaN) */
+  SFC_ERR_NOMEM = -3,    /* a device allocation failed; state unchanged */
+  SFC_ERR_CAPACITY = -4, /* output buffer too small; see sfc_query_batch */
+  SFC_ERR_DEVICE = -5,   /* a HIP runtime error */
+  SFC_ERR_UNSUPPORTED = -6
+} sfc_status;
+
+enum { SFC_CURVE_MORTON = 0, SFC_CURVE_HILBERT = 1 };
+enum { SFC_SEARCH_BINARY = 0, SFC_SEARCH_LEARNED = 1 };
+
+typedef struct {
+  int curve;    /* SFC_CURVE_MORTON (Alg. 2) or SFC_CURVE_HILBERT */
+  int search;   /* SFC_SEARCH_BINARY; SFC_SEARCH_LEARNED fits the learned
+                   index at build time (binary search stays the fallback) */
+  void* stream; /* hipStream_t, NULL = the null stream */
+  /* Device memory hooks; alloc == NULL uses the library's caching pool over
+     hipMalloc.  alloc returns NULL on failure.  release(NULL, ctx) is never
+     called. */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*release)(void* ptr, void* ctx);
+  void* alloc_ctx;
+} sfc_options;
+
+/* Fills *opt with Morton curve, binary search, null stream, the pool. */
+void sfc_default_options(sfc_options* opt);
+
+/* Human-readable name of a status code (static string). */
+const char* sfc_status_string(sfc_status s);
+
+/*
+ * Build the index of n points (Sec. 2.1; Alg. 2; Def. 3).
+ *   xy      device, 2*n doubles, interleaved, each in [0,1).
+ *   n       number of points, 0 <= n <= 2^32 - 1.
+ *   opt     options (curve, search, stream, allocator); NULL = defaults.
+ *   out     host; receives the new handle on SFC_OK.
+ * Keys: each coordinate is quantised to floor(v * 2^32); Morton puts x's
+ * bit i at key bit 2i and y's at 2i+1; Hilbert follows the four-state
+ * Hilbert order starting at (0,0) and ending at (2^32-1, 0), most significant
+ * level first.  The points are then sorted by (key, id): ties keep input
+ * order.  Errors: SFC_ERR_INVALID (NULL xy with n > 0, NULL out, bad option),
+ * SFC_ERR_DOMAIN (a coordinate outside [0,1)), SFC_ERR_NOMEM, SFC_ERR_DEVICE.
+ * On error nothing is allocated and *out is not written.  Synchronises the
+ * stream.
+ */
+sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt,
+                     sfc_index** out);
+
+/*
+ * Batched distance queries (Alg. 1; Problem Statement).
+ *   q         device, 2*m doubles (qx, qy interleaved); q may lie anywhere.
+ *   delta     device, m doubles, each finite and >= 0.
+ *   m         number of queries.
+ *   offsets   device, m+1 uint64: CSR row starts; offsets[m] = total.
+ *   ids       device, ids_cap uint32: the reported point ids.  Within a query
+ *             they come in curve order (ascending key, ties by id).
+ *   ids_cap   capacity of ids in elements.
+ *   total_out host; receives the number of reported ids.
+ * If total > ids_cap the call returns SFC_ERR_CAPACITY after writing offsets
+ * and *total_out; only the first ids_cap ids are written then.  A query with
+ * delta < 0 or a non-finite value makes the call return SFC_ERR_INVALID with
+ * offsets and ids unspecified.  Synchronises the stream.
+ */
+sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta,
+                           uint64_t m, uint64_t* offsets, uint32_t* ids,
+                           uint64_t ids_cap, uint64_t* total_out);
+
+/* Number of points currently reported by queries (live points). */
+uint64_t sfc_size(const sfc_index* h);
+
+/*
+ * Read-only view of the sorted construction (for inspection and tests).
+ *   keys  device, n uint64 curve keys, ascending.
+ *   ids   device, n uint32 point ids in the same order.
+ *   xy    device, 2*n doubles, the points in the same order.
+ * The pointers stay valid until the next call that modifies the handle.
+ */
+sfc_status sfc_index_view(const sfc_index* h, const uint64_t** keys,
+                          const uint32_t** ids, const double** xy,
+                          uint64_t* n);
+
+/* Copies the sorted construction into caller buffers (device memory, sized
+   as in sfc_index_view; any pointer may be NULL).  Stream-ordered; waits for
+   the copies before returning. */
+sfc_status sfc_index_copy(const sfc_index* h, uint64_t* keys, uint32_t* ids, double* xy);
+
+/*
+ * Curve keys only (the first step of the construction), no sort.
+ *   xy device 2*n doubles; keys device n uint64; curve as in sfc_options.
+ * Errors: SFC_ERR_INVALID, SFC_ERR_DOMAIN, SFC_ERR_DEVICE.  Synchronises the
+ * stream.
+ */
+sfc_status sfc_keys(const double* xy, uint64_t n, int curve, void* stream,
+                    uint64_t* keys);
+
+/*
+ * Key ranges and index ranges of queries (cells(Q) and the binary searches of
+ * Alg. 1), four slots per query.  Slot r < nranges[j] of query j holds the
+ * r-th merged key interval [key_lo, key_hi] (inclusive, ascending) and its
+ * index range [begin, end) in the sorted keys.  Unused slots hold zeros.
+ *   q, delta        device, as in sfc_query_batch.
+ *   key_lo, key_hi  device, 4*m uint64.
+ *   begin, end      device, 4*m uint64.
+ *   nranges         device, m uint32 (0 when the box misses [0,1)^2).
+ * Errors: SFC_ERR_INVALID for a bad query.  Synchronises the stream.
+ */
+sfc_status sfc_query_ranges(sfc_index* h, const double* q, const double* delta,
+                            uint64_t m, uint64_t* key_lo, uint64_t* key_hi,
+                            uint64_t* begin, uint64_t* end, uint32_t* nranges);
+
+/* Counters of the last sfc_query_batch on h. */
+typedef struct {
+  uint64_t queries;
+  uint64_t ranges;      /* non-empty key ranges searched */
+  uint64_t candidates;  /* points scanned (sum of index range lengths) */
+  uint64_t reported;    /* ids reported */
+} sfc_query_stats;
+sfc_status sfc_last_query_stats(const sfc_index* h, sfc_query_stats* out);
+
+/* Frees the handle and its device memory (NULL-safe).  Waits for the
+   handle's stream first. */
+void sfc_free(sfc_index* h);
+
+/*
+ * Kernel timing.  While enabled, every kernel launch of the library is
+ * bracketed by two HIP events recorded on the stream it is launched on.
+ * sfc_profile_read synchronises those events and returns, per kernel name,
+ * the number of launches and the summed duration in milliseconds.
+ *   names   host, array of max pointers to static strings (may be NULL).
+ *   launches, ms  host arrays of max entries (may be NULL).
+ * Returns the number of distinct kernels seen (which may exceed max).
+ */
+void sfc_profile_enable(int on);
+void sfc_profile_reset(void);
+int sfc_profile_read(const char** names, uint64_t* launches, double* ms,
+                     int max);
+
+/* Releases the cached device blocks of the library's allocation pool. */
+void sfc_pool_trim(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFC_H_ */

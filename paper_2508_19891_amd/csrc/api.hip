@@ -1,0 +1,497 @@
+// C ABI of libsfc: handle management, device memory, kernel timing, and the
+// host-side sequencing of the construction and query kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+#include "sfc.h"
+
+// ---- caching device allocator -----------------------------------------------
+
+namespace sfc {
+namespace {
+
+// Blocks are kept per device and rounded size; a released block is reused by
+// the next request of the same rounded size.  Every call of the library
+// synchronises its stream before it returns a block, so reuse never overlaps
+// work in flight.
+struct Pool {
+  std::mutex mu;
+  std::map<std::pair<int, size_t>, std::vector<void*>> free_blocks;
+  std::map<void*, std::pair<int, size_t>> live;
+};
+Pool& pool() {
+  static Pool* p = new Pool();
+  return *p;
+}
+
+size_t round_size(size_t b) {
+  const size_t g = b <= (1u << 20) ? 256 : (size_t)2 << 20;
+  return (b + g - 1) / g * g;
+}
+
+}  // namespace
+
+void* Allocator::get(size_t bytes) const {
+  if (bytes == 0) bytes = 256;
+  if (alloc) return alloc(bytes, ctx);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  const size_t r = round_size(bytes);
+  Pool& P = pool();
+  {
+    std::lock_guard<std::mutex> g(P.mu);
+    auto it = P.free_blocks.find({dev, r});
+    if (it != P.free_blocks.end() && !it->second.empty()) {
+      void* ptr = it->second.back();
+      it->second.pop_back();
+      P.live[ptr] = {dev, r};
+      return ptr;
+    }
+  }
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, r) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(P.mu);
+  P.live[ptr] = {dev, r};
+  return ptr;
+}
+
+void Allocator::put(void* ptr) const {
+  if (!ptr) return;
+  if (release) {
+    release(ptr, ctx);
+    return;
+  }
+  Pool& P = pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  auto it = P.live.find(ptr);
+  if (it == P.live.end()) return;
+  P.free_blocks[it->second].push_back(ptr);
+  P.live.erase(it);
+}
+
+// ---- kernel timing ----------------------------------------------------------
+
+namespace {
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> spare;
+  std::map<std::string, std::pair<uint64_t, double>> acc;
+  std::vector<std::string> order;
+};
+ProfState& prof() {
+  static ProfState* p = new ProfState();
+  return *p;
+}
+hipEvent_t take_event(ProfState& P) {
+  if (!P.spare.empty()) {
+    hipEvent_t e = P.spare.back();
+    P.spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s) {
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  if (!P.on) return;
+  hipEvent_t e = take_event(P);
+  if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
+}
+
+ProfScope::~ProfScope() {
+  if (!ev0) return;
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  hipEvent_t e = take_event(P);
+  if (e && hipEventRecord(e, stream) == hipSuccess) {
+    P.pending.push_back({name, (hipEvent_t)ev0, e});
+  } else {
+    P.spare.push_back((hipEvent_t)ev0);
+  }
+}
+
+namespace {
+void prof_drain(ProfState& P) {
+  for (auto& pe : P.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pe.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+      auto it = P.acc.find(pe.name);
+      if (it == P.acc.end()) {
+        P.order.push_back(pe.name);
+        P.acc[pe.name] = {1, (double)ms};
+      } else {
+        it->second.first += 1;
+        it->second.second += ms;
+      }
+    }
+    P.spare.push_back(pe.a);
+    P.spare.push_back(pe.b);
+  }
+  P.pending.clear();
+}
+}  // namespace
+
+uint64_t* pinned_scratch() {
+  static thread_local uint64_t* p = nullptr;
+  if (!p) {
+    if (hipHostMalloc((void**)&p, 4096, hipHostMallocDefault) != hipSuccess) p = nullptr;
+  }
+  return p;
+}
+
+}  // namespace sfc
+
+// ---- the handle --------------------------------------------------------------
+
+struct sfc_index {
+  int curve = SFC_CURVE_MORTON;
+  int search = SFC_SEARCH_BINARY;
+  hipStream_t stream = nullptr;
+  sfc::Allocator alloc;
+  uint64_t n = 0;
+  uint64_t* keys = nullptr;
+  uint32_t* ids = nullptr;
+  double* xy = nullptr;
+  void* ws = nullptr;          // query scratch (grow-only)
+  size_t ws_bytes = 0;
+  sfc_query_stats last{};
+};
+
+namespace {
+
+using sfc::align256;
+
+sfc_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return SFC_OK;
+  if (e == hipErrorOutOfMemory) return SFC_ERR_NOMEM;
+  return SFC_ERR_DEVICE;
+}
+
+#define SFC_TRY(expr)                              \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) {                        \
+      (void)hipGetLastError();                     \
+      return from_hip(_e);                         \
+    }                                              \
+  } while (0)
+
+bool valid_options(const sfc_options& o) {
+  if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT) return false;
+  if (o.search != SFC_SEARCH_BINARY && o.search != SFC_SEARCH_LEARNED) return false;
+  if ((o.alloc == nullptr) != (o.release == nullptr)) return false;
+  return true;
+}
+
+// Reads `count` uint64 words from device memory after the stream's work.
+hipError_t read_words(const void* dev, uint64_t* host, size_t count, hipStream_t s) {
+  uint64_t* pin = sfc::pinned_scratch();
+  if (!pin || count > 512) return hipErrorInvalidValue;
+  hipError_t e = hipMemcpyAsync(pin, dev, count * 8, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  std::memcpy(host, pin, count * 8);
+  return hipSuccess;
+}
+
+sfc_status ensure_ws(sfc_index* h, size_t bytes) {
+  if (h->ws_bytes >= bytes) return SFC_OK;
+  if (h->ws) {
+    (void)hipStreamSynchronize(h->stream);
+    h->alloc.put(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  h->ws = h->alloc.get(bytes);
+  if (!h->ws) return SFC_ERR_NOMEM;
+  h->ws_bytes = bytes;
+  return SFC_OK;
+}
+
+void release_arrays(sfc_index* h) {
+  h->alloc.put(h->keys);
+  h->alloc.put(h->ids);
+  h->alloc.put(h->xy);
+  h->alloc.put(h->ws);
+  h->keys = nullptr;
+  h->ids = nullptr;
+  h->xy = nullptr;
+  h->ws = nullptr;
+  h->ws_bytes = 0;
+}
+
+// Runs ranges + searches + scan; on SFC_OK *total_cand holds the number of
+// candidates.
+sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, uint64_t m,
+                      sfc::QueryScratch* qs, uint64_t* total_cand, uint64_t* dbg_lo,
+                      uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e, uint32_t* dbg_nr) {
+  sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
+  if (st != SFC_OK) return st;
+  sfc::query_scratch_carve(h->ws, m, qs);
+  SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, *qs, dbg_lo, dbg_hi, dbg_b,
+                             dbg_e, dbg_nr, h->stream));
+  uint64_t words[2] = {0, 0};
+  // seg_off[4m] and the error word (counters[2], in the low half of word 1).
+  SFC_TRY(hipMemcpyAsync(sfc::pinned_scratch(), qs->seg_off + 4 * m, 8, hipMemcpyDeviceToHost,
+                         h->stream));
+  SFC_TRY(hipMemcpyAsync(sfc::pinned_scratch() + 1, qs->counters, 16, hipMemcpyDeviceToHost,
+                         h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  words[0] = sfc::pinned_scratch()[0];
+  const uint32_t* c32 = (const uint32_t*)(sfc::pinned_scratch() + 1);
+  const uint32_t err = c32[2];
+  if (err & sfc::kErrInvalidQuery) return SFC_ERR_INVALID;
+  if (err & sfc::kErrLookback) return SFC_ERR_DEVICE;
+  *total_cand = words[0];
+  return SFC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sfc_default_options(sfc_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->curve = SFC_CURVE_MORTON;
+  opt->search = SFC_SEARCH_BINARY;
+}
+
+const char* sfc_status_string(sfc_status s) {
+  switch (s) {
+    case SFC_OK: return "ok";
+    case SFC_ERR_INVALID: return "invalid argument";
+    case SFC_ERR_DOMAIN: return "point coordinate outside [0,1)";
+    case SFC_ERR_NOMEM: return "out of device memory";
+    case SFC_ERR_CAPACITY: return "output buffer too small";
+    case SFC_ERR_DEVICE: return "HIP device error";
+    case SFC_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+sfc_status sfc_keys(const double* xy, uint64_t n, int curve, void* stream, uint64_t* keys) {
+  if ((n > 0 && (!xy || !keys)) || n > 0xFFFFFFFFull) return SFC_ERR_INVALID;
+  if (curve != SFC_CURVE_MORTON && curve != SFC_CURVE_HILBERT) return SFC_ERR_INVALID;
+  if (n == 0) return SFC_OK;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t blocks = 0;
+  sfc::build_scratch_bytes(n, &blocks);
+  sfc::Allocator a;
+  void* tmp = a.get(align256((size_t)blocks * 8 * 256 * 4) + 256);
+  if (!tmp) return SFC_ERR_NOMEM;
+  uint32_t* partial = (uint32_t*)tmp;
+  uint32_t* err = (uint32_t*)((char*)tmp + align256((size_t)blocks * 8 * 256 * 4));
+  sfc_status st = SFC_OK;
+  hipError_t e = sfc::fill_u32(err, 0, 1, s);
+  if (e == hipSuccess) e = sfc::launch_keys(xy, n, curve, keys, err, partial, blocks, nullptr, 0, s);
+  uint64_t w = 0;
+  if (e == hipSuccess) e = read_words(err, &w, 1, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    st = from_hip(e);
+  } else if ((uint32_t)w & sfc::kErrDomain) {
+    st = SFC_ERR_DOMAIN;
+  }
+  a.put(tmp);
+  return st;
+}
+
+sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_index** out) {
+  sfc_options o;
+  sfc_default_options(&o);
+  if (opt) o = *opt;
+  if (!out || (n > 0 && !xy) || n > 0xFFFFFFFFull || !valid_options(o)) return SFC_ERR_INVALID;
+  if (o.search == SFC_SEARCH_LEARNED) return SFC_ERR_UNSUPPORTED;
+  sfc_index* h = new (std::nothrow) sfc_index();
+  if (!h) return SFC_ERR_NOMEM;
+  h->curve = o.curve;
+  h->search = o.search;
+  h->stream = (hipStream_t)o.stream;
+  h->alloc.alloc = o.alloc;
+  h->alloc.release = o.release;
+  h->alloc.ctx = o.alloc_ctx;
+  h->n = n;
+  if (n > 0) {
+    h->keys = (uint64_t*)h->alloc.get(n * 8);
+    h->ids = (uint32_t*)h->alloc.get(n * 4);
+    h->xy = (double*)h->alloc.get(n * 16);
+    const size_t sb = sfc::build_scratch_bytes(n, nullptr) + 256;
+    void* scratch = h->alloc.get(sb);
+    if (!h->keys || !h->ids || !h->xy || !scratch) {
+      h->alloc.put(scratch);
+      release_arrays(h);
+      delete h;
+      return SFC_ERR_NOMEM;
+    }
+    uint32_t* err = (uint32_t*)((char*)scratch + sb - 256);
+    hipError_t e = sfc::fill_u32(err, 0, 1, h->stream);
+    if (e == hipSuccess)
+      e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, h->xy, scratch, err, h->stream);
+    uint64_t w = 0;
+    if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
+    h->alloc.put(scratch);
+    sfc_status st = SFC_OK;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      st = from_hip(e);
+    } else if ((uint32_t)w & sfc::kErrDomain) {
+      st = SFC_ERR_DOMAIN;
+    } else if ((uint32_t)w & sfc::kErrLookback) {
+      st = SFC_ERR_DEVICE;
+    }
+    if (st != SFC_OK) {
+      (void)hipStreamSynchronize(h->stream);
+      release_arrays(h);
+      delete h;
+      return st;
+    }
+  }
+  *out = h;
+  return SFC_OK;
+}
+
+sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, uint64_t m,
+                           uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
+                           uint64_t* total_out) {
+  if (!h || !offsets || !total_out || (m > 0 && (!q || !delta)) || (ids_cap > 0 && !ids))
+    return SFC_ERR_INVALID;
+  if (m > (1ull << 36)) return SFC_ERR_INVALID;
+  sfc::QueryScratch qs{};
+  uint64_t total_cand = 0;
+  if (m > 0) {
+    sfc_status st = run_ranges(h, q, delta, m, &qs, &total_cand, nullptr, nullptr, nullptr,
+                               nullptr, nullptr);
+    if (st != SFC_OK) return st;
+  } else {
+    sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(0));
+    if (st != SFC_OK) return st;
+    sfc::query_scratch_carve(h->ws, 0, &qs);
+  }
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_cand, offsets, ids,
+                              ids_cap,
+                              h->stream));
+  uint64_t total = 0;
+  SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
+  uint64_t cw[2];
+  SFC_TRY(read_words(qs.counters, cw, 2, h->stream));
+  if (((const uint32_t*)cw)[2] & sfc::kErrLookback) return SFC_ERR_DEVICE;
+  h->last.queries = m;
+  h->last.candidates = total_cand;
+  h->last.reported = total;
+  h->last.ranges = 0;
+  *total_out = total;
+  return total > ids_cap ? SFC_ERR_CAPACITY : SFC_OK;
+}
+
+sfc_status sfc_query_ranges(sfc_index* h, const double* q, const double* delta, uint64_t m,
+                            uint64_t* key_lo, uint64_t* key_hi, uint64_t* begin, uint64_t* end,
+                            uint32_t* nranges) {
+  if (!h || (m > 0 && (!q || !delta || !key_lo || !key_hi || !begin || !end || !nranges)))
+    return SFC_ERR_INVALID;
+  if (m == 0) return SFC_OK;
+  sfc::QueryScratch qs{};
+  uint64_t total_cand = 0;
+  return run_ranges(h, q, delta, m, &qs, &total_cand, key_lo, key_hi, begin, end, nranges);
+}
+
+uint64_t sfc_size(const sfc_index* h) { return h ? h->n : 0; }
+
+sfc_status sfc_index_view(const sfc_index* h, const uint64_t** keys, const uint32_t** ids,
+                          const double** xy, uint64_t* n) {
+  if (!h) return SFC_ERR_INVALID;
+  if (keys) *keys = h->keys;
+  if (ids) *ids = h->ids;
+  if (xy) *xy = h->xy;
+  if (n) *n = h->n;
+  return SFC_OK;
+}
+
+sfc_status sfc_index_copy(const sfc_index* h, uint64_t* keys, uint32_t* ids, double* xy) {
+  if (!h) return SFC_ERR_INVALID;
+  if (h->n == 0) return SFC_OK;
+  if (keys) SFC_TRY(hipMemcpyAsync(keys, h->keys, h->n * 8, hipMemcpyDeviceToDevice, h->stream));
+  if (ids) SFC_TRY(hipMemcpyAsync(ids, h->ids, h->n * 4, hipMemcpyDeviceToDevice, h->stream));
+  if (xy) SFC_TRY(hipMemcpyAsync(xy, h->xy, h->n * 16, hipMemcpyDeviceToDevice, h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  return SFC_OK;
+}
+
+sfc_status sfc_last_query_stats(const sfc_index* h, sfc_query_stats* out) {
+  if (!h || !out) return SFC_ERR_INVALID;
+  *out = h->last;
+  return SFC_OK;
+}
+
+void sfc_free(sfc_index* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  release_arrays(h);
+  delete h;
+}
+
+void sfc_profile_enable(int on) {
+  sfc::ProfState& P = sfc::prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.on = on != 0;
+}
+
+void sfc_profile_reset(void) {
+  sfc::ProfState& P = sfc::prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  sfc::prof_drain(P);
+  P.acc.clear();
+  P.order.clear();
+}
+
+int sfc_profile_read(const char** names, uint64_t* launches, double* ms, int max) {
+  sfc::ProfState& P = sfc::prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  sfc::prof_drain(P);
+  int i = 0;
+  for (const std::string& k : P.order) {
+    if (i < max) {
+      const auto& v = P.acc[k];
+      // The key strings live in the map for the life of the process.
+      if (names) names[i] = P.acc.find(k)->first.c_str();
+      if (launches) launches[i] = v.first;
+      if (ms) ms[i] = v.second;
+    }
+    ++i;
+  }
+  return i;
+}
+
+void sfc_pool_trim(void) {
+  sfc::Pool& P = sfc::pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  for (auto& kv : P.free_blocks)
+    for (void* p : kv.second) (void)hipFree(p);
+  P.free_blocks.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Curve keys on the device: quantisation, Z-order (Alg. 2) and Hilbert
+// (Sec. 2.1 "Choice of RSFC"), both as labels in the sense of Def. 3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sfc {
+
+constexpr double kTwo32 = 4294967296.0;   // 2^32
+
+// Grid cell of a coordinate in [0,1): floor(v * 2^32).  The scaling by a
+// power of two is exact, so the product is below 2^32 for every v < 1.
+__host__ __device__ __forceinline__ uint32_t quantize(double v) {
+  return (uint32_t)__builtin_floor(v * kTwo32);
+}
+
+__host__ __device__ __forceinline__ bool in_unit(double v) { return v >= 0.0 && v < 1.0; }
+
+// Spreads the 32 bits of v to the even bit positions of a 64-bit word.
+__host__ __device__ __forceinline__ uint64_t spread_bits(uint32_t v) {
+  uint64_t x = v;
+  x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
+
+// Z-order: x's bit i at key bit 2i, y's bit i at key bit 2i+1.
+__host__ __device__ __forceinline__ uint64_t morton_key(uint32_t x, uint32_t y) {
+  return spread_bits(x) | (spread_bits(y) << 1);
+}
+
+// Hilbert order.  The frame of a sub-square is one of four symmetries of the
+// square, kept as two bits: bit 0 = x and y exchanged, bit 1 = both
+// complemented.  At each level the pair of coordinate bits is mapped into the
+// frame, giving (x', y'); the sub-square's rank is 2x' + (x' xor y') (the
+// order (0,0), (0,1), (1,1), (1,0)); a lower-left child (y' = 0, x' = 0)
+// exchanges the axes of its frame and a lower-right child (y' = 0, x' = 1)
+// exchanges and complements them.  The four symmetries commute, so frames
+// compose by xor.  kHilbertLut applies four levels at once: index
+// (frame << 8) | (4 x bits << 4) | (4 y bits), entry (frame' << 8) | 8 key
+// bits.
+struct HilbertLut {
+  uint16_t v[4 * 256];
+};
+
+constexpr HilbertLut make_hilbert_lut() {
+  HilbertLut t{};
+  for (int f0 = 0; f0 < 4; ++f0) {
+    for (int xn = 0; xn < 16; ++xn) {
+      for (int yn = 0; yn < 16; ++yn) {
+        int f = f0;
+        int digits = 0;
+        for (int b = 3; b >= 0; --b) {
+          const int xb = (xn >> b) & 1;
+          const int yb = (yn >> b) & 1;
+          const int sw = f & 1;
+          const int cp = (f >> 1) & 1;
+          const int xp = (sw ? yb : xb) ^ cp;
+          const int yp = (sw ? xb : yb) ^ cp;
+          digits = (digits << 2) | ((xp << 1) | (xp ^ yp));
+          const int low = yp == 0 ? 1 : 0;
+          f ^= low | ((low & xp) << 1);
+        }
+        t.v[(f0 << 8) | (xn << 4) | yn] = (uint16_t)((f << 8) | digits);
+      }
+    }
+  }
+  return t;
+}
+
+// The table in constant memory (one copy per translation unit).
+namespace {
+__constant__ HilbertLut kHilbertLutConst = make_hilbert_lut();
+}  // namespace
+
+// Hilbert key through a lookup table (in LDS or constant memory): eight
+// steps of four levels, most significant first, starting in the identity
+// frame.
+__host__ __device__ __forceinline__ uint64_t hilbert_key_lut(const uint16_t* lut, uint32_t x,
+                                                    uint32_t y) {
+  uint64_t key = 0;
+  uint32_t f = 0;
+#pragma unroll
+  for (int s = 28; s >= 0; s -= 4) {
+    const uint32_t idx = (f << 8) | (((x >> s) & 15u) << 4) | ((y >> s) & 15u);
+    const uint32_t e = lut[idx];
+    key = (key << 8) | (e & 0xFFu);
+    f = e >> 8;
+  }
+  return key;
+}
+
+}  // namespace sfc

@@ -1,0 +1,55 @@
+// Internal host-side interfaces between the translation units of libsfc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sfc {
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Fill kernel (used instead of hipMemsetAsync so that every step of a batch
+// can be recorded into a HIP graph).
+hipError_t fill_u64(uint64_t* p, uint64_t value, uint64_t count, hipStream_t s);
+hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s);
+
+// ---- construction (build.hip) ----
+size_t build_scratch_bytes(uint64_t n, uint32_t* keygen_blocks);
+hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
+                       uint32_t* partial, uint32_t blocks, uint64_t* zero, uint64_t nzero,
+                       hipStream_t s);
+hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
+                      uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
+                      hipStream_t s);
+hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,
+                         hipStream_t s);
+
+// ---- queries (query.hip) ----
+struct QueryScratch {
+  uint32_t* slot_begin;   // 4m
+  uint64_t* seg_off;      // 4m + 1
+  uint64_t* blk_status;   // ceil(4m / 256)
+  uint32_t* counters;     // [0] block counter, [1] tile counter, [2] error
+  uint64_t* carry;        // [0] reports before the current chunk, [1] total
+  uint64_t* tile_status;  // kCompactChunkTiles
+};
+constexpr uint64_t kCompactTile = 2048;             // candidates per tile
+constexpr uint64_t kCompactChunkTiles = 1ull << 20; // tiles per launch
+size_t query_scratch_bytes(uint64_t m);
+void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs);
+
+// Ranges, searches and the exclusive scan of candidate counts; optionally
+// records the ranges for inspection (dbg_* may be null).
+hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
+                         uint64_t n, int curve, const QueryScratch& qs, uint64_t* dbg_lo,
+                         uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e, uint32_t* dbg_nr,
+                         hipStream_t s);
+// Test-and-compact over all candidates (total_cand known on the host).
+hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
+                          const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
+                          uint64_t total_cand,
+                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s);
+
+}  // namespace sfc

@@ -1,0 +1,295 @@
+"""ctypes binding of libsfc (the C ABI in include/sfc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libsfc.  Device buffers are torch CUDA tensors (torch supplies
+memory and streams); every function raises if the library is not built or if
+a call returns an error status.  There is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfc.so")
+
+SFC_OK = 0
+SFC_ERR_INVALID = -1
+SFC_ERR_DOMAIN = -2
+SFC_ERR_NOMEM = -3
+SFC_ERR_CAPACITY = -4
+SFC_ERR_DEVICE = -5
+SFC_ERR_UNSUPPORTED = -6
+
+MORTON = 0
+HILBERT = 1
+BINARY = 0
+LEARNED = 1
+
+EXPORTS = [
+    "sfc_default_options", "sfc_status_string", "sfc_build", "sfc_query_batch", "sfc_size",
+    "sfc_index_view", "sfc_index_copy", "sfc_keys", "sfc_query_ranges",
+    "sfc_last_query_stats", "sfc_free", "sfc_profile_enable", "sfc_profile_reset",
+    "sfc_profile_read", "sfc_pool_trim",
+]
+
+
+class SfcError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class DomainError(SfcError):
+    pass
+
+
+class CapacityError(SfcError):
+    def __init__(self, status, what, total):
+        super().__init__(status, what)
+        self.total = total
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("curve", ctypes.c_int),
+        ("search", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("alloc", ctypes.c_void_p),
+        ("release", ctypes.c_void_p),
+        ("alloc_ctx", ctypes.c_void_p),
+    ]
+
+
+class QueryStats(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_uint64), ("ranges", ctypes.c_uint64),
+                ("candidates", ctypes.c_uint64), ("reported", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Opens libsfc.so (built by build_lib.py); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2508_19891_amd.build_lib")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    L.sfc_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.sfc_default_options.restype = None
+    L.sfc_status_string.argtypes = [i32]
+    L.sfc_status_string.restype = ctypes.c_char_p
+    L.sfc_build.argtypes = [vp, u64, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.sfc_build.restype = i32
+    L.sfc_query_batch.argtypes = [vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(u64)]
+    L.sfc_query_batch.restype = i32
+    L.sfc_size.argtypes = [vp]
+    L.sfc_size.restype = u64
+    L.sfc_index_view.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u64)]
+    L.sfc_index_view.restype = i32
+    L.sfc_index_copy.argtypes = [vp, vp, vp, vp]
+    L.sfc_index_copy.restype = i32
+    L.sfc_keys.argtypes = [vp, u64, i32, vp, vp]
+    L.sfc_keys.restype = i32
+    L.sfc_query_ranges.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp, vp]
+    L.sfc_query_ranges.restype = i32
+    L.sfc_last_query_stats.argtypes = [vp, ctypes.POINTER(QueryStats)]
+    L.sfc_last_query_stats.restype = i32
+    L.sfc_free.argtypes = [vp]
+    L.sfc_free.restype = None
+    L.sfc_profile_enable.argtypes = [i32]
+    L.sfc_profile_enable.restype = None
+    L.sfc_profile_reset.argtypes = []
+    L.sfc_profile_reset.restype = None
+    L.sfc_profile_read.argtypes = [vp, vp, vp, i32]
+    L.sfc_profile_read.restype = i32
+    L.sfc_pool_trim.argtypes = []
+    L.sfc_pool_trim.restype = None
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return lib().sfc_status_string(status).decode()
+
+
+def _check(status: int, what: str):
+    if status == SFC_OK:
+        return
+    if status == SFC_ERR_DOMAIN:
+        raise DomainError(status, what)
+    raise SfcError(status, what)
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None or t.numel() == 0 else ctypes.c_void_p(t.data_ptr())
+
+
+def current_stream_handle() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---- the entry points, one per C function ------------------------------------------
+
+
+def sfc_keys(xy: torch.Tensor, curve: int = MORTON) -> torch.Tensor:
+    """Curve keys of the points (n, 2) float64 -> (n,) uint64 (as int64 bits)."""
+    xy = _dev(xy, torch.float64, "xy")
+    n = xy.shape[0]
+    keys = torch.empty(n, dtype=torch.int64, device=xy.device)
+    _check(lib().sfc_keys(_ptr(xy), n, curve, ctypes.c_void_p(current_stream_handle()),
+                          _ptr(keys)), "sfc_keys")
+    return keys
+
+
+class Index:
+    """An index built by sfc_build; freed by close() or on garbage collection."""
+
+    def __init__(self, xy: torch.Tensor, curve: int = MORTON, search: int = BINARY):
+        xy = _dev(xy, torch.float64, "xy")
+        if xy.ndim != 2 or xy.shape[1] != 2:
+            raise ValueError("xy must have shape (n, 2)")
+        L = lib()
+        opt = Options()
+        L.sfc_default_options(ctypes.byref(opt))
+        opt.curve = curve
+        opt.search = search
+        opt.stream = current_stream_handle()
+        h = ctypes.c_void_p()
+        _check(L.sfc_build(_ptr(xy), xy.shape[0], ctypes.byref(opt), ctypes.byref(h)),
+               "sfc_build")
+        self._h = h
+        self.curve = curve
+        self.search = search
+        self.device = xy.device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sfc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("index is closed")
+        return self._h
+
+    def size(self) -> int:
+        return int(lib().sfc_size(self.handle))
+
+    def sorted_arrays(self):
+        """Copies of the sorted (keys int64-bits, ids int32-bits, xy (n,2))."""
+        n = self.size()
+        keys = torch.empty(n, dtype=torch.int64, device=self.device)
+        ids = torch.empty(n, dtype=torch.int32, device=self.device)
+        xy = torch.empty((n, 2), dtype=torch.float64, device=self.device)
+        _check(lib().sfc_index_copy(self.handle, _ptr(keys), _ptr(ids), _ptr(xy)),
+               "sfc_index_copy")
+        return keys, ids, xy
+
+    def query(self, q: torch.Tensor, delta: torch.Tensor, ids_cap: int | None = None,
+              out_ids: torch.Tensor | None = None, out_offsets: torch.Tensor | None = None):
+        """Batched queries; returns (offsets int64[m+1], ids int32[total]).
+
+        Without ids_cap/out_ids the call is made twice when the first guess of
+        the output size is too small (the second call has the exact size)."""
+        q = _dev(q, torch.float64, "q")
+        delta = _dev(delta, torch.float64, "delta")
+        m = q.shape[0]
+        if q.ndim != 2 or q.shape[1] != 2 or delta.shape != (m,):
+            raise ValueError("q must be (m, 2) and delta (m,)")
+        offsets = out_offsets if out_offsets is not None else torch.empty(
+            m + 1, dtype=torch.int64, device=self.device)
+        if out_ids is None:
+            cap = ids_cap if ids_cap is not None else max(16 * m, 1024)
+            out_ids = torch.empty(cap, dtype=torch.int32, device=self.device)
+        total = ctypes.c_uint64(0)
+        st = lib().sfc_query_batch(self.handle, _ptr(q), _ptr(delta), m, _ptr(offsets),
+                                   _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY and ids_cap is None:
+            out_ids = torch.empty(max(int(total.value), 1), dtype=torch.int32, device=self.device)
+            st = lib().sfc_query_batch(self.handle, _ptr(q), _ptr(delta), m, _ptr(offsets),
+                                       _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY:
+            raise CapacityError(st, "sfc_query_batch", int(total.value))
+        _check(st, "sfc_query_batch")
+        return offsets, out_ids[: int(total.value)]
+
+    def query_ranges(self, q: torch.Tensor, delta: torch.Tensor):
+        """Per query four slots of (key_lo, key_hi, begin, end) and the number
+        of ranges; tensors of shape (m, 4) and (m,)."""
+        q = _dev(q, torch.float64, "q")
+        delta = _dev(delta, torch.float64, "delta")
+        m = q.shape[0]
+        dev = self.device
+        klo = torch.zeros((m, 4), dtype=torch.int64, device=dev)
+        khi = torch.zeros((m, 4), dtype=torch.int64, device=dev)
+        b = torch.zeros((m, 4), dtype=torch.int64, device=dev)
+        e = torch.zeros((m, 4), dtype=torch.int64, device=dev)
+        nr = torch.zeros(m, dtype=torch.int32, device=dev)
+        _check(lib().sfc_query_ranges(self.handle, _ptr(q), _ptr(delta), m, _ptr(klo), _ptr(khi),
+                                      _ptr(b), _ptr(e), _ptr(nr)), "sfc_query_ranges")
+        return klo, khi, b, e, nr
+
+    def last_stats(self) -> dict:
+        s = QueryStats()
+        _check(lib().sfc_last_query_stats(self.handle, ctypes.byref(s)), "sfc_last_query_stats")
+        return {"queries": s.queries, "ranges": s.ranges, "candidates": s.candidates,
+                "reported": s.reported}
+
+
+def sfc_build(xy: torch.Tensor, curve: int = MORTON, search: int = BINARY) -> Index:
+    return Index(xy, curve, search)
+
+
+def sfc_query_batch(index: Index, q: torch.Tensor, delta: torch.Tensor, **kw):
+    return index.query(q, delta, **kw)
+
+
+def sfc_free(index: Index):
+    index.close()
+
+
+def profile_enable(on: bool = True):
+    lib().sfc_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().sfc_profile_reset()
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} of the launches since the last reset."""
+    L = lib()
+    k = L.sfc_profile_read(None, None, None, 0)
+    names = (ctypes.c_char_p * max(k, 1))()
+    launches = (ctypes.c_uint64 * max(k, 1))()
+    ms = (ctypes.c_double * max(k, 1))()
+    k = L.sfc_profile_read(names, launches, ms, k)
+    return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(k)}
+
+
+def u64(t: torch.Tensor):
+    """View of an int64 tensor holding uint64 bit patterns as numpy uint64."""
+    return t.detach().cpu().numpy().view("uint64")
