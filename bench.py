@@ -1,0 +1,214 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input that
+is already resident in device memory: construction of the index over n points
+(curve keys, radix sort of (key, id), gather of the points) followed by one
+batch of m distance queries (ranges, searches, exact test, compaction into
+CSR).  Prints one JSON line on stdout; progress goes to stderr.
+
+Workload: n = 2^24 points, 80% from 16 isotropic Gaussians (sigma 0.01,
+uniform centres) and 20% uniform, clamped to [0,1)^2; Hilbert keys; 2^20
+queries drawn from the same mixture, each with a radius aimed at an expected
+output log-uniform in [1, 1000] points.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash(name: str) -> str:
+    path = os.path.join(ROOT, "paper_2508_19891_amd", "csrc", name)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(kernel: str, source: str, launches_candidates: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256_16") != kernel_source_hash(source):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, curve: int, m_sample: int):
+    """The oracle timed on the host: full construction (single thread) and a
+    bounded sample of the queries (contiguous slices over the host threads);
+    the query time is scaled to the full batch."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    idx = oracle.build(wl.points, curve)
+    t_build = time.perf_counter() - t0
+    qs = wl.queries[:m_sample]
+    ds = wl.delta[:m_sample]
+    t0 = time.perf_counter()
+    off, _ = oracle.query(idx, qs, ds, curve, nthreads=threads)
+    t_query = time.perf_counter() - t0
+    m = wl.queries.shape[0]
+    t_step = t_build + t_query * (m / m_sample)
+    return {
+        "value": m / t_step,
+        "unit": "queries/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle build of all {wl.points.shape[0]} points on 1 thread "
+                   f"({t_build:.2f} s) + the first {m_sample} of {m} queries on {threads} "
+                   f"threads ({t_query:.2f} s, scaled x{m / m_sample:g})"),
+        "reported_sample": int(off[-1]),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-log2", type=int, default=24)
+    ap.add_argument("--m-log2", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2", type=int, default=17)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2508_19891_amd import sfc, workload
+
+    n, m = 1 << args.n_log2, 1 << args.m_log2
+    curve = sfc.HILBERT
+    log(f"generating workload n={n} m={m}")
+    wl = workload.clustered_loguniform(n=n, m=m, curve=curve)
+    dev = torch.device("cuda:0")
+    pts = torch.as_tensor(wl.points).to(dev)
+    q = torch.as_tensor(wl.queries).to(dev)
+    d = torch.as_tensor(wl.delta).to(dev)
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
+
+    def run_mode(refine: bool):
+        # Size the output once (capacity errors in the timed region would be a bug).
+        idx = sfc.Index(pts, curve, refine=refine)
+        _, ids0 = idx.query(q, d)
+        total = int(ids0.numel())
+        stats = idx.last_stats()
+        idx.close()
+        out_ids = torch.empty(total + 1024, dtype=torch.int32, device=dev)
+        del ids0
+        log(f"refine={refine}: reports per batch {total}, candidates {stats['candidates']}")
+
+        def step():
+            ix = sfc.Index(pts, curve, refine=refine)
+            ix.query(q, d, out_ids=out_ids, out_offsets=offsets)
+            ix.close()
+
+        for i in range(args.warmup):
+            step()
+            log(f"warmup {i + 1}/{args.warmup}")
+        torch.cuda.synchronize()
+        sfc.profile_reset()
+        sfc.profile_enable(True)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sfc.profile_enable(False)
+        kern = sfc.profile_read()
+        log(f"timed {args.steps} steps in {dt:.3f} s")
+        return dt / args.steps * 1e3, kern, stats, total
+
+    ms_paper, kern_paper, stats_paper, _ = run_mode(False)
+    ms_step, kern, stats, total = run_mode(True)
+
+    # Algorithmic bytes per step of each kernel (what the method must move).
+    cand, rep = stats["candidates"], total
+    tiles = math.ceil(cand / 4096)
+    slots = 8 * m   # refined layout: eight slots (begin u32, count u32, offset u64) per query
+    algo = {
+        "keygen_hist": 16 * n + 8 * n,                      # points in, keys out
+        "onesweep_pass": 8 * 24 * n,                        # 8 passes x (key+id) in and out
+        "ranges_search": 24 * m + 8 * slots,                # queries in; begin+count per slot
+        "compact_test": 16 * cand + 24 * m + 12 * slots + cand // 8 + 4 * tiles,
+        "compact_write": cand // 8 + 8 * tiles + 4 * rep + 4 * rep + 8 * (m + 1) + 12 * slots,
+    }
+    # The last radix pass also gathers the points (random 16 B reads, 16 B writes).
+    algo["onesweep_pass"] += 32 * n
+    kern_gbs = {}
+    for k, b in algo.items():
+        if k in kern:
+            kern_gbs[k] = b / (kern[k][1] / args.steps * 1e-3) / 1e9
+    dom = max((k for k in algo if k in kern), key=lambda k: kern[k][1])
+    d_launch, d_ms = kern[dom]
+    launches_per_step = d_launch / args.steps
+    bytes_per_launch = algo[dom] / launches_per_step
+    achieved = bytes_per_launch / (d_ms / d_launch * 1e-3) / 1e9
+    traffic = load_traffic(dom, "query.hip" if dom.startswith(("compact", "ranges")) else "build.hip",
+                           launches_per_step)
+
+    line = {
+        "metric": "queries/s + reported pts/s at n=2^24, learned vs bsearch index, % HBM peak",
+        "value": m / (ms_step * 1e-3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name + "_hilbert", "n": n, "m": m, "curve": "hilbert",
+                   "search": "binary", "ranges": "refined", "step": "build + one query batch"},
+        "paper_ranges": {"queries_per_s": m / (ms_paper * 1e-3), "ms_per_step": ms_paper,
+                         "candidates_per_step": stats_paper["candidates"],
+                         "kernels_ms_per_step": {k: v[1] / args.steps
+                                                 for k, v in kern_paper.items()}},
+        "reported_pts_per_s": rep / (ms_step * 1e-3),
+        "reported_per_step": rep,
+        "candidates_per_step": cand,
+        "candidates_per_report": cand / max(rep, 1),
+        "build_ms_per_step": sum(kern[k][1] for k in ("keygen_hist", "hist_reduce", "onesweep_pass")
+                                 if k in kern) / args.steps,
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items()},
+        "roofline": {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "kernels_algorithmic_gbs": kern_gbs,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        line["cpu_baseline"] = cpu_baseline(wl, curve, min(m, 1 << args.cpu_sample_log2))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

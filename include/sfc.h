@@ -66,6 +66,9 @@ typedef struct {
   int curve;    /* SFC_CURVE_MORTON (Alg. 2) or SFC_CURVE_HILBERT */
   int search;   /* SFC_SEARCH_BINARY; SFC_SEARCH_LEARNED fits the learned
                    index at build time (binary search stays the fallback) */
+  int refine;   /* 0: scan the at most four cells of cells(Q) whole (Alg. 1);
+                   1: split a crowded cell once and scan only its children
+                   that meet the query box.  Same reported ids, same order. */
   void* stream; /* hipStream_t, NULL = the null stream */
   /* Device memory hooks; alloc == NULL uses the library's caching pool over
      hipMalloc.  alloc returns NULL on failure.  release(NULL, ctx) is never
@@ -75,7 +78,8 @@ typedef struct {
   void* alloc_ctx;
 } sfc_options;
 
-/* Fills *opt with Morton curve, binary search, null stream, the pool. */
+/* Fills *opt with Morton curve, binary search, no refinement, null stream,
+   the pool. */
 void sfc_default_options(sfc_options* opt);
 
 /* Human-readable name of a status code (static string). */

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -169,6 +170,8 @@ uint64_t* pinned_scratch() {
 struct sfc_index {
   int curve = SFC_CURVE_MORTON;
   int search = SFC_SEARCH_BINARY;
+  int refine = 0;
+  uint32_t refine_min = 32;
   hipStream_t stream = nullptr;
   sfc::Allocator alloc;
   uint64_t n = 0;
@@ -177,6 +180,8 @@ struct sfc_index {
   double* xy = nullptr;
   void* ws = nullptr;          // query scratch (grow-only)
   size_t ws_bytes = 0;
+  void* cws = nullptr;         // compaction scratch (grow-only)
+  size_t cws_bytes = 0;
   sfc_query_stats last{};
 };
 
@@ -202,6 +207,7 @@ sfc_status from_hip(hipError_t e) {
 bool valid_options(const sfc_options& o) {
   if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT) return false;
   if (o.search != SFC_SEARCH_BINARY && o.search != SFC_SEARCH_LEARNED) return false;
+  if (o.refine != 0 && o.refine != 1) return false;
   if ((o.alloc == nullptr) != (o.release == nullptr)) return false;
   return true;
 }
@@ -218,25 +224,30 @@ hipError_t read_words(const void* dev, uint64_t* host, size_t count, hipStream_t
   return hipSuccess;
 }
 
-sfc_status ensure_ws(sfc_index* h, size_t bytes) {
-  if (h->ws_bytes >= bytes) return SFC_OK;
-  if (h->ws) {
+sfc_status grow(sfc_index* h, void** buf, size_t* have, size_t bytes) {
+  if (*have >= bytes) return SFC_OK;
+  if (*buf) {
     (void)hipStreamSynchronize(h->stream);
-    h->alloc.put(h->ws);
-    h->ws = nullptr;
-    h->ws_bytes = 0;
+    h->alloc.put(*buf);
+    *buf = nullptr;
+    *have = 0;
   }
-  h->ws = h->alloc.get(bytes);
-  if (!h->ws) return SFC_ERR_NOMEM;
-  h->ws_bytes = bytes;
+  *buf = h->alloc.get(bytes);
+  if (!*buf) return SFC_ERR_NOMEM;
+  *have = bytes;
   return SFC_OK;
 }
+
+sfc_status ensure_ws(sfc_index* h, size_t bytes) { return grow(h, &h->ws, &h->ws_bytes, bytes); }
 
 void release_arrays(sfc_index* h) {
   h->alloc.put(h->keys);
   h->alloc.put(h->ids);
   h->alloc.put(h->xy);
   h->alloc.put(h->ws);
+  h->alloc.put(h->cws);
+  h->cws = nullptr;
+  h->cws_bytes = 0;
   h->keys = nullptr;
   h->ids = nullptr;
   h->xy = nullptr;
@@ -252,12 +263,12 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, uint64
   sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
   if (st != SFC_OK) return st;
   sfc::query_scratch_carve(h->ws, m, qs);
-  SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, *qs, dbg_lo, dbg_hi, dbg_b,
-                             dbg_e, dbg_nr, h->stream));
+  SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
+                             h->refine_min, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
   uint64_t words[2] = {0, 0};
   // seg_off[4m] and the error word (counters[2], in the low half of word 1).
-  SFC_TRY(hipMemcpyAsync(sfc::pinned_scratch(), qs->seg_off + 4 * m, 8, hipMemcpyDeviceToHost,
-                         h->stream));
+  SFC_TRY(hipMemcpyAsync(sfc::pinned_scratch(), qs->seg_off + (m << qs->ss), 8,
+                         hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipMemcpyAsync(sfc::pinned_scratch() + 1, qs->counters, 16, hipMemcpyDeviceToHost,
                          h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
@@ -265,7 +276,7 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, uint64
   const uint32_t* c32 = (const uint32_t*)(sfc::pinned_scratch() + 1);
   const uint32_t err = c32[2];
   if (err & sfc::kErrInvalidQuery) return SFC_ERR_INVALID;
-  if (err & sfc::kErrLookback) return SFC_ERR_DEVICE;
+  if (err & (sfc::kErrLookback | sfc::kErrInternal)) return SFC_ERR_DEVICE;
   *total_cand = words[0];
   return SFC_OK;
 }
@@ -331,6 +342,8 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_i
   if (!h) return SFC_ERR_NOMEM;
   h->curve = o.curve;
   h->search = o.search;
+  h->refine = o.refine;
+  if (const char* env = std::getenv("SFC_REFINE_MIN")) h->refine_min = (uint32_t)std::atoi(env);
   h->stream = (hipStream_t)o.stream;
   h->alloc.alloc = o.alloc;
   h->alloc.release = o.release;
@@ -361,7 +374,7 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_i
       st = from_hip(e);
     } else if ((uint32_t)w & sfc::kErrDomain) {
       st = SFC_ERR_DOMAIN;
-    } else if ((uint32_t)w & sfc::kErrLookback) {
+    } else if ((uint32_t)w & (sfc::kErrLookback | sfc::kErrInternal)) {
       st = SFC_ERR_DEVICE;
     }
     if (st != SFC_OK) {
@@ -392,14 +405,19 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, u
     if (st != SFC_OK) return st;
     sfc::query_scratch_carve(h->ws, 0, &qs);
   }
-  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_cand, offsets, ids,
-                              ids_cap,
-                              h->stream));
+  {
+    sfc_status st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(total_cand));
+    if (st != SFC_OK) return st;
+  }
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_cand, h->cws, offsets,
+                              ids, ids_cap, h->stream));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
-  uint64_t cw[2];
-  SFC_TRY(read_words(qs.counters, cw, 2, h->stream));
-  if (((const uint32_t*)cw)[2] & sfc::kErrLookback) return SFC_ERR_DEVICE;
+  if (m > 0) {
+    uint64_t cw[2];
+    SFC_TRY(read_words(qs.counters, cw, 2, h->stream));
+    if (((const uint32_t*)cw)[2] & (sfc::kErrLookback | sfc::kErrInternal)) return SFC_ERR_DEVICE;
+  }
   h->last.queries = m;
   h->last.candidates = total_cand;
   h->last.reported = total;

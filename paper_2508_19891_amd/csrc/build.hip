@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
     const uint32_t v = sm.st.v[j];
     const uint32_t pos = s_gbase[(uint32_t)(k >> shift) & 255u] + j;
     if (pos >= n || (GATHER && v >= n)) {   // cannot happen with a consistent histogram
-      atomicOr(err, kErrLookback);
+      atomicOr(err, kErrInternal);
       continue;
     }
     kout[pos] = k;

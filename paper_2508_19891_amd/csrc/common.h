@@ -27,6 +27,7 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr uint32_t kErrDomain = 1u;
 constexpr uint32_t kErrInvalidQuery = 2u;
 constexpr uint32_t kErrLookback = 4u;
+constexpr uint32_t kErrInternal = 8u;   // an index outside its array (never expected)
 
 __device__ __forceinline__ uint64_t ld_acquire_agent(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

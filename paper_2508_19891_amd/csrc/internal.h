@@ -26,30 +26,39 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,
                          hipStream_t s);
 
+// ---- device-wide scan (scan.hip) ----
+// out[i] = carry + sum(in[0..i)), out[count] = carry + sum(in); carry_in is a
+// device word or null (zero).  partial holds scan_scratch_bytes(count).
+size_t scan_scratch_bytes(uint64_t count);
+hipError_t scan_excl(const uint32_t* in, uint64_t* out, uint64_t count, const uint64_t* carry_in,
+                     uint64_t* partial, hipStream_t s);
+
 // ---- queries (query.hip) ----
 struct QueryScratch {
-  uint32_t* slot_begin;   // 4m
-  uint64_t* seg_off;      // 4m + 1
-  uint64_t* blk_status;   // ceil(4m / 256)
-  uint32_t* counters;     // [0] block counter, [1] tile counter, [2] error
-  uint64_t* carry;        // [0] reports before the current chunk, [1] total
-  uint64_t* tile_status;  // kCompactChunkTiles
+  uint32_t* slot_begin;   // 4m: first sorted index of each query slot
+  uint32_t* slot_count;   // 4m: candidates of each query slot
+  uint64_t* seg_off;      // 4m + 1: exclusive scan of slot_count
+  uint64_t* scan_tmp;     // scan partials
+  uint32_t* counters;     // [2] error word
+  int ss;                 // log2 of the slots per query (2: method's ranges, 3: refined)
 };
-constexpr uint64_t kCompactTile = 2048;             // candidates per tile
-constexpr uint64_t kCompactChunkTiles = 1ull << 20; // tiles per launch
+constexpr uint64_t kCompactTile = 4096;             // candidates per tile
+constexpr uint64_t kCompactChunkTiles = 1ull << 19; // tiles per launch
 size_t query_scratch_bytes(uint64_t m);
 void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs);
+size_t compact_scratch_bytes(uint64_t total_cand);
 
-// Ranges, searches and the exclusive scan of candidate counts; optionally
-// records the ranges for inspection (dbg_* may be null).
+// Ranges and searches per query slot, then the scan of candidate counts into
+// segment offsets; optionally records the ranges (dbg_* may be null).
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
-                         uint64_t n, int curve, const QueryScratch& qs, uint64_t* dbg_lo,
-                         uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e, uint32_t* dbg_nr,
-                         hipStream_t s);
-// Test-and-compact over all candidates (total_cand known on the host).
+                         uint64_t n, int curve, bool refine, uint32_t refine_min, QueryScratch& qs,
+                         uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
+                         uint32_t* dbg_nr, hipStream_t s);
+// Test-and-compact over all candidates (total_cand known on the host);
+// cscratch holds compact_scratch_bytes(total_cand).
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
-                          uint64_t total_cand,
-                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s);
+                          uint64_t total_cand, void* cscratch, uint64_t* offsets,
+                          uint32_t* out_ids, uint64_t cap, hipStream_t s);
 
 }  // namespace sfc

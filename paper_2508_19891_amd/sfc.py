@@ -56,6 +56,7 @@ class Options(ctypes.Structure):
     _fields_ = [
         ("curve", ctypes.c_int),
         ("search", ctypes.c_int),
+        ("refine", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("alloc", ctypes.c_void_p),
         ("release", ctypes.c_void_p),
@@ -160,7 +161,8 @@ def sfc_keys(xy: torch.Tensor, curve: int = MORTON) -> torch.Tensor:
 class Index:
     """An index built by sfc_build; freed by close() or on garbage collection."""
 
-    def __init__(self, xy: torch.Tensor, curve: int = MORTON, search: int = BINARY):
+    def __init__(self, xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,
+                 refine: bool = False):
         xy = _dev(xy, torch.float64, "xy")
         if xy.ndim != 2 or xy.shape[1] != 2:
             raise ValueError("xy must have shape (n, 2)")
@@ -169,6 +171,7 @@ class Index:
         L.sfc_default_options(ctypes.byref(opt))
         opt.curve = curve
         opt.search = search
+        opt.refine = 1 if refine else 0
         opt.stream = current_stream_handle()
         h = ctypes.c_void_p()
         _check(L.sfc_build(_ptr(xy), xy.shape[0], ctypes.byref(opt), ctypes.byref(h)),
@@ -259,8 +262,9 @@ class Index:
                 "reported": s.reported}
 
 
-def sfc_build(xy: torch.Tensor, curve: int = MORTON, search: int = BINARY) -> Index:
-    return Index(xy, curve, search)
+def sfc_build(xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,
+              refine: bool = False) -> Index:
+    return Index(xy, curve, search, refine)
 
 
 def sfc_query_batch(index: Index, q: torch.Tensor, delta: torch.Tensor, **kw):

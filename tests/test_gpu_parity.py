@@ -99,8 +99,8 @@ def test_ranges_match_oracle(curve):
             assert (int(klo[j, r]), int(khi[j, r]), int(b[j, r]), int(e[j, r])) == (lo, hi, bb, ee)
 
 
-def check_query(pts, qs, ds, curve, nthreads=4):
-    idx = sfc.Index(dev(pts), curve)
+def check_query(pts, qs, ds, curve, nthreads=4, refine=False):
+    idx = sfc.Index(dev(pts), curve, refine=refine)
     off, ids = idx.query(dev(qs), dev(ds))
     ref_off, ref_ids = oracle.query(oracle.build(pts, curve), qs, ds, curve, nthreads=nthreads)
     got_off = off.cpu().numpy().view(np.uint64)
@@ -110,17 +110,26 @@ def check_query(pts, qs, ds, curve, nthreads=4):
     return idx, ref_off
 
 
+@pytest.mark.parametrize("refine", [False, True])
 @pytest.mark.parametrize("curve", [MORTON, HILBERT])
 @pytest.mark.parametrize("n,m", [(1, 1), (100, 7), (4097, 1000), (65_536, 10_000), (250_000, 20_000)])
-def test_query_matches_oracle(curve, n, m):
+def test_query_matches_oracle(curve, n, m, refine):
     rng = np.random.default_rng(n + m)
     pts = adversarial_points(rng, n)
     qs, ds = _queries(rng, m)
-    check_query(pts, qs, ds, curve)
+    check_query(pts, qs, ds, curve, refine=refine)
 
 
+@pytest.mark.parametrize("refine", [False, True])
 @pytest.mark.parametrize("curve", [MORTON, HILBERT])
-def test_query_edge_cases(curve):
+def test_query_clustered(curve, refine):
+    wl = workload.clustered_loguniform(n=300_000, m=30_000, curve=curve)
+    check_query(wl.points, wl.queries, wl.delta, curve, refine=refine)
+
+
+@pytest.mark.parametrize("refine", [False, True])
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_query_edge_cases(curve, refine):
     rng = np.random.default_rng(77)
     pts = adversarial_points(rng, 20_000)
     qs, ds = _queries(rng, 500)
@@ -129,18 +138,19 @@ def test_query_edge_cases(curve):
     special_d = [2.0, 0.0, 0.0, 0.25, 0.5, 1e-300, 0.1, 0.0, 1e-12]
     qs = np.concatenate([special_q, qs, special_q])
     ds = np.concatenate([special_d, ds, special_d])
-    check_query(pts, qs, ds, curve)
+    check_query(pts, qs, ds, curve, refine=refine)
 
 
-def test_query_all_empty_and_trailing_empty():
+@pytest.mark.parametrize("refine", [False, True])
+def test_query_all_empty_and_trailing_empty(refine):
     rng = np.random.default_rng(3)
     pts = rng.random((5000, 2))
     far = np.full((300, 2), 5.0)
-    check_query(pts, far, np.full(300, 0.1), MORTON)
+    check_query(pts, far, np.full(300, 0.1), MORTON, refine=refine)
     qs = np.concatenate([rng.random((50, 2)), far])
-    check_query(pts, qs, np.full(350, 0.05), MORTON)
+    check_query(pts, qs, np.full(350, 0.05), MORTON, refine=refine)
     qs = np.concatenate([far, rng.random((50, 2)), far])
-    check_query(pts, qs, np.full(650, 0.05), HILBERT)
+    check_query(pts, qs, np.full(650, 0.05), HILBERT, refine=refine)
 
 
 def test_query_zero_queries():
@@ -179,13 +189,16 @@ def test_query_capacity():
     assert np.array_equal(ids.cpu().numpy().view(np.uint32), ref_ids)
 
 
-def test_query_large_outputs_many_tiles():
+@pytest.mark.parametrize("refine", [False, True])
+def test_query_large_outputs_many_tiles(refine):
     # Huge radii: every query reports every point; candidates span many tiles.
     rng = np.random.default_rng(8)
     pts = rng.random((30_000, 2))
     qs = rng.random((300, 2))
     ds = np.full(300, 1.5)
-    check_query(pts, qs, ds, HILBERT)
+    check_query(pts, qs, ds, HILBERT, refine=refine)
+    ds = np.full(300, 0.3)
+    check_query(pts, qs, ds, MORTON, refine=refine)
 
 
 def test_query_repeatable():
