@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--m-log2", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=17)
+    ap.add_argument("--only-refined", action="store_true",
+                    help="time only the refined range mode (for profiler runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device-to-device three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -96,6 +100,16 @@ def main():
     import torch
 
     from paper_2508_19891_amd import sfc, workload
+
+    if args.copy_probe:
+        # A plain copy kernel of known size: 2^30 bytes read and 2^30 written per launch.
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy probe: 3 x 2^30 B device-to-device")
 
     n, m = 1 << args.n_log2, 1 << args.m_log2
     curve = sfc.HILBERT
@@ -139,7 +153,10 @@ def main():
         log(f"timed {args.steps} steps in {dt:.3f} s")
         return dt / args.steps * 1e3, kern, stats, total
 
-    ms_paper, kern_paper, stats_paper, _ = run_mode(False)
+    if args.only_refined:
+        ms_paper, kern_paper, stats_paper = float("nan"), {}, {"candidates": None}
+    else:
+        ms_paper, kern_paper, stats_paper, _ = run_mode(False)
     ms_step, kern, stats, total = run_mode(True)
 
     # Algorithmic bytes per step of each kernel (what the method must move).

@@ -255,29 +255,26 @@ void release_arrays(sfc_index* h) {
   h->ws_bytes = 0;
 }
 
-// Runs ranges + searches + scan; on SFC_OK *total_cand holds the number of
-// candidates.
+// Runs ranges + searches + scan; on SFC_OK *total_rows holds the number of
+// candidate rows and *total_cand the number of candidates.
 sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, uint64_t m,
-                      sfc::QueryScratch* qs, uint64_t* total_cand, uint64_t* dbg_lo,
-                      uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e, uint32_t* dbg_nr) {
+                      sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
+                      uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
+                      uint32_t* dbg_nr) {
   sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
   if (st != SFC_OK) return st;
   sfc::query_scratch_carve(h->ws, m, qs);
   SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
                              h->refine_min, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
-  uint64_t words[2] = {0, 0};
-  // seg_off[4m] and the error word (counters[2], in the low half of word 1).
-  SFC_TRY(hipMemcpyAsync(sfc::pinned_scratch(), qs->seg_off + (m << qs->ss), 8,
-                         hipMemcpyDeviceToHost, h->stream));
-  SFC_TRY(hipMemcpyAsync(sfc::pinned_scratch() + 1, qs->counters, 16, hipMemcpyDeviceToHost,
-                         h->stream));
+  uint64_t* pin = sfc::pinned_scratch();
+  SFC_TRY(hipMemcpyAsync(pin, qs->row_off + (m << qs->ss), 8, hipMemcpyDeviceToHost, h->stream));
+  SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 32, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
-  words[0] = sfc::pinned_scratch()[0];
-  const uint32_t* c32 = (const uint32_t*)(sfc::pinned_scratch() + 1);
-  const uint32_t err = c32[2];
+  const uint32_t err = ((const uint32_t*)(pin + 1))[2];
   if (err & sfc::kErrInvalidQuery) return SFC_ERR_INVALID;
   if (err & (sfc::kErrLookback | sfc::kErrInternal)) return SFC_ERR_DEVICE;
-  *total_cand = words[0];
+  *total_rows = pin[0];
+  *total_cand = pin[3];   // counters[4..5]
   return SFC_OK;
 }
 
@@ -395,10 +392,10 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, u
     return SFC_ERR_INVALID;
   if (m > (1ull << 36)) return SFC_ERR_INVALID;
   sfc::QueryScratch qs{};
-  uint64_t total_cand = 0;
+  uint64_t total_rows = 0, total_cand = 0;
   if (m > 0) {
-    sfc_status st = run_ranges(h, q, delta, m, &qs, &total_cand, nullptr, nullptr, nullptr,
-                               nullptr, nullptr);
+    sfc_status st = run_ranges(h, q, delta, m, &qs, &total_rows, &total_cand, nullptr, nullptr,
+                               nullptr, nullptr, nullptr);
     if (st != SFC_OK) return st;
   } else {
     sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(0));
@@ -406,10 +403,10 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, u
     sfc::query_scratch_carve(h->ws, 0, &qs);
   }
   {
-    sfc_status st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(total_cand));
+    sfc_status st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(total_rows));
     if (st != SFC_OK) return st;
   }
-  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_cand, h->cws, offsets,
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_rows, h->cws, offsets,
                               ids, ids_cap, h->stream));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
@@ -433,8 +430,9 @@ sfc_status sfc_query_ranges(sfc_index* h, const double* q, const double* delta, 
     return SFC_ERR_INVALID;
   if (m == 0) return SFC_OK;
   sfc::QueryScratch qs{};
-  uint64_t total_cand = 0;
-  return run_ranges(h, q, delta, m, &qs, &total_cand, key_lo, key_hi, begin, end, nranges);
+  uint64_t total_rows = 0, total_cand = 0;
+  return run_ranges(h, q, delta, m, &qs, &total_rows, &total_cand, key_lo, key_hi, begin, end,
+                    nranges);
 }
 
 uint64_t sfc_size(const sfc_index* h) { return h ? h->n : 0; }

@@ -35,18 +35,19 @@ hipError_t scan_excl(const uint32_t* in, uint64_t* out, uint64_t count, const ui
 
 // ---- queries (query.hip) ----
 struct QueryScratch {
-  uint32_t* slot_begin;   // 4m: first sorted index of each query slot
-  uint32_t* slot_count;   // 4m: candidates of each query slot
-  uint64_t* seg_off;      // 4m + 1: exclusive scan of slot_count
+  uint32_t* slot_begin;   // per query slot: first sorted index of its range
+  uint32_t* slot_count;   // per query slot: its number of candidates
+  uint32_t* slot_rows;    // per query slot: rows of 64 candidates
+  uint64_t* row_off;      // exclusive scan of slot_rows (+ total at the end)
   uint64_t* scan_tmp;     // scan partials
-  uint32_t* counters;     // [2] error word
+  uint32_t* counters;     // [2] error word, [4..5] total candidates (u64)
   int ss;                 // log2 of the slots per query (2: method's ranges, 3: refined)
 };
-constexpr uint64_t kCompactTile = 4096;             // candidates per tile
+constexpr uint64_t kCompactTileRows = 64;           // rows of 64 candidates per tile
 constexpr uint64_t kCompactChunkTiles = 1ull << 19; // tiles per launch
 size_t query_scratch_bytes(uint64_t m);
 void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs);
-size_t compact_scratch_bytes(uint64_t total_cand);
+size_t compact_scratch_bytes(uint64_t total_rows);
 
 // Ranges and searches per query slot, then the scan of candidate counts into
 // segment offsets; optionally records the ranges (dbg_* may be null).
@@ -54,11 +55,11 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
                          uint64_t n, int curve, bool refine, uint32_t refine_min, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s);
-// Test-and-compact over all candidates (total_cand known on the host);
-// cscratch holds compact_scratch_bytes(total_cand).
+// Test-and-compact over all candidate rows (total_rows known on the host);
+// cscratch holds compact_scratch_bytes(total_rows).
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
-                          uint64_t total_cand, void* cscratch, uint64_t* offsets,
+                          uint64_t total_rows, void* cscratch, uint64_t* offsets,
                           uint32_t* out_ids, uint64_t cap, hipStream_t s);
 
 }  // namespace sfc

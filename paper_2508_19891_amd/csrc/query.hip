@@ -16,6 +16,8 @@
 //                  offsets of the queries whose candidates start in it.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "common.h"
 #include "curve.h"
 #include "internal.h"
@@ -219,7 +221,8 @@ template <int CURVE, bool REFINE>
 __global__ __launch_bounds__(256) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint64_t* __restrict__ keys, uint64_t n, uint32_t refine_min,
-    uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count, uint32_t* counters,
+    uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
+    uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
     uint64_t* __restrict__ dbg_lo, uint64_t* __restrict__ dbg_hi, uint64_t* __restrict__ dbg_b,
     uint64_t* __restrict__ dbg_e, uint32_t* __restrict__ dbg_nr) {
   __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
@@ -297,10 +300,16 @@ __global__ __launch_bounds__(256) void ranges_search(
     }
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&counters[2], kErrInvalidQuery);
+  // Candidates of the wave, for the statistics.
+  uint64_t wc = (e0 - b0) + (e1 - b1);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wc += __shfl_xor(wc, o, 64);
+  if (lane_id() == 0 && wc) atomicAdd(cand_total, (unsigned long long)wc);
   if (j < m) {
     if (!REFINE) {
       slot_begin[g] = (uint32_t)b0;
       slot_count[g] = (uint32_t)(e0 - b0);
+      slot_rows[g] = (uint32_t)((e0 - b0 + 63) >> 6);
       if (dbg_lo) {
         dbg_lo[g] = klo;
         dbg_hi[g] = khi;
@@ -311,56 +320,21 @@ __global__ __launch_bounds__(256) void ranges_search(
     } else {
       slot_begin[2 * g] = (uint32_t)b0;
       slot_count[2 * g] = (uint32_t)(e0 - b0);
+      slot_rows[2 * g] = (uint32_t)((e0 - b0 + 63) >> 6);
       slot_begin[2 * g + 1] = (uint32_t)b1;
       slot_count[2 * g + 1] = (uint32_t)(e1 - b1);
+      slot_rows[2 * g + 1] = (uint32_t)((e1 - b1 + 63) >> 6);
     }
   }
 }
 
-// Largest s in [0, nseg) with seg_off[s] <= c, for c < seg_off[nseg]; the
-// whole wave searches with 64 probes per step (wave-uniform result).
-__device__ __forceinline__ uint64_t wave_segment_of(const uint64_t* __restrict__ seg_off,
-                                                    uint64_t nseg, uint64_t c, uint64_t lo) {
-  const uint32_t lane = lane_id();
-  uint64_t hi = nseg - 1;   // invariant: seg_off[lo] <= c and the answer lies in [lo, hi]
-  while (hi - lo >= 64) {
-    const uint64_t stride = (hi - lo) / 64 + 1;
-    const uint64_t idx = lo + lane * stride;
-    const bool le = idx <= hi && seg_off[idx] <= c;
-    const uint64_t bal = __ballot(le);
-    const uint64_t nlo = lo + (uint64_t)(63 - __clzll(bal)) * stride;
-    hi = nlo + stride - 1 < hi ? nlo + stride - 1 : hi;
-    lo = nlo;
-  }
-  const uint64_t idx = lo + lane;
-  const bool le = idx <= hi && seg_off[idx] <= c;
-  const uint64_t bal = __ballot(le);
-  return lo + (uint64_t)(63 - __clzll(bal));
-}
-
-// Largest s in [0, nseg) with seg_off[s] <= c (one lane, scalar search).
-__device__ __forceinline__ uint64_t segment_of(const uint64_t* __restrict__ seg_off,
-                                               uint64_t nseg, uint64_t c) {
-  uint64_t lo = 0, len = nseg + 1;
-  while (len > 0) {
-    const uint64_t h = len >> 1;
-    if (seg_off[lo + h] <= c) {
-      lo += h + 1;
-      len -= h + 1;
-    } else {
-      len = h;
-    }
-  }
-  return lo - 1;
-}
-
-// First query index qq in [0, m] with seg_off[qq << ss] >= v (m if none).
-__device__ __forceinline__ uint64_t first_query_at(const uint64_t* __restrict__ seg_off,
-                                                   uint64_t m, int ss, uint64_t v) {
+// First query index qq in [0, m] with off[qq << ss] >= v (m if none).
+__device__ __forceinline__ uint64_t first_query_at(const uint64_t* __restrict__ off, uint64_t m,
+                                                   int ss, uint64_t v) {
   uint64_t lo = 0, len = m;
   while (len > 0) {
     const uint64_t h = len >> 1;
-    if (seg_off[(lo + h) << ss] < v) {
+    if (off[(lo + h) << ss] < v) {
       lo += h + 1;
       len -= h + 1;
     } else {
@@ -370,128 +344,100 @@ __device__ __forceinline__ uint64_t first_query_at(const uint64_t* __restrict__ 
   return lo;
 }
 
-// A register window over the flat segment list (one segment per query slot):
-// lane i holds the end E of segment base + i and its first sorted index B;
-// S0 is the start of segment base.  The segment of candidate c is then
-// base + #{i : E_i <= c}, found by a binary search over the lanes.
-struct SegWindow {
-  uint64_t base = 0, S0 = 0, E = 0, last = 0;
-  uint32_t B = 0;
-  bool valid = false;
-
-  __device__ __forceinline__ void load(const uint64_t* __restrict__ seg_off,
-                                       const uint32_t* __restrict__ slot_begin, uint64_t nseg,
-                                       uint64_t b) {
-    const uint64_t i = b + lane_id();
-    base = b;
-    E = i < nseg ? seg_off[i + 1] : ~0ull;
-    B = i < nseg ? slot_begin[i] : 0u;
-    S0 = seg_off[b];
-    last = __shfl(E, 63, 64);
-    valid = true;
-  }
-
-  // Makes the window start at or before the segment of row start r0 (which
-  // must be a valid candidate) and cover it.
-  __device__ __forceinline__ void ensure(const uint64_t* __restrict__ seg_off,
-                                         const uint32_t* __restrict__ slot_begin, uint64_t nseg,
-                                         uint64_t r0) {
-    if (valid && r0 < last) return;
-    const uint64_t lo = valid ? base + 63 : 0;   // seg_off[base + 63] <= last <= r0
-    load(seg_off, slot_begin, nseg, wave_segment_of(seg_off, nseg, r0, lo));
-  }
-
-  // Segment sc and sorted position pos of candidate c of the row starting
-  // at r0 (wave-wide call; inactive lanes get unspecified values).
-  __device__ __forceinline__ void locate(const uint64_t* __restrict__ seg_off,
-                                         const uint32_t* __restrict__ slot_begin, uint64_t nseg,
-                                         uint64_t r0, uint64_t c, bool active, uint64_t& sc,
-                                         uint64_t& pos) const {
-    const uint32_t lane = lane_id();
-    const uint32_t rel = E <= r0 ? 0u : (E - r0 >= 64 ? 64u : (uint32_t)(E - r0));
-    uint32_t k = 0;
-#pragma unroll
-    for (uint32_t bstep = 32; bstep >= 1; bstep >>= 1) {
-      const uint32_t v = (uint32_t)__shfl((int)rel, (int)(k + bstep - 1), 64);
-      if (v <= lane) k += bstep;
-    }
-    const uint32_t lastrel = (uint32_t)__shfl((int)rel, 63, 64);
-    if (k == 63 && lastrel <= lane) k = 64;
-    const uint64_t e_prev = __shfl(E, (int)(k == 0 ? 0 : (k > 63 ? 63 : k - 1)), 64);
-    const uint32_t b_k = (uint32_t)__shfl((int)B, (int)(k > 63 ? 63 : k), 64);
-    sc = base + k;
-    uint64_t sstart = k == 0 ? S0 : e_prev;
-    uint32_t sb = b_k;
-    if (k == 64 && active) {   // more than 64 segments end inside this row (rare)
-      sc = segment_of(seg_off, nseg, c);
-      sstart = seg_off[sc];
-      sb = slot_begin[sc];
-    }
-    pos = (uint64_t)sb + (c - sstart);
-  }
-};
-
-constexpr int kRows = 8;                                  // rows of 64 per iteration
+// The candidates are laid out in rows of 64: each query slot (segment) s
+// owns rows [row_off[s], row_off[s+1]), row k of s holding its candidates
+// 64k .. 64k+63 (the last row partly filled).  So every row belongs to one
+// slot and one query, found by a scalar walk, and the query's data are
+// wave-uniform.  A tile is 64 consecutive rows: four waves of kIters x kRows.
+constexpr int kRows = 8;                                  // rows per iteration
 constexpr int kIters = 2;                                 // iterations per wave
 constexpr int kTileRows = 4 * kRows * kIters;             // 64 rows per tile
-static_assert(kCompactTile == (uint64_t)kTileRows * kWave, "tile shape");
+constexpr uint64_t kWaveRows = (uint64_t)kRows * kIters;  // rows per wave
+static_assert(kCompactTileRows == (uint64_t)kTileRows, "tile shape");
 
-// Pass 1: exact test of every candidate; per 64-candidate row, the mask of
-// accepted lanes, and per tile the number of accepted candidates.
+// Row descriptors of a launch's rows [rbase, rend): for row r of slot s,
+// (first sorted index of the row, number of valid lanes, query index).  One
+// block per 256 slots; the block's rows are spread over its threads and each
+// finds its slot by a binary search in LDS.
+__global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ row_off,
+                                                   const uint32_t* __restrict__ slot_begin,
+                                                   const uint32_t* __restrict__ slot_count,
+                                                   uint64_t nseg, int ss, uint64_t rbase,
+                                                   uint64_t rend, uint4* __restrict__ row_meta) {
+  __shared__ uint64_t st[257];
+  const uint64_t s0 = (uint64_t)blockIdx.x * 256;
+  const uint32_t tid = threadIdx.x;
+  st[tid] = row_off[s0 + tid < nseg ? s0 + tid : nseg];
+  if (tid == 0) st[256] = row_off[s0 + 256 < nseg ? s0 + 256 : nseg];
+  __syncthreads();
+  const uint64_t r0 = st[0] > rbase ? st[0] : rbase;
+  const uint64_t r1 = st[256] < rend ? st[256] : rend;
+  for (uint64_t r = r0 + tid; r < r1; r += 256) {
+    uint32_t lo = 0, len = 256;   // largest k with st[k] <= r
+    while (len > 0) {
+      const uint32_t h = len >> 1;
+      if (st[lo + h] <= r) {
+        lo += h + 1;
+        len -= h + 1;
+      } else {
+        len = h;
+      }
+    }
+    const uint32_t k = lo - 1;
+    const uint64_t sg = s0 + k;
+    const uint64_t local = (r - st[k]) * kWave;
+    const uint64_t cnt = slot_count[sg];
+    const uint64_t nv = cnt - local < (uint64_t)kWave ? cnt - local : (uint64_t)kWave;
+    row_meta[r - rbase] = make_uint4((uint32_t)(slot_begin[sg] + local), (uint32_t)nv,
+                                     (uint32_t)(sg >> ss), 0u);
+  }
+}
+
+// Pass 1: the exact test of every candidate; per row the 64-bit mask of the
+// accepted lanes, per tile their number.  Each wave handles 16 consecutive
+// rows as ITERS groups of ROWS rows whose point loads are in flight together.
+template <int ROWS, int ITERS>
 __global__ __launch_bounds__(256) void compact_test(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
-    const double2* __restrict__ pts, uint64_t npts, const uint64_t* __restrict__ seg_off,
-    const uint32_t* __restrict__ slot_begin, int ss, uint64_t total_cand, uint64_t chunk_base,
-    uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits, uint32_t* counters) {
+    const double2* __restrict__ pts, uint64_t npts, const uint4* __restrict__ row_meta,
+    uint64_t total_rows, uint64_t rbase, uint64_t* __restrict__ masks,
+    uint32_t* __restrict__ tile_hits, uint32_t* counters) {
   __shared__ uint32_t s_cnt[4];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t tile = blockIdx.x;
-  const uint64_t tile_start = chunk_base + tile * kCompactTile;
-  const uint64_t nseg = m << ss;
-  SegWindow win;
+  const uint64_t wrow0 = rbase + tile * kTileRows + (uint64_t)w * kWaveRows;
   uint32_t cnt = 0;
-  for (int it = 0; it < kIters; ++it) {
-    const uint64_t c0 = tile_start + (uint64_t)(w * kIters + it) * (kRows * kWave);
-    uint32_t pos[kRows], qix[kRows];
-    uint32_t act = 0;
+  for (int it = 0; it < ITERS; ++it) {
+    const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;   // first row of the group
+    uint4 md = make_uint4(0, 0, 0, 0);
+    if (lane < (uint32_t)ROWS && g0 + lane < total_rows) md = row_meta[g0 + lane - rbase];
+    uint32_t pos[ROWS];
+    double qx[ROWS], qy[ROWS], dd[ROWS];
+    bool act[ROWS];
 #pragma unroll
-    for (int jr = 0; jr < kRows; ++jr) {
-      pos[jr] = 0;
-      qix[jr] = 0;
-      const uint64_t r0 = c0 + (uint64_t)jr * kWave;
-      if (r0 >= total_cand) continue;   // wave-uniform
-      const uint64_t c = r0 + lane;
-      const bool active = c < total_cand;
-      win.ensure(seg_off, slot_begin, nseg, r0);
-      uint64_t sc, p64;
-      win.locate(seg_off, slot_begin, nseg, r0, c, active, sc, p64);
-      if (active) {
-        if (p64 < npts && (sc >> ss) < m) {
-          pos[jr] = (uint32_t)p64;
-          qix[jr] = (uint32_t)(sc >> ss);
-          act |= 1u << jr;
-        } else {
-          atomicOr(&counters[2], kErrInternal);
-        }
-      }
+    for (int jr = 0; jr < ROWS; ++jr) {
+      const uint32_t pb = __builtin_amdgcn_readlane(md.x, jr);
+      const uint32_t nv = __builtin_amdgcn_readlane(md.y, jr);
+      const uint32_t qi = __builtin_amdgcn_readlane(md.z, jr);
+      const uint64_t p64 = (uint64_t)pb + lane;
+      act[jr] = lane < nv && p64 < npts && qi < m;
+      pos[jr] = act[jr] ? (uint32_t)p64 : 0u;
+      const uint32_t qs = qi < m ? qi : 0u;
+      const double2 qq = q[qs];
+      qx[jr] = qq.x;
+      qy[jr] = qq.y;
+      dd[jr] = delta[qs];
     }
-    double2 pv[kRows], qv[kRows];
-    double dv[kRows];
+    double2 pv[ROWS];
 #pragma unroll
-    for (int jr = 0; jr < kRows; ++jr) {
-      if ((act >> jr) & 1u) {
-        pv[jr] = pts[pos[jr]];
-        qv[jr] = q[qix[jr]];
-        dv[jr] = delta[qix[jr]];
-      }
-    }
+    for (int jr = 0; jr < ROWS; ++jr)
+      if (act[jr]) pv[jr] = pts[pos[jr]];
 #pragma unroll
-    for (int jr = 0; jr < kRows; ++jr) {
-      const bool hit =
-          ((act >> jr) & 1u) && within(pv[jr].x, pv[jr].y, qv[jr].x, qv[jr].y, dv[jr]);
+    for (int jr = 0; jr < ROWS; ++jr) {
+      const bool hit = act[jr] && within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]);
       const uint64_t bal = __ballot(hit);
       cnt += (uint32_t)__popcll(bal);
-      if (lane == 0) masks[tile * kTileRows + (uint64_t)(w * kIters + it) * kRows + jr] = bal;
+      if (lane == 0) masks[tile * kTileRows + (uint64_t)(w * ITERS + it) * ROWS + jr] = bal;
     }
   }
   if (lane == 0) s_cnt[w] = cnt;
@@ -499,27 +445,28 @@ __global__ __launch_bounds__(256) void compact_test(
   if (tid == 0) tile_hits[tile] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
 }
 
-// Pass 2: the ids of the accepted candidates, in candidate order, at the
-// tile's offset; and the CSR offsets of the queries whose candidates start in
-// the tile (for the last tile also of the trailing queries without any).
+// Pass 2: the ids of the accepted candidates at the tile's output offset, in
+// row order (= curve order per query); and the CSR offsets of the queries
+// whose first row lies in the tile (for the last tile also of the trailing
+// queries without rows).
+template <int ROWS, int ITERS>
 __global__ __launch_bounds__(256) void compact_write(
     const uint32_t* __restrict__ ids, uint64_t npts, uint64_t m,
-    const uint64_t* __restrict__ seg_off, const uint32_t* __restrict__ slot_begin, int ss,
-    uint64_t total_cand, uint64_t chunk_base, const uint64_t* __restrict__ masks,
+    const uint64_t* __restrict__ row_off, int ss, const uint4* __restrict__ row_meta,
+    uint64_t total_rows, uint64_t rbase, const uint64_t* __restrict__ masks,
     const uint64_t* __restrict__ tile_off, uint64_t* __restrict__ offsets,
-    uint32_t* __restrict__ out_ids, uint64_t cap, uint32_t* counters) {
+    uint32_t* __restrict__ out_ids, uint64_t cap) {
   __shared__ uint64_t s_mask[kTileRows];
   __shared__ uint32_t s_pre[kTileRows + 1];
   __shared__ uint64_t s_qrange[2];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t tile = blockIdx.x;
-  const uint64_t tile_start = chunk_base + tile * kCompactTile;
-  const uint64_t nseg = m << ss;
+  const uint64_t trow0 = rbase + tile * kTileRows;
   if (tid < kTileRows) s_mask[tid] = masks[tile * kTileRows + tid];
-  if (tid == 64) s_qrange[0] = first_query_at(seg_off, m, ss, tile_start);
+  if (tid == 64) s_qrange[0] = first_query_at(row_off, m, ss, trow0);
   if (tid == 128) {
-    const uint64_t tile_end = tile_start + kCompactTile;
-    s_qrange[1] = tile_end >= total_cand ? m : first_query_at(seg_off, m, ss, tile_end);
+    const uint64_t tend = trow0 + kTileRows;
+    s_qrange[1] = tend >= total_rows ? m : first_query_at(row_off, m, ss, tend);
   }
   __syncthreads();
   if (tid < 64) {   // exclusive scan of the row counts (one wave)
@@ -536,59 +483,35 @@ __global__ __launch_bounds__(256) void compact_write(
   __syncthreads();
   const uint64_t prefix = tile_off[tile];
   const uint64_t below = lanemask_lt();
-
-  SegWindow win;
-  for (int it = 0; it < kIters; ++it) {
-    // Locate the accepted candidates of eight rows, then load their ids
-    // together, then store them.
-    uint32_t pos[kRows];
-    uint64_t opos[kRows];
-    uint32_t act = 0;
+  const uint64_t wrow0 = trow0 + (uint64_t)w * kWaveRows;
+  for (int it = 0; it < ITERS; ++it) {
+    const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;
+    const int ri0 = (w * ITERS + it) * ROWS;
+    uint32_t pbase = 0;
+    if (lane < (uint32_t)ROWS && g0 + lane < total_rows) pbase = row_meta[g0 + lane - rbase].x;
+    uint32_t idv[ROWS];
+    uint64_t opos[ROWS];
+    bool act[ROWS];
 #pragma unroll
-    for (int jr = 0; jr < kRows; ++jr) {
-      pos[jr] = 0;
-      opos[jr] = 0;
-      const int ri = (w * kIters + it) * kRows + jr;
-      const uint64_t mask = s_mask[ri];
-      if (mask == 0) continue;   // wave-uniform
-      const uint64_t r0 = tile_start + (uint64_t)ri * kWave;
-      const uint64_t c = r0 + lane;
-      const bool hit = (mask >> lane) & 1ull;
-      win.ensure(seg_off, slot_begin, nseg, r0);
-      uint64_t sc, p64;
-      win.locate(seg_off, slot_begin, nseg, r0, c, hit, sc, p64);
-      if (hit) {
-        if (p64 < npts) {
-          pos[jr] = (uint32_t)p64;
-          opos[jr] = prefix + s_pre[ri] + (uint64_t)__popcll(mask & below);
-          act |= 1u << jr;
-        } else {
-          atomicOr(&counters[2], kErrInternal);
-        }
-      }
+    for (int jr = 0; jr < ROWS; ++jr) {
+      const uint64_t mask = s_mask[ri0 + jr];
+      const uint64_t p64 = (uint64_t)__builtin_amdgcn_readlane(pbase, jr) + lane;
+      act[jr] = ((mask >> lane) & 1ull) && p64 < npts;
+      opos[jr] = prefix + s_pre[ri0 + jr] + (uint64_t)__popcll(mask & below);
+      idv[jr] = act[jr] ? ids[p64] : 0u;
     }
-    uint32_t idv[kRows];
 #pragma unroll
-    for (int jr = 0; jr < kRows; ++jr) idv[jr] = ((act >> jr) & 1u) ? ids[pos[jr]] : 0u;
-#pragma unroll
-    for (int jr = 0; jr < kRows; ++jr)
-      if (((act >> jr) & 1u) && opos[jr] < cap) out_ids[opos[jr]] = idv[jr];
+    for (int jr = 0; jr < ROWS; ++jr)
+      if (act[jr] && opos[jr] < cap) out_ids[opos[jr]] = idv[jr];
   }
 
-  const uint64_t valid = total_cand - tile_start < kCompactTile ? total_cand - tile_start
-                                                                : kCompactTile;
+  const uint64_t valid = total_rows - trow0 < (uint64_t)kTileRows ? total_rows - trow0
+                                                                  : (uint64_t)kTileRows;
   for (uint64_t qq = s_qrange[0] + tid; qq < s_qrange[1]; qq += 256) {
-    const uint64_t x = seg_off[qq << ss] - tile_start;
-    uint64_t hb;
-    if (x >= valid) {
-      hb = s_pre[kTileRows];
-    } else {
-      const uint32_t r = (uint32_t)(x >> 6), bpos = (uint32_t)(x & 63);
-      hb = s_pre[r] + (uint64_t)__popcll(s_mask[r] & ((1ull << bpos) - 1));
-    }
-    offsets[qq] = prefix + hb;
+    const uint64_t x = row_off[qq << ss] - trow0;
+    offsets[qq] = prefix + (x >= valid ? s_pre[kTileRows] : s_pre[x]);
   }
-  if (tid == 0 && tile_start + valid == total_cand) offsets[m] = prefix + s_pre[kTileRows];
+  if (tid == 0 && trow0 + valid == total_rows) offsets[m] = prefix + s_pre[kTileRows];
 }
 
 __global__ void fill64_kernel(uint64_t* p, uint64_t v, uint64_t count) {
@@ -600,6 +523,17 @@ __global__ void fill32_kernel(uint32_t* p, uint32_t v, uint64_t count) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
     p[i] = v;
+}
+
+// Tuning knob: shape of the test kernel's row groups, iterations x rows
+// (SFC_TEST_VARIANT = 0: 1 x 16, 1: 4 x 4, 2: 2 x 8, 3: 8 x 2, 4: 16 x 1).
+// Same results for all.
+int test_variant() {
+  static const int v = [] {
+    const char* e = std::getenv("SFC_TEST_VARIANT");
+    return e ? std::atoi(e) : 0;
+  }();
+  return v;
 }
 
 uint32_t fill_blocks(uint64_t count) {
@@ -623,7 +557,7 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) 
 
 size_t query_scratch_bytes(uint64_t m) {
   const uint64_t nseg = 8 * m;   // room for the refined layout (eight slots per query)
-  return align256(nseg * 4) * 2 + align256((nseg + 1) * 8) + scan_scratch_bytes(nseg) +
+  return align256(nseg * 4) * 3 + align256((nseg + 1) * 8) + scan_scratch_bytes(nseg) +
          align256(64);
 }
 
@@ -632,18 +566,19 @@ void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs) {
   char* p = (char*)base;
   qs->slot_begin = (uint32_t*)p;  p += align256(nseg * 4);
   qs->slot_count = (uint32_t*)p;  p += align256(nseg * 4);
-  qs->seg_off = (uint64_t*)p;     p += align256((nseg + 1) * 8);
+  qs->slot_rows = (uint32_t*)p;   p += align256(nseg * 4);
+  qs->row_off = (uint64_t*)p;     p += align256((nseg + 1) * 8);
   qs->scan_tmp = (uint64_t*)p;    p += scan_scratch_bytes(nseg);
   qs->counters = (uint32_t*)p;
   qs->ss = 2;
 }
 
-size_t compact_scratch_bytes(uint64_t total_cand) {
-  uint64_t tiles = (total_cand + kCompactTile - 1) / kCompactTile;
+size_t compact_scratch_bytes(uint64_t total_rows) {
+  uint64_t tiles = (total_rows + kCompactTileRows - 1) / kCompactTileRows;
   if (tiles > kCompactChunkTiles) tiles = kCompactChunkTiles;
   if (tiles == 0) tiles = 1;
   return align256(tiles * kTileRows * 8) + align256(tiles * 4) + 2 * align256((tiles + 1) * 8) +
-         scan_scratch_bytes(tiles);
+         align256(tiles * kTileRows * 16) + scan_scratch_bytes(tiles);
 }
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
@@ -656,12 +591,14 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   if ((e = fill_u32(qs.counters, 0, 16, s)) != hipSuccess) return e;
   if (dbg_lo) refine = false;   // the inspected ranges are the method's merged ranges
   qs.ss = refine ? 3 : 2;
+  unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
   {
     ProfScope ps("ranges_search", s);
 #define SFC_RANGES(C, R)                                                                       \
   ranges_search<C, R><<<blocks, 256, 0, s>>>((const double2*)q, delta, m, keys, n, refine_min, \
-                                             qs.slot_begin, qs.slot_count, qs.counters, dbg_lo, \
-                                             dbg_hi, dbg_b, dbg_e, dbg_nr)
+                                             qs.slot_begin, qs.slot_count, qs.slot_rows,       \
+                                             qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e,  \
+                                             dbg_nr)
     if (curve == SFC_CURVE_HILBERT) {
       if (refine) SFC_RANGES(SFC_CURVE_HILBERT, true);
       else SFC_RANGES(SFC_CURVE_HILBERT, false);
@@ -672,17 +609,17 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
 #undef SFC_RANGES
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return scan_excl(qs.slot_count, qs.seg_off, m << qs.ss, nullptr, qs.scan_tmp, s);
+  return scan_excl(qs.slot_rows, qs.row_off, m << qs.ss, nullptr, qs.scan_tmp, s);
 }
 
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
-                          uint64_t total_cand, void* cscratch, uint64_t* offsets,
+                          uint64_t total_rows, void* cscratch, uint64_t* offsets,
                           uint32_t* out_ids, uint64_t cap, hipStream_t s) {
   hipError_t e;
   if (m == 0) return fill_u64(offsets, 0, 1, s);
-  if (total_cand == 0) return fill_u64(offsets, 0, m + 1, s);
-  const uint64_t tiles = (total_cand + kCompactTile - 1) / kCompactTile;
+  if (total_rows == 0) return fill_u64(offsets, 0, m + 1, s);
+  const uint64_t tiles = (total_rows + kCompactTileRows - 1) / kCompactTileRows;
   const uint64_t ch = tiles < kCompactChunkTiles ? tiles : kCompactChunkTiles;
   char* p = (char*)cscratch;
   uint64_t* masks = (uint64_t*)p;     p += align256(ch * kTileRows * 8);
@@ -690,25 +627,44 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
   uint64_t* toff[2];
   toff[0] = (uint64_t*)p;             p += align256((ch + 1) * 8);
   toff[1] = (uint64_t*)p;             p += align256((ch + 1) * 8);
+  uint4* meta = (uint4*)p;            p += align256(ch * kTileRows * 16);
   uint64_t* stmp = (uint64_t*)p;
+  const uint64_t nseg = m << qs.ss;
   const uint64_t* carry = nullptr;
   int buf = 0;
   for (uint64_t t0 = 0; t0 < tiles; t0 += kCompactChunkTiles, buf ^= 1) {
     const uint64_t nt = tiles - t0 < kCompactChunkTiles ? tiles - t0 : kCompactChunkTiles;
-    const uint64_t cbase = t0 * kCompactTile;
+    const uint64_t rbase = t0 * kCompactTileRows;
+    {
+      ProfScope ps("expand_rows", s);
+      const uint64_t rend = rbase + nt * kTileRows;
+      expand_rows<<<(uint32_t)((nseg + 255) / 256), 256, 0, s>>>(
+          qs.row_off, qs.slot_begin, qs.slot_count, nseg, qs.ss, rbase,
+          rend < total_rows ? rend : total_rows, meta);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     {
       ProfScope ps("compact_test", s);
-      compact_test<<<(uint32_t)nt, 256, 0, s>>>((const double2*)q, delta, m, (const double2*)pts,
-                                                npts, qs.seg_off, qs.slot_begin, qs.ss,
-                                                total_cand, cbase, masks, hits, qs.counters);
+#define SFC_TEST(R, I)                                                                          \
+  compact_test<R, I><<<(uint32_t)nt, 256, 0, s>>>((const double2*)q, delta, m,                \
+                                                  (const double2*)pts, npts, meta, total_rows, \
+                                                  rbase, masks, hits, qs.counters)
+      switch (test_variant()) {
+        case 1: SFC_TEST(4, 4); break;
+        case 2: SFC_TEST(8, 2); break;
+        case 3: SFC_TEST(2, 8); break;
+        case 4: SFC_TEST(1, 16); break;
+        default: SFC_TEST(16, 1); break;
+      }
+#undef SFC_TEST
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = scan_excl(hits, toff[buf], nt, carry, stmp, s)) != hipSuccess) return e;
     {
       ProfScope ps("compact_write", s);
-      compact_write<<<(uint32_t)nt, 256, 0, s>>>(ids, npts, m, qs.seg_off, qs.slot_begin, qs.ss,
-                                                 total_cand, cbase, masks, toff[buf], offsets,
-                                                 out_ids, cap, qs.counters);
+      compact_write<4, 4><<<(uint32_t)nt, 256, 0, s>>>(ids, npts, m, qs.row_off, qs.ss, meta,
+                                                       total_rows, rbase, masks, toff[buf],
+                                                       offsets, out_ids, cap);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     carry = toff[buf] + nt;
