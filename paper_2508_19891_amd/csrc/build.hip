@@ -13,6 +13,8 @@
 //                  last pass also gathers the points into key order.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "common.h"
 #include "curve.h"
 #include "internal.h"
@@ -210,14 +212,41 @@ __global__ void gather_points(const uint32_t* __restrict__ ids, const double2* _
   if (i < n) out[i] = xy[ids[i]];
 }
 
-constexpr int kItems = 16;
-constexpr uint64_t kSortTile = (uint64_t)kSortThreads * kItems;
+// Keys per thread of a radix pass (tuning knob SFC_SORT_ITEMS: 8, 12 or 16).
+int sort_items() {
+  static const int v = [] {
+    const char* e = std::getenv("SFC_SORT_ITEMS");
+    const int k = e ? std::atoi(e) : 16;
+    return (k == 8 || k == 12) ? k : 16;
+  }();
+  return v;
+}
+uint64_t sort_tile() { return (uint64_t)kSortThreads * sort_items(); }
+
+template <int ITEMS>
+hipError_t launch_pass(int pass, uint64_t tiles, const uint64_t* kin, const uint32_t* vin,
+                       uint64_t* kout, uint32_t* vout, uint64_t n, const uint32_t* hist,
+                       uint64_t* st, uint64_t* st_next, uint32_t* counter, uint32_t* err,
+                       const double* xy, double* xy_out, hipStream_t s) {
+  const int shift = 8 * pass;
+  if (pass == 0)
+    onesweep_pass<ITEMS, true, false><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
+        kin, vin, kout, vout, n, shift, hist, st, st_next, counter, err, nullptr, nullptr);
+  else if (pass == kDigits - 1)
+    onesweep_pass<ITEMS, false, true><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
+        kin, vin, kout, vout, n, shift, hist, st, st_next, counter, err, (const double2*)xy,
+        (double2*)xy_out);
+  else
+    onesweep_pass<ITEMS, false, false><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
+        kin, vin, kout, vout, n, shift, hist, st, st_next, counter, err, nullptr, nullptr);
+  return hipGetLastError();
+}
 
 }  // namespace
 
 // Device bytes of scratch needed by sort_build for n points.
 size_t build_scratch_bytes(uint64_t n, uint32_t* keygen_blocks) {
-  const uint64_t tiles = (n + kSortTile - 1) / kSortTile;
+  const uint64_t tiles = (n + sort_tile() - 1) / sort_tile();
   uint64_t blocks = (n + 1023) / 1024;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
@@ -254,7 +283,7 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   if (n == 0) return hipSuccess;
   uint32_t kblocks = 0;
   build_scratch_bytes(n, &kblocks);
-  const uint64_t tiles = (n + kSortTile - 1) / kSortTile;
+  const uint64_t tiles = (n + sort_tile() - 1) / sort_tile();
   char* p = (char*)scratch;
   uint64_t* keys_b = (uint64_t*)p;      p += align256(n * 8);
   uint32_t* ids_b = (uint32_t*)p;       p += align256(n * 4);
@@ -284,21 +313,23 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     uint32_t* vout = (pass & 1) ? ids_out : ids_b;
     uint64_t* st = status + (uint64_t)(pass & 1) * tiles * kRadix;
     uint64_t* st_next = status + (uint64_t)((pass + 1) & 1) * tiles * kRadix;
-    const int shift = 8 * pass;
     ProfScope ps("onesweep_pass", s);
-    if (pass == 0)
-      onesweep_pass<kItems, true, false><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
-          kin, vin, kout, vout, n, shift, hist + pass * kRadix, st, st_next, counters + pass,
-          err_host_visible, nullptr, nullptr);
-    else if (pass == kDigits - 1)
-      onesweep_pass<kItems, false, true><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
-          kin, vin, kout, vout, n, shift, hist + pass * kRadix, st, st_next, counters + pass,
-          err_host_visible, (const double2*)xy, (double2*)xy_out);
-    else
-      onesweep_pass<kItems, false, false><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
-          kin, vin, kout, vout, n, shift, hist + pass * kRadix, st, st_next, counters + pass,
-          err_host_visible, nullptr, nullptr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint32_t* hp = hist + pass * kRadix;
+    switch (sort_items()) {
+      case 16:
+        e = launch_pass<16>(pass, tiles, kin, vin, kout, vout, n, hp, st, st_next,
+                            counters + pass, err_host_visible, xy, xy_out, s);
+        break;
+      case 12:
+        e = launch_pass<12>(pass, tiles, kin, vin, kout, vout, n, hp, st, st_next,
+                            counters + pass, err_host_visible, xy, xy_out, s);
+        break;
+      default:
+        e = launch_pass<8>(pass, tiles, kin, vin, kout, vout, n, hp, st, st_next,
+                           counters + pass, err_host_visible, xy, xy_out, s);
+        break;
+    }
+    if (e != hipSuccess) return e;
     kin = kout;
     vin = vout;
   }
