@@ -69,6 +69,9 @@ typedef struct {
   int refine;   /* 0: scan the at most four cells of cells(Q) whole (Alg. 1);
                    1: split a crowded cell once and scan only its children
                    that meet the query box.  Same reported ids, same order. */
+  int learn_steps; /* training steps of the learned router when search is
+                      SFC_SEARCH_LEARNED; 0 = its quantile initialisation
+                      only; < 0 = the default (1024) */
   void* stream; /* hipStream_t, NULL = the null stream */
   /* Device memory hooks; alloc == NULL uses the library's caching pool over
      hipMalloc.  alloc returns NULL on failure.  release(NULL, ctx) is never
@@ -78,8 +81,8 @@ typedef struct {
   void* alloc_ctx;
 } sfc_options;
 
-/* Fills *opt with Morton curve, binary search, no refinement, null stream,
-   the pool. */
+/* Fills *opt with Morton curve, binary search, no refinement, default
+   training steps, null stream, the pool. */
 void sfc_default_options(sfc_options* opt);
 
 /* Human-readable name of a status code (static string). */
@@ -173,6 +176,55 @@ typedef struct {
   uint64_t reported;    /* ids reported */
 } sfc_query_stats;
 sfc_status sfc_last_query_stats(const sfc_index* h, sfc_query_stats* out);
+
+/*
+ * Learned index (an addition to the paper's method; binary search stays the
+ * reference and the fallback).  The router is a network 1 -> 32 -> 32 -> 1
+ * of clipped ramp units (min(max(w x + b, 0), 1)) with non-negative weights,
+ * evaluated in FP32 with fused multiply-adds in a fixed order; its input is
+ * the key's top 24 bits / 2^24 and its output, times 4096, picks one of 4096
+ * leaves.  Non-negative weights make the router monotone in the key, so each
+ * leaf holds a contiguous range keys[S..E) of the sorted keys.  A leaf
+ * predicts a rank by a least-squares line (FP64) and stores the exact range
+ * [elo, ehi] of (lower bound - prediction) over every query key that can
+ * reach it.  A lower bound searches that window, is verified against its
+ * neighbours, and falls back to a full binary search if the check fails, so
+ * results equal plain binary search for any model.
+ * The router is trained on the GPU (Adam, mean squared error to rank/n over
+ * 2^16 evenly spaced sorted keys, batches of 128), starting from ramps
+ * placed at the sample quantiles.
+ */
+typedef struct {
+  int fitted;                 /* 0 until a model exists */
+  uint32_t steps;             /* training steps used */
+  float loss_init, loss_final;/* sample MSE before / after training */
+  uint32_t leaves, leaves_nonempty, max_leaf;
+  double mean_window;         /* search window, averaged over the keys */
+  uint32_t max_window;
+  uint64_t endpoints_last;    /* learned lower bounds in the last batch */
+  uint64_t fallbacks_last;    /* of which fell back to binary search */
+} sfc_learned_info;
+
+/* Selects the search for later queries; SFC_SEARCH_LEARNED fits the model
+   first if there is none (n >= 2).  Synchronises the stream. */
+sfc_status sfc_set_search(sfc_index* h, int search);
+/* (Re)fits the learned index with the given training steps (< 0: the
+   handle's default).  SFC_ERR_UNSUPPORTED for n < 2. */
+sfc_status sfc_learned_fit(sfc_index* h, int steps);
+sfc_status sfc_learned_info_get(const sfc_index* h, sfc_learned_info* out);
+/* Router parameters (1153 floats, host): w1[32], b1[32], W2[32][32] (row =
+   output unit), b2[32], w3[32], b3.  SFC_ERR_UNSUPPORTED before a fit. */
+sfc_status sfc_learned_params(const sfc_index* h, float* params);
+/* Test hook for the fallback path: sets every leaf's window to the single
+   predicted position, so that most learned lower bounds fail verification
+   and fall back to binary search.  Results stay exact. */
+sfc_status sfc_learned_shrink_windows(sfc_index* h);
+/* Gradient (host, 1153 floats) and loss of the mean squared error of one
+   batch of count <= 128 samples (host x[count], t[count]) at the given
+   parameters (host), computed by the trainer's own GPU code.  For checking
+   the training kernels; synchronous, uses the null stream. */
+sfc_status sfc_learned_grad(const float* params, const float* x, const float* t,
+                            uint32_t count, float* grad, float* loss);
 
 /* Frees the handle and its device memory (NULL-safe).  Waits for the
    handle's stream first. */

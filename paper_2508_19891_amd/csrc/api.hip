@@ -13,6 +13,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "learned.h"
 #include "sfc.h"
 
 // ---- caching device allocator -----------------------------------------------
@@ -183,6 +184,11 @@ struct sfc_index {
   void* cws = nullptr;         // compaction scratch (grow-only)
   size_t cws_bytes = 0;
   sfc_query_stats last{};
+  // learned index
+  float* lparams = nullptr;        // device, sfc::kParams
+  sfc::LeafRec* lleaves = nullptr; // device, sfc::kLeaves
+  sfc_learned_info linfo{};
+  int learn_steps = 1024;
 };
 
 namespace {
@@ -248,6 +254,11 @@ void release_arrays(sfc_index* h) {
   h->alloc.put(h->cws);
   h->cws = nullptr;
   h->cws_bytes = 0;
+  h->alloc.put(h->lparams);
+  h->alloc.put(h->lleaves);
+  h->lparams = nullptr;
+  h->lleaves = nullptr;
+  h->linfo = sfc_learned_info{};
   h->keys = nullptr;
   h->ids = nullptr;
   h->xy = nullptr;
@@ -264,17 +275,70 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, uint64
   sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
   if (st != SFC_OK) return st;
   sfc::query_scratch_carve(h->ws, m, qs);
+  const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted;
   SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                             h->refine_min, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
+                             h->refine_min, learned ? h->lparams : nullptr,
+                             learned ? h->lleaves : nullptr, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e,
+                             dbg_nr, h->stream));
   uint64_t* pin = sfc::pinned_scratch();
   SFC_TRY(hipMemcpyAsync(pin, qs->row_off + (m << qs->ss), 8, hipMemcpyDeviceToHost, h->stream));
-  SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 32, hipMemcpyDeviceToHost, h->stream));
+  SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 48, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
   const uint32_t err = ((const uint32_t*)(pin + 1))[2];
   if (err & sfc::kErrInvalidQuery) return SFC_ERR_INVALID;
   if (err & (sfc::kErrLookback | sfc::kErrInternal)) return SFC_ERR_DEVICE;
   *total_rows = pin[0];
   *total_cand = pin[3];   // counters[4..5]
+  h->linfo.endpoints_last = learned ? pin[4] : 0;
+  h->linfo.fallbacks_last = learned ? pin[5] : 0;
+  return SFC_OK;
+}
+
+sfc_status fit_learned(sfc_index* h, int steps) {
+  if (h->n < 2) return SFC_ERR_UNSUPPORTED;
+  if (steps < 0) steps = h->learn_steps;
+  if (!h->lparams) h->lparams = (float*)h->alloc.get(sfc::kParams * sizeof(float));
+  if (!h->lleaves) h->lleaves = (sfc::LeafRec*)h->alloc.get(sfc::kLeaves * sizeof(sfc::LeafRec));
+  void* scratch = h->alloc.get(sfc::learned_scratch_bytes());
+  if (!h->lparams || !h->lleaves || !scratch) {
+    h->alloc.put(scratch);
+    return SFC_ERR_NOMEM;
+  }
+  float* losses = (float*)((char*)scratch + sfc::learned_scratch_bytes() - 256);
+  hipError_t e = sfc::learned_fit(h->keys, h->n, (uint32_t)steps, 1e-3f, h->lparams, h->lleaves,
+                                  scratch, losses, h->stream);
+  std::vector<sfc::LeafRec> leaves(sfc::kLeaves);
+  float lh[2] = {0.f, 0.f};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(leaves.data(), h->lleaves, sfc::kLeaves * sizeof(sfc::LeafRec),
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(lh, losses, 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  h->alloc.put(scratch);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return from_hip(e);
+  }
+  sfc_learned_info& I = h->linfo;
+  I.fitted = 1;
+  I.steps = (uint32_t)steps;
+  I.loss_init = lh[0];
+  I.loss_final = lh[1];
+  I.leaves = sfc::kLeaves;
+  I.leaves_nonempty = 0;
+  I.max_leaf = 0;
+  I.max_window = 0;
+  double wsum = 0.0;
+  for (const sfc::LeafRec& L : leaves) {
+    const uint32_t size = L.E - L.S;
+    if (size == 0) continue;
+    ++I.leaves_nonempty;
+    if (size > I.max_leaf) I.max_leaf = size;
+    const uint32_t win = (uint32_t)(L.ehi - L.elo + 1);
+    if (win > I.max_window) I.max_window = win;
+    wsum += (double)size * win;
+  }
+  I.mean_window = wsum / (double)h->n;
   return SFC_OK;
 }
 
@@ -287,6 +351,7 @@ void sfc_default_options(sfc_options* opt) {
   std::memset(opt, 0, sizeof(*opt));
   opt->curve = SFC_CURVE_MORTON;
   opt->search = SFC_SEARCH_BINARY;
+  opt->learn_steps = -1;
 }
 
 const char* sfc_status_string(sfc_status s) {
@@ -334,12 +399,12 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_i
   sfc_default_options(&o);
   if (opt) o = *opt;
   if (!out || (n > 0 && !xy) || n > 0xFFFFFFFFull || !valid_options(o)) return SFC_ERR_INVALID;
-  if (o.search == SFC_SEARCH_LEARNED) return SFC_ERR_UNSUPPORTED;
   sfc_index* h = new (std::nothrow) sfc_index();
   if (!h) return SFC_ERR_NOMEM;
   h->curve = o.curve;
   h->search = o.search;
   h->refine = o.refine;
+  if (o.learn_steps >= 0) h->learn_steps = o.learn_steps;
   if (const char* env = std::getenv("SFC_REFINE_MIN")) h->refine_min = (uint32_t)std::atoi(env);
   h->stream = (hipStream_t)o.stream;
   h->alloc.alloc = o.alloc;
@@ -376,6 +441,14 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_i
     }
     if (st != SFC_OK) {
       (void)hipStreamSynchronize(h->stream);
+      release_arrays(h);
+      delete h;
+      return st;
+    }
+  }
+  if (h->search == SFC_SEARCH_LEARNED && n >= 2) {
+    sfc_status st = fit_learned(h, -1);
+    if (st != SFC_OK) {
       release_arrays(h);
       delete h;
       return st;
@@ -460,6 +533,76 @@ sfc_status sfc_index_copy(const sfc_index* h, uint64_t* keys, uint32_t* ids, dou
 sfc_status sfc_last_query_stats(const sfc_index* h, sfc_query_stats* out) {
   if (!h || !out) return SFC_ERR_INVALID;
   *out = h->last;
+  return SFC_OK;
+}
+
+sfc_status sfc_set_search(sfc_index* h, int search) {
+  if (!h || (search != SFC_SEARCH_BINARY && search != SFC_SEARCH_LEARNED)) return SFC_ERR_INVALID;
+  if (search == SFC_SEARCH_LEARNED && !h->linfo.fitted && h->n >= 2) {
+    sfc_status st = fit_learned(h, -1);
+    if (st != SFC_OK) return st;
+  }
+  h->search = search;
+  return SFC_OK;
+}
+
+sfc_status sfc_learned_fit(sfc_index* h, int steps) {
+  if (!h) return SFC_ERR_INVALID;
+  return fit_learned(h, steps);
+}
+
+sfc_status sfc_learned_shrink_windows(sfc_index* h) {
+  if (!h) return SFC_ERR_INVALID;
+  if (!h->linfo.fitted) return SFC_ERR_UNSUPPORTED;
+  std::vector<sfc::LeafRec> leaves(sfc::kLeaves);
+  SFC_TRY(hipMemcpyAsync(leaves.data(), h->lleaves, sfc::kLeaves * sizeof(sfc::LeafRec),
+                         hipMemcpyDeviceToHost, h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  for (sfc::LeafRec& L : leaves) L.elo = L.ehi = 0;
+  SFC_TRY(hipMemcpyAsync(h->lleaves, leaves.data(), sfc::kLeaves * sizeof(sfc::LeafRec),
+                         hipMemcpyHostToDevice, h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  return SFC_OK;
+}
+
+sfc_status sfc_learned_info_get(const sfc_index* h, sfc_learned_info* out) {
+  if (!h || !out) return SFC_ERR_INVALID;
+  *out = h->linfo;
+  return SFC_OK;
+}
+
+sfc_status sfc_learned_params(const sfc_index* h, float* params) {
+  if (!h || !params) return SFC_ERR_INVALID;
+  if (!h->linfo.fitted) return SFC_ERR_UNSUPPORTED;
+  SFC_TRY(hipMemcpyAsync(params, h->lparams, sfc::kParams * sizeof(float), hipMemcpyDeviceToHost,
+                         h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  return SFC_OK;
+}
+
+sfc_status sfc_learned_grad(const float* params, const float* x, const float* t, uint32_t count,
+                            float* grad, float* loss) {
+  if (!params || !x || !t || !grad || !loss || count < 1 || count > 128) return SFC_ERR_INVALID;
+  sfc::Allocator a;
+  const size_t pb = sfc::align256(sfc::kParams * 4);
+  char* d = (char*)a.get(2 * pb + 2 * 512 + 256);
+  if (!d) return SFC_ERR_NOMEM;
+  float* dp = (float*)d;
+  float* dg = (float*)(d + pb);
+  float* dx = (float*)(d + 2 * pb);
+  float* dt = (float*)(d + 2 * pb + 512);
+  float* dl = (float*)(d + 2 * pb + 1024);
+  hipError_t e = hipMemcpy(dp, params, sfc::kParams * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dx, x, count * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dt, t, count * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = sfc::learned_grad(dp, dx, dt, (int)count, dg, dl, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(grad, dg, sfc::kParams * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(loss, dl, 4, hipMemcpyDeviceToHost);
+  a.put(d);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return from_hip(e);
+  }
   return SFC_OK;
 }
 

@@ -40,7 +40,8 @@ struct QueryScratch {
   uint32_t* slot_rows;    // per query slot: rows of 64 candidates
   uint64_t* row_off;      // exclusive scan of slot_rows (+ total at the end)
   uint64_t* scan_tmp;     // scan partials
-  uint32_t* counters;     // [2] error word, [4..5] total candidates (u64)
+  uint32_t* counters;     // [2] error word; u64 at [4]: candidates, [6]: learned
+                          // endpoints, [8]: learned fallbacks
   int ss;                 // log2 of the slots per query (2: method's ranges, 3: refined)
 };
 constexpr uint64_t kCompactTileRows = 64;           // rows of 64 candidates per tile
@@ -51,8 +52,11 @@ size_t compact_scratch_bytes(uint64_t total_rows);
 
 // Ranges and searches per query slot, then the scan of candidate counts into
 // segment offsets; optionally records the ranges (dbg_* may be null).
+struct LeafRec;
+// lparams/leaves non-null: searches go through the learned index.
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
-                         uint64_t n, int curve, bool refine, uint32_t refine_min, QueryScratch& qs,
+                         uint64_t n, int curve, bool refine, uint32_t refine_min,
+                         const float* lparams, const LeafRec* leaves, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s);
 // Test-and-compact over all candidate rows (total_rows known on the host);
@@ -61,5 +65,16 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t total_rows, void* cscratch, uint64_t* offsets,
                           uint32_t* out_ids, uint64_t cap, hipStream_t s);
+
+// ---- learned index (learned.hip) ----
+size_t learned_scratch_bytes();
+// Trains the router (steps Adam steps, 0 = quantile initialisation only) on
+// samples of the sorted keys, then fits the leaves.  params: kParams floats,
+// leaves: kLeaves records, losses: 2 floats (sample loss before / after).
+hipError_t learned_fit(const uint64_t* keys, uint64_t n, uint32_t steps, float lr, float* params,
+                       LeafRec* leaves, void* scratch, float* losses, hipStream_t s);
+// Gradient of one batch (cnt <= 128 samples) with the trainer's own code.
+hipError_t learned_grad(const float* params, const float* xs, const float* ts, int cnt,
+                        float* grad, float* loss, hipStream_t s);
 
 }  // namespace sfc

@@ -21,6 +21,7 @@
 #include "common.h"
 #include "curve.h"
 #include "internal.h"
+#include "learned.h"
 
 namespace sfc {
 
@@ -206,6 +207,24 @@ __device__ __forceinline__ void search_within(const uint64_t* __restrict__ keys,
   re = b + y;
 }
 
+// Index range [b, e) of the key interval [klo, khi]: two binary searches, or
+// the learned index (whose lower bounds are verified and fall back to binary
+// search, so the result is the same).  *fb counts the fallbacks.
+template <bool LEARNED>
+__device__ __forceinline__ void find_range(const uint64_t* __restrict__ keys, uint64_t n,
+                                           const float* __restrict__ P,
+                                           const LeafRec* __restrict__ leaves, uint64_t klo,
+                                           uint64_t khi, uint64_t& b, uint64_t& e, uint32_t& fb) {
+  if (!LEARNED) {
+    search_pair(keys, n, klo, khi, b, e);
+    return;
+  }
+  bool f0 = false, f1 = false;
+  b = learned_lower_bound(keys, n, P, leaves, klo, &f0);
+  e = khi == ~0ull ? n : learned_lower_bound(keys, n, P, leaves, khi + 1, &f1);
+  fb += (uint32_t)f0 + (uint32_t)f1;
+}
+
 // One lane per (query, slot).
 //   REFINE = false: four slots per query, slot r holds the r-th merged key
 //     range of cells(Q) and its index range (the method as stated: at most
@@ -217,10 +236,11 @@ __device__ __forceinline__ void search_within(const uint64_t* __restrict__ keys,
 //     (consecutive children in key order), and each run is located by two
 //     searches inside the cell's index range.  Only points outside the box
 //     are dropped, so the reported set and its order are unchanged.
-template <int CURVE, bool REFINE>
+template <int CURVE, bool REFINE, bool LEARNED>
 __global__ __launch_bounds__(256) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
-    const uint64_t* __restrict__ keys, uint64_t n, uint32_t refine_min,
+    const uint64_t* __restrict__ keys, uint64_t n, const float* __restrict__ P,
+    const LeafRec* __restrict__ leaves, uint32_t refine_min,
     uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
     uint64_t* __restrict__ dbg_lo, uint64_t* __restrict__ dbg_hi, uint64_t* __restrict__ dbg_b,
@@ -236,6 +256,7 @@ __global__ __launch_bounds__(256) void ranges_search(
   uint64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0, klo = 0, khi = 0;
   int nr = 0;
   bool bad = false;
+  uint32_t fb = 0, ends = 0;
   if (j < m) {
     const double2 qq = q[j];
     const double d = delta[j];
@@ -247,7 +268,8 @@ __global__ __launch_bounds__(256) void ranges_search(
       if (r < nr) {
         klo = lo[r];
         khi = hi[r];
-        search_pair(keys, n, klo, khi, b0, e0);
+        find_range<LEARNED>(keys, n, P, leaves, klo, khi, b0, e0, fb);
+        ends += 2;
       }
     } else {
       uint64_t lo[4], hi[4];
@@ -256,7 +278,8 @@ __global__ __launch_bounds__(256) void ranges_search(
       int L = 0;
       nr = query_cells<CURVE>(lut, qq.x, qq.y, d, lo, hi, cx, cy, &L, box);
       if (r < nr) {
-        search_pair(keys, n, lo[r], hi[r], b0, e0);
+        find_range<LEARNED>(keys, n, P, leaves, lo[r], hi[r], b0, e0, fb);
+        ends += 2;
         if (e0 - b0 > refine_min && L >= 1 && L < 32) {
           // Children at level L-1 that meet the box, in key order.
           const int Lc = L - 1;
@@ -300,11 +323,21 @@ __global__ __launch_bounds__(256) void ranges_search(
     }
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&counters[2], kErrInvalidQuery);
-  // Candidates of the wave, for the statistics.
+  // Candidates (and learned-index endpoints and fallbacks) of the wave, for
+  // the statistics.
   uint64_t wc = (e0 - b0) + (e1 - b1);
+  uint32_t wf = fb, we = ends;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) wc += __shfl_xor(wc, o, 64);
-  if (lane_id() == 0 && wc) atomicAdd(cand_total, (unsigned long long)wc);
+  for (int o = 32; o >= 1; o >>= 1) {
+    wc += __shfl_xor(wc, o, 64);
+    wf += __shfl_xor(wf, o, 64);
+    we += __shfl_xor(we, o, 64);
+  }
+  if (lane_id() == 0) {
+    if (wc) atomicAdd(cand_total, (unsigned long long)wc);
+    if (LEARNED && we) atomicAdd(cand_total + 1, (unsigned long long)we);
+    if (LEARNED && wf) atomicAdd(cand_total + 2, (unsigned long long)wf);
+  }
   if (j < m) {
     if (!REFINE) {
       slot_begin[g] = (uint32_t)b0;
@@ -582,7 +615,8 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
 }
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
-                         uint64_t n, int curve, bool refine, uint32_t refine_min, QueryScratch& qs,
+                         uint64_t n, int curve, bool refine, uint32_t refine_min,
+                         const float* lparams, const LeafRec* leaves, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s) {
   if (m == 0) return hipSuccess;
@@ -591,21 +625,28 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   if ((e = fill_u32(qs.counters, 0, 16, s)) != hipSuccess) return e;
   if (dbg_lo) refine = false;   // the inspected ranges are the method's merged ranges
   qs.ss = refine ? 3 : 2;
+  const bool learned = lparams != nullptr && leaves != nullptr;
   unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
   {
-    ProfScope ps("ranges_search", s);
-#define SFC_RANGES(C, R)                                                                       \
-  ranges_search<C, R><<<blocks, 256, 0, s>>>((const double2*)q, delta, m, keys, n, refine_min, \
-                                             qs.slot_begin, qs.slot_count, qs.slot_rows,       \
-                                             qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e,  \
-                                             dbg_nr)
+    ProfScope ps(learned ? "ranges_learned" : "ranges_search", s);
+#define SFC_RANGES(C, R, L)                                                                  \
+  ranges_search<C, R, L><<<blocks, 256, 0, s>>>(                                              \
+      (const double2*)q, delta, m, keys, n, lparams, leaves, refine_min, qs.slot_begin,      \
+      qs.slot_count, qs.slot_rows, qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr)
+#define SFC_RANGES_C(C)                         \
+  if (refine) {                                 \
+    if (learned) SFC_RANGES(C, true, true);     \
+    else SFC_RANGES(C, true, false);            \
+  } else {                                      \
+    if (learned) SFC_RANGES(C, false, true);    \
+    else SFC_RANGES(C, false, false);           \
+  }
     if (curve == SFC_CURVE_HILBERT) {
-      if (refine) SFC_RANGES(SFC_CURVE_HILBERT, true);
-      else SFC_RANGES(SFC_CURVE_HILBERT, false);
+      SFC_RANGES_C(SFC_CURVE_HILBERT)
     } else {
-      if (refine) SFC_RANGES(SFC_CURVE_MORTON, true);
-      else SFC_RANGES(SFC_CURVE_MORTON, false);
+      SFC_RANGES_C(SFC_CURVE_MORTON)
     }
+#undef SFC_RANGES_C
 #undef SFC_RANGES
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

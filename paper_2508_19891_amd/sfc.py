@@ -32,8 +32,12 @@ EXPORTS = [
     "sfc_default_options", "sfc_status_string", "sfc_build", "sfc_query_batch", "sfc_size",
     "sfc_index_view", "sfc_index_copy", "sfc_keys", "sfc_query_ranges",
     "sfc_last_query_stats", "sfc_free", "sfc_profile_enable", "sfc_profile_reset",
-    "sfc_profile_read", "sfc_pool_trim",
+    "sfc_profile_read", "sfc_pool_trim", "sfc_set_search", "sfc_learned_fit",
+    "sfc_learned_info_get", "sfc_learned_params", "sfc_learned_grad",
+    "sfc_learned_shrink_windows",
 ]
+
+NPARAM = 1153
 
 
 class SfcError(RuntimeError):
@@ -57,11 +61,21 @@ class Options(ctypes.Structure):
         ("curve", ctypes.c_int),
         ("search", ctypes.c_int),
         ("refine", ctypes.c_int),
+        ("learn_steps", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("alloc", ctypes.c_void_p),
         ("release", ctypes.c_void_p),
         ("alloc_ctx", ctypes.c_void_p),
     ]
+
+
+class LearnedInfo(ctypes.Structure):
+    _fields_ = [("fitted", ctypes.c_int), ("steps", ctypes.c_uint32),
+                ("loss_init", ctypes.c_float), ("loss_final", ctypes.c_float),
+                ("leaves", ctypes.c_uint32), ("leaves_nonempty", ctypes.c_uint32),
+                ("max_leaf", ctypes.c_uint32), ("mean_window", ctypes.c_double),
+                ("max_window", ctypes.c_uint32), ("endpoints_last", ctypes.c_uint64),
+                ("fallbacks_last", ctypes.c_uint64)]
 
 
 class QueryStats(ctypes.Structure):
@@ -111,6 +125,18 @@ def lib() -> ctypes.CDLL:
     L.sfc_profile_read.restype = i32
     L.sfc_pool_trim.argtypes = []
     L.sfc_pool_trim.restype = None
+    L.sfc_set_search.argtypes = [vp, i32]
+    L.sfc_set_search.restype = i32
+    L.sfc_learned_fit.argtypes = [vp, i32]
+    L.sfc_learned_fit.restype = i32
+    L.sfc_learned_info_get.argtypes = [vp, ctypes.POINTER(LearnedInfo)]
+    L.sfc_learned_info_get.restype = i32
+    L.sfc_learned_params.argtypes = [vp, vp]
+    L.sfc_learned_params.restype = i32
+    L.sfc_learned_grad.argtypes = [vp, vp, vp, u32, vp, vp]
+    L.sfc_learned_grad.restype = i32
+    L.sfc_learned_shrink_windows.argtypes = [vp]
+    L.sfc_learned_shrink_windows.restype = i32
     _lib = L
     return L
 
@@ -162,7 +188,7 @@ class Index:
     """An index built by sfc_build; freed by close() or on garbage collection."""
 
     def __init__(self, xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,
-                 refine: bool = False):
+                 refine: bool = False, learn_steps: int = -1):
         xy = _dev(xy, torch.float64, "xy")
         if xy.ndim != 2 or xy.shape[1] != 2:
             raise ValueError("xy must have shape (n, 2)")
@@ -172,6 +198,7 @@ class Index:
         opt.curve = curve
         opt.search = search
         opt.refine = 1 if refine else 0
+        opt.learn_steps = learn_steps
         opt.stream = current_stream_handle()
         h = ctypes.c_void_p()
         _check(L.sfc_build(_ptr(xy), xy.shape[0], ctypes.byref(opt), ctypes.byref(h)),
@@ -255,6 +282,28 @@ class Index:
                                       _ptr(b), _ptr(e), _ptr(nr)), "sfc_query_ranges")
         return klo, khi, b, e, nr
 
+    def set_search(self, search: int):
+        _check(lib().sfc_set_search(self.handle, search), "sfc_set_search")
+        self.search = search
+
+    def learned_fit(self, steps: int = -1):
+        _check(lib().sfc_learned_fit(self.handle, steps), "sfc_learned_fit")
+
+    def learned_info(self) -> dict:
+        i = LearnedInfo()
+        _check(lib().sfc_learned_info_get(self.handle, ctypes.byref(i)), "sfc_learned_info_get")
+        return {f: getattr(i, f) for f, _ in LearnedInfo._fields_}
+
+    def learned_params(self):
+        import numpy as np
+        out = np.zeros(NPARAM, np.float32)
+        _check(lib().sfc_learned_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)),
+               "sfc_learned_params")
+        return out
+
+    def learned_shrink_windows(self):
+        _check(lib().sfc_learned_shrink_windows(self.handle), "sfc_learned_shrink_windows")
+
     def last_stats(self) -> dict:
         s = QueryStats()
         _check(lib().sfc_last_query_stats(self.handle, ctypes.byref(s)), "sfc_last_query_stats")
@@ -273,6 +322,22 @@ def sfc_query_batch(index: Index, q: torch.Tensor, delta: torch.Tensor, **kw):
 
 def sfc_free(index: Index):
     index.close()
+
+
+def learned_grad(params, x, t):
+    """(gradient float32[1153], loss) of one batch through the GPU trainer's
+    backward code (host numpy arrays in and out)."""
+    import numpy as np
+    p = np.ascontiguousarray(params, np.float32)
+    x = np.ascontiguousarray(x, np.float32)
+    t = np.ascontiguousarray(t, np.float32)
+    g = np.zeros(NPARAM, np.float32)
+    loss = np.zeros(1, np.float32)
+    vp = ctypes.c_void_p
+    _check(lib().sfc_learned_grad(p.ctypes.data_as(vp), x.ctypes.data_as(vp),
+                                  t.ctypes.data_as(vp), len(x), g.ctypes.data_as(vp),
+                                  loss.ctypes.data_as(vp)), "sfc_learned_grad")
+    return g, float(loss[0])
 
 
 def profile_enable(on: bool = True):
