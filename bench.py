@@ -121,19 +121,21 @@ def main():
     d = torch.as_tensor(wl.delta).to(dev)
     offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
 
-    def run_mode(refine: bool):
+    def run_mode(refine: bool, search: int = sfc.BINARY):
         # Size the output once (capacity errors in the timed region would be a bug).
-        idx = sfc.Index(pts, curve, refine=refine)
+        idx = sfc.Index(pts, curve, refine=refine, search=search)
         _, ids0 = idx.query(q, d)
         total = int(ids0.numel())
         stats = idx.last_stats()
+        linfo = idx.learned_info() if search == sfc.LEARNED else None
         idx.close()
         out_ids = torch.empty(total + 1024, dtype=torch.int32, device=dev)
         del ids0
-        log(f"refine={refine}: reports per batch {total}, candidates {stats['candidates']}")
+        log(f"refine={refine} search={search}: reports per batch {total}, "
+            f"candidates {stats['candidates']}")
 
         def step():
-            ix = sfc.Index(pts, curve, refine=refine)
+            ix = sfc.Index(pts, curve, refine=refine, search=search)
             ix.query(q, d, out_ids=out_ids, out_offsets=offsets)
             ix.close()
 
@@ -151,6 +153,8 @@ def main():
         sfc.profile_enable(False)
         kern = sfc.profile_read()
         log(f"timed {args.steps} steps in {dt:.3f} s")
+        if linfo is not None:
+            stats = dict(stats, learned=linfo)
         return dt / args.steps * 1e3, kern, stats, total
 
     if args.only_refined:
@@ -158,6 +162,10 @@ def main():
     else:
         ms_paper, kern_paper, stats_paper, _ = run_mode(False)
     ms_step, kern, stats, total = run_mode(True)
+    if args.only_refined:
+        ms_l, kern_l, stats_l = float("nan"), {}, {}
+    else:
+        ms_l, kern_l, stats_l, _ = run_mode(True, sfc.LEARNED)
 
     # Algorithmic bytes per step of each kernel (what the method must move).
     cand, rep = stats["candidates"], total
@@ -199,6 +207,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name + "_hilbert", "n": n, "m": m, "curve": "hilbert",
                    "search": "binary", "ranges": "refined", "step": "build + one query batch"},
+        "learned_vs_bsearch": {
+            "step": "build + fit + one query batch (refined ranges, learned search)",
+            "queries_per_s": m / (ms_l * 1e-3), "ms_per_step": ms_l,
+            "search_ms_learned": kern_l.get("ranges_learned", (0, float("nan")))[1] / args.steps,
+            "search_ms_bsearch": kern.get("ranges_search", (0, float("nan")))[1] / args.steps,
+            "fit_ms": sum(v[1] for k, v in kern_l.items() if k.startswith("learned_"))
+            / args.steps,
+            "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern_l.items()},
+            "model": {k: stats_l.get("learned", {}).get(k) for k in
+                      ("steps", "loss_init", "loss_final", "leaves_nonempty", "max_leaf",
+                       "mean_window", "max_window", "endpoints_last", "fallbacks_last")},
+        },
         "paper_ranges": {"queries_per_s": m / (ms_paper * 1e-3), "ms_per_step": ms_paper,
                          "candidates_per_step": stats_paper["candidates"],
                          "kernels_ms_per_step": {k: v[1] / args.steps

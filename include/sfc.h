@@ -71,7 +71,7 @@ typedef struct {
                    that meet the query box.  Same reported ids, same order. */
   int learn_steps; /* training steps of the learned router when search is
                       SFC_SEARCH_LEARNED; 0 = its quantile initialisation
-                      only; < 0 = the default (1024) */
+                      only; < 0 = the default (256) */
   void* stream; /* hipStream_t, NULL = the null stream */
   /* Device memory hooks; alloc == NULL uses the library's caching pool over
      hipMalloc.  alloc returns NULL on failure.  release(NULL, ctx) is never

@@ -188,7 +188,7 @@ struct sfc_index {
   float* lparams = nullptr;        // device, sfc::kParams
   sfc::LeafRec* lleaves = nullptr; // device, sfc::kLeaves
   sfc_learned_info linfo{};
-  int learn_steps = 1024;
+  int learn_steps = 256;
 };
 
 namespace {
