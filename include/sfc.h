@@ -125,6 +125,25 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta,
                            uint64_t m, uint64_t* offsets, uint32_t* ids,
                            uint64_t ids_cap, uint64_t* total_out);
 
+/*
+ * Many independent point sets in one index (batched instances).  Set s owns
+ * the input points xy[set_off[s] .. set_off[s+1]) (set_off: host, n_sets + 1
+ * non-decreasing offsets, set_off[0] = 0, 1 <= n_sets <= 65536).  The
+ * construction runs every set in the same kernels: the key passes of the
+ * radix sort are followed by stable passes over the set index, so the sorted
+ * arrays hold the sets one after another, each in (key, id) order at its own
+ * input positions.  Ids are input positions, as in sfc_build.  Binary search
+ * only (SFC_SEARCH_LEARNED -> SFC_ERR_UNSUPPORTED).  Errors as sfc_build.
+ */
+sfc_status sfc_build_sets(const double* xy, const uint64_t* set_off, uint32_t n_sets,
+                          const sfc_options* opt, sfc_index** out);
+/* Queries over an index built by sfc_build_sets: query j is answered within
+   set qset[j] (device, m uint32); a set index >= n_sets is an invalid query.
+   Output and errors as sfc_query_batch. */
+sfc_status sfc_query_sets(sfc_index* h, const double* q, const double* delta,
+                          const uint32_t* qset, uint64_t m, uint64_t* offsets, uint32_t* ids,
+                          uint64_t ids_cap, uint64_t* total_out);
+
 /* Number of points currently reported by queries (live points). */
 uint64_t sfc_size(const sfc_index* h);
 

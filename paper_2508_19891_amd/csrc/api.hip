@@ -189,6 +189,9 @@ struct sfc_index {
   sfc::LeafRec* lleaves = nullptr; // device, sfc::kLeaves
   sfc_learned_info linfo{};
   int learn_steps = 256;
+  // point sets (sfc_build_sets)
+  uint32_t n_sets = 0;
+  uint64_t* set_off = nullptr;     // device, n_sets + 1
 };
 
 namespace {
@@ -256,6 +259,8 @@ void release_arrays(sfc_index* h) {
   h->cws_bytes = 0;
   h->alloc.put(h->lparams);
   h->alloc.put(h->lleaves);
+  h->alloc.put(h->set_off);
+  h->set_off = nullptr;
   h->lparams = nullptr;
   h->lleaves = nullptr;
   h->linfo = sfc_learned_info{};
@@ -268,18 +273,18 @@ void release_arrays(sfc_index* h) {
 
 // Runs ranges + searches + scan; on SFC_OK *total_rows holds the number of
 // candidate rows and *total_cand the number of candidates.
-sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, uint64_t m,
-                      sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
+sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const uint32_t* qset,
+                      uint64_t m, sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
                       uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                       uint32_t* dbg_nr) {
   sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
   if (st != SFC_OK) return st;
   sfc::query_scratch_carve(h->ws, m, qs);
-  const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted;
+  const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
   SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
                              h->refine_min, learned ? h->lparams : nullptr,
-                             learned ? h->lleaves : nullptr, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e,
-                             dbg_nr, h->stream));
+                             learned ? h->lleaves : nullptr, qset, qset ? h->set_off : nullptr,
+                             h->n_sets, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
   uint64_t* pin = sfc::pinned_scratch();
   SFC_TRY(hipMemcpyAsync(pin, qs->row_off + (m << qs->ss), 8, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 48, hipMemcpyDeviceToHost, h->stream));
@@ -394,7 +399,11 @@ sfc_status sfc_keys(const double* xy, uint64_t n, int curve, void* stream, uint6
   return st;
 }
 
-sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_index** out) {
+}  // extern "C"
+
+namespace {
+sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host, uint32_t n_sets,
+                      const sfc_options* opt, sfc_index** out) {
   sfc_options o;
   sfc_default_options(&o);
   if (opt) o = *opt;
@@ -411,6 +420,23 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_i
   h->alloc.release = o.release;
   h->alloc.ctx = o.alloc_ctx;
   h->n = n;
+  if (set_off_host) {
+    h->n_sets = n_sets;
+    h->set_off = (uint64_t*)h->alloc.get((n_sets + 1) * 8);
+    if (!h->set_off) {
+      delete h;
+      return SFC_ERR_NOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(h->set_off, set_off_host, (n_sets + 1) * 8,
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      release_arrays(h);
+      delete h;
+      return from_hip(e);
+    }
+  }
   if (n > 0) {
     h->keys = (uint64_t*)h->alloc.get(n * 8);
     h->ids = (uint32_t*)h->alloc.get(n * 4);
@@ -426,7 +452,8 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_i
     uint32_t* err = (uint32_t*)((char*)scratch + sb - 256);
     hipError_t e = sfc::fill_u32(err, 0, 1, h->stream);
     if (e == hipSuccess)
-      e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, h->xy, scratch, err, h->stream);
+      e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, h->xy, scratch, err, h->stream,
+                          h->set_off, h->n_sets);
     uint64_t w = 0;
     if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
     h->alloc.put(scratch);
@@ -446,7 +473,7 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_i
       return st;
     }
   }
-  if (h->search == SFC_SEARCH_LEARNED && n >= 2) {
+  if (h->search == SFC_SEARCH_LEARNED && n >= 2 && !set_off_host) {
     sfc_status st = fit_learned(h, -1);
     if (st != SFC_OK) {
       release_arrays(h);
@@ -458,17 +485,37 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_i
   return SFC_OK;
 }
 
-sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, uint64_t m,
-                           uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
-                           uint64_t* total_out) {
+}  // namespace
+
+extern "C" {
+
+sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt, sfc_index** out) {
+  return build_impl(xy, n, nullptr, 0, opt, out);
+}
+
+sfc_status sfc_build_sets(const double* xy, const uint64_t* set_off, uint32_t n_sets,
+                          const sfc_options* opt, sfc_index** out) {
+  if (!set_off || n_sets < 1 || n_sets > 65536 || set_off[0] != 0) return SFC_ERR_INVALID;
+  for (uint32_t i = 0; i < n_sets; ++i)
+    if (set_off[i + 1] < set_off[i]) return SFC_ERR_INVALID;
+  if (opt && opt->search == SFC_SEARCH_LEARNED) return SFC_ERR_UNSUPPORTED;
+  return build_impl(xy, set_off[n_sets], set_off, n_sets, opt, out);
+}
+
+}  // extern "C"
+
+namespace {
+sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const uint32_t* qset,
+                      uint64_t m, uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
+                      uint64_t* total_out) {
   if (!h || !offsets || !total_out || (m > 0 && (!q || !delta)) || (ids_cap > 0 && !ids))
     return SFC_ERR_INVALID;
   if (m > (1ull << 36)) return SFC_ERR_INVALID;
   sfc::QueryScratch qs{};
   uint64_t total_rows = 0, total_cand = 0;
   if (m > 0) {
-    sfc_status st = run_ranges(h, q, delta, m, &qs, &total_rows, &total_cand, nullptr, nullptr,
-                               nullptr, nullptr, nullptr);
+    sfc_status st = run_ranges(h, q, delta, qset, m, &qs, &total_rows, &total_cand, nullptr,
+                               nullptr, nullptr, nullptr, nullptr);
     if (st != SFC_OK) return st;
   } else {
     sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(0));
@@ -496,6 +543,23 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, u
   return total > ids_cap ? SFC_ERR_CAPACITY : SFC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, uint64_t m,
+                           uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
+                           uint64_t* total_out) {
+  return query_impl(h, q, delta, nullptr, m, offsets, ids, ids_cap, total_out);
+}
+
+sfc_status sfc_query_sets(sfc_index* h, const double* q, const double* delta,
+                          const uint32_t* qset, uint64_t m, uint64_t* offsets, uint32_t* ids,
+                          uint64_t ids_cap, uint64_t* total_out) {
+  if (!h || (m > 0 && !qset) || h->n_sets == 0) return SFC_ERR_INVALID;
+  return query_impl(h, q, delta, qset, m, offsets, ids, ids_cap, total_out);
+}
+
 sfc_status sfc_query_ranges(sfc_index* h, const double* q, const double* delta, uint64_t m,
                             uint64_t* key_lo, uint64_t* key_hi, uint64_t* begin, uint64_t* end,
                             uint32_t* nranges) {
@@ -504,8 +568,8 @@ sfc_status sfc_query_ranges(sfc_index* h, const double* q, const double* delta, 
   if (m == 0) return SFC_OK;
   sfc::QueryScratch qs{};
   uint64_t total_rows = 0, total_cand = 0;
-  return run_ranges(h, q, delta, m, &qs, &total_rows, &total_cand, key_lo, key_hi, begin, end,
-                    nranges);
+  return run_ranges(h, q, delta, nullptr, m, &qs, &total_rows, &total_cand, key_lo, key_hi, begin,
+                    end, nranges);
 }
 
 uint64_t sfc_size(const sfc_index* h) { return h ? h->n : 0; }

@@ -93,14 +93,24 @@ __global__ __launch_bounds__(256) void hist_reduce(const uint32_t* __restrict__ 
   if (s) atomicAdd(&hist[col], s);
 }
 
-// One stable pass of the LSD radix sort over digit (key >> shift) & 255.
-template <int ITEMS, bool FIRST, bool GATHER>
+// Digit of an element in a pass: a byte of the key, or (SETPASS) a byte of
+// the point set the element's id belongs to.  Padding (id 0xFFFFFFFF) takes
+// digit 255 so that it sorts last.
+template <bool SETPASS>
+__device__ __forceinline__ uint32_t pass_digit(uint64_t k, uint32_t v, int shift,
+                                               const uint32_t* __restrict__ set_id) {
+  if (!SETPASS) return (uint32_t)(k >> shift) & 255u;
+  return v == 0xFFFFFFFFu ? 255u : (set_id[v] >> shift) & 255u;
+}
+
+// One stable pass of the LSD radix sort over the digit pass_digit(...).
+template <int ITEMS, bool FIRST, bool GATHER, bool SETPASS>
 __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
     const uint32_t* __restrict__ hist, uint64_t* status, uint64_t* __restrict__ status_next,
     uint32_t* tile_counter, uint32_t* err, const double2* __restrict__ xy_in,
-    double2* __restrict__ xy_out) {
+    double2* __restrict__ xy_out, const uint32_t* __restrict__ set_id) {
   constexpr int kTile = kSortThreads * ITEMS;
   __shared__ union {
     uint32_t wave_hist[kSortWaves][kRadix];
@@ -133,7 +143,7 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
       val[i] = FIRST ? (uint32_t)idx : vin[idx];
     } else {
       key[i] = ~0ull;   // padding sorts to the end of the last digit
-      val[i] = 0;
+      val[i] = 0xFFFFFFFFu;
     }
   }
 
@@ -143,7 +153,7 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
   const uint64_t below_mask = lanemask_lt();
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
+    const uint32_t d = pass_digit<SETPASS>(key[i], val[i], shift, set_id);
     uint64_t match = ~0ull;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
   uint32_t lpos[ITEMS];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t dd = (uint32_t)(key[i] >> shift) & 255u;
+    const uint32_t dd = pass_digit<SETPASS>(key[i], val[i], shift, set_id);
     lpos[i] = s_local[dd] + sm.wave_hist[w][dd] + rank[i];
   }
   __syncthreads();
@@ -195,7 +205,7 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
   for (uint32_t j = tid; j < valid; j += kSortThreads) {
     const uint64_t k = sm.st.k[j];
     const uint32_t v = sm.st.v[j];
-    const uint32_t pos = s_gbase[(uint32_t)(k >> shift) & 255u] + j;
+    const uint32_t pos = s_gbase[pass_digit<SETPASS>(k, v, shift, set_id)] + j;
     if (pos >= n || (GATHER && v >= n)) {   // cannot happen with a consistent histogram
       atomicOr(err, kErrInternal);
       continue;
@@ -223,26 +233,67 @@ int sort_items() {
 }
 uint64_t sort_tile() { return (uint64_t)kSortThreads * sort_items(); }
 
+// Set id of every input position (sets are contiguous in the input).
+__global__ void fill_set_ids(const uint64_t* __restrict__ set_off, uint32_t n_sets, uint64_t n,
+                             uint32_t* __restrict__ set_id) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t lo = 0, len = n_sets + 1;   // last s with set_off[s] <= i
+  while (len > 0) {
+    const uint32_t h = len >> 1;
+    if (set_off[lo + h] <= i) {
+      lo += h + 1;
+      len -= h + 1;
+    } else {
+      len = h;
+    }
+  }
+  set_id[i] = lo - 1;
+}
+
+// Histograms of the set passes: hist[b][d] = points of sets whose byte b is d.
+__global__ void set_histograms(const uint64_t* __restrict__ set_off, uint32_t n_sets,
+                               uint32_t* __restrict__ hist) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sets) return;
+  const uint32_t size = (uint32_t)(set_off[s + 1] - set_off[s]);
+  if (size == 0) return;
+  atomicAdd(&hist[s & 255u], size);
+  atomicAdd(&hist[kRadix + ((s >> 8) & 255u)], size);
+}
+
 template <int ITEMS>
-hipError_t launch_pass(int pass, uint64_t tiles, const uint64_t* kin, const uint32_t* vin,
-                       uint64_t* kout, uint32_t* vout, uint64_t n, const uint32_t* hist,
-                       uint64_t* st, uint64_t* st_next, uint32_t* counter, uint32_t* err,
-                       const double* xy, double* xy_out, hipStream_t s) {
-  const int shift = 8 * pass;
-  if (pass == 0)
-    onesweep_pass<ITEMS, true, false><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
-        kin, vin, kout, vout, n, shift, hist, st, st_next, counter, err, nullptr, nullptr);
-  else if (pass == kDigits - 1)
-    onesweep_pass<ITEMS, false, true><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
-        kin, vin, kout, vout, n, shift, hist, st, st_next, counter, err, (const double2*)xy,
-        (double2*)xy_out);
-  else
-    onesweep_pass<ITEMS, false, false><<<(uint32_t)tiles, kSortThreads, 0, s>>>(
-        kin, vin, kout, vout, n, shift, hist, st, st_next, counter, err, nullptr, nullptr);
+hipError_t launch_pass(bool first, bool gather, bool setpass, int shift, uint64_t tiles,
+                       const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
+                       uint64_t n, const uint32_t* hist, uint64_t* st, uint64_t* st_next,
+                       uint32_t* counter, uint32_t* err, const double* xy, double* xy_out,
+                       const uint32_t* set_id, hipStream_t s) {
+  const dim3 g((uint32_t)tiles), b(kSortThreads);
+  const double2* xi = (const double2*)xy;
+  double2* xo = (double2*)xy_out;
+#define SFC_PASS(F, G, S)                                                                   \
+  onesweep_pass<ITEMS, F, G, S><<<g, b, 0, s>>>(kin, vin, kout, vout, n, shift, hist, st,   \
+                                                st_next, counter, err, G ? xi : nullptr,    \
+                                                G ? xo : nullptr, set_id)
+  if (setpass) {
+    if (gather) SFC_PASS(false, true, true);
+    else SFC_PASS(false, false, true);
+  } else if (first) {
+    SFC_PASS(true, false, false);
+  } else if (gather) {
+    SFC_PASS(false, true, false);
+  } else {
+    SFC_PASS(false, false, false);
+  }
+#undef SFC_PASS
   return hipGetLastError();
 }
 
 }  // namespace
+
+// Number of stable set passes after the key passes: one byte of the set
+// index per pass.
+int set_passes(uint32_t n_sets) { return n_sets <= 1 ? 0 : (n_sets <= 256 ? 1 : 2); }
 
 // Device bytes of scratch needed by sort_build for n points.
 size_t build_scratch_bytes(uint64_t n, uint32_t* keygen_blocks) {
@@ -255,9 +306,10 @@ size_t build_scratch_bytes(uint64_t n, uint32_t* keygen_blocks) {
   b += align256(n * 8);                             // keys ping
   b += align256(n * 4);                             // ids ping
   b += align256(blocks * kDigits * kRadix * 4);     // per-block histograms
-  b += align256(kDigits * kRadix * 4);              // histogram
+  b += align256((kDigits + 2) * kRadix * 4);        // histograms (keys, set bytes)
   b += align256(2 * tiles * kRadix * 8);            // look-back status (two buffers)
   b += align256(64);                                // counters + error word
+  b += align256(n * 4);                             // set id per input point
   return b;
 }
 
@@ -277,9 +329,14 @@ hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, 
 
 // Full construction into the caller's sorted arrays (keys_out, ids_out,
 // xy_out, each with room for n entries); scratch holds build_scratch_bytes(n).
+// With n_sets > 1 sets (set_off: device, n_sets + 1 offsets into the input),
+// stable passes over the set index follow the key passes, so that the result
+// is ordered by (set, key, id) and set s keeps the positions
+// [set_off[s], set_off[s+1]).  No host synchronisation: the whole sequence can
+// be recorded into a graph.
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err_host_visible,
-                      hipStream_t s) {
+                      hipStream_t s, const uint64_t* set_off, uint32_t n_sets) {
   if (n == 0) return hipSuccess;
   uint32_t kblocks = 0;
   build_scratch_bytes(n, &kblocks);
@@ -288,16 +345,24 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   uint64_t* keys_b = (uint64_t*)p;      p += align256(n * 8);
   uint32_t* ids_b = (uint32_t*)p;       p += align256(n * 4);
   uint32_t* partial = (uint32_t*)p;     p += align256((uint64_t)kblocks * kDigits * kRadix * 4);
-  uint32_t* hist = (uint32_t*)p;        p += align256(kDigits * kRadix * 4);
+  uint32_t* hist = (uint32_t*)p;        p += align256((kDigits + 2) * kRadix * 4);
   uint64_t* status = (uint64_t*)p;      p += align256(2 * tiles * kRadix * 8);
-  uint32_t* counters = (uint32_t*)p;    // [0..7] tile counters, [8] error
+  uint32_t* counters = (uint32_t*)p;    p += align256(64);   // tile counter per pass
+  uint32_t* set_id = (uint32_t*)p;
+
+  const int sp = set_off ? set_passes(n_sets) : 0;
+  const int passes = kDigits + sp;
+  // Pass p writes the output buffers when passes - 1 - p is even, so that the
+  // last pass lands in them; the keys are generated into the other buffer.
+  auto out_is_final = [&](int pass) { return ((passes - 1 - pass) & 1) == 0; };
+  uint64_t* keys_first = out_is_final(0) ? keys_b : keys_out;
 
   hipError_t e;
   // The first look-back buffer is zeroed by keygen_hist, the second by the
   // first pass.
-  if ((e = fill_u32(hist, 0, kDigits * kRadix, s)) != hipSuccess) return e;
+  if ((e = fill_u32(hist, 0, (kDigits + 2) * kRadix, s)) != hipSuccess) return e;
   if ((e = fill_u32(counters, 0, 16, s)) != hipSuccess) return e;
-  e = launch_keys(xy, n, curve, keys_out, err_host_visible, partial, kblocks, status,
+  e = launch_keys(xy, n, curve, keys_first, err_host_visible, partial, kblocks, status,
                   tiles * kRadix, s);
   if (e != hipSuccess) return e;
   {
@@ -306,29 +371,34 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     hist_reduce<<<dim3(kDigits, chunks), 256, 0, s>>>(partial, kblocks, hist);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const uint64_t* kin = keys_out;
+  if (sp > 0) {
+    ProfScope ps("set_prep", s);
+    fill_set_ids<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(set_off, n_sets, n, set_id);
+    set_histograms<<<(n_sets + 255) / 256, 256, 0, s>>>(set_off, n_sets, hist + kDigits * kRadix);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const uint64_t* kin = keys_first;
   const uint32_t* vin = nullptr;
-  for (int pass = 0; pass < kDigits; ++pass) {
-    uint64_t* kout = (pass & 1) ? keys_out : keys_b;
-    uint32_t* vout = (pass & 1) ? ids_out : ids_b;
+  for (int pass = 0; pass < passes; ++pass) {
+    const bool fin = out_is_final(pass);
+    uint64_t* kout = fin ? keys_out : keys_b;
+    uint32_t* vout = fin ? ids_out : ids_b;
     uint64_t* st = status + (uint64_t)(pass & 1) * tiles * kRadix;
     uint64_t* st_next = status + (uint64_t)((pass + 1) & 1) * tiles * kRadix;
-    ProfScope ps("onesweep_pass", s);
+    const bool setpass = pass >= kDigits;
+    const int shift = setpass ? 8 * (pass - kDigits) : 8 * pass;
+    const bool gather = pass == passes - 1;
+    ProfScope ps(setpass ? "set_pass" : "onesweep_pass", s);
     const uint32_t* hp = hist + pass * kRadix;
+#define SFC_LAUNCH(I)                                                                          \
+  launch_pass<I>(pass == 0, gather, setpass, shift, tiles, kin, vin, kout, vout, n, hp, st,   \
+                 st_next, counters + pass, err_host_visible, xy, xy_out, set_id, s)
     switch (sort_items()) {
-      case 16:
-        e = launch_pass<16>(pass, tiles, kin, vin, kout, vout, n, hp, st, st_next,
-                            counters + pass, err_host_visible, xy, xy_out, s);
-        break;
-      case 12:
-        e = launch_pass<12>(pass, tiles, kin, vin, kout, vout, n, hp, st, st_next,
-                            counters + pass, err_host_visible, xy, xy_out, s);
-        break;
-      default:
-        e = launch_pass<8>(pass, tiles, kin, vin, kout, vout, n, hp, st, st_next,
-                           counters + pass, err_host_visible, xy, xy_out, s);
-        break;
+      case 16: e = SFC_LAUNCH(16); break;
+      case 12: e = SFC_LAUNCH(12); break;
+      default: e = SFC_LAUNCH(8); break;
     }
+#undef SFC_LAUNCH
     if (e != hipSuccess) return e;
     kin = kout;
     vin = vout;

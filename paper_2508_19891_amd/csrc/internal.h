@@ -22,7 +22,7 @@ hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, 
                        hipStream_t s);
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
-                      hipStream_t s);
+                      hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0);
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,
                          hipStream_t s);
 
@@ -54,9 +54,12 @@ size_t compact_scratch_bytes(uint64_t total_rows);
 // segment offsets; optionally records the ranges (dbg_* may be null).
 struct LeafRec;
 // lparams/leaves non-null: searches go through the learned index.
+// qset/set_off non-null: query j searches only set qset[j] (positions
+// [set_off[s], set_off[s+1]) of the sorted arrays).
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min,
-                         const float* lparams, const LeafRec* leaves, QueryScratch& qs,
+                         const float* lparams, const LeafRec* leaves, const uint32_t* qset,
+                         const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s);
 // Test-and-compact over all candidate rows (total_rows known on the host);

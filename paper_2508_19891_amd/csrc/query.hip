@@ -240,8 +240,8 @@ template <int CURVE, bool REFINE, bool LEARNED>
 __global__ __launch_bounds__(256) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint64_t* __restrict__ keys, uint64_t n, const float* __restrict__ P,
-    const LeafRec* __restrict__ leaves, uint32_t refine_min,
-    uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
+    const LeafRec* __restrict__ leaves, uint32_t refine_min, const uint32_t* __restrict__ qset,
+    const uint64_t* __restrict__ set_off, uint32_t n_sets, uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
     uint64_t* __restrict__ dbg_lo, uint64_t* __restrict__ dbg_hi, uint64_t* __restrict__ dbg_b,
     uint64_t* __restrict__ dbg_e, uint32_t* __restrict__ dbg_nr) {
@@ -257,7 +257,21 @@ __global__ __launch_bounds__(256) void ranges_search(
   int nr = 0;
   bool bad = false;
   uint32_t fb = 0, ends = 0;
-  if (j < m) {
+  // With point sets, a query searches only its own set's keys: positions
+  // [base, base + nn) of the sorted arrays.
+  uint64_t base = 0, nn = n;
+  if (j < m && qset) {
+    const uint32_t sj = qset[j];
+    if (sj >= n_sets) {
+      bad = true;
+      nn = 0;
+    } else {
+      base = set_off[sj];
+      nn = set_off[sj + 1] - base;
+    }
+  }
+  const uint64_t* kseg = keys + base;
+  if (j < m && !bad) {
     const double2 qq = q[j];
     const double d = delta[j];
     if (!(finite(qq.x) && finite(qq.y) && finite(d) && d >= 0.0)) {
@@ -268,7 +282,9 @@ __global__ __launch_bounds__(256) void ranges_search(
       if (r < nr) {
         klo = lo[r];
         khi = hi[r];
-        find_range<LEARNED>(keys, n, P, leaves, klo, khi, b0, e0, fb);
+        find_range<LEARNED>(kseg, nn, P, leaves, klo, khi, b0, e0, fb);
+        b0 += base;
+        e0 += base;
         ends += 2;
       }
     } else {
@@ -278,7 +294,9 @@ __global__ __launch_bounds__(256) void ranges_search(
       int L = 0;
       nr = query_cells<CURVE>(lut, qq.x, qq.y, d, lo, hi, cx, cy, &L, box);
       if (r < nr) {
-        find_range<LEARNED>(keys, n, P, leaves, lo[r], hi[r], b0, e0, fb);
+        find_range<LEARNED>(kseg, nn, P, leaves, lo[r], hi[r], b0, e0, fb);
+        b0 += base;
+        e0 += base;
         ends += 2;
         if (e0 - b0 > refine_min && L >= 1 && L < 32) {
           // Children at level L-1 that meet the box, in key order.
@@ -616,7 +634,8 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min,
-                         const float* lparams, const LeafRec* leaves, QueryScratch& qs,
+                         const float* lparams, const LeafRec* leaves, const uint32_t* qset,
+                         const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s) {
   if (m == 0) return hipSuccess;
@@ -625,13 +644,14 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   if ((e = fill_u32(qs.counters, 0, 16, s)) != hipSuccess) return e;
   if (dbg_lo) refine = false;   // the inspected ranges are the method's merged ranges
   qs.ss = refine ? 3 : 2;
-  const bool learned = lparams != nullptr && leaves != nullptr;
+  const bool learned = lparams != nullptr && leaves != nullptr && qset == nullptr;
   unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
   {
     ProfScope ps(learned ? "ranges_learned" : "ranges_search", s);
 #define SFC_RANGES(C, R, L)                                                                  \
   ranges_search<C, R, L><<<blocks, 256, 0, s>>>(                                              \
-      (const double2*)q, delta, m, keys, n, lparams, leaves, refine_min, qs.slot_begin,      \
+      (const double2*)q, delta, m, keys, n, lparams, leaves, refine_min, qset, set_off,      \
+      n_sets, qs.slot_begin,                                                                  \
       qs.slot_count, qs.slot_rows, qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr)
 #define SFC_RANGES_C(C)                         \
   if (refine) {                                 \

@@ -34,7 +34,7 @@ EXPORTS = [
     "sfc_last_query_stats", "sfc_free", "sfc_profile_enable", "sfc_profile_reset",
     "sfc_profile_read", "sfc_pool_trim", "sfc_set_search", "sfc_learned_fit",
     "sfc_learned_info_get", "sfc_learned_params", "sfc_learned_grad",
-    "sfc_learned_shrink_windows",
+    "sfc_learned_shrink_windows", "sfc_build_sets", "sfc_query_sets",
 ]
 
 NPARAM = 1153
@@ -137,6 +137,10 @@ def lib() -> ctypes.CDLL:
     L.sfc_learned_grad.restype = i32
     L.sfc_learned_shrink_windows.argtypes = [vp]
     L.sfc_learned_shrink_windows.restype = i32
+    L.sfc_build_sets.argtypes = [vp, vp, u32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.sfc_build_sets.restype = i32
+    L.sfc_query_sets.argtypes = [vp, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(u64)]
+    L.sfc_query_sets.restype = i32
     _lib = L
     return L
 
@@ -188,7 +192,9 @@ class Index:
     """An index built by sfc_build; freed by close() or on garbage collection."""
 
     def __init__(self, xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,
-                 refine: bool = False, learn_steps: int = -1):
+                 refine: bool = False, learn_steps: int = -1, set_off=None):
+        """set_off (host sequence of n_sets + 1 offsets): build independent
+        point sets with sfc_build_sets; query them with query_sets."""
         xy = _dev(xy, torch.float64, "xy")
         if xy.ndim != 2 or xy.shape[1] != 2:
             raise ValueError("xy must have shape (n, 2)")
@@ -201,8 +207,18 @@ class Index:
         opt.learn_steps = learn_steps
         opt.stream = current_stream_handle()
         h = ctypes.c_void_p()
-        _check(L.sfc_build(_ptr(xy), xy.shape[0], ctypes.byref(opt), ctypes.byref(h)),
-               "sfc_build")
+        if set_off is None:
+            _check(L.sfc_build(_ptr(xy), xy.shape[0], ctypes.byref(opt), ctypes.byref(h)),
+                   "sfc_build")
+            self.n_sets = 0
+        else:
+            import numpy as np
+            so = np.ascontiguousarray(set_off, np.uint64)
+            if int(so[-1]) != xy.shape[0]:
+                raise ValueError("set_off[-1] must equal the number of points")
+            _check(L.sfc_build_sets(_ptr(xy), so.ctypes.data_as(ctypes.c_void_p), len(so) - 1,
+                                    ctypes.byref(opt), ctypes.byref(h)), "sfc_build_sets")
+            self.n_sets = len(so) - 1
         self._h = h
         self.curve = curve
         self.search = search
@@ -264,6 +280,30 @@ class Index:
         if st == SFC_ERR_CAPACITY:
             raise CapacityError(st, "sfc_query_batch", int(total.value))
         _check(st, "sfc_query_batch")
+        return offsets, out_ids[: int(total.value)]
+
+    def query_sets(self, q: torch.Tensor, delta: torch.Tensor, qset: torch.Tensor,
+                   out_ids: torch.Tensor | None = None, out_offsets: torch.Tensor | None = None):
+        """Queries of an index of point sets; qset (m,) int32 holds each
+        query's set.  Returns (offsets int64[m+1], ids int32[total])."""
+        q = _dev(q, torch.float64, "q")
+        delta = _dev(delta, torch.float64, "delta")
+        qset = _dev(qset, torch.int32, "qset")
+        m = q.shape[0]
+        offsets = out_offsets if out_offsets is not None else torch.empty(
+            m + 1, dtype=torch.int64, device=self.device)
+        cap_given = out_ids is not None
+        if out_ids is None:
+            out_ids = torch.empty(max(16 * m, 1024), dtype=torch.int32, device=self.device)
+        total = ctypes.c_uint64(0)
+        args = (self.handle, _ptr(q), _ptr(delta), _ptr(qset), m, _ptr(offsets))
+        st = lib().sfc_query_sets(*args, _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY and not cap_given:
+            out_ids = torch.empty(max(int(total.value), 1), dtype=torch.int32, device=self.device)
+            st = lib().sfc_query_sets(*args, _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY:
+            raise CapacityError(st, "sfc_query_sets", int(total.value))
+        _check(st, "sfc_query_sets")
         return offsets, out_ids[: int(total.value)]
 
     def query_ranges(self, q: torch.Tensor, delta: torch.Tensor):
