@@ -144,6 +144,37 @@ sfc_status sfc_query_sets(sfc_index* h, const double* q, const double* delta,
                           const uint32_t* qset, uint64_t m, uint64_t* offsets, uint32_t* ids,
                           uint64_t ids_cap, uint64_t* total_out);
 
+/*
+ * Graphs: one construction or one query batch recorded once (HIP graph) and
+ * replayed by a single launch.  Every size that depends on the data lives in
+ * device memory, so no step synchronises with the host inside the graph.
+ *
+ * sfc_graph_build: replaying rebuilds h in place (keys, ids, points; the
+ *   learned model is not refitted) from the current contents of xy (device,
+ *   same n and sets as h was built with).  sfc_graph_wait reports
+ *   SFC_ERR_DOMAIN for a coordinate outside [0,1).
+ * sfc_graph_query: one batch of m >= 1 queries over fixed buffers (q, delta,
+ *   qset or NULL, offsets, ids as in sfc_query_batch / sfc_query_sets).
+ *   max_rows bounds the candidate rows (64 candidates each, at most 2^25);
+ *   a batch with more rows makes sfc_graph_wait return SFC_ERR_CAPACITY
+ *   (offsets and ids then unspecified; build a graph with a larger bound).
+ *   An output larger than ids_cap returns SFC_ERR_CAPACITY with *total_out
+ *   set.  The graph reads h's arrays at replay time; it must not outlive h.
+ * sfc_graph_launch enqueues one replay on h's stream; sfc_graph_wait waits
+ *   for it and checks its flags.  A graph holds its own scratch, so two graphs
+ *   of one handle may be launched on the handle's stream one after another,
+ *   not concurrently.
+ */
+typedef struct sfc_graph sfc_graph;
+sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out);
+sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
+                           const uint32_t* qset, uint64_t m, uint64_t max_rows,
+                           uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
+                           sfc_graph** out);
+sfc_status sfc_graph_launch(sfc_graph* g);
+sfc_status sfc_graph_wait(sfc_graph* g, uint64_t* total_out);
+void sfc_graph_free(sfc_graph* g);   /* NULL-safe; waits for h's stream */
+
 /* Number of points currently reported by queries (live points). */
 uint64_t sfc_size(const sfc_index* h);
 

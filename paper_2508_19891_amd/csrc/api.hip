@@ -2,6 +2,7 @@
 // host-side sequencing of the construction and query kernels.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -114,10 +115,12 @@ hipEvent_t take_event(ProfState& P) {
 }
 }  // namespace
 
+std::atomic<int> g_capturing{0};   // no timing events inside graph capture
+
 ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s) {
   ProfState& P = prof();
   std::lock_guard<std::mutex> g(P.mu);
-  if (!P.on) return;
+  if (!P.on || g_capturing.load() > 0) return;
   hipEvent_t e = take_event(P);
   if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
 }
@@ -526,8 +529,8 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
     sfc_status st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(total_rows));
     if (st != SFC_OK) return st;
   }
-  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_rows, h->cws, offsets,
-                              ids, ids_cap, h->stream));
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_rows, false, h->cws,
+                              offsets, ids, ids_cap, h->stream));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
   if (m > 0) {
@@ -668,6 +671,164 @@ sfc_status sfc_learned_grad(const float* params, const float* x, const float* t,
     return from_hip(e);
   }
   return SFC_OK;
+}
+
+}  // extern "C"
+
+struct sfc_graph {
+  sfc_index* h = nullptr;
+  int kind = 0;                 // 0: construction, 1: query batch
+  hipStream_t cap = nullptr;    // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* scratch = nullptr;      // construction scratch, or query scratch
+  void* cscratch = nullptr;     // compaction scratch (queries)
+  uint32_t* err = nullptr;      // construction error word
+  sfc::QueryScratch qs{};
+  uint64_t m = 0, max_rows = 0, cap_ids = 0;
+  uint64_t* offsets = nullptr;
+};
+
+namespace {
+
+void graph_release(sfc_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  if (g->h) {
+    g->h->alloc.put(g->scratch);
+    g->h->alloc.put(g->cscratch);
+  }
+  delete g;
+}
+
+// Records fn(stream) into g's graph and instantiates it.
+template <typename F>
+sfc_status graph_capture(sfc_graph* g, F fn) {
+  SFC_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+  SFC_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+  sfc::g_capturing.fetch_add(1);
+  hipError_t e = fn(g->cap);
+  sfc::g_capturing.fetch_sub(1);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(g->cap, &graph);
+  if (e == hipSuccess) e = e2;
+  g->graph = graph;
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return from_hip(e);
+  }
+  return SFC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out) {
+  if (!h || !out || (h->n > 0 && !xy)) return SFC_ERR_INVALID;
+  if (h->n == 0) return SFC_ERR_UNSUPPORTED;
+  sfc_graph* g = new (std::nothrow) sfc_graph();
+  if (!g) return SFC_ERR_NOMEM;
+  g->h = h;
+  g->kind = 0;
+  const size_t sb = sfc::build_scratch_bytes(h->n, nullptr) + 256;
+  g->scratch = h->alloc.get(sb);
+  if (!g->scratch) {
+    graph_release(g);
+    return SFC_ERR_NOMEM;
+  }
+  g->err = (uint32_t*)((char*)g->scratch + sb - 256);
+  sfc_status st = graph_capture(g, [&](hipStream_t s) {
+    hipError_t e = sfc::fill_u32(g->err, 0, 1, s);
+    if (e == hipSuccess)
+      e = sfc::sort_build(xy, h->n, h->curve, h->keys, h->ids, h->xy, g->scratch, g->err, s,
+                          h->set_off, h->n_sets);
+    return e;
+  });
+  if (st != SFC_OK) {
+    graph_release(g);
+    return st;
+  }
+  *out = g;
+  return SFC_OK;
+}
+
+sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
+                           const uint32_t* qset, uint64_t m, uint64_t max_rows, uint64_t* offsets,
+                           uint32_t* ids, uint64_t ids_cap, sfc_graph** out) {
+  if (!h || !out || !offsets || m == 0 || !q || !delta || (ids_cap > 0 && !ids)) return SFC_ERR_INVALID;
+  if (qset && h->n_sets == 0) return SFC_ERR_INVALID;
+  if (max_rows == 0 || max_rows > sfc::kCompactChunkTiles * sfc::kCompactTileRows)
+    return SFC_ERR_INVALID;
+  sfc_graph* g = new (std::nothrow) sfc_graph();
+  if (!g) return SFC_ERR_NOMEM;
+  g->h = h;
+  g->kind = 1;
+  g->m = m;
+  g->max_rows = max_rows;
+  g->cap_ids = ids_cap;
+  g->offsets = offsets;
+  g->scratch = h->alloc.get(sfc::query_scratch_bytes(m));
+  g->cscratch = h->alloc.get(sfc::compact_scratch_bytes(max_rows));
+  if (!g->scratch || !g->cscratch) {
+    graph_release(g);
+    return SFC_ERR_NOMEM;
+  }
+  sfc::query_scratch_carve(g->scratch, m, &g->qs);
+  const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
+  sfc_status st = graph_capture(g, [&](hipStream_t s) {
+    hipError_t e = sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
+                                      h->refine_min, learned ? h->lparams : nullptr,
+                                      learned ? h->lleaves : nullptr, qset,
+                                      qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr,
+                                      nullptr, nullptr, nullptr, nullptr, s);
+    if (e == hipSuccess)
+      e = sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, g->qs, max_rows, true,
+                              g->cscratch, offsets, ids, ids_cap, s);
+    return e;
+  });
+  if (st != SFC_OK) {
+    graph_release(g);
+    return st;
+  }
+  *out = g;
+  return SFC_OK;
+}
+
+sfc_status sfc_graph_launch(sfc_graph* g) {
+  if (!g || !g->exec) return SFC_ERR_INVALID;
+  SFC_TRY(hipGraphLaunch(g->exec, g->h->stream));
+  return SFC_OK;
+}
+
+sfc_status sfc_graph_wait(sfc_graph* g, uint64_t* total_out) {
+  if (!g) return SFC_ERR_INVALID;
+  sfc_index* h = g->h;
+  if (g->kind == 0) {
+    uint64_t w = 0;
+    SFC_TRY(read_words(g->err, &w, 1, h->stream));
+    if ((uint32_t)w & sfc::kErrDomain) return SFC_ERR_DOMAIN;
+    if ((uint32_t)w & (sfc::kErrLookback | sfc::kErrInternal)) return SFC_ERR_DEVICE;
+    return SFC_OK;
+  }
+  uint64_t cw[2];
+  uint64_t total = 0;
+  SFC_TRY(read_words(g->qs.counters, cw, 2, h->stream));
+  SFC_TRY(read_words(g->offsets + g->m, &total, 1, h->stream));
+  const uint32_t err = ((const uint32_t*)cw)[2];
+  if (err & sfc::kErrInvalidQuery) return SFC_ERR_INVALID;
+  if (err & (sfc::kErrLookback | sfc::kErrInternal)) return SFC_ERR_DEVICE;
+  if (err & sfc::kErrOverflow) return SFC_ERR_CAPACITY;   // more candidate rows than max_rows
+  if (total_out) *total_out = total;
+  return total > g->cap_ids ? SFC_ERR_CAPACITY : SFC_OK;
+}
+
+void sfc_graph_free(sfc_graph* g) {
+  if (g && g->h) (void)hipStreamSynchronize(g->h->stream);
+  graph_release(g);
 }
 
 void sfc_free(sfc_index* h) {

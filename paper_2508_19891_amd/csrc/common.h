@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 
@@ -28,6 +29,7 @@ constexpr uint32_t kErrDomain = 1u;
 constexpr uint32_t kErrInvalidQuery = 2u;
 constexpr uint32_t kErrLookback = 4u;
 constexpr uint32_t kErrInternal = 8u;   // an index outside its array (never expected)
+constexpr uint32_t kErrOverflow = 16u;  // more candidate rows than a fixed plan holds
 
 __device__ __forceinline__ uint64_t ld_acquire_agent(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -97,6 +99,9 @@ struct ProfScope {
   ProfScope(const char* name, hipStream_t s);
   ~ProfScope();
 };
+
+// Nonzero while a stream capture is in progress (no timing events then).
+extern std::atomic<int> g_capturing;
 
 // Pinned host scratch for small device-to-host reads.
 uint64_t* pinned_scratch();

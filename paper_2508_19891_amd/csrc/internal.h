@@ -62,12 +62,19 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
                          const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s);
-// Test-and-compact over all candidate rows (total_rows known on the host);
-// cscratch holds compact_scratch_bytes(total_rows).
+// Test-and-compact over the candidate rows.  device_sized = false: max_rows
+// is the exact row count (known on the host), processed in chunks.
+// device_sized = true: max_rows is a capacity, the count is read on the
+// device (a plan for graph capture); more rows raise kErrOverflow.  cscratch
+// holds compact_scratch_bytes(max_rows).
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
-                          uint64_t total_rows, void* cscratch, uint64_t* offsets,
-                          uint32_t* out_ids, uint64_t cap, hipStream_t s);
+                          uint64_t max_rows, bool device_sized, void* cscratch,
+                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s);
+// Scan with the element count in device memory (count_dev <= max_count).
+hipError_t scan_excl_dev(const uint32_t* in, uint64_t* out, const uint32_t* count_dev,
+                         uint64_t max_count, const uint64_t* carry_in, uint64_t* partial,
+                         hipStream_t s);
 
 // ---- learned index (learned.hip) ----
 size_t learned_scratch_bytes();

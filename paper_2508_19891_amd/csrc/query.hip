@@ -414,8 +414,10 @@ __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ 
                                                    const uint32_t* __restrict__ slot_begin,
                                                    const uint32_t* __restrict__ slot_count,
                                                    uint64_t nseg, int ss, uint64_t rbase,
-                                                   uint64_t rend, uint4* __restrict__ row_meta) {
+                                                   uint64_t row_end, uint4* __restrict__ row_meta) {
   __shared__ uint64_t st[257];
+  const uint64_t total = row_off[nseg];
+  const uint64_t rend = total < row_end ? total : row_end;
   const uint64_t s0 = (uint64_t)blockIdx.x * 256;
   const uint32_t tid = threadIdx.x;
   st[tid] = row_off[s0 + tid < nseg ? s0 + tid : nseg];
@@ -451,49 +453,59 @@ template <int ROWS, int ITERS>
 __global__ __launch_bounds__(256) void compact_test(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const double2* __restrict__ pts, uint64_t npts, const uint4* __restrict__ row_meta,
-    uint64_t total_rows, uint64_t rbase, uint64_t* __restrict__ masks,
-    uint32_t* __restrict__ tile_hits, uint32_t* counters) {
+    const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
+    bool flag_overflow, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits,
+    uint32_t* counters) {
   __shared__ uint32_t s_cnt[4];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const uint64_t tile = blockIdx.x;
-  const uint64_t wrow0 = rbase + tile * kTileRows + (uint64_t)w * kWaveRows;
-  uint32_t cnt = 0;
-  for (int it = 0; it < ITERS; ++it) {
-    const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;   // first row of the group
-    uint4 md = make_uint4(0, 0, 0, 0);
-    if (lane < (uint32_t)ROWS && g0 + lane < total_rows) md = row_meta[g0 + lane - rbase];
-    uint32_t pos[ROWS];
-    double qx[ROWS], qy[ROWS], dd[ROWS];
-    bool act[ROWS];
+  const uint64_t total_all = *total_rows_dev;
+  const uint64_t total_rows = total_all < row_end ? total_all : row_end;
+  const uint64_t ntiles = (total_rows - rbase + kTileRows - 1) / kTileRows;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t wrow0 = rbase + tile * kTileRows + (uint64_t)w * kWaveRows;
+    uint32_t cnt = 0;
+    for (int it = 0; it < ITERS; ++it) {
+      const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;   // first row of the group
+      uint4 md = make_uint4(0, 0, 0, 0);
+      if (lane < (uint32_t)ROWS && g0 + lane < total_rows) md = row_meta[g0 + lane - rbase];
+      uint32_t pos[ROWS];
+      double qx[ROWS], qy[ROWS], dd[ROWS];
+      bool act[ROWS];
 #pragma unroll
-    for (int jr = 0; jr < ROWS; ++jr) {
-      const uint32_t pb = __builtin_amdgcn_readlane(md.x, jr);
-      const uint32_t nv = __builtin_amdgcn_readlane(md.y, jr);
-      const uint32_t qi = __builtin_amdgcn_readlane(md.z, jr);
-      const uint64_t p64 = (uint64_t)pb + lane;
-      act[jr] = lane < nv && p64 < npts && qi < m;
-      pos[jr] = act[jr] ? (uint32_t)p64 : 0u;
-      const uint32_t qs = qi < m ? qi : 0u;
-      const double2 qq = q[qs];
-      qx[jr] = qq.x;
-      qy[jr] = qq.y;
-      dd[jr] = delta[qs];
+      for (int jr = 0; jr < ROWS; ++jr) {
+        const uint32_t pb = __builtin_amdgcn_readlane(md.x, jr);
+        const uint32_t nv = __builtin_amdgcn_readlane(md.y, jr);
+        const uint32_t qi = __builtin_amdgcn_readlane(md.z, jr);
+        const uint64_t p64 = (uint64_t)pb + lane;
+        act[jr] = lane < nv && p64 < npts && qi < m;
+        pos[jr] = act[jr] ? (uint32_t)p64 : 0u;
+        const uint32_t qs = qi < m ? qi : 0u;
+        const double2 qq = q[qs];
+        qx[jr] = qq.x;
+        qy[jr] = qq.y;
+        dd[jr] = delta[qs];
+      }
+      double2 pv[ROWS];
+#pragma unroll
+      for (int jr = 0; jr < ROWS; ++jr)
+        if (act[jr]) pv[jr] = pts[pos[jr]];
+#pragma unroll
+      for (int jr = 0; jr < ROWS; ++jr) {
+        const bool hit = act[jr] && within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]);
+        const uint64_t bal = __ballot(hit);
+        cnt += (uint32_t)__popcll(bal);
+        if (lane == 0) masks[tile * kTileRows + (uint64_t)(w * ITERS + it) * ROWS + jr] = bal;
+      }
     }
-    double2 pv[ROWS];
-#pragma unroll
-    for (int jr = 0; jr < ROWS; ++jr)
-      if (act[jr]) pv[jr] = pts[pos[jr]];
-#pragma unroll
-    for (int jr = 0; jr < ROWS; ++jr) {
-      const bool hit = act[jr] && within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]);
-      const uint64_t bal = __ballot(hit);
-      cnt += (uint32_t)__popcll(bal);
-      if (lane == 0) masks[tile * kTileRows + (uint64_t)(w * ITERS + it) * ROWS + jr] = bal;
-    }
+    if (lane == 0) s_cnt[w] = cnt;
+    __syncthreads();
+    if (tid == 0) tile_hits[tile] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    __syncthreads();
   }
-  if (lane == 0) s_cnt[w] = cnt;
-  __syncthreads();
-  if (tid == 0) tile_hits[tile] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+  if (blockIdx.x == 0 && tid == 0) {
+    counters[12] = (uint32_t)ntiles;   // tile count for the scan that follows
+    if (flag_overflow && total_all > row_end) atomicOr(&counters[2], kErrOverflow);
+  }
 }
 
 // Pass 2: the ids of the accepted candidates at the tile's output offset, in
@@ -504,65 +516,74 @@ template <int ROWS, int ITERS>
 __global__ __launch_bounds__(256) void compact_write(
     const uint32_t* __restrict__ ids, uint64_t npts, uint64_t m,
     const uint64_t* __restrict__ row_off, int ss, const uint4* __restrict__ row_meta,
-    uint64_t total_rows, uint64_t rbase, const uint64_t* __restrict__ masks,
-    const uint64_t* __restrict__ tile_off, uint64_t* __restrict__ offsets,
-    uint32_t* __restrict__ out_ids, uint64_t cap) {
+    const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
+    const uint64_t* __restrict__ masks, const uint64_t* __restrict__ tile_off,
+    uint64_t* __restrict__ offsets, uint32_t* __restrict__ out_ids, uint64_t cap) {
   __shared__ uint64_t s_mask[kTileRows];
   __shared__ uint32_t s_pre[kTileRows + 1];
   __shared__ uint64_t s_qrange[2];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const uint64_t tile = blockIdx.x;
-  const uint64_t trow0 = rbase + tile * kTileRows;
-  if (tid < kTileRows) s_mask[tid] = masks[tile * kTileRows + tid];
-  if (tid == 64) s_qrange[0] = first_query_at(row_off, m, ss, trow0);
-  if (tid == 128) {
-    const uint64_t tend = trow0 + kTileRows;
-    s_qrange[1] = tend >= total_rows ? m : first_query_at(row_off, m, ss, tend);
-  }
-  __syncthreads();
-  if (tid < 64) {   // exclusive scan of the row counts (one wave)
-    const uint32_t v = (uint32_t)__popcll(s_mask[tid]);
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o, 64);
-      if (lane >= (uint32_t)o) x += y;
-    }
-    s_pre[tid] = x - v;
-    if (tid == 63) s_pre[kTileRows] = x;
-  }
-  __syncthreads();
-  const uint64_t prefix = tile_off[tile];
+  const uint64_t total_all = *total_rows_dev;
+  const uint64_t total_rows = total_all < row_end ? total_all : row_end;
+  const uint64_t ntiles = (total_rows - rbase + kTileRows - 1) / kTileRows;
   const uint64_t below = lanemask_lt();
-  const uint64_t wrow0 = trow0 + (uint64_t)w * kWaveRows;
-  for (int it = 0; it < ITERS; ++it) {
-    const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;
-    const int ri0 = (w * ITERS + it) * ROWS;
-    uint32_t pbase = 0;
-    if (lane < (uint32_t)ROWS && g0 + lane < total_rows) pbase = row_meta[g0 + lane - rbase].x;
-    uint32_t idv[ROWS];
-    uint64_t opos[ROWS];
-    bool act[ROWS];
-#pragma unroll
-    for (int jr = 0; jr < ROWS; ++jr) {
-      const uint64_t mask = s_mask[ri0 + jr];
-      const uint64_t p64 = (uint64_t)__builtin_amdgcn_readlane(pbase, jr) + lane;
-      act[jr] = ((mask >> lane) & 1ull) && p64 < npts;
-      opos[jr] = prefix + s_pre[ri0 + jr] + (uint64_t)__popcll(mask & below);
-      idv[jr] = act[jr] ? ids[p64] : 0u;
+  if (ntiles == 0 && rbase == 0 && blockIdx.x == 0) {   // no candidates at all
+    for (uint64_t qq = tid; qq <= m; qq += 256) offsets[qq] = 0;
+    return;
+  }
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t trow0 = rbase + tile * kTileRows;
+    if (tid < kTileRows) s_mask[tid] = masks[tile * kTileRows + tid];
+    if (tid == 64) s_qrange[0] = first_query_at(row_off, m, ss, trow0);
+    if (tid == 128) {
+      const uint64_t tend = trow0 + kTileRows;
+      s_qrange[1] = tend >= total_rows ? m : first_query_at(row_off, m, ss, tend);
     }
+    __syncthreads();
+    if (tid < 64) {   // exclusive scan of the row counts (one wave)
+      const uint32_t v = (uint32_t)__popcll(s_mask[tid]);
+      uint32_t x = v;
 #pragma unroll
-    for (int jr = 0; jr < ROWS; ++jr)
-      if (act[jr] && opos[jr] < cap) out_ids[opos[jr]] = idv[jr];
-  }
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+      }
+      s_pre[tid] = x - v;
+      if (tid == 63) s_pre[kTileRows] = x;
+    }
+    __syncthreads();
+    const uint64_t prefix = tile_off[tile];
+    const uint64_t wrow0 = trow0 + (uint64_t)w * kWaveRows;
+    for (int it = 0; it < ITERS; ++it) {
+      const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;
+      const int ri0 = (w * ITERS + it) * ROWS;
+      uint32_t pbase = 0;
+      if (lane < (uint32_t)ROWS && g0 + lane < total_rows) pbase = row_meta[g0 + lane - rbase].x;
+      uint32_t idv[ROWS];
+      uint64_t opos[ROWS];
+      bool act[ROWS];
+#pragma unroll
+      for (int jr = 0; jr < ROWS; ++jr) {
+        const uint64_t mask = s_mask[ri0 + jr];
+        const uint64_t p64 = (uint64_t)__builtin_amdgcn_readlane(pbase, jr) + lane;
+        act[jr] = ((mask >> lane) & 1ull) && p64 < npts;
+        opos[jr] = prefix + s_pre[ri0 + jr] + (uint64_t)__popcll(mask & below);
+        idv[jr] = act[jr] ? ids[p64] : 0u;
+      }
+#pragma unroll
+      for (int jr = 0; jr < ROWS; ++jr)
+        if (act[jr] && opos[jr] < cap) out_ids[opos[jr]] = idv[jr];
+    }
 
-  const uint64_t valid = total_rows - trow0 < (uint64_t)kTileRows ? total_rows - trow0
-                                                                  : (uint64_t)kTileRows;
-  for (uint64_t qq = s_qrange[0] + tid; qq < s_qrange[1]; qq += 256) {
-    const uint64_t x = row_off[qq << ss] - trow0;
-    offsets[qq] = prefix + (x >= valid ? s_pre[kTileRows] : s_pre[x]);
+    const uint64_t valid = total_rows - trow0 < (uint64_t)kTileRows ? total_rows - trow0
+                                                                    : (uint64_t)kTileRows;
+    for (uint64_t qq = s_qrange[0] + tid; qq < s_qrange[1]; qq += 256) {
+      const uint64_t x = row_off[qq << ss] - trow0;
+      offsets[qq] = prefix + (x >= valid ? s_pre[kTileRows] : s_pre[x]);
+    }
+    if (tid == 0 && trow0 + valid == total_rows) offsets[m] = prefix + s_pre[kTileRows];
+    __syncthreads();
   }
-  if (tid == 0 && trow0 + valid == total_rows) offsets[m] = prefix + s_pre[kTileRows];
 }
 
 __global__ void fill64_kernel(uint64_t* p, uint64_t v, uint64_t count) {
@@ -673,43 +694,56 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   return scan_excl(qs.slot_rows, qs.row_off, m << qs.ss, nullptr, qs.scan_tmp, s);
 }
 
+// Blocks of the compaction kernels (grid-stride over tiles beyond this).
+constexpr uint64_t kCompactGrid = 4096;
+
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
-                          uint64_t total_rows, void* cscratch, uint64_t* offsets,
-                          uint32_t* out_ids, uint64_t cap, hipStream_t s) {
+                          uint64_t max_rows, bool device_sized, void* cscratch,
+                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s) {
   hipError_t e;
   if (m == 0) return fill_u64(offsets, 0, 1, s);
-  if (total_rows == 0) return fill_u64(offsets, 0, m + 1, s);
-  const uint64_t tiles = (total_rows + kCompactTileRows - 1) / kCompactTileRows;
-  const uint64_t ch = tiles < kCompactChunkTiles ? tiles : kCompactChunkTiles;
-  char* p = (char*)cscratch;
-  uint64_t* masks = (uint64_t*)p;     p += align256(ch * kTileRows * 8);
-  uint32_t* hits = (uint32_t*)p;      p += align256(ch * 4);
-  uint64_t* toff[2];
-  toff[0] = (uint64_t*)p;             p += align256((ch + 1) * 8);
-  toff[1] = (uint64_t*)p;             p += align256((ch + 1) * 8);
-  uint4* meta = (uint4*)p;            p += align256(ch * kTileRows * 16);
-  uint64_t* stmp = (uint64_t*)p;
   const uint64_t nseg = m << qs.ss;
+  const uint64_t* total_dev = qs.row_off + nseg;
+  // Host-sized: max_rows is the exact number of rows, processed in chunks of
+  // at most kCompactChunkTiles tiles.  Device-sized: max_rows is a capacity;
+  // one chunk, the count is read on the device, overflow is flagged.
+  const uint64_t tiles_all = (max_rows + kCompactTileRows - 1) / kCompactTileRows;
+  if (!device_sized && max_rows == 0) return fill_u64(offsets, 0, m + 1, s);
+  const uint64_t ch_tiles = tiles_all < kCompactChunkTiles ? (tiles_all ? tiles_all : 1)
+                                                           : kCompactChunkTiles;
+  if (device_sized && tiles_all > kCompactChunkTiles) return hipErrorInvalidValue;
+  char* p = (char*)cscratch;
+  uint64_t* masks = (uint64_t*)p;     p += align256(ch_tiles * kTileRows * 8);
+  uint32_t* hits = (uint32_t*)p;      p += align256(ch_tiles * 4);
+  uint64_t* toff[2];
+  toff[0] = (uint64_t*)p;             p += align256((ch_tiles + 1) * 8);
+  toff[1] = (uint64_t*)p;             p += align256((ch_tiles + 1) * 8);
+  uint4* meta = (uint4*)p;            p += align256(ch_tiles * kTileRows * 16);
+  uint64_t* stmp = (uint64_t*)p;
   const uint64_t* carry = nullptr;
   int buf = 0;
-  for (uint64_t t0 = 0; t0 < tiles; t0 += kCompactChunkTiles, buf ^= 1) {
-    const uint64_t nt = tiles - t0 < kCompactChunkTiles ? tiles - t0 : kCompactChunkTiles;
-    const uint64_t rbase = t0 * kCompactTileRows;
+  const uint64_t chunks = device_sized ? 1 : (tiles_all + kCompactChunkTiles - 1) / kCompactChunkTiles;
+  for (uint64_t c = 0; c < chunks; ++c, buf ^= 1) {
+    const uint64_t rbase = c * kCompactChunkTiles * kCompactTileRows;
+    const uint64_t nt = device_sized ? ch_tiles
+                                     : (tiles_all - c * kCompactChunkTiles < kCompactChunkTiles
+                                            ? tiles_all - c * kCompactChunkTiles
+                                            : kCompactChunkTiles);
+    const uint64_t row_end = device_sized ? max_rows : rbase + nt * kCompactTileRows;
+    const uint32_t grid = (uint32_t)(nt < kCompactGrid ? (nt ? nt : 1) : kCompactGrid);
     {
       ProfScope ps("expand_rows", s);
-      const uint64_t rend = rbase + nt * kTileRows;
       expand_rows<<<(uint32_t)((nseg + 255) / 256), 256, 0, s>>>(
-          qs.row_off, qs.slot_begin, qs.slot_count, nseg, qs.ss, rbase,
-          rend < total_rows ? rend : total_rows, meta);
+          qs.row_off, qs.slot_begin, qs.slot_count, nseg, qs.ss, rbase, row_end, meta);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {
       ProfScope ps("compact_test", s);
-#define SFC_TEST(R, I)                                                                          \
-  compact_test<R, I><<<(uint32_t)nt, 256, 0, s>>>((const double2*)q, delta, m,                \
-                                                  (const double2*)pts, npts, meta, total_rows, \
-                                                  rbase, masks, hits, qs.counters)
+#define SFC_TEST(R, I)                                                                       \
+  compact_test<R, I><<<grid, 256, 0, s>>>((const double2*)q, delta, m, (const double2*)pts, \
+                                          npts, meta, total_dev, rbase, row_end,            \
+                                          device_sized, masks, hits, qs.counters)
       switch (test_variant()) {
         case 1: SFC_TEST(4, 4); break;
         case 2: SFC_TEST(8, 2); break;
@@ -720,15 +754,16 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
 #undef SFC_TEST
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = scan_excl(hits, toff[buf], nt, carry, stmp, s)) != hipSuccess) return e;
+    if ((e = scan_excl_dev(hits, toff[buf], qs.counters + 12, nt, carry, stmp, s)) != hipSuccess)
+      return e;
     {
       ProfScope ps("compact_write", s);
-      compact_write<4, 4><<<(uint32_t)nt, 256, 0, s>>>(ids, npts, m, qs.row_off, qs.ss, meta,
-                                                       total_rows, rbase, masks, toff[buf],
-                                                       offsets, out_ids, cap);
+      compact_write<4, 4><<<grid, 256, 0, s>>>(ids, npts, m, qs.row_off, qs.ss, meta, total_dev,
+                                               rbase, row_end, masks, toff[buf], offsets,
+                                               out_ids, cap);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    carry = toff[buf] + nt;
+    carry = toff[buf] + nt;   // the chunk's total, read by the next chunk's scan
   }
   return hipSuccess;
 }

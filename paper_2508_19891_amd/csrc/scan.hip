@@ -109,7 +109,82 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks(const uint32_t* __re
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = partial[gridDim.x];
 }
 
+// Device-sized variant: the element count is read from device memory, and a
+// fixed number of blocks (chosen from an upper bound of the count) each scan
+// one contiguous chunk in steps of kScanBlock elements.
+__device__ __forceinline__ void dev_chunk(uint64_t count, uint64_t* first, uint64_t* last) {
+  const uint64_t per = ((count + gridDim.x - 1) / gridDim.x + kScanItems - 1) / kScanItems *
+                       kScanItems;
+  *first = (uint64_t)blockIdx.x * per;
+  *last = *first + per < count ? *first + per : count;
+  if (*first > count) *first = count;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_dev_sums(const uint32_t* __restrict__ in,
+                                                              const uint32_t* __restrict__ count_dev,
+                                                              uint64_t* __restrict__ partial) {
+  __shared__ uint64_t s_tmp[kScanThreads / 64];
+  const uint64_t count = *count_dev;
+  uint64_t first, last;
+  dev_chunk(count, &first, &last);
+  uint64_t acc = 0;
+  for (uint64_t b = first; b < last; b += kScanBlock) {
+    uint32_t v[kScanItems];
+    const uint64_t f = b + (uint64_t)threadIdx.x * kScanItems;
+    uint64_t tot;
+    block_scan_u64(f < last ? load_items(in, last, f, v) : 0u, s_tmp, &tot);
+    acc += tot;
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_dev_blocks(const uint32_t* __restrict__ in,
+                                                                const uint32_t* __restrict__ count_dev,
+                                                                const uint64_t* __restrict__ partial,
+                                                                uint64_t* __restrict__ out) {
+  __shared__ uint64_t s_tmp[kScanThreads / 64];
+  const uint64_t count = *count_dev;
+  uint64_t first, last;
+  dev_chunk(count, &first, &last);
+  uint64_t carry = partial[blockIdx.x];
+  for (uint64_t b = first; b < last; b += kScanBlock) {
+    uint32_t v[kScanItems];
+    const uint64_t f = b + (uint64_t)threadIdx.x * kScanItems;
+    const uint64_t s = f < last ? load_items(in, last, f, v) : 0u;
+    if (f >= last) {
+#pragma unroll
+      for (int i = 0; i < kScanItems; ++i) v[i] = 0;
+    }
+    uint64_t tot;
+    uint64_t run = carry + block_scan_u64(s, s_tmp, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (f + i < last) out[f + i] = run;
+      run += v[i];
+    }
+    carry += tot;
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = partial[gridDim.x];
+}
+
 }  // namespace
+
+uint32_t scan_dev_blocks_for(uint64_t max_count) {
+  uint64_t nb = (max_count + kScanBlock - 1) / kScanBlock;
+  if (nb > 1024) nb = 1024;
+  return nb < 1 ? 1u : (uint32_t)nb;
+}
+
+hipError_t scan_excl_dev(const uint32_t* in, uint64_t* out, const uint32_t* count_dev,
+                         uint64_t max_count, const uint64_t* carry_in, uint64_t* partial,
+                         hipStream_t s) {
+  const uint32_t nb = scan_dev_blocks_for(max_count);
+  ProfScope ps("scan", s);
+  scan_dev_sums<<<nb, kScanThreads, 0, s>>>(in, count_dev, partial);
+  scan_partials<<<1, 1024, 0, s>>>(partial, nb, carry_in);
+  scan_dev_blocks<<<nb, kScanThreads, 0, s>>>(in, count_dev, partial, out);
+  return hipGetLastError();
+}
 
 size_t scan_scratch_bytes(uint64_t count) {
   return align256(((count + kScanBlock - 1) / kScanBlock + 1) * 8);

@@ -34,7 +34,8 @@ EXPORTS = [
     "sfc_last_query_stats", "sfc_free", "sfc_profile_enable", "sfc_profile_reset",
     "sfc_profile_read", "sfc_pool_trim", "sfc_set_search", "sfc_learned_fit",
     "sfc_learned_info_get", "sfc_learned_params", "sfc_learned_grad",
-    "sfc_learned_shrink_windows", "sfc_build_sets", "sfc_query_sets",
+    "sfc_learned_shrink_windows", "sfc_build_sets", "sfc_query_sets", "sfc_graph_build",
+    "sfc_graph_query", "sfc_graph_launch", "sfc_graph_wait", "sfc_graph_free",
 ]
 
 NPARAM = 1153
@@ -141,6 +142,16 @@ def lib() -> ctypes.CDLL:
     L.sfc_build_sets.restype = i32
     L.sfc_query_sets.argtypes = [vp, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(u64)]
     L.sfc_query_sets.restype = i32
+    L.sfc_graph_build.argtypes = [vp, vp, ctypes.POINTER(vp)]
+    L.sfc_graph_build.restype = i32
+    L.sfc_graph_query.argtypes = [vp, vp, vp, vp, u64, u64, vp, vp, u64, ctypes.POINTER(vp)]
+    L.sfc_graph_query.restype = i32
+    L.sfc_graph_launch.argtypes = [vp]
+    L.sfc_graph_launch.restype = i32
+    L.sfc_graph_wait.argtypes = [vp, ctypes.POINTER(u64)]
+    L.sfc_graph_wait.restype = i32
+    L.sfc_graph_free.argtypes = [vp]
+    L.sfc_graph_free.restype = None
     _lib = L
     return L
 
@@ -349,6 +360,68 @@ class Index:
         _check(lib().sfc_last_query_stats(self.handle, ctypes.byref(s)), "sfc_last_query_stats")
         return {"queries": s.queries, "ranges": s.ranges, "candidates": s.candidates,
                 "reported": s.reported}
+
+
+class Graph:
+    """A recorded construction or query batch (sfc_graph_*).  Keeps the
+    tensors it was recorded with alive; launch() enqueues a replay, wait()
+    synchronises and returns the total (query graphs)."""
+
+    def __init__(self, index: Index, handle, keep):
+        self.index = index
+        self._g = handle
+        self._keep = keep
+
+    @classmethod
+    def build(cls, index: Index, xy: torch.Tensor) -> "Graph":
+        xy = _dev(xy, torch.float64, "xy")
+        g = ctypes.c_void_p()
+        _check(lib().sfc_graph_build(index.handle, _ptr(xy), ctypes.byref(g)), "sfc_graph_build")
+        return cls(index, g, (xy,))
+
+    @classmethod
+    def query(cls, index: Index, q: torch.Tensor, delta: torch.Tensor, max_rows: int,
+              ids_cap: int, qset: torch.Tensor | None = None) -> "Graph":
+        q = _dev(q, torch.float64, "q")
+        delta = _dev(delta, torch.float64, "delta")
+        if qset is not None:
+            qset = _dev(qset, torch.int32, "qset")
+        m = q.shape[0]
+        offsets = torch.empty(m + 1, dtype=torch.int64, device=index.device)
+        ids = torch.empty(max(ids_cap, 1), dtype=torch.int32, device=index.device)
+        g = ctypes.c_void_p()
+        _check(lib().sfc_graph_query(index.handle, _ptr(q), _ptr(delta), _ptr(qset), m, max_rows,
+                                     _ptr(offsets), _ptr(ids), ids_cap, ctypes.byref(g)),
+               "sfc_graph_query")
+        obj = cls(index, g, (q, delta, qset))
+        obj.offsets, obj.ids = offsets, ids
+        return obj
+
+    def launch(self):
+        _check(lib().sfc_graph_launch(self._g), "sfc_graph_launch")
+
+    def wait(self) -> int:
+        total = ctypes.c_uint64(0)
+        st = lib().sfc_graph_wait(self._g, ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY:
+            raise CapacityError(st, "sfc_graph_wait", int(total.value))
+        _check(st, "sfc_graph_wait")
+        return int(total.value)
+
+    def result(self):
+        total = self.wait()
+        return self.offsets, self.ids[:total]
+
+    def close(self):
+        if getattr(self, "_g", None):
+            lib().sfc_graph_free(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sfc_build(xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,
