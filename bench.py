@@ -78,6 +78,73 @@ def cpu_baseline(wl, curve: int, m_sample: int):
     }
 
 
+def batched_sets_bench(args, sfc, workload, torch):
+    """256 independent point sets (sizes 2^U[10,20], uniform or clustered by
+    coin) with 2^U[8,16] queries each: all sets built in one pass sequence and
+    all queries in one batch, recorded as two graphs, against the same work
+    done set by set with separate calls."""
+    dev = torch.device("cuda:0")
+    wl = workload.batched_uneven(n_sets=256, curve=sfc.MORTON)
+    pts = torch.as_tensor(wl.points).to(dev)
+    q = torch.as_tensor(wl.queries).to(dev)
+    d = torch.as_tensor(wl.delta).to(dev)
+    qs = torch.as_tensor(wl.qset.astype("int32")).to(dev)
+    n, m = pts.shape[0], q.shape[0]
+    log(f"batched sets: {n} points, {m} queries")
+    tune_b, tune_b_ms = sfc.autotune_build(pts, sfc.MORTON, wl.set_off)
+    idx = sfc.Index(pts, sfc.MORTON, refine=True, set_off=wl.set_off)
+    off, ids = idx.query_sets(q, d, qs)
+    st = idx.last_stats()
+    rep, rows = int(ids.numel()), st["rows"]
+    tune_q, tune_q_ms = sfc.autotune_query(idx, q, d, qs, ids_cap=rep + 1)
+    gb = sfc.Graph.build(idx, pts)
+    gq = sfc.Graph.query(idx, q, d, max_rows=rows + 64, ids_cap=rep + 1, qset=qs)
+
+    def timed(fn, steps):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    def graph_step():
+        gb.launch()
+        gq.launch()
+        assert gq.wait() == rep
+
+    def eager_step():
+        ix = sfc.Index(pts, sfc.MORTON, refine=True, set_off=wl.set_off)
+        ix.query_sets(q, d, qs)
+        ix.close()
+
+    so, qoff = wl.set_off, np.searchsorted(wl.qset, np.arange(257))
+
+    def separate_step():
+        for s in range(256):
+            a, b = int(so[s]), int(so[s + 1])
+            ix = sfc.Index(pts[a:b], sfc.MORTON, refine=True)
+            if qoff[s + 1] > qoff[s]:
+                ix.query(q[qoff[s]:qoff[s + 1]], d[qoff[s]:qoff[s + 1]])
+            ix.close()
+
+    ms_graph = timed(graph_step, args.steps)
+    ms_eager = timed(eager_step, args.steps)
+    ms_sep = timed(separate_step, max(1, args.steps // 5))
+    gb.close()
+    gq.close()
+    idx.close()
+    return {"workload": wl.name, "sets": 256, "points": n, "queries": m, "reported": rep,
+            "ms_per_step_graph": ms_graph, "ms_per_step_batched_eager": ms_eager,
+            "ms_per_step_separate_calls": ms_sep,
+            "queries_per_s_graph": m / (ms_graph * 1e-3),
+            "speedup_vs_separate": ms_sep / ms_graph,
+            "autotune": {"sort_items": tune_b, "sort_items_ms": tune_b_ms,
+                         "test_shape": tune_q, "test_shape_ms": tune_q_ms}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +156,8 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=17)
     ap.add_argument("--only-refined", action="store_true",
                     help="time only the refined range mode (for profiler runs)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched point-set measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (counter calibration)")
     args = ap.parse_args()
@@ -241,6 +310,8 @@ def main():
         },
         "kernels_algorithmic_gbs": kern_gbs,
     }
+    if not args.no_batched and not args.only_refined:
+        line["batched_sets"] = batched_sets_bench(args, sfc, workload, torch)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         line["cpu_baseline"] = cpu_baseline(wl, curve, min(m, 1 << args.cpu_sample_log2))

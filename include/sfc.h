@@ -155,7 +155,9 @@ sfc_status sfc_query_sets(sfc_index* h, const double* q, const double* delta,
  *   SFC_ERR_DOMAIN for a coordinate outside [0,1).
  * sfc_graph_query: one batch of m >= 1 queries over fixed buffers (q, delta,
  *   qset or NULL, offsets, ids as in sfc_query_batch / sfc_query_sets).
- *   max_rows bounds the candidate rows (64 candidates each, at most 2^25);
+ *   max_rows bounds the candidate rows (64 candidates each, at most 2^40;
+ *   the graph's scratch covers one chunk of at most 2^25 rows, so it stays
+ *   under 1 GB however large the bound);
  *   a batch with more rows makes sfc_graph_wait return SFC_ERR_CAPACITY
  *   (offsets and ids then unspecified; build a graph with a larger bound).
  *   An output larger than ids_cap returns SFC_ERR_CAPACITY with *total_out
@@ -174,6 +176,25 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
 sfc_status sfc_graph_launch(sfc_graph* g);
 sfc_status sfc_graph_wait(sfc_graph* g, uint64_t* total_out);
 void sfc_graph_free(sfc_graph* g);   /* NULL-safe; waits for h's stream */
+
+/*
+ * Autotuner.  Times the launch shapes of a kernel on the caller's data with
+ * HIP events and records the fastest for the size bucket (floor(log2)) of
+ * that data; later calls of this process with sizes in the same bucket use
+ * it.  Results are identical for every shape.
+ * sfc_autotune_build: keys per thread of the radix passes (8, 12, 16; 3 timed
+ *   builds each; ms[3], *best = the chosen count).  set_off/n_sets as in
+ *   sfc_build_sets, or NULL/0.
+ * sfc_autotune_query: row groups of the exact-test kernel (5 shapes, 3 timed
+ *   batches each; ms[5], *best = the chosen shape index), for the bucket of
+ *   the batch's candidate rows; buffers as in sfc_query_batch (qset may be
+ *   NULL).  best and ms may be NULL.  Synchronises the stream.
+ */
+sfc_status sfc_autotune_build(const double* xy, uint64_t n, const uint64_t* set_off,
+                              uint32_t n_sets, const sfc_options* opt, int* best, double* ms);
+sfc_status sfc_autotune_query(sfc_index* h, const double* q, const double* delta,
+                              const uint32_t* qset, uint64_t m, uint64_t* offsets,
+                              uint32_t* ids, uint64_t ids_cap, int* best, double* ms);
 
 /* Number of points currently reported by queries (live points). */
 uint64_t sfc_size(const sfc_index* h);
@@ -221,7 +242,9 @@ sfc_status sfc_query_ranges(sfc_index* h, const double* q, const double* delta,
 /* Counters of the last sfc_query_batch on h. */
 typedef struct {
   uint64_t queries;
-  uint64_t ranges;      /* non-empty key ranges searched */
+  uint64_t rows;        /* candidate rows: each non-empty range contributes
+                           ceil(length / 64); a recorded query batch of the
+                           same queries needs max_rows >= this */
   uint64_t candidates;  /* points scanned (sum of index range lengths) */
   uint64_t reported;    /* ids reported */
 } sfc_query_stats;
@@ -265,6 +288,12 @@ sfc_status sfc_learned_info_get(const sfc_index* h, sfc_learned_info* out);
 /* Router parameters (1153 floats, host): w1[32], b1[32], W2[32][32] (row =
    output unit), b2[32], w3[32], b3.  SFC_ERR_UNSUPPORTED before a fit. */
 sfc_status sfc_learned_params(const sfc_index* h, float* params);
+/* Test hook for the compaction's chunking: candidate rows are tested and
+   written in chunks of up to 2^19 tiles of 64 rows (2^25 rows); this sets the
+   chunk to `tiles` tiles for every later call and graph recording in the
+   process (0 or more than 2^19 restores 2^19), so that the multi-chunk path
+   can be checked on small inputs.  Results do not depend on it. */
+sfc_status sfc_debug_chunk_tiles(uint64_t tiles);
 /* Test hook for the fallback path: sets every leaf's window to the single
    predicted position, so that most learned lower bounds fail verification
    and fall back to binary search.  Results stay exact. */

@@ -159,6 +159,23 @@ void prof_drain(ProfState& P) {
 }
 }  // namespace
 
+namespace {
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tune;   // (op, size bucket) -> choice
+int bucket(uint64_t size) { return size ? 63 - __builtin_clzll(size) : 0; }
+}  // namespace
+
+int tuned(TuneOp op, uint64_t size) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find({(int)op, bucket(size)});
+  return it == g_tune.end() ? -1 : it->second;
+}
+
+void set_tuned(TuneOp op, uint64_t size, int value) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[{(int)op, bucket(size)}] = value;
+}
+
 uint64_t* pinned_scratch() {
   static thread_local uint64_t* p = nullptr;
   if (!p) {
@@ -541,7 +558,7 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
   h->last.queries = m;
   h->last.candidates = total_cand;
   h->last.reported = total;
-  h->last.ranges = 0;
+  h->last.rows = total_rows;
   *total_out = total;
   return total > ids_cap ? SFC_ERR_CAPACITY : SFC_OK;
 }
@@ -616,6 +633,11 @@ sfc_status sfc_set_search(sfc_index* h, int search) {
 sfc_status sfc_learned_fit(sfc_index* h, int steps) {
   if (!h) return SFC_ERR_INVALID;
   return fit_learned(h, steps);
+}
+
+sfc_status sfc_debug_chunk_tiles(uint64_t tiles) {
+  sfc::set_compact_chunk_tiles(tiles);
+  return SFC_OK;
 }
 
 sfc_status sfc_learned_shrink_windows(sfc_index* h) {
@@ -761,8 +783,7 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
                            uint32_t* ids, uint64_t ids_cap, sfc_graph** out) {
   if (!h || !out || !offsets || m == 0 || !q || !delta || (ids_cap > 0 && !ids)) return SFC_ERR_INVALID;
   if (qset && h->n_sets == 0) return SFC_ERR_INVALID;
-  if (max_rows == 0 || max_rows > sfc::kCompactChunkTiles * sfc::kCompactTileRows)
-    return SFC_ERR_INVALID;
+  if (max_rows == 0 || max_rows > (1ull << 40)) return SFC_ERR_INVALID;
   sfc_graph* g = new (std::nothrow) sfc_graph();
   if (!g) return SFC_ERR_NOMEM;
   g->h = h;
@@ -829,6 +850,101 @@ sfc_status sfc_graph_wait(sfc_graph* g, uint64_t* total_out) {
 void sfc_graph_free(sfc_graph* g) {
   if (g && g->h) (void)hipStreamSynchronize(g->h->stream);
   graph_release(g);
+}
+
+}  // extern "C"
+
+namespace {
+// Mean milliseconds of fn() over reps launches after one warm-up, timed with
+// HIP events on stream s.
+template <typename F>
+sfc_status time_ms(hipStream_t s, int reps, F fn, double* ms) {
+  sfc_status st = fn();
+  if (st != SFC_OK && st != SFC_ERR_CAPACITY) return st;
+  hipEvent_t a, b;
+  SFC_TRY(hipEventCreate(&a));
+  SFC_TRY(hipEventCreate(&b));
+  SFC_TRY(hipEventRecord(a, s));
+  for (int i = 0; i < reps; ++i) {
+    st = fn();
+    if (st != SFC_OK && st != SFC_ERR_CAPACITY) break;
+  }
+  SFC_TRY(hipEventRecord(b, s));
+  SFC_TRY(hipEventSynchronize(b));
+  float t = 0.f;
+  SFC_TRY(hipEventElapsedTime(&t, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = t / reps;
+  return st == SFC_ERR_CAPACITY ? SFC_OK : st;
+}
+}  // namespace
+
+extern "C" {
+
+sfc_status sfc_autotune_build(const double* xy, uint64_t n, const uint64_t* set_off,
+                              uint32_t n_sets, const sfc_options* opt, int* best, double* ms) {
+  if (n == 0 || !xy) return SFC_ERR_INVALID;
+  static const int kItems[3] = {8, 12, 16};
+  sfc_options o;
+  sfc_default_options(&o);
+  if (opt) o = *opt;
+  o.search = SFC_SEARCH_BINARY;
+  double t[3] = {0, 0, 0};
+  int pick = 16;
+  double tb = 1e30;
+  for (int v = 0; v < 3; ++v) {
+    sfc::set_tuned(sfc::kTuneSortItems, n, kItems[v]);
+    sfc_status st = time_ms((hipStream_t)o.stream, 3, [&] {
+      sfc_index* h = nullptr;
+      sfc_status r = set_off ? sfc_build_sets(xy, set_off, n_sets, &o, &h) : sfc_build(xy, n, &o, &h);
+      sfc_free(h);
+      return r;
+    }, &t[v]);
+    if (st != SFC_OK) return st;
+    if (t[v] < tb) {
+      tb = t[v];
+      pick = kItems[v];
+    }
+  }
+  sfc::set_tuned(sfc::kTuneSortItems, n, pick);
+  if (best) *best = pick;
+  if (ms) for (int v = 0; v < 3; ++v) ms[v] = t[v];
+  return SFC_OK;
+}
+
+sfc_status sfc_autotune_query(sfc_index* h, const double* q, const double* delta,
+                              const uint32_t* qset, uint64_t m, uint64_t* offsets, uint32_t* ids,
+                              uint64_t ids_cap, int* best, double* ms) {
+  if (!h || m == 0) return SFC_ERR_INVALID;
+  uint64_t total = 0;
+  sfc_status st = query_impl(h, q, delta, qset, m, offsets, ids, ids_cap, &total);
+  if (st != SFC_OK && st != SFC_ERR_CAPACITY) return st;
+  // The test kernel's shape is chosen per bucket of the batch's candidate rows.
+  sfc::QueryScratch qs{};
+  uint64_t rows = 0, cand = 0;
+  st = run_ranges(h, q, delta, qset, m, &qs, &rows, &cand, nullptr, nullptr, nullptr, nullptr,
+                  nullptr);
+  if (st != SFC_OK) return st;
+  double t[5] = {0, 0, 0, 0, 0};
+  int pick = 0;
+  double tb = 1e30;
+  for (int v = 0; v < 5; ++v) {
+    sfc::set_tuned(sfc::kTuneTestShape, rows, v);
+    st = time_ms(h->stream, 3, [&] {
+      uint64_t tot = 0;
+      return query_impl(h, q, delta, qset, m, offsets, ids, ids_cap, &tot);
+    }, &t[v]);
+    if (st != SFC_OK) return st;
+    if (t[v] < tb) {
+      tb = t[v];
+      pick = v;
+    }
+  }
+  sfc::set_tuned(sfc::kTuneTestShape, rows, pick);
+  if (best) *best = pick;
+  if (ms) for (int v = 0; v < 5; ++v) ms[v] = t[v];
+  return SFC_OK;
 }
 
 void sfc_free(sfc_index* h) {

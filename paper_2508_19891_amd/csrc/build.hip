@@ -222,16 +222,17 @@ __global__ void gather_points(const uint32_t* __restrict__ ids, const double2* _
   if (i < n) out[i] = xy[ids[i]];
 }
 
-// Keys per thread of a radix pass (tuning knob SFC_SORT_ITEMS: 8, 12 or 16).
-int sort_items() {
-  static const int v = [] {
+// Keys per thread of a radix pass: 8, 12 or 16.  The environment variable
+// SFC_SORT_ITEMS overrides; else the autotuner's choice for this size; else 16.
+int sort_items(uint64_t n) {
+  static const int env = [] {
     const char* e = std::getenv("SFC_SORT_ITEMS");
-    const int k = e ? std::atoi(e) : 16;
-    return (k == 8 || k == 12) ? k : 16;
+    return e ? std::atoi(e) : 0;
   }();
-  return v;
+  int k = env ? env : tuned(kTuneSortItems, n);
+  return (k == 8 || k == 12) ? k : 16;
 }
-uint64_t sort_tile() { return (uint64_t)kSortThreads * sort_items(); }
+uint64_t sort_tile(uint64_t n) { return (uint64_t)kSortThreads * sort_items(n); }
 
 // Set id of every input position (sets are contiguous in the input).
 __global__ void fill_set_ids(const uint64_t* __restrict__ set_off, uint32_t n_sets, uint64_t n,
@@ -297,7 +298,7 @@ int set_passes(uint32_t n_sets) { return n_sets <= 1 ? 0 : (n_sets <= 256 ? 1 : 
 
 // Device bytes of scratch needed by sort_build for n points.
 size_t build_scratch_bytes(uint64_t n, uint32_t* keygen_blocks) {
-  const uint64_t tiles = (n + sort_tile() - 1) / sort_tile();
+  const uint64_t tiles = (n + sort_tile(n) - 1) / sort_tile(n);
   uint64_t blocks = (n + 1023) / 1024;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
@@ -340,7 +341,7 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   if (n == 0) return hipSuccess;
   uint32_t kblocks = 0;
   build_scratch_bytes(n, &kblocks);
-  const uint64_t tiles = (n + sort_tile() - 1) / sort_tile();
+  const uint64_t tiles = (n + sort_tile(n) - 1) / sort_tile(n);
   char* p = (char*)scratch;
   uint64_t* keys_b = (uint64_t*)p;      p += align256(n * 8);
   uint32_t* ids_b = (uint32_t*)p;       p += align256(n * 4);
@@ -393,7 +394,7 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
 #define SFC_LAUNCH(I)                                                                          \
   launch_pass<I>(pass == 0, gather, setpass, shift, tiles, kin, vin, kout, vout, n, hp, st,   \
                  st_next, counters + pass, err_host_visible, xy, xy_out, set_id, s)
-    switch (sort_items()) {
+    switch (sort_items(n)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;
       default: e = SFC_LAUNCH(8); break;

@@ -10,6 +10,12 @@ namespace sfc {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Launch shapes chosen by the autotuner, per size bucket (floor(log2 size)).
+// tuned(op, size) returns -1 when the bucket has no entry.
+enum TuneOp { kTuneSortItems = 0, kTuneTestShape = 1 };
+int tuned(TuneOp op, uint64_t size);
+void set_tuned(TuneOp op, uint64_t size, int value);
+
 // Fill kernel (used instead of hipMemsetAsync so that every step of a batch
 // can be recorded into a HIP graph).
 hipError_t fill_u64(uint64_t* p, uint64_t value, uint64_t count, hipStream_t s);
@@ -46,6 +52,9 @@ struct QueryScratch {
 };
 constexpr uint64_t kCompactTileRows = 64;           // rows of 64 candidates per tile
 constexpr uint64_t kCompactChunkTiles = 1ull << 19; // tiles per launch
+// Tiles per chunk in effect (kCompactChunkTiles unless a test lowered it).
+uint64_t compact_chunk_tiles();
+void set_compact_chunk_tiles(uint64_t tiles);
 size_t query_scratch_bytes(uint64_t m);
 void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs);
 size_t compact_scratch_bytes(uint64_t total_rows);

@@ -16,6 +16,8 @@
 //                  offsets of the queries whose candidates start in it.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <cstdlib>
 
 #include "common.h"
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(256) void compact_test(
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
   const uint64_t total_rows = total_all < row_end ? total_all : row_end;
-  const uint64_t ntiles = (total_rows - rbase + kTileRows - 1) / kTileRows;
+  const uint64_t ntiles = total_rows > rbase ? (total_rows - rbase + kTileRows - 1) / kTileRows : 0;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t wrow0 = rbase + tile * kTileRows + (uint64_t)w * kWaveRows;
     uint32_t cnt = 0;
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(256) void compact_write(
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
   const uint64_t total_rows = total_all < row_end ? total_all : row_end;
-  const uint64_t ntiles = (total_rows - rbase + kTileRows - 1) / kTileRows;
+  const uint64_t ntiles = total_rows > rbase ? (total_rows - rbase + kTileRows - 1) / kTileRows : 0;
   const uint64_t below = lanemask_lt();
   if (ntiles == 0 && rbase == 0 && blockIdx.x == 0) {   // no candidates at all
     for (uint64_t qq = tid; qq <= m; qq += 256) offsets[qq] = 0;
@@ -597,15 +599,20 @@ __global__ void fill32_kernel(uint32_t* p, uint32_t v, uint64_t count) {
     p[i] = v;
 }
 
-// Tuning knob: shape of the test kernel's row groups, iterations x rows
-// (SFC_TEST_VARIANT = 0: 1 x 16, 1: 4 x 4, 2: 2 x 8, 3: 8 x 2, 4: 16 x 1).
-// Same results for all.
-int test_variant() {
-  static const int v = [] {
+// Tiles per compaction chunk (lowered only by the test hook).
+std::atomic<uint64_t> g_chunk_tiles{kCompactChunkTiles};
+
+// Shape of the test kernel's row groups, iterations x rows: 0: 1 x 16,
+// 1: 4 x 4, 2: 2 x 8, 3: 8 x 2, 4: 16 x 1 (same results for all).  The
+// environment variable SFC_TEST_VARIANT overrides; else the autotuner's choice
+// for this number of rows; else 0.
+int test_variant(uint64_t rows) {
+  static const int env = [] {
     const char* e = std::getenv("SFC_TEST_VARIANT");
-    return e ? std::atoi(e) : 0;
+    return e ? std::atoi(e) + 1 : 0;
   }();
-  return v;
+  const int v = env ? env - 1 : tuned(kTuneTestShape, rows);
+  return v >= 0 && v <= 4 ? v : 0;
 }
 
 uint32_t fill_blocks(uint64_t count) {
@@ -615,6 +622,12 @@ uint32_t fill_blocks(uint64_t count) {
 }
 
 }  // namespace
+
+uint64_t compact_chunk_tiles() { return g_chunk_tiles.load(std::memory_order_relaxed); }
+void set_compact_chunk_tiles(uint64_t tiles) {
+  g_chunk_tiles.store(tiles == 0 || tiles > kCompactChunkTiles ? kCompactChunkTiles : tiles,
+                      std::memory_order_relaxed);
+}
 
 hipError_t fill_u64(uint64_t* p, uint64_t value, uint64_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
@@ -705,14 +718,14 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
   if (m == 0) return fill_u64(offsets, 0, 1, s);
   const uint64_t nseg = m << qs.ss;
   const uint64_t* total_dev = qs.row_off + nseg;
-  // Host-sized: max_rows is the exact number of rows, processed in chunks of
-  // at most kCompactChunkTiles tiles.  Device-sized: max_rows is a capacity;
-  // one chunk, the count is read on the device, overflow is flagged.
+  // Rows are processed in chunks of at most kCompactChunkTiles tiles.
+  // Host-sized: max_rows is the exact number of rows.  Device-sized: max_rows
+  // is a capacity; each kernel reads the row count on the device, chunks past
+  // it do no work, and a count above the capacity is flagged as overflow.
   const uint64_t tiles_all = (max_rows + kCompactTileRows - 1) / kCompactTileRows;
   if (!device_sized && max_rows == 0) return fill_u64(offsets, 0, m + 1, s);
-  const uint64_t ch_tiles = tiles_all < kCompactChunkTiles ? (tiles_all ? tiles_all : 1)
-                                                           : kCompactChunkTiles;
-  if (device_sized && tiles_all > kCompactChunkTiles) return hipErrorInvalidValue;
+  const uint64_t chunk = compact_chunk_tiles();
+  const uint64_t ch_tiles = tiles_all < chunk ? (tiles_all ? tiles_all : 1) : chunk;
   char* p = (char*)cscratch;
   uint64_t* masks = (uint64_t*)p;     p += align256(ch_tiles * kTileRows * 8);
   uint32_t* hits = (uint32_t*)p;      p += align256(ch_tiles * 4);
@@ -723,14 +736,17 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
   uint64_t* stmp = (uint64_t*)p;
   const uint64_t* carry = nullptr;
   int buf = 0;
-  const uint64_t chunks = device_sized ? 1 : (tiles_all + kCompactChunkTiles - 1) / kCompactChunkTiles;
+  const uint64_t chunks = tiles_all ? (tiles_all + chunk - 1) / chunk : 1;
   for (uint64_t c = 0; c < chunks; ++c, buf ^= 1) {
-    const uint64_t rbase = c * kCompactChunkTiles * kCompactTileRows;
-    const uint64_t nt = device_sized ? ch_tiles
-                                     : (tiles_all - c * kCompactChunkTiles < kCompactChunkTiles
-                                            ? tiles_all - c * kCompactChunkTiles
-                                            : kCompactChunkTiles);
-    const uint64_t row_end = device_sized ? max_rows : rbase + nt * kCompactTileRows;
+    const uint64_t rbase = c * chunk * kCompactTileRows;
+    const uint64_t nt = tiles_all - c * chunk < chunk ? (tiles_all ? tiles_all - c * chunk : 1)
+                                                      : chunk;
+    // A full chunk ends at its last tile; the last chunk at the capacity
+    // (device-sized) or at the exact count (host-sized, a multiple of 64 rows
+    // past it is never read because the kernels clamp to the count).
+    const uint64_t row_end = c + 1 < chunks ? rbase + nt * kCompactTileRows
+                             : device_sized ? max_rows : rbase + nt * kCompactTileRows;
+    const bool flag = device_sized && c + 1 == chunks;
     const uint32_t grid = (uint32_t)(nt < kCompactGrid ? (nt ? nt : 1) : kCompactGrid);
     {
       ProfScope ps("expand_rows", s);
@@ -742,9 +758,9 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
       ProfScope ps("compact_test", s);
 #define SFC_TEST(R, I)                                                                       \
   compact_test<R, I><<<grid, 256, 0, s>>>((const double2*)q, delta, m, (const double2*)pts, \
-                                          npts, meta, total_dev, rbase, row_end,            \
-                                          device_sized, masks, hits, qs.counters)
-      switch (test_variant()) {
+                                          npts, meta, total_dev, rbase, row_end, flag,      \
+                                          masks, hits, qs.counters)
+      switch (test_variant(max_rows)) {
         case 1: SFC_TEST(4, 4); break;
         case 2: SFC_TEST(8, 2); break;
         case 3: SFC_TEST(2, 8); break;
@@ -763,7 +779,10 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
                                                out_ids, cap);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    carry = toff[buf] + nt;   // the chunk's total, read by the next chunk's scan
+    // The chunk's total, read by the next chunk's scan.  A chunk has tiles
+    // only when every chunk before it was full, so this slot is always
+    // written when it is consumed.
+    carry = toff[buf] + nt;
   }
   return hipSuccess;
 }

@@ -36,6 +36,7 @@ EXPORTS = [
     "sfc_learned_info_get", "sfc_learned_params", "sfc_learned_grad",
     "sfc_learned_shrink_windows", "sfc_build_sets", "sfc_query_sets", "sfc_graph_build",
     "sfc_graph_query", "sfc_graph_launch", "sfc_graph_wait", "sfc_graph_free",
+    "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
 ]
 
 NPARAM = 1153
@@ -80,7 +81,7 @@ class LearnedInfo(ctypes.Structure):
 
 
 class QueryStats(ctypes.Structure):
-    _fields_ = [("queries", ctypes.c_uint64), ("ranges", ctypes.c_uint64),
+    _fields_ = [("queries", ctypes.c_uint64), ("rows", ctypes.c_uint64),
                 ("candidates", ctypes.c_uint64), ("reported", ctypes.c_uint64)]
 
 
@@ -152,6 +153,13 @@ def lib() -> ctypes.CDLL:
     L.sfc_graph_wait.restype = i32
     L.sfc_graph_free.argtypes = [vp]
     L.sfc_graph_free.restype = None
+    L.sfc_autotune_build.argtypes = [vp, u64, vp, u32, ctypes.POINTER(Options),
+                                     ctypes.POINTER(i32), vp]
+    L.sfc_autotune_build.restype = i32
+    L.sfc_autotune_query.argtypes = [vp, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(i32), vp]
+    L.sfc_autotune_query.restype = i32
+    L.sfc_debug_chunk_tiles.argtypes = [u64]
+    L.sfc_debug_chunk_tiles.restype = i32
     _lib = L
     return L
 
@@ -358,7 +366,7 @@ class Index:
     def last_stats(self) -> dict:
         s = QueryStats()
         _check(lib().sfc_last_query_stats(self.handle, ctypes.byref(s)), "sfc_last_query_stats")
-        return {"queries": s.queries, "ranges": s.ranges, "candidates": s.candidates,
+        return {"queries": s.queries, "rows": s.rows, "candidates": s.candidates,
                 "reported": s.reported}
 
 
@@ -422,6 +430,53 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def debug_chunk_tiles(tiles: int):
+    """Test hook: compaction chunk size in tiles of 64 rows (0 = default)."""
+    _check(lib().sfc_debug_chunk_tiles(tiles), "sfc_debug_chunk_tiles")
+
+
+def autotune_build(xy: torch.Tensor, curve: int = MORTON, set_off=None):
+    """Times the radix passes' keys-per-thread shapes on these points and
+    records the fastest for their size; returns (best, {shape: ms})."""
+    import numpy as np
+    xy = _dev(xy, torch.float64, "xy")
+    L = lib()
+    opt = Options()
+    L.sfc_default_options(ctypes.byref(opt))
+    opt.curve = curve
+    opt.stream = current_stream_handle()
+    best = ctypes.c_int(0)
+    ms = (ctypes.c_double * 3)()
+    so = None if set_off is None else np.ascontiguousarray(set_off, np.uint64)
+    _check(L.sfc_autotune_build(_ptr(xy), xy.shape[0],
+                                None if so is None else so.ctypes.data_as(ctypes.c_void_p),
+                                0 if so is None else len(so) - 1, ctypes.byref(opt),
+                                ctypes.byref(best), ms), "sfc_autotune_build")
+    return best.value, dict(zip((8, 12, 16), list(ms)))
+
+
+def autotune_query(index: Index, q: torch.Tensor, delta: torch.Tensor,
+                   qset: torch.Tensor | None = None, ids_cap: int | None = None):
+    """Times the test kernel's shapes on this batch and records the fastest
+    for its candidate-row bucket; returns (best, [ms per shape])."""
+    q = _dev(q, torch.float64, "q")
+    delta = _dev(delta, torch.float64, "delta")
+    if qset is not None:
+        qset = _dev(qset, torch.int32, "qset")
+    m = q.shape[0]
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=index.device)
+    if ids_cap is None:
+        off, ids = (index.query(q, delta) if qset is None else index.query_sets(q, delta, qset))
+        ids_cap = ids.numel() + 1
+    ids = torch.empty(max(ids_cap, 1), dtype=torch.int32, device=index.device)
+    best = ctypes.c_int(0)
+    ms = (ctypes.c_double * 5)()
+    _check(lib().sfc_autotune_query(index.handle, _ptr(q), _ptr(delta), _ptr(qset), m,
+                                    _ptr(offsets), _ptr(ids), ids_cap, ctypes.byref(best), ms),
+           "sfc_autotune_query")
+    return best.value, list(ms)
 
 
 def sfc_build(xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,

@@ -91,3 +91,40 @@ def test_sets_query_graph_and_overflow():
     with pytest.raises(sfc.CapacityError):
         small.wait()
     small.close()
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 64])
+def test_multi_chunk_compaction(chunk):
+    """Compaction in many small chunks (eager: exact count; graph: capacity
+    larger than the count, read on the device) equals the oracle."""
+    wl = workload.clustered_loguniform(n=120_000, m=6_000, curve=HILBERT, seed=23)
+    ref = oracle.query(oracle.build(wl.points, HILBERT), wl.queries, wl.delta, HILBERT,
+                       nthreads=4)
+    q, d = dev(wl.queries), dev(wl.delta)
+    try:
+        sfc.debug_chunk_tiles(chunk)
+        idx = sfc.Index(dev(wl.points), HILBERT, refine=True)
+        off, ids = idx.query(q, d)
+        assert np.array_equal(off.cpu().numpy().view(np.uint64), ref[0])
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), ref[1])
+        rows = idx.last_stats()["rows"]
+        assert rows > 4 * 64 * chunk            # several chunks
+        g = sfc.Graph.query(idx, q, d, max_rows=rows + 5 * 64 * chunk + 17,
+                            ids_cap=ids.numel() + 1)
+        for rep in range(3):
+            g.launch()
+            goff, gids = g.result()
+            assert torch.equal(goff, off) and torch.equal(gids, ids), rep
+        g.close()
+        tight = sfc.Graph.query(idx, q, d, max_rows=rows, ids_cap=ids.numel())
+        tight.launch()
+        goff, gids = tight.result()
+        assert torch.equal(goff, off) and torch.equal(gids, ids)
+        tight.close()
+        short = sfc.Graph.query(idx, q, d, max_rows=rows - 1, ids_cap=ids.numel())
+        short.launch()
+        with pytest.raises(sfc.CapacityError):
+            short.wait()
+        short.close()
+    finally:
+        sfc.debug_chunk_tiles(0)
