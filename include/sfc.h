@@ -126,6 +126,65 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta,
                            uint64_t ids_cap, uint64_t* total_out);
 
 /*
+ * Updates (the paper's dynamic variant: Section 2, implementation details,
+ * "Dynamic implementation", there a B-tree multimap of (key, point) pairs;
+ * measured in the dynamic synthetic experiments of Section 3).  The stored
+ * run stays one sorted array: an insert sorts its batch like sfc_build and
+ * merges the two sorted runs; an erase marks the entry with a tombstone;
+ * tombstones are dropped by a compaction.  Not available for indexes built
+ * with sfc_build_sets (SFC_ERR_UNSUPPORTED).
+ *
+ * Epochs.  A built index is at epoch 0; every sfc_insert and sfc_erase with
+ * k > 0 advances the epoch by one.  An entry inserted at epoch i and erased
+ * at epoch r (r = infinity while live) is visible at epochs e with
+ * i <= e < r.  sfc_query_batch answers at the current epoch;
+ * sfc_query_epochs answers query j at qepoch[j], any epoch in
+ * [oldest, current].  By default oldest follows the current epoch (only the
+ * latest state is queryable); after sfc_hold_epochs(h, 1) older epochs stay
+ * queryable until the caller calls sfc_retire(h, e) (oldest = e).
+ * Compaction drops the tombstones with r <= oldest; it runs by itself when
+ * they reach a tenth of the stored entries, or on sfc_compact.
+ * The learned index, when fitted, has its leaves refitted (router kept)
+ * after every merge and compaction.  Each update synchronises the stream and
+ * makes every recorded graph of h stale (sfc_graph_launch then returns
+ * SFC_ERR_INVALID); the arrays of sfc_index_view move.
+ *
+ * sfc_insert: k points (device, 2*k doubles, in [0,1)) get the ids
+ *   next_id .. next_id + k - 1 in input order (next_id: see
+ *   sfc_update_info; it starts at n); ids_out (device, k uint32, or NULL)
+ *   receives them.  SFC_ERR_DOMAIN leaves h unchanged.  Ids are never
+ *   reused; at most 2^32 - 2 ids over the life of h.
+ * sfc_erase: ids (device, k uint32); unknown, already erased and repeated
+ *   ids are skipped; *erased_out (host, or NULL) = entries erased.
+ * sfc_query_epochs: as sfc_query_batch, with qepoch (device, m uint32);
+ *   an epoch outside [oldest, current] gives SFC_ERR_INVALID.
+ * sfc_hold_epochs: hold = 1 keeps older epochs queryable; hold = 0 retires
+ *   every epoch before the current one.
+ * sfc_retire: epochs below `epoch` (<= current) are no longer queried.
+ */
+sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_out);
+sfc_status sfc_erase(sfc_index* h, const uint32_t* ids, uint64_t k, uint64_t* erased_out);
+sfc_status sfc_query_epochs(sfc_index* h, const double* q, const double* delta,
+                            const uint32_t* qepoch, uint64_t m, uint64_t* offsets,
+                            uint32_t* ids, uint64_t ids_cap, uint64_t* total_out);
+sfc_status sfc_hold_epochs(sfc_index* h, int hold);
+sfc_status sfc_retire(sfc_index* h, uint32_t epoch);
+sfc_status sfc_compact(sfc_index* h);
+typedef struct {
+  uint32_t epoch;       /* current epoch */
+  uint32_t oldest;      /* oldest queryable epoch */
+  uint32_t next_id;     /* id of the next inserted point */
+  uint32_t hold;        /* sfc_hold_epochs state */
+  uint64_t stored;      /* entries in the sorted run (sfc_size) */
+  uint64_t live;        /* stored entries without a tombstone */
+  uint64_t dead;        /* stored entries with a tombstone */
+  uint64_t droppable;   /* tombstones the next compaction drops */
+  uint64_t merges;      /* inserts merged */
+  uint64_t compactions; /* compactions run */
+} sfc_update_info;
+sfc_status sfc_update_info_get(const sfc_index* h, sfc_update_info* out);
+
+/*
  * Many independent point sets in one index (batched instances).  Set s owns
  * the input points xy[set_off[s] .. set_off[s+1]) (set_off: host, n_sets + 1
  * non-decreasing offsets, set_off[0] = 0, 1 <= n_sets <= 65536).  The

@@ -212,6 +212,22 @@ struct sfc_index {
   // point sets (sfc_build_sets)
   uint32_t n_sets = 0;
   uint64_t* set_off = nullptr;     // device, n_sets + 1
+  // updates (sfc_insert / sfc_erase); ins == null until the first update
+  uint32_t* ins = nullptr;         // device, insert epoch per stored entry
+  uint32_t* era = nullptr;         // device, erase epoch per stored entry
+  uint64_t cap = 0;                // entries allocated in keys/ids/xy/ins/era
+  sfc::Run spare{};                // the other half of the merge ping-pong
+  uint64_t spare_cap = 0;
+  uint64_t* key_of = nullptr;      // device, key of every id handed out
+  uint64_t key_of_cap = 0;
+  uint64_t* upd_word = nullptr;    // device, counters of the update kernels
+  uint32_t next_id = 0;
+  uint32_t epoch = 0, oldest = 0, max_ins = 0;
+  int hold = 0;
+  uint64_t dead = 0;               // stored entries with a tombstone
+  std::vector<std::pair<uint32_t, uint64_t>> tombs;   // (erase epoch, entries), not dropped
+  uint64_t generation = 0;         // bumped by every update; recorded graphs check it
+  uint64_t merges = 0, compactions = 0;
 };
 
 namespace {
@@ -281,6 +297,21 @@ void release_arrays(sfc_index* h) {
   h->alloc.put(h->lleaves);
   h->alloc.put(h->set_off);
   h->set_off = nullptr;
+  h->alloc.put(h->ins);
+  h->alloc.put(h->era);
+  h->alloc.put(h->spare.keys);
+  h->alloc.put(h->spare.ids);
+  h->alloc.put(h->spare.xy);
+  h->alloc.put(h->spare.ins);
+  h->alloc.put(h->spare.era);
+  h->alloc.put(h->key_of);
+  h->alloc.put(h->upd_word);
+  h->ins = h->era = nullptr;
+  h->spare = sfc::Run{};
+  h->spare_cap = 0;
+  h->key_of = nullptr;
+  h->key_of_cap = 0;
+  h->upd_word = nullptr;
   h->lparams = nullptr;
   h->lleaves = nullptr;
   h->linfo = sfc_learned_info{};
@@ -296,7 +327,7 @@ void release_arrays(sfc_index* h) {
 sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const uint32_t* qset,
                       uint64_t m, sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
                       uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
-                      uint32_t* dbg_nr) {
+                      uint32_t* dbg_nr, const uint32_t* qepoch = nullptr) {
   sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
   if (st != SFC_OK) return st;
   sfc::query_scratch_carve(h->ws, m, qs);
@@ -305,6 +336,8 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
                              h->refine_min, learned ? h->lparams : nullptr,
                              learned ? h->lleaves : nullptr, qset, qset ? h->set_off : nullptr,
                              h->n_sets, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
+  if (qepoch)
+    SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs->counters + 2, h->stream));
   uint64_t* pin = sfc::pinned_scratch();
   SFC_TRY(hipMemcpyAsync(pin, qs->row_off + (m << qs->ss), 8, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 48, hipMemcpyDeviceToHost, h->stream));
@@ -317,6 +350,26 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   h->linfo.endpoints_last = learned ? pin[4] : 0;
   h->linfo.fallbacks_last = learned ? pin[5] : 0;
   return SFC_OK;
+}
+
+// Size and window statistics of the fitted leaves.
+void leaf_stats(sfc_index* h, const std::vector<sfc::LeafRec>& leaves) {
+  sfc_learned_info& I = h->linfo;
+  I.leaves = sfc::kLeaves;
+  I.leaves_nonempty = 0;
+  I.max_leaf = 0;
+  I.max_window = 0;
+  double wsum = 0.0;
+  for (const sfc::LeafRec& L : leaves) {
+    const uint32_t size = L.E - L.S;
+    if (size == 0) continue;
+    ++I.leaves_nonempty;
+    if (size > I.max_leaf) I.max_leaf = size;
+    const uint32_t win = (uint32_t)(L.ehi - L.elo + 1);
+    if (win > I.max_window) I.max_window = win;
+    wsum += (double)size * win;
+  }
+  I.mean_window = h->n ? wsum / (double)h->n : 0.0;
 }
 
 sfc_status fit_learned(sfc_index* h, int steps) {
@@ -349,21 +402,35 @@ sfc_status fit_learned(sfc_index* h, int steps) {
   I.steps = (uint32_t)steps;
   I.loss_init = lh[0];
   I.loss_final = lh[1];
-  I.leaves = sfc::kLeaves;
-  I.leaves_nonempty = 0;
-  I.max_leaf = 0;
-  I.max_window = 0;
-  double wsum = 0.0;
-  for (const sfc::LeafRec& L : leaves) {
-    const uint32_t size = L.E - L.S;
-    if (size == 0) continue;
-    ++I.leaves_nonempty;
-    if (size > I.max_leaf) I.max_leaf = size;
-    const uint32_t win = (uint32_t)(L.ehi - L.elo + 1);
-    if (win > I.max_window) I.max_window = win;
-    wsum += (double)size * win;
+  leaf_stats(h, leaves);
+  return SFC_OK;
+}
+
+// Refits the leaves of a fitted learned index after the keys changed (the
+// router is kept); with fewer than two keys the index falls back to binary
+// search until the next fit.
+sfc_status refit_leaves(sfc_index* h) {
+  if (!h->linfo.fitted) return SFC_OK;
+  if (h->n < 2) {
+    h->linfo.fitted = 0;
+    return SFC_OK;
   }
-  I.mean_window = wsum / (double)h->n;
+  void* scratch = h->alloc.get(sfc::learned_scratch_bytes());
+  if (!scratch) return SFC_ERR_NOMEM;
+  std::vector<sfc::LeafRec> leaves(sfc::kLeaves);
+  hipError_t e = sfc::learned_refit_leaves(h->keys, h->n, h->lparams, h->lleaves, scratch,
+                                           h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(leaves.data(), h->lleaves, sfc::kLeaves * sizeof(sfc::LeafRec),
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  h->alloc.put(scratch);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->linfo.fitted = 0;
+    return from_hip(e);
+  }
+  leaf_stats(h, leaves);
   return SFC_OK;
 }
 
@@ -440,6 +507,8 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
   h->alloc.release = o.release;
   h->alloc.ctx = o.alloc_ctx;
   h->n = n;
+  h->cap = n;
+  h->next_id = (uint32_t)n;
   if (set_off_host) {
     h->n_sets = n_sets;
     h->set_off = (uint64_t*)h->alloc.get((n_sets + 1) * 8);
@@ -525,17 +594,30 @@ sfc_status sfc_build_sets(const double* xy, const uint64_t* set_off, uint32_t n_
 }  // extern "C"
 
 namespace {
+// The entries a query of h sees: all stored ones unless updates left
+// tombstones or entries newer than the oldest queryable epoch.
+bool epoch_view(const sfc_index* h, const uint32_t* qepoch, sfc::EpochView* ev) {
+  if (!h->ins || (h->dead == 0 && h->max_ins <= h->oldest)) return false;
+  ev->ins = h->ins;
+  ev->era = h->era;
+  ev->qepoch = qepoch;
+  ev->epoch = h->epoch;
+  return true;
+}
+
 sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const uint32_t* qset,
                       uint64_t m, uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
-                      uint64_t* total_out) {
+                      uint64_t* total_out, const uint32_t* qepoch = nullptr) {
   if (!h || !offsets || !total_out || (m > 0 && (!q || !delta)) || (ids_cap > 0 && !ids))
     return SFC_ERR_INVALID;
   if (m > (1ull << 36)) return SFC_ERR_INVALID;
   sfc::QueryScratch qs{};
   uint64_t total_rows = 0, total_cand = 0;
+  sfc::EpochView ev;
+  const bool filtered = epoch_view(h, qepoch, &ev);
   if (m > 0) {
     sfc_status st = run_ranges(h, q, delta, qset, m, &qs, &total_rows, &total_cand, nullptr,
-                               nullptr, nullptr, nullptr, nullptr);
+                               nullptr, nullptr, nullptr, nullptr, qepoch);
     if (st != SFC_OK) return st;
   } else {
     sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(0));
@@ -547,7 +629,7 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
     if (st != SFC_OK) return st;
   }
   SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_rows, false, h->cws,
-                              offsets, ids, ids_cap, h->stream));
+                              offsets, ids, ids_cap, h->stream, filtered ? &ev : nullptr));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
   if (m > 0) {
@@ -571,6 +653,13 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, u
                            uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
                            uint64_t* total_out) {
   return query_impl(h, q, delta, nullptr, m, offsets, ids, ids_cap, total_out);
+}
+
+sfc_status sfc_query_epochs(sfc_index* h, const double* q, const double* delta,
+                            const uint32_t* qepoch, uint64_t m, uint64_t* offsets, uint32_t* ids,
+                            uint64_t ids_cap, uint64_t* total_out) {
+  if (!h || (m > 0 && !qepoch)) return SFC_ERR_INVALID;
+  return query_impl(h, q, delta, nullptr, m, offsets, ids, ids_cap, total_out, qepoch);
 }
 
 sfc_status sfc_query_sets(sfc_index* h, const double* q, const double* delta,
@@ -709,6 +798,7 @@ struct sfc_graph {
   sfc::QueryScratch qs{};
   uint64_t m = 0, max_rows = 0, cap_ids = 0;
   uint64_t* offsets = nullptr;
+  uint64_t generation = 0;      // h's generation at recording
 };
 
 namespace {
@@ -751,11 +841,12 @@ extern "C" {
 
 sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out) {
   if (!h || !out || (h->n > 0 && !xy)) return SFC_ERR_INVALID;
-  if (h->n == 0) return SFC_ERR_UNSUPPORTED;
+  if (h->n == 0 || h->ins) return SFC_ERR_UNSUPPORTED;
   sfc_graph* g = new (std::nothrow) sfc_graph();
   if (!g) return SFC_ERR_NOMEM;
   g->h = h;
   g->kind = 0;
+  g->generation = h->generation;
   const size_t sb = sfc::build_scratch_bytes(h->n, nullptr) + 256;
   g->scratch = h->alloc.get(sb);
   if (!g->scratch) {
@@ -788,6 +879,7 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   if (!g) return SFC_ERR_NOMEM;
   g->h = h;
   g->kind = 1;
+  g->generation = h->generation;
   g->m = m;
   g->max_rows = max_rows;
   g->cap_ids = ids_cap;
@@ -800,6 +892,8 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   }
   sfc::query_scratch_carve(g->scratch, m, &g->qs);
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
+  sfc::EpochView ev;
+  const bool filtered = epoch_view(h, nullptr, &ev);
   sfc_status st = graph_capture(g, [&](hipStream_t s) {
     hipError_t e = sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
                                       h->refine_min, learned ? h->lparams : nullptr,
@@ -808,7 +902,7 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
                                       nullptr, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess)
       e = sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, g->qs, max_rows, true,
-                              g->cscratch, offsets, ids, ids_cap, s);
+                              g->cscratch, offsets, ids, ids_cap, s, filtered ? &ev : nullptr);
     return e;
   });
   if (st != SFC_OK) {
@@ -821,6 +915,7 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
 
 sfc_status sfc_graph_launch(sfc_graph* g) {
   if (!g || !g->exec) return SFC_ERR_INVALID;
+  if (g->generation != g->h->generation) return SFC_ERR_INVALID;   // recorded before an update
   SFC_TRY(hipGraphLaunch(g->exec, g->h->stream));
   return SFC_OK;
 }
@@ -992,6 +1087,291 @@ void sfc_pool_trim(void) {
   for (auto& kv : P.free_blocks)
     for (void* p : kv.second) (void)hipFree(p);
   P.free_blocks.clear();
+}
+
+}  // extern "C"
+
+// ---- updates ---------------------------------------------------------------
+
+namespace {
+
+// Allocates the epoch arrays (everything stored so far: inserted at epoch 0,
+// live) and the id -> key table, before the first update.
+sfc_status ensure_dynamic(sfc_index* h) {
+  if (h->ins) return SFC_OK;
+  const uint64_t c = h->cap ? h->cap : 1;
+  const uint64_t kc = h->next_id > 1024 ? h->next_id : 1024;
+  uint32_t* ins = (uint32_t*)h->alloc.get(c * 4);
+  uint32_t* era = (uint32_t*)h->alloc.get(c * 4);
+  uint64_t* key_of = (uint64_t*)h->alloc.get(kc * 8);
+  uint64_t* word = (uint64_t*)h->alloc.get(256);
+  if (!ins || !era || !key_of || !word) {
+    h->alloc.put(ins);
+    h->alloc.put(era);
+    h->alloc.put(key_of);
+    h->alloc.put(word);
+    return SFC_ERR_NOMEM;
+  }
+  hipError_t e = sfc::fill_u32(ins, 0, c, h->stream);
+  if (e == hipSuccess) e = sfc::fill_u32(era, sfc::kLiveEpoch, c, h->stream);
+  if (e == hipSuccess) e = sfc::record_keys(h->keys, h->ids, h->n, key_of, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->alloc.put(ins);
+    h->alloc.put(era);
+    h->alloc.put(key_of);
+    h->alloc.put(word);
+    return from_hip(e);
+  }
+  h->ins = ins;
+  h->era = era;
+  h->key_of = key_of;
+  h->key_of_cap = kc;
+  h->upd_word = word;
+  return SFC_OK;
+}
+
+// The spare run holds at least `need` entries (grown by a quarter beyond).
+sfc_status ensure_spare(sfc_index* h, uint64_t need) {
+  if (need == 0) need = 1;
+  if (h->spare_cap >= need) return SFC_OK;
+  sfc::Run& r = h->spare;
+  h->alloc.put(r.keys);
+  h->alloc.put(r.ids);
+  h->alloc.put(r.xy);
+  h->alloc.put(r.ins);
+  h->alloc.put(r.era);
+  r = sfc::Run{};
+  h->spare_cap = 0;
+  const uint64_t c = need + need / 4;
+  r.keys = (uint64_t*)h->alloc.get(c * 8);
+  r.ids = (uint32_t*)h->alloc.get(c * 4);
+  r.xy = (double*)h->alloc.get(c * 16);
+  r.ins = (uint32_t*)h->alloc.get(c * 4);
+  r.era = (uint32_t*)h->alloc.get(c * 4);
+  if (!r.keys || !r.ids || !r.xy || !r.ins || !r.era) {
+    h->alloc.put(r.keys);
+    h->alloc.put(r.ids);
+    h->alloc.put(r.xy);
+    h->alloc.put(r.ins);
+    h->alloc.put(r.era);
+    r = sfc::Run{};
+    return SFC_ERR_NOMEM;
+  }
+  h->spare_cap = c;
+  return SFC_OK;
+}
+
+// The id -> key table covers ids [0, need).
+sfc_status ensure_key_of(sfc_index* h, uint64_t need) {
+  if (h->key_of_cap >= need) return SFC_OK;
+  uint64_t c = h->key_of_cap * 2;
+  if (c < need) c = need;
+  uint64_t* t = (uint64_t*)h->alloc.get(c * 8);
+  if (!t) return SFC_ERR_NOMEM;
+  hipError_t e = hipMemcpyAsync(t, h->key_of, (uint64_t)h->next_id * 8, hipMemcpyDeviceToDevice,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->alloc.put(t);
+    return from_hip(e);
+  }
+  h->alloc.put(h->key_of);
+  h->key_of = t;
+  h->key_of_cap = c;
+  return SFC_OK;
+}
+
+sfc::Run current_run(const sfc_index* h) {
+  sfc::Run r;
+  r.keys = h->keys;
+  r.ids = h->ids;
+  r.xy = h->xy;
+  r.ins = h->ins;
+  r.era = h->era;
+  return r;
+}
+
+void swap_runs(sfc_index* h) {
+  std::swap(h->keys, h->spare.keys);
+  std::swap(h->ids, h->spare.ids);
+  std::swap(h->xy, h->spare.xy);
+  std::swap(h->ins, h->spare.ins);
+  std::swap(h->era, h->spare.era);
+  std::swap(h->cap, h->spare_cap);
+}
+
+uint64_t droppable(const sfc_index* h) {
+  uint64_t d = 0;
+  for (const auto& t : h->tombs)
+    if (t.first <= h->oldest) d += t.second;
+  return d;
+}
+
+// Drops every tombstone no queryable epoch sees (era <= oldest).
+sfc_status compact_now(sfc_index* h) {
+  const uint64_t drop = droppable(h);
+  if (drop == 0) return SFC_OK;
+  const uint64_t keep = h->n - drop;
+  // Room for every stored entry: the device's count decides what is written.
+  sfc_status st = ensure_spare(h, h->n);
+  if (st != SFC_OK) return st;
+  void* scratch = h->alloc.get(sfc::compact_entries_scratch(h->n));
+  if (!scratch) return SFC_ERR_NOMEM;
+  uint64_t* kept_dev = nullptr;
+  uint64_t kept = 0;
+  hipError_t e = sfc::compact_entries(current_run(h), h->n, h->oldest, h->spare, scratch,
+                                      &kept_dev, h->stream);
+  if (e == hipSuccess) e = read_words(kept_dev, &kept, 1, h->stream);
+  h->alloc.put(scratch);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return from_hip(e);
+  }
+  if (kept != keep) return SFC_ERR_DEVICE;   // the host's tombstone count disagrees
+  swap_runs(h);
+  h->n = keep;
+  h->dead -= drop;
+  std::vector<std::pair<uint32_t, uint64_t>> rest;
+  for (const auto& t : h->tombs)
+    if (t.first > h->oldest) rest.push_back(t);
+  h->tombs.swap(rest);
+  ++h->generation;
+  ++h->compactions;
+  return refit_leaves(h);
+}
+
+// Compacts once the droppable tombstones reach a tenth of the stored entries.
+sfc_status maybe_compact(sfc_index* h) {
+  const uint64_t d = droppable(h);
+  if (d > 0 && d * 10 >= h->n) return compact_now(h);
+  return SFC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_out) {
+  if (!h || (k > 0 && !xy)) return SFC_ERR_INVALID;
+  if (h->n_sets) return SFC_ERR_UNSUPPORTED;
+  if (k == 0) return SFC_OK;
+  if ((uint64_t)h->next_id + k > 0xFFFFFFFEull) return SFC_ERR_INVALID;
+  if (h->epoch >= 0xFFFFFFFEu) return SFC_ERR_UNSUPPORTED;
+  sfc_status st = ensure_dynamic(h);
+  if (st == SFC_OK) st = ensure_key_of(h, (uint64_t)h->next_id + k);
+  if (st == SFC_OK) st = ensure_spare(h, h->n + k);
+  if (st != SFC_OK) return st;
+  const size_t sb = sfc::build_scratch_bytes(k, nullptr) + 256;
+  char* batch = (char*)h->alloc.get(align256(k * 8) + align256(k * 4) + align256(k * 16) + sb);
+  if (!batch) return SFC_ERR_NOMEM;
+  uint64_t* bkeys = (uint64_t*)batch;
+  uint32_t* bids = (uint32_t*)(batch + align256(k * 8));
+  double* bxy = (double*)(batch + align256(k * 8) + align256(k * 4));
+  void* scratch = batch + align256(k * 8) + align256(k * 4) + align256(k * 16);
+  uint32_t* err = (uint32_t*)((char*)scratch + sb - 256);
+  const uint32_t ep = h->epoch + 1;
+  // Sort the batch, merge it into the spare run; the swap happens only when
+  // the batch's coordinates were all in the domain.
+  hipError_t e = sfc::fill_u32(err, 0, 1, h->stream);
+  if (e == hipSuccess)
+    e = sfc::sort_build(xy, k, h->curve, bkeys, bids, bxy, scratch, err, h->stream);
+  if (e == hipSuccess)
+    e = sfc::merge_runs(current_run(h), h->n, bkeys, bids, bxy, k, h->next_id, ep, h->spare,
+                        h->key_of, h->stream);
+  if (e == hipSuccess && ids_out) e = sfc::fill_iota(ids_out, k, h->next_id, h->stream);
+  uint64_t w = 0;
+  if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
+  h->alloc.put(batch);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return from_hip(e);
+  }
+  if ((uint32_t)w & sfc::kErrDomain) return SFC_ERR_DOMAIN;
+  if ((uint32_t)w & (sfc::kErrLookback | sfc::kErrInternal)) return SFC_ERR_DEVICE;
+  swap_runs(h);
+  h->n += k;
+  h->next_id += (uint32_t)k;
+  h->epoch = ep;
+  h->max_ins = ep;
+  if (!h->hold) h->oldest = ep;
+  ++h->generation;
+  ++h->merges;
+  const uint64_t compactions = h->compactions;
+  st = maybe_compact(h);   // a compaction refits the learned leaves itself
+  if (st == SFC_OK && h->compactions == compactions) st = refit_leaves(h);
+  return st;
+}
+
+sfc_status sfc_erase(sfc_index* h, const uint32_t* ids, uint64_t k, uint64_t* erased_out) {
+  if (!h || (k > 0 && !ids)) return SFC_ERR_INVALID;
+  if (h->n_sets) return SFC_ERR_UNSUPPORTED;
+  if (k == 0) {
+    if (erased_out) *erased_out = 0;
+    return SFC_OK;
+  }
+  if (h->epoch >= 0xFFFFFFFEu) return SFC_ERR_UNSUPPORTED;
+  sfc_status st = ensure_dynamic(h);
+  if (st != SFC_OK) return st;
+  const uint32_t ep = h->epoch + 1;
+  uint64_t cnt = 0;
+  hipError_t e = sfc::fill_u64(h->upd_word, 0, 1, h->stream);
+  if (e == hipSuccess)
+    e = sfc::erase_entries(ids, k, h->next_id, h->key_of, current_run(h), h->n, ep,
+                           (unsigned long long*)h->upd_word, h->stream);
+  if (e == hipSuccess) e = read_words(h->upd_word, &cnt, 1, h->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return from_hip(e);
+  }
+  h->epoch = ep;
+  if (cnt) {
+    h->tombs.emplace_back(ep, cnt);
+    h->dead += cnt;
+  }
+  if (!h->hold) h->oldest = ep;
+  ++h->generation;
+  if (erased_out) *erased_out = cnt;
+  return maybe_compact(h);
+}
+
+sfc_status sfc_hold_epochs(sfc_index* h, int hold) {
+  if (!h || (hold != 0 && hold != 1)) return SFC_ERR_INVALID;
+  h->hold = hold;
+  if (!hold && h->oldest != h->epoch) {
+    h->oldest = h->epoch;
+    return maybe_compact(h);
+  }
+  return SFC_OK;
+}
+
+sfc_status sfc_retire(sfc_index* h, uint32_t epoch) {
+  if (!h || epoch > h->epoch) return SFC_ERR_INVALID;
+  if (epoch <= h->oldest) return SFC_OK;
+  h->oldest = epoch;
+  return maybe_compact(h);
+}
+
+sfc_status sfc_compact(sfc_index* h) {
+  if (!h) return SFC_ERR_INVALID;
+  return compact_now(h);
+}
+
+sfc_status sfc_update_info_get(const sfc_index* h, sfc_update_info* out) {
+  if (!h || !out) return SFC_ERR_INVALID;
+  out->epoch = h->epoch;
+  out->oldest = h->oldest;
+  out->next_id = h->next_id;
+  out->hold = (uint32_t)h->hold;
+  out->stored = h->n;
+  out->dead = h->dead;
+  out->live = h->n - h->dead;
+  out->droppable = droppable(h);
+  out->merges = h->merges;
+  out->compactions = h->compactions;
+  return SFC_OK;
 }
 
 }  // extern "C"

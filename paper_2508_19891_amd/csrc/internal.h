@@ -76,14 +76,56 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
 // device_sized = true: max_rows is a capacity, the count is read on the
 // device (a plan for graph capture); more rows raise kErrOverflow.  cscratch
 // holds compact_scratch_bytes(max_rows).
+struct EpochView;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
-                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s);
+                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s,
+                          const EpochView* ev = nullptr);
 // Scan with the element count in device memory (count_dev <= max_count).
 hipError_t scan_excl_dev(const uint32_t* in, uint64_t* out, const uint32_t* count_dev,
                          uint64_t max_count, const uint64_t* carry_in, uint64_t* partial,
                          hipStream_t s);
+
+// ---- updates (update.hip) ----
+constexpr uint32_t kLiveEpoch = 0xFFFFFFFFu;   // era of an entry not erased
+// The stored run: sorted (key, id) with the points and the epochs at which
+// each entry was inserted (ins) and erased (era).
+struct Run {
+  uint64_t* keys = nullptr;
+  uint32_t* ids = nullptr;
+  double* xy = nullptr;
+  uint32_t* ins = nullptr;
+  uint32_t* era = nullptr;
+};
+// Which stored entries a query sees: those with ins <= e < era, e = the
+// query's epoch (qepoch[j], or `epoch` when qepoch is null).  ins == null:
+// every entry is visible.
+struct EpochView {
+  const uint32_t* ins = nullptr;
+  const uint32_t* era = nullptr;
+  const uint32_t* qepoch = nullptr;
+  uint32_t epoch = 0;
+};
+// Merges the stored run (n entries) with a sorted batch (k entries, local
+// ids bids) into `out` (n + k entries).
+hipError_t merge_runs(const Run& stored, uint64_t n, const uint64_t* bkeys, const uint32_t* bids,
+                      const double* bxy, uint64_t k, uint32_t id_base, uint32_t epoch,
+                      const Run& out, uint64_t* key_of, hipStream_t s);
+hipError_t record_keys(const uint64_t* keys, const uint32_t* ids, uint64_t n, uint64_t* key_of,
+                       hipStream_t s);
+hipError_t erase_entries(const uint32_t* del, uint64_t k, uint32_t next_id, const uint64_t* key_of,
+                         const Run& stored, uint64_t n, uint32_t epoch,
+                         unsigned long long* erased, hipStream_t s);
+// Drops the entries with era <= oldest; *kept_total points at the device
+// word that receives the number kept.
+size_t compact_entries_scratch(uint64_t n);
+hipError_t compact_entries(const Run& stored, uint64_t n, uint32_t oldest, const Run& out,
+                           void* scratch, uint64_t** kept_total, hipStream_t s);
+hipError_t fill_iota(uint32_t* out, uint64_t k, uint32_t first, hipStream_t s);
+// Raises kErrInvalidQuery in *err for an epoch outside [oldest, epoch].
+hipError_t validate_epochs(const uint32_t* qe, uint64_t m, uint32_t oldest, uint32_t epoch,
+                           uint32_t* err, hipStream_t s);
 
 // ---- learned index (learned.hip) ----
 size_t learned_scratch_bytes();
@@ -92,6 +134,9 @@ size_t learned_scratch_bytes();
 // leaves: kLeaves records, losses: 2 floats (sample loss before / after).
 hipError_t learned_fit(const uint64_t* keys, uint64_t n, uint32_t steps, float lr, float* params,
                        LeafRec* leaves, void* scratch, float* losses, hipStream_t s);
+// Refits the leaves for changed keys with the router kept (after an update).
+hipError_t learned_refit_leaves(const uint64_t* keys, uint64_t n, const float* params,
+                                LeafRec* leaves, void* scratch, hipStream_t s);
 // Gradient of one batch (cnt <= 128 samples) with the trainer's own code.
 hipError_t learned_grad(const float* params, const float* xs, const float* ts, int cnt,
                         float* grad, float* loss, hipStream_t s);

@@ -99,6 +99,10 @@ __device__ __forceinline__ uint64_t learned_lower_bound(const uint64_t* __restri
   int64_t wlo = p + L.elo, whi = p + L.ehi;
   wlo = wlo < (int64_t)L.S ? (int64_t)L.S : wlo;
   whi = whi > (int64_t)L.E ? (int64_t)L.E : whi;
+  // The leaves describe the keys they were fitted on; the clamp to [0, n]
+  // keeps every probe inside the array should they ever be stale.
+  whi = whi > (int64_t)n ? (int64_t)n : whi;
+  wlo = wlo > whi ? whi : wlo;
   if (whi < wlo) whi = wlo;
   const uint64_t r = lower_bound_in(keys, (uint64_t)wlo, (uint64_t)whi, k);
   const bool ok = (r == 0 || keys[r - 1] < k) && (r == n || keys[r] >= k);

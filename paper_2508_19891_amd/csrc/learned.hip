@@ -433,6 +433,26 @@ hipError_t learned_fit(const uint64_t* keys, uint64_t n, uint32_t steps, float l
   return hipSuccess;
 }
 
+hipError_t learned_refit_leaves(const uint64_t* keys, uint64_t n, const float* params,
+                                LeafRec* leaves, void* scratch, hipStream_t s) {
+  if (n == 0) return hipErrorInvalidValue;
+  char* p = (char*)scratch;
+  p += 2 * align256(kSamples * 4);
+  uint32_t* bounds = (uint32_t*)p;
+  hipError_t e;
+  {
+    ProfScope ps("learned_bounds", s);
+    learned_bounds<<<(kLeaves + 1 + 255) / 256, 256, 0, s>>>(keys, n, params, bounds);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    ProfScope ps("learned_leaves", s);
+    learned_leaves<<<kLeaves, 256, 0, s>>>(keys, n, bounds, leaves);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t learned_grad(const float* params, const float* xs, const float* ts, int cnt,
                         float* grad, float* loss, hipStream_t s) {
   if (cnt < 1 || cnt > kBatch) return hipErrorInvalidValue;

@@ -451,13 +451,16 @@ __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ 
 // Pass 1: the exact test of every candidate; per row the 64-bit mask of the
 // accepted lanes, per tile their number.  Each wave handles 16 consecutive
 // rows as ITERS groups of ROWS rows whose point loads are in flight together.
-template <int ROWS, int ITERS>
+// EPOCH: a candidate that passes the test also has to be visible at the
+// query's epoch (ins <= e < era); only those lanes read the epochs.
+template <int ROWS, int ITERS, bool EPOCH>
 __global__ __launch_bounds__(256) void compact_test(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const double2* __restrict__ pts, uint64_t npts, const uint4* __restrict__ row_meta,
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     bool flag_overflow, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits,
-    uint32_t* counters) {
+    uint32_t* counters, const uint32_t* __restrict__ ins, const uint32_t* __restrict__ era,
+    const uint32_t* __restrict__ qepoch, uint32_t epoch) {
   __shared__ uint32_t s_cnt[4];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
@@ -472,6 +475,7 @@ __global__ __launch_bounds__(256) void compact_test(
       if (lane < (uint32_t)ROWS && g0 + lane < total_rows) md = row_meta[g0 + lane - rbase];
       uint32_t pos[ROWS];
       double qx[ROWS], qy[ROWS], dd[ROWS];
+      uint32_t qe[ROWS];
       bool act[ROWS];
 #pragma unroll
       for (int jr = 0; jr < ROWS; ++jr) {
@@ -486,6 +490,7 @@ __global__ __launch_bounds__(256) void compact_test(
         qx[jr] = qq.x;
         qy[jr] = qq.y;
         dd[jr] = delta[qs];
+        if (EPOCH) qe[jr] = qepoch ? qepoch[qs] : epoch;
       }
       double2 pv[ROWS];
 #pragma unroll
@@ -493,7 +498,8 @@ __global__ __launch_bounds__(256) void compact_test(
         if (act[jr]) pv[jr] = pts[pos[jr]];
 #pragma unroll
       for (int jr = 0; jr < ROWS; ++jr) {
-        const bool hit = act[jr] && within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]);
+        bool hit = act[jr] && within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]);
+        if (EPOCH && hit) hit = ins[pos[jr]] <= qe[jr] && qe[jr] < era[pos[jr]];
         const uint64_t bal = __ballot(hit);
         cnt += (uint32_t)__popcll(bal);
         if (lane == 0) masks[tile * kTileRows + (uint64_t)(w * ITERS + it) * ROWS + jr] = bal;
@@ -713,7 +719,8 @@ constexpr uint64_t kCompactGrid = 4096;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
-                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s) {
+                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s,
+                          const EpochView* ev) {
   hipError_t e;
   if (m == 0) return fill_u64(offsets, 0, 1, s);
   const uint64_t nseg = m << qs.ss;
@@ -756,17 +763,25 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
     }
     {
       ProfScope ps("compact_test", s);
-#define SFC_TEST(R, I)                                                                       \
-  compact_test<R, I><<<grid, 256, 0, s>>>((const double2*)q, delta, m, (const double2*)pts, \
-                                          npts, meta, total_dev, rbase, row_end, flag,      \
-                                          masks, hits, qs.counters)
-      switch (test_variant(max_rows)) {
-        case 1: SFC_TEST(4, 4); break;
-        case 2: SFC_TEST(8, 2); break;
-        case 3: SFC_TEST(2, 8); break;
-        case 4: SFC_TEST(1, 16); break;
-        default: SFC_TEST(16, 1); break;
+#define SFC_TEST(R, I, E)                                                                  \
+  compact_test<R, I, E><<<grid, 256, 0, s>>>(                                             \
+      (const double2*)q, delta, m, (const double2*)pts, npts, meta, total_dev, rbase,     \
+      row_end, flag, masks, hits, qs.counters, ev ? ev->ins : nullptr,                    \
+      ev ? ev->era : nullptr, ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u)
+#define SFC_TEST_SHAPES(E)                  \
+  switch (test_variant(max_rows)) {         \
+    case 1: SFC_TEST(4, 4, E); break;       \
+    case 2: SFC_TEST(8, 2, E); break;       \
+    case 3: SFC_TEST(2, 8, E); break;       \
+    case 4: SFC_TEST(1, 16, E); break;      \
+    default: SFC_TEST(16, 1, E); break;     \
+  }
+      if (ev && ev->ins) {
+        SFC_TEST_SHAPES(true)
+      } else {
+        SFC_TEST_SHAPES(false)
       }
+#undef SFC_TEST_SHAPES
 #undef SFC_TEST
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -37,6 +37,8 @@ EXPORTS = [
     "sfc_learned_shrink_windows", "sfc_build_sets", "sfc_query_sets", "sfc_graph_build",
     "sfc_graph_query", "sfc_graph_launch", "sfc_graph_wait", "sfc_graph_free",
     "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
+    "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
+    "sfc_compact", "sfc_update_info_get",
 ]
 
 NPARAM = 1153
@@ -83,6 +85,14 @@ class LearnedInfo(ctypes.Structure):
 class QueryStats(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_uint64), ("rows", ctypes.c_uint64),
                 ("candidates", ctypes.c_uint64), ("reported", ctypes.c_uint64)]
+
+
+class UpdateInfo(ctypes.Structure):
+    _fields_ = [("epoch", ctypes.c_uint32), ("oldest", ctypes.c_uint32),
+                ("next_id", ctypes.c_uint32), ("hold", ctypes.c_uint32),
+                ("stored", ctypes.c_uint64), ("live", ctypes.c_uint64),
+                ("dead", ctypes.c_uint64), ("droppable", ctypes.c_uint64),
+                ("merges", ctypes.c_uint64), ("compactions", ctypes.c_uint64)]
 
 
 _lib = None
@@ -160,6 +170,20 @@ def lib() -> ctypes.CDLL:
     L.sfc_autotune_query.restype = i32
     L.sfc_debug_chunk_tiles.argtypes = [u64]
     L.sfc_debug_chunk_tiles.restype = i32
+    L.sfc_insert.argtypes = [vp, vp, u64, vp]
+    L.sfc_insert.restype = i32
+    L.sfc_erase.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
+    L.sfc_erase.restype = i32
+    L.sfc_query_epochs.argtypes = [vp, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(u64)]
+    L.sfc_query_epochs.restype = i32
+    L.sfc_hold_epochs.argtypes = [vp, i32]
+    L.sfc_hold_epochs.restype = i32
+    L.sfc_retire.argtypes = [vp, u32]
+    L.sfc_retire.restype = i32
+    L.sfc_compact.argtypes = [vp]
+    L.sfc_compact.restype = i32
+    L.sfc_update_info_get.argtypes = [vp, ctypes.POINTER(UpdateInfo)]
+    L.sfc_update_info_get.restype = i32
     _lib = L
     return L
 
@@ -324,6 +348,61 @@ class Index:
             raise CapacityError(st, "sfc_query_sets", int(total.value))
         _check(st, "sfc_query_sets")
         return offsets, out_ids[: int(total.value)]
+
+    def query_epochs(self, q: torch.Tensor, delta: torch.Tensor, qepoch: torch.Tensor,
+                     out_ids: torch.Tensor | None = None,
+                     out_offsets: torch.Tensor | None = None):
+        """Queries answered at per-query epochs qepoch (m,) int32 (uint32
+        values).  Returns (offsets int64[m+1], ids int32[total])."""
+        q = _dev(q, torch.float64, "q")
+        delta = _dev(delta, torch.float64, "delta")
+        qepoch = _dev(qepoch, torch.int32, "qepoch")
+        m = q.shape[0]
+        offsets = out_offsets if out_offsets is not None else torch.empty(
+            m + 1, dtype=torch.int64, device=self.device)
+        cap_given = out_ids is not None
+        if out_ids is None:
+            out_ids = torch.empty(max(16 * m, 1024), dtype=torch.int32, device=self.device)
+        total = ctypes.c_uint64(0)
+        args = (self.handle, _ptr(q), _ptr(delta), _ptr(qepoch), m, _ptr(offsets))
+        st = lib().sfc_query_epochs(*args, _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY and not cap_given:
+            out_ids = torch.empty(max(int(total.value), 1), dtype=torch.int32, device=self.device)
+            st = lib().sfc_query_epochs(*args, _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY:
+            raise CapacityError(st, "sfc_query_epochs", int(total.value))
+        _check(st, "sfc_query_epochs")
+        return offsets, out_ids[: int(total.value)]
+
+    def insert(self, xy: torch.Tensor, want_ids: bool = True):
+        """Inserts points (k, 2); returns their ids (int32 tensor) or None."""
+        xy = _dev(xy, torch.float64, "xy")
+        k = xy.shape[0]
+        ids = torch.empty(k, dtype=torch.int32, device=self.device) if want_ids else None
+        _check(lib().sfc_insert(self.handle, _ptr(xy), k, _ptr(ids)), "sfc_insert")
+        return ids
+
+    def erase(self, ids: torch.Tensor) -> int:
+        """Erases ids (k,) int32; returns the number of entries erased."""
+        ids = _dev(ids, torch.int32, "ids")
+        cnt = ctypes.c_uint64(0)
+        _check(lib().sfc_erase(self.handle, _ptr(ids), ids.numel(), ctypes.byref(cnt)),
+               "sfc_erase")
+        return int(cnt.value)
+
+    def hold_epochs(self, hold: bool = True):
+        _check(lib().sfc_hold_epochs(self.handle, 1 if hold else 0), "sfc_hold_epochs")
+
+    def retire(self, epoch: int):
+        _check(lib().sfc_retire(self.handle, epoch), "sfc_retire")
+
+    def compact(self):
+        _check(lib().sfc_compact(self.handle), "sfc_compact")
+
+    def update_info(self) -> dict:
+        u = UpdateInfo()
+        _check(lib().sfc_update_info_get(self.handle, ctypes.byref(u)), "sfc_update_info_get")
+        return {f: int(getattr(u, f)) for f, _ in UpdateInfo._fields_}
 
     def query_ranges(self, q: torch.Tensor, delta: torch.Tensor):
         """Per query four slots of (key_lo, key_hi, begin, end) and the number
