@@ -145,6 +145,41 @@ def batched_sets_bench(args, sfc, workload, torch):
                          "test_shape": tune_q, "test_shape_ms": tune_q_ms}}
 
 
+def serving_bench(args, sfc, workload, torch):
+    """Poisson stream of query / insert / erase batches (40/40/20, sizes
+    2^U[10,16]) over 2^25 clustered points, Morton keys, learned search:
+    first the saturation throughput (every request queued at time 0), then
+    arrivals at 0.5, 0.8 and 0.95 of it; p50/p99 from arrival to completion."""
+    from paper_2508_19891_amd import serving
+    dev = torch.device("cuda:0")
+    trace = workload.serving_trace(n0=1 << args.serving_n_log2, requests=args.serving_requests)
+    log(f"serving: n0={len(trace.initial)}, {len(trace.kind)} requests")
+    pools = serving.Pools.upload(trace, dev)
+    init = torch.as_tensor(trace.initial).to(dev)
+    out_ids = torch.empty(1 << 26, dtype=torch.int32, device=dev)
+    out = {"workload": trace.name, "curve": "morton", "search": "learned",
+           "mix": "40% query, 40% insert, 20% erase batches of 2^U[10,16]"}
+
+    def one(rate):
+        idx = sfc.Index(init, sfc.MORTON, search=sfc.LEARNED, refine=True)
+        torch.cuda.synchronize()
+        run = serving.serve(idx, trace, pools, rate=rate, out_ids=out_ids)
+        s = serving.summarize(trace, run)
+        s["compactions"] = idx.update_info()["compactions"]
+        idx.close()
+        return s
+
+    sat = one(float("inf"))
+    out["saturation"] = sat
+    for f in (0.5, 0.8, 0.95):
+        rate = f * sat["requests_per_s"]
+        s = one(rate)
+        s["offered_requests_per_s"] = rate
+        out[f"load_{f}"] = s
+        log(f"serving at {f} of saturation: p50 {s['p50_ms']:.2f} ms, p99 {s['p99_ms']:.2f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +193,10 @@ def main():
                     help="time only the refined range mode (for profiler runs)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched point-set measurement")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the insert/erase/query serving measurement")
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-n-log2", type=int, default=25)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (counter calibration)")
     args = ap.parse_args()
@@ -312,6 +351,8 @@ def main():
     }
     if not args.no_batched and not args.only_refined:
         line["batched_sets"] = batched_sets_bench(args, sfc, workload, torch)
+    if not args.no_serving and not args.only_refined:
+        line["serving"] = serving_bench(args, sfc, workload, torch)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         line["cpu_baseline"] = cpu_baseline(wl, curve, min(m, 1 << args.cpu_sample_log2))

@@ -168,3 +168,81 @@ def batched_uneven(n_sets: int = 256, log2_n: tuple = (10, 20), log2_m: tuple = 
     set_off[1:] = np.cumsum(ns)
     return BatchedWorkload(f"batched_{n_sets}sets", np.concatenate(pts), set_off,
                            np.concatenate(qs), np.concatenate(ds), np.concatenate(qset), curve)
+
+
+# ---- serving trace ------------------------------------------------------------
+
+QUERY, INSERT, ERASE = 0, 1, 2
+
+
+@dataclasses.dataclass
+class ServingTrace:
+    """A request stream over an initial point set.  Request r has a kind, a
+    size and the start of its payload in the pool of its kind; gaps are
+    Exp(1) inter-arrival draws (a Poisson process once divided by the
+    rate).  Erase payloads are ids live at that point of the stream, drawn
+    uniformly without replacement (ids: 0..n0-1 for the initial points, then
+    consecutive ids per insert in stream order)."""
+    name: str
+    initial: np.ndarray      # (n0, 2)
+    kind: np.ndarray         # (R,) int8
+    size: np.ndarray         # (R,) int64
+    start: np.ndarray        # (R,) int64, offset into the kind's pool
+    gaps: np.ndarray         # (R,) float64
+    queries: np.ndarray      # (Mq, 2)
+    delta: np.ndarray        # (Mq,)
+    inserts: np.ndarray      # (Mi, 2)
+    erase_ids: np.ndarray    # (Me,) uint32
+    curve: int
+
+
+def serving_trace(n0: int = 1 << 25, requests: int = 2000, seed: int = 5, curve: int = 0,
+                  mix: tuple = (0.4, 0.4, 0.2), log2_size: tuple = (10, 16),
+                  c_lo: float = 1.0, c_hi: float = 1000.0) -> ServingTrace:
+    """Clustered initial points; query, insert and erase requests in the
+    proportions ``mix`` with sizes round(2^U[log2_size]); queries and
+    inserted points from the same mixture, radii aimed at an output
+    log-uniform in [c_lo, c_hi] over the live count at that point."""
+    rng = _rng(5000 + seed)
+    mixture = make_mixture(500 + seed)
+    initial = clustered_points(n0, 1000 + seed, mixture)
+    kind = rng.choice(3, size=requests, p=np.asarray(mix, np.float64)).astype(np.int8)
+    size = np.rint(2.0 ** rng.uniform(*log2_size, requests)).astype(np.int64)
+    gaps = rng.exponential(1.0, requests)
+    start = np.zeros(requests, np.int64)
+    tot = [0, 0, 0]
+    for r in range(requests):
+        start[r] = tot[kind[r]]
+        tot[kind[r]] += size[r]
+    queries = clustered_points(tot[QUERY], 2000 + seed, mixture)
+    inserts = clustered_points(tot[INSERT], 3000 + seed, mixture)
+    # The live id set, simulated along the stream (swap-remove array).
+    live = np.empty(n0 + tot[INSERT], np.int64)
+    live[:n0] = np.arange(n0)
+    count, next_id = n0, n0
+    erase_ids = np.empty(tot[ERASE], np.uint32)
+    live_at_query = np.empty(tot[QUERY], np.int64)
+    for r in range(requests):
+        k = int(size[r])
+        if kind[r] == INSERT:
+            live[count:count + k] = np.arange(next_id, next_id + k)
+            count += k
+            next_id += k
+        elif kind[r] == ERASE:
+            k = min(k, count)
+            size[r] = k
+            pos = rng.choice(count, size=k, replace=False)
+            erase_ids[start[r]:start[r] + k] = live[pos]
+            new_count = count - k
+            holes = pos[pos < new_count]
+            tail = np.arange(new_count, count)
+            keep_tail = tail[~np.isin(tail, pos)]
+            live[holes] = live[keep_tail]
+            count = new_count
+        else:
+            live_at_query[start[r]:start[r] + k] = count
+    delta = np.empty(tot[QUERY])
+    c = loguniform(_rng(4000 + seed), c_lo, c_hi, tot[QUERY])
+    delta[:] = np.sqrt(c / (math.pi * np.maximum(live_at_query, 1) * mixture.density(queries)))
+    return ServingTrace(f"serving_n{n0}_r{requests}", initial, kind, size, start, gaps, queries,
+                        delta, inserts, erase_ids, curve)

@@ -1,0 +1,69 @@
+"""The continuous-batching loop: every query request, answered in a batch
+with others (in the mix) or in a tick of its own (alone), equals the oracle
+over the snapshot of the epoch it was admitted at."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import HILBERT, MORTON
+from paper_2508_19891_amd import serving, sfc, workload
+from snapshots import Model
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.mark.parametrize("curve,search", [(MORTON, sfc.LEARNED), (HILBERT, sfc.BINARY)])
+def test_batched_and_alone_equal_snapshot_oracle(curve, search):
+    trace = workload.serving_trace(n0=20_000, requests=90, seed=7, curve=curve,
+                                   log2_size=(6, 11))
+    pools = serving.Pools.upload(trace, DEV)
+    init = torch.as_tensor(trace.initial).to(DEV)
+    runs = []
+    for max_tick in (16, 1):
+        idx = sfc.Index(init, curve, search=search, refine=True)
+        runs.append((idx, serving.serve(idx, trace, pools, max_tick=max_tick, record=True)))
+    mixed, alone = runs[0][1], runs[1][1]
+    assert mixed.ticks < alone.ticks == len(trace.kind)
+
+    model = Model(trace.initial, hold=True)    # never retires: keeps every snapshot
+    expect_epoch = {}
+    for r in range(len(trace.kind)):
+        a, k = int(trace.start[r]), int(trace.size[r])
+        if trace.kind[r] == workload.INSERT:
+            model.insert(trace.inserts[a:a + k])
+        elif trace.kind[r] == workload.ERASE:
+            assert model.erase(trace.erase_ids[a:a + k]) == k
+        else:
+            expect_epoch[r] = model.epoch
+    for r, e in expect_epoch.items():
+        assert mixed.admitted[r] == e and alone.admitted[r] == e
+        a, k = int(trace.start[r]), int(trace.size[r])
+        want = model.reference(trace.queries[a:a + k], trace.delta[a:a + k], np.full(k, e), curve)
+        for run in (mixed, alone):
+            off, ids = run.outputs[r]
+            assert np.array_equal(off.view(np.uint64), want[0]), r
+            assert np.array_equal(ids.view(np.uint32), want[1]), r
+
+    # After the stream: compaction leaves exactly the live entries, sorted.
+    for idx, _ in runs:
+        idx.compact()
+        live = model.visible(model.epoch)
+        keys, ids, _ = idx.sorted_arrays()
+        sk, si = oracle.build(model.xy[live], curve)[:2]
+        assert np.array_equal(keys.cpu().numpy().view(np.uint64), sk)
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), live[si].astype(np.uint32))
+        info = idx.update_info()
+        assert info["dead"] == 0 and info["stored"] == len(live)
+
+
+def test_poisson_arrivals_complete_after_arrival():
+    trace = workload.serving_trace(n0=30_000, requests=60, seed=8, log2_size=(6, 10))
+    pools = serving.Pools.upload(trace, DEV)
+    idx = sfc.Index(torch.as_tensor(trace.initial).to(DEV), MORTON, refine=True)
+    run = serving.serve(idx, trace, pools, rate=2000.0)
+    lat = run.latency()
+    assert (lat > 0).all() and np.all(np.diff(run.arrival) >= 0)
+    s = serving.summarize(trace, run)
+    assert s["p99_ms"] >= s["p50_ms"] > 0 and s["requests"] == 60
