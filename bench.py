@@ -38,16 +38,21 @@ def kernel_source_hash(name: str) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(kernel: str, source: str, launches_candidates: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+def load_traffic(kernel: str, source: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (its 'key: value' lines), or None if the kernel's source changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.md")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    if rec.get("source_sha256_16") != kernel_source_hash(source):
+    rec = {}
+    for line in open(path):
+        k, sep, v = line.partition(": ")
+        if sep and k in ("kernel", "bytes_per_launch", "source", "source_sha256_16"):
+            rec[k] = v.strip()
+    if rec.get("kernel") != kernel or rec.get("source_sha256_16") != kernel_source_hash(source):
         return None
-    return rec.get("bytes_per_launch")
+    return float(rec["bytes_per_launch"])
 
 
 def cpu_baseline(wl, curve: int, m_sample: int):
@@ -297,8 +302,7 @@ def main():
     launches_per_step = d_launch / args.steps
     bytes_per_launch = algo[dom] / launches_per_step
     achieved = bytes_per_launch / (d_ms / d_launch * 1e-3) / 1e9
-    traffic = load_traffic(dom, "query.hip" if dom.startswith(("compact", "ranges")) else "build.hip",
-                           launches_per_step)
+    traffic = load_traffic(dom, "query.hip" if dom.startswith(("compact", "ranges")) else "build.hip")
 
     line = {
         "metric": "queries/s + reported pts/s at n=2^24, learned vs bsearch index, % HBM peak",
