@@ -316,12 +316,16 @@ sfc_status sfc_last_query_stats(const sfc_index* h, sfc_query_stats* out);
  * evaluated in FP32 with fused multiply-adds in a fixed order; its input is
  * the key's top 24 bits / 2^24 and its output, times 4096, picks one of 4096
  * leaves.  Non-negative weights make the router monotone in the key, so each
- * leaf holds a contiguous range keys[S..E) of the sorted keys.  A leaf
- * predicts a rank by a least-squares line (FP64) and stores the exact range
- * [elo, ehi] of (lower bound - prediction) over every query key that can
- * reach it.  A lower bound searches that window, is verified against its
- * neighbours, and falls back to a full binary search if the check fails, so
- * results equal plain binary search for any model.
+ * leaf holds a contiguous range keys[S..E) of the sorted keys.  A leaf is cut
+ * into pieces of 256 keys; the last piece whose first key is below the query
+ * key brackets the lower bound, and the piece predicts it by linear
+ * interpolation (FP64) with the exact range [elo, ehi] of (lower bound -
+ * prediction) over every query key that can reach it.  A lower bound
+ * searches that window, is checked against its neighbours, and falls back to
+ * a full binary search if the check fails, so results equal plain binary
+ * search for any model.  Queries evaluate the router through its exact
+ * tabulation (the first input of every leaf, found by evaluating the
+ * network), which gives the same leaf for every key.
  * The router is trained on the GPU (Adam, mean squared error to rank/n over
  * 2^16 evenly spaced sorted keys, batches of 128), starting from ramps
  * placed at the sample quantiles.
@@ -331,10 +335,15 @@ typedef struct {
   uint32_t steps;             /* training steps used */
   float loss_init, loss_final;/* sample MSE before / after training */
   uint32_t leaves, leaves_nonempty, max_leaf;
-  double mean_window;         /* search window, averaged over the keys */
+  double mean_window;         /* last-mile window, averaged over the keys */
   uint32_t max_window;
   uint64_t endpoints_last;    /* learned lower bounds in the last batch */
   uint64_t fallbacks_last;    /* of which fell back to binary search */
+  uint32_t pieces;            /* pieces over all leaves */
+  double search_steps;        /* ceil(log2(pieces of the leaf + 1)) + ceil(log2(window
+                                 + 1)), averaged over the keys: the search steps of a
+                                 lower bound after routing (binary search takes
+                                 about log2(n)) */
 } sfc_learned_info;
 
 /* Selects the search for later queries; SFC_SEARCH_LEARNED fits the model
@@ -353,7 +362,13 @@ sfc_status sfc_learned_params(const sfc_index* h, float* params);
    process (0 or more than 2^19 restores 2^19), so that the multi-chunk path
    can be checked on small inputs.  Results do not depend on it. */
 sfc_status sfc_debug_chunk_tiles(uint64_t tiles);
-/* Test hook for the fallback path: sets every leaf's window to the single
+/* Leaf of each key (device keys[count]) by evaluating the router network
+   (direct) and through the tabulation the queries use (table); both device
+   uint32[count].  For checking that the two agree.  SFC_ERR_UNSUPPORTED
+   before a fit. */
+sfc_status sfc_learned_route(sfc_index* h, const uint64_t* keys, uint64_t count,
+                             uint32_t* direct, uint32_t* table);
+/* Test hook for the fallback path: sets every piece's window to the single
    predicted position, so that most learned lower bounds fail verification
    and fall back to binary search.  Results stay exact. */
 sfc_status sfc_learned_shrink_windows(sfc_index* h);

@@ -2,6 +2,7 @@
 // host-side sequencing of the construction and query kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -206,7 +207,9 @@ struct sfc_index {
   sfc_query_stats last{};
   // learned index
   float* lparams = nullptr;        // device, sfc::kParams
-  sfc::LeafRec* lleaves = nullptr; // device, sfc::kLeaves
+  void* lmodel = nullptr;          // device: tabulated router, leaves and pieces
+  uint64_t lmodel_n = 0;           // keys lmodel is sized for
+  sfc::LearnedArrays larr{};       // carved from lmodel
   sfc_learned_info linfo{};
   int learn_steps = 256;
   // point sets (sfc_build_sets)
@@ -294,7 +297,7 @@ void release_arrays(sfc_index* h) {
   h->cws = nullptr;
   h->cws_bytes = 0;
   h->alloc.put(h->lparams);
-  h->alloc.put(h->lleaves);
+  h->alloc.put(h->lmodel);
   h->alloc.put(h->set_off);
   h->set_off = nullptr;
   h->alloc.put(h->ins);
@@ -313,7 +316,9 @@ void release_arrays(sfc_index* h) {
   h->key_of_cap = 0;
   h->upd_word = nullptr;
   h->lparams = nullptr;
-  h->lleaves = nullptr;
+  h->lmodel = nullptr;
+  h->lmodel_n = 0;
+  h->larr = sfc::LearnedArrays{};
   h->linfo = sfc_learned_info{};
   h->keys = nullptr;
   h->ids = nullptr;
@@ -332,9 +337,10 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   if (st != SFC_OK) return st;
   sfc::query_scratch_carve(h->ws, m, qs);
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
+  const sfc::LearnedView lv = h->larr.view();
   SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                             h->refine_min, learned ? h->lparams : nullptr,
-                             learned ? h->lleaves : nullptr, qset, qset ? h->set_off : nullptr,
+                             h->refine_min, learned ? &lv : nullptr, qset,
+                             qset ? h->set_off : nullptr,
                              h->n_sets, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs->counters + 2, h->stream));
@@ -352,47 +358,99 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   return SFC_OK;
 }
 
-// Size and window statistics of the fitted leaves.
-void leaf_stats(sfc_index* h, const std::vector<sfc::LeafRec>& leaves) {
+// Size and window statistics of the fitted leaves and pieces (read back).
+hipError_t leaf_stats(sfc_index* h) {
+  const sfc::LearnedArrays& a = h->larr;
+  std::vector<uint2> lp(sfc::kLeaves + 1);
+  hipError_t e = hipMemcpyAsync(lp.data(), a.lp, lp.size() * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return e;
+  std::vector<uint32_t> lb(sfc::kLeaves + 1), po(sfc::kLeaves + 1);
+  for (int l = 0; l <= sfc::kLeaves; ++l) {
+    lb[l] = lp[l].x;
+    po[l] = lp[l].y;
+  }
+  const uint32_t np = po[sfc::kLeaves] < a.max_pieces ? po[sfc::kLeaves] : a.max_pieces;
+  std::vector<sfc::PieceRec> pr(np);
+  if (np) {
+    e = hipMemcpyAsync(pr.data(), a.pr, np * sizeof(sfc::PieceRec), hipMemcpyDeviceToHost,
+                       h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+  }
   sfc_learned_info& I = h->linfo;
   I.leaves = sfc::kLeaves;
   I.leaves_nonempty = 0;
   I.max_leaf = 0;
   I.max_window = 0;
-  double wsum = 0.0;
-  for (const sfc::LeafRec& L : leaves) {
-    const uint32_t size = L.E - L.S;
+  I.pieces = np;
+  double wsum = 0.0, ssum = 0.0;
+  for (int l = 0; l < sfc::kLeaves; ++l) {
+    const uint32_t size = lb[l + 1] > lb[l] ? lb[l + 1] - lb[l] : 0;
     if (size == 0) continue;
     ++I.leaves_nonempty;
     if (size > I.max_leaf) I.max_leaf = size;
-    const uint32_t win = (uint32_t)(L.ehi - L.elo + 1);
-    if (win > I.max_window) I.max_window = win;
-    wsum += (double)size * win;
+    const uint32_t f = po[l + 1] - po[l];
+    const double piece_steps = std::ceil(std::log2((double)f + 1.0));
+    for (uint32_t j = po[l]; j < po[l + 1] && j < np; ++j) {
+      const uint32_t keys_j = std::min<uint32_t>(sfc::kPiece, size - (j - po[l]) * sfc::kPiece);
+      const uint32_t win = (uint32_t)(pr[j].ehi - pr[j].elo + 1);
+      if (win > I.max_window) I.max_window = win;
+      wsum += (double)keys_j * win;
+      ssum += (double)keys_j * (piece_steps + std::ceil(std::log2((double)win + 1.0)));
+    }
   }
   I.mean_window = h->n ? wsum / (double)h->n : 0.0;
+  I.search_steps = h->n ? ssum / (double)h->n : 0.0;
+  return hipSuccess;
+}
+
+// The model buffer holds the arrays for at least n keys; a larger buffer
+// keeps the router's tabulation (its first part).
+sfc_status ensure_lmodel(sfc_index* h, uint64_t n) {
+  if (h->lmodel && h->lmodel_n >= n) return SFC_OK;
+  const uint64_t cap = n + n / 4;
+  void* buf = h->alloc.get(sfc::learned_model_bytes(cap));
+  if (!buf) return SFC_ERR_NOMEM;
+  sfc::LearnedArrays a = sfc::learned_carve(buf, cap);
+  if (h->lmodel) {
+    hipError_t e = hipMemcpyAsync(a.xb, h->larr.xb, (sfc::kLeaves + 1) * 4,
+                                  hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(a.rt, h->larr.rt, (sfc::kRouteSlots + 1) * 4, hipMemcpyDeviceToDevice,
+                         h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      h->alloc.put(buf);
+      return from_hip(e);
+    }
+    h->alloc.put(h->lmodel);
+  }
+  h->lmodel = buf;
+  h->lmodel_n = cap;
+  h->larr = a;
+  return SFC_OK;
 }
 
 sfc_status fit_learned(sfc_index* h, int steps) {
   if (h->n < 2) return SFC_ERR_UNSUPPORTED;
   if (steps < 0) steps = h->learn_steps;
   if (!h->lparams) h->lparams = (float*)h->alloc.get(sfc::kParams * sizeof(float));
-  if (!h->lleaves) h->lleaves = (sfc::LeafRec*)h->alloc.get(sfc::kLeaves * sizeof(sfc::LeafRec));
+  if (!h->lparams) return SFC_ERR_NOMEM;
+  sfc_status st = ensure_lmodel(h, h->n);
+  if (st != SFC_OK) return st;
   void* scratch = h->alloc.get(sfc::learned_scratch_bytes());
-  if (!h->lparams || !h->lleaves || !scratch) {
-    h->alloc.put(scratch);
-    return SFC_ERR_NOMEM;
-  }
+  if (!scratch) return SFC_ERR_NOMEM;
   float* losses = (float*)((char*)scratch + sfc::learned_scratch_bytes() - 256);
-  hipError_t e = sfc::learned_fit(h->keys, h->n, (uint32_t)steps, 1e-3f, h->lparams, h->lleaves,
+  h->linfo.fitted = 0;
+  hipError_t e = sfc::learned_fit(h->keys, h->n, (uint32_t)steps, 1e-3f, h->lparams, h->larr,
                                   scratch, losses, h->stream);
-  std::vector<sfc::LeafRec> leaves(sfc::kLeaves);
   float lh[2] = {0.f, 0.f};
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(leaves.data(), h->lleaves, sfc::kLeaves * sizeof(sfc::LeafRec),
-                       hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(lh, losses, 8, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   h->alloc.put(scratch);
+  if (e == hipSuccess) e = leaf_stats(h);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return from_hip(e);
@@ -402,11 +460,10 @@ sfc_status fit_learned(sfc_index* h, int steps) {
   I.steps = (uint32_t)steps;
   I.loss_init = lh[0];
   I.loss_final = lh[1];
-  leaf_stats(h, leaves);
   return SFC_OK;
 }
 
-// Refits the leaves of a fitted learned index after the keys changed (the
+// Refits the pieces of a fitted learned index after the keys changed (the
 // router is kept); with fewer than two keys the index falls back to binary
 // search until the next fit.
 sfc_status refit_leaves(sfc_index* h) {
@@ -415,22 +472,18 @@ sfc_status refit_leaves(sfc_index* h) {
     h->linfo.fitted = 0;
     return SFC_OK;
   }
-  void* scratch = h->alloc.get(sfc::learned_scratch_bytes());
-  if (!scratch) return SFC_ERR_NOMEM;
-  std::vector<sfc::LeafRec> leaves(sfc::kLeaves);
-  hipError_t e = sfc::learned_refit_leaves(h->keys, h->n, h->lparams, h->lleaves, scratch,
-                                           h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(leaves.data(), h->lleaves, sfc::kLeaves * sizeof(sfc::LeafRec),
-                       hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  h->alloc.put(scratch);
+  sfc_status st = ensure_lmodel(h, h->n);
+  if (st != SFC_OK) {
+    h->linfo.fitted = 0;
+    return st;
+  }
+  hipError_t e = sfc::learned_refit_leaves(h->keys, h->n, h->larr, h->stream);
+  if (e == hipSuccess) e = leaf_stats(h);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     h->linfo.fitted = 0;
     return from_hip(e);
   }
-  leaf_stats(h, leaves);
   return SFC_OK;
 }
 
@@ -732,13 +785,24 @@ sfc_status sfc_debug_chunk_tiles(uint64_t tiles) {
 sfc_status sfc_learned_shrink_windows(sfc_index* h) {
   if (!h) return SFC_ERR_INVALID;
   if (!h->linfo.fitted) return SFC_ERR_UNSUPPORTED;
-  std::vector<sfc::LeafRec> leaves(sfc::kLeaves);
-  SFC_TRY(hipMemcpyAsync(leaves.data(), h->lleaves, sfc::kLeaves * sizeof(sfc::LeafRec),
+  const uint32_t np = h->linfo.pieces;
+  std::vector<sfc::PieceRec> pr(np);
+  if (np == 0) return SFC_OK;
+  SFC_TRY(hipMemcpyAsync(pr.data(), h->larr.pr, np * sizeof(sfc::PieceRec),
                          hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
-  for (sfc::LeafRec& L : leaves) L.elo = L.ehi = 0;
-  SFC_TRY(hipMemcpyAsync(h->lleaves, leaves.data(), sfc::kLeaves * sizeof(sfc::LeafRec),
+  for (sfc::PieceRec& r : pr) r.elo = r.ehi = 0;
+  SFC_TRY(hipMemcpyAsync(h->larr.pr, pr.data(), np * sizeof(sfc::PieceRec),
                          hipMemcpyHostToDevice, h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  return SFC_OK;
+}
+
+sfc_status sfc_learned_route(sfc_index* h, const uint64_t* keys, uint64_t count,
+                             uint32_t* direct, uint32_t* table) {
+  if (!h || (count > 0 && (!keys || !direct || !table))) return SFC_ERR_INVALID;
+  if (!h->linfo.fitted) return SFC_ERR_UNSUPPORTED;
+  SFC_TRY(sfc::learned_route_both(h->lparams, h->larr, keys, count, direct, table, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
   return SFC_OK;
 }
@@ -892,12 +956,12 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   }
   sfc::query_scratch_carve(g->scratch, m, &g->qs);
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
+  const sfc::LearnedView lv = h->larr.view();
   sfc::EpochView ev;
   const bool filtered = epoch_view(h, nullptr, &ev);
   sfc_status st = graph_capture(g, [&](hipStream_t s) {
     hipError_t e = sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                                      h->refine_min, learned ? h->lparams : nullptr,
-                                      learned ? h->lleaves : nullptr, qset,
+                                      h->refine_min, learned ? &lv : nullptr, qset,
                                       qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr,
                                       nullptr, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess)

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "learned.h"
+
 namespace sfc {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -61,13 +63,12 @@ size_t compact_scratch_bytes(uint64_t total_rows);
 
 // Ranges and searches per query slot, then the scan of candidate counts into
 // segment offsets; optionally records the ranges (dbg_* may be null).
-struct LeafRec;
-// lparams/leaves non-null: searches go through the learned index.
+// lview non-null: searches go through the learned index.
 // qset/set_off non-null: query j searches only set qset[j] (positions
 // [set_off[s], set_off[s+1]) of the sorted arrays).
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min,
-                         const float* lparams, const LeafRec* leaves, const uint32_t* qset,
+                         const LearnedView* lview, const uint32_t* qset,
                          const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s);
@@ -129,14 +130,23 @@ hipError_t validate_epochs(const uint32_t* qe, uint64_t m, uint32_t oldest, uint
 
 // ---- learned index (learned.hip) ----
 size_t learned_scratch_bytes();
+// Device arrays of a learned index sized for n keys (learned_model_bytes(n)
+// bytes, carved by learned_carve).
+size_t learned_model_bytes(uint64_t n);
+uint32_t learned_max_pieces(uint64_t n);
+LearnedArrays learned_carve(void* base, uint64_t n);
 // Trains the router (steps Adam steps, 0 = quantile initialisation only) on
-// samples of the sorted keys, then fits the leaves.  params: kParams floats,
-// leaves: kLeaves records, losses: 2 floats (sample loss before / after).
+// samples of the sorted keys, tabulates it, then fits the leaves' pieces.
+// params: kParams floats; losses: 2 floats (sample loss before / after).
 hipError_t learned_fit(const uint64_t* keys, uint64_t n, uint32_t steps, float lr, float* params,
-                       LeafRec* leaves, void* scratch, float* losses, hipStream_t s);
-// Refits the leaves for changed keys with the router kept (after an update).
-hipError_t learned_refit_leaves(const uint64_t* keys, uint64_t n, const float* params,
-                                LeafRec* leaves, void* scratch, hipStream_t s);
+                       const LearnedArrays& a, void* scratch, float* losses, hipStream_t s);
+// Refits the leaves' pieces for changed keys with the router kept (after an
+// update); a must have been carved for at least n keys.
+hipError_t learned_refit_leaves(const uint64_t* keys, uint64_t n, const LearnedArrays& a,
+                                hipStream_t s);
+// Leaf of each key by evaluating the router and through its tabulation.
+hipError_t learned_route_both(const float* params, const LearnedArrays& a, const uint64_t* keys,
+                              uint64_t count, uint32_t* direct, uint32_t* table, hipStream_t s);
 // Gradient of one batch (cnt <= 128 samples) with the trainer's own code.
 hipError_t learned_grad(const float* params, const float* xs, const float* ts, int cnt,
                         float* grad, float* loss, hipStream_t s);

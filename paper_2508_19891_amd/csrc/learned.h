@@ -1,8 +1,24 @@
-// Learned index over the sorted keys: a monotone router network picks one of
-// kLeaves linear leaves, the leaf predicts the rank of a key, and an exact
-// per-leaf error window plus a last-mile binary search gives the lower bound.
-// A verification of the result falls back to a full binary search, so the
-// answer always equals std::lower_bound over the keys.
+// Learned index over the sorted keys.  A monotone router network maps a
+// key's top bits to one of kLeaves leaves; a leaf holds a contiguous run
+// keys[S..E) and is cut into pieces of kPiece keys; a piece predicts a rank
+// by linear interpolation from its first key towards the next piece's, with
+// the exact window of (lower bound - prediction) stored per piece, and a
+// last-mile binary search in that window gives the lower bound.  A check of
+// the result falls back to a full binary search, so the answer always equals
+// std::lower_bound over the keys.
+//
+// The router is evaluated in two equivalent ways.  Training and the fit
+// evaluate the network itself.  Queries read its tabulation: the router is
+// monotone in its 24-bit input X, so leaf(X) is a step function, fully
+// described by the first input of every leaf (xb); a table over the top 16
+// bits of X brackets the leaf and a short search in xb finds it.  Both give
+// the same leaf for every X (the table is built from the same device
+// function).
+//
+// On the GPU the cost of a lower bound is its chain of dependent loads, so
+// the searches below end in a scan of at most 16 sorted entries whose loads
+// are independent of each other: a binary search over a few hundred keys
+// takes about eight dependent probes, the scan one round trip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,17 +40,42 @@ constexpr int kOffW3 = kOffB2 + kHidden;
 constexpr int kOffB3 = kOffW3 + kHidden;
 constexpr int kParams = kOffB3 + 1;   // 1153
 
-struct LeafRec {
-  uint64_t base;   // smallest key of the leaf (0 for an empty leaf)
-  double a, b;     // rank ~ a + b * (key - base)
-  uint32_t S, E;   // the leaf's keys are keys[S..E)
-  int32_t elo, ehi;   // lower bound - prediction lies in [elo, ehi]
+constexpr uint32_t kPiece = 256;      // keys per piece (the last piece of a leaf may be shorter)
+constexpr int kXBits = 24;            // router input: the top 24 key bits
+constexpr int kRouteBits = 16;        // leaf bracket table over the top 16 input bits
+constexpr uint32_t kRouteSlots = 1u << kRouteBits;
+
+struct PieceRec {
+  double s;          // ranks per key unit from the piece's first key
+  int32_t elo, ehi;  // lower bound - prediction lies in [elo, ehi]
+};
+
+// Device view of a fitted learned index (all arrays in device memory).
+struct LearnedView {
+  const uint32_t* xb;   // kLeaves + 1: first router input X of each leaf (xb[kLeaves] = 2^24)
+  const uint32_t* rt;   // kRouteSlots + 1: leaf of X = min(t << 8, 2^24 - 1)
+  const uint2* lp;      // kLeaves + 1: (first key index, first piece) of each leaf;
+                        // lp[kLeaves] = (n, number of pieces)
+  const uint64_t* fk;   // first key of each piece
+  const PieceRec* pr;   // model and window of each piece
+};
+
+// The same arrays, writable, as the fit carves them from one allocation.
+struct LearnedArrays {
+  uint32_t* xb = nullptr;
+  uint32_t* rt = nullptr;
+  uint2* lp = nullptr;
+  uint64_t* fk = nullptr;
+  PieceRec* pr = nullptr;
+  uint32_t max_pieces = 0;
+  __host__ __device__ LearnedView view() const { return LearnedView{xb, rt, lp, fk, pr}; }
 };
 
 // Router input: the top 24 bits of the key as a float in [0, 1) (exact, so
 // the map key -> x is monotone).
+__device__ __forceinline__ float router_input_x(uint32_t X) { return (float)X * 0x1p-24f; }
 __device__ __forceinline__ float router_input(uint64_t key) {
-  return (float)(uint32_t)(key >> 40) * 0x1p-24f;
+  return router_input_x((uint32_t)(key >> 40));
 }
 
 // The network's output for input x: clip-ramp units, fused multiply-adds in
@@ -56,20 +97,24 @@ __device__ __forceinline__ float router_output(const float* __restrict__ P, floa
   return y;
 }
 
-__device__ __forceinline__ uint32_t router_leaf(const float* __restrict__ P, uint64_t key) {
-  const float y = router_output(P, router_input(key));
+// Leaf of router input X (0 <= X < 2^24), by evaluating the network.
+__device__ __forceinline__ uint32_t router_leaf_x(const float* __restrict__ P, uint32_t X) {
+  const float y = router_output(P, router_input_x(X));
   float f = floorf(y * (float)kLeaves);
   f = fminf(fmaxf(f, 0.f), (float)(kLeaves - 1));
   return (uint32_t)f;
 }
 
-// The leaf's rank prediction, rounded to nearest and clamped to [S, E].
-__device__ __forceinline__ int64_t leaf_predict(const LeafRec& L, uint64_t key) {
-#pragma clang fp contract(off)
-  const double u = key >= L.base ? (double)(key - L.base) : -(double)(L.base - key);
-  double p = floor(L.a + L.b * u + 0.5);
-  p = fmin(fmax(p, (double)L.S), (double)L.E);
-  return (int64_t)p;
+// Leaf of router input X through the tabulation (equal to router_leaf_x).
+__device__ __forceinline__ uint32_t route(const LearnedView& v, uint32_t X) {
+  const uint32_t t = X >> (kXBits - kRouteBits);
+  uint32_t lo = v.rt[t], hi = v.rt[t + 1];   // leaf(X) in [lo, hi]
+  while (lo < hi) {                          // largest l in [lo, hi] with xb[l] <= X
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (v.xb[mid] <= X) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // First index i in [lo, hi) with keys[i] >= k, hi if none.
@@ -88,26 +133,206 @@ __device__ __forceinline__ uint64_t lower_bound_in(const uint64_t* __restrict__ 
   return lo;
 }
 
+// The same result: binary steps down to at most 16 entries, then one scan
+// that counts the entries < k (loads clamped into the range, all issued
+// before the compares).
+__device__ __forceinline__ uint64_t lower_bound_scan(const uint64_t* __restrict__ a, uint64_t lo,
+                                                     uint64_t hi, uint64_t k) {
+  uint64_t len = hi - lo;
+  while (len > 16) {
+    const uint64_t h = len >> 1;
+    if (a[lo + h] < k) {
+      lo += h + 1;
+      len -= h + 1;
+    } else {
+      len = h;
+    }
+  }
+  if (len == 0) return lo;
+  uint64_t v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = a[lo + ((uint64_t)i < len ? (uint64_t)i : len - 1)];
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) c += ((uint64_t)i < len && v[i] < k) ? 1u : 0u;
+  return lo + c;
+}
+
+// The piece's rank prediction for a key k > fk: R + round(s * (k - fk)),
+// clamped to [R + 1, Rn] (the bracket the lower bound lies in).
+__device__ __forceinline__ int64_t piece_predict(double s, uint64_t fk, uint64_t R, uint64_t Rn,
+                                                 uint64_t k) {
+#pragma clang fp contract(off)
+  const double u = (double)(k - fk);
+  double p = (double)R + floor(s * u + 0.5);
+  p = fmin(fmax(p, (double)(R + 1)), (double)Rn);
+  return (int64_t)p;
+}
+
 // Lower bound of k through the learned index; *fell_back is set when the
-// verification failed and the full binary search answered.
+// check of the result failed and the full binary search answered.
 __device__ __forceinline__ uint64_t learned_lower_bound(const uint64_t* __restrict__ keys,
-                                                       uint64_t n, const float* __restrict__ P,
-                                                       const LeafRec* __restrict__ leaves,
+                                                       uint64_t n, const LearnedView& v,
                                                        uint64_t k, bool* fell_back) {
-  const LeafRec L = leaves[router_leaf(P, k)];
-  const int64_t p = leaf_predict(L, k);
-  int64_t wlo = p + L.elo, whi = p + L.ehi;
-  wlo = wlo < (int64_t)L.S ? (int64_t)L.S : wlo;
-  whi = whi > (int64_t)L.E ? (int64_t)L.E : whi;
-  // The leaves describe the keys they were fitted on; the clamp to [0, n]
-  // keeps every probe inside the array should they ever be stale.
-  whi = whi > (int64_t)n ? (int64_t)n : whi;
-  wlo = wlo > whi ? whi : wlo;
-  if (whi < wlo) whi = wlo;
-  const uint64_t r = lower_bound_in(keys, (uint64_t)wlo, (uint64_t)whi, k);
+  // Keys of lower leaves are < k and keys of higher leaves > k (monotone
+  // routing), so the lower bound lies in [S, E].
+  const uint32_t l = route(v, (uint32_t)(k >> 40));
+  const uint2 a = v.lp[l], b = v.lp[l + 1];
+  uint64_t S = a.x, E = b.x;
+  E = E > n ? n : E;   // keeps every probe inside the array should the fit be stale
+  S = S > E ? E : S;
+  uint64_t r = S;
+  if (E > S) {
+    // The last piece whose first key is < k brackets the lower bound in
+    // (R, Rn]; no such piece means keys[S] >= k, so the bound is S.
+    const uint32_t p0 = a.y, p1 = b.y > a.y ? b.y : a.y;
+    const uint32_t c = (uint32_t)lower_bound_scan(v.fk, p0, p1, k);
+    if (c > p0) {
+      const uint32_t j = c - 1;
+      uint64_t R = S + (uint64_t)(j - p0) * kPiece;
+      R = R < E ? R : E - 1;
+      const uint64_t Rn = R + kPiece < E ? R + kPiece : E;
+      const PieceRec pc = v.pr[j];
+      const int64_t p = piece_predict(pc.s, v.fk[j], R, Rn, k);
+      int64_t wlo = p + pc.elo, whi = p + pc.ehi;
+      wlo = wlo < (int64_t)(R + 1) ? (int64_t)(R + 1) : wlo;
+      whi = whi > (int64_t)Rn ? (int64_t)Rn : whi;
+      if (whi < wlo) whi = wlo;
+      r = lower_bound_scan(keys, (uint64_t)wlo, (uint64_t)whi, k);
+    }
+  }
   const bool ok = (r == 0 || keys[r - 1] < k) && (r == n || keys[r] >= k);
   *fell_back = !ok;
   return ok ? r : lower_bound_in(keys, 0, n, k);
+}
+
+// ---- two lower bounds in lockstep ------------------------------------------
+// A range [klo, khi] needs two lower bounds; walking both chains step by step
+// keeps two independent loads in flight at every step (as the interleaved
+// binary searches of the plain path do), which halves the dependent latency.
+
+constexpr int kScan2 = 8;   // entries scanned at the end of each search
+
+// Lower bounds of k[i] in [lo[i], hi[i]) of the sorted array a, for i = 0, 1.
+__device__ __forceinline__ void lower_bound_scan_pair(const uint64_t* __restrict__ a,
+                                                      uint64_t lo[2], const uint64_t hi[2],
+                                                      const uint64_t k[2]) {
+  uint64_t len[2] = {hi[0] - lo[0], hi[1] - lo[1]};
+  while (len[0] > (uint64_t)kScan2 || len[1] > (uint64_t)kScan2) {
+    uint64_t x[2] = {0, 0}, h[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      h[i] = len[i] >> 1;
+      if (len[i] > (uint64_t)kScan2) x[i] = a[lo[i] + h[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (len[i] > (uint64_t)kScan2) {
+        if (x[i] < k[i]) {
+          lo[i] += h[i] + 1;
+          len[i] -= h[i] + 1;
+        } else {
+          len[i] = h[i];
+        }
+      }
+    }
+  }
+  uint64_t v[2][kScan2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int t = 0; t < kScan2; ++t)
+      v[i][t] = len[i] ? a[lo[i] + ((uint64_t)t < len[i] ? (uint64_t)t : len[i] - 1)] : 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int t = 0; t < kScan2; ++t) c += ((uint64_t)t < len[i] && v[i][t] < k[i]) ? 1u : 0u;
+    lo[i] += c;
+  }
+}
+
+// r[i] = lower bound of k[i] over keys[0, n) for i = 0, 1 (the same result as
+// learned_lower_bound); returns the number of checks that fell back.
+__device__ __forceinline__ uint32_t learned_lower_bound_pair(const uint64_t* __restrict__ keys,
+                                                            uint64_t n, const LearnedView& v,
+                                                            const uint64_t k[2], uint64_t r[2]) {
+  // Route: bracket from the table, then the short search in xb.
+  uint32_t X[2], lo[2], hi[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    X[i] = (uint32_t)(k[i] >> 40);
+    const uint32_t t = X[i] >> (kXBits - kRouteBits);
+    lo[i] = v.rt[t];
+    hi[i] = v.rt[t + 1];
+  }
+  while (lo[0] < hi[0] || lo[1] < hi[1]) {
+    uint32_t mid[2], x[2] = {0, 0};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      mid[i] = (lo[i] + hi[i] + 1) >> 1;
+      if (lo[i] < hi[i]) x[i] = v.xb[mid[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (lo[i] < hi[i]) {
+        if (x[i] <= X[i]) lo[i] = mid[i];
+        else hi[i] = mid[i] - 1;
+      }
+    }
+  }
+  // Leaves and their piece ranges.
+  uint64_t S[2], E[2], plo[2], phi[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const uint2 a = v.lp[lo[i]], b = v.lp[lo[i] + 1];
+    E[i] = b.x > n ? n : b.x;
+    S[i] = a.x > E[i] ? E[i] : a.x;
+    plo[i] = a.y;
+    phi[i] = E[i] > S[i] ? (b.y > a.y ? b.y : a.y) : a.y;   // no pieces for an empty leaf
+  }
+  const uint64_t p0[2] = {plo[0], plo[1]};
+  lower_bound_scan_pair(v.fk, plo, phi, k);
+  // The bracketing piece, its prediction and window.
+  uint64_t wlo[2], whi[2];
+  bool searched[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    searched[i] = plo[i] > p0[i];
+    wlo[i] = whi[i] = S[i];
+    if (searched[i]) {
+      const uint64_t j = plo[i] - 1;
+      uint64_t R = S[i] + (j - p0[i]) * kPiece;
+      R = R < E[i] ? R : E[i] - 1;
+      const uint64_t Rn = R + kPiece < E[i] ? R + kPiece : E[i];
+      const PieceRec pc = v.pr[j];
+      const int64_t p = piece_predict(pc.s, v.fk[j], R, Rn, k[i]);
+      int64_t a = p + pc.elo, b = p + pc.ehi;
+      a = a < (int64_t)(R + 1) ? (int64_t)(R + 1) : a;
+      b = b > (int64_t)Rn ? (int64_t)Rn : b;
+      if (b < a) b = a;
+      wlo[i] = (uint64_t)a;
+      whi[i] = (uint64_t)b;
+    }
+  }
+  lower_bound_scan_pair(keys, wlo, whi, k);
+  uint32_t fb = 0;
+  uint64_t below[2], at[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    r[i] = wlo[i];
+    below[i] = r[i] > 0 ? keys[r[i] - 1] : 0;
+    at[i] = r[i] < n ? keys[r[i]] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const bool ok = (r[i] == 0 || below[i] < k[i]) && (r[i] == n || at[i] >= k[i]);
+    if (!ok) {
+      r[i] = lower_bound_in(keys, 0, n, k[i]);
+      ++fb;
+    }
+  }
+  return fb;
 }
 
 }  // namespace sfc

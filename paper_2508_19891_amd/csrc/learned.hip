@@ -7,12 +7,16 @@
 //                    samples (forward and backward written out below), with
 //                    w1, W2, w3 projected onto >= 0 after every step so that
 //                    the router stays monotone.
-//   learned_bounds   first key index of every leaf: a binary search per leaf
-//                    over the sorted keys, valid because routing is monotone.
-//   learned_leaves   one workgroup per leaf: least-squares line of rank on
-//                    key - base (FP64, centred, fixed reduction order), then
+//   learned_xbounds  tabulation of the trained router: the first input X of
+//   learned_radix    every leaf (a binary search over X per leaf, valid
+//                    because routing is monotone) and the leaf at every
+//                    2^8-th input.
+//   learned_keybounds first key index of every leaf.
+//   learned_piece_offsets  pieces per leaf (ceil(size / kPiece)) and their
+//                    exclusive scan (one workgroup).
+//   learned_pieces   one wave per piece: first key, interpolation slope and
 //                    the exact window of (lower bound - prediction) over every
-//                    query key the leaf can receive.
+//                    query key the piece can receive.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -255,160 +259,204 @@ __global__ __launch_bounds__(kTrainThreads) void learned_train(const float* __re
   }
 }
 
-// bounds[l] = first index whose key routes to a leaf >= l (bounds[kLeaves] = n).
-__global__ __launch_bounds__(256) void learned_bounds(const uint64_t* __restrict__ keys, uint64_t n,
-                                                      const float* __restrict__ P,
-                                                      uint32_t* __restrict__ bounds) {
+__global__ __launch_bounds__(256) void learned_xbounds(const float* __restrict__ P,
+                                                       uint32_t* __restrict__ xb) {
   const uint32_t l = blockIdx.x * 256 + threadIdx.x;
   if (l > (uint32_t)kLeaves) return;
-  if (l == (uint32_t)kLeaves) {
-    bounds[l] = (uint32_t)n;
+  if (l == 0 || l == (uint32_t)kLeaves) {
+    xb[l] = l == 0 ? 0u : (1u << kXBits);
     return;
   }
-  uint64_t lo = 0, len = n;
+  uint32_t lo = 0, len = 1u << kXBits;   // first X with leaf(X) >= l, 2^24 if none
   while (len > 0) {
-    const uint64_t h = len >> 1;
-    if (router_leaf(P, keys[lo + h]) < l) {
+    const uint32_t h = len >> 1;
+    if (router_leaf_x(P, lo + h) < l) {
       lo += h + 1;
       len -= h + 1;
     } else {
       len = h;
     }
   }
-  bounds[l] = (uint32_t)lo;
+  xb[l] = lo;
 }
 
-__device__ __forceinline__ double block_sum_f64(double v, double* s) {
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-    __syncthreads();
-  }
-  const double r = s[0];
-  __syncthreads();
-  return r;
+__global__ __launch_bounds__(256) void learned_radix(const float* __restrict__ P,
+                                                     uint32_t* __restrict__ rt) {
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t > kRouteSlots) return;
+  const uint32_t X = t < kRouteSlots ? t << (kXBits - kRouteBits) : (1u << kXBits) - 1;
+  rt[t] = router_leaf_x(P, X);
 }
 
-__device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* s) {
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) s[threadIdx.x] = min(s[threadIdx.x], s[threadIdx.x + o]);
-    __syncthreads();
-  }
-  const int64_t r = s[0];
-  __syncthreads();
-  return r;
+// lp[l].x = first index whose key routes to a leaf >= l: keys route by their
+// top 24 bits, so that is the lower bound of xb[l] << 40 (lp[kLeaves].x = n).
+__global__ __launch_bounds__(256) void learned_keybounds(const uint64_t* __restrict__ keys,
+                                                         uint64_t n,
+                                                         const uint32_t* __restrict__ xb,
+                                                         uint2* __restrict__ lp) {
+  const uint32_t l = blockIdx.x * 256 + threadIdx.x;
+  if (l > (uint32_t)kLeaves) return;
+  const uint32_t X = xb[l];
+  lp[l].x = (l == (uint32_t)kLeaves || X >= (1u << kXBits))
+                ? (uint32_t)n
+                : (uint32_t)lower_bound_in(keys, 0, n, (uint64_t)X << (64 - kXBits));
 }
 
-__device__ __forceinline__ int64_t block_max_i64(int64_t v, int64_t* s) {
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + o]);
-    __syncthreads();
-  }
-  const int64_t r = s[0];
-  __syncthreads();
-  return r;
-}
-
-// One workgroup per leaf l: keys[S..E).
-__global__ __launch_bounds__(256) void learned_leaves(const uint64_t* __restrict__ keys, uint64_t n,
-                                                      const uint32_t* __restrict__ bounds,
-                                                      LeafRec* __restrict__ leaves) {
-#pragma clang fp contract(off)
-  __shared__ double s_d[256];
-  __shared__ int64_t s_i[256];
-  __shared__ LeafRec s_leaf;
-  const uint32_t l = blockIdx.x;
-  const uint64_t S = bounds[l], E = bounds[l + 1];
+// lp[l].y = first piece of leaf l (lp[kLeaves].y = number of pieces); one block.
+__global__ __launch_bounds__(256) void learned_piece_offsets(uint2* __restrict__ lp) {
+  constexpr int kPer = kLeaves / 256;
+  __shared__ uint32_t s_w[4];
   const uint32_t tid = threadIdx.x;
-  if (E <= S) {
-    if (tid == 0) {
-      LeafRec r;
-      r.base = 0;
-      r.a = (double)S;
-      r.b = 0.0;
-      r.S = (uint32_t)S;
-      r.E = (uint32_t)S;
-      r.elo = 0;
-      r.ehi = 0;
-      leaves[l] = r;
-    }
-    return;
+  uint32_t c[kPer], sum = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const uint32_t l = tid * kPer + i;
+    const uint32_t S = lp[l].x, E = lp[l + 1].x;
+    const uint32_t size = E > S ? E - S : 0u;
+    c[i] = (size + kPiece - 1) / kPiece;
+    sum += c[i];
   }
-  const uint64_t base = keys[S];
-  const double cnt = (double)(E - S);
-  // Centred least squares of r = i - S on u = key - base.
-  double su = 0.0, sr = 0.0;
-  for (uint64_t i = S + tid; i < E; i += 256) {
-    su += (double)(keys[i] - base);
-    sr += (double)(i - S);
+  uint32_t x = sum;   // inclusive scan over the wave
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if ((tid & 63) >= (uint32_t)o) x += y;
   }
-  const double mu = block_sum_f64(su, s_d) / cnt;
-  const double mr = block_sum_f64(sr, s_d) / cnt;
-  double cuv = 0.0, cuu = 0.0;
-  for (uint64_t i = S + tid; i < E; i += 256) {
-    const double du = (double)(keys[i] - base) - mu;
-    const double dr = (double)(i - S) - mr;
-    cuv += du * dr;
-    cuu += du * du;
-  }
-  const double Cuv = block_sum_f64(cuv, s_d);
-  const double Cuu = block_sum_f64(cuu, s_d);
-  const double b = Cuu > 0.0 ? Cuv / Cuu : 0.0;
-  const double a = (double)S + mr - b * mu;
-  if (tid == 0) {
-    s_leaf.base = base;
-    s_leaf.a = a;
-    s_leaf.b = b;
-    s_leaf.S = (uint32_t)S;
-    s_leaf.E = (uint32_t)E;
-    s_leaf.elo = 0;
-    s_leaf.ehi = 0;
-  }
+  if ((tid & 63) == 63) s_w[tid >> 6] = x;
   __syncthreads();
-  const LeafRec L = s_leaf;
-  // Window: a query key k routed here has its lower bound LB in [S, E].  For
-  // k in (keys[i-1], keys[i]] with i the first index of its key, LB = i and
-  // the prediction lies between pred(keys[i-1] + 1) and pred(keys[i]); for k
-  // above the leaf's last key, LB = E and the prediction lies between
-  // pred(last + 1) and E.
-  int64_t lo = 0, hi = 0;
-  for (uint64_t i = S + tid; i < E; i += 256) {
-    const uint64_t k = keys[i];
-    if (i > 0 && keys[i - 1] == k) continue;
+  uint32_t run = x - sum;
+  for (uint32_t w = 0; w < (tid >> 6); ++w) run += s_w[w];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    lp[tid * kPer + i].y = run;
+    run += c[i];
+  }
+  if (tid == 255) lp[kLeaves].y = run;
+}
+
+// One wave per piece j of leaf l: keys[R..Rn), R = lb[l] + (j - po[l]) * kPiece.
+// A query key k picks the last piece of its leaf with first key < k, so the
+// piece receives k in (keys[R], kmax] (kmax: the next piece's first key, or
+// the largest key routed to the leaf), and the lower bound lies in (R, Rn].
+// For i in (R, Rn) the keys in (keys[i-1], keys[i]] have lower bound i (when
+// keys[i-1] < keys[i]); the keys in (keys[Rn-1], kmax] have lower bound Rn.
+// The prediction is monotone in k, so each interval's extremes of
+// (bound - prediction) are at its ends.
+__global__ __launch_bounds__(256) void learned_pieces(const uint64_t* __restrict__ keys,
+                                                      uint64_t n, const uint32_t* __restrict__ xb,
+                                                      const uint2* __restrict__ lp,
+                                                      uint32_t max_pieces,
+                                                      uint64_t* __restrict__ fk,
+                                                      PieceRec* __restrict__ pr) {
+#pragma clang fp contract(off)
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t np = lp[kLeaves].y;
+  if (j >= np || j >= max_pieces) return;
+  uint32_t lo = 0, hi = kLeaves - 1;   // leaf: largest l with first piece <= j
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (lp[mid].y <= j) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint32_t l = lo;
+  const uint64_t S = lp[l].x, E = lp[l + 1].x < n ? lp[l + 1].x : n;
+  const uint64_t R = S + (uint64_t)(j - lp[l].y) * kPiece;
+  if (R >= E) return;   // never: pieces cover exactly their leaf
+  const uint64_t Rn = R + kPiece < E ? R + kPiece : E;
+  const bool last = j + 1 >= lp[l + 1].y;
+  const uint64_t f = keys[R];
+  uint64_t kmax;
+  double span;
+  if (!last) {
+    kmax = keys[Rn];
+    span = (double)(kmax - f);
+  } else {
+    kmax = xb[l + 1] >= (1u << kXBits) ? ~0ull : ((uint64_t)xb[l + 1] << (64 - kXBits)) - 1;
+    span = (double)(keys[E - 1] - f) + 1.0;
+  }
+  const double sl = span > 0.0 ? (double)(Rn - R) / span : 0.0;
+  int64_t emin = INT64_MAX, emax = INT64_MIN;
+  for (uint64_t i = R + 1 + lane; i <= Rn; i += 64) {
+    uint64_t klo, khi;   // keys with lower bound i: (klo - 1, khi]
+    if (i < Rn) {
+      if (keys[i - 1] == keys[i]) continue;
+      klo = keys[i - 1] + 1;
+      khi = keys[i];
+    } else {
+      if (keys[Rn - 1] >= kmax) continue;
+      klo = keys[Rn - 1] + 1;
+      khi = kmax;
+    }
     const int64_t ii = (int64_t)i;
-    lo = min(lo, ii - leaf_predict(L, k));
-    const uint64_t kprev = i > 0 ? keys[i - 1] + 1 : 0;
-    hi = max(hi, ii - leaf_predict(L, kprev));
+    emin = min(emin, ii - piece_predict(sl, f, R, Rn, khi));
+    emax = max(emax, ii - piece_predict(sl, f, R, Rn, klo));
   }
-  if (tid == 0 && keys[E - 1] != ~0ull) hi = max(hi, (int64_t)E - leaf_predict(L, keys[E - 1] + 1));
-  const int64_t elo = block_min_i64(lo, s_i);
-  const int64_t ehi = block_max_i64(hi, s_i);
-  if (tid == 0) {
-    LeafRec r = L;
-    r.elo = (int32_t)elo;
-    r.ehi = (int32_t)ehi;
-    leaves[l] = r;
+  for (int o = 32; o > 0; o >>= 1) {
+    emin = min(emin, (int64_t)__shfl_xor(emin, o, 64));
+    emax = max(emax, (int64_t)__shfl_xor(emax, o, 64));
   }
+  if (lane == 0) {
+    PieceRec rec;
+    rec.s = sl;
+    rec.elo = emin > emax ? 0 : (int32_t)emin;
+    rec.ehi = emin > emax ? 0 : (int32_t)emax;
+    fk[j] = f;
+    pr[j] = rec;
+  }
+}
+
+hipError_t fit_pieces(const uint64_t* keys, uint64_t n, const LearnedArrays& a, uint32_t max_pieces,
+                      hipStream_t s) {
+  hipError_t e;
+  {
+    ProfScope ps("learned_bounds", s);
+    learned_keybounds<<<(kLeaves + 1 + 255) / 256, 256, 0, s>>>(keys, n, a.xb, a.lp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    learned_piece_offsets<<<1, 256, 0, s>>>(a.lp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    ProfScope ps("learned_pieces", s);
+    learned_pieces<<<(max_pieces + 3) / 4, 256, 0, s>>>(keys, n, a.xb, a.lp, max_pieces, a.fk,
+                                                        a.pr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
 
-size_t learned_scratch_bytes() { return align256(kSamples * 4) * 2 + align256((kLeaves + 1) * 4) + 256; }
+size_t learned_scratch_bytes() { return align256(kSamples * 4) * 2 + 256; }
+
+uint32_t learned_max_pieces(uint64_t n) { return (uint32_t)(n / kPiece + kLeaves + 1); }
+
+size_t learned_model_bytes(uint64_t n) {
+  const uint64_t np = learned_max_pieces(n);
+  return align256((kLeaves + 1) * 4) + align256((kRouteSlots + 1) * 4) +
+         align256((kLeaves + 1) * 8) + align256(np * 8) + align256(np * sizeof(PieceRec));
+}
+
+LearnedArrays learned_carve(void* base, uint64_t n) {
+  const uint64_t np = learned_max_pieces(n);
+  char* p = (char*)base;
+  LearnedArrays a;
+  a.xb = (uint32_t*)p;   p += align256((kLeaves + 1) * 4);
+  a.rt = (uint32_t*)p;   p += align256((kRouteSlots + 1) * 4);
+  a.lp = (uint2*)p;      p += align256((kLeaves + 1) * 8);
+  a.fk = (uint64_t*)p;   p += align256(np * 8);
+  a.pr = (PieceRec*)p;
+  a.max_pieces = (uint32_t)np;
+  return a;
+}
 
 hipError_t learned_fit(const uint64_t* keys, uint64_t n, uint32_t steps, float lr, float* params,
-                       LeafRec* leaves, void* scratch, float* losses, hipStream_t s) {
+                       const LearnedArrays& a, void* scratch, float* losses, hipStream_t s) {
   if (n == 0) return hipErrorInvalidValue;
   uint32_t S = kSamples;
   while ((uint64_t)S > n) S >>= 1;
   char* p = (char*)scratch;
   float* xs = (float*)p;          p += align256(kSamples * 4);
-  float* ts = (float*)p;          p += align256(kSamples * 4);
-  uint32_t* bounds = (uint32_t*)p;
+  float* ts = (float*)p;
   hipError_t e;
   {
     ProfScope ps("learned_sample", s);
@@ -421,42 +469,45 @@ hipError_t learned_fit(const uint64_t* keys, uint64_t n, uint32_t steps, float l
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   {
-    ProfScope ps("learned_bounds", s);
-    learned_bounds<<<(kLeaves + 1 + 255) / 256, 256, 0, s>>>(keys, n, params, bounds);
+    ProfScope ps("learned_tabulate", s);
+    learned_xbounds<<<(kLeaves + 1 + 255) / 256, 256, 0, s>>>(params, a.xb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    learned_radix<<<(kRouteSlots + 1 + 255) / 256, 256, 0, s>>>(params, a.rt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  {
-    ProfScope ps("learned_leaves", s);
-    learned_leaves<<<kLeaves, 256, 0, s>>>(keys, n, bounds, leaves);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return fit_pieces(keys, n, a, a.max_pieces, s);
 }
 
-hipError_t learned_refit_leaves(const uint64_t* keys, uint64_t n, const float* params,
-                                LeafRec* leaves, void* scratch, hipStream_t s) {
+hipError_t learned_refit_leaves(const uint64_t* keys, uint64_t n, const LearnedArrays& a,
+                                hipStream_t s) {
   if (n == 0) return hipErrorInvalidValue;
-  char* p = (char*)scratch;
-  p += 2 * align256(kSamples * 4);
-  uint32_t* bounds = (uint32_t*)p;
-  hipError_t e;
-  {
-    ProfScope ps("learned_bounds", s);
-    learned_bounds<<<(kLeaves + 1 + 255) / 256, 256, 0, s>>>(keys, n, params, bounds);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  {
-    ProfScope ps("learned_leaves", s);
-    learned_leaves<<<kLeaves, 256, 0, s>>>(keys, n, bounds, leaves);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return fit_pieces(keys, n, a, a.max_pieces, s);
 }
 
 hipError_t learned_grad(const float* params, const float* xs, const float* ts, int cnt,
                         float* grad, float* loss, hipStream_t s) {
   if (cnt < 1 || cnt > kBatch) return hipErrorInvalidValue;
   learned_grad_kernel<<<1, kTrainThreads, 0, s>>>(params, xs, ts, cnt, grad, loss);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void route_both_kernel(const float* __restrict__ P,
+                                                         LearnedView v,
+                                                         const uint64_t* __restrict__ keys,
+                                                         uint64_t count, uint32_t* __restrict__ direct,
+                                                         uint32_t* __restrict__ table) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t X = (uint32_t)(keys[i] >> (64 - kXBits));
+  direct[i] = router_leaf_x(P, X);
+  table[i] = route(v, X);
+}
+
+hipError_t learned_route_both(const float* params, const LearnedArrays& a, const uint64_t* keys,
+                              uint64_t count, uint32_t* direct, uint32_t* table, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  route_both_kernel<<<(uint32_t)((count + 255) / 256), 256, 0, s>>>(params, a.view(), keys, count,
+                                                                   direct, table);
   return hipGetLastError();
 }
 

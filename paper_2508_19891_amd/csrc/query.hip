@@ -214,17 +214,19 @@ __device__ __forceinline__ void search_within(const uint64_t* __restrict__ keys,
 // search, so the result is the same).  *fb counts the fallbacks.
 template <bool LEARNED>
 __device__ __forceinline__ void find_range(const uint64_t* __restrict__ keys, uint64_t n,
-                                           const float* __restrict__ P,
-                                           const LeafRec* __restrict__ leaves, uint64_t klo,
-                                           uint64_t khi, uint64_t& b, uint64_t& e, uint32_t& fb) {
+                                           const LearnedView& lv, uint64_t klo, uint64_t khi,
+                                           uint64_t& b, uint64_t& e, uint32_t& fb) {
   if (!LEARNED) {
     search_pair(keys, n, klo, khi, b, e);
     return;
   }
-  bool f0 = false, f1 = false;
-  b = learned_lower_bound(keys, n, P, leaves, klo, &f0);
-  e = khi == ~0ull ? n : learned_lower_bound(keys, n, P, leaves, khi + 1, &f1);
-  fb += (uint32_t)f0 + (uint32_t)f1;
+  // khi = 2^64 - 1 has no successor key: its bound is n, and the second
+  // chain then searches klo again (cheaper than a divergent branch).
+  const uint64_t k2[2] = {klo, khi == ~0ull ? klo : khi + 1};
+  uint64_t r2[2];
+  fb += learned_lower_bound_pair(keys, n, lv, k2, r2);
+  b = r2[0];
+  e = khi == ~0ull ? n : r2[1];
 }
 
 // One lane per (query, slot).
@@ -241,8 +243,8 @@ __device__ __forceinline__ void find_range(const uint64_t* __restrict__ keys, ui
 template <int CURVE, bool REFINE, bool LEARNED>
 __global__ __launch_bounds__(256) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
-    const uint64_t* __restrict__ keys, uint64_t n, const float* __restrict__ P,
-    const LeafRec* __restrict__ leaves, uint32_t refine_min, const uint32_t* __restrict__ qset,
+    const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, uint32_t refine_min,
+    const uint32_t* __restrict__ qset,
     const uint64_t* __restrict__ set_off, uint32_t n_sets, uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
     uint64_t* __restrict__ dbg_lo, uint64_t* __restrict__ dbg_hi, uint64_t* __restrict__ dbg_b,
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(256) void ranges_search(
       if (r < nr) {
         klo = lo[r];
         khi = hi[r];
-        find_range<LEARNED>(kseg, nn, P, leaves, klo, khi, b0, e0, fb);
+        find_range<LEARNED>(kseg, nn, lv, klo, khi, b0, e0, fb);
         b0 += base;
         e0 += base;
         ends += 2;
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(256) void ranges_search(
       int L = 0;
       nr = query_cells<CURVE>(lut, qq.x, qq.y, d, lo, hi, cx, cy, &L, box);
       if (r < nr) {
-        find_range<LEARNED>(kseg, nn, P, leaves, lo[r], hi[r], b0, e0, fb);
+        find_range<LEARNED>(kseg, nn, lv, lo[r], hi[r], b0, e0, fb);
         b0 += base;
         e0 += base;
         ends += 2;
@@ -343,20 +345,31 @@ __global__ __launch_bounds__(256) void ranges_search(
     }
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&counters[2], kErrInvalidQuery);
-  // Candidates (and learned-index endpoints and fallbacks) of the wave, for
-  // the statistics.
+  // Candidates (and learned-index endpoints and fallbacks) of the block, for
+  // the statistics: one device atomic per counter and block (atomics on one
+  // address from every wave of the grid serialise).
+  __shared__ unsigned long long s_stat[3][4];
   uint64_t wc = (e0 - b0) + (e1 - b1);
   uint32_t wf = fb, we = ends;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     wc += __shfl_xor(wc, o, 64);
-    wf += __shfl_xor(wf, o, 64);
-    we += __shfl_xor(we, o, 64);
+    if (LEARNED) {
+      wf += __shfl_xor(wf, o, 64);
+      we += __shfl_xor(we, o, 64);
+    }
   }
+  const uint32_t wv = threadIdx.x >> 6;
   if (lane_id() == 0) {
-    if (wc) atomicAdd(cand_total, (unsigned long long)wc);
-    if (LEARNED && we) atomicAdd(cand_total + 1, (unsigned long long)we);
-    if (LEARNED && wf) atomicAdd(cand_total + 2, (unsigned long long)wf);
+    s_stat[0][wv] = wc;
+    s_stat[1][wv] = we;
+    s_stat[2][wv] = wf;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3 && (threadIdx.x == 0 || LEARNED)) {
+    const unsigned long long t = s_stat[threadIdx.x][0] + s_stat[threadIdx.x][1] +
+                                 s_stat[threadIdx.x][2] + s_stat[threadIdx.x][3];
+    if (t) atomicAdd(cand_total + threadIdx.x, t);
   }
   if (j < m) {
     if (!REFINE) {
@@ -541,11 +554,17 @@ __global__ __launch_bounds__(256) void compact_write(
   }
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t trow0 = rbase + tile * kTileRows;
+    // The queries whose first row lies in [trow0, tend) are those after the
+    // query of row trow0 - 1 up to the query of row tend - 1: read from the
+    // row descriptors, so only a chunk's first tile searches row_off.
     if (tid < kTileRows) s_mask[tid] = masks[tile * kTileRows + tid];
-    if (tid == 64) s_qrange[0] = first_query_at(row_off, m, ss, trow0);
+    if (tid == 64)
+      s_qrange[0] = trow0 == 0      ? 0
+                    : trow0 > rbase ? (uint64_t)row_meta[trow0 - 1 - rbase].z + 1
+                                    : first_query_at(row_off, m, ss, trow0);
     if (tid == 128) {
       const uint64_t tend = trow0 + kTileRows;
-      s_qrange[1] = tend >= total_rows ? m : first_query_at(row_off, m, ss, tend);
+      s_qrange[1] = tend >= total_rows ? m : (uint64_t)row_meta[tend - 1 - rbase].z + 1;
     }
     __syncthreads();
     if (tid < 64) {   // exclusive scan of the row counts (one wave)
@@ -674,7 +693,7 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min,
-                         const float* lparams, const LeafRec* leaves, const uint32_t* qset,
+                         const LearnedView* lview, const uint32_t* qset,
                          const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s) {
@@ -684,13 +703,14 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   if ((e = fill_u32(qs.counters, 0, 16, s)) != hipSuccess) return e;
   if (dbg_lo) refine = false;   // the inspected ranges are the method's merged ranges
   qs.ss = refine ? 3 : 2;
-  const bool learned = lparams != nullptr && leaves != nullptr && qset == nullptr;
+  const bool learned = lview != nullptr && qset == nullptr;
+  const LearnedView lv = learned ? *lview : LearnedView{};
   unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
   {
     ProfScope ps(learned ? "ranges_learned" : "ranges_search", s);
 #define SFC_RANGES(C, R, L)                                                                  \
   ranges_search<C, R, L><<<blocks, 256, 0, s>>>(                                              \
-      (const double2*)q, delta, m, keys, n, lparams, leaves, refine_min, qset, set_off,      \
+      (const double2*)q, delta, m, keys, n, lv, refine_min, qset, set_off,                   \
       n_sets, qs.slot_begin,                                                                  \
       qs.slot_count, qs.slot_rows, qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr)
 #define SFC_RANGES_C(C)                         \

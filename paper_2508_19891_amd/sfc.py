@@ -38,7 +38,7 @@ EXPORTS = [
     "sfc_graph_query", "sfc_graph_launch", "sfc_graph_wait", "sfc_graph_free",
     "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
-    "sfc_compact", "sfc_update_info_get",
+    "sfc_compact", "sfc_update_info_get", "sfc_learned_route",
 ]
 
 NPARAM = 1153
@@ -79,7 +79,8 @@ class LearnedInfo(ctypes.Structure):
                 ("leaves", ctypes.c_uint32), ("leaves_nonempty", ctypes.c_uint32),
                 ("max_leaf", ctypes.c_uint32), ("mean_window", ctypes.c_double),
                 ("max_window", ctypes.c_uint32), ("endpoints_last", ctypes.c_uint64),
-                ("fallbacks_last", ctypes.c_uint64)]
+                ("fallbacks_last", ctypes.c_uint64), ("pieces", ctypes.c_uint32),
+                ("search_steps", ctypes.c_double)]
 
 
 class QueryStats(ctypes.Structure):
@@ -184,6 +185,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_compact.restype = i32
     L.sfc_update_info_get.argtypes = [vp, ctypes.POINTER(UpdateInfo)]
     L.sfc_update_info_get.restype = i32
+    L.sfc_learned_route.argtypes = [vp, vp, u64, vp, vp]
+    L.sfc_learned_route.restype = i32
     _lib = L
     return L
 
@@ -438,6 +441,15 @@ class Index:
         _check(lib().sfc_learned_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)),
                "sfc_learned_params")
         return out
+
+    def learned_route(self, keys: torch.Tensor):
+        """(direct, table) leaves of keys (int64 tensor holding uint64 bits)."""
+        keys = _dev(keys, torch.int64, "keys")
+        d = torch.empty(keys.numel(), dtype=torch.int32, device=self.device)
+        t = torch.empty_like(d)
+        _check(lib().sfc_learned_route(self.handle, _ptr(keys), keys.numel(), _ptr(d), _ptr(t)),
+               "sfc_learned_route")
+        return d, t
 
     def learned_shrink_windows(self):
         _check(lib().sfc_learned_shrink_windows(self.handle), "sfc_learned_shrink_windows")

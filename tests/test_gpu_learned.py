@@ -123,3 +123,26 @@ def test_gpu_gradient_matches_fp64_reference(seed):
     assert abs(loss_gpu - learned.loss(p32, x, t)) <= 1e-4 * max(1.0, learned.loss(p32, x, t))
     err = np.linalg.norm(g_gpu - g_ref) / max(np.linalg.norm(g_ref), 1e-12)
     assert err < 1e-3, err
+
+
+def test_tabulated_router_equals_network_for_every_input():
+    """Every 24-bit router input (each X << 40, and the key just below it)
+    gets the same leaf from the network and from the tabulation."""
+    pts, _, _ = _clustered(200_000, 10, MORTON, seed=13)
+    idx = sfc.Index(dev(pts), MORTON, search=sfc.LEARNED)
+    X = torch.arange(1 << 24, dtype=torch.int64, device=DEV)
+    for keys in (X << 40, (X << 40) | ((1 << 40) - 1)):
+        d, t = idx.learned_route(keys)
+        assert torch.equal(d, t)
+        assert bool((d[1:] >= d[:-1]).all())          # monotone
+
+
+def test_learned_search_takes_fewer_steps_than_binary_search():
+    pts, qs, ds = _clustered(1 << 20, 20_000, MORTON, seed=14)
+    idx = sfc.Index(dev(pts), MORTON, search=sfc.LEARNED, refine=True)
+    info = idx.learned_info()
+    print("learned info", info)
+    assert info["pieces"] >= (1 << 20) // 256
+    assert info["search_steps"] < 0.6 * 20
+    idx.query(dev(qs), dev(ds))
+    assert idx.learned_info()["fallbacks_last"] == 0
