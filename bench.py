@@ -275,10 +275,65 @@ def main():
     else:
         ms_paper, kern_paper, stats_paper, _ = run_mode(False)
     ms_step, kern, stats, total = run_mode(True)
+    def query_only(search: int):
+        """One index (built and, for the learned search, fitted once); the
+        timed steps are query batches only."""
+        torch.cuda.synchronize()
+        sfc.profile_reset()
+        sfc.profile_enable(True)
+        idx = sfc.Index(pts, curve, refine=True, search=search)
+        torch.cuda.synchronize()
+        sfc.profile_enable(False)
+        fit = {k: v[1] for k, v in sfc.profile_read().items() if k.startswith("learned_")}
+        _, ids0 = idx.query(q, d)
+        out_ids = torch.empty(ids0.numel() + 1024, dtype=torch.int32, device=dev)
+        del ids0
+        for _ in range(max(1, args.warmup)):
+            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
+        torch.cuda.synchronize()
+        sfc.profile_reset()
+        sfc.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps * 1e3
+        sfc.profile_enable(False)
+        kern_q = {k: v[1] / args.steps for k, v in sfc.profile_read().items()}
+        info = idx.learned_info() if search == sfc.LEARNED else None
+        rep_q = idx.last_stats()["reported"]
+        idx.close()
+        log(f"query-only search={search}: {dt:.3f} ms per batch")
+        return dt, kern_q, fit, info, rep_q
+
     if args.only_refined:
-        ms_l, kern_l, stats_l = float("nan"), {}, {}
+        lvb = None
     else:
-        ms_l, kern_l, stats_l, _ = run_mode(True, sfc.LEARNED)
+        ms_qb, kern_qb, _, _, rep_qb = query_only(sfc.BINARY)
+        ms_ql, kern_ql, fit_l, info_l, rep_ql = query_only(sfc.LEARNED)
+        assert rep_qb == rep_ql == total
+        lvb = {
+            "step": "one query batch over a built index (refined ranges); the learned index is "
+                    "fitted once beforehand",
+            "queries_per_s_learned": m / (ms_ql * 1e-3),
+            "queries_per_s_bsearch": m / (ms_qb * 1e-3),
+            "reported_pts_per_s_learned": rep_ql / (ms_ql * 1e-3),
+            "reported_pts_per_s_bsearch": rep_qb / (ms_qb * 1e-3),
+            "ms_per_batch_learned": ms_ql,
+            "ms_per_batch_bsearch": ms_qb,
+            "speedup_batch": ms_qb / ms_ql,
+            "search_ms_learned": kern_ql.get("ranges_learned", float("nan")),
+            "search_ms_bsearch": kern_qb.get("ranges_search", float("nan")),
+            "speedup_search": kern_qb.get("ranges_search", float("nan"))
+            / kern_ql.get("ranges_learned", float("nan")),
+            "fit_ms_once": fit_l,
+            "kernels_ms_per_batch_learned": kern_ql,
+            "kernels_ms_per_batch_bsearch": kern_qb,
+            "model": {k: info_l.get(k) for k in
+                      ("steps", "loss_init", "loss_final", "leaves_nonempty", "max_leaf", "pieces",
+                       "mean_window", "max_window", "search_steps", "endpoints_last",
+                       "fallbacks_last")},
+        }
 
     # Algorithmic bytes per step of each kernel (what the method must move).
     cand, rep = stats["candidates"], total
@@ -319,18 +374,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name + "_hilbert", "n": n, "m": m, "curve": "hilbert",
                    "search": "binary", "ranges": "refined", "step": "build + one query batch"},
-        "learned_vs_bsearch": {
-            "step": "build + fit + one query batch (refined ranges, learned search)",
-            "queries_per_s": m / (ms_l * 1e-3), "ms_per_step": ms_l,
-            "search_ms_learned": kern_l.get("ranges_learned", (0, float("nan")))[1] / args.steps,
-            "search_ms_bsearch": kern.get("ranges_search", (0, float("nan")))[1] / args.steps,
-            "fit_ms": sum(v[1] for k, v in kern_l.items() if k.startswith("learned_"))
-            / args.steps,
-            "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern_l.items()},
-            "model": {k: stats_l.get("learned", {}).get(k) for k in
-                      ("steps", "loss_init", "loss_final", "leaves_nonempty", "max_leaf",
-                       "mean_window", "max_window", "endpoints_last", "fallbacks_last")},
-        },
+        "learned_vs_bsearch": lvb,
         "paper_ranges": {"queries_per_s": m / (ms_paper * 1e-3), "ms_per_step": ms_paper,
                          "candidates_per_step": stats_paper["candidates"],
                          "kernels_ms_per_step": {k: v[1] / args.steps
