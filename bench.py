@@ -39,20 +39,18 @@ def kernel_source_hash(name: str) -> str:
 
 
 def load_traffic(kernel: str, source: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (its 'key: value' lines), or None if the kernel's source changed since
-    the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.md")
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (its 'traffic: kernel bytes source hash' lines), or None if the
+    kernel's source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_clustered_n2p24_m2p20_refined.md")
     if not os.path.exists(path):
         return None
-    rec = {}
     for line in open(path):
-        k, sep, v = line.partition(": ")
-        if sep and k in ("kernel", "bytes_per_launch", "source", "source_sha256_16"):
-            rec[k] = v.strip()
-    if rec.get("kernel") != kernel or rec.get("source_sha256_16") != kernel_source_hash(source):
-        return None
-    return float(rec["bytes_per_launch"])
+        parts = line.split()
+        if len(parts) == 5 and parts[0] == "traffic:" and parts[1] == kernel:
+            if parts[3] == source and parts[4] == kernel_source_hash(source):
+                return float(parts[2])
+    return None
 
 
 def cpu_baseline(wl, curve: int, m_sample: int):
