@@ -338,14 +338,15 @@ def main():
     tiles = math.ceil(cand / 4096)
     slots = 8 * m   # refined layout: eight slots (begin u32, count u32, offset u64) per query
     algo = {
-        "keygen_hist": 16 * n + 8 * n,                      # points in, keys out
-        "onesweep_pass": 8 * 24 * n,                        # 8 passes x (key+id) in and out
+        "keygen_tiles": 16 * n + 8 * n,                     # points in, keys out
+        "tile_hist": 7 * 8 * n,                             # passes 2..8 read the keys
+        "scatter_pass": 8 * 24 * n,                         # 8 passes x (key+id) in and out
         "ranges_search": 24 * m + 8 * slots,                # queries in; begin+count per slot
         "compact_test": 16 * cand + 24 * m + 12 * slots + cand // 8 + 4 * tiles,
         "compact_write": cand // 8 + 8 * tiles + 4 * rep + 4 * rep + 8 * (m + 1) + 12 * slots,
     }
     # The last radix pass also gathers the points (random 16 B reads, 16 B writes).
-    algo["onesweep_pass"] += 32 * n
+    algo["scatter_pass"] += 32 * n
     kern_gbs = {}
     for k, b in algo.items():
         if k in kern:
@@ -355,7 +356,8 @@ def main():
     launches_per_step = d_launch / args.steps
     bytes_per_launch = algo[dom] / launches_per_step
     achieved = bytes_per_launch / (d_ms / d_launch * 1e-3) / 1e9
-    traffic = load_traffic(dom, "query.hip" if dom.startswith(("compact", "ranges")) else "build.hip")
+    traffic = load_traffic(dom, "build.hip" if dom in ("keygen_tiles", "tile_hist", "digit_scan", "scatter_pass")
+                           else "query.hip")
 
     line = {
         "metric": "queries/s + reported pts/s at n=2^24, learned vs bsearch index, % HBM peak",
@@ -381,7 +383,7 @@ def main():
         "reported_per_step": rep,
         "candidates_per_step": cand,
         "candidates_per_report": cand / max(rep, 1),
-        "build_ms_per_step": sum(kern[k][1] for k in ("keygen_hist", "hist_reduce", "onesweep_pass")
+        "build_ms_per_step": sum(kern[k][1] for k in ("keygen_tiles", "tile_hist", "digit_scan", "scatter_pass")
                                  if k in kern) / args.steps,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items()},
         "roofline": {

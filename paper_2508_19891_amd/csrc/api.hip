@@ -517,16 +517,13 @@ sfc_status sfc_keys(const double* xy, uint64_t n, int curve, void* stream, uint6
   if (curve != SFC_CURVE_MORTON && curve != SFC_CURVE_HILBERT) return SFC_ERR_INVALID;
   if (n == 0) return SFC_OK;
   hipStream_t s = (hipStream_t)stream;
-  uint32_t blocks = 0;
-  sfc::build_scratch_bytes(n, &blocks);
   sfc::Allocator a;
-  void* tmp = a.get(align256((size_t)blocks * 8 * 256 * 4) + 256);
+  void* tmp = a.get(256);
   if (!tmp) return SFC_ERR_NOMEM;
-  uint32_t* partial = (uint32_t*)tmp;
-  uint32_t* err = (uint32_t*)((char*)tmp + align256((size_t)blocks * 8 * 256 * 4));
+  uint32_t* err = (uint32_t*)tmp;
   sfc_status st = SFC_OK;
   hipError_t e = sfc::fill_u32(err, 0, 1, s);
-  if (e == hipSuccess) e = sfc::launch_keys(xy, n, curve, keys, err, partial, blocks, nullptr, 0, s);
+  if (e == hipSuccess) e = sfc::launch_keys(xy, n, curve, keys, err, nullptr, s);
   uint64_t w = 0;
   if (e == hipSuccess) e = read_words(err, &w, 1, s);
   if (e != hipSuccess) {
@@ -583,7 +580,7 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
     h->keys = (uint64_t*)h->alloc.get(n * 8);
     h->ids = (uint32_t*)h->alloc.get(n * 4);
     h->xy = (double*)h->alloc.get(n * 16);
-    const size_t sb = sfc::build_scratch_bytes(n, nullptr) + 256;
+    const size_t sb = sfc::build_scratch_bytes(n) + 256;
     void* scratch = h->alloc.get(sb);
     if (!h->keys || !h->ids || !h->xy || !scratch) {
       h->alloc.put(scratch);
@@ -911,7 +908,7 @@ sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out) {
   g->h = h;
   g->kind = 0;
   g->generation = h->generation;
-  const size_t sb = sfc::build_scratch_bytes(h->n, nullptr) + 256;
+  const size_t sb = sfc::build_scratch_bytes(h->n) + 256;
   g->scratch = h->alloc.get(sb);
   if (!g->scratch) {
     graph_release(g);
@@ -1328,7 +1325,7 @@ sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_
   if (st == SFC_OK) st = ensure_key_of(h, (uint64_t)h->next_id + k);
   if (st == SFC_OK) st = ensure_spare(h, h->n + k);
   if (st != SFC_OK) return st;
-  const size_t sb = sfc::build_scratch_bytes(k, nullptr) + 256;
+  const size_t sb = sfc::build_scratch_bytes(k) + 256;
   char* batch = (char*)h->alloc.get(align256(k * 8) + align256(k * 4) + align256(k * 16) + sb);
   if (!batch) return SFC_ERR_NOMEM;
   uint64_t* bkeys = (uint64_t*)batch;

@@ -1,16 +1,27 @@
 // Construction (Sec. 2.1 "Storing P twice"; Alg. 2; Def. 3): curve keys,
 // an LSD radix sort of (key, id) and the gather of the points into key order.
 //
-// Kernels, in launch order for n points:
-//   keygen_hist    quantise, key, write keys; per-block LDS histograms of the
-//                  eight 8-bit digits; zero the look-back state of the sort.
-//   hist_reduce    sum the per-block histograms into one 8 x 256 table.
-//   onesweep_pass  x8: one stable counting pass per digit.  Each block ranks
-//                  a tile in LDS with wave64 ballots, publishes its digit
-//                  counts through a decoupled look-back, and scatters the
-//                  tile through LDS so that writes go out digit-contiguous.
-//                  The first pass takes ids from the position (iota); the
-//                  last pass also gathers the points into key order.
+// Kernels, in launch order for n points (one workgroup per tile of 2048 to
+// 4096 points):
+//   keygen_tiles   quantise, key, write keys; the tile's counts of the first
+//                  digit (LDS histograms per wave).
+//   then per 8-bit digit (eight passes, plus one or two passes over the set
+//   index for point sets):
+//   tile_hist      the tile's digit counts (from the second pass on);
+//   digit_scan     one workgroup per digit: exclusive scan of the digit's
+//                  counts over the tiles, and the digit's total;
+//   scatter_pass   rank the tile in LDS with wave64 ballots and scatter it
+//                  through LDS so that writes go out digit-contiguous, at
+//                  base(digit) + scan(digit, tile).  The first pass takes ids
+//                  from the position (iota); the last pass also gathers the
+//                  points into key order.
+// No workgroup waits on another.  Tiles are assigned so that each XCD (the
+// hardware deals workgroups to the eight XCDs in turn) scatters a contiguous
+// range of tiles: the runs that consecutive tiles write for one digit are
+// adjacent in the output, and they then meet in the same L2, which writes
+// back whole lines.  (A single-pass scheme with a decoupled look-back between
+// tiles, measured first, spent much of each pass polling status words across
+// the XCDs, and its dynamic tile order cannot be made XCD-contiguous.)
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -45,22 +56,33 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_t
   return x - v + add;
 }
 
-template <int CURVE>
-__global__ __launch_bounds__(256) void keygen_hist(const double2* __restrict__ xy, uint64_t n,
-                                                  uint64_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ partial,
-                                                  uint32_t* __restrict__ err,
-                                                  uint64_t* __restrict__ zero, uint64_t nzero) {
-  __shared__ uint32_t hist[kDigits][kRadix];
-  __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
-  for (int i = threadIdx.x; i < kDigits * kRadix; i += blockDim.x) (&hist[0][0])[i] = 0;
-  if (CURVE == SFC_CURVE_HILBERT)
-    for (int i = threadIdx.x; i < 1024; i += blockDim.x) lut[i] = kHilbertLutConst.v[i];
+// Per-wave LDS digit counts of a block, summed and stored digit-major:
+// counts[d * tiles + tile].
+__device__ __forceinline__ void store_tile_counts(uint32_t (*h)[kRadix], uint32_t* counts,
+                                                  uint64_t tiles, uint64_t tile) {
   __syncthreads();
+  const uint32_t d = threadIdx.x;
+  counts[(uint64_t)d * tiles + tile] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
 
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+// One workgroup per sort tile of tile_len input points: quantise, key, write
+// keys; with counts != null also the tile's counts of the first digit.
+template <int CURVE>
+__global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ xy, uint64_t n,
+                                                   uint32_t tile_len, uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ err,
+                                                   uint32_t* __restrict__ counts, uint64_t tiles) {
+  __shared__ uint32_t h[kSortWaves][kRadix];
+  __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
+  for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
+  if (CURVE == SFC_CURVE_HILBERT)
+    for (int i = threadIdx.x; i < 1024; i += 256) lut[i] = kHilbertLutConst.v[i];
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * tile_len;
+  const uint64_t end = base + tile_len < n ? base + tile_len : n;
+  const uint32_t w = threadIdx.x >> 6;
   bool bad = false;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  for (uint64_t i = base + threadIdx.x; i < end; i += 256) {
     const double2 p = xy[i];
     uint64_t key = 0;
     if (in_unit(p.x) && in_unit(p.y)) {
@@ -70,27 +92,10 @@ __global__ __launch_bounds__(256) void keygen_hist(const double2* __restrict__ x
       bad = true;
     }
     keys[i] = key;
-#pragma unroll
-    for (int d = 0; d < kDigits; ++d) atomicAdd(&hist[d][(key >> (8 * d)) & 255u], 1u);
+    if (counts) atomicAdd(&h[w][key & 255u], 1u);
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(err, kErrDomain);
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nzero; i += stride)
-    zero[i] = 0;
-  __syncthreads();
-  uint32_t* out = partial + (uint64_t)blockIdx.x * kDigits * kRadix;
-  for (int i = threadIdx.x; i < kDigits * kRadix; i += blockDim.x) out[i] = (&hist[0][0])[i];
-}
-
-// hist[c] += sum over a slice of blocks of partial[b][c]; grid = (8, chunks).
-__global__ __launch_bounds__(256) void hist_reduce(const uint32_t* __restrict__ partial,
-                                                   uint32_t nblocks, uint32_t* __restrict__ hist) {
-  const uint32_t col = blockIdx.x * 256 + threadIdx.x;   // digit position * 256 + digit
-  const uint32_t chunks = gridDim.y;
-  const uint32_t b0 = (uint32_t)(((uint64_t)nblocks * blockIdx.y) / chunks);
-  const uint32_t b1 = (uint32_t)(((uint64_t)nblocks * (blockIdx.y + 1)) / chunks);
-  uint32_t s = 0;
-  for (uint32_t b = b0; b < b1; ++b) s += partial[(uint64_t)b * kDigits * kRadix + col];
-  if (s) atomicAdd(&hist[col], s);
+  if (counts) store_tile_counts(h, counts, tiles, blockIdx.x);
 }
 
 // Digit of an element in a pass: a byte of the key, or (SETPASS) a byte of
@@ -103,14 +108,75 @@ __device__ __forceinline__ uint32_t pass_digit(uint64_t k, uint32_t v, int shift
   return v == 0xFFFFFFFFu ? 255u : (set_id[v] >> shift) & 255u;
 }
 
+// The tile's digit counts for a pass.
+template <bool SETPASS>
+__global__ __launch_bounds__(256) void tile_hist(const uint64_t* __restrict__ kin,
+                                                 const uint32_t* __restrict__ vin, uint64_t n,
+                                                 uint32_t tile_len, int shift,
+                                                 const uint32_t* __restrict__ set_id,
+                                                 uint32_t* __restrict__ counts, uint64_t tiles) {
+  __shared__ uint32_t h[kSortWaves][kRadix];
+  for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * tile_len;
+  const uint64_t end = base + tile_len < n ? base + tile_len : n;
+  const uint32_t w = threadIdx.x >> 6;
+  for (uint64_t i = base + threadIdx.x; i < end; i += 256) {
+    const uint32_t d = SETPASS ? pass_digit<true>(0, vin[i], shift, set_id)
+                               : pass_digit<false>(kin[i], 0, shift, set_id);
+    atomicAdd(&h[w][d], 1u);
+  }
+  store_tile_counts(h, counts, tiles, blockIdx.x);
+}
+
+// One workgroup per digit d: rel[d * tiles + t] = sum of the digit's counts
+// of tiles < t; dtot[d] = the digit's total.
+__global__ __launch_bounds__(256) void digit_scan(const uint32_t* __restrict__ counts,
+                                                  uint64_t tiles, uint32_t* __restrict__ rel,
+                                                  uint32_t* __restrict__ dtot) {
+  __shared__ uint32_t s_tmp[kSortWaves];
+  const uint32_t* c = counts + (uint64_t)blockIdx.x * tiles;
+  uint32_t* r = rel + (uint64_t)blockIdx.x * tiles;
+  uint32_t carry = 0;
+  for (uint64_t b = 0; b < tiles; b += 256 * 16) {
+    const uint64_t f = b + (uint64_t)threadIdx.x * 16;
+    uint32_t v[16], sum = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      v[i] = f + i < tiles ? c[f + i] : 0u;
+      sum += v[i];
+    }
+    const uint32_t excl = block_excl_scan256(sum, s_tmp);
+    uint32_t run = carry + excl;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (f + i < tiles) r[f + i] = run;
+      run += v[i];
+    }
+    // The block total: the last thread's exclusive prefix plus its sum.
+    if (threadIdx.x == 255) s_tmp[0] = excl + sum;
+    __syncthreads();
+    carry += s_tmp[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
+// Tile of workgroup b: XCD b % 8 takes the contiguous tiles
+// [x * per, (x + 1) * per); tiles past the end are idle workgroups.
+__device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t tiles) {
+  const uint64_t per = (tiles + 7) / 8;
+  return (b & 7) * per + (b >> 3);
+}
+
 // One stable pass of the LSD radix sort over the digit pass_digit(...).
 template <int ITEMS, bool FIRST, bool GATHER, bool SETPASS>
-__global__ __launch_bounds__(kSortThreads) void onesweep_pass(
+__global__ __launch_bounds__(kSortThreads) void scatter_pass(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
-    const uint32_t* __restrict__ hist, uint64_t* status, uint64_t* __restrict__ status_next,
-    uint32_t* tile_counter, uint32_t* err, const double2* __restrict__ xy_in,
-    double2* __restrict__ xy_out, const uint32_t* __restrict__ set_id) {
+    const uint32_t* __restrict__ rel, const uint32_t* __restrict__ dtot, uint64_t tiles,
+    uint32_t* err, const double2* __restrict__ xy_in, double2* __restrict__ xy_out,
+    const uint32_t* __restrict__ set_id) {
   constexpr int kTile = kSortThreads * ITEMS;
   __shared__ union {
     uint32_t wave_hist[kSortWaves][kRadix];
@@ -122,13 +188,11 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
   __shared__ uint32_t s_local[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_tmp[kSortWaves];
-  __shared__ uint32_t s_tile;
 
+  const uint64_t tile = xcd_tile(blockIdx.x, tiles);
+  if (tile >= tiles) return;   // the whole workgroup: no barrier is skipped by part of it
   const uint32_t tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
   for (uint32_t i = tid; i < kSortWaves * kRadix; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
-  __syncthreads();
-  const uint64_t tile = s_tile;
   const uint64_t base = tile * kTile;
   const uint64_t wbase = base + (uint64_t)w * (kWave * ITEMS);
 
@@ -146,6 +210,12 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
       val[i] = 0xFFFFFFFFu;
     }
   }
+  // This tile's offset within each digit's bucket and the digit totals (read
+  // early, used after the ranking).
+  const uint32_t d = tid;
+  const uint32_t rl = rel[(uint64_t)d * tiles + tile];
+  const uint32_t dt = dtot[d];
+  __syncthreads();
 
   // Rank within the wave, in (item, lane) order: lanes holding the same digit
   // are found with eight ballots; the lowest of them bumps the wave's counter.
@@ -153,24 +223,23 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
   const uint64_t below_mask = lanemask_lt();
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t d = pass_digit<SETPASS>(key[i], val[i], shift, set_id);
+    const uint32_t dg = pass_digit<SETPASS>(key[i], val[i], shift, set_id);
     uint64_t match = ~0ull;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
+      const bool bit = (dg >> b) & 1u;
       const uint64_t bal = __ballot(bit);
       match &= bit ? bal : ~bal;
     }
     const uint32_t cnt = (uint32_t)__popcll(match);
     const uint32_t below = (uint32_t)__popcll(match & below_mask);
-    const uint32_t pre = wh[d];
-    if (below == 0) wh[d] = pre + cnt;
+    const uint32_t pre = wh[dg];
+    if (below == 0) wh[dg] = pre + cnt;
     rank[i] = pre + below;
   }
   __syncthreads();
 
   // Thread d: tile count of digit d and per-wave exclusive bases.
-  const uint32_t d = tid;
   uint32_t tot = 0;
 #pragma unroll
   for (int ww = 0; ww < kSortWaves; ++ww) {
@@ -178,13 +247,10 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
     sm.wave_hist[ww][d] = tot;
     tot += c;
   }
-  if (tile > 0) st_release_agent(status + tile * kRadix + d, kFlagAggregate | tot);
-  status_next[tile * kRadix + d] = 0;
   const uint32_t local = block_excl_scan256(tot, s_tmp);
-  const uint32_t gstart = block_excl_scan256(hist[d], s_tmp);
-  const uint64_t excl = lookback_publish(status, tile, kRadix, d, tot, err);
+  const uint32_t dbase = block_excl_scan256(dt, s_tmp);
   s_local[d] = local;
-  s_gbase[d] = gstart + (uint32_t)excl - local;
+  s_gbase[d] = dbase + rl - local;
   __syncthreads();
 
   uint32_t lpos[ITEMS];
@@ -206,7 +272,7 @@ __global__ __launch_bounds__(kSortThreads) void onesweep_pass(
     const uint64_t k = sm.st.k[j];
     const uint32_t v = sm.st.v[j];
     const uint32_t pos = s_gbase[pass_digit<SETPASS>(k, v, shift, set_id)] + j;
-    if (pos >= n || (GATHER && v >= n)) {   // cannot happen with a consistent histogram
+    if (pos >= n || (GATHER && v >= n)) {   // cannot happen with consistent counts
       atomicOr(err, kErrInternal);
       continue;
     }
@@ -252,30 +318,19 @@ __global__ void fill_set_ids(const uint64_t* __restrict__ set_off, uint32_t n_se
   set_id[i] = lo - 1;
 }
 
-// Histograms of the set passes: hist[b][d] = points of sets whose byte b is d.
-__global__ void set_histograms(const uint64_t* __restrict__ set_off, uint32_t n_sets,
-                               uint32_t* __restrict__ hist) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_sets) return;
-  const uint32_t size = (uint32_t)(set_off[s + 1] - set_off[s]);
-  if (size == 0) return;
-  atomicAdd(&hist[s & 255u], size);
-  atomicAdd(&hist[kRadix + ((s >> 8) & 255u)], size);
-}
-
 template <int ITEMS>
-hipError_t launch_pass(bool first, bool gather, bool setpass, int shift, uint64_t tiles,
-                       const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
-                       uint64_t n, const uint32_t* hist, uint64_t* st, uint64_t* st_next,
-                       uint32_t* counter, uint32_t* err, const double* xy, double* xy_out,
-                       const uint32_t* set_id, hipStream_t s) {
-  const dim3 g((uint32_t)tiles), b(kSortThreads);
+hipError_t launch_scatter(bool first, bool gather, bool setpass, int shift, uint64_t tiles,
+                          const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                          uint32_t* vout, uint64_t n, const uint32_t* rel, const uint32_t* dtot,
+                          uint32_t* err, const double* xy, double* xy_out, const uint32_t* set_id,
+                          hipStream_t s) {
+  const dim3 g((uint32_t)(((tiles + 7) / 8) * 8)), b(kSortThreads);
   const double2* xi = (const double2*)xy;
   double2* xo = (double2*)xy_out;
-#define SFC_PASS(F, G, S)                                                                   \
-  onesweep_pass<ITEMS, F, G, S><<<g, b, 0, s>>>(kin, vin, kout, vout, n, shift, hist, st,   \
-                                                st_next, counter, err, G ? xi : nullptr,    \
-                                                G ? xo : nullptr, set_id)
+#define SFC_PASS(F, G, S)                                                                      \
+  scatter_pass<ITEMS, F, G, S><<<g, b, 0, s>>>(kin, vin, kout, vout, n, shift, rel, dtot,     \
+                                               tiles, err, G ? xi : nullptr, G ? xo : nullptr, \
+                                               set_id)
   if (setpass) {
     if (gather) SFC_PASS(false, true, true);
     else SFC_PASS(false, false, true);
@@ -297,34 +352,31 @@ hipError_t launch_pass(bool first, bool gather, bool setpass, int shift, uint64_
 int set_passes(uint32_t n_sets) { return n_sets <= 1 ? 0 : (n_sets <= 256 ? 1 : 2); }
 
 // Device bytes of scratch needed by sort_build for n points.
-size_t build_scratch_bytes(uint64_t n, uint32_t* keygen_blocks) {
+size_t build_scratch_bytes(uint64_t n) {
   const uint64_t tiles = (n + sort_tile(n) - 1) / sort_tile(n);
-  uint64_t blocks = (n + 1023) / 1024;
-  if (blocks > 1024) blocks = 1024;
-  if (blocks < 1) blocks = 1;
-  if (keygen_blocks) *keygen_blocks = (uint32_t)blocks;
+  const uint64_t cells = tiles * kRadix;   // (digit, tile) counts of a pass
   size_t b = 0;
-  b += align256(n * 8);                             // keys ping
-  b += align256(n * 4);                             // ids ping
-  b += align256(blocks * kDigits * kRadix * 4);     // per-block histograms
-  b += align256((kDigits + 2) * kRadix * 4);        // histograms (keys, set bytes)
-  b += align256(2 * tiles * kRadix * 8);            // look-back status (two buffers)
-  b += align256(64);                                // counters + error word
-  b += align256(n * 4);                             // set id per input point
+  b += align256(n * 8);                    // keys ping
+  b += align256(n * 4);                    // ids ping
+  b += align256(cells * 4);                // tile counts
+  b += align256(cells * 4);                // their scan within each digit
+  b += align256(kRadix * 4);               // digit totals
+  b += align256(n * 4);                    // set id per input point
   return b;
 }
 
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
-                       uint32_t* partial, uint32_t blocks, uint64_t* zero, uint64_t nzero,
-                       hipStream_t s) {
+                       uint32_t* counts, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  ProfScope ps("keygen_hist", s);
+  const uint32_t tile = (uint32_t)sort_tile(n);
+  const uint64_t tiles = (n + tile - 1) / tile;
+  ProfScope ps("keygen_tiles", s);
   if (curve == SFC_CURVE_HILBERT)
-    keygen_hist<SFC_CURVE_HILBERT><<<blocks, 256, 0, s>>>((const double2*)xy, n, keys, partial,
-                                                          err, zero, nzero);
+    keygen_tiles<SFC_CURVE_HILBERT><<<(uint32_t)tiles, 256, 0, s>>>((const double2*)xy, n, tile,
+                                                                    keys, err, counts, tiles);
   else
-    keygen_hist<SFC_CURVE_MORTON><<<blocks, 256, 0, s>>>((const double2*)xy, n, keys, partial,
-                                                         err, zero, nzero);
+    keygen_tiles<SFC_CURVE_MORTON><<<(uint32_t)tiles, 256, 0, s>>>((const double2*)xy, n, tile,
+                                                                   keys, err, counts, tiles);
   return hipGetLastError();
 }
 
@@ -339,16 +391,15 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err_host_visible,
                       hipStream_t s, const uint64_t* set_off, uint32_t n_sets) {
   if (n == 0) return hipSuccess;
-  uint32_t kblocks = 0;
-  build_scratch_bytes(n, &kblocks);
-  const uint64_t tiles = (n + sort_tile(n) - 1) / sort_tile(n);
+  const uint32_t tile = (uint32_t)sort_tile(n);
+  const uint64_t tiles = (n + tile - 1) / tile;
+  const uint64_t cells = tiles * kRadix;
   char* p = (char*)scratch;
   uint64_t* keys_b = (uint64_t*)p;      p += align256(n * 8);
   uint32_t* ids_b = (uint32_t*)p;       p += align256(n * 4);
-  uint32_t* partial = (uint32_t*)p;     p += align256((uint64_t)kblocks * kDigits * kRadix * 4);
-  uint32_t* hist = (uint32_t*)p;        p += align256((kDigits + 2) * kRadix * 4);
-  uint64_t* status = (uint64_t*)p;      p += align256(2 * tiles * kRadix * 8);
-  uint32_t* counters = (uint32_t*)p;    p += align256(64);   // tile counter per pass
+  uint32_t* counts = (uint32_t*)p;      p += align256(cells * 4);
+  uint32_t* rel = (uint32_t*)p;         p += align256(cells * 4);
+  uint32_t* dtot = (uint32_t*)p;        p += align256(kRadix * 4);
   uint32_t* set_id = (uint32_t*)p;
 
   const int sp = set_off ? set_passes(n_sets) : 0;
@@ -358,24 +409,11 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   auto out_is_final = [&](int pass) { return ((passes - 1 - pass) & 1) == 0; };
   uint64_t* keys_first = out_is_final(0) ? keys_b : keys_out;
 
-  hipError_t e;
-  // The first look-back buffer is zeroed by keygen_hist, the second by the
-  // first pass.
-  if ((e = fill_u32(hist, 0, (kDigits + 2) * kRadix, s)) != hipSuccess) return e;
-  if ((e = fill_u32(counters, 0, 16, s)) != hipSuccess) return e;
-  e = launch_keys(xy, n, curve, keys_first, err_host_visible, partial, kblocks, status,
-                  tiles * kRadix, s);
+  hipError_t e = launch_keys(xy, n, curve, keys_first, err_host_visible, counts, s);
   if (e != hipSuccess) return e;
-  {
-    ProfScope ps("hist_reduce", s);
-    const uint32_t chunks = kblocks < 16 ? kblocks : 16;
-    hist_reduce<<<dim3(kDigits, chunks), 256, 0, s>>>(partial, kblocks, hist);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
   if (sp > 0) {
     ProfScope ps("set_prep", s);
     fill_set_ids<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(set_off, n_sets, n, set_id);
-    set_histograms<<<(n_sets + 255) / 256, 256, 0, s>>>(set_off, n_sets, hist + kDigits * kRadix);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const uint64_t* kin = keys_first;
@@ -384,16 +422,28 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     const bool fin = out_is_final(pass);
     uint64_t* kout = fin ? keys_out : keys_b;
     uint32_t* vout = fin ? ids_out : ids_b;
-    uint64_t* st = status + (uint64_t)(pass & 1) * tiles * kRadix;
-    uint64_t* st_next = status + (uint64_t)((pass + 1) & 1) * tiles * kRadix;
     const bool setpass = pass >= kDigits;
     const int shift = setpass ? 8 * (pass - kDigits) : 8 * pass;
     const bool gather = pass == passes - 1;
-    ProfScope ps(setpass ? "set_pass" : "onesweep_pass", s);
-    const uint32_t* hp = hist + pass * kRadix;
-#define SFC_LAUNCH(I)                                                                          \
-  launch_pass<I>(pass == 0, gather, setpass, shift, tiles, kin, vin, kout, vout, n, hp, st,   \
-                 st_next, counters + pass, err_host_visible, xy, xy_out, set_id, s)
+    if (pass > 0) {
+      ProfScope ps("tile_hist", s);
+      if (setpass)
+        tile_hist<true><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, set_id, counts,
+                                                        tiles);
+      else
+        tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, set_id, counts,
+                                                         tiles);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+      ProfScope ps("digit_scan", s);
+      digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    ProfScope ps(setpass ? "set_pass" : "scatter_pass", s);
+#define SFC_LAUNCH(I)                                                                        \
+  launch_scatter<I>(pass == 0, gather, setpass, shift, tiles, kin, vin, kout, vout, n, rel, dtot, \
+                    err_host_visible, xy, xy_out, set_id, s)
     switch (sort_items(n)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;

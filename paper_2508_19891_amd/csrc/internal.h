@@ -24,10 +24,11 @@ hipError_t fill_u64(uint64_t* p, uint64_t value, uint64_t count, hipStream_t s);
 hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s);
 
 // ---- construction (build.hip) ----
-size_t build_scratch_bytes(uint64_t n, uint32_t* keygen_blocks);
+size_t build_scratch_bytes(uint64_t n);
+// Keys of n points (err: device word, kErrDomain is or-ed in); counts, if
+// not null, receives the first digit's counts per sort tile.
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
-                       uint32_t* partial, uint32_t blocks, uint64_t* zero, uint64_t nzero,
-                       hipStream_t s);
+                       uint32_t* counts, hipStream_t s);
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
                       hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0);
