@@ -148,6 +148,66 @@ def batched_sets_bench(args, sfc, workload, torch):
                          "test_shape": tune_q, "test_shape_ms": tune_q_ms}}
 
 
+def learned_large_bench(args, sfc, workload, torch):
+    """The learned-index shape: 2^26 clustered points, Morton keys, 2^22
+    uniform queries with delta = sqrt(10 / (pi n)) (about 10 reports each at
+    unit density); query batches over one built index, binary vs learned
+    search, the learned fit timed once."""
+    dev = torch.device("cuda:0")
+    wl = workload.clustered_uniform_queries(n=1 << 26, m=1 << 22, curve=sfc.MORTON)
+    n, m = wl.points.shape[0], wl.queries.shape[0]
+    log(f"learned at scale: n={n} m={m}")
+    pts = torch.as_tensor(wl.points).to(dev)
+    q = torch.as_tensor(wl.queries).to(dev)
+    d = torch.as_tensor(wl.delta).to(dev)
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    out = {"workload": wl.name + "_morton", "n": n, "m": m}
+    reps = []
+    for name, search in (("bsearch", sfc.BINARY), ("learned", sfc.LEARNED)):
+        torch.cuda.synchronize()
+        sfc.profile_reset()
+        sfc.profile_enable(True)
+        idx = sfc.Index(pts, sfc.MORTON, search=search)
+        torch.cuda.synchronize()
+        sfc.profile_enable(False)
+        build = {k: v[1] for k, v in sfc.profile_read().items()}
+        _, ids0 = idx.query(q, d)
+        out_ids = torch.empty(ids0.numel() + 1024, dtype=torch.int32, device=dev)
+        reps.append(int(ids0.numel()))
+        del ids0
+        for _ in range(max(1, args.warmup)):
+            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
+        torch.cuda.synchronize()
+        sfc.profile_reset()
+        sfc.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        sfc.profile_enable(False)
+        kern = {k: v[1] / args.steps for k, v in sfc.profile_read().items()}
+        out[name] = {"ms_per_batch": ms, "queries_per_s": m / (ms * 1e-3),
+                     "search_ms": kern.get("ranges_learned" if search else "ranges_search"),
+                     "kernels_ms_per_batch": kern,
+                     "build_ms": sum(v for k, v in build.items() if not k.startswith("learned_")),
+                     "fit_ms": sum(v for k, v in build.items() if k.startswith("learned_"))}
+        if search == sfc.LEARNED:
+            info = idx.learned_info()
+            out[name]["model"] = {k: info[k] for k in ("leaves_nonempty", "max_leaf", "pieces",
+                                                       "mean_window", "max_window", "search_steps",
+                                                       "fallbacks_last")}
+        idx.close()
+        del out_ids
+    assert reps[0] == reps[1]
+    out["reported_per_batch"] = reps[0]
+    out["speedup_batch"] = out["bsearch"]["ms_per_batch"] / out["learned"]["ms_per_batch"]
+    out["speedup_search"] = out["bsearch"]["search_ms"] / out["learned"]["search_ms"]
+    del pts, q, d
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_bench(args, sfc, workload, torch):
     """Poisson stream of query / insert / erase batches (40/40/20, sizes
     2^U[10,16]) over 2^25 clustered points, Morton keys, learned search:
@@ -196,6 +256,8 @@ def main():
                     help="time only the refined range mode (for profiler runs)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched point-set measurement")
+    ap.add_argument("--no-learned-large", action="store_true",
+                    help="skip the learned-index measurement at n=2^26")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the insert/erase/query serving measurement")
     ap.add_argument("--serving-requests", type=int, default=1000)
@@ -399,6 +461,8 @@ def main():
     }
     if not args.no_batched and not args.only_refined:
         line["batched_sets"] = batched_sets_bench(args, sfc, workload, torch)
+    if not args.no_learned_large and not args.only_refined:
+        line["learned_large"] = learned_large_bench(args, sfc, workload, torch)
     if not args.no_serving and not args.only_refined:
         line["serving"] = serving_bench(args, sfc, workload, torch)
     if not args.no_cpu_baseline:
