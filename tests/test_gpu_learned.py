@@ -146,3 +146,35 @@ def test_learned_search_takes_fewer_steps_than_binary_search():
     assert info["search_steps"] < 0.6 * 20
     idx.query(dev(qs), dev(ds))
     assert idx.learned_info()["fallbacks_last"] == 0
+
+
+def test_trained_router_against_its_initialisation():
+    """What training buys over the router's quantile initialisation: the
+    sample loss drops, and the search after routing takes no more steps."""
+    pts, qs, ds = _clustered(1 << 20, 20_000, HILBERT, seed=15)
+    init = sfc.Index(dev(pts), HILBERT, search=sfc.LEARNED, learn_steps=0)
+    trained = sfc.Index(dev(pts), HILBERT, search=sfc.LEARNED, learn_steps=512)
+    a, b = init.learned_info(), trained.learned_info()
+    print("init", a["loss_final"], a["search_steps"], a["max_leaf"],
+          "trained", b["loss_final"], b["search_steps"], b["max_leaf"])
+    assert b["loss_final"] < a["loss_final"]
+    assert b["search_steps"] <= a["search_steps"] + 0.25
+    for ix in (init, trained):
+        off, ids = ix.query(dev(qs), dev(ds))
+        assert ix.learned_info()["fallbacks_last"] == 0
+    ref = oracle.query(oracle.build(pts, HILBERT), qs, ds, HILBERT, nthreads=4)
+    assert np.array_equal(ids.cpu().numpy().view(np.uint32), ref[1])
+
+
+def test_learned_search_in_a_recorded_graph():
+    pts, qs, ds = _clustered(150_000, 8_000, MORTON, seed=16)
+    idx = sfc.Index(dev(pts), MORTON, search=sfc.LEARNED, refine=True)
+    q, d = dev(qs), dev(ds)
+    want = idx.query(q, d)
+    g = sfc.Graph.query(idx, q, d, max_rows=idx.last_stats()["rows"] + 64,
+                        ids_cap=want[1].numel() + 1)
+    for _ in range(3):
+        g.launch()
+        off, ids = g.result()
+        assert torch.equal(off, want[0]) and torch.equal(ids, want[1])
+    g.close()
