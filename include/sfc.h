@@ -117,7 +117,11 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt,
  *   ids_cap   capacity of ids in elements.
  *   total_out host; receives the number of reported ids.
  * If total > ids_cap the call returns SFC_ERR_CAPACITY after writing offsets
- * and *total_out; only the first ids_cap ids are written then.  A query with
+ * and *total_out.  When the batch has at most 2^25 candidate rows (64
+ * candidates each; every batch in practice) the ids buffer is left untouched
+ * and the batch's test results are kept: sfc_query_retry then writes the ids
+ * into a large enough buffer without rerunning the searches and the test.
+ * Larger batches write the first ids_cap ids and must be rerun.  A query with
  * delta < 0 or a non-finite value makes the call return SFC_ERR_INVALID with
  * offsets and ids unspecified.  Synchronises the stream.
  */
@@ -183,6 +187,17 @@ typedef struct {
   uint64_t compactions; /* compactions run */
 } sfc_update_info;
 sfc_status sfc_update_info_get(const sfc_index* h, sfc_update_info* out);
+
+/*
+ * Write pass of the last sfc_query_batch / sfc_query_sets / sfc_query_epochs
+ * call on h that returned SFC_ERR_CAPACITY with its test results kept:
+ * offsets (device, m+1) and ids (device, ids_cap) as in that call.  Valid
+ * until the next call that queries or updates h; SFC_ERR_UNSUPPORTED if no
+ * such batch is kept, SFC_ERR_CAPACITY (with *total_out) if ids_cap is still
+ * too small.  The query inputs are not read again.  Synchronises the stream.
+ */
+sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
+                           uint64_t* total_out);
 
 /*
  * Many independent point sets in one index (batched instances).  Set s owns

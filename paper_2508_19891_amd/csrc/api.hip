@@ -209,6 +209,7 @@ struct sfc_index {
   float* lparams = nullptr;        // device, sfc::kParams
   void* lmodel = nullptr;          // device: tabulated router, leaves and pieces
   uint64_t lmodel_n = 0;           // keys lmodel is sized for
+  bool lstats_stale = false;       // leaf statistics not yet read back after a refit
   sfc::LearnedArrays larr{};       // carved from lmodel
   sfc_learned_info linfo{};
   int learn_steps = 256;
@@ -230,6 +231,14 @@ struct sfc_index {
   uint64_t dead = 0;               // stored entries with a tombstone
   std::vector<std::pair<uint32_t, uint64_t>> tombs;   // (erase epoch, entries), not dropped
   uint64_t generation = 0;         // bumped by every update; recorded graphs check it
+  // A batch that returned SFC_ERR_CAPACITY from a single compaction chunk:
+  // its masks and offsets are still in ws/cws, so the same call with a
+  // larger ids buffer reruns only the write pass.
+  struct Pending {
+    bool valid = false;
+    uint64_t m = 0, rows = 0, total = 0, generation = 0;
+    sfc::QueryScratch qs{};
+  } pending;
   uint64_t merges = 0, compactions = 0;
 };
 
@@ -333,6 +342,7 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
                       uint64_t m, sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
                       uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                       uint32_t* dbg_nr, const uint32_t* qepoch = nullptr) {
+  h->pending.valid = false;   // the scratch is about to be reused
   sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
   if (st != SFC_OK) return st;
   sfc::query_scratch_carve(h->ws, m, qs);
@@ -451,6 +461,7 @@ sfc_status fit_learned(sfc_index* h, int steps) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   h->alloc.put(scratch);
   if (e == hipSuccess) e = leaf_stats(h);
+  h->lstats_stale = false;
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return from_hip(e);
@@ -477,8 +488,10 @@ sfc_status refit_leaves(sfc_index* h) {
     h->linfo.fitted = 0;
     return st;
   }
+  // The statistics are read back when asked for (sfc_learned_info_get), so
+  // that an update does not wait for a copy of every piece.
   hipError_t e = sfc::learned_refit_leaves(h->keys, h->n, h->larr, h->stream);
-  if (e == hipSuccess) e = leaf_stats(h);
+  h->lstats_stale = true;
   if (e != hipSuccess) {
     (void)hipGetLastError();
     h->linfo.fitted = 0;
@@ -665,6 +678,7 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
   uint64_t total_rows = 0, total_cand = 0;
   sfc::EpochView ev;
   const bool filtered = epoch_view(h, qepoch, &ev);
+  h->pending.valid = false;
   if (m > 0) {
     sfc_status st = run_ranges(h, q, delta, qset, m, &qs, &total_rows, &total_cand, nullptr,
                                nullptr, nullptr, nullptr, nullptr, qepoch);
@@ -692,6 +706,15 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
   h->last.reported = total;
   h->last.rows = total_rows;
   *total_out = total;
+  if (total > ids_cap && m > 0 && sfc::compact_single_chunk(total_rows)) {
+    sfc_index::Pending& p = h->pending;
+    p.valid = true;
+    p.m = m;
+    p.rows = total_rows;
+    p.total = total;
+    p.generation = h->generation;
+    p.qs = qs;
+  }
   return total > ids_cap ? SFC_ERR_CAPACITY : SFC_OK;
 }
 
@@ -703,6 +726,26 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, u
                            uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
                            uint64_t* total_out) {
   return query_impl(h, q, delta, nullptr, m, offsets, ids, ids_cap, total_out);
+}
+
+sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
+                           uint64_t* total_out) {
+  if (!h || !offsets || !total_out || (ids_cap > 0 && !ids)) return SFC_ERR_INVALID;
+  const sfc_index::Pending p = h->pending;
+  if (!p.valid || p.generation != h->generation) return SFC_ERR_UNSUPPORTED;
+  if (ids_cap < p.total) {
+    *total_out = p.total;
+    return SFC_ERR_CAPACITY;
+  }
+  h->pending.valid = false;
+  SFC_TRY(sfc::launch_compact(nullptr, nullptr, p.m, h->xy, h->ids, h->n, p.qs, p.rows, false,
+                              h->cws, offsets, ids, ids_cap, h->stream, nullptr, true));
+  uint64_t total = 0;
+  SFC_TRY(read_words(offsets + p.m, &total, 1, h->stream));
+  if (total != p.total) return SFC_ERR_DEVICE;
+  h->last.reported = total;
+  *total_out = total;
+  return SFC_OK;
 }
 
 sfc_status sfc_query_epochs(sfc_index* h, const double* q, const double* delta,
@@ -782,6 +825,10 @@ sfc_status sfc_debug_chunk_tiles(uint64_t tiles) {
 sfc_status sfc_learned_shrink_windows(sfc_index* h) {
   if (!h) return SFC_ERR_INVALID;
   if (!h->linfo.fitted) return SFC_ERR_UNSUPPORTED;
+  if (h->lstats_stale) {
+    SFC_TRY(leaf_stats(h));
+    h->lstats_stale = false;
+  }
   const uint32_t np = h->linfo.pieces;
   std::vector<sfc::PieceRec> pr(np);
   if (np == 0) return SFC_OK;
@@ -806,6 +853,12 @@ sfc_status sfc_learned_route(sfc_index* h, const uint64_t* keys, uint64_t count,
 
 sfc_status sfc_learned_info_get(const sfc_index* h, sfc_learned_info* out) {
   if (!h || !out) return SFC_ERR_INVALID;
+  if (h->linfo.fitted && h->lstats_stale) {
+    // Reading the statistics back changes no observable state of the index.
+    sfc_index* m = const_cast<sfc_index*>(h);
+    SFC_TRY(leaf_stats(m));
+    m->lstats_stale = false;
+  }
   *out = h->linfo;
   return SFC_OK;
 }

@@ -83,7 +83,11 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s,
-                          const EpochView* ev = nullptr);
+                          const EpochView* ev = nullptr, bool write_only = false);
+// Whether a batch of total_rows rows (host-sized) is compacted in one chunk:
+// then an output larger than the capacity leaves the ids untouched, and the
+// write pass can be rerun alone (write_only) for a larger buffer.
+bool compact_single_chunk(uint64_t total_rows);
 // Scan with the element count in device memory (count_dev <= max_count).
 hipError_t scan_excl_dev(const uint32_t* in, uint64_t* out, const uint32_t* count_dev,
                          uint64_t max_count, const uint64_t* carry_in, uint64_t* partial,

@@ -539,7 +539,8 @@ __global__ __launch_bounds__(256) void compact_write(
     const uint64_t* __restrict__ row_off, int ss, const uint4* __restrict__ row_meta,
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     const uint64_t* __restrict__ masks, const uint64_t* __restrict__ tile_off,
-    uint64_t* __restrict__ offsets, uint32_t* __restrict__ out_ids, uint64_t cap) {
+    uint64_t* __restrict__ offsets, uint32_t* __restrict__ out_ids, uint64_t cap,
+    bool whole) {
   __shared__ uint64_t s_mask[kTileRows];
   __shared__ uint32_t s_pre[kTileRows + 1];
   __shared__ uint64_t s_qrange[2];
@@ -552,6 +553,10 @@ __global__ __launch_bounds__(256) void compact_write(
     for (uint64_t qq = tid; qq <= m; qq += 256) offsets[qq] = 0;
     return;
   }
+  // whole: this launch covers every row, so tile_off[ntiles] is the batch's
+  // total; an output larger than cap then leaves out_ids untouched (the
+  // offsets are still written).
+  const bool write_ids = !whole || ntiles == 0 || tile_off[ntiles] <= cap;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t trow0 = rbase + tile * kTileRows;
     // The queries whose first row lies in [trow0, tend) are those after the
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(256) void compact_write(
       }
 #pragma unroll
       for (int jr = 0; jr < ROWS; ++jr)
-        if (act[jr] && opos[jr] < cap) out_ids[opos[jr]] = idv[jr];
+        if (write_ids && act[jr] && opos[jr] < cap) out_ids[opos[jr]] = idv[jr];
     }
 
     const uint64_t valid = total_rows - trow0 < (uint64_t)kTileRows ? total_rows - trow0
@@ -650,6 +655,9 @@ uint32_t fill_blocks(uint64_t count) {
 }  // namespace
 
 uint64_t compact_chunk_tiles() { return g_chunk_tiles.load(std::memory_order_relaxed); }
+bool compact_single_chunk(uint64_t total_rows) {
+  return (total_rows + kCompactTileRows - 1) / kCompactTileRows <= compact_chunk_tiles();
+}
 void set_compact_chunk_tiles(uint64_t tiles) {
   g_chunk_tiles.store(tiles == 0 || tiles > kCompactChunkTiles ? kCompactChunkTiles : tiles,
                       std::memory_order_relaxed);
@@ -741,7 +749,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s,
-                          const EpochView* ev) {
+                          const EpochView* ev, bool write_only) {
   hipError_t e;
   if (m == 0) return fill_u64(offsets, 0, 1, s);
   const uint64_t nseg = m << qs.ss;
@@ -765,6 +773,9 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
   const uint64_t* carry = nullptr;
   int buf = 0;
   const uint64_t chunks = tiles_all ? (tiles_all + chunk - 1) / chunk : 1;
+  // write_only: the masks and tile offsets of an earlier call on the same
+  // batch are still in cscratch (one chunk only); run the write pass again.
+  if (write_only && (chunks != 1 || device_sized)) return hipErrorInvalidValue;
   for (uint64_t c = 0; c < chunks; ++c, buf ^= 1) {
     const uint64_t rbase = c * chunk * kCompactTileRows;
     const uint64_t nt = tiles_all - c * chunk < chunk ? (tiles_all ? tiles_all - c * chunk : 1)
@@ -776,13 +787,13 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
                              : device_sized ? max_rows : rbase + nt * kCompactTileRows;
     const bool flag = device_sized && c + 1 == chunks;
     const uint32_t grid = (uint32_t)(nt < kCompactGrid ? (nt ? nt : 1) : kCompactGrid);
-    {
+    if (!write_only) {
       ProfScope ps("expand_rows", s);
       expand_rows<<<(uint32_t)((nseg + 255) / 256), 256, 0, s>>>(
           qs.row_off, qs.slot_begin, qs.slot_count, nseg, qs.ss, rbase, row_end, meta);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    {
+    if (!write_only) {
       ProfScope ps("compact_test", s);
 #define SFC_TEST(R, I, E)                                                                  \
   compact_test<R, I, E><<<grid, 256, 0, s>>>(                                             \
@@ -806,7 +817,8 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
 #undef SFC_TEST
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = scan_excl_dev(hits, toff[buf], qs.counters + 12, nt, carry, stmp, s)) != hipSuccess)
+    if (!write_only &&
+        (e = scan_excl_dev(hits, toff[buf], qs.counters + 12, nt, carry, stmp, s)) != hipSuccess)
       return e;
     {
       ProfScope ps("compact_write", s);
@@ -815,7 +827,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
       // 10^7 rows); more id loads in flight per wave.
       compact_write<8, 2><<<grid, 256, 0, s>>>(ids, npts, m, qs.row_off, qs.ss, meta, total_dev,
                                                rbase, row_end, masks, toff[buf], offsets,
-                                               out_ids, cap);
+                                               out_ids, cap, chunks == 1);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // The chunk's total, read by the next chunk's scan.  A chunk has tiles

@@ -38,7 +38,7 @@ EXPORTS = [
     "sfc_graph_query", "sfc_graph_launch", "sfc_graph_wait", "sfc_graph_free",
     "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
-    "sfc_compact", "sfc_update_info_get", "sfc_learned_route",
+    "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
 ]
 
 NPARAM = 1153
@@ -187,6 +187,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_update_info_get.restype = i32
     L.sfc_learned_route.argtypes = [vp, vp, u64, vp, vp]
     L.sfc_learned_route.restype = i32
+    L.sfc_query_retry.argtypes = [vp, vp, vp, u64, ctypes.POINTER(u64)]
+    L.sfc_query_retry.restype = i32
     _lib = L
     return L
 
@@ -304,8 +306,9 @@ class Index:
               out_ids: torch.Tensor | None = None, out_offsets: torch.Tensor | None = None):
         """Batched queries; returns (offsets int64[m+1], ids int32[total]).
 
-        Without ids_cap/out_ids the call is made twice when the first guess of
-        the output size is too small (the second call has the exact size)."""
+        Without ids_cap/out_ids a first guess of the output size that is too
+        small is followed by the library's write-only retry into a buffer of
+        the exact size."""
         q = _dev(q, torch.float64, "q")
         delta = _dev(delta, torch.float64, "delta")
         m = q.shape[0]
@@ -313,20 +316,42 @@ class Index:
             raise ValueError("q must be (m, 2) and delta (m,)")
         offsets = out_offsets if out_offsets is not None else torch.empty(
             m + 1, dtype=torch.int64, device=self.device)
+        auto = ids_cap is None and out_ids is None   # may retry with the exact size
         if out_ids is None:
             cap = ids_cap if ids_cap is not None else max(16 * m, 1024)
             out_ids = torch.empty(cap, dtype=torch.int32, device=self.device)
         total = ctypes.c_uint64(0)
         st = lib().sfc_query_batch(self.handle, _ptr(q), _ptr(delta), m, _ptr(offsets),
                                    _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
-        if st == SFC_ERR_CAPACITY and ids_cap is None:
-            out_ids = torch.empty(max(int(total.value), 1), dtype=torch.int32, device=self.device)
-            st = lib().sfc_query_batch(self.handle, _ptr(q), _ptr(delta), m, _ptr(offsets),
-                                       _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY and auto:
+            out_ids, st = self._retry(offsets, total, lambda o, t: lib().sfc_query_batch(
+                self.handle, _ptr(q), _ptr(delta), m, _ptr(offsets), _ptr(o), o.numel(),
+                ctypes.byref(t)))
         if st == SFC_ERR_CAPACITY:
             raise CapacityError(st, "sfc_query_batch", int(total.value))
         _check(st, "sfc_query_batch")
         return offsets, out_ids[: int(total.value)]
+
+    def _retry(self, offsets, total, rerun):
+        """After SFC_ERR_CAPACITY: an ids buffer of the exact size, filled by
+        the kept batch's write pass (sfc_query_retry), or by rerunning the
+        batch when the library kept none.  Returns (ids buffer, status)."""
+        out_ids = torch.empty(max(int(total.value), 1), dtype=torch.int32, device=self.device)
+        st = lib().sfc_query_retry(self.handle, _ptr(offsets), _ptr(out_ids), out_ids.numel(),
+                                   ctypes.byref(total))
+        if st == SFC_ERR_UNSUPPORTED:
+            st = rerun(out_ids, total)
+        return out_ids, st
+
+    def query_retry(self, offsets: torch.Tensor, out_ids: torch.Tensor) -> int:
+        """sfc_query_retry into caller buffers; returns the total."""
+        total = ctypes.c_uint64(0)
+        st = lib().sfc_query_retry(self.handle, _ptr(offsets), _ptr(out_ids), out_ids.numel(),
+                                   ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY:
+            raise CapacityError(st, "sfc_query_retry", int(total.value))
+        _check(st, "sfc_query_retry")
+        return int(total.value)
 
     def query_sets(self, q: torch.Tensor, delta: torch.Tensor, qset: torch.Tensor,
                    out_ids: torch.Tensor | None = None, out_offsets: torch.Tensor | None = None):
@@ -345,8 +370,8 @@ class Index:
         args = (self.handle, _ptr(q), _ptr(delta), _ptr(qset), m, _ptr(offsets))
         st = lib().sfc_query_sets(*args, _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
         if st == SFC_ERR_CAPACITY and not cap_given:
-            out_ids = torch.empty(max(int(total.value), 1), dtype=torch.int32, device=self.device)
-            st = lib().sfc_query_sets(*args, _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+            out_ids, st = self._retry(offsets, total, lambda o, t: lib().sfc_query_sets(
+                *args, _ptr(o), o.numel(), ctypes.byref(t)))
         if st == SFC_ERR_CAPACITY:
             raise CapacityError(st, "sfc_query_sets", int(total.value))
         _check(st, "sfc_query_sets")
@@ -370,8 +395,8 @@ class Index:
         args = (self.handle, _ptr(q), _ptr(delta), _ptr(qepoch), m, _ptr(offsets))
         st = lib().sfc_query_epochs(*args, _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
         if st == SFC_ERR_CAPACITY and not cap_given:
-            out_ids = torch.empty(max(int(total.value), 1), dtype=torch.int32, device=self.device)
-            st = lib().sfc_query_epochs(*args, _ptr(out_ids), out_ids.numel(), ctypes.byref(total))
+            out_ids, st = self._retry(offsets, total, lambda o, t: lib().sfc_query_epochs(
+                *args, _ptr(o), o.numel(), ctypes.byref(t)))
         if st == SFC_ERR_CAPACITY:
             raise CapacityError(st, "sfc_query_epochs", int(total.value))
         _check(st, "sfc_query_epochs")

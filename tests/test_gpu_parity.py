@@ -216,3 +216,58 @@ def test_uniform_fixed_radius_workload():
     wl = workload.uniform_fixed_radius(n=1 << 16, m=10_000, curve=MORTON)
     _, ref_off = check_query(wl.points, wl.queries, wl.delta, MORTON)
     assert abs(ref_off[-1] / 10_000 - 9.941) < 0.25
+
+
+@pytest.mark.parametrize("refine", [False, True])
+def test_capacity_keeps_ids_and_retry_writes_only(refine):
+    rng = np.random.default_rng(41)
+    pts = rng.random((50_000, 2))
+    qs = rng.random((3000, 2))
+    ds = np.full(3000, 0.02)
+    ref_off, ref_ids = oracle.query(oracle.build(pts, HILBERT), qs, ds, HILBERT)
+    idx = sfc.Index(dev(pts), HILBERT, refine=refine)
+    q, d = dev(qs), dev(ds)
+    offsets = torch.empty(3001, dtype=torch.int64, device=DEV)
+    small = torch.full((100,), 0x7FFFFFFF, dtype=torch.int32, device=DEV)
+    with pytest.raises(sfc.CapacityError) as ei:
+        idx.query(q, d, out_ids=small, out_offsets=offsets)
+    assert ei.value.total == len(ref_ids)
+    assert bool((small == 0x7FFFFFFF).all())                      # ids untouched
+    assert np.array_equal(offsets.cpu().numpy().view(np.uint64), ref_off)
+    with pytest.raises(sfc.CapacityError):                          # still too small
+        idx.query_retry(offsets, small)
+    big = torch.empty(len(ref_ids), dtype=torch.int32, device=DEV)
+    assert idx.query_retry(offsets, big) == len(ref_ids)
+    assert np.array_equal(big.cpu().numpy().view(np.uint32), ref_ids)
+    with pytest.raises(sfc.SfcError):                               # nothing kept any more
+        idx.query_retry(offsets, big)
+    # Any later query drops the kept batch; the binding then reruns instead.
+    with pytest.raises(sfc.CapacityError):
+        idx.query(q, d, out_ids=small, out_offsets=offsets)
+    idx.query(q[:10], d[:10])
+    with pytest.raises(sfc.SfcError):
+        idx.query_retry(offsets, big)
+    off2, ids2 = idx.query(q, d)                                    # binding's own retry
+    assert np.array_equal(ids2.cpu().numpy().view(np.uint32), ref_ids)
+
+
+def test_capacity_many_chunks_writes_prefix_and_reruns():
+    rng = np.random.default_rng(42)
+    pts = rng.random((40_000, 2))
+    qs = rng.random((2000, 2))
+    ds = np.full(2000, 0.03)
+    ref_off, ref_ids = oracle.query(oracle.build(pts, MORTON), qs, ds, MORTON)
+    try:
+        sfc.debug_chunk_tiles(2)
+        idx = sfc.Index(dev(pts), MORTON)
+        small = torch.full((50,), -1, dtype=torch.int32, device=DEV)
+        offsets = torch.empty(2001, dtype=torch.int64, device=DEV)
+        with pytest.raises(sfc.CapacityError):
+            idx.query(dev(qs), dev(ds), out_ids=small, out_offsets=offsets)
+        assert np.array_equal(small.cpu().numpy().view(np.uint32), ref_ids[:50])
+        with pytest.raises(sfc.SfcError):
+            idx.query_retry(offsets, torch.empty(len(ref_ids), dtype=torch.int32, device=DEV))
+        off, ids = idx.query(dev(qs), dev(ds), ids_cap=None)
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), ref_ids)
+    finally:
+        sfc.debug_chunk_tiles(0)
