@@ -223,23 +223,29 @@ def serving_bench(args, sfc, workload, torch):
     out = {"workload": trace.name, "curve": "morton", "search": "learned",
            "mix": "40% query, 40% insert, 20% erase batches of 2^U[10,16]"}
 
-    def one(rate):
+    def one(rate, slots):
         idx = sfc.Index(init, sfc.MORTON, search=sfc.LEARNED, refine=True)
         torch.cuda.synchronize()
-        run = serving.serve(idx, trace, pools, rate=rate, out_ids=out_ids)
+        run = serving.serve(idx, trace, pools, rate=rate, out_ids=out_ids, slots=slots,
+                            slot_queries=1 << 20, slot_ids=1 << 27, slot_rows=1 << 24)
         s = serving.summarize(trace, run)
         s["compactions"] = idx.update_info()["compactions"]
         idx.close()
         return s
 
-    sat = one(float("inf"))
-    out["saturation"] = sat
-    for f in (0.5, 0.8, 0.95):
-        rate = f * sat["requests_per_s"]
-        s = one(rate)
-        s["offered_requests_per_s"] = rate
-        out[f"load_{f}"] = s
-        log(f"serving at {f} of saturation: p50 {s['p50_ms']:.2f} ms, p99 {s['p99_ms']:.2f} ms")
+    # Each tick answered before the next (slots 0), and query batches queued
+    # into three slots while the next arrivals are admitted (slots 3).
+    for mode, slots in (("sync", 0), ("queued", 3)):
+        sat = one(float("inf"), slots)
+        res = {"saturation": sat}
+        for f in (0.5, 0.8, 0.95):
+            rate = f * sat["requests_per_s"]
+            s = one(rate, slots)
+            s["offered_requests_per_s"] = rate
+            res[f"load_{f}"] = s
+            log(f"serving ({mode}) at {f} of saturation: p50 {s['p50_ms']:.2f} ms, "
+                f"p99 {s['p99_ms']:.2f} ms")
+        out[mode] = res
     return out
 
 

@@ -189,6 +189,23 @@ typedef struct {
 sfc_status sfc_update_info_get(const sfc_index* h, sfc_update_info* out);
 
 /*
+ * A query batch queued on h's stream without waiting for it (for serving
+ * loops that admit more work while a batch runs).  q, delta, qepoch (NULL:
+ * the current epoch), offsets and ids as in sfc_query_epochs; the candidate
+ * rows are bounded by max_rows as in sfc_graph_query.  When the stream
+ * reaches the end of the batch, *flags (device uint32) holds its status bits:
+ * 0 = complete; 2 = an invalid query or epoch; 16 = more rows than max_rows
+ * (offsets and ids unspecified; rerun with a larger bound); 8 = internal
+ * error.  offsets[m] is the total; ids beyond ids_cap are not written (compare
+ * the total with ids_cap).  The caller keeps every buffer alive until then.
+ * Batches and updates issued later on h are ordered after it (same stream).
+ * SFC_ERR_UNSUPPORTED for indexes of point sets.
+ */
+sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
+                           const uint32_t* qepoch, uint64_t m, uint64_t max_rows,
+                           uint64_t* offsets, uint32_t* ids, uint64_t ids_cap, uint32_t* flags);
+
+/*
  * Write pass of the last sfc_query_batch / sfc_query_sets / sfc_query_epochs
  * call on h that returned SFC_ERR_CAPACITY with its test results kept:
  * offsets (device, m+1) and ids (device, ids_cap) as in that call.  Valid

@@ -728,6 +728,35 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta, u
   return query_impl(h, q, delta, nullptr, m, offsets, ids, ids_cap, total_out);
 }
 
+sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
+                           const uint32_t* qepoch, uint64_t m, uint64_t max_rows,
+                           uint64_t* offsets, uint32_t* ids, uint64_t ids_cap, uint32_t* flags) {
+  if (!h || !offsets || !flags || m == 0 || !q || !delta || (ids_cap > 0 && !ids))
+    return SFC_ERR_INVALID;
+  if (m > (1ull << 36) || max_rows == 0 || max_rows > (1ull << 40)) return SFC_ERR_INVALID;
+  if (h->n_sets) return SFC_ERR_UNSUPPORTED;
+  h->pending.valid = false;
+  // Growing a scratch buffer waits for the work queued on it first.
+  sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
+  if (st == SFC_OK) st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(max_rows));
+  if (st != SFC_OK) return st;
+  sfc::QueryScratch qs{};
+  sfc::query_scratch_carve(h->ws, m, &qs);
+  const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted;
+  const sfc::LearnedView lv = h->larr.view();
+  sfc::EpochView ev;
+  const bool filtered = epoch_view(h, qepoch, &ev);
+  SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
+                             h->refine_min, learned ? &lv : nullptr, nullptr, nullptr, 0, qs,
+                             nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
+  if (qepoch)
+    SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs.counters + 2, h->stream));
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, max_rows, true, h->cws,
+                              offsets, ids, ids_cap, h->stream, filtered ? &ev : nullptr));
+  SFC_TRY(hipMemcpyAsync(flags, qs.counters + 2, 4, hipMemcpyDeviceToDevice, h->stream));
+  return SFC_OK;
+}
+
 sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
                            uint64_t* total_out) {
   if (!h || !offsets || !total_out || (ids_cap > 0 && !ids)) return SFC_ERR_INVALID;

@@ -5,10 +5,21 @@ the requests that have arrived (at most ``max_tick`` of them), applies the
 inserts and erases one by one in stream order, and answers the queries of
 all of them in one batch, each query at the epoch it was admitted at (the
 epoch after the updates that arrived before it), so that batching never
-changes an answer.  After the batch every older epoch is retired, which
-lets the index drop the tombstones no query can see any more.  All GPU work
-runs in the library; this loop only slices the request pools and keeps the
-clock.
+changes an answer.  Epochs older than every query still running are
+retired, which lets the index drop the tombstones no query can see any
+more.  All GPU work runs in the library; this loop only slices the request
+pools and keeps the clock.
+
+Two modes:
+  * ``slots = 0``: each tick's query batch is answered before the next tick
+    starts (sfc_query_epochs).
+  * ``slots = k > 0``: query batches are queued without waiting
+    (sfc_query_async) into k preallocated output slots; while they run, the
+    loop admits the next arrivals and queues their work behind them, and a
+    batch's requests complete when its slot's event has passed.  A tick with
+    queries waits only for a free slot (admission as slots free up).  A batch
+    that outgrew its slot is answered again synchronously into larger
+    buffers.
 """
 from __future__ import annotations
 
@@ -40,6 +51,26 @@ class Pools:
 
 
 @dataclasses.dataclass
+class Slot:
+    """Preallocated outputs of one queued query batch."""
+    offsets: torch.Tensor
+    ids: torch.Tensor
+    flags: torch.Tensor
+    event: torch.cuda.Event
+    max_rows: int
+    busy: bool = False
+    members: list = dataclasses.field(default_factory=list)   # (request, epoch, size)
+    batch: tuple = ()                                           # (q, delta, epochs)
+
+
+def make_slots(k: int, device, max_queries: int, max_ids: int, max_rows: int) -> list:
+    return [Slot(torch.empty(max_queries + 1, dtype=torch.int64, device=device),
+                 torch.empty(max_ids, dtype=torch.int32, device=device),
+                 torch.zeros(1, dtype=torch.int32, device=device),
+                 torch.cuda.Event(enable_timing=True), max_rows) for _ in range(k)]
+
+
+@dataclasses.dataclass
 class Run:
     arrival: np.ndarray       # seconds from the start
     done: np.ndarray          # completion, seconds from the start
@@ -53,9 +84,14 @@ class Run:
 
 
 def serve(index: sfc.Index, trace: ServingTrace, pools: Pools, rate: float = float("inf"),
-          max_tick: int = 16, record: bool = False, out_ids: torch.Tensor | None = None) -> Run:
+          max_tick: int = 16, record: bool = False, out_ids: torch.Tensor | None = None,
+          slots: int = 0, slot_queries: int = 1 << 20, slot_ids: int = 1 << 26,
+          slot_rows: int = 1 << 24) -> Run:
     """Runs the trace with Poisson arrivals at ``rate`` requests/s (inf: all
     at time 0) and returns arrival and completion times per request."""
+    if slots > 0:
+        return _serve_async(index, trace, pools, rate, max_tick, record, slots, slot_queries,
+                            slot_ids, slot_rows)
     R = len(trace.kind)
     arrival = np.zeros(R) if not np.isfinite(rate) else np.cumsum(trace.gaps) / rate
     done = np.zeros(R)
@@ -124,6 +160,132 @@ def serve(index: sfc.Index, trace: ServingTrace, pools: Pools, rate: float = flo
         index.retire(epoch)
         ticks += 1
         i = j
+    seconds = time.perf_counter() - t0
+    return Run(arrival, done, admitted, ticks, seconds, outputs)
+
+
+def _serve_async(index, trace, pools, rate, max_tick, record, nslots, slot_queries, slot_ids,
+                 slot_rows) -> Run:
+    R = len(trace.kind)
+    arrival = np.zeros(R) if not np.isfinite(rate) else np.cumsum(trace.gaps) / rate
+    done = np.zeros(R)
+    admitted = np.full(R, -1, np.int64)
+    outputs = {}
+    index.hold_epochs(True)
+    epoch = index.update_info()["epoch"]
+    dev = pools.queries.device
+    pool = make_slots(nslots, dev, slot_queries, slot_ids, slot_rows)
+    busy = []                      # slots in launch order
+    start = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+
+    def finish(slot: Slot):
+        """The slot's batch has run: check it, record its requests."""
+        slot.event.synchronize()
+        t_done = start.elapsed_time(slot.event) * 1e-3
+        m = sum(k for _, _, k in slot.members)
+        flags = int(slot.flags.item())
+        total = int(slot.offsets[m].item()) if flags == 0 else -1
+        if flags != 0 or total > slot.ids.numel():
+            if flags & ~16:
+                raise sfc.SfcError(sfc.SFC_ERR_INVALID, f"query batch flags {flags}")
+            q, d, e = slot.batch          # outgrew the slot: answer it again, synchronously
+            off, ids = index.query_epochs(q, d, e)
+            t_done = time.perf_counter() - t0
+        else:
+            off, ids = slot.offsets[:m + 1], slot.ids[:total]
+        base = 0
+        if record:
+            off_h = off.cpu().numpy()
+            ids_h = ids.cpu().numpy()
+        for r, e_r, k in slot.members:
+            done[r] = t_done
+            admitted[r] = e_r
+            if record:
+                o = off_h[base:base + k + 1]
+                outputs[r] = (o - o[0], ids_h[o[0]:o[-1]].copy())
+            base += k
+        slot.busy = False
+        slot.members = []
+        slot.batch = ()
+
+    def reap(block: bool):
+        """Completes finished slots in launch order (the oldest first)."""
+        while busy and (block or busy[0].event.query()):
+            finish(busy.pop(0))
+            block = False
+
+    ticks = 0
+    i = 0
+    while i < R:
+        reap(False)
+        now = time.perf_counter() - t0
+        if arrival[i] > now and busy:
+            reap(True)                 # nothing arrived yet: wait for the oldest batch
+            continue
+        if arrival[i] > now:
+            wait = arrival[i] - now
+            if wait > 2e-3:
+                time.sleep(wait - 1e-3)
+            while time.perf_counter() - t0 < arrival[i]:
+                pass
+            now = time.perf_counter() - t0
+        j = int(np.searchsorted(arrival, now, side="right"))
+        j = min(max(j, i + 1), i + max_tick)
+        pending = []
+        for r in range(i, j):
+            a, k = int(trace.start[r]), int(trace.size[r])
+            if trace.kind[r] == QUERY:
+                pending.append((r, epoch, k))
+            elif trace.kind[r] == INSERT:
+                index.insert(pools.inserts[a:a + k], want_ids=False)
+                epoch += 1
+                done[r] = time.perf_counter() - t0
+            else:
+                index.erase(pools.erase_ids[a:a + k])
+                epoch += 1
+                done[r] = time.perf_counter() - t0
+        # an update waits for all queued work, so slots may have finished
+        reap(False)
+        while pending:
+            if len(busy) == nslots:
+                reap(True)             # admission: wait until a slot frees up
+            slot = next(sl for sl in pool if not sl.busy)
+            take, m = [], 0
+            while pending and m + pending[0][2] <= slot_queries:
+                take.append(pending.pop(0))
+                m += take[-1][2]
+            if not take:               # a single request larger than a slot
+                take.append(pending.pop(0))
+                m = take[0][2]
+            qs, ds, es = [], [], []
+            for r, e, k in take:
+                a = int(trace.start[r])
+                qs.append(pools.queries[a:a + k])
+                ds.append(pools.delta[a:a + k])
+                es.append(torch.full((k,), e, dtype=torch.int32, device=dev))
+            q = torch.cat(qs) if len(qs) > 1 else qs[0]
+            d = torch.cat(ds) if len(ds) > 1 else ds[0]
+            e = torch.cat(es) if len(es) > 1 else es[0]
+            slot.members = take
+            slot.batch = (q, d, e)
+            slot.busy = True
+            if m <= slot_queries:
+                index.query_async(q, d, e, slot.max_rows, slot.offsets, slot.ids, slot.flags)
+            else:
+                slot.flags.fill_(16)   # answered synchronously when reaped
+            slot.event.record()
+            busy.append(slot)
+        # retire what no queued or running query can see
+        oldest = min([e for sl in busy for _, e, _ in sl.members], default=epoch)
+        index.retire(oldest)
+        ticks += 1
+        i = j
+    while busy:
+        reap(True)
+    index.retire(epoch)
     seconds = time.perf_counter() - t0
     return Run(arrival, done, admitted, ticks, seconds, outputs)
 

@@ -39,6 +39,7 @@ EXPORTS = [
     "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
+    "sfc_query_async",
 ]
 
 NPARAM = 1153
@@ -189,6 +190,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_learned_route.restype = i32
     L.sfc_query_retry.argtypes = [vp, vp, vp, u64, ctypes.POINTER(u64)]
     L.sfc_query_retry.restype = i32
+    L.sfc_query_async.argtypes = [vp, vp, vp, vp, u64, u64, vp, vp, u64, vp]
+    L.sfc_query_async.restype = i32
     _lib = L
     return L
 
@@ -401,6 +404,20 @@ class Index:
             raise CapacityError(st, "sfc_query_epochs", int(total.value))
         _check(st, "sfc_query_epochs")
         return offsets, out_ids[: int(total.value)]
+
+    def query_async(self, q: torch.Tensor, delta: torch.Tensor, qepoch: torch.Tensor | None,
+                    max_rows: int, out_offsets: torch.Tensor, out_ids: torch.Tensor,
+                    flags: torch.Tensor):
+        """Queues a batch (sfc_query_async) and returns at once; the caller
+        keeps the tensors alive until the stream has passed the batch, then
+        reads flags[0] and out_offsets[-1]."""
+        q = _dev(q, torch.float64, "q")
+        delta = _dev(delta, torch.float64, "delta")
+        if qepoch is not None:
+            qepoch = _dev(qepoch, torch.int32, "qepoch")
+        _check(lib().sfc_query_async(self.handle, _ptr(q), _ptr(delta), _ptr(qepoch), q.shape[0],
+                                     max_rows, _ptr(out_offsets), _ptr(out_ids), out_ids.numel(),
+                                     _ptr(flags)), "sfc_query_async")
 
     def insert(self, xy: torch.Tensor, want_ids: bool = True):
         """Inserts points (k, 2); returns their ids (int32 tensor) or None."""

@@ -21,10 +21,12 @@ def test_batched_and_alone_equal_snapshot_oracle(curve, search):
     pools = serving.Pools.upload(trace, DEV)
     init = torch.as_tensor(trace.initial).to(DEV)
     runs = []
-    for max_tick in (16, 1):
+    for max_tick, slots in ((16, 0), (1, 0), (16, 3)):
         idx = sfc.Index(init, curve, search=search, refine=True)
-        runs.append((idx, serving.serve(idx, trace, pools, max_tick=max_tick, record=True)))
-    mixed, alone = runs[0][1], runs[1][1]
+        runs.append((idx, serving.serve(idx, trace, pools, max_tick=max_tick, record=True,
+                                        slots=slots, slot_queries=1 << 14, slot_ids=1 << 20,
+                                        slot_rows=1 << 16)))
+    mixed, alone, queued = runs[0][1], runs[1][1], runs[2][1]
     assert mixed.ticks < alone.ticks == len(trace.kind)
 
     model = Model(trace.initial, hold=True)    # never retires: keeps every snapshot
@@ -38,10 +40,10 @@ def test_batched_and_alone_equal_snapshot_oracle(curve, search):
         else:
             expect_epoch[r] = model.epoch
     for r, e in expect_epoch.items():
-        assert mixed.admitted[r] == e and alone.admitted[r] == e
+        assert mixed.admitted[r] == e and alone.admitted[r] == e and queued.admitted[r] == e
         a, k = int(trace.start[r]), int(trace.size[r])
         want = model.reference(trace.queries[a:a + k], trace.delta[a:a + k], np.full(k, e), curve)
-        for run in (mixed, alone):
+        for run in (mixed, alone, queued):
             off, ids = run.outputs[r]
             assert np.array_equal(off.view(np.uint64), want[0]), r
             assert np.array_equal(ids.view(np.uint32), want[1]), r
@@ -67,3 +69,17 @@ def test_poisson_arrivals_complete_after_arrival():
     assert (lat > 0).all() and np.all(np.diff(run.arrival) >= 0)
     s = serving.summarize(trace, run)
     assert s["p99_ms"] >= s["p50_ms"] > 0 and s["requests"] == 60
+
+
+def test_queued_batches_that_outgrow_their_slot_are_answered_again():
+    trace = workload.serving_trace(n0=20_000, requests=40, seed=9, log2_size=(6, 10))
+    pools = serving.Pools.upload(trace, DEV)
+    init = torch.as_tensor(trace.initial).to(DEV)
+    ref_idx = sfc.Index(init, MORTON, refine=True)
+    ref = serving.serve(ref_idx, trace, pools, record=True)
+    idx = sfc.Index(init, MORTON, refine=True)
+    run = serving.serve(idx, trace, pools, record=True, slots=2, slot_queries=300,
+                        slot_ids=500, slot_rows=128)
+    for r, (off, ids) in ref.outputs.items():
+        assert np.array_equal(run.outputs[r][0], off) and np.array_equal(run.outputs[r][1], ids)
+    assert (run.latency() > 0).all()
