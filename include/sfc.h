@@ -79,6 +79,11 @@ typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*release)(void* ptr, void* ctx);
   void* alloc_ctx;
+  int early_term; /* 1: keep an occupancy bit for every quadtree node down to
+                     depth 12 (Sec. 2.2 "Early termination"; 2.8 MB) and skip
+                     the cells of cells(Q) that hold no point; rebuilt after
+                     inserts and compactions (an erase leaves a bit set, which
+                     only costs a search).  Same results.  Not with point sets. */
 } sfc_options;
 
 /* Fills *opt with Morton curve, binary search, no refinement, default
@@ -338,8 +343,13 @@ typedef struct {
                            same queries needs max_rows >= this */
   uint64_t candidates;  /* points scanned (sum of index range lengths) */
   uint64_t reported;    /* ids reported */
+  uint64_t pruned;      /* cells skipped by early termination */
 } sfc_query_stats;
 sfc_status sfc_last_query_stats(const sfc_index* h, sfc_query_stats* out);
+/* The early-termination bitmap (device out, at least 699051 uint32 words):
+   bit (4^k - 1)/3 + p is set when a stored key has top 2k bits p (k = 0..12).
+   SFC_ERR_UNSUPPORTED when the index was built without it. */
+sfc_status sfc_occupancy_copy(const sfc_index* h, uint32_t* out, uint64_t words);
 
 /*
  * Learned index (an addition to the paper's method; binary search stays the

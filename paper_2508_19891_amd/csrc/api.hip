@@ -216,6 +216,9 @@ struct sfc_index {
   // point sets (sfc_build_sets)
   uint32_t n_sets = 0;
   uint64_t* set_off = nullptr;     // device, n_sets + 1
+  // early termination: occupancy bits of the quadtree nodes (null: off)
+  uint32_t* occ = nullptr;
+  uint64_t last_pruned = 0;
   // updates (sfc_insert / sfc_erase); ins == null until the first update
   uint32_t* ins = nullptr;         // device, insert epoch per stored entry
   uint32_t* era = nullptr;         // device, erase epoch per stored entry
@@ -265,6 +268,7 @@ bool valid_options(const sfc_options& o) {
   if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT) return false;
   if (o.search != SFC_SEARCH_BINARY && o.search != SFC_SEARCH_LEARNED) return false;
   if (o.refine != 0 && o.refine != 1) return false;
+  if (o.early_term != 0 && o.early_term != 1) return false;
   if ((o.alloc == nullptr) != (o.release == nullptr)) return false;
   return true;
 }
@@ -318,6 +322,8 @@ void release_arrays(sfc_index* h) {
   h->alloc.put(h->spare.era);
   h->alloc.put(h->key_of);
   h->alloc.put(h->upd_word);
+  h->alloc.put(h->occ);
+  h->occ = nullptr;
   h->ins = h->era = nullptr;
   h->spare = sfc::Run{};
   h->spare_cap = 0;
@@ -349,7 +355,7 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
   const sfc::LearnedView lv = h->larr.view();
   SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                             h->refine_min, learned ? &lv : nullptr, qset,
+                             h->refine_min, learned ? &lv : nullptr, h->occ, qset,
                              qset ? h->set_off : nullptr,
                              h->n_sets, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
   if (qepoch)
@@ -365,6 +371,7 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   *total_cand = pin[3];   // counters[4..5]
   h->linfo.endpoints_last = learned ? pin[4] : 0;
   h->linfo.fallbacks_last = learned ? pin[5] : 0;
+  h->last_pruned = pin[6];   // counters[10..11]
   return SFC_OK;
 }
 
@@ -510,6 +517,7 @@ void sfc_default_options(sfc_options* opt) {
   opt->curve = SFC_CURVE_MORTON;
   opt->search = SFC_SEARCH_BINARY;
   opt->learn_steps = -1;
+  opt->early_term = 0;
 }
 
 const char* sfc_status_string(sfc_status s) {
@@ -625,6 +633,18 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
       return st;
     }
   }
+  if (o.early_term) {
+    h->occ = (uint32_t*)h->alloc.get(sfc::kOccWords * 4);
+    hipError_t e = h->occ ? sfc::build_occupancy(h->keys, h->n, h->occ, h->stream)
+                          : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      release_arrays(h);
+      delete h;
+      return from_hip(e);
+    }
+  }
   if (h->search == SFC_SEARCH_LEARNED && n >= 2 && !set_off_host) {
     sfc_status st = fit_learned(h, -1);
     if (st != SFC_OK) {
@@ -650,7 +670,7 @@ sfc_status sfc_build_sets(const double* xy, const uint64_t* set_off, uint32_t n_
   if (!set_off || n_sets < 1 || n_sets > 65536 || set_off[0] != 0) return SFC_ERR_INVALID;
   for (uint32_t i = 0; i < n_sets; ++i)
     if (set_off[i + 1] < set_off[i]) return SFC_ERR_INVALID;
-  if (opt && opt->search == SFC_SEARCH_LEARNED) return SFC_ERR_UNSUPPORTED;
+  if (opt && (opt->search == SFC_SEARCH_LEARNED || opt->early_term)) return SFC_ERR_UNSUPPORTED;
   return build_impl(xy, set_off[n_sets], set_off, n_sets, opt, out);
 }
 
@@ -705,6 +725,7 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
   h->last.candidates = total_cand;
   h->last.reported = total;
   h->last.rows = total_rows;
+  h->last.pruned = m > 0 ? h->last_pruned : 0;
   *total_out = total;
   if (total > ids_cap && m > 0 && sfc::compact_single_chunk(total_rows)) {
     sfc_index::Pending& p = h->pending;
@@ -747,7 +768,8 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
   sfc::EpochView ev;
   const bool filtered = epoch_view(h, qepoch, &ev);
   SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                             h->refine_min, learned ? &lv : nullptr, nullptr, nullptr, 0, qs,
+                             h->refine_min, learned ? &lv : nullptr, h->occ, nullptr, nullptr, 0,
+                             qs,
                              nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs.counters + 2, h->stream));
@@ -821,6 +843,15 @@ sfc_status sfc_index_copy(const sfc_index* h, uint64_t* keys, uint32_t* ids, dou
   if (keys) SFC_TRY(hipMemcpyAsync(keys, h->keys, h->n * 8, hipMemcpyDeviceToDevice, h->stream));
   if (ids) SFC_TRY(hipMemcpyAsync(ids, h->ids, h->n * 4, hipMemcpyDeviceToDevice, h->stream));
   if (xy) SFC_TRY(hipMemcpyAsync(xy, h->xy, h->n * 16, hipMemcpyDeviceToDevice, h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  return SFC_OK;
+}
+
+sfc_status sfc_occupancy_copy(const sfc_index* h, uint32_t* out, uint64_t words) {
+  if (!h || (words > 0 && !out)) return SFC_ERR_INVALID;
+  if (!h->occ) return SFC_ERR_UNSUPPORTED;
+  if (words < sfc::kOccWords) return SFC_ERR_CAPACITY;
+  SFC_TRY(hipMemcpyAsync(out, h->occ, sfc::kOccWords * 4, hipMemcpyDeviceToDevice, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
   return SFC_OK;
 }
@@ -1002,6 +1033,7 @@ sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out) {
     if (e == hipSuccess)
       e = sfc::sort_build(xy, h->n, h->curve, h->keys, h->ids, h->xy, g->scratch, g->err, s,
                           h->set_off, h->n_sets);
+    if (e == hipSuccess && h->occ) e = sfc::build_occupancy(h->keys, h->n, h->occ, s);
     return e;
   });
   if (st != SFC_OK) {
@@ -1040,7 +1072,7 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   const bool filtered = epoch_view(h, nullptr, &ev);
   sfc_status st = graph_capture(g, [&](hipStream_t s) {
     hipError_t e = sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                                      h->refine_min, learned ? &lv : nullptr, qset,
+                                      h->refine_min, learned ? &lv : nullptr, h->occ, qset,
                                       qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr,
                                       nullptr, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess)
@@ -1377,6 +1409,7 @@ sfc_status compact_now(sfc_index* h) {
   swap_runs(h);
   h->n = keep;
   h->dead -= drop;
+  if (h->occ) SFC_TRY(sfc::build_occupancy(h->keys, h->n, h->occ, h->stream));
   std::vector<std::pair<uint32_t, uint64_t>> rest;
   for (const auto& t : h->tombs)
     if (t.first > h->oldest) rest.push_back(t);
@@ -1439,6 +1472,7 @@ sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_
   h->next_id += (uint32_t)k;
   h->epoch = ep;
   h->max_ins = ep;
+  if (h->occ) SFC_TRY(sfc::build_occupancy(h->keys, h->n, h->occ, h->stream));
   if (!h->hold) h->oldest = ep;
   ++h->generation;
   ++h->merges;

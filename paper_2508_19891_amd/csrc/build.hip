@@ -282,6 +282,26 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
   }
 }
 
+// Occupancy bits of every quadtree node down to depth kOccDepth: point i
+// marks the depth-k node of its key for each k where its prefix differs from
+// point i-1's (the keys are sorted), so each occupied node is marked once.
+__global__ __launch_bounds__(256) void occupancy_mark(const uint64_t* __restrict__ keys, uint64_t n,
+                                                      uint32_t* occ) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const uint64_t k = keys[i];
+    const uint64_t prev = i > 0 ? keys[i - 1] : ~k;
+    for (int dep = 0; dep <= kOccDepth; ++dep) {
+      const int sh = 64 - 2 * dep;
+      const uint64_t p = dep == 0 ? 0 : k >> sh;
+      const bool first = i == 0 || (dep > 0 && (prev >> sh) != p);
+      if (!first) continue;
+      const uint64_t node = occ_level_offset(dep) + p;
+      atomicOr(occ + (node >> 5), 1u << (node & 31));
+    }
+  }
+}
+
 __global__ void gather_points(const uint32_t* __restrict__ ids, const double2* __restrict__ xy,
                               double2* __restrict__ out, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -455,6 +475,16 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     vin = vout;
   }
   return hipSuccess;
+}
+
+hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipStream_t s) {
+  hipError_t e = fill_u32(occ, 0, kOccWords, s);
+  if (e != hipSuccess || n == 0) return e;
+  ProfScope ps("occupancy_mark", s);
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  occupancy_mark<<<(uint32_t)blocks, 256, 0, s>>>(keys, n, occ);
+  return hipGetLastError();
 }
 
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,

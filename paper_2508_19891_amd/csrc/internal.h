@@ -12,6 +12,16 @@ namespace sfc {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Occupancy bitmap of the quadtree nodes of depths 0..kOccDepth (early
+// termination): depth k starts at bit (4^k - 1) / 3, node p of depth k (the
+// top 2k key bits) at that offset + p.
+constexpr int kOccDepth = 12;
+__host__ __device__ constexpr uint64_t occ_level_offset(int k) {
+  return ((1ull << (2 * k)) - 1) / 3;
+}
+constexpr uint64_t kOccBits = occ_level_offset(kOccDepth + 1);
+constexpr uint64_t kOccWords = (kOccBits + 31) / 32;
+
 // Launch shapes chosen by the autotuner, per size bucket (floor(log2 size)).
 // tuned(op, size) returns -1 when the bucket has no entry.
 enum TuneOp { kTuneSortItems = 0, kTuneTestShape = 1 };
@@ -34,6 +44,8 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
                       hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0);
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,
                          hipStream_t s);
+// Early-termination occupancy bitmap (kOccWords words) of n sorted keys.
+hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipStream_t s);
 
 // ---- device-wide scan (scan.hip) ----
 // out[i] = carry + sum(in[0..i)), out[count] = carry + sum(in); carry_in is a
@@ -65,11 +77,13 @@ size_t compact_scratch_bytes(uint64_t total_rows);
 // Ranges and searches per query slot, then the scan of candidate counts into
 // segment offsets; optionally records the ranges (dbg_* may be null).
 // lview non-null: searches go through the learned index.
+// occ non-null: cells whose occupancy bit is clear are skipped (early
+// termination; not applied when the ranges are recorded for inspection).
 // qset/set_off non-null: query j searches only set qset[j] (positions
 // [set_off[s], set_off[s+1]) of the sorted arrays).
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min,
-                         const LearnedView* lview, const uint32_t* qset,
+                         const LearnedView* lview, const uint32_t* occ, const uint32_t* qset,
                          const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s);

@@ -75,17 +75,37 @@ __device__ __forceinline__ uint64_t cell_key(const uint16_t* lut, uint32_t x, ui
   return CURVE == SFC_CURVE_HILBERT ? hilbert_key_lut(lut, x, y) : morton_key(x, y);
 }
 
+// Early termination (Sec. 2.2, "Early termination"): one occupancy bit per
+// quadtree node down to depth kOccDepth, nodes of depth k numbered by the
+// top 2k bits of their keys (the prefix property of the curve) after the
+// (4^k - 1) / 3 nodes of the shallower levels.  A level-L cell is a node of
+// depth 32 - L; a deeper cell is checked through its depth-kOccDepth
+// ancestor.  A cell whose bit is clear holds no point and is skipped, so the
+// reported set never changes.
+__device__ __forceinline__ bool cell_occupied(const uint32_t* __restrict__ occ, int L,
+                                              uint64_t key) {
+  const int k = 32 - L;
+  const int kk = k < kOccDepth ? k : kOccDepth;
+  const uint64_t node = occ_level_offset(kk) + (kk == 0 ? 0 : key >> (64 - 2 * kk));
+  return (occ[node >> 5] >> (node & 31)) & 1u;
+}
+
 // Merged key intervals of cells(Q) for query (qx, qy, d); returns their
-// number (0..4), ascending and non-adjacent.
+// number (0..4), ascending and non-adjacent.  occ (may be null): skip cells
+// that hold no point (counted in *pruned).
 template <int CURVE>
 __device__ int query_ranges(const uint16_t* lut, double qx, double qy, double d, uint64_t lo[4],
-                            uint64_t hi[4]) {
+                            uint64_t hi[4], const uint32_t* occ, uint32_t* pruned) {
   int64_t lx, hx, ly, hy;
   if (!axis_box(qx, d, lx, hx) || !axis_box(qy, d, ly, hy)) return 0;
   const uint64_t sx = (uint64_t)(hx - lx + 1), sy = (uint64_t)(hy - ly + 1);
   const uint64_t side = sx > sy ? sx : sy;
   const int L = side <= 1 ? 0 : 64 - __clzll(side - 1);   // ceil(log2 side)
   if (L >= 32) {
+    if (occ && !cell_occupied(occ, 32, 0)) {
+      ++*pruned;
+      return 0;
+    }
     lo[0] = 0;
     hi[0] = ~0ull;
     return 1;
@@ -97,6 +117,10 @@ __device__ int query_ranges(const uint16_t* lut, double qx, double qy, double d,
   for (uint32_t cx = cx0; cx <= cx1; ++cx) {
     for (uint32_t cy = cy0; cy <= cy1; ++cy) {
       const uint64_t key = cell_key<CURVE>(lut, cx << L, cy << L) & ~span;
+      if (occ && !cell_occupied(occ, L, key)) {
+        ++*pruned;
+        continue;
+      }
       lo[k] = key;
       hi[k] = key | span;
       ++k;
@@ -162,7 +186,7 @@ __device__ __forceinline__ void search_pair(const uint64_t* __restrict__ keys, u
 template <int CURVE>
 __device__ int query_cells(const uint16_t* lut, double qx, double qy, double d, uint64_t lo[4],
                            uint64_t hi[4], uint32_t cx[4], uint32_t cy[4], int* Lout,
-                           int64_t box[4]) {
+                           int64_t box[4], const uint32_t* occ, uint32_t* pruned) {
   int64_t lx, hx, ly, hy;
   if (!axis_box(qx, d, lx, hx) || !axis_box(qy, d, ly, hy)) return 0;
   box[0] = lx;
@@ -174,6 +198,10 @@ __device__ int query_cells(const uint16_t* lut, double qx, double qy, double d, 
   const int L = side <= 1 ? 0 : 64 - __clzll(side - 1);
   *Lout = L;
   if (L >= 32) {
+    if (occ && !cell_occupied(occ, 32, 0)) {
+      ++*pruned;
+      return 0;
+    }
     lo[0] = 0;
     hi[0] = ~0ull;
     cx[0] = cy[0] = 0;
@@ -184,6 +212,10 @@ __device__ int query_cells(const uint16_t* lut, double qx, double qy, double d, 
   for (uint32_t x = (uint32_t)(lx >> L); x <= (uint32_t)(hx >> L); ++x) {
     for (uint32_t y = (uint32_t)(ly >> L); y <= (uint32_t)(hy >> L); ++y) {
       const uint64_t key = cell_key<CURVE>(lut, x << L, y << L) & ~span;
+      if (occ && !cell_occupied(occ, L, key)) {
+        ++*pruned;
+        continue;
+      }
       int j = k++;
       for (; j > 0 && lo[j - 1] > key; --j) {
         lo[j] = lo[j - 1];
@@ -244,7 +276,7 @@ template <int CURVE, bool REFINE, bool LEARNED>
 __global__ __launch_bounds__(256) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, uint32_t refine_min,
-    const uint32_t* __restrict__ qset,
+    const uint32_t* __restrict__ occ, const uint32_t* __restrict__ qset,
     const uint64_t* __restrict__ set_off, uint32_t n_sets, uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
     uint64_t* __restrict__ dbg_lo, uint64_t* __restrict__ dbg_hi, uint64_t* __restrict__ dbg_b,
@@ -260,7 +292,7 @@ __global__ __launch_bounds__(256) void ranges_search(
   uint64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0, klo = 0, khi = 0;
   int nr = 0;
   bool bad = false;
-  uint32_t fb = 0, ends = 0;
+  uint32_t fb = 0, ends = 0, pruned = 0;
   // With point sets, a query searches only its own set's keys: positions
   // [base, base + nn) of the sorted arrays.
   uint64_t base = 0, nn = n;
@@ -282,7 +314,9 @@ __global__ __launch_bounds__(256) void ranges_search(
       bad = true;
     } else if (!REFINE) {
       uint64_t lo[4], hi[4];
-      nr = query_ranges<CURVE>(lut, qq.x, qq.y, d, lo, hi);
+      uint32_t pr = 0;
+      nr = query_ranges<CURVE>(lut, qq.x, qq.y, d, lo, hi, occ, &pr);
+      if (r == 0) pruned = pr;
       if (r < nr) {
         klo = lo[r];
         khi = hi[r];
@@ -296,7 +330,9 @@ __global__ __launch_bounds__(256) void ranges_search(
       uint32_t cx[4], cy[4];
       int64_t box[4];
       int L = 0;
-      nr = query_cells<CURVE>(lut, qq.x, qq.y, d, lo, hi, cx, cy, &L, box);
+      uint32_t pr = 0;
+      nr = query_cells<CURVE>(lut, qq.x, qq.y, d, lo, hi, cx, cy, &L, box, occ, &pr);
+      if (r == 0) pruned = pr;
       if (r < nr) {
         find_range<LEARNED>(kseg, nn, lv, lo[r], hi[r], b0, e0, fb);
         b0 += base;
@@ -348,12 +384,13 @@ __global__ __launch_bounds__(256) void ranges_search(
   // Candidates (and learned-index endpoints and fallbacks) of the block, for
   // the statistics: one device atomic per counter and block (atomics on one
   // address from every wave of the grid serialise).
-  __shared__ unsigned long long s_stat[3][4];
+  __shared__ unsigned long long s_stat[4][4];
   uint64_t wc = (e0 - b0) + (e1 - b1);
-  uint32_t wf = fb, we = ends;
+  uint32_t wf = fb, we = ends, wp = pruned;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     wc += __shfl_xor(wc, o, 64);
+    wp += __shfl_xor(wp, o, 64);
     if (LEARNED) {
       wf += __shfl_xor(wf, o, 64);
       we += __shfl_xor(we, o, 64);
@@ -364,9 +401,10 @@ __global__ __launch_bounds__(256) void ranges_search(
     s_stat[0][wv] = wc;
     s_stat[1][wv] = we;
     s_stat[2][wv] = wf;
+    s_stat[3][wv] = wp;
   }
   __syncthreads();
-  if (threadIdx.x < 3 && (threadIdx.x == 0 || LEARNED)) {
+  if (threadIdx.x < 4 && (threadIdx.x == 0 || threadIdx.x == 3 || LEARNED)) {
     const unsigned long long t = s_stat[threadIdx.x][0] + s_stat[threadIdx.x][1] +
                                  s_stat[threadIdx.x][2] + s_stat[threadIdx.x][3];
     if (t) atomicAdd(cand_total + threadIdx.x, t);
@@ -702,7 +740,7 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min,
-                         const LearnedView* lview, const uint32_t* qset,
+                         const LearnedView* lview, const uint32_t* occ, const uint32_t* qset,
                          const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
                          uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                          uint32_t* dbg_nr, hipStream_t s) {
@@ -719,7 +757,8 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
     ProfScope ps(learned ? "ranges_learned" : "ranges_search", s);
 #define SFC_RANGES(C, R, L)                                                                  \
   ranges_search<C, R, L><<<blocks, 256, 0, s>>>(                                              \
-      (const double2*)q, delta, m, keys, n, lv, refine_min, qset, set_off,                   \
+      (const double2*)q, delta, m, keys, n, lv, refine_min, dbg_lo ? nullptr : occ, qset,    \
+      set_off,                                                                                \
       n_sets, qs.slot_begin,                                                                  \
       qs.slot_count, qs.slot_rows, qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr)
 #define SFC_RANGES_C(C)                         \

@@ -39,7 +39,7 @@ EXPORTS = [
     "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
-    "sfc_query_async",
+    "sfc_query_async", "sfc_occupancy_copy",
 ]
 
 NPARAM = 1153
@@ -71,6 +71,7 @@ class Options(ctypes.Structure):
         ("alloc", ctypes.c_void_p),
         ("release", ctypes.c_void_p),
         ("alloc_ctx", ctypes.c_void_p),
+        ("early_term", ctypes.c_int),
     ]
 
 
@@ -86,7 +87,8 @@ class LearnedInfo(ctypes.Structure):
 
 class QueryStats(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_uint64), ("rows", ctypes.c_uint64),
-                ("candidates", ctypes.c_uint64), ("reported", ctypes.c_uint64)]
+                ("candidates", ctypes.c_uint64), ("reported", ctypes.c_uint64),
+                ("pruned", ctypes.c_uint64)]
 
 
 class UpdateInfo(ctypes.Structure):
@@ -192,6 +194,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_query_retry.restype = i32
     L.sfc_query_async.argtypes = [vp, vp, vp, vp, u64, u64, vp, vp, u64, vp]
     L.sfc_query_async.restype = i32
+    L.sfc_occupancy_copy.argtypes = [vp, vp, u64]
+    L.sfc_occupancy_copy.restype = i32
     _lib = L
     return L
 
@@ -243,7 +247,8 @@ class Index:
     """An index built by sfc_build; freed by close() or on garbage collection."""
 
     def __init__(self, xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,
-                 refine: bool = False, learn_steps: int = -1, set_off=None):
+                 refine: bool = False, learn_steps: int = -1, set_off=None,
+                 early_term: bool = False):
         """set_off (host sequence of n_sets + 1 offsets): build independent
         point sets with sfc_build_sets; query them with query_sets."""
         xy = _dev(xy, torch.float64, "xy")
@@ -256,6 +261,7 @@ class Index:
         opt.search = search
         opt.refine = 1 if refine else 0
         opt.learn_steps = learn_steps
+        opt.early_term = 1 if early_term else 0
         opt.stream = current_stream_handle()
         h = ctypes.c_void_p()
         if set_off is None:
@@ -419,6 +425,13 @@ class Index:
                                      max_rows, _ptr(out_offsets), _ptr(out_ids), out_ids.numel(),
                                      _ptr(flags)), "sfc_query_async")
 
+    def occupancy(self) -> torch.Tensor:
+        """The early-termination bitmap (int32 words)."""
+        out = torch.empty(699051, dtype=torch.int32, device=self.device)
+        _check(lib().sfc_occupancy_copy(self.handle, _ptr(out), out.numel()),
+               "sfc_occupancy_copy")
+        return out
+
     def insert(self, xy: torch.Tensor, want_ids: bool = True):
         """Inserts points (k, 2); returns their ids (int32 tensor) or None."""
         xy = _dev(xy, torch.float64, "xy")
@@ -500,7 +513,7 @@ class Index:
         s = QueryStats()
         _check(lib().sfc_last_query_stats(self.handle, ctypes.byref(s)), "sfc_last_query_stats")
         return {"queries": s.queries, "rows": s.rows, "candidates": s.candidates,
-                "reported": s.reported}
+                "reported": s.reported, "pruned": s.pruned}
 
 
 class Graph:
