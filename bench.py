@@ -208,6 +208,47 @@ def learned_large_bench(args, sfc, workload, torch):
     return out
 
 
+def early_term_bench(args, sfc, workload, torch, pts_c2):
+    """Sparse queries, where early termination pays: the bench's clustered
+    2^24 points (Hilbert) with 2^20 uniform queries aimed at one report per
+    query at unit density (most land in the sparse background and report
+    nothing); query batches over one built index with and without the
+    occupancy bits."""
+    dev = torch.device("cuda:0")
+    n = pts_c2.shape[0]
+    m = 1 << 20
+    qh = workload.uniform_points(m, 7007)
+    q = torch.as_tensor(qh).to(dev)
+    d = torch.full((m,), workload.radius_for_count(1.0, n), dtype=torch.float64, device=dev)
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    out = {"workload": f"clustered_n{n}_hilbert_uniformq_m{m}_c1"}
+    for name, et in (("plain", False), ("early_term", True)):
+        idx = sfc.Index(pts_c2, sfc.HILBERT, refine=True, early_term=et)
+        _, ids0 = idx.query(q, d)
+        out_ids = torch.empty(ids0.numel() + 1024, dtype=torch.int32, device=dev)
+        rep = int(ids0.numel())
+        for _ in range(max(1, args.warmup)):
+            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
+        torch.cuda.synchronize()
+        sfc.profile_reset()
+        sfc.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        sfc.profile_enable(False)
+        st = idx.last_stats()
+        out[name] = {"ms_per_batch": ms, "queries_per_s": m / (ms * 1e-3), "reported": rep,
+                     "candidates": st["candidates"], "cells_pruned": st["pruned"],
+                     "kernels_ms_per_batch": {k: v[1] / args.steps
+                                              for k, v in sfc.profile_read().items()}}
+        idx.close()
+    assert out["plain"]["reported"] == out["early_term"]["reported"]
+    out["speedup_batch"] = out["plain"]["ms_per_batch"] / out["early_term"]["ms_per_batch"]
+    return out
+
+
 def serving_bench(args, sfc, workload, torch):
     """Poisson stream of query / insert / erase batches (40/40/20, sizes
     2^U[10,16]) over 2^25 clustered points, Morton keys, learned search:
@@ -264,6 +305,8 @@ def main():
                     help="skip the batched point-set measurement")
     ap.add_argument("--no-learned-large", action="store_true",
                     help="skip the learned-index measurement at n=2^26")
+    ap.add_argument("--no-early-term", action="store_true",
+                    help="skip the early-termination measurement")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the insert/erase/query serving measurement")
     ap.add_argument("--serving-requests", type=int, default=1000)
@@ -467,6 +510,8 @@ def main():
     }
     if not args.no_batched and not args.only_refined:
         line["batched_sets"] = batched_sets_bench(args, sfc, workload, torch)
+    if not args.no_early_term and not args.only_refined:
+        line["early_termination"] = early_term_bench(args, sfc, workload, torch, pts)
     if not args.no_learned_large and not args.only_refined:
         line["learned_large"] = learned_large_bench(args, sfc, workload, torch)
     if not args.no_serving and not args.only_refined:

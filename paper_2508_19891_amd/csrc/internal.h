@@ -64,6 +64,7 @@ struct QueryScratch {
   uint32_t* counters;     // [2] error word; u64 at [4]: candidates, [6]: learned
                           // endpoints, [8]: learned fallbacks
   int ss;                 // log2 of the slots per query (2: method's ranges, 3: refined)
+  uint64_t* pairs;        // dense (query, cell) work list: 4 * query + cell
 };
 constexpr uint64_t kCompactTileRows = 64;           // rows of 64 candidates per tile
 constexpr uint64_t kCompactChunkTiles = 1ull << 19; // tiles per launch

@@ -5,15 +5,20 @@
 //                  level l = ceil(log2 side), the at most four level-l cells
 //                  meeting the box and their merged key intervals (the
 //                  Observation gives each cell's interval); slot r then runs
-//                  the two searches of interval r over the sorted keys.  The
-//                  candidate counts are scanned in the same kernel (block
-//                  scan + decoupled look-back) into segment offsets.
-//   compact        the candidates of all queries form one flat index space;
-//                  a block tests 2048 consecutive candidates (four waves of
-//                  eight 64-lane rows) with the exact distance test, learns
-//                  its output position through a decoupled look-back and
-//                  writes the reported ids, in candidate order, plus the CSR
-//                  offsets of the queries whose candidates start in it.
+//                  the two searches of interval r over the sorted keys
+//                  (binary search or the learned index), optionally split
+//                  once into the cell's children that meet the box.
+//   cells_pack     with early termination: the cells whose quadtree node
+//                  holds a point, as a dense (query, cell) work list, so the
+//                  search spends lanes only on them.
+//   scan           candidate rows of every slot -> row offsets.
+//   expand_rows    rows -> (slot, first candidate) tiles.
+//   compact_test   a block tests its tiles' candidates (64-lane rows) with
+//                  the exact distance test and counts the hits per tile;
+//                  the hit counts are scanned on the device.
+//   compact_write  the same tiles again: reported ids at the scanned
+//                  positions, in candidate order, and the CSR offsets of the
+//                  queries.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -276,18 +281,35 @@ template <int CURVE, bool REFINE, bool LEARNED>
 __global__ __launch_bounds__(256) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, uint32_t refine_min,
-    const uint32_t* __restrict__ occ, const uint32_t* __restrict__ qset,
+    const uint32_t* __restrict__ occ, const uint64_t* __restrict__ pairs,
+    const uint64_t* __restrict__ pair_total, const uint32_t* __restrict__ qset,
     const uint64_t* __restrict__ set_off, uint32_t n_sets, uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
     uint64_t* __restrict__ dbg_lo, uint64_t* __restrict__ dbg_hi, uint64_t* __restrict__ dbg_b,
     uint64_t* __restrict__ dbg_e, uint32_t* __restrict__ dbg_nr) {
   __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
+  // Blocks past the listed pairs have nothing to do (uniform per block).
+  if (pairs && (uint64_t)blockIdx.x * 256 >= *pair_total) return;
   if (CURVE == SFC_CURVE_HILBERT)
     for (int i = threadIdx.x; i < 1024; i += 256) lut[i] = kHilbertLutConst.v[i];
   __syncthreads();
+  // Lane -> (query, cell): four lanes per query, or (pairs) one lane per
+  // cell that survived early termination, packed densely; idle lanes take
+  // j = m.
   const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint64_t j = g >> 2;
-  const int r = (int)(g & 3);
+  uint64_t j, sidx;
+  int r;
+  if (pairs) {
+    const bool act = g < *pair_total;
+    const uint64_t pr = act ? pairs[g] : 0;
+    j = act ? pr >> 2 : m;
+    r = (int)(pr & 3);
+    sidx = pr;
+  } else {
+    j = g >> 2;
+    r = (int)(g & 3);
+    sidx = g;
+  }
 
   uint64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0, klo = 0, khi = 0;
   int nr = 0;
@@ -316,7 +338,7 @@ __global__ __launch_bounds__(256) void ranges_search(
       uint64_t lo[4], hi[4];
       uint32_t pr = 0;
       nr = query_ranges<CURVE>(lut, qq.x, qq.y, d, lo, hi, occ, &pr);
-      if (r == 0) pruned = pr;
+      if (r == 0 && !pairs) pruned = pr;
       if (r < nr) {
         klo = lo[r];
         khi = hi[r];
@@ -332,7 +354,7 @@ __global__ __launch_bounds__(256) void ranges_search(
       int L = 0;
       uint32_t pr = 0;
       nr = query_cells<CURVE>(lut, qq.x, qq.y, d, lo, hi, cx, cy, &L, box, occ, &pr);
-      if (r == 0) pruned = pr;
+      if (r == 0 && !pairs) pruned = pr;
       if (r < nr) {
         find_range<LEARNED>(kseg, nn, lv, lo[r], hi[r], b0, e0, fb);
         b0 += base;
@@ -411,25 +433,110 @@ __global__ __launch_bounds__(256) void ranges_search(
   }
   if (j < m) {
     if (!REFINE) {
-      slot_begin[g] = (uint32_t)b0;
-      slot_count[g] = (uint32_t)(e0 - b0);
-      slot_rows[g] = (uint32_t)((e0 - b0 + 63) >> 6);
+      slot_begin[sidx] = (uint32_t)b0;
+      slot_count[sidx] = (uint32_t)(e0 - b0);
+      slot_rows[sidx] = (uint32_t)((e0 - b0 + 63) >> 6);
       if (dbg_lo) {
-        dbg_lo[g] = klo;
-        dbg_hi[g] = khi;
-        dbg_b[g] = b0;
-        dbg_e[g] = e0;
+        dbg_lo[sidx] = klo;
+        dbg_hi[sidx] = khi;
+        dbg_b[sidx] = b0;
+        dbg_e[sidx] = e0;
         if (r == 0) dbg_nr[j] = (uint32_t)nr;
       }
     } else {
-      slot_begin[2 * g] = (uint32_t)b0;
-      slot_count[2 * g] = (uint32_t)(e0 - b0);
-      slot_rows[2 * g] = (uint32_t)((e0 - b0 + 63) >> 6);
-      slot_begin[2 * g + 1] = (uint32_t)b1;
-      slot_count[2 * g + 1] = (uint32_t)(e1 - b1);
-      slot_rows[2 * g + 1] = (uint32_t)((e1 - b1 + 63) >> 6);
+      slot_begin[2 * sidx] = (uint32_t)b0;
+      slot_count[2 * sidx] = (uint32_t)(e0 - b0);
+      slot_rows[2 * sidx] = (uint32_t)((e0 - b0 + 63) >> 6);
+      slot_begin[2 * sidx + 1] = (uint32_t)b1;
+      slot_count[2 * sidx + 1] = (uint32_t)(e1 - b1);
+      slot_rows[2 * sidx + 1] = (uint32_t)((e1 - b1 + 63) >> 6);
     }
   }
+}
+
+// The cells of every query that survive early termination, as a dense work
+// list of (query, cell) pairs (4 * query + cell) for the search.  One thread
+// per query; a block's pairs are contiguous, at a base taken with one atomic
+// on the list's length, so the list's order across blocks varies from run to
+// run -- the search writes each pair's results to the pair's own slots, so
+// results do not depend on it.  The slots of cells a query does not have are
+// cleared here; invalid queries (and bad set indices) raise the flag and list
+// no cell.
+template <int CURVE, bool REFINE>
+__global__ __launch_bounds__(256) void cells_pack(
+    const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
+    const uint32_t* __restrict__ occ, const uint32_t* __restrict__ qset, uint32_t n_sets,
+    uint64_t* __restrict__ pairs, unsigned long long* pair_total, uint32_t* __restrict__ slot_begin,
+    uint32_t* __restrict__ slot_count, uint32_t* __restrict__ slot_rows, uint32_t* counters,
+    unsigned long long* pruned_total) {
+  __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
+  __shared__ uint32_t s_cnt[4];
+  __shared__ uint32_t s_pr[4];
+  __shared__ unsigned long long s_base;
+  if (CURVE == SFC_CURVE_HILBERT)
+    for (int i = threadIdx.x; i < 1024; i += 256) lut[i] = kHilbertLutConst.v[i];
+  __syncthreads();
+  const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  uint32_t nr = 0, pr = 0;
+  bool bad = false;
+  if (j < m) {
+    if (qset && qset[j] >= n_sets) {
+      bad = true;
+    } else {
+      const double2 qq = q[j];
+      const double d = delta[j];
+      if (!(finite(qq.x) && finite(qq.y) && finite(d) && d >= 0.0)) {
+        bad = true;
+      } else if (REFINE) {
+        uint64_t lo[4], hi[4];
+        uint32_t cx[4], cy[4];
+        int64_t box[4];
+        int L = 0;
+        nr = (uint32_t)query_cells<CURVE>(lut, qq.x, qq.y, d, lo, hi, cx, cy, &L, box, occ, &pr);
+      } else {
+        uint64_t lo[4], hi[4];
+        nr = (uint32_t)query_ranges<CURVE>(lut, qq.x, qq.y, d, lo, hi, occ, &pr);
+      }
+    }
+    for (uint32_t r = nr; r < 4; ++r) {
+      if (!REFINE) {
+        slot_begin[4 * j + r] = 0;
+        slot_count[4 * j + r] = 0;
+        slot_rows[4 * j + r] = 0;
+      } else {
+        for (uint32_t h = 0; h < 2; ++h) {
+          slot_begin[8 * j + 2 * r + h] = 0;
+          slot_count[8 * j + 2 * r + h] = 0;
+          slot_rows[8 * j + 2 * r + h] = 0;
+        }
+      }
+    }
+  }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&counters[2], kErrInvalidQuery);
+  // Block-exclusive offsets of the cell counts: wave prefix, then waves.
+  const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+  uint32_t inc = nr, wp = pr;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += t;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wp += __shfl_xor(wp, o, 64);
+  if (lane == 63) s_cnt[wv] = inc;
+  if (lane == 0) s_pr[wv] = wp;
+  __syncthreads();
+  uint32_t before = 0;
+  for (uint32_t w = 0; w < wv; ++w) before += s_cnt[w];
+  if (threadIdx.x == 0) {
+    const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    s_base = tot ? atomicAdd(pair_total, (unsigned long long)tot) : 0;
+    const uint32_t p = s_pr[0] + s_pr[1] + s_pr[2] + s_pr[3];
+    if (p) atomicAdd(pruned_total, (unsigned long long)p);
+  }
+  __syncthreads();
+  const uint64_t o = s_base + before + inc - nr;
+  for (uint32_t r = 0; r < nr; ++r) pairs[o + r] = 4 * j + r;
 }
 
 // First query index qq in [0, m] with off[qq << ss] >= v (m if none).
@@ -715,7 +822,7 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) 
 size_t query_scratch_bytes(uint64_t m) {
   const uint64_t nseg = 8 * m;   // room for the refined layout (eight slots per query)
   return align256(nseg * 4) * 3 + align256((nseg + 1) * 8) + scan_scratch_bytes(nseg) +
-         align256(64);
+         align256(64) + align256(4 * m * 8);
 }
 
 void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs) {
@@ -726,7 +833,8 @@ void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs) {
   qs->slot_rows = (uint32_t*)p;   p += align256(nseg * 4);
   qs->row_off = (uint64_t*)p;     p += align256((nseg + 1) * 8);
   qs->scan_tmp = (uint64_t*)p;    p += scan_scratch_bytes(nseg);
-  qs->counters = (uint32_t*)p;
+  qs->counters = (uint32_t*)p;    p += align256(64);
+  qs->pairs = (uint64_t*)p;
   qs->ss = 2;
 }
 
@@ -753,13 +861,37 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   const bool learned = lview != nullptr && qset == nullptr;
   const LearnedView lv = learned ? *lview : LearnedView{};
   unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
+  // With early termination (and no inspected ranges) the search runs one
+  // lane per surviving cell, from a dense list of (query, cell) pairs.
+  const bool dense = occ != nullptr && dbg_lo == nullptr;
+  unsigned long long* total = (unsigned long long*)(qs.counters + 14);   // cleared above
+  const uint64_t* pairs = nullptr;
+  const uint64_t* pair_total = nullptr;
+  if (dense) {
+    const uint32_t qb = (uint32_t)((m + 255) / 256);
+    ProfScope ps("cells_pack", s);
+#define SFC_CELLS(C, R)                                                                    \
+  cells_pack<C, R><<<qb, 256, 0, s>>>((const double2*)q, delta, m, occ, qset, n_sets,       \
+                                      qs.pairs, total, qs.slot_begin, qs.slot_count,        \
+                                      qs.slot_rows, qs.counters, cand + 3)
+    if (curve == SFC_CURVE_HILBERT) {
+      if (refine) SFC_CELLS(SFC_CURVE_HILBERT, true);
+      else SFC_CELLS(SFC_CURVE_HILBERT, false);
+    } else {
+      if (refine) SFC_CELLS(SFC_CURVE_MORTON, true);
+      else SFC_CELLS(SFC_CURVE_MORTON, false);
+    }
+#undef SFC_CELLS
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    pairs = qs.pairs;
+    pair_total = (const uint64_t*)total;
+  }
   {
     ProfScope ps(learned ? "ranges_learned" : "ranges_search", s);
 #define SFC_RANGES(C, R, L)                                                                  \
   ranges_search<C, R, L><<<blocks, 256, 0, s>>>(                                              \
-      (const double2*)q, delta, m, keys, n, lv, refine_min, dbg_lo ? nullptr : occ, qset,    \
-      set_off,                                                                                \
-      n_sets, qs.slot_begin,                                                                  \
+      (const double2*)q, delta, m, keys, n, lv, refine_min, dbg_lo ? nullptr : occ, pairs,   \
+      pair_total, qset, set_off, n_sets, qs.slot_begin,                                       \
       qs.slot_count, qs.slot_rows, qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr)
 #define SFC_RANGES_C(C)                         \
   if (refine) {                                 \

@@ -96,3 +96,47 @@ def test_bitmap_follows_updates_and_graph_rebuilds():
     want = expected_bitmap(oracle.build(other, MORTON)[0])
     assert np.array_equal(fresh.occupancy().cpu().numpy().view(np.uint32), want)
     g.close()
+
+
+@pytest.mark.parametrize("refine", [False, True])
+def test_graph_replays_with_early_term(refine):
+    """Recorded query batches over the dense (query, cell) work list: every
+    replay equals the oracle, with eager batches between replays (the list's
+    order across blocks varies from run to run; the results may not)."""
+    pts, qs, ds = _sparse_queries(150_000, 12_000, 55)
+    ref = oracle.query(oracle.build(pts, MORTON), qs, ds, MORTON, nthreads=4)
+    idx = sfc.Index(dev(pts), MORTON, refine=refine, early_term=True)
+    q, d = dev(qs), dev(ds)
+    off, ids = idx.query(q, d)
+    rows = idx.last_stats()["candidates"] // 64 + 8 * len(qs)
+    g = sfc.Graph.query(idx, q, d, max_rows=int(rows * 2), ids_cap=ids.numel() + 16)
+    for rep in range(4):
+        g.launch()
+        goff, gids = g.result()
+        assert np.array_equal(goff.cpu().numpy().view(np.uint64), ref[0]), rep
+        assert np.array_equal(gids.cpu().numpy().view(np.uint32), ref[1]), rep
+        e_off, e_ids = idx.query(q, d)
+        assert torch.equal(e_off, off) and torch.equal(e_ids, ids)
+    g.close()
+
+
+def test_sets_refuse_early_term():
+    """An index of several point sets keeps no occupancy bits (the bits would
+    have to be per set): asking for them is refused, not ignored."""
+    wl = workload.batched_uneven(n_sets=5, log2_n=(6, 9), log2_m=(3, 5), seed=56)
+    with pytest.raises(sfc.SfcError) as ei:
+        sfc.Index(dev(wl.points), HILBERT, set_off=wl.set_off, early_term=True)
+    assert ei.value.status == sfc.SFC_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("bad", [(0.5, 0.5, -1.0), (float("nan"), 0.5, 0.1)])
+def test_invalid_query_with_early_term(bad):
+    pts, qs, ds = _sparse_queries(20_000, 500, 57)
+    qs[123], ds[123] = bad[:2], bad[2]
+    idx = sfc.Index(dev(pts), MORTON, refine=True, early_term=True)
+    with pytest.raises(sfc.SfcError) as ei:
+        idx.query(dev(qs), dev(ds))
+    assert ei.value.status == sfc.SFC_ERR_INVALID
+    off, ids = idx.query(torch.empty((0, 2), dtype=torch.float64, device=DEV),
+                         torch.empty(0, dtype=torch.float64, device=DEV))
+    assert off.cpu().tolist() == [0] and ids.numel() == 0
