@@ -23,6 +23,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MORTON = 0
 HILBERT = 1
+L2 = 0       # closed Euclidean ball of radius delta
+LINF = 1     # closed axis-parallel square window of half side delta
 
 
 def compile_lib() -> str:
@@ -63,9 +65,9 @@ def lib():
         L.oracle_box_ranges.restype = i32
         L.oracle_index_ranges.argtypes = [vp, u64, dbl, dbl, dbl, i32, vp]
         L.oracle_index_ranges.restype = i32
-        L.oracle_query.argtypes = [vp, vp, vp, u64, vp, vp, u64, i32, vp, vp, u64, i32]
+        L.oracle_query.argtypes = [vp, vp, vp, u64, vp, vp, u64, i32, vp, vp, u64, i32, i32]
         L.oracle_query.restype = i64
-        L.oracle_brute.argtypes = [vp, u64, vp, vp, u64, vp, vp, u64]
+        L.oracle_brute.argtypes = [vp, u64, vp, vp, u64, vp, vp, u64, i32]
         L.oracle_brute.restype = i64
         _lib = L
     return _lib
@@ -170,9 +172,10 @@ def index_ranges(sorted_keys, qx: float, qy: float, delta: float, curve: int):
     return [(int(be[2 * i]), int(be[2 * i + 1])) for i in range(k)]
 
 
-def query(index, q, delta, curve: int, nthreads: int = 1):
+def query(index, q, delta, curve: int, nthreads: int = 1, metric: int = L2):
     """CSR (offsets u64[m+1], ids u32[total]) of a query batch over a built
-    index (the tuple returned by :func:`build`)."""
+    index (the tuple returned by :func:`build`).  metric L2: the ball of
+    radius delta; LINF: the square window of half side delta."""
     sk, si, sxy = index
     sk = np.ascontiguousarray(sk, np.uint64)
     si = np.ascontiguousarray(si, np.uint32)
@@ -185,28 +188,28 @@ def query(index, q, delta, curve: int, nthreads: int = 1):
     off = np.zeros(m + 1, np.uint64)
     L = lib()
     tot = L.oracle_query(_p(sk), _p(si), _p(sxy), sk.shape[0], _p(q), _p(d), m, curve,
-                         _p(off), None, 0, nthreads)
+                         _p(off), None, 0, nthreads, metric)
     if tot < 0:
         raise InvalidQuery("invalid query")
     ids = np.zeros(max(int(tot), 1), np.uint32)
     L.oracle_query(_p(sk), _p(si), _p(sxy), sk.shape[0], _p(q), _p(d), m, curve,
-                   _p(off), _p(ids), int(tot), nthreads)
+                   _p(off), _p(ids), int(tot), nthreads, metric)
     return off, ids[: int(tot)]
 
 
-def brute(xy, q, delta):
-    """Brute-force CSR (ids ascending per query)."""
+def brute(xy, q, delta, metric: int = L2):
+    """Brute-force CSR (ids ascending per query), same test as :func:`query`."""
     xy = _xy(xy)
     q = _xy(q)
     d = np.ascontiguousarray(delta, np.float64)
     m = q.shape[0]
     off = np.zeros(m + 1, np.uint64)
     L = lib()
-    tot = L.oracle_brute(_p(xy), xy.shape[0], _p(q), _p(d), m, _p(off), None, 0)
+    tot = L.oracle_brute(_p(xy), xy.shape[0], _p(q), _p(d), m, _p(off), None, 0, metric)
     if tot < 0:
         raise InvalidQuery("invalid query")
     ids = np.zeros(max(int(tot), 1), np.uint32)
-    L.oracle_brute(_p(xy), xy.shape[0], _p(q), _p(d), m, _p(off), _p(ids), int(tot))
+    L.oracle_brute(_p(xy), xy.shape[0], _p(q), _p(d), m, _p(off), _p(ids), int(tot), metric)
     return off, ids[: int(tot)]
 
 

@@ -43,7 +43,13 @@
 //   * Morton: x bits on even key positions, y bits on odd positions;
 //   * Hilbert: the four-state machine in hilbert_step() below, most
 //     significant level first, starting in state 0 at (0,0);
-//   * ranges of adjacent cells are merged (hi + 1 == next lo).
+//   * ranges of adjacent cells are merged (hi + 1 == next lo);
+//   * square windows (Sec. 4, the experiments' queries: an axis-parallel
+//     square of side delta relative to the domain): taken as the closed
+//     L-infinity ball of radius r = half the side around q, accepted iff
+//        dx = px-qx; dy = py-qy; |dx| <= r and |dy| <= r
+//     in binary64.  The window is its own bounding square, so cells(Q) and
+//     the widened box are those of the Euclidean query of radius r.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -130,6 +136,17 @@ bool within(double px, double py, double qx, double qy, double delta) {
   return s <= r2;
 }
 
+// Metric 1: the closed axis-parallel square of half side delta around q.
+bool within_window(double px, double py, double qx, double qy, double delta) {
+  double dx = px - qx;
+  double dy = py - qy;
+  return std::fabs(dx) <= delta && std::fabs(dy) <= delta;
+}
+
+bool accept(int metric, double px, double py, double qx, double qy, double delta) {
+  return metric == 1 ? within_window(px, py, qx, qy, delta) : within(px, py, qx, qy, delta);
+}
+
 bool valid_query(double qx, double qy, double delta) {
   return std::isfinite(qx) && std::isfinite(qy) && std::isfinite(delta) &&
          delta >= 0.0;
@@ -207,7 +224,7 @@ int ranges(double qx, double qy, double delta, int curve, Range out[4]) {
 
 // Alg. 1 for one query: report ids in array order within each key range.
 void query_one(const uint64_t* keys, const uint32_t* ids, const double* xy,
-               uint64_t n, double qx, double qy, double delta, int curve,
+               uint64_t n, double qx, double qy, double delta, int curve, int metric,
                std::vector<uint32_t>* out) {
   Range r[4];
   int k = ranges(qx, qy, delta, curve, r);
@@ -216,7 +233,7 @@ void query_one(const uint64_t* keys, const uint32_t* ids, const double* xy,
     const uint64_t* e = std::upper_bound(keys, keys + n, r[i].hi);
     for (const uint64_t* p = b; p < e; ++p) {
       uint64_t j = (uint64_t)(p - keys);
-      if (within(xy[2 * j], xy[2 * j + 1], qx, qy, delta)) out->push_back(ids[j]);
+      if (accept(metric, xy[2 * j], xy[2 * j + 1], qx, qy, delta)) out->push_back(ids[j]);
     }
   }
 }
@@ -325,10 +342,13 @@ int oracle_index_ranges(const uint64_t* keys, uint64_t n, double qx, double qy,
 // if cap >= total, ids[total] in curve order per query.  Returns the total
 // number of reports, or -1 for an invalid query.  Queries are split into
 // nthreads contiguous slices whose outputs are concatenated in order.
+// metric 0: Euclidean ball of radius delta; 1: square window of half side
+// delta.
 int64_t oracle_query(const uint64_t* keys, const uint32_t* ids, const double* xy,
                      uint64_t n, const double* q, const double* delta, uint64_t m,
                      int curve, uint64_t* offsets, uint32_t* out, uint64_t cap,
-                     int nthreads) {
+                     int nthreads, int metric) {
+  if (metric != 0 && metric != 1) return -1;
   for (uint64_t j = 0; j < m; ++j)
     if (!valid_query(q[2 * j], q[2 * j + 1], delta[j])) return -1;
   if (nthreads < 1) nthreads = 1;
@@ -339,7 +359,7 @@ int64_t oracle_query(const uint64_t* keys, const uint32_t* ids, const double* xy
     uint64_t b = m * (uint64_t)(t + 1) / (uint64_t)nthreads;
     for (uint64_t j = a; j < b; ++j) {
       size_t before = part[t].size();
-      query_one(keys, ids, xy, n, q[2 * j], q[2 * j + 1], delta[j], curve, &part[t]);
+      query_one(keys, ids, xy, n, q[2 * j], q[2 * j + 1], delta[j], curve, metric, &part[t]);
       cnt[t].push_back(part[t].size() - before);
     }
   };
@@ -372,13 +392,14 @@ int64_t oracle_query(const uint64_t* keys, const uint32_t* ids, const double* xy
 // Ids come in ascending order per query.  Same return convention as above.
 int64_t oracle_brute(const double* xy, uint64_t n, const double* q,
                      const double* delta, uint64_t m, uint64_t* offsets,
-                     uint32_t* out, uint64_t cap) {
+                     uint32_t* out, uint64_t cap, int metric) {
+  if (metric != 0 && metric != 1) return -1;
   uint64_t total = 0;
   for (uint64_t j = 0; j < m; ++j) {
     if (!valid_query(q[2 * j], q[2 * j + 1], delta[j])) return -1;
     offsets[j] = total;
     for (uint64_t i = 0; i < n; ++i) {
-      if (within(xy[2 * i], xy[2 * i + 1], q[2 * j], q[2 * j + 1], delta[j])) {
+      if (accept(metric, xy[2 * i], xy[2 * i + 1], q[2 * j], q[2 * j + 1], delta[j])) {
         if (total < cap) out[total] = (uint32_t)i;
         ++total;
       }

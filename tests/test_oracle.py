@@ -440,3 +440,149 @@ def test_far_query_large_radius_widening(curve):
     assert ref[1].tolist() == list(range(17))
     got = oracle.query(oracle.build(pts, curve), q, d, curve)
     assert np.array_equal(oracle.canonical(*got), oracle.canonical(*ref))
+
+
+# ---- square windows (the experiments' queries, Sec. 4) ---------------------------------------
+
+LINF = oracle.LINF
+
+
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_window_grid_counts_closed_form(curve):
+    """Points on the dyadic grid (i h, j h), h = 2^-7: every difference and
+    comparison is exact, so the closed window of half side r around a grid
+    point (a h, b h) holds exactly the grid points with |i - a| <= k and
+    |j - b| <= k for r in [k h, (k+1) h), clipped to the square: the ids
+    follow from integer arithmetic alone."""
+    g = 128
+    h = 1.0 / g
+    ii, jj = np.meshgrid(np.arange(g), np.arange(g), indexing="ij")
+    pts = np.stack([ii.ravel() * h, jj.ravel() * h], 1)       # id = i * g + j
+    idx = oracle.build(pts, curve)
+    rng = np.random.default_rng(41)
+    cases = [(0, 0, 0), (0, 0, 3), (127, 127, 2), (64, 5, 7), (10, 120, 0)]
+    cases += [tuple(int(v) for v in t) for t in zip(rng.integers(0, g, 20),
+                                                    rng.integers(0, g, 20),
+                                                    rng.integers(0, 12, 20))]
+    qs, ds, want = [], [], []
+    for a, b, k in cases:
+        for r in (k * h, k * h + h / 2):                       # on a grid line, between lines
+            qs.append((a * h, b * h))
+            ds.append(r)
+            xs = [i for i in range(g) if abs(i - a) <= k]
+            ys = [j for j in range(g) if abs(j - b) <= k]
+            want.append(sorted(i * g + j for i in xs for j in ys))
+    off, ids = oracle.query(idx, np.array(qs), np.array(ds), curve, metric=LINF)
+    for t, w in enumerate(want):
+        assert sorted(ids[off[t]:off[t + 1]].tolist()) == w, cases[t // 2]
+    # The count is the product of the clipped side counts.
+    a, b, k = 64, 5, 7
+    assert len(want[cases.index((a, b, k)) * 2]) == (2 * k + 1) * (b + k + 1)
+
+
+def test_window_between_ball_and_scaled_ball():
+    """Geometry: the ball of radius r lies in the square of half side r,
+    which lies in the ball of radius r sqrt 2 (a relative margin of 1e-9
+    covers the rounding of either test)."""
+    rng = np.random.default_rng(42)
+    pts = rng.random((3000, 2))
+    qs = rng.random((200, 2))
+    ds = 10 ** rng.uniform(-2.5, -0.7, 200)
+    ball = oracle.brute(pts, qs, ds)
+    win = oracle.brute(pts, qs, ds, metric=LINF)
+    big = oracle.brute(pts, qs, ds * math.sqrt(2) * (1 + 1e-9))
+    for j in range(200):
+        b = set(ball[1][ball[0][j]:ball[0][j + 1]].tolist())
+        w = set(win[1][win[0][j]:win[0][j + 1]].tolist())
+        g = set(big[1][big[0][j]:big[0][j + 1]].tolist())
+        assert b <= w <= g
+    assert win[0][-1] > ball[0][-1]
+
+
+def test_window_expected_output_closed_form():
+    """Uniform points; windows of half side r whose centres keep them inside
+    the square: a point lies in a window with probability (2r)^2, here 10 / n
+    (10 reports per query on average)."""
+    n, m = 1 << 16, 10_000
+    r = math.sqrt(10.0 / n) / 2
+    rng = np.random.default_rng(43)
+    pts = rng.random((n, 2))
+    qs = rng.uniform(r, 1 - r, (m, 2))
+    off, _ = oracle.query(oracle.build(pts, MORTON), qs, np.full(m, r), MORTON, nthreads=4,
+                          metric=LINF)
+    assert abs(off[-1] / m - 10.0) < 0.25
+
+
+def _window_adversarial(rng):
+    """Points one ulp inside and outside every side and corner of the
+    windows, on quantum edges, and duplicates."""
+    pts = list(rng.random((400, 2)))
+    qs, ds = [], []
+    for _ in range(50):
+        q = rng.random(2)
+        d = 10 ** rng.uniform(-9, -1)
+        qs.append(q)
+        ds.append(d)
+        for sx in (-1, 0, 1):
+            for sy in (-1, 0, 1):
+                p = q + d * np.array([sx, sy])
+                for t in (p, np.nextafter(p, q), np.nextafter(p, 2 * p - q)):
+                    if np.all(t >= 0) and np.all(t < 1):
+                        pts.append(t)
+        for sx in (-1, 1):
+            e = np.floor((q[0] + sx * d) * 2 ** 32) / 2 ** 32
+            for ex in (e, np.nextafter(e, 0), np.nextafter(e, 1)):
+                p = np.array([ex, q[1]])
+                if np.all(p >= 0) and np.all(p < 1):
+                    pts.append(p)
+    pts = np.array(pts)
+    pts = np.concatenate([pts, pts[:100]])
+    qs += [np.array([0.5, 0.5]), pts[3], np.array([-0.3, 0.5]), np.array([1.2, -0.1])]
+    ds += [0.5, 0.0, 0.31, 0.25]
+    return pts, np.array(qs), np.array(ds)
+
+
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_window_query_equals_brute_force_adversarial(curve):
+    rng = np.random.default_rng(44 + curve)
+    pts, qs, ds = _window_adversarial(rng)
+    got = oracle.query(oracle.build(pts, curve), qs, ds, curve, metric=LINF)
+    ref = oracle.brute(pts, qs, ds, metric=LINF)
+    assert np.array_equal(oracle.canonical(*got), oracle.canonical(*ref))
+    # half side 1/2 around the centre covers the square [0, 1)^2 whole
+    j = len(qs) - 4
+    assert ref[0][j + 1] - ref[0][j] == len(pts)
+
+
+@settings(max_examples=30, deadline=None)
+@given(seed=st.integers(0, 2 ** 31), n=st.integers(0, 300), m=st.integers(0, 30),
+       curve=st.sampled_from([MORTON, HILBERT]), scale=st.floats(-7, 0.3))
+def test_window_query_equals_brute_force_random(seed, n, m, curve, scale):
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    qs = rng.uniform(-0.1, 1.1, (m, 2))
+    ds = 10 ** (scale + rng.uniform(-1, 1, m))
+    got = oracle.query(oracle.build(pts, curve), qs, ds, curve, metric=LINF)
+    ref = oracle.brute(pts, qs, ds, metric=LINF)
+    assert np.array_equal(oracle.canonical(*got), oracle.canonical(*ref))
+
+
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_window_far_query_large_half_side(curve):
+    """The widened box under the window test: for q = (2^25 + 1/2, 1/2) and
+    half side 2^25 the rounded |dx| <= r accepts (1/2 - k 2^-32, 1/2) exactly
+    for k <= 16 (doubles near 2^25 are 32 quanta apart; k = 16 is the tie,
+    rounded to even), several quanta past the exact edge."""
+    k = np.arange(0, 24)
+    pts = np.stack([0.5 - k * 2.0 ** -32, np.full(k.shape, 0.5)], 1)
+    q = np.array([[2.0 ** 25 + 0.5, 0.5]])
+    d = np.array([2.0 ** 25])
+    ref = oracle.brute(pts, q, d, metric=LINF)
+    assert ref[1].tolist() == list(range(17))
+    got = oracle.query(oracle.build(pts, curve), q, d, curve, metric=LINF)
+    assert np.array_equal(oracle.canonical(*got), oracle.canonical(*ref))
+
+
+def test_metric_must_be_known():
+    with pytest.raises(oracle.InvalidQuery):
+        oracle.brute(np.zeros((1, 2)), np.zeros((1, 2)), np.zeros(1), metric=2)
