@@ -61,6 +61,13 @@ typedef enum {
 
 enum { SFC_CURVE_MORTON = 0, SFC_CURVE_HILBERT = 1 };
 enum { SFC_SEARCH_BINARY = 0, SFC_SEARCH_LEARNED = 1 };
+/* The exact test of a query (q, delta): SFC_METRIC_L2 reports the points of
+   the closed Euclidean ball of radius delta (Sec. 2, Problem Statement);
+   SFC_METRIC_LINF those of the closed axis-parallel square window of half
+   side delta (the queries of the experiments, Sec. 4, whose window side is
+   2 * delta).  Both use the same cells(Q): the window is the ball's
+   bounding square. */
+enum { SFC_METRIC_L2 = 0, SFC_METRIC_LINF = 1 };
 
 typedef struct {
   int curve;    /* SFC_CURVE_MORTON (Alg. 2) or SFC_CURVE_HILBERT */
@@ -84,10 +91,13 @@ typedef struct {
                      the cells of cells(Q) that hold no point; rebuilt after
                      inserts and compactions (an erase leaves a bit set, which
                      only costs a search).  Same results.  Not with point sets. */
+  int metric;     /* SFC_METRIC_L2 (default) or SFC_METRIC_LINF, for every
+                     query entry point; sfc_set_metric changes it */
 } sfc_options;
 
 /* Fills *opt with Morton curve, binary search, no refinement, default
-   training steps, null stream, the pool. */
+   training steps, null stream, the pool, no early termination, the
+   Euclidean metric. */
 void sfc_default_options(sfc_options* opt);
 
 /* Human-readable name of a status code (static string). */
@@ -391,6 +401,12 @@ typedef struct {
 /* Selects the search for later queries; SFC_SEARCH_LEARNED fits the model
    first if there is none (n >= 2).  Synchronises the stream. */
 sfc_status sfc_set_search(sfc_index* h, int search);
+/* Selects the exact test (SFC_METRIC_L2 or SFC_METRIC_LINF) of later query
+   batches, sfc_graph_query recordings included; a recorded graph keeps the
+   metric it was recorded with, and sfc_query_retry completes its batch with
+   the metric that batch was tested with.  SFC_ERR_INVALID for another
+   value.  No device work. */
+sfc_status sfc_set_metric(sfc_index* h, int metric);
 /* (Re)fits the learned index with the given training steps (< 0: the
    handle's default).  SFC_ERR_UNSUPPORTED for n < 2. */
 sfc_status sfc_learned_fit(sfc_index* h, int steps);

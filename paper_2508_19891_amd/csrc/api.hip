@@ -193,6 +193,7 @@ struct sfc_index {
   int curve = SFC_CURVE_MORTON;
   int search = SFC_SEARCH_BINARY;
   int refine = 0;
+  int metric = SFC_METRIC_L2;   // exact test of the query batches
   uint32_t refine_min = 32;
   hipStream_t stream = nullptr;
   sfc::Allocator alloc;
@@ -269,6 +270,7 @@ bool valid_options(const sfc_options& o) {
   if (o.search != SFC_SEARCH_BINARY && o.search != SFC_SEARCH_LEARNED) return false;
   if (o.refine != 0 && o.refine != 1) return false;
   if (o.early_term != 0 && o.early_term != 1) return false;
+  if (o.metric != SFC_METRIC_L2 && o.metric != SFC_METRIC_LINF) return false;
   if ((o.alloc == nullptr) != (o.release == nullptr)) return false;
   return true;
 }
@@ -518,6 +520,7 @@ void sfc_default_options(sfc_options* opt) {
   opt->search = SFC_SEARCH_BINARY;
   opt->learn_steps = -1;
   opt->early_term = 0;
+  opt->metric = SFC_METRIC_L2;
 }
 
 const char* sfc_status_string(sfc_status s) {
@@ -571,6 +574,7 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
   h->curve = o.curve;
   h->search = o.search;
   h->refine = o.refine;
+  h->metric = o.metric;
   if (o.learn_steps >= 0) h->learn_steps = o.learn_steps;
   if (const char* env = std::getenv("SFC_REFINE_MIN")) h->refine_min = (uint32_t)std::atoi(env);
   h->stream = (hipStream_t)o.stream;
@@ -713,7 +717,8 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
     if (st != SFC_OK) return st;
   }
   SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_rows, false, h->cws,
-                              offsets, ids, ids_cap, h->stream, filtered ? &ev : nullptr));
+                              offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, h->stream,
+                              filtered ? &ev : nullptr));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
   if (m > 0) {
@@ -774,7 +779,8 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs.counters + 2, h->stream));
   SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, max_rows, true, h->cws,
-                              offsets, ids, ids_cap, h->stream, filtered ? &ev : nullptr));
+                              offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, h->stream,
+                              filtered ? &ev : nullptr));
   SFC_TRY(hipMemcpyAsync(flags, qs.counters + 2, 4, hipMemcpyDeviceToDevice, h->stream));
   return SFC_OK;
 }
@@ -790,7 +796,7 @@ sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint6
   }
   h->pending.valid = false;
   SFC_TRY(sfc::launch_compact(nullptr, nullptr, p.m, h->xy, h->ids, h->n, p.qs, p.rows, false,
-                              h->cws, offsets, ids, ids_cap, h->stream, nullptr, true));
+                              h->cws, offsets, ids, ids_cap, false, h->stream, nullptr, true));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + p.m, &total, 1, h->stream));
   if (total != p.total) return SFC_ERR_DEVICE;
@@ -869,6 +875,12 @@ sfc_status sfc_set_search(sfc_index* h, int search) {
     if (st != SFC_OK) return st;
   }
   h->search = search;
+  return SFC_OK;
+}
+
+sfc_status sfc_set_metric(sfc_index* h, int metric) {
+  if (!h || (metric != SFC_METRIC_L2 && metric != SFC_METRIC_LINF)) return SFC_ERR_INVALID;
+  h->metric = metric;
   return SFC_OK;
 }
 
@@ -1077,7 +1089,8 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
                                       nullptr, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess)
       e = sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, g->qs, max_rows, true,
-                              g->cscratch, offsets, ids, ids_cap, s, filtered ? &ev : nullptr);
+                              g->cscratch, offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, s,
+                              filtered ? &ev : nullptr);
     return e;
   });
   if (st != SFC_OK) {

@@ -92,12 +92,14 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
 // is the exact row count (known on the host), processed in chunks.
 // device_sized = true: max_rows is a capacity, the count is read on the
 // device (a plan for graph capture); more rows raise kErrOverflow.  cscratch
-// holds compact_scratch_bytes(max_rows).
+// holds compact_scratch_bytes(max_rows).  window: the square-window test
+// (half side delta) instead of the Euclidean ball.
 struct EpochView;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
-                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s,
+                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
+                          hipStream_t s,
                           const EpochView* ev = nullptr, bool write_only = false);
 // Whether a batch of total_rows rows (host-sized) is compacted in one chunk:
 // then an output larger than the capacity leaves the ids untouched, and the

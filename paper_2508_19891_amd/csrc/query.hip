@@ -50,6 +50,18 @@ __device__ __forceinline__ bool within(double px, double py, double qx, double q
   return s <= r2;
 }
 
+// The square-window test (the experiments' queries, Sec. 4): the closed
+// axis-parallel square of half side d around q, in binary64.  The window is
+// its own bounding square, so the cells and key ranges are those of the
+// Euclidean query of radius d.
+__device__ __forceinline__ bool within_window(double px, double py, double qx, double qy,
+                                              double d) {
+#pragma clang fp contract(off)
+  const double dx = px - qx;
+  const double dy = py - qy;
+  return fabs(dx) <= d && fabs(dy) <= d;
+}
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 __device__ __forceinline__ int64_t floor_clamped(double v) {
@@ -611,6 +623,7 @@ __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ 
 // rows as ITERS groups of ROWS rows whose point loads are in flight together.
 // EPOCH: a candidate that passes the test also has to be visible at the
 // query's epoch (ins <= e < era); only those lanes read the epochs.
+// window: the square-window test instead of the Euclidean one.
 template <int ROWS, int ITERS, bool EPOCH>
 __global__ __launch_bounds__(256) void compact_test(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
@@ -618,7 +631,7 @@ __global__ __launch_bounds__(256) void compact_test(
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     bool flag_overflow, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits,
     uint32_t* counters, const uint32_t* __restrict__ ins, const uint32_t* __restrict__ era,
-    const uint32_t* __restrict__ qepoch, uint32_t epoch) {
+    const uint32_t* __restrict__ qepoch, uint32_t epoch, bool window) {
   __shared__ uint32_t s_cnt[4];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
@@ -656,7 +669,8 @@ __global__ __launch_bounds__(256) void compact_test(
         if (act[jr]) pv[jr] = pts[pos[jr]];
 #pragma unroll
       for (int jr = 0; jr < ROWS; ++jr) {
-        bool hit = act[jr] && within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]);
+        bool hit = act[jr] && (window ? within_window(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr])
+                                      : within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]));
         if (EPOCH && hit) hit = ins[pos[jr]] <= qe[jr] && qe[jr] < era[pos[jr]];
         const uint64_t bal = __ballot(hit);
         cnt += (uint32_t)__popcll(bal);
@@ -919,8 +933,8 @@ constexpr uint64_t kCompactGrid = 4096;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
-                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, hipStream_t s,
-                          const EpochView* ev, bool write_only) {
+                          uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
+                          hipStream_t s, const EpochView* ev, bool write_only) {
   hipError_t e;
   if (m == 0) return fill_u64(offsets, 0, 1, s);
   const uint64_t nseg = m << qs.ss;
@@ -970,7 +984,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
   compact_test<R, I, E><<<grid, 256, 0, s>>>(                                             \
       (const double2*)q, delta, m, (const double2*)pts, npts, meta, total_dev, rbase,     \
       row_end, flag, masks, hits, qs.counters, ev ? ev->ins : nullptr,                    \
-      ev ? ev->era : nullptr, ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u)
+      ev ? ev->era : nullptr, ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u, window)
 #define SFC_TEST_SHAPES(E)                  \
   switch (test_variant(max_rows)) {         \
     case 1: SFC_TEST(4, 4, E); break;       \

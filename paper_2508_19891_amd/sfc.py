@@ -27,6 +27,8 @@ MORTON = 0
 HILBERT = 1
 BINARY = 0
 LEARNED = 1
+L2 = 0      # closed Euclidean ball of radius delta
+LINF = 1    # closed axis-parallel square window of half side delta
 
 EXPORTS = [
     "sfc_default_options", "sfc_status_string", "sfc_build", "sfc_query_batch", "sfc_size",
@@ -39,7 +41,7 @@ EXPORTS = [
     "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
-    "sfc_query_async", "sfc_occupancy_copy",
+    "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric",
 ]
 
 NPARAM = 1153
@@ -72,6 +74,7 @@ class Options(ctypes.Structure):
         ("release", ctypes.c_void_p),
         ("alloc_ctx", ctypes.c_void_p),
         ("early_term", ctypes.c_int),
+        ("metric", ctypes.c_int),
     ]
 
 
@@ -143,6 +146,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_pool_trim.restype = None
     L.sfc_set_search.argtypes = [vp, i32]
     L.sfc_set_search.restype = i32
+    L.sfc_set_metric.argtypes = [vp, i32]
+    L.sfc_set_metric.restype = i32
     L.sfc_learned_fit.argtypes = [vp, i32]
     L.sfc_learned_fit.restype = i32
     L.sfc_learned_info_get.argtypes = [vp, ctypes.POINTER(LearnedInfo)]
@@ -248,9 +253,11 @@ class Index:
 
     def __init__(self, xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,
                  refine: bool = False, learn_steps: int = -1, set_off=None,
-                 early_term: bool = False):
+                 early_term: bool = False, metric: int = L2):
         """set_off (host sequence of n_sets + 1 offsets): build independent
-        point sets with sfc_build_sets; query them with query_sets."""
+        point sets with sfc_build_sets; query them with query_sets.  metric:
+        L2 (ball of radius delta) or LINF (square window of half side
+        delta)."""
         xy = _dev(xy, torch.float64, "xy")
         if xy.ndim != 2 or xy.shape[1] != 2:
             raise ValueError("xy must have shape (n, 2)")
@@ -262,6 +269,7 @@ class Index:
         opt.refine = 1 if refine else 0
         opt.learn_steps = learn_steps
         opt.early_term = 1 if early_term else 0
+        opt.metric = metric
         opt.stream = current_stream_handle()
         h = ctypes.c_void_p()
         if set_off is None:
@@ -279,6 +287,7 @@ class Index:
         self._h = h
         self.curve = curve
         self.search = search
+        self.metric = metric
         self.device = xy.device
 
     def close(self):
@@ -477,6 +486,10 @@ class Index:
         _check(lib().sfc_query_ranges(self.handle, _ptr(q), _ptr(delta), m, _ptr(klo), _ptr(khi),
                                       _ptr(b), _ptr(e), _ptr(nr)), "sfc_query_ranges")
         return klo, khi, b, e, nr
+
+    def set_metric(self, metric: int):
+        _check(lib().sfc_set_metric(self.handle, metric), "sfc_set_metric")
+        self.metric = metric
 
     def set_search(self, search: int):
         _check(lib().sfc_set_search(self.handle, search), "sfc_set_search")

@@ -130,6 +130,23 @@ def clustered_uniform_queries(n: int = 1 << 26, m: int = 1 << 22, curve: int = 0
     return Workload(f"clustered_n{n}_m{m}_uniformq", pts, q, d, curve)
 
 
+def square_windows(n: int = 10_000_000, m: int = 1_000_000, side: float = 1e-3, curve: int = 0,
+                   seed: int = 6, points: str = "uniform") -> Workload:
+    """The experiments' query shape (Sec. 4): uniform centres and square
+    windows whose side is ``side`` times the side of the domain (delta =
+    side / 2, the half side; the domain is the unit square); uniform or
+    clustered points."""
+    if points == "uniform":
+        pts = uniform_points(n, 1000 + seed)
+    elif points == "clustered":
+        pts = clustered_points(n, 1000 + seed, make_mixture(500 + seed))
+    else:
+        raise ValueError("points must be 'uniform' or 'clustered'")
+    q = uniform_points(m, 2000 + seed)
+    d = np.full(m, side / 2)
+    return Workload(f"{points}_n{n}_m{m}_window{side:g}", pts, q, d, curve)
+
+
 @dataclasses.dataclass
 class BatchedWorkload:
     name: str

@@ -65,7 +65,7 @@ class Model:
     def visible(self, e):
         return np.nonzero(self.stored & (self.ins <= e) & (e < self.era))[0]
 
-    def reference(self, qs, ds, epochs, curve):
+    def reference(self, qs, ds, epochs, curve, metric=oracle.L2):
         """Oracle answers (offsets, ids) for queries at the given epochs."""
         m = len(qs)
         per_q = [None] * m
@@ -77,7 +77,7 @@ class Model:
                     per_q[j] = np.zeros(0, np.uint32)
                 continue
             off, idx = oracle.query(oracle.build(self.xy[ids], curve), qs[sel], ds[sel], curve,
-                                    nthreads=4)
+                                    nthreads=4, metric=metric)
             for t, j in enumerate(sel):
                 per_q[j] = ids[idx[off[t]:off[t + 1]]].astype(np.uint32)
         offsets = np.zeros(m + 1, np.uint64)

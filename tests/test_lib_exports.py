@@ -32,3 +32,17 @@ def test_library_exports_declared_symbols():
 
 def test_binding_covers_declared_symbols():
     assert set(declared_functions()) <= set(sfc.EXPORTS)
+
+
+def test_options_layout_matches_header():
+    """sfc_default_options (host only) fills the binding's struct: every field
+    lands where the header puts it, the last one (metric) included."""
+    if not os.path.exists(sfc.LIB_PATH):
+        build_lib.build()
+    L = ctypes.CDLL(sfc.LIB_PATH)
+    opt = sfc.Options()
+    ctypes.memset(ctypes.byref(opt), 0x5A, ctypes.sizeof(opt))
+    L.sfc_default_options(ctypes.byref(opt))
+    assert (opt.curve, opt.search, opt.refine, opt.learn_steps) == (sfc.MORTON, sfc.BINARY, 0, -1)
+    assert opt.early_term == 0 and opt.metric == sfc.L2
+    assert not opt.stream and not opt.alloc_ctx
