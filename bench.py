@@ -249,6 +249,61 @@ def early_term_bench(args, sfc, workload, torch, pts_c2):
     return out
 
 
+def paper_windows_bench(args, sfc, workload, torch):
+    """The paper's query sweep (Sec. 4): 10^7 points from its normal
+    distribution (centre 1/2, sigma 1/8), 10^6 uniform query centres, square
+    windows of relative side 1e-7 .. 0.02 (half side = side / 2); Morton
+    (Curve-Z) and Hilbert (Curve-H) keys, with the method's ranges and with
+    refined ranges.  The paper's single-threaded seconds for the same sweep
+    (its own CPU, n = 10^7, 10^6 queries) ride along as context."""
+    dev = torch.device("cuda:0")
+    n, m = 10_000_000, 1_000_000
+    sides = [1e-7, 1e-4, 1e-3, 1e-2, 2e-2]
+    paper_s = {"morton": [0.114, 0.199, 0.696, 9.849, 34.773],
+               "hilbert": [0.323, 0.324, 0.725, 9.765, 34.740]}
+    wl = workload.square_windows(n=n, m=m, side=sides[0], points="normal")
+    pts = torch.as_tensor(wl.points).to(dev)
+    q = torch.as_tensor(wl.queries).to(dev)
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    out = {"workload": f"normal_n{n}_uniformq_m{m}_square_windows",
+           "paper_context": "single-threaded seconds per 10^6 queries, n = 10^7, "
+                            "Xeon w5-3435X (the paper's sweep table)"}
+    for cname, curve in (("morton", sfc.MORTON), ("hilbert", sfc.HILBERT)):
+        for refine in (False, True):
+            idx = sfc.Index(pts, curve, refine=refine, metric=sfc.LINF)
+            rows = []
+            for i, side in enumerate(sides):
+                d = torch.full((m,), side / 2, dtype=torch.float64, device=dev)
+                try:
+                    idx.query(q, d, ids_cap=1, out_offsets=offsets)
+                    total = int(offsets[m].item())
+                except sfc.CapacityError as e:   # the usual case: only the size is wanted
+                    total = int(e.total)
+                out_ids = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+                steps = max(2, args.steps // (4 if side >= 1e-2 else 1))
+                idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / steps * 1e3
+                st = idx.last_stats()
+                rows.append({"side": side, "ms_per_batch": ms, "queries_per_s": m / (ms * 1e-3),
+                             "reported": total, "reported_pts_per_s": total / (ms * 1e-3),
+                             "candidates_per_report": st["candidates"] / max(total, 1),
+                             "paper_cpu_s": paper_s[cname][i],
+                             "paper_cpu_s_over_gpu_s": paper_s[cname][i] / (ms * 1e-3)})
+                del out_ids
+                log(f"windows {cname} refine={refine} side={side:g}: {ms:.3f} ms, "
+                    f"{total} reported")
+            out[f"{cname}_{'refined' if refine else 'ranges'}"] = rows
+            idx.close()
+    del pts, q
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_bench(args, sfc, workload, torch):
     """Poisson stream of query / insert / erase batches (40/40/20, sizes
     2^U[10,16]) over 2^25 clustered points, Morton keys, learned search:
@@ -307,6 +362,8 @@ def main():
                     help="skip the learned-index measurement at n=2^26")
     ap.add_argument("--no-early-term", action="store_true",
                     help="skip the early-termination measurement")
+    ap.add_argument("--no-windows", action="store_true",
+                    help="skip the paper's square-window sweep")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the insert/erase/query serving measurement")
     ap.add_argument("--serving-requests", type=int, default=1000)
@@ -512,6 +569,8 @@ def main():
         line["batched_sets"] = batched_sets_bench(args, sfc, workload, torch)
     if not args.no_early_term and not args.only_refined:
         line["early_termination"] = early_term_bench(args, sfc, workload, torch, pts)
+    if not args.no_windows and not args.only_refined:
+        line["paper_windows"] = paper_windows_bench(args, sfc, workload, torch)
     if not args.no_learned_large and not args.only_refined:
         line["learned_large"] = learned_large_bench(args, sfc, workload, torch)
     if not args.no_serving and not args.only_refined:

@@ -551,22 +551,6 @@ __global__ __launch_bounds__(256) void cells_pack(
   for (uint32_t r = 0; r < nr; ++r) pairs[o + r] = 4 * j + r;
 }
 
-// First query index qq in [0, m] with off[qq << ss] >= v (m if none).
-__device__ __forceinline__ uint64_t first_query_at(const uint64_t* __restrict__ off, uint64_t m,
-                                                   int ss, uint64_t v) {
-  uint64_t lo = 0, len = m;
-  while (len > 0) {
-    const uint64_t h = len >> 1;
-    if (off[(lo + h) << ss] < v) {
-      lo += h + 1;
-      len -= h + 1;
-    } else {
-      len = h;
-    }
-  }
-  return lo;
-}
-
 // The candidates are laid out in rows of 64: each query slot (segment) s
 // owns rows [row_off[s], row_off[s+1]), row k of s holding its candidates
 // 64k .. 64k+63 (the last row partly filled).  So every row belongs to one
@@ -689,47 +673,30 @@ __global__ __launch_bounds__(256) void compact_test(
 }
 
 // Pass 2: the ids of the accepted candidates at the tile's output offset, in
-// row order (= curve order per query); and the CSR offsets of the queries
-// whose first row lies in the tile (for the last tile also of the trailing
-// queries without rows).
+// row order (= curve order per query), and the absolute output position of
+// every row of the tile (row_pre, chunk-relative index; the entry one past a
+// tile's last row is the next tile's first, and the one at the batch's last
+// row + 1 is the total).
 template <int ROWS, int ITERS>
 __global__ __launch_bounds__(256) void compact_write(
-    const uint32_t* __restrict__ ids, uint64_t npts, uint64_t m,
-    const uint64_t* __restrict__ row_off, int ss, const uint4* __restrict__ row_meta,
+    const uint32_t* __restrict__ ids, uint64_t npts, const uint4* __restrict__ row_meta,
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     const uint64_t* __restrict__ masks, const uint64_t* __restrict__ tile_off,
-    uint64_t* __restrict__ offsets, uint32_t* __restrict__ out_ids, uint64_t cap,
-    bool whole) {
+    uint64_t* __restrict__ row_pre, uint32_t* __restrict__ out_ids, uint64_t cap, bool whole) {
   __shared__ uint64_t s_mask[kTileRows];
   __shared__ uint32_t s_pre[kTileRows + 1];
-  __shared__ uint64_t s_qrange[2];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
   const uint64_t total_rows = total_all < row_end ? total_all : row_end;
   const uint64_t ntiles = total_rows > rbase ? (total_rows - rbase + kTileRows - 1) / kTileRows : 0;
   const uint64_t below = lanemask_lt();
-  if (ntiles == 0 && rbase == 0 && blockIdx.x == 0) {   // no candidates at all
-    for (uint64_t qq = tid; qq <= m; qq += 256) offsets[qq] = 0;
-    return;
-  }
   // whole: this launch covers every row, so tile_off[ntiles] is the batch's
   // total; an output larger than cap then leaves out_ids untouched (the
   // offsets are still written).
   const bool write_ids = !whole || ntiles == 0 || tile_off[ntiles] <= cap;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t trow0 = rbase + tile * kTileRows;
-    // The queries whose first row lies in [trow0, tend) are those after the
-    // query of row trow0 - 1 up to the query of row tend - 1: read from the
-    // row descriptors, so only a chunk's first tile searches row_off.
     if (tid < kTileRows) s_mask[tid] = masks[tile * kTileRows + tid];
-    if (tid == 64)
-      s_qrange[0] = trow0 == 0      ? 0
-                    : trow0 > rbase ? (uint64_t)row_meta[trow0 - 1 - rbase].z + 1
-                                    : first_query_at(row_off, m, ss, trow0);
-    if (tid == 128) {
-      const uint64_t tend = trow0 + kTileRows;
-      s_qrange[1] = tend >= total_rows ? m : (uint64_t)row_meta[tend - 1 - rbase].z + 1;
-    }
     __syncthreads();
     if (tid < 64) {   // exclusive scan of the row counts (one wave)
       const uint32_t v = (uint32_t)__popcll(s_mask[tid]);
@@ -744,6 +711,8 @@ __global__ __launch_bounds__(256) void compact_write(
     }
     __syncthreads();
     const uint64_t prefix = tile_off[tile];
+    if (tid <= kTileRows && trow0 + tid <= total_rows)
+      row_pre[tile * kTileRows + tid] = prefix + s_pre[tid];
     const uint64_t wrow0 = trow0 + (uint64_t)w * kWaveRows;
     for (int it = 0; it < ITERS; ++it) {
       const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;
@@ -765,15 +734,31 @@ __global__ __launch_bounds__(256) void compact_write(
       for (int jr = 0; jr < ROWS; ++jr)
         if (write_ids && act[jr] && opos[jr] < cap) out_ids[opos[jr]] = idv[jr];
     }
-
-    const uint64_t valid = total_rows - trow0 < (uint64_t)kTileRows ? total_rows - trow0
-                                                                    : (uint64_t)kTileRows;
-    for (uint64_t qq = s_qrange[0] + tid; qq < s_qrange[1]; qq += 256) {
-      const uint64_t x = row_off[qq << ss] - trow0;
-      offsets[qq] = prefix + (x >= valid ? s_pre[kTileRows] : s_pre[x]);
-    }
-    if (tid == 0 && trow0 + valid == total_rows) offsets[m] = prefix + s_pre[kTileRows];
     __syncthreads();
+  }
+}
+
+// The CSR offsets of the queries whose first row lies in this chunk: query
+// j's offset is the output position of row row_off[j << ss] (a query with no
+// rows takes the position of the next row, trailing ones the total).  One
+// thread per query; the chunk owns rows [rbase, rend) below the total and,
+// if the total falls in (rbase, rend], the total itself.
+__global__ __launch_bounds__(256) void query_offsets(
+    const uint64_t* __restrict__ row_off, int ss, uint64_t m,
+    const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t rend, uint64_t row_end,
+    const uint64_t* __restrict__ row_pre, uint64_t* __restrict__ offsets) {
+  const uint64_t total_all = *total_rows_dev;
+  const uint64_t total = total_all < row_end ? total_all : row_end;
+  const bool owns_total = total == 0 ? rbase == 0 : (rbase < total && total <= rend);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= m; j += stride) {
+    uint64_t r = row_off[j << ss];
+    if (r > total) r = total;   // past the capacity (flagged as overflow)
+    if (r == total) {
+      if (owns_total) offsets[j] = total == 0 ? 0 : row_pre[r - rbase];
+    } else if (r >= rbase && r < rend) {
+      offsets[j] = row_pre[r - rbase];
+    }
   }
 }
 
@@ -857,7 +842,8 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
   if (tiles > kCompactChunkTiles) tiles = kCompactChunkTiles;
   if (tiles == 0) tiles = 1;
   return align256(tiles * kTileRows * 8) + align256(tiles * 4) + 2 * align256((tiles + 1) * 8) +
-         align256(tiles * kTileRows * 16) + scan_scratch_bytes(tiles);
+         align256(tiles * kTileRows * 16) + align256((tiles * kTileRows + 1) * 8) +
+         scan_scratch_bytes(tiles);
 }
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
@@ -954,6 +940,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
   toff[0] = (uint64_t*)p;             p += align256((ch_tiles + 1) * 8);
   toff[1] = (uint64_t*)p;             p += align256((ch_tiles + 1) * 8);
   uint4* meta = (uint4*)p;            p += align256(ch_tiles * kTileRows * 16);
+  uint64_t* rpre = (uint64_t*)p;      p += align256((ch_tiles * kTileRows + 1) * 8);
   uint64_t* stmp = (uint64_t*)p;
   const uint64_t* carry = nullptr;
   int buf = 0;
@@ -1010,9 +997,15 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
       // Eight rows per group, two groups per wave: measured fastest of the
       // shapes 16x1, 8x2, 4x4, 2x8, 1x16 (0.77 ms vs 0.99 ms for 4x4 at
       // 10^7 rows); more id loads in flight per wave.
-      compact_write<8, 2><<<grid, 256, 0, s>>>(ids, npts, m, qs.row_off, qs.ss, meta, total_dev,
-                                               rbase, row_end, masks, toff[buf], offsets,
-                                               out_ids, cap, chunks == 1);
+      compact_write<8, 2><<<grid, 256, 0, s>>>(ids, npts, meta, total_dev, rbase, row_end, masks,
+                                               toff[buf], rpre, out_ids, cap, chunks == 1);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+      ProfScope ps("query_offsets", s);
+      query_offsets<<<fill_blocks(m + 1), 256, 0, s>>>(qs.row_off, qs.ss, m, total_dev, rbase,
+                                                        rbase + nt * kCompactTileRows, row_end,
+                                                        rpre, offsets);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // The chunk's total, read by the next chunk's scan.  A chunk has tiles

@@ -60,6 +60,15 @@ def uniform_points(n: int, seed: int) -> np.ndarray:
     return _rng(seed).random((n, 2))
 
 
+def normal_points(n: int, seed: int, sigma: float = 0.125) -> np.ndarray:
+    """The paper's normal distribution (Sec. 4 "Data"): both coordinates
+    normal around the centre of the domain with standard deviation sigma
+    times its side (1/8), clamped to [0, 1 - 2^-53]."""
+    p = 0.5 + sigma * _rng(seed).standard_normal((n, 2))
+    np.clip(p, 0.0, ONE_BELOW, out=p)
+    return p
+
+
 def make_mixture(seed: int, k: int = 16, sigma: float = 0.01, frac: float = 0.8) -> Mixture:
     return Mixture(centres=_rng(seed).random((k, 2)), sigma=sigma, frac=frac)
 
@@ -134,14 +143,16 @@ def square_windows(n: int = 10_000_000, m: int = 1_000_000, side: float = 1e-3, 
                    seed: int = 6, points: str = "uniform") -> Workload:
     """The experiments' query shape (Sec. 4): uniform centres and square
     windows whose side is ``side`` times the side of the domain (delta =
-    side / 2, the half side; the domain is the unit square); uniform or
-    clustered points."""
+    side / 2, the half side; the domain is the unit square); uniform,
+    normal (the paper's query experiments) or clustered points."""
     if points == "uniform":
         pts = uniform_points(n, 1000 + seed)
+    elif points == "normal":
+        pts = normal_points(n, 1000 + seed)
     elif points == "clustered":
         pts = clustered_points(n, 1000 + seed, make_mixture(500 + seed))
     else:
-        raise ValueError("points must be 'uniform' or 'clustered'")
+        raise ValueError("points must be 'uniform', 'normal' or 'clustered'")
     q = uniform_points(m, 2000 + seed)
     d = np.full(m, side / 2)
     return Workload(f"{points}_n{n}_m{m}_window{side:g}", pts, q, d, curve)
