@@ -163,7 +163,8 @@ def learned_large_bench(args, sfc, workload, torch):
     offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
     out = {"workload": wl.name + "_morton", "n": n, "m": m}
     reps = []
-    for name, search in (("bsearch", sfc.BINARY), ("learned", sfc.LEARNED)):
+    for name, search in (("bsearch", sfc.BINARY), ("learned", sfc.LEARNED),
+                         ("stree", sfc.STREE)):
         torch.cuda.synchronize()
         sfc.profile_reset()
         sfc.profile_enable(True)
@@ -188,10 +189,13 @@ def learned_large_bench(args, sfc, workload, torch):
         sfc.profile_enable(False)
         kern = {k: v[1] / args.steps for k, v in sfc.profile_read().items()}
         out[name] = {"ms_per_batch": ms, "queries_per_s": m / (ms * 1e-3),
-                     "search_ms": kern.get("ranges_learned" if search else "ranges_search"),
+                     "search_ms": kern.get({sfc.BINARY: "ranges_search", sfc.LEARNED:
+                                            "ranges_learned", sfc.STREE: "ranges_stree"}[search]),
                      "kernels_ms_per_batch": kern,
-                     "build_ms": sum(v for k, v in build.items() if not k.startswith("learned_")),
-                     "fit_ms": sum(v for k, v in build.items() if k.startswith("learned_"))}
+                     "build_ms": sum(v for k, v in build.items()
+                                     if not k.startswith("learned_") and k != "stree_fill"),
+                     "fit_ms": sum(v for k, v in build.items()
+                                   if k.startswith("learned_") or k == "stree_fill")}
         if search == sfc.LEARNED:
             info = idx.learned_info()
             out[name]["model"] = {k: info[k] for k in ("leaves_nonempty", "max_leaf", "pieces",
@@ -199,10 +203,11 @@ def learned_large_bench(args, sfc, workload, torch):
                                                        "fallbacks_last")}
         idx.close()
         del out_ids
-    assert reps[0] == reps[1]
+    assert reps[0] == reps[1] == reps[2]
     out["reported_per_batch"] = reps[0]
     out["speedup_batch"] = out["bsearch"]["ms_per_batch"] / out["learned"]["ms_per_batch"]
     out["speedup_search"] = out["bsearch"]["search_ms"] / out["learned"]["search_ms"]
+    out["speedup_search_stree"] = out["bsearch"]["search_ms"] / out["stree"]["search_ms"]
     del pts, q, d
     torch.cuda.empty_cache()
     return out
@@ -477,7 +482,8 @@ def main():
     else:
         ms_qb, kern_qb, _, _, rep_qb = query_only(sfc.BINARY)
         ms_ql, kern_ql, fit_l, info_l, rep_ql = query_only(sfc.LEARNED)
-        assert rep_qb == rep_ql == total
+        ms_qs, kern_qs, _, _, rep_qs = query_only(sfc.STREE)
+        assert rep_qb == rep_ql == rep_qs == total
         lvb = {
             "step": "one query batch over a built index (refined ranges); the learned index is "
                     "fitted once beforehand",
@@ -499,6 +505,11 @@ def main():
                       ("steps", "loss_init", "loss_final", "leaves_nonempty", "max_leaf", "pieces",
                        "mean_window", "max_window", "search_steps", "endpoints_last",
                        "fallbacks_last")},
+            # the third search: the static search tree over the keys
+            "queries_per_s_stree": m / (ms_qs * 1e-3),
+            "ms_per_batch_stree": ms_qs,
+            "search_ms_stree": kern_qs.get("ranges_stree", float("nan")),
+            "kernels_ms_per_batch_stree": kern_qs,
         }
 
     # Algorithmic bytes per step of each kernel (what the method must move).

@@ -60,7 +60,14 @@ typedef enum {
 } sfc_status;
 
 enum { SFC_CURVE_MORTON = 0, SFC_CURVE_HILBERT = 1 };
-enum { SFC_SEARCH_BINARY = 0, SFC_SEARCH_LEARNED = 1 };
+/* The search that turns a key interval into an index range (all three give
+   the same ranges: std::lower_bound / std::upper_bound over the keys):
+   binary search; the learned index; the static search tree of Sec. 2.1
+   "Storing P twice" (a B+-tree over the keys whose lowest layer is the key
+   array and whose upper layers hold the first key of every 16-key line of
+   the layer below: about n/15 extra keys, one line read per layer, rebuilt
+   after inserts and compactions). */
+enum { SFC_SEARCH_BINARY = 0, SFC_SEARCH_LEARNED = 1, SFC_SEARCH_STREE = 2 };
 /* The exact test of a query (q, delta): SFC_METRIC_L2 reports the points of
    the closed Euclidean ball of radius delta (Sec. 2, Problem Statement);
    SFC_METRIC_LINF those of the closed axis-parallel square window of half
@@ -72,7 +79,8 @@ enum { SFC_METRIC_L2 = 0, SFC_METRIC_LINF = 1 };
 typedef struct {
   int curve;    /* SFC_CURVE_MORTON (Alg. 2) or SFC_CURVE_HILBERT */
   int search;   /* SFC_SEARCH_BINARY; SFC_SEARCH_LEARNED fits the learned
-                   index at build time (binary search stays the fallback) */
+                   index at build time (binary search stays the fallback);
+                   SFC_SEARCH_STREE builds the static search tree */
   int refine;   /* 0: scan the at most four cells of cells(Q) whole (Alg. 1);
                    1: split a crowded cell once and scan only its children
                    that meet the query box.  Same reported ids, same order. */
@@ -239,7 +247,8 @@ sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint6
  * radix sort are followed by stable passes over the set index, so the sorted
  * arrays hold the sets one after another, each in (key, id) order at its own
  * input positions.  Ids are input positions, as in sfc_build.  Binary search
- * only (SFC_SEARCH_LEARNED -> SFC_ERR_UNSUPPORTED).  Errors as sfc_build.
+ * only (another search or early_term -> SFC_ERR_UNSUPPORTED).  Errors as
+ * sfc_build.
  */
 sfc_status sfc_build_sets(const double* xy, const uint64_t* set_off, uint32_t n_sets,
                           const sfc_options* opt, sfc_index** out);
@@ -399,7 +408,9 @@ typedef struct {
 } sfc_learned_info;
 
 /* Selects the search for later queries; SFC_SEARCH_LEARNED fits the model
-   first if there is none (n >= 2).  Synchronises the stream. */
+   first if there is none (n >= 2), SFC_SEARCH_STREE builds the tree if it
+   is not built.  SFC_ERR_UNSUPPORTED for a search other than binary on an
+   index of point sets.  Synchronises the stream. */
 sfc_status sfc_set_search(sfc_index* h, int search);
 /* Selects the exact test (SFC_METRIC_L2 or SFC_METRIC_LINF) of later query
    batches, sfc_graph_query recordings included; a recorded graph keeps the

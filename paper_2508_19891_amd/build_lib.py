@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfc.so")
-SOURCES = ["api.hip", "build.hip", "query.hip", "scan.hip", "learned.hip", "update.hip"]
+SOURCES = ["api.hip", "build.hip", "query.hip", "scan.hip", "learned.hip", "update.hip",
+           "stree.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -217,6 +217,10 @@ struct sfc_index {
   // point sets (sfc_build_sets)
   uint32_t n_sets = 0;
   uint64_t* set_off = nullptr;     // device, n_sets + 1
+  // static search tree: layers above the keys (built while search is STREE)
+  void* stree = nullptr;
+  size_t stree_bytes = 0;
+  bool stree_ready = false;
   // early termination: occupancy bits of the quadtree nodes (null: off)
   uint32_t* occ = nullptr;
   uint64_t last_pruned = 0;
@@ -267,7 +271,9 @@ sfc_status from_hip(hipError_t e) {
 
 bool valid_options(const sfc_options& o) {
   if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT) return false;
-  if (o.search != SFC_SEARCH_BINARY && o.search != SFC_SEARCH_LEARNED) return false;
+  if (o.search != SFC_SEARCH_BINARY && o.search != SFC_SEARCH_LEARNED &&
+      o.search != SFC_SEARCH_STREE)
+    return false;
   if (o.refine != 0 && o.refine != 1) return false;
   if (o.early_term != 0 && o.early_term != 1) return false;
   if (o.metric != SFC_METRIC_L2 && o.metric != SFC_METRIC_LINF) return false;
@@ -326,6 +332,10 @@ void release_arrays(sfc_index* h) {
   h->alloc.put(h->upd_word);
   h->alloc.put(h->occ);
   h->occ = nullptr;
+  h->alloc.put(h->stree);
+  h->stree = nullptr;
+  h->stree_bytes = 0;
+  h->stree_ready = false;
   h->ins = h->era = nullptr;
   h->spare = sfc::Run{};
   h->spare_cap = 0;
@@ -344,6 +354,25 @@ void release_arrays(sfc_index* h) {
   h->ws_bytes = 0;
 }
 
+// The static search tree's layers above the current keys, (re)built on the
+// handle's stream; the buffer grows first when the keys outgrew it.
+sfc_status stree_refresh(sfc_index* h) {
+  const size_t need = sfc::stree_bytes(h->n);
+  if (need > h->stree_bytes) {
+    SFC_TRY(hipStreamSynchronize(h->stream));   // the old layers may still be read
+    h->alloc.put(h->stree);
+    h->stree = h->alloc.get(need);
+    h->stree_bytes = h->stree ? need : 0;
+    h->stree_ready = false;
+    if (!h->stree) return SFC_ERR_NOMEM;
+  }
+  SFC_TRY(sfc::stree_build(sfc::stree_view(h->keys, h->n, h->stree), h->stream));
+  h->stree_ready = true;
+  return SFC_OK;
+}
+
+bool stree_on(const sfc_index* h) { return h->search == SFC_SEARCH_STREE && h->stree_ready; }
+
 // Runs ranges + searches + scan; on SFC_OK *total_rows holds the number of
 // candidate rows and *total_cand the number of candidates.
 sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const uint32_t* qset,
@@ -356,8 +385,10 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   sfc::query_scratch_carve(h->ws, m, qs);
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
   const sfc::LearnedView lv = h->larr.view();
+  const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
   SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                             h->refine_min, learned ? &lv : nullptr, h->occ, qset,
+                             h->refine_min, learned ? &lv : nullptr, stree_on(h) ? &sv : nullptr,
+                             h->occ, qset,
                              qset ? h->set_off : nullptr,
                              h->n_sets, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
   if (qepoch)
@@ -649,6 +680,15 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
       return from_hip(e);
     }
   }
+  if (h->search == SFC_SEARCH_STREE) {
+    sfc_status st = stree_refresh(h);
+    if (st == SFC_OK) st = from_hip(hipStreamSynchronize(h->stream));
+    if (st != SFC_OK) {
+      release_arrays(h);
+      delete h;
+      return st;
+    }
+  }
   if (h->search == SFC_SEARCH_LEARNED && n >= 2 && !set_off_host) {
     sfc_status st = fit_learned(h, -1);
     if (st != SFC_OK) {
@@ -674,7 +714,7 @@ sfc_status sfc_build_sets(const double* xy, const uint64_t* set_off, uint32_t n_
   if (!set_off || n_sets < 1 || n_sets > 65536 || set_off[0] != 0) return SFC_ERR_INVALID;
   for (uint32_t i = 0; i < n_sets; ++i)
     if (set_off[i + 1] < set_off[i]) return SFC_ERR_INVALID;
-  if (opt && (opt->search == SFC_SEARCH_LEARNED || opt->early_term)) return SFC_ERR_UNSUPPORTED;
+  if (opt && (opt->search != SFC_SEARCH_BINARY || opt->early_term)) return SFC_ERR_UNSUPPORTED;
   return build_impl(xy, set_off[n_sets], set_off, n_sets, opt, out);
 }
 
@@ -770,10 +810,12 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
   sfc::query_scratch_carve(h->ws, m, &qs);
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted;
   const sfc::LearnedView lv = h->larr.view();
+  const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
   sfc::EpochView ev;
   const bool filtered = epoch_view(h, qepoch, &ev);
   SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                             h->refine_min, learned ? &lv : nullptr, h->occ, nullptr, nullptr, 0,
+                             h->refine_min, learned ? &lv : nullptr, stree_on(h) ? &sv : nullptr,
+                             h->occ, nullptr, nullptr, 0,
                              qs,
                              nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
   if (qepoch)
@@ -869,9 +911,16 @@ sfc_status sfc_last_query_stats(const sfc_index* h, sfc_query_stats* out) {
 }
 
 sfc_status sfc_set_search(sfc_index* h, int search) {
-  if (!h || (search != SFC_SEARCH_BINARY && search != SFC_SEARCH_LEARNED)) return SFC_ERR_INVALID;
+  if (!h || (search != SFC_SEARCH_BINARY && search != SFC_SEARCH_LEARNED &&
+             search != SFC_SEARCH_STREE))
+    return SFC_ERR_INVALID;
+  if (h->n_sets && search != SFC_SEARCH_BINARY) return SFC_ERR_UNSUPPORTED;
   if (search == SFC_SEARCH_LEARNED && !h->linfo.fitted && h->n >= 2) {
     sfc_status st = fit_learned(h, -1);
+    if (st != SFC_OK) return st;
+  }
+  if (search == SFC_SEARCH_STREE && !h->stree_ready) {
+    sfc_status st = stree_refresh(h);
     if (st != SFC_OK) return st;
   }
   h->search = search;
@@ -1046,6 +1095,8 @@ sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out) {
       e = sfc::sort_build(xy, h->n, h->curve, h->keys, h->ids, h->xy, g->scratch, g->err, s,
                           h->set_off, h->n_sets);
     if (e == hipSuccess && h->occ) e = sfc::build_occupancy(h->keys, h->n, h->occ, s);
+    if (e == hipSuccess && h->stree_ready)
+      e = sfc::stree_build(sfc::stree_view(h->keys, h->n, h->stree), s);
     return e;
   });
   if (st != SFC_OK) {
@@ -1080,11 +1131,13 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   sfc::query_scratch_carve(g->scratch, m, &g->qs);
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
   const sfc::LearnedView lv = h->larr.view();
+  const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
   sfc::EpochView ev;
   const bool filtered = epoch_view(h, nullptr, &ev);
   sfc_status st = graph_capture(g, [&](hipStream_t s) {
     hipError_t e = sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                                      h->refine_min, learned ? &lv : nullptr, h->occ, qset,
+                                      h->refine_min, learned ? &lv : nullptr,
+                                      stree_on(h) ? &sv : nullptr, h->occ, qset,
                                       qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr,
                                       nullptr, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess)
@@ -1423,6 +1476,10 @@ sfc_status compact_now(sfc_index* h) {
   h->n = keep;
   h->dead -= drop;
   if (h->occ) SFC_TRY(sfc::build_occupancy(h->keys, h->n, h->occ, h->stream));
+  if (h->stree_ready) {
+    sfc_status st2 = stree_refresh(h);
+    if (st2 != SFC_OK) return st2;
+  }
   std::vector<std::pair<uint32_t, uint64_t>> rest;
   for (const auto& t : h->tombs)
     if (t.first > h->oldest) rest.push_back(t);
@@ -1486,6 +1543,10 @@ sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_
   h->epoch = ep;
   h->max_ins = ep;
   if (h->occ) SFC_TRY(sfc::build_occupancy(h->keys, h->n, h->occ, h->stream));
+  if (h->stree_ready) {
+    st = stree_refresh(h);
+    if (st != SFC_OK) return st;
+  }
   if (!h->hold) h->oldest = ep;
   ++h->generation;
   ++h->merges;

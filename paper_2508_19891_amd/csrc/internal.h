@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "learned.h"
+#include "stree.h"
 
 namespace sfc {
 
@@ -77,17 +78,18 @@ size_t compact_scratch_bytes(uint64_t total_rows);
 
 // Ranges and searches per query slot, then the scan of candidate counts into
 // segment offsets; optionally records the ranges (dbg_* may be null).
-// lview non-null: searches go through the learned index.
+// lview non-null: searches go through the learned index; else sview
+// non-null: through the static search tree (both only without point sets).
 // occ non-null: cells whose occupancy bit is clear are skipped (early
 // termination; not applied when the ranges are recorded for inspection).
 // qset/set_off non-null: query j searches only set qset[j] (positions
 // [set_off[s], set_off[s+1]) of the sorted arrays).
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min,
-                         const LearnedView* lview, const uint32_t* occ, const uint32_t* qset,
-                         const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
-                         uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
-                         uint32_t* dbg_nr, hipStream_t s);
+                         const LearnedView* lview, const StreeView* sview, const uint32_t* occ,
+                         const uint32_t* qset, const uint64_t* set_off, uint32_t n_sets,
+                         QueryScratch& qs, uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b,
+                         uint64_t* dbg_e, uint32_t* dbg_nr, hipStream_t s);
 // Test-and-compact over the candidate rows.  device_sized = false: max_rows
 // is the exact row count (known on the host), processed in chunks.
 // device_sized = true: max_rows is a capacity, the count is read on the

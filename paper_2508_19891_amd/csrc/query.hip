@@ -29,6 +29,7 @@
 #include "curve.h"
 #include "internal.h"
 #include "learned.h"
+#include "stree.h"
 
 namespace sfc {
 
@@ -261,12 +262,19 @@ __device__ __forceinline__ void search_within(const uint64_t* __restrict__ keys,
 // Index range [b, e) of the key interval [klo, khi]: two binary searches, or
 // the learned index (whose lower bounds are verified and fall back to binary
 // search, so the result is the same).  *fb counts the fallbacks.
-template <bool LEARNED>
+// Index range [b, e) of the key interval [klo, khi]: SEARCH 0 binary
+// search, 1 the learned index, 2 the static search tree.
+template <int SEARCH>
 __device__ __forceinline__ void find_range(const uint64_t* __restrict__ keys, uint64_t n,
-                                           const LearnedView& lv, uint64_t klo, uint64_t khi,
-                                           uint64_t& b, uint64_t& e, uint32_t& fb) {
-  if (!LEARNED) {
+                                           const LearnedView& lv, const StreeView& sv,
+                                           uint64_t klo, uint64_t khi, uint64_t& b, uint64_t& e,
+                                           uint32_t& fb) {
+  if (SEARCH == 0) {
     search_pair(keys, n, klo, khi, b, e);
+    return;
+  }
+  if (SEARCH == 2) {
+    stree_range(sv, klo, khi, b, e);
     return;
   }
   // khi = 2^64 - 1 has no successor key: its bound is n, and the second
@@ -289,16 +297,17 @@ __device__ __forceinline__ void find_range(const uint64_t* __restrict__ keys, ui
 //     (consecutive children in key order), and each run is located by two
 //     searches inside the cell's index range.  Only points outside the box
 //     are dropped, so the reported set and its order are unchanged.
-template <int CURVE, bool REFINE, bool LEARNED>
+template <int CURVE, bool REFINE, int SEARCH>
 __global__ __launch_bounds__(256) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
-    const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, uint32_t refine_min,
-    const uint32_t* __restrict__ occ, const uint64_t* __restrict__ pairs,
+    const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, StreeView sv,
+    uint32_t refine_min, const uint32_t* __restrict__ occ, const uint64_t* __restrict__ pairs,
     const uint64_t* __restrict__ pair_total, const uint32_t* __restrict__ qset,
     const uint64_t* __restrict__ set_off, uint32_t n_sets, uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
     uint64_t* __restrict__ dbg_lo, uint64_t* __restrict__ dbg_hi, uint64_t* __restrict__ dbg_b,
     uint64_t* __restrict__ dbg_e, uint32_t* __restrict__ dbg_nr) {
+  constexpr bool LEARNED = SEARCH == 1;
   __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
   // Blocks past the listed pairs have nothing to do (uniform per block).
   if (pairs && (uint64_t)blockIdx.x * 256 >= *pair_total) return;
@@ -354,7 +363,7 @@ __global__ __launch_bounds__(256) void ranges_search(
       if (r < nr) {
         klo = lo[r];
         khi = hi[r];
-        find_range<LEARNED>(kseg, nn, lv, klo, khi, b0, e0, fb);
+        find_range<SEARCH>(kseg, nn, lv, sv, klo, khi, b0, e0, fb);
         b0 += base;
         e0 += base;
         ends += 2;
@@ -368,7 +377,7 @@ __global__ __launch_bounds__(256) void ranges_search(
       nr = query_cells<CURVE>(lut, qq.x, qq.y, d, lo, hi, cx, cy, &L, box, occ, &pr);
       if (r == 0 && !pairs) pruned = pr;
       if (r < nr) {
-        find_range<LEARNED>(kseg, nn, lv, lo[r], hi[r], b0, e0, fb);
+        find_range<SEARCH>(kseg, nn, lv, sv, lo[r], hi[r], b0, e0, fb);
         b0 += base;
         e0 += base;
         ends += 2;
@@ -848,10 +857,10 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min,
-                         const LearnedView* lview, const uint32_t* occ, const uint32_t* qset,
-                         const uint64_t* set_off, uint32_t n_sets, QueryScratch& qs,
-                         uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
-                         uint32_t* dbg_nr, hipStream_t s) {
+                         const LearnedView* lview, const StreeView* sview, const uint32_t* occ,
+                         const uint32_t* qset, const uint64_t* set_off, uint32_t n_sets,
+                         QueryScratch& qs, uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b,
+                         uint64_t* dbg_e, uint32_t* dbg_nr, hipStream_t s) {
   if (m == 0) return hipSuccess;
   const uint32_t blocks = (uint32_t)((4 * m + 255) / 256);
   hipError_t e;
@@ -859,7 +868,9 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   if (dbg_lo) refine = false;   // the inspected ranges are the method's merged ranges
   qs.ss = refine ? 3 : 2;
   const bool learned = lview != nullptr && qset == nullptr;
+  const bool stree = !learned && sview != nullptr && qset == nullptr;
   const LearnedView lv = learned ? *lview : LearnedView{};
+  const StreeView sv = stree ? *sview : StreeView{};
   unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
   // With early termination (and no inspected ranges) the search runs one
   // lane per surviving cell, from a dense list of (query, cell) pairs.
@@ -887,19 +898,21 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
     pair_total = (const uint64_t*)total;
   }
   {
-    ProfScope ps(learned ? "ranges_learned" : "ranges_search", s);
-#define SFC_RANGES(C, R, L)                                                                  \
-  ranges_search<C, R, L><<<blocks, 256, 0, s>>>(                                              \
-      (const double2*)q, delta, m, keys, n, lv, refine_min, dbg_lo ? nullptr : occ, pairs,   \
-      pair_total, qset, set_off, n_sets, qs.slot_begin,                                       \
+    ProfScope ps(learned ? "ranges_learned" : stree ? "ranges_stree" : "ranges_search", s);
+#define SFC_RANGES(C, R, S)                                                                  \
+  ranges_search<C, R, S><<<blocks, 256, 0, s>>>(                                              \
+      (const double2*)q, delta, m, keys, n, lv, sv, refine_min, dbg_lo ? nullptr : occ,       \
+      pairs, pair_total, qset, set_off, n_sets, qs.slot_begin,                                \
       qs.slot_count, qs.slot_rows, qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr)
+#define SFC_RANGES_R(C, R)                      \
+  if (learned) SFC_RANGES(C, R, 1);             \
+  else if (stree) SFC_RANGES(C, R, 2);          \
+  else SFC_RANGES(C, R, 0);
 #define SFC_RANGES_C(C)                         \
   if (refine) {                                 \
-    if (learned) SFC_RANGES(C, true, true);     \
-    else SFC_RANGES(C, true, false);            \
+    SFC_RANGES_R(C, true)                       \
   } else {                                      \
-    if (learned) SFC_RANGES(C, false, true);    \
-    else SFC_RANGES(C, false, false);           \
+    SFC_RANGES_R(C, false)                      \
   }
     if (curve == SFC_CURVE_HILBERT) {
       SFC_RANGES_C(SFC_CURVE_HILBERT)
@@ -907,6 +920,7 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
       SFC_RANGES_C(SFC_CURVE_MORTON)
     }
 #undef SFC_RANGES_C
+#undef SFC_RANGES_R
 #undef SFC_RANGES
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

@@ -27,6 +27,7 @@ MORTON = 0
 HILBERT = 1
 BINARY = 0
 LEARNED = 1
+STREE = 2   # static search tree over the keys
 L2 = 0      # closed Euclidean ball of radius delta
 LINF = 1    # closed axis-parallel square window of half side delta
 

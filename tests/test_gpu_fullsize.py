@@ -39,6 +39,7 @@ CONFIGS = [
     # (search, refine, metric, early_term, queries)
     (sfc.BINARY, True, L2, False, "clustered"),      # the headline step
     (sfc.LEARNED, True, L2, False, "clustered"),     # learned-index leg
+    (sfc.STREE, True, L2, False, "clustered"),       # static search tree
     (sfc.BINARY, False, L2, False, "clustered"),     # the method's ranges, unrefined
     (sfc.BINARY, True, L2, True, "uniform"),         # early-termination leg
     (sfc.BINARY, True, LINF, False, "clustered"),    # square windows
