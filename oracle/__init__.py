@@ -69,6 +69,22 @@ def lib():
         L.oracle_query.restype = i64
         L.oracle_brute.argtypes = [vp, u64, vp, vp, u64, vp, vp, u64, i32]
         L.oracle_brute.restype = i64
+        L.oracle_morton3.argtypes = [u32, u32, u32]
+        L.oracle_morton3.restype = u64
+        L.oracle_keys3.argtypes = [vp, u64, vp]
+        L.oracle_keys3.restype = i32
+        L.oracle_build3.argtypes = [vp, u64, vp, vp, vp]
+        L.oracle_build3.restype = i32
+        L.oracle_box3.argtypes = [vp, dbl, vp]
+        L.oracle_box3.restype = i32
+        L.oracle_ranges3.argtypes = [vp, dbl, vp, vp]
+        L.oracle_ranges3.restype = i32
+        L.oracle_box_ranges3.argtypes = [vp, vp, vp]
+        L.oracle_box_ranges3.restype = i32
+        L.oracle_query3.argtypes = [vp, vp, vp, u64, vp, vp, u64, vp, vp, u64, i32, i32]
+        L.oracle_query3.restype = i64
+        L.oracle_brute3.argtypes = [vp, u64, vp, vp, u64, vp, vp, u64, i32]
+        L.oracle_brute3.restype = i64
         _lib = L
     return _lib
 
@@ -221,3 +237,107 @@ def canonical(offsets, ids):
     m = offsets.shape[0] - 1
     qidx = np.repeat(np.arange(m, dtype=np.int64), np.diff(offsets))
     return np.sort(qidx * (1 << 32) + ids[: offsets[-1]])
+
+
+# ---- three dimensions (d = 3 Morton codes) ------------------------------------
+
+
+def _xyz(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 2 or a.shape[1] != 3:
+        raise ValueError("expected an (n, 3) array of float64")
+    return a
+
+
+def morton3(x: int, y: int, z: int) -> int:
+    return int(lib().oracle_morton3(x, y, z))
+
+
+def keys3(xyz) -> np.ndarray:
+    xyz = _xyz(xyz)
+    k = np.zeros(xyz.shape[0], np.uint64)
+    if lib().oracle_keys3(_p(xyz), xyz.shape[0], _p(k)) != 0:
+        raise DomainError("coordinate outside [0,1)")
+    return k
+
+
+def build3(xyz):
+    """(sorted keys u64, ids u32, points f64 (n, 3)) of a 3-D point set."""
+    xyz = _xyz(xyz)
+    n = xyz.shape[0]
+    k = np.zeros(n, np.uint64)
+    i = np.zeros(n, np.uint32)
+    s = np.zeros((n, 3), np.float64)
+    if lib().oracle_build3(_p(xyz), n, _p(k), _p(i), _p(s)) != 0:
+        raise DomainError("coordinate outside [0,1)")
+    return k, i, s
+
+
+def box3(q, delta: float):
+    """Widened integer box (lx, hx, ly, hy, lz, hz), or None when empty."""
+    qq = np.ascontiguousarray(q, np.float64)
+    b = np.zeros(6, np.int64)
+    r = lib().oracle_box3(_p(qq), delta, _p(b))
+    if r < 0:
+        raise InvalidQuery("invalid query")
+    return tuple(int(v) for v in b) if r == 1 else None
+
+
+def ranges3(q, delta: float):
+    """Merged key ranges [(lo, hi), ...] (inclusive) of a 3-D query, at most 8."""
+    qq = np.ascontiguousarray(q, np.float64)
+    lo = np.zeros(8, np.uint64)
+    hi = np.zeros(8, np.uint64)
+    k = lib().oracle_ranges3(_p(qq), delta, _p(lo), _p(hi))
+    if k < 0:
+        raise InvalidQuery("invalid query")
+    return [(int(lo[i]), int(hi[i])) for i in range(k)]
+
+
+def box_ranges3(box):
+    b = np.ascontiguousarray(box, np.int64)
+    lo = np.zeros(8, np.uint64)
+    hi = np.zeros(8, np.uint64)
+    k = lib().oracle_box_ranges3(_p(b), _p(lo), _p(hi))
+    if k < 0:
+        raise ValueError("box outside the domain")
+    return [(int(lo[i]), int(hi[i])) for i in range(k)]
+
+
+def query3(index, q, delta, nthreads: int = 1, metric: int = L2):
+    """CSR (offsets u64[m+1], ids u32[total]) of 3-D queries over build3's
+    output: ball of radius delta (L2) or cube of half side delta (LINF)."""
+    sk, si, sxyz = index
+    sk = np.ascontiguousarray(sk, np.uint64)
+    si = np.ascontiguousarray(si, np.uint32)
+    sxyz = _xyz(sxyz)
+    q = _xyz(q)
+    d = np.ascontiguousarray(delta, np.float64)
+    m = q.shape[0]
+    if d.shape != (m,):
+        raise ValueError("delta must have one entry per query")
+    off = np.zeros(m + 1, np.uint64)
+    L = lib()
+    tot = L.oracle_query3(_p(sk), _p(si), _p(sxyz), sk.shape[0], _p(q), _p(d), m, _p(off), None,
+                          0, nthreads, metric)
+    if tot < 0:
+        raise InvalidQuery("invalid query")
+    ids = np.zeros(max(int(tot), 1), np.uint32)
+    L.oracle_query3(_p(sk), _p(si), _p(sxyz), sk.shape[0], _p(q), _p(d), m, _p(off), _p(ids),
+                    int(tot), nthreads, metric)
+    return off, ids[: int(tot)]
+
+
+def brute3(xyz, q, delta, metric: int = L2):
+    xyz = _xyz(xyz)
+    q = _xyz(q)
+    d = np.ascontiguousarray(delta, np.float64)
+    m = q.shape[0]
+    off = np.zeros(m + 1, np.uint64)
+    L = lib()
+    tot = L.oracle_brute3(_p(xyz), xyz.shape[0], _p(q), _p(d), m, _p(off), None, 0, metric)
+    if tot < 0:
+        raise InvalidQuery("invalid query")
+    ids = np.zeros(max(int(tot), 1), np.uint32)
+    L.oracle_brute3(_p(xyz), xyz.shape[0], _p(q), _p(d), m, _p(off), _p(ids), int(tot), metric)
+    return off, ids[: int(tot)]

@@ -44,6 +44,13 @@
 //   * Hilbert: the four-state machine in hilbert_step() below, most
 //     significant level first, starting in state 0 at (0,0);
 //   * ranges of adjacent cells are merged (hi + 1 == next lo);
+//   * three dimensions (Sec. 1 and Sec. 2.1: the Z-order method generalises
+//     to R^d through d-dimensional Morton codes): points in [0,1)^3, 21 bits
+//     per axis (a 63-bit key), unit cell floor(v * 2^21); bit i of x, y, z at
+//     key positions 3i, 3i+1, 3i+2; cells(Q) are the at most 8 level-l cubes
+//     meeting the box; the test sums the three squares left to right,
+//        s = (dx*dx + dy*dy) + dz*dz <= d*d;
+//     the box widens by w = 1 + floor((|q_c| + delta) * 2^-29) quanta;
 //   * square windows (Sec. 4, the experiments' queries: an axis-parallel
 //     square of side delta relative to the domain): taken as the closed
 //     L-infinity ball of radius r = half the side around q, accepted iff
@@ -238,9 +245,267 @@ void query_one(const uint64_t* keys, const uint32_t* ids, const double* xy,
   }
 }
 
+// ---- three dimensions --------------------------------------------------------
+
+constexpr double kTwo21 = 2097152.0;            // 2^21
+constexpr double kTwo22 = 4194304.0;            // 2^22
+constexpr double kTwoM29 = 1.0 / 536870912.0;   // 2^-29
+constexpr int64_t kMaxCell3 = 2097151;          // 2^21 - 1
+
+bool quantize3(double v, uint32_t* u) {
+  if (!(v >= 0.0 && v < 1.0)) return false;
+  double s = std::floor(v * kTwo21);
+  if (s > (double)kMaxCell3) s = (double)kMaxCell3;
+  *u = (uint32_t)s;
+  return true;
+}
+
+// The d = 3 Morton code, bit by bit: x bit i -> key bit 3i, y -> 3i+1,
+// z -> 3i+2.
+uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  uint64_t key = 0;
+  for (int i = 0; i < 21; ++i) {
+    key |= (uint64_t)((x >> i) & 1u) << (3 * i);
+    key |= (uint64_t)((y >> i) & 1u) << (3 * i + 1);
+    key |= (uint64_t)((z >> i) & 1u) << (3 * i + 2);
+  }
+  return key;
+}
+
+bool within3(const double* p, const double* q, double delta) {
+  double dx = p[0] - q[0];
+  double dy = p[1] - q[1];
+  double dz = p[2] - q[2];
+  double t = dx * dx;
+  double u = dy * dy;
+  double v = dz * dz;
+  double s = t + u;
+  s = s + v;
+  double r2 = delta * delta;
+  return s <= r2;
+}
+
+bool within_window3(const double* p, const double* q, double delta) {
+  double dx = p[0] - q[0];
+  double dy = p[1] - q[1];
+  double dz = p[2] - q[2];
+  return std::fabs(dx) <= delta && std::fabs(dy) <= delta && std::fabs(dz) <= delta;
+}
+
+bool valid_query3(const double* q, double delta) {
+  return std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]) &&
+         std::isfinite(delta) && delta >= 0.0;
+}
+
+int64_t floor_clamped3(double v) {
+  if (v < -kTwo22) v = -kTwo22;
+  if (v > kTwo22) v = kTwo22;
+  return (int64_t)std::floor(v);
+}
+
+bool axis_box3(double c, double delta, int64_t* lo, int64_t* hi) {
+  double w_real = std::floor((std::fabs(c) + delta) * kTwoM29);
+  if (w_real > kTwo22) w_real = kTwo22;
+  int64_t w = 1 + (int64_t)w_real;
+  int64_t l = floor_clamped3((c - delta) * kTwo21) - w;
+  int64_t h = floor_clamped3((c + delta) * kTwo21) + w;
+  if (l < 0) l = 0;
+  if (h > kMaxCell3) h = kMaxCell3;
+  if (l > h) return false;
+  *lo = l;
+  *hi = h;
+  return true;
+}
+
+// Key intervals of the level-l cubes meeting the box b = {lx,hx,ly,hy,lz,hz},
+// sorted and merged (at most 8).
+int box_ranges3(const int64_t* b, Range out[8]) {
+  int64_t side = std::max(b[1] - b[0] + 1, std::max(b[3] - b[2] + 1, b[5] - b[4] + 1));
+  int level = 0;
+  while (((int64_t)1 << level) < side) ++level;
+  if (level >= 21) {
+    out[0] = Range{0, ((uint64_t)1 << 63) - 1};
+    return 1;
+  }
+  std::vector<Range> cells;
+  const uint64_t span = ((uint64_t)1 << (3 * level)) - 1;
+  for (int64_t cx = b[0] >> level; cx <= (b[1] >> level); ++cx)
+    for (int64_t cy = b[2] >> level; cy <= (b[3] >> level); ++cy)
+      for (int64_t cz = b[4] >> level; cz <= (b[5] >> level); ++cz) {
+        uint64_t key = morton3((uint32_t)(cx << level), (uint32_t)(cy << level),
+                               (uint32_t)(cz << level));
+        cells.push_back(Range{key & ~span, (key & ~span) | span});
+      }
+  std::sort(cells.begin(), cells.end(),
+            [](const Range& a, const Range& c) { return a.lo < c.lo; });
+  int k = 0;
+  for (const Range& r : cells) {
+    if (k > 0 && out[k - 1].hi + 1 == r.lo) {
+      out[k - 1].hi = r.hi;
+    } else {
+      out[k++] = r;
+    }
+  }
+  return k;
+}
+
+int ranges3(const double* q, double delta, Range out[8]) {
+  int64_t b[6];
+  for (int a = 0; a < 3; ++a)
+    if (!axis_box3(q[a], delta, &b[2 * a], &b[2 * a + 1])) return 0;
+  return box_ranges3(b, out);
+}
+
+void query3_one(const uint64_t* keys, const uint32_t* ids, const double* xyz, uint64_t n,
+                const double* q, double delta, int metric, std::vector<uint32_t>* out) {
+  Range r[8];
+  int k = ranges3(q, delta, r);
+  for (int i = 0; i < k; ++i) {
+    const uint64_t* b = std::lower_bound(keys, keys + n, r[i].lo);
+    const uint64_t* e = std::upper_bound(keys, keys + n, r[i].hi);
+    for (const uint64_t* p = b; p < e; ++p) {
+      uint64_t j = (uint64_t)(p - keys);
+      bool hit = metric == 1 ? within_window3(xyz + 3 * j, q, delta)
+                             : within3(xyz + 3 * j, q, delta);
+      if (hit) out->push_back(ids[j]);
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+uint64_t oracle_morton3(uint32_t x, uint32_t y, uint32_t z) { return morton3(x, y, z); }
+
+// Keys of n points (xyz interleaved).  Returns 0, or -2 for a coordinate
+// outside [0,1).
+int oracle_keys3(const double* xyz, uint64_t n, uint64_t* keys) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint32_t u[3];
+    for (int a = 0; a < 3; ++a)
+      if (!quantize3(xyz[3 * i + a], &u[a])) return -2;
+    keys[i] = morton3(u[0], u[1], u[2]);
+  }
+  return 0;
+}
+
+// Sort of (key, id) pairs, then the points in that order.
+int oracle_build3(const double* xyz, uint64_t n, uint64_t* keys_out, uint32_t* ids_out,
+                  double* xyz_out) {
+  std::vector<std::pair<uint64_t, uint32_t>> kv(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    uint32_t u[3];
+    for (int a = 0; a < 3; ++a)
+      if (!quantize3(xyz[3 * i + a], &u[a])) return -2;
+    kv[i] = {morton3(u[0], u[1], u[2]), (uint32_t)i};
+  }
+  std::sort(kv.begin(), kv.end());
+  for (uint64_t i = 0; i < n; ++i) {
+    keys_out[i] = kv[i].first;
+    ids_out[i] = kv[i].second;
+    for (int a = 0; a < 3; ++a) xyz_out[3 * i + a] = xyz[3 * (uint64_t)kv[i].second + a];
+  }
+  return 0;
+}
+
+// Widened integer box {lx,hx,ly,hy,lz,hz}: 1 non-empty, 0 empty, -1 invalid.
+int oracle_box3(const double* q, double delta, int64_t* box) {
+  if (!valid_query3(q, delta)) return -1;
+  for (int a = 0; a < 3; ++a)
+    if (!axis_box3(q[a], delta, &box[2 * a], &box[2 * a + 1])) return 0;
+  return 1;
+}
+
+// Merged key ranges of a query (at most 8), or -1 for an invalid query.
+int oracle_ranges3(const double* q, double delta, uint64_t* lo, uint64_t* hi) {
+  if (!valid_query3(q, delta)) return -1;
+  Range r[8];
+  int k = ranges3(q, delta, r);
+  for (int i = 0; i < k; ++i) {
+    lo[i] = r[i].lo;
+    hi[i] = r[i].hi;
+  }
+  return k;
+}
+
+// Merged key ranges of the cubes of an integer box inside [0, 2^21)^3, or -1.
+int oracle_box_ranges3(const int64_t* box, uint64_t* lo, uint64_t* hi) {
+  for (int a = 0; a < 3; ++a)
+    if (box[2 * a] < 0 || box[2 * a] > box[2 * a + 1] || box[2 * a + 1] > kMaxCell3) return -1;
+  Range r[8];
+  int k = box_ranges3(box, r);
+  for (int i = 0; i < k; ++i) {
+    lo[i] = r[i].lo;
+    hi[i] = r[i].hi;
+  }
+  return k;
+}
+
+// Batched 3-D queries over a built set; conventions as oracle_query.
+int64_t oracle_query3(const uint64_t* keys, const uint32_t* ids, const double* xyz, uint64_t n,
+                      const double* q, const double* delta, uint64_t m, uint64_t* offsets,
+                      uint32_t* out, uint64_t cap, int nthreads, int metric) {
+  if (metric != 0 && metric != 1) return -1;
+  for (uint64_t j = 0; j < m; ++j)
+    if (!valid_query3(q + 3 * j, delta[j])) return -1;
+  if (nthreads < 1) nthreads = 1;
+  std::vector<std::vector<uint32_t>> part(nthreads);
+  std::vector<std::vector<uint64_t>> cnt(nthreads);
+  auto work = [&](int t) {
+    uint64_t a = m * (uint64_t)t / (uint64_t)nthreads;
+    uint64_t b = m * (uint64_t)(t + 1) / (uint64_t)nthreads;
+    for (uint64_t j = a; j < b; ++j) {
+      size_t before = part[t].size();
+      query3_one(keys, ids, xyz, n, q + 3 * j, delta[j], metric, &part[t]);
+      cnt[t].push_back(part[t].size() - before);
+    }
+  };
+  if (nthreads == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthreads; ++t) pool.emplace_back(work, t);
+    for (auto& th : pool) th.join();
+  }
+  uint64_t total = 0, j = 0;
+  for (int t = 0; t < nthreads; ++t)
+    for (uint64_t c : cnt[t]) {
+      offsets[j++] = total;
+      total += c;
+    }
+  offsets[m] = total;
+  if (cap >= total) {
+    uint64_t at = 0;
+    for (int t = 0; t < nthreads; ++t) {
+      if (!part[t].empty()) std::memcpy(out + at, part[t].data(), part[t].size() * 4);
+      at += part[t].size();
+    }
+  }
+  return (int64_t)total;
+}
+
+// Brute force in 3-D, ids ascending per query.
+int64_t oracle_brute3(const double* xyz, uint64_t n, const double* q, const double* delta,
+                      uint64_t m, uint64_t* offsets, uint32_t* out, uint64_t cap, int metric) {
+  if (metric != 0 && metric != 1) return -1;
+  uint64_t total = 0;
+  for (uint64_t j = 0; j < m; ++j) {
+    if (!valid_query3(q + 3 * j, delta[j])) return -1;
+    offsets[j] = total;
+    for (uint64_t i = 0; i < n; ++i) {
+      bool hit = metric == 1 ? within_window3(xyz + 3 * i, q + 3 * j, delta[j])
+                             : within3(xyz + 3 * i, q + 3 * j, delta[j]);
+      if (hit) {
+        if (total < cap) out[total] = (uint32_t)i;
+        ++total;
+      }
+    }
+  }
+  offsets[m] = total;
+  return (int64_t)total;
+}
+
 
 uint64_t oracle_morton(uint32_t x, uint32_t y) { return morton(x, y); }
 uint64_t oracle_hilbert(uint32_t x, uint32_t y) { return hilbert(x, y); }
