@@ -59,7 +59,13 @@ typedef enum {
   SFC_ERR_UNSUPPORTED = -6
 } sfc_status;
 
-enum { SFC_CURVE_MORTON = 0, SFC_CURVE_HILBERT = 1 };
+/* SFC_CURVE_MORTON3: points in [0,1)^3 (x, y, z interleaved, three doubles
+   per point and per query) keyed by the d = 3 Morton code (Sec. 1 and
+   Sec. 2.1: the Z-order method generalises to R^d): 21 bits per axis, a
+   63-bit key, at most 8 cube ranges per query.  With it: binary search or
+   the static search tree, no refinement, no early termination, no point
+   sets, no updates, no range inspection (SFC_ERR_UNSUPPORTED). */
+enum { SFC_CURVE_MORTON = 0, SFC_CURVE_HILBERT = 1, SFC_CURVE_MORTON3 = 2 };
 /* The search that turns a key interval into an index range (all three give
    the same ranges: std::lower_bound / std::upper_bound over the keys):
    binary search; the learned index; the static search tree of Sec. 2.1

@@ -270,7 +270,9 @@ sfc_status from_hip(hipError_t e) {
   } while (0)
 
 bool valid_options(const sfc_options& o) {
-  if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT) return false;
+  if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT &&
+      o.curve != SFC_CURVE_MORTON3)
+    return false;
   if (o.search != SFC_SEARCH_BINARY && o.search != SFC_SEARCH_LEARNED &&
       o.search != SFC_SEARCH_STREE)
     return false;
@@ -373,6 +375,9 @@ sfc_status stree_refresh(sfc_index* h) {
 
 bool stree_on(const sfc_index* h) { return h->search == SFC_SEARCH_STREE && h->stree_ready; }
 
+// Coordinates per point and per query.
+int dim_of(const sfc_index* h) { return h->curve == SFC_CURVE_MORTON3 ? 3 : 2; }
+
 // Runs ranges + searches + scan; on SFC_OK *total_rows holds the number of
 // candidate rows and *total_cand the number of candidates.
 sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const uint32_t* qset,
@@ -386,11 +391,15 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
   const sfc::LearnedView lv = h->larr.view();
   const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
-  SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                             h->refine_min, learned ? &lv : nullptr, stree_on(h) ? &sv : nullptr,
-                             h->occ, qset,
-                             qset ? h->set_off : nullptr,
-                             h->n_sets, *qs, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr, h->stream));
+  if (dim_of(h) == 3)
+    SFC_TRY(sfc::launch_ranges3(q, delta, m, h->keys, h->n, stree_on(h) ? &sv : nullptr, *qs,
+                                h->stream));
+  else
+    SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
+                               h->refine_min, learned ? &lv : nullptr,
+                               stree_on(h) ? &sv : nullptr, h->occ, qset,
+                               qset ? h->set_off : nullptr, h->n_sets, *qs, dbg_lo, dbg_hi, dbg_b,
+                               dbg_e, dbg_nr, h->stream));
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs->counters + 2, h->stream));
   uint64_t* pin = sfc::pinned_scratch();
@@ -569,7 +578,8 @@ const char* sfc_status_string(sfc_status s) {
 
 sfc_status sfc_keys(const double* xy, uint64_t n, int curve, void* stream, uint64_t* keys) {
   if ((n > 0 && (!xy || !keys)) || n > 0xFFFFFFFFull) return SFC_ERR_INVALID;
-  if (curve != SFC_CURVE_MORTON && curve != SFC_CURVE_HILBERT) return SFC_ERR_INVALID;
+  if (curve != SFC_CURVE_MORTON && curve != SFC_CURVE_HILBERT && curve != SFC_CURVE_MORTON3)
+    return SFC_ERR_INVALID;
   if (n == 0) return SFC_OK;
   hipStream_t s = (hipStream_t)stream;
   sfc::Allocator a;
@@ -600,6 +610,9 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
   sfc_default_options(&o);
   if (opt) o = *opt;
   if (!out || (n > 0 && !xy) || n > 0xFFFFFFFFull || !valid_options(o)) return SFC_ERR_INVALID;
+  if (o.curve == SFC_CURVE_MORTON3 &&
+      (o.search == SFC_SEARCH_LEARNED || o.refine || o.early_term || set_off_host))
+    return SFC_ERR_UNSUPPORTED;
   sfc_index* h = new (std::nothrow) sfc_index();
   if (!h) return SFC_ERR_NOMEM;
   h->curve = o.curve;
@@ -635,7 +648,7 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
   if (n > 0) {
     h->keys = (uint64_t*)h->alloc.get(n * 8);
     h->ids = (uint32_t*)h->alloc.get(n * 4);
-    h->xy = (double*)h->alloc.get(n * 16);
+    h->xy = (double*)h->alloc.get(n * 8 * dim_of(h));
     const size_t sb = sfc::build_scratch_bytes(n) + 256;
     void* scratch = h->alloc.get(sb);
     if (!h->keys || !h->ids || !h->xy || !scratch) {
@@ -757,8 +770,8 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
     if (st != SFC_OK) return st;
   }
   SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_rows, false, h->cws,
-                              offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, h->stream,
-                              filtered ? &ev : nullptr));
+                              offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, dim_of(h),
+                              h->stream, filtered ? &ev : nullptr));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
   if (m > 0) {
@@ -813,16 +826,19 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
   const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
   sfc::EpochView ev;
   const bool filtered = epoch_view(h, qepoch, &ev);
-  SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                             h->refine_min, learned ? &lv : nullptr, stree_on(h) ? &sv : nullptr,
-                             h->occ, nullptr, nullptr, 0,
-                             qs,
-                             nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
+  if (dim_of(h) == 3)
+    SFC_TRY(sfc::launch_ranges3(q, delta, m, h->keys, h->n, stree_on(h) ? &sv : nullptr, qs,
+                                h->stream));
+  else
+    SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
+                               h->refine_min, learned ? &lv : nullptr,
+                               stree_on(h) ? &sv : nullptr, h->occ, nullptr, nullptr, 0, qs,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs.counters + 2, h->stream));
   SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, max_rows, true, h->cws,
-                              offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, h->stream,
-                              filtered ? &ev : nullptr));
+                              offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, dim_of(h),
+                              h->stream, filtered ? &ev : nullptr));
   SFC_TRY(hipMemcpyAsync(flags, qs.counters + 2, 4, hipMemcpyDeviceToDevice, h->stream));
   return SFC_OK;
 }
@@ -838,7 +854,8 @@ sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint6
   }
   h->pending.valid = false;
   SFC_TRY(sfc::launch_compact(nullptr, nullptr, p.m, h->xy, h->ids, h->n, p.qs, p.rows, false,
-                              h->cws, offsets, ids, ids_cap, false, h->stream, nullptr, true));
+                              h->cws, offsets, ids, ids_cap, false, dim_of(h), h->stream, nullptr,
+                              true));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + p.m, &total, 1, h->stream));
   if (total != p.total) return SFC_ERR_DEVICE;
@@ -866,6 +883,7 @@ sfc_status sfc_query_ranges(sfc_index* h, const double* q, const double* delta, 
                             uint32_t* nranges) {
   if (!h || (m > 0 && (!q || !delta || !key_lo || !key_hi || !begin || !end || !nranges)))
     return SFC_ERR_INVALID;
+  if (dim_of(h) == 3) return SFC_ERR_UNSUPPORTED;   // eight ranges per query, not four
   if (m == 0) return SFC_OK;
   sfc::QueryScratch qs{};
   uint64_t total_rows = 0, total_cand = 0;
@@ -890,7 +908,8 @@ sfc_status sfc_index_copy(const sfc_index* h, uint64_t* keys, uint32_t* ids, dou
   if (h->n == 0) return SFC_OK;
   if (keys) SFC_TRY(hipMemcpyAsync(keys, h->keys, h->n * 8, hipMemcpyDeviceToDevice, h->stream));
   if (ids) SFC_TRY(hipMemcpyAsync(ids, h->ids, h->n * 4, hipMemcpyDeviceToDevice, h->stream));
-  if (xy) SFC_TRY(hipMemcpyAsync(xy, h->xy, h->n * 16, hipMemcpyDeviceToDevice, h->stream));
+  if (xy)
+    SFC_TRY(hipMemcpyAsync(xy, h->xy, h->n * 8 * dim_of(h), hipMemcpyDeviceToDevice, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
   return SFC_OK;
 }
@@ -915,6 +934,7 @@ sfc_status sfc_set_search(sfc_index* h, int search) {
              search != SFC_SEARCH_STREE))
     return SFC_ERR_INVALID;
   if (h->n_sets && search != SFC_SEARCH_BINARY) return SFC_ERR_UNSUPPORTED;
+  if (dim_of(h) == 3 && search == SFC_SEARCH_LEARNED) return SFC_ERR_UNSUPPORTED;
   if (search == SFC_SEARCH_LEARNED && !h->linfo.fitted && h->n >= 2) {
     sfc_status st = fit_learned(h, -1);
     if (st != SFC_OK) return st;
@@ -1135,15 +1155,19 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   sfc::EpochView ev;
   const bool filtered = epoch_view(h, nullptr, &ev);
   sfc_status st = graph_capture(g, [&](hipStream_t s) {
-    hipError_t e = sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                                      h->refine_min, learned ? &lv : nullptr,
-                                      stree_on(h) ? &sv : nullptr, h->occ, qset,
-                                      qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr,
-                                      nullptr, nullptr, nullptr, nullptr, s);
+    hipError_t e =
+        dim_of(h) == 3
+            ? sfc::launch_ranges3(q, delta, m, h->keys, h->n, stree_on(h) ? &sv : nullptr, g->qs,
+                                  s)
+            : sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
+                                 h->refine_min, learned ? &lv : nullptr,
+                                 stree_on(h) ? &sv : nullptr, h->occ, qset,
+                                 qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, s);
     if (e == hipSuccess)
       e = sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, g->qs, max_rows, true,
-                              g->cscratch, offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, s,
-                              filtered ? &ev : nullptr);
+                              g->cscratch, offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF,
+                              dim_of(h), s, filtered ? &ev : nullptr);
     return e;
   });
   if (st != SFC_OK) {
@@ -1502,7 +1526,7 @@ extern "C" {
 
 sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_out) {
   if (!h || (k > 0 && !xy)) return SFC_ERR_INVALID;
-  if (h->n_sets) return SFC_ERR_UNSUPPORTED;
+  if (h->n_sets || dim_of(h) == 3) return SFC_ERR_UNSUPPORTED;
   if (k == 0) return SFC_OK;
   if ((uint64_t)h->next_id + k > 0xFFFFFFFEull) return SFC_ERR_INVALID;
   if (h->epoch >= 0xFFFFFFFEu) return SFC_ERR_UNSUPPORTED;
@@ -1558,7 +1582,7 @@ sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_
 
 sfc_status sfc_erase(sfc_index* h, const uint32_t* ids, uint64_t k, uint64_t* erased_out) {
   if (!h || (k > 0 && !ids)) return SFC_ERR_INVALID;
-  if (h->n_sets) return SFC_ERR_UNSUPPORTED;
+  if (h->n_sets || dim_of(h) == 3) return SFC_ERR_UNSUPPORTED;
   if (k == 0) {
     if (erased_out) *erased_out = 0;
     return SFC_OK;

@@ -98,6 +98,34 @@ __global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ 
   if (counts) store_tile_counts(h, counts, tiles, blockIdx.x);
 }
 
+// keygen_tiles for points in [0,1)^3 (three doubles each) and the d = 3
+// Morton code.
+__global__ __launch_bounds__(256) void keygen3_tiles(const double* __restrict__ xyz, uint64_t n,
+                                                    uint32_t tile_len, uint64_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ err,
+                                                    uint32_t* __restrict__ counts, uint64_t tiles) {
+  __shared__ uint32_t h[kSortWaves][kRadix];
+  for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * tile_len;
+  const uint64_t end = base + tile_len < n ? base + tile_len : n;
+  const uint32_t w = threadIdx.x >> 6;
+  bool bad = false;
+  for (uint64_t i = base + threadIdx.x; i < end; i += 256) {
+    const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    uint64_t key = 0;
+    if (in_unit(x) && in_unit(y) && in_unit(z)) {
+      key = morton3_key(quantize3(x), quantize3(y), quantize3(z));
+    } else {
+      bad = true;
+    }
+    keys[i] = key;
+    if (counts) atomicAdd(&h[w][key & 255u], 1u);
+  }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(err, kErrDomain);
+  if (counts) store_tile_counts(h, counts, tiles, blockIdx.x);
+}
+
 // Digit of an element in a pass: a byte of the key, or (SETPASS) a byte of
 // the point set the element's id belongs to.  Padding (id 0xFFFFFFFF) takes
 // digit 255 so that it sorts last.
@@ -308,6 +336,18 @@ __global__ void gather_points(const uint32_t* __restrict__ ids, const double2* _
   if (i < n) out[i] = xy[ids[i]];
 }
 
+__global__ void gather_points3(const uint32_t* __restrict__ ids, const double* __restrict__ xyz,
+                               double* __restrict__ out, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const uint64_t v = ids[i];
+    const double x = xyz[3 * v], y = xyz[3 * v + 1], z = xyz[3 * v + 2];
+    out[3 * i] = x;
+    out[3 * i + 1] = y;
+    out[3 * i + 2] = z;
+  }
+}
+
 // Keys per thread of a radix pass: 8, 12 or 16.  The environment variable
 // SFC_SORT_ITEMS overrides; else the autotuner's choice for this size; else 16.
 int sort_items(uint64_t n) {
@@ -391,7 +431,9 @@ hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, 
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
   ProfScope ps("keygen_tiles", s);
-  if (curve == SFC_CURVE_HILBERT)
+  if (curve == SFC_CURVE_MORTON3)
+    keygen3_tiles<<<(uint32_t)tiles, 256, 0, s>>>(xy, n, tile, keys, err, counts, tiles);
+  else if (curve == SFC_CURVE_HILBERT)
     keygen_tiles<SFC_CURVE_HILBERT><<<(uint32_t)tiles, 256, 0, s>>>((const double2*)xy, n, tile,
                                                                     keys, err, counts, tiles);
   else
@@ -444,7 +486,8 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     uint32_t* vout = fin ? ids_out : ids_b;
     const bool setpass = pass >= kDigits;
     const int shift = setpass ? 8 * (pass - kDigits) : 8 * pass;
-    const bool gather = pass == passes - 1;
+    // The points travel with the last pass (in 3-D they are gathered after it).
+    const bool gather = pass == passes - 1 && curve != SFC_CURVE_MORTON3;
     if (pass > 0) {
       ProfScope ps("tile_hist", s);
       if (setpass)
@@ -473,6 +516,11 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     if (e != hipSuccess) return e;
     kin = kout;
     vin = vout;
+  }
+  if (curve == SFC_CURVE_MORTON3) {
+    ProfScope ps("gather_points3", s);
+    gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids_out, xy, xy_out, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }

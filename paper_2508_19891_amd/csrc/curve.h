@@ -34,6 +34,31 @@ __host__ __device__ __forceinline__ uint64_t morton_key(uint32_t x, uint32_t y) 
   return spread_bits(x) | (spread_bits(y) << 1);
 }
 
+// Three dimensions (the d-dimensional Morton code of Sec. 1 / Sec. 2.1 for
+// d = 3): 21 bits per axis, cell floor(v * 2^21); x's bit i at key bit 3i,
+// y's at 3i+1, z's at 3i+2 (a 63-bit key).
+constexpr double kTwo21 = 2097152.0;   // 2^21
+constexpr uint32_t kMaxCell3 = 2097151u;
+
+__host__ __device__ __forceinline__ uint32_t quantize3(double v) {
+  return (uint32_t)__builtin_floor(v * kTwo21);
+}
+
+// Spreads the low 21 bits of v to every third bit position.
+__host__ __device__ __forceinline__ uint64_t spread_bits3(uint32_t v) {
+  uint64_t x = v & 0x1FFFFFu;
+  x = (x | (x << 32)) & 0x001F00000000FFFFull;
+  x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+  x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+  x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__host__ __device__ __forceinline__ uint64_t morton3_key(uint32_t x, uint32_t y, uint32_t z) {
+  return spread_bits3(x) | (spread_bits3(y) << 1) | (spread_bits3(z) << 2);
+}
+
 // Hilbert order.  The frame of a sub-square is one of four symmetries of the
 // square, kept as two bits: bit 0 = x and y exchanged, bit 1 = both
 // complemented.  At each level the pair of coordinate bits is mapped into the

@@ -90,18 +90,25 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
                          const uint32_t* qset, const uint64_t* set_off, uint32_t n_sets,
                          QueryScratch& qs, uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b,
                          uint64_t* dbg_e, uint32_t* dbg_nr, hipStream_t s);
+// Three dimensions (points and queries of three doubles, d = 3 Morton keys):
+// the at most 8 cube ranges of every query and their searches (binary, or the
+// static search tree when sview is non-null), then the scan, as
+// launch_ranges.
+hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
+                          uint64_t n, const StreeView* sview, QueryScratch& qs, hipStream_t s);
 // Test-and-compact over the candidate rows.  device_sized = false: max_rows
 // is the exact row count (known on the host), processed in chunks.
 // device_sized = true: max_rows is a capacity, the count is read on the
 // device (a plan for graph capture); more rows raise kErrOverflow.  cscratch
 // holds compact_scratch_bytes(max_rows).  window: the square-window test
-// (half side delta) instead of the Euclidean ball.
+// (half side delta) instead of the Euclidean ball.  dim: 2, or 3 for points
+// and queries of three doubles.
 struct EpochView;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
-                          hipStream_t s,
+                          int dim, hipStream_t s,
                           const EpochView* ev = nullptr, bool write_only = false);
 // Whether a batch of total_rows rows (host-sized) is compacted in one chunk:
 // then an output larger than the capacity leaves the ids untouched, and the

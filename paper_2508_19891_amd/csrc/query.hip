@@ -475,6 +475,135 @@ __global__ __launch_bounds__(256) void ranges_search(
   }
 }
 
+// ---- three dimensions (d = 3 Morton codes) ------------------------------------
+
+constexpr double kTwo22 = 4194304.0;            // 2^22
+constexpr double kTwoM29 = 1.0 / 536870912.0;   // 2^-29
+
+// The d = 3 test: the squares summed left to right, no contraction.
+__device__ __forceinline__ bool within3(double px, double py, double pz, double qx, double qy,
+                                        double qz, double d) {
+#pragma clang fp contract(off)
+  const double dx = px - qx;
+  const double dy = py - qy;
+  const double dz = pz - qz;
+  const double t = dx * dx;
+  const double u = dy * dy;
+  const double v = dz * dz;
+  const double s = (t + u) + v;
+  return s <= d * d;
+}
+
+__device__ __forceinline__ bool within_window3(double px, double py, double pz, double qx,
+                                               double qy, double qz, double d) {
+#pragma clang fp contract(off)
+  const double dx = px - qx;
+  const double dy = py - qy;
+  const double dz = pz - qz;
+  return fabs(dx) <= d && fabs(dy) <= d && fabs(dz) <= d;
+}
+
+// One axis of the widened box on the 2^21 grid: w = 1 + floor((|c| + d)
+// 2^-29) quanta cover the rounding of the test.
+__device__ __forceinline__ bool axis_box3(double c, double d, int64_t& lo, int64_t& hi) {
+#pragma clang fp contract(off)
+  double wr = __builtin_floor((__builtin_fabs(c) + d) * kTwoM29);
+  wr = wr > kTwo22 ? kTwo22 : wr;
+  const int64_t w = 1 + (int64_t)wr;
+  double a = (c - d) * kTwo21, b = (c + d) * kTwo21;
+  a = a < -kTwo22 ? -kTwo22 : (a > kTwo22 ? kTwo22 : a);
+  b = b < -kTwo22 ? -kTwo22 : (b > kTwo22 ? kTwo22 : b);
+  int64_t l = (int64_t)__builtin_floor(a) - w;
+  int64_t h = (int64_t)__builtin_floor(b) + w;
+  l = l < 0 ? 0 : l;
+  h = h > (int64_t)kMaxCell3 ? (int64_t)kMaxCell3 : h;
+  lo = l;
+  hi = h;
+  return l <= h;
+}
+
+// Merged key intervals of the level-l cubes meeting the widened box (at most
+// 8), ascending and non-adjacent.
+__device__ int query_ranges3(double qx, double qy, double qz, double d, uint64_t lo[8],
+                             uint64_t hi[8]) {
+  int64_t b[6];
+  if (!axis_box3(qx, d, b[0], b[1]) || !axis_box3(qy, d, b[2], b[3]) ||
+      !axis_box3(qz, d, b[4], b[5]))
+    return 0;
+  uint64_t side = (uint64_t)(b[1] - b[0] + 1);
+  side = (uint64_t)(b[3] - b[2] + 1) > side ? (uint64_t)(b[3] - b[2] + 1) : side;
+  side = (uint64_t)(b[5] - b[4] + 1) > side ? (uint64_t)(b[5] - b[4] + 1) : side;
+  const int L = side <= 1 ? 0 : 64 - __clzll(side - 1);
+  if (L >= 21) {
+    lo[0] = 0;
+    hi[0] = (1ull << 63) - 1;
+    return 1;
+  }
+  const uint64_t span = (1ull << (3 * L)) - 1;
+  int k = 0;
+  for (uint32_t cx = (uint32_t)(b[0] >> L); cx <= (uint32_t)(b[1] >> L); ++cx)
+    for (uint32_t cy = (uint32_t)(b[2] >> L); cy <= (uint32_t)(b[3] >> L); ++cy)
+      for (uint32_t cz = (uint32_t)(b[4] >> L); cz <= (uint32_t)(b[5] >> L); ++cz) {
+        const uint64_t key = morton3_key(cx << L, cy << L, cz << L) & ~span;
+        int t = k++;
+        for (; t > 0 && lo[t - 1] > key; --t) lo[t] = lo[t - 1];
+        lo[t] = key;
+      }
+  int r = 0;
+  for (int i = 0; i < k; ++i) {
+    if (r > 0 && hi[r - 1] + 1 == lo[i]) {
+      hi[r - 1] = lo[i] | span;
+    } else {
+      lo[r] = lo[i];
+      hi[r] = lo[i] | span;
+      ++r;
+    }
+  }
+  return r;
+}
+
+// One lane per (query, slot), eight slots per query: every lane derives the
+// query's cubes, slot r searches interval r.
+template <int SEARCH>
+__global__ __launch_bounds__(256) void ranges_search3(
+    const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
+    const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, StreeView sv,
+    uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
+    uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total) {
+  const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t j = g >> 3;
+  const int r = (int)(g & 7);
+  uint64_t b0 = 0, e0 = 0;
+  uint32_t fb = 0;
+  bool bad = false;
+  if (j < m) {
+    const double qx = q[3 * j], qy = q[3 * j + 1], qz = q[3 * j + 2], d = delta[j];
+    if (!(finite(qx) && finite(qy) && finite(qz) && finite(d) && d >= 0.0)) {
+      bad = true;
+    } else {
+      uint64_t lo[8], hi[8];
+      const int nr = query_ranges3(qx, qy, qz, d, lo, hi);
+      if (r < nr) find_range<SEARCH>(keys, n, lv, sv, lo[r], hi[r], b0, e0, fb);
+    }
+  }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&counters[2], kErrInvalidQuery);
+  __shared__ unsigned long long s_c[4];
+  unsigned long long wc = e0 - b0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wc += __shfl_xor(wc, o, 64);
+  if (lane_id() == 0) s_c[threadIdx.x >> 6] = wc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+    if (t) atomicAdd(cand_total, t);
+  }
+  if (j < m) {
+    slot_begin[g] = (uint32_t)b0;
+    slot_count[g] = (uint32_t)(e0 - b0);
+    slot_rows[g] = (uint32_t)((e0 - b0 + 63) >> 6);
+  }
+}
+
 // The cells of every query that survive early termination, as a dense work
 // list of (query, cell) pairs (4 * query + cell) for the search.  One thread
 // per query; a block's pairs are contiguous, at a base taken with one atomic
@@ -617,10 +746,10 @@ __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ 
 // EPOCH: a candidate that passes the test also has to be visible at the
 // query's epoch (ins <= e < era); only those lanes read the epochs.
 // window: the square-window test instead of the Euclidean one.
-template <int ROWS, int ITERS, bool EPOCH>
+template <int ROWS, int ITERS, bool EPOCH, int DIM>
 __global__ __launch_bounds__(256) void compact_test(
-    const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
-    const double2* __restrict__ pts, uint64_t npts, const uint4* __restrict__ row_meta,
+    const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
+    const double* __restrict__ pts, uint64_t npts, const uint4* __restrict__ row_meta,
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     bool flag_overflow, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits,
     uint32_t* counters, const uint32_t* __restrict__ ins, const uint32_t* __restrict__ era,
@@ -638,7 +767,7 @@ __global__ __launch_bounds__(256) void compact_test(
       uint4 md = make_uint4(0, 0, 0, 0);
       if (lane < (uint32_t)ROWS && g0 + lane < total_rows) md = row_meta[g0 + lane - rbase];
       uint32_t pos[ROWS];
-      double qx[ROWS], qy[ROWS], dd[ROWS];
+      double qx[ROWS], qy[ROWS], qz[ROWS], dd[ROWS];
       uint32_t qe[ROWS];
       bool act[ROWS];
 #pragma unroll
@@ -650,20 +779,43 @@ __global__ __launch_bounds__(256) void compact_test(
         act[jr] = lane < nv && p64 < npts && qi < m;
         pos[jr] = act[jr] ? (uint32_t)p64 : 0u;
         const uint32_t qs = qi < m ? qi : 0u;
-        const double2 qq = q[qs];
-        qx[jr] = qq.x;
-        qy[jr] = qq.y;
+        if (DIM == 2) {
+          const double2 qq = ((const double2*)q)[qs];
+          qx[jr] = qq.x;
+          qy[jr] = qq.y;
+        } else {
+          qx[jr] = q[3 * (uint64_t)qs];
+          qy[jr] = q[3 * (uint64_t)qs + 1];
+          qz[jr] = q[3 * (uint64_t)qs + 2];
+        }
         dd[jr] = delta[qs];
         if (EPOCH) qe[jr] = qepoch ? qepoch[qs] : epoch;
       }
       double2 pv[ROWS];
-#pragma unroll
-      for (int jr = 0; jr < ROWS; ++jr)
-        if (act[jr]) pv[jr] = pts[pos[jr]];
+      double pz[ROWS];
 #pragma unroll
       for (int jr = 0; jr < ROWS; ++jr) {
-        bool hit = act[jr] && (window ? within_window(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr])
-                                      : within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]));
+        if (act[jr]) {
+          if (DIM == 2) {
+            pv[jr] = ((const double2*)pts)[pos[jr]];
+          } else {
+            pv[jr].x = pts[3 * (uint64_t)pos[jr]];
+            pv[jr].y = pts[3 * (uint64_t)pos[jr] + 1];
+            pz[jr] = pts[3 * (uint64_t)pos[jr] + 2];
+          }
+        }
+      }
+#pragma unroll
+      for (int jr = 0; jr < ROWS; ++jr) {
+        bool hit;
+        if (DIM == 2)
+          hit = act[jr] && (window ? within_window(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr])
+                                   : within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]));
+        else
+          hit = act[jr] && (window ? within_window3(pv[jr].x, pv[jr].y, pz[jr], qx[jr], qy[jr],
+                                                    qz[jr], dd[jr])
+                                   : within3(pv[jr].x, pv[jr].y, pz[jr], qx[jr], qy[jr], qz[jr],
+                                             dd[jr]));
         if (EPOCH && hit) hit = ins[pos[jr]] <= qe[jr] && qe[jr] < era[pos[jr]];
         const uint64_t bal = __ballot(hit);
         cnt += (uint32_t)__popcll(bal);
@@ -930,11 +1082,34 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
 // Blocks of the compaction kernels (grid-stride over tiles beyond this).
 constexpr uint64_t kCompactGrid = 4096;
 
+hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
+                          uint64_t n, const StreeView* sview, QueryScratch& qs, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipError_t e;
+  if ((e = fill_u32(qs.counters, 0, 16, s)) != hipSuccess) return e;
+  qs.ss = 3;
+  const uint32_t blocks = (uint32_t)((8 * m + 255) / 256);
+  unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
+  const LearnedView lv{};
+  {
+    ProfScope ps(sview ? "ranges_stree3" : "ranges_search3", s);
+    if (sview)
+      ranges_search3<2><<<blocks, 256, 0, s>>>(q, delta, m, keys, n, lv, *sview, qs.slot_begin,
+                                               qs.slot_count, qs.slot_rows, qs.counters, cand);
+    else
+      ranges_search3<0><<<blocks, 256, 0, s>>>(q, delta, m, keys, n, lv, StreeView{},
+                                               qs.slot_begin, qs.slot_count, qs.slot_rows,
+                                               qs.counters, cand);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return scan_excl(qs.slot_rows, qs.row_off, m << qs.ss, nullptr, qs.scan_tmp, s);
+}
+
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
-                          hipStream_t s, const EpochView* ev, bool write_only) {
+                          int dim, hipStream_t s, const EpochView* ev, bool write_only) {
   hipError_t e;
   if (m == 0) return fill_u64(offsets, 0, 1, s);
   const uint64_t nseg = m << qs.ss;
@@ -982,10 +1157,16 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
     if (!write_only) {
       ProfScope ps("compact_test", s);
 #define SFC_TEST(R, I, E)                                                                  \
-  compact_test<R, I, E><<<grid, 256, 0, s>>>(                                             \
-      (const double2*)q, delta, m, (const double2*)pts, npts, meta, total_dev, rbase,     \
-      row_end, flag, masks, hits, qs.counters, ev ? ev->ins : nullptr,                    \
-      ev ? ev->era : nullptr, ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u, window)
+  if (dim == 3)                                                                            \
+    compact_test<R, I, E, 3><<<grid, 256, 0, s>>>(                                         \
+        q, delta, m, pts, npts, meta, total_dev, rbase, row_end, flag, masks, hits,        \
+        qs.counters, ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                       \
+        ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u, window);                           \
+  else                                                                                     \
+    compact_test<R, I, E, 2><<<grid, 256, 0, s>>>(                                         \
+        q, delta, m, pts, npts, meta, total_dev, rbase, row_end, flag, masks, hits,        \
+        qs.counters, ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                       \
+        ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u, window)
 #define SFC_TEST_SHAPES(E)                  \
   switch (test_variant(max_rows)) {         \
     case 1: SFC_TEST(4, 4, E); break;       \

@@ -25,6 +25,7 @@ SFC_ERR_UNSUPPORTED = -6
 
 MORTON = 0
 HILBERT = 1
+MORTON3 = 2   # points in [0,1)^3, d = 3 Morton keys
 BINARY = 0
 LEARNED = 1
 STREE = 2   # static search tree over the keys
@@ -240,7 +241,8 @@ def current_stream_handle() -> int:
 
 
 def sfc_keys(xy: torch.Tensor, curve: int = MORTON) -> torch.Tensor:
-    """Curve keys of the points (n, 2) float64 -> (n,) uint64 (as int64 bits)."""
+    """Curve keys of the points (n, 2) float64, or (n, 3) for MORTON3 ->
+    (n,) uint64 (as int64 bits)."""
     xy = _dev(xy, torch.float64, "xy")
     n = xy.shape[0]
     keys = torch.empty(n, dtype=torch.int64, device=xy.device)
@@ -260,8 +262,9 @@ class Index:
         L2 (ball of radius delta) or LINF (square window of half side
         delta)."""
         xy = _dev(xy, torch.float64, "xy")
-        if xy.ndim != 2 or xy.shape[1] != 2:
-            raise ValueError("xy must have shape (n, 2)")
+        self.dim = 3 if curve == MORTON3 else 2
+        if xy.ndim != 2 or xy.shape[1] != self.dim:
+            raise ValueError(f"xy must have shape (n, {self.dim})")
         L = lib()
         opt = Options()
         L.sfc_default_options(ctypes.byref(opt))
@@ -316,7 +319,7 @@ class Index:
         n = self.size()
         keys = torch.empty(n, dtype=torch.int64, device=self.device)
         ids = torch.empty(n, dtype=torch.int32, device=self.device)
-        xy = torch.empty((n, 2), dtype=torch.float64, device=self.device)
+        xy = torch.empty((n, self.dim), dtype=torch.float64, device=self.device)
         _check(lib().sfc_index_copy(self.handle, _ptr(keys), _ptr(ids), _ptr(xy)),
                "sfc_index_copy")
         return keys, ids, xy
@@ -331,8 +334,8 @@ class Index:
         q = _dev(q, torch.float64, "q")
         delta = _dev(delta, torch.float64, "delta")
         m = q.shape[0]
-        if q.ndim != 2 or q.shape[1] != 2 or delta.shape != (m,):
-            raise ValueError("q must be (m, 2) and delta (m,)")
+        if q.ndim != 2 or q.shape[1] != self.dim or delta.shape != (m,):
+            raise ValueError(f"q must be (m, {self.dim}) and delta (m,)")
         offsets = out_offsets if out_offsets is not None else torch.empty(
             m + 1, dtype=torch.int64, device=self.device)
         auto = ids_cap is None and out_ids is None   # may retry with the exact size
@@ -445,6 +448,8 @@ class Index:
     def insert(self, xy: torch.Tensor, want_ids: bool = True):
         """Inserts points (k, 2); returns their ids (int32 tensor) or None."""
         xy = _dev(xy, torch.float64, "xy")
+        if xy.ndim != 2 or xy.shape[1] != self.dim:
+            raise ValueError(f"xy must have shape (k, {self.dim})")
         k = xy.shape[0]
         ids = torch.empty(k, dtype=torch.int32, device=self.device) if want_ids else None
         _check(lib().sfc_insert(self.handle, _ptr(xy), k, _ptr(ids)), "sfc_insert")

@@ -158,6 +158,35 @@ def square_windows(n: int = 10_000_000, m: int = 1_000_000, side: float = 1e-3, 
     return Workload(f"{points}_n{n}_m{m}_window{side:g}", pts, q, d, curve)
 
 
+def clustered3(n: int = 1 << 24, m: int = 1 << 20, seed: int = 9, c_lo: float = 1.0,
+               c_hi: float = 300.0, frac: float = 0.8, sigma: float = 0.02,
+               k: int = 16) -> Workload:
+    """Three dimensions: a fraction ``frac`` of the points from k isotropic
+    Gaussians (uniform centres, standard deviation sigma), the rest uniform in
+    [0,1)^3, clamped and shuffled; queries from the same mixture, delta aimed
+    at c ~ logU[c_lo, c_hi] reports: delta = (3 c / (4 pi n f(q)))^(1/3) with
+    f the mixture's analytic density.  curve is 2 (d = 3 Morton)."""
+    rng = _rng(1000 + seed)
+    centres = _rng(500 + seed).random((k, 3))
+
+    def sample(cnt, r):
+        nc = (int(round(frac * 1000)) * cnt) // 1000
+        comp = r.integers(0, k, nc)
+        pc = centres[comp] + sigma * r.standard_normal((nc, 3))
+        p = np.concatenate([pc, r.random((cnt - nc, 3))], axis=0)
+        np.clip(p, 0.0, ONE_BELOW, out=p)
+        return p[r.permutation(cnt)]
+
+    pts = sample(n, rng)
+    q = sample(m, _rng(2000 + seed))
+    d2 = ((q[:, None, :] - centres[None, :, :]) ** 2).sum(-1)
+    g = np.exp(-d2 / (2.0 * sigma ** 2)) / (2.0 * math.pi * sigma ** 2) ** 1.5
+    f = (1.0 - frac) + (frac / k) * g.sum(1)
+    c = loguniform(_rng(3000 + seed), c_lo, c_hi, m)
+    d = np.cbrt(3.0 * c / (4.0 * math.pi * n * f))
+    return Workload(f"clustered3_n{n}_m{m}_loguniform", pts, q, d, 2)
+
+
 @dataclasses.dataclass
 class BatchedWorkload:
     name: str

@@ -1,0 +1,142 @@
+"""Three dimensions (d = 3 Morton keys) through the C ABI against the 3-D
+oracle: keys, sorted arrays, query results (ball and cube window, binary
+search and the static search tree), edge cases, recorded graphs, and the
+options three dimensions refuse."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import L2, LINF
+from paper_2508_19891_amd import sfc, workload
+from test_oracle3 import _adversarial3
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+M3 = sfc.MORTON3
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(DEV)
+
+
+def check(idx, pts, qs, ds, metric=L2):
+    ref = oracle.query3(oracle.build3(pts), qs, ds, nthreads=4, metric=metric)
+    off, ids = idx.query(dev(qs), dev(ds))
+    assert np.array_equal(off.cpu().numpy().view(np.uint64), ref[0])
+    assert np.array_equal(ids.cpu().numpy().view(np.uint32), ref[1])
+    return ref
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 100_003])
+def test_keys_and_sorted_arrays(n):
+    rng = np.random.default_rng(90 + n)
+    pts = rng.random((n, 3))
+    if n > 10:
+        pts[n // 2:n // 2 + 50] = pts[:50]
+    keys = sfc.sfc_keys(dev(pts), M3)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), oracle.keys3(pts))
+    idx = sfc.Index(dev(pts), M3)
+    k, i, x = idx.sorted_arrays()
+    ok, oi, ox = oracle.build3(pts)
+    assert np.array_equal(k.cpu().numpy().view(np.uint64), ok)
+    assert np.array_equal(i.cpu().numpy().view(np.uint32), oi)
+    assert np.array_equal(x.cpu().numpy(), ox)
+
+
+@pytest.mark.parametrize("search", [sfc.BINARY, sfc.STREE])
+@pytest.mark.parametrize("metric", [sfc.L2, sfc.LINF])
+def test_clustered_queries(metric, search):
+    wl = workload.clustered3(n=200_000, m=20_000, seed=91)
+    idx = sfc.Index(dev(wl.points), M3, search=search, metric=metric)
+    ref = check(idx, wl.points, wl.queries, wl.delta, LINF if metric == sfc.LINF else L2)
+    assert ref[1].size > 200_000
+
+
+@pytest.mark.parametrize("metric", [sfc.L2, sfc.LINF])
+def test_adversarial_edges(metric):
+    pts, qs, ds = _adversarial3(np.random.default_rng(92 + metric))
+    for search in (sfc.BINARY, sfc.STREE):
+        idx = sfc.Index(dev(pts), M3, search=search, metric=metric)
+        check(idx, pts, qs, ds, LINF if metric == sfc.LINF else L2)
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(93)
+    pts = rng.random((5000, 3))
+    qs = np.array([[0.5, 0.5, 0.5], [-0.4, 0.5, 0.5], [1.5, 1.5, 1.5], pts[7], [0.2, 0.2, 0.2],
+                   [2.0 ** 33 + 0.5, 0.5, 0.5]])
+    ds = np.array([2.0, 0.3, 0.1, 0.0, 1e-300, 2.0 ** 33])
+    idx = sfc.Index(dev(pts), M3)
+    ref = check(idx, pts, qs, ds)
+    assert ref[0][1] - ref[0][0] == 5000 and ref[0][3] - ref[0][2] == 0
+    # the far query: points 2 quanta past the exact edge are found
+    k = np.arange(8)
+    far = np.stack([0.5 - k * 2.0 ** -21, np.full(8, 0.5), np.full(8, 0.5)], 1)
+    idx2 = sfc.Index(dev(far), M3)
+    off, ids = idx2.query(dev(qs[-1:]), dev(ds[-1:]))
+    assert sorted(ids.cpu().tolist()) == [0, 1, 2]
+    # empty index and empty batch
+    empty = sfc.Index(torch.empty((0, 3), dtype=torch.float64, device=DEV), M3)
+    off, ids = empty.query(dev(qs), dev(ds))
+    assert off.cpu().tolist() == [0] * 7 and ids.numel() == 0
+    off, ids = idx.query(torch.empty((0, 3), dtype=torch.float64, device=DEV),
+                         torch.empty(0, dtype=torch.float64, device=DEV))
+    assert off.cpu().tolist() == [0]
+
+
+@pytest.mark.parametrize("bad", [(0.5, 0.5, 0.5, -1.0), (0.5, float("nan"), 0.5, 0.1),
+                                 (0.5, 0.5, float("inf"), 0.1)])
+def test_invalid_query(bad):
+    pts = np.random.default_rng(94).random((1000, 3))
+    idx = sfc.Index(dev(pts), M3)
+    qs = np.full((50, 3), 0.5)
+    ds = np.full(50, 0.01)
+    qs[17], ds[17] = bad[:3], bad[3]
+    with pytest.raises(sfc.SfcError) as ei:
+        idx.query(dev(qs), dev(ds))
+    assert ei.value.status == sfc.SFC_ERR_INVALID
+
+
+def test_domain_error_and_refused_options():
+    with pytest.raises(sfc.DomainError):
+        sfc.Index(dev(np.array([[0.5, 0.5, 1.0]])), M3)
+    pts = dev(np.random.default_rng(95).random((500, 3)))
+    for kw in ({"search": sfc.LEARNED}, {"refine": True}, {"early_term": True},
+               {"set_off": [0, 200, 500]}):
+        with pytest.raises(sfc.SfcError) as ei:
+            sfc.Index(pts, M3, **kw)
+        assert ei.value.status == sfc.SFC_ERR_UNSUPPORTED, kw
+    idx = sfc.Index(pts, M3)
+    with pytest.raises(sfc.SfcError) as ei:
+        idx.insert(pts[:10])
+    assert ei.value.status == sfc.SFC_ERR_UNSUPPORTED
+    with pytest.raises(sfc.SfcError) as ei:
+        idx.query_ranges(pts[:5], torch.full((5,), 0.1, dtype=torch.float64, device=DEV))
+    assert ei.value.status == sfc.SFC_ERR_UNSUPPORTED
+    with pytest.raises(ValueError):
+        sfc.Index(pts[:, :2].contiguous(), M3)
+
+
+def test_graphs_3d():
+    wl = workload.clustered3(n=80_000, m=6_000, seed=96)
+    buf = dev(wl.points)
+    idx = sfc.Index(buf, M3, search=sfc.STREE)
+    q, d = dev(wl.queries), dev(wl.delta)
+    off, ids = idx.query(q, d)
+    rows = idx.last_stats()["candidates"] // 64 + 8 * len(wl.queries)
+    g = sfc.Graph.query(idx, q, d, max_rows=int(rows * 2), ids_cap=ids.numel() + 16)
+    for _ in range(3):
+        g.launch()
+        goff, gids = g.result()
+        assert torch.equal(goff, off) and torch.equal(gids, ids)
+        e_off, e_ids = idx.query(q, d)
+        assert torch.equal(e_ids, ids)
+    g.close()
+    other = workload.clustered3(n=80_000, m=10, seed=97).points
+    gb = sfc.Graph.build(idx, buf)
+    buf.copy_(dev(other))
+    gb.launch()
+    gb.wait()
+    check(idx, other, wl.queries, wl.delta)
+    gb.close()
