@@ -309,6 +309,58 @@ def paper_windows_bench(args, sfc, workload, torch):
     return out
 
 
+def three_d_bench(args, sfc, workload, torch):
+    """Three dimensions (d = 3 Morton keys): 2^24 clustered points in the
+    unit cube, 2^20 queries from the same mixture with radii aimed at
+    1..300 reports; one step = build + one query batch, binary search and the
+    static search tree."""
+    dev = torch.device("cuda:0")
+    wl = workload.clustered3(n=1 << 24, m=1 << 20)
+    n, m = wl.points.shape[0], wl.queries.shape[0]
+    pts = torch.as_tensor(wl.points).to(dev)
+    q = torch.as_tensor(wl.queries).to(dev)
+    d = torch.as_tensor(wl.delta).to(dev)
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    out = {"workload": wl.name, "n": n, "m": m}
+    reps = []
+    for name, search in (("bsearch", sfc.BINARY), ("stree", sfc.STREE)):
+        idx = sfc.Index(pts, sfc.MORTON3, search=search)
+        _, ids0 = idx.query(q, d)
+        out_ids = torch.empty(ids0.numel() + 1024, dtype=torch.int32, device=dev)
+        reps.append(int(ids0.numel()))
+        del ids0
+        idx.close()
+
+        def step():
+            ix = sfc.Index(pts, sfc.MORTON3, search=search)
+            ix.query(q, d, out_ids=out_ids, out_offsets=offsets)
+            return ix
+
+        for _ in range(max(1, args.warmup)):
+            step().close()
+        torch.cuda.synchronize()
+        sfc.profile_reset()
+        sfc.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ix = step()
+            ix.close()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        sfc.profile_enable(False)
+        kern = {k: v[1] / args.steps for k, v in sfc.profile_read().items()}
+        out[name] = {"ms_per_step": ms, "queries_per_s": m / (ms * 1e-3),
+                     "reported_pts_per_s": reps[-1] / (ms * 1e-3),
+                     "kernels_ms_per_step": kern}
+        del out_ids
+        log(f"3-D {name}: {ms:.3f} ms per step (build + batch)")
+    assert reps[0] == reps[1]
+    out["reported_per_batch"] = reps[0]
+    del pts, q, d
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_bench(args, sfc, workload, torch):
     """Poisson stream of query / insert / erase batches (40/40/20, sizes
     2^U[10,16]) over 2^25 clustered points, Morton keys, learned search:
@@ -367,6 +419,7 @@ def main():
                     help="skip the learned-index measurement at n=2^26")
     ap.add_argument("--no-early-term", action="store_true",
                     help="skip the early-termination measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional leg")
     ap.add_argument("--no-windows", action="store_true",
                     help="skip the paper's square-window sweep")
     ap.add_argument("--no-serving", action="store_true",
@@ -582,6 +635,8 @@ def main():
         line["early_termination"] = early_term_bench(args, sfc, workload, torch, pts)
     if not args.no_windows and not args.only_refined:
         line["paper_windows"] = paper_windows_bench(args, sfc, workload, torch)
+    if not args.no_3d and not args.only_refined:
+        line["three_d"] = three_d_bench(args, sfc, workload, torch)
     if not args.no_learned_large and not args.only_refined:
         line["learned_large"] = learned_large_bench(args, sfc, workload, torch)
     if not args.no_serving and not args.only_refined:

@@ -77,3 +77,31 @@ def test_full_size(full, search, refine, metric, early_term, queries):
         assert np.array_equal(np.sort(got), ref[1][ref[0][t]:ref[0][t + 1]]), j
         assert np.all(np.diff(rank[got]) > 0), j
     idx.close()
+
+
+def test_full_size_3d():
+    """Three dimensions at 2^24 points and 2^20 queries (the 3-D bench leg's
+    shape), static search tree: offsets, soundness of every report in the
+    3-D test's order, a sample against brute force."""
+    wl = workload.clustered3(n=N, m=M)
+    qs, ds = wl.queries, wl.delta
+    idx = sfc.Index(torch.as_tensor(wl.points).to(DEV), sfc.MORTON3, search=sfc.STREE)
+    off, ids = idx.query(torch.as_tensor(qs).to(DEV), torch.as_tensor(ds).to(DEV))
+    off = off.cpu().numpy().view(np.uint64).astype(np.int64)
+    ids = ids.cpu().numpy().view(np.uint32)
+    assert off[0] == 0 and np.all(np.diff(off) >= 0) and off[-1] == ids.size
+    for a in range(0, M, 1 << 16):
+        b = min(M, a + (1 << 16))
+        sl = slice(off[a], off[b])
+        qi = np.repeat(np.arange(a, b), np.diff(off[a:b + 1]))
+        p, q, d = wl.points[ids[sl]], qs[qi], ds[qi]
+        dx, dy, dz = p[:, 0] - q[:, 0], p[:, 1] - q[:, 1], p[:, 2] - q[:, 2]
+        assert ((dx * dx + dy * dy) + dz * dz <= d * d).all(), a
+    rng = np.random.default_rng(72)
+    sample = np.sort(rng.choice(M, SAMPLE, replace=False))
+    sample[0] = int(np.argmax(np.diff(off)))
+    ref = oracle.brute3(wl.points, qs[sample], ds[sample])
+    for t, j in enumerate(sample):
+        got = np.sort(ids[off[j]:off[j + 1]])
+        assert np.array_equal(got, ref[1][ref[0][t]:ref[0][t + 1]]), j
+    idx.close()
