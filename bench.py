@@ -312,8 +312,9 @@ def paper_windows_bench(args, sfc, workload, torch):
 def three_d_bench(args, sfc, workload, torch):
     """Three dimensions (d = 3 Morton keys): 2^24 clustered points in the
     unit cube, 2^20 queries from the same mixture with radii aimed at
-    1..300 reports; one step = build + one query batch, binary search and the
-    static search tree."""
+    1..300 reports; one step = build + one query batch; refined cubes with
+    binary search and with the static search tree, and the static search
+    tree over the unsplit cubes."""
     dev = torch.device("cuda:0")
     wl = workload.clustered3(n=1 << 24, m=1 << 20)
     n, m = wl.points.shape[0], wl.queries.shape[0]
@@ -323,8 +324,9 @@ def three_d_bench(args, sfc, workload, torch):
     offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
     out = {"workload": wl.name, "n": n, "m": m}
     reps = []
-    for name, search in (("bsearch", sfc.BINARY), ("stree", sfc.STREE)):
-        idx = sfc.Index(pts, sfc.MORTON3, search=search)
+    for name, search, refine in (("bsearch", sfc.BINARY, True), ("stree", sfc.STREE, True),
+                                 ("stree_unrefined", sfc.STREE, False)):
+        idx = sfc.Index(pts, sfc.MORTON3, search=search, refine=refine)
         _, ids0 = idx.query(q, d)
         out_ids = torch.empty(ids0.numel() + 1024, dtype=torch.int32, device=dev)
         reps.append(int(ids0.numel()))
@@ -332,7 +334,7 @@ def three_d_bench(args, sfc, workload, torch):
         idx.close()
 
         def step():
-            ix = sfc.Index(pts, sfc.MORTON3, search=search)
+            ix = sfc.Index(pts, sfc.MORTON3, search=search, refine=refine)
             ix.query(q, d, out_ids=out_ids, out_offsets=offsets)
             return ix
 
@@ -349,12 +351,17 @@ def three_d_bench(args, sfc, workload, torch):
         ms = (time.perf_counter() - t0) / args.steps * 1e3
         sfc.profile_enable(False)
         kern = {k: v[1] / args.steps for k, v in sfc.profile_read().items()}
+        ix = sfc.Index(pts, sfc.MORTON3, search=search, refine=refine)
+        ix.query(q, d, out_ids=out_ids, out_offsets=offsets)
+        cand = ix.last_stats()["candidates"]
+        ix.close()
         out[name] = {"ms_per_step": ms, "queries_per_s": m / (ms * 1e-3),
                      "reported_pts_per_s": reps[-1] / (ms * 1e-3),
+                     "candidates_per_report": cand / max(reps[-1], 1),
                      "kernels_ms_per_step": kern}
         del out_ids
         log(f"3-D {name}: {ms:.3f} ms per step (build + batch)")
-    assert reps[0] == reps[1]
+    assert reps[0] == reps[1] == reps[2]
     out["reported_per_batch"] = reps[0]
     del pts, q, d
     torch.cuda.empty_cache()

@@ -63,8 +63,10 @@ typedef enum {
    per point and per query) keyed by the d = 3 Morton code (Sec. 1 and
    Sec. 2.1: the Z-order method generalises to R^d): 21 bits per axis, a
    63-bit key, at most 8 cube ranges per query.  With it: binary search or
-   the static search tree, no refinement, no early termination, no point
-   sets, no updates, no range inspection (SFC_ERR_UNSUPPORTED). */
+   the static search tree, with or without refinement (a crowded cube is
+   split once into at most four runs of its children that meet the box); no
+   early termination, learned index, point sets, updates or range inspection
+   (SFC_ERR_UNSUPPORTED). */
 enum { SFC_CURVE_MORTON = 0, SFC_CURVE_HILBERT = 1, SFC_CURVE_MORTON3 = 2 };
 /* The search that turns a key interval into an index range (all three give
    the same ranges: std::lower_bound / std::upper_bound over the keys):

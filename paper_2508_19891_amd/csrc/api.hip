@@ -378,6 +378,10 @@ bool stree_on(const sfc_index* h) { return h->search == SFC_SEARCH_STREE && h->s
 // Coordinates per point and per query.
 int dim_of(const sfc_index* h) { return h->curve == SFC_CURVE_MORTON3 ? 3 : 2; }
 
+// Query slots per query the scratch must hold (three dimensions refined:
+// four runs for each of eight cubes).
+uint32_t slots_of(const sfc_index* h) { return dim_of(h) == 3 && h->refine ? 32 : 8; }
+
 // Runs ranges + searches + scan; on SFC_OK *total_rows holds the number of
 // candidate rows and *total_cand the number of candidates.
 sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const uint32_t* qset,
@@ -385,14 +389,15 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
                       uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
                       uint32_t* dbg_nr, const uint32_t* qepoch = nullptr) {
   h->pending.valid = false;   // the scratch is about to be reused
-  sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
+  sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m, slots_of(h)));
   if (st != SFC_OK) return st;
-  sfc::query_scratch_carve(h->ws, m, qs);
+  sfc::query_scratch_carve(h->ws, m, qs, slots_of(h));
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
   const sfc::LearnedView lv = h->larr.view();
   const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
   if (dim_of(h) == 3)
-    SFC_TRY(sfc::launch_ranges3(q, delta, m, h->keys, h->n, stree_on(h) ? &sv : nullptr, *qs,
+    SFC_TRY(sfc::launch_ranges3(q, delta, m, h->keys, h->n, h->refine != 0, h->refine_min,
+                                stree_on(h) ? &sv : nullptr, *qs,
                                 h->stream));
   else
     SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
@@ -611,7 +616,7 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
   if (opt) o = *opt;
   if (!out || (n > 0 && !xy) || n > 0xFFFFFFFFull || !valid_options(o)) return SFC_ERR_INVALID;
   if (o.curve == SFC_CURVE_MORTON3 &&
-      (o.search == SFC_SEARCH_LEARNED || o.refine || o.early_term || set_off_host))
+      (o.search == SFC_SEARCH_LEARNED || o.early_term || set_off_host))
     return SFC_ERR_UNSUPPORTED;
   sfc_index* h = new (std::nothrow) sfc_index();
   if (!h) return SFC_ERR_NOMEM;
@@ -816,18 +821,19 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
   if (h->n_sets) return SFC_ERR_UNSUPPORTED;
   h->pending.valid = false;
   // Growing a scratch buffer waits for the work queued on it first.
-  sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m));
+  sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m, slots_of(h)));
   if (st == SFC_OK) st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(max_rows));
   if (st != SFC_OK) return st;
   sfc::QueryScratch qs{};
-  sfc::query_scratch_carve(h->ws, m, &qs);
+  sfc::query_scratch_carve(h->ws, m, &qs, slots_of(h));
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted;
   const sfc::LearnedView lv = h->larr.view();
   const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
   sfc::EpochView ev;
   const bool filtered = epoch_view(h, qepoch, &ev);
   if (dim_of(h) == 3)
-    SFC_TRY(sfc::launch_ranges3(q, delta, m, h->keys, h->n, stree_on(h) ? &sv : nullptr, qs,
+    SFC_TRY(sfc::launch_ranges3(q, delta, m, h->keys, h->n, h->refine != 0, h->refine_min,
+                                stree_on(h) ? &sv : nullptr, qs,
                                 h->stream));
   else
     SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
@@ -1142,13 +1148,13 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   g->max_rows = max_rows;
   g->cap_ids = ids_cap;
   g->offsets = offsets;
-  g->scratch = h->alloc.get(sfc::query_scratch_bytes(m));
+  g->scratch = h->alloc.get(sfc::query_scratch_bytes(m, slots_of(h)));
   g->cscratch = h->alloc.get(sfc::compact_scratch_bytes(max_rows));
   if (!g->scratch || !g->cscratch) {
     graph_release(g);
     return SFC_ERR_NOMEM;
   }
-  sfc::query_scratch_carve(g->scratch, m, &g->qs);
+  sfc::query_scratch_carve(g->scratch, m, &g->qs, slots_of(h));
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
   const sfc::LearnedView lv = h->larr.view();
   const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
@@ -1157,7 +1163,8 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   sfc_status st = graph_capture(g, [&](hipStream_t s) {
     hipError_t e =
         dim_of(h) == 3
-            ? sfc::launch_ranges3(q, delta, m, h->keys, h->n, stree_on(h) ? &sv : nullptr, g->qs,
+            ? sfc::launch_ranges3(q, delta, m, h->keys, h->n, h->refine != 0, h->refine_min,
+                                stree_on(h) ? &sv : nullptr, g->qs,
                                   s)
             : sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
                                  h->refine_min, learned ? &lv : nullptr,

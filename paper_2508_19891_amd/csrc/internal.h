@@ -72,8 +72,11 @@ constexpr uint64_t kCompactChunkTiles = 1ull << 19; // tiles per launch
 // Tiles per chunk in effect (kCompactChunkTiles unless a test lowered it).
 uint64_t compact_chunk_tiles();
 void set_compact_chunk_tiles(uint64_t tiles);
-size_t query_scratch_bytes(uint64_t m);
-void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs);
+// Query scratch for m queries of up to `slots` slots each (8: the plane,
+// either layout, and three dimensions unrefined; 32: three dimensions
+// refined).
+size_t query_scratch_bytes(uint64_t m, uint32_t slots = 8);
+void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slots = 8);
 size_t compact_scratch_bytes(uint64_t total_rows);
 
 // Ranges and searches per query slot, then the scan of candidate counts into
@@ -92,10 +95,12 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
                          uint64_t* dbg_e, uint32_t* dbg_nr, hipStream_t s);
 // Three dimensions (points and queries of three doubles, d = 3 Morton keys):
 // the at most 8 cube ranges of every query and their searches (binary, or the
-// static search tree when sview is non-null), then the scan, as
+// static search tree when sview is non-null; refine: crowded cubes split once
+// into at most four runs of children, 32 slots per query), then the scan, as
 // launch_ranges.
 hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
-                          uint64_t n, const StreeView* sview, QueryScratch& qs, hipStream_t s);
+                          uint64_t n, bool refine, uint32_t refine_min, const StreeView* sview,
+                          QueryScratch& qs, hipStream_t s);
 // Test-and-compact over the candidate rows.  device_sized = false: max_rows
 // is the exact row count (known on the host), processed in chunks.
 // device_sized = true: max_rows is a capacity, the count is read on the

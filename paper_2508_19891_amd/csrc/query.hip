@@ -562,33 +562,121 @@ __device__ int query_ranges3(double qx, double qy, double qz, double d, uint64_t
   return r;
 }
 
-// One lane per (query, slot), eight slots per query: every lane derives the
-// query's cubes, slot r searches interval r.
-template <int SEARCH>
+// The level-l cubes meeting the widened box, unmerged and sorted by key, with
+// their coordinates at level l (for the refinement); *L gets l, b the box.
+__device__ int query_cubes3(double qx, double qy, double qz, double d, uint64_t lo[8],
+                            uint32_t cx[8], uint32_t cy[8], uint32_t cz[8], int* L,
+                            int64_t b[6]) {
+  if (!axis_box3(qx, d, b[0], b[1]) || !axis_box3(qy, d, b[2], b[3]) ||
+      !axis_box3(qz, d, b[4], b[5]))
+    return 0;
+  uint64_t side = (uint64_t)(b[1] - b[0] + 1);
+  side = (uint64_t)(b[3] - b[2] + 1) > side ? (uint64_t)(b[3] - b[2] + 1) : side;
+  side = (uint64_t)(b[5] - b[4] + 1) > side ? (uint64_t)(b[5] - b[4] + 1) : side;
+  const int l = side <= 1 ? 0 : 64 - __clzll(side - 1);
+  if (l >= 21) {
+    *L = 21;
+    lo[0] = 0;
+    cx[0] = cy[0] = cz[0] = 0;
+    return 1;
+  }
+  *L = l;
+  int k = 0;
+  for (uint32_t x = (uint32_t)(b[0] >> l); x <= (uint32_t)(b[1] >> l); ++x)
+    for (uint32_t y = (uint32_t)(b[2] >> l); y <= (uint32_t)(b[3] >> l); ++y)
+      for (uint32_t z = (uint32_t)(b[4] >> l); z <= (uint32_t)(b[5] >> l); ++z) {
+        const uint64_t key = morton3_key(x << l, y << l, z << l);
+        int t = k++;
+        for (; t > 0 && lo[t - 1] > key; --t) {
+          lo[t] = lo[t - 1];
+          cx[t] = cx[t - 1];
+          cy[t] = cy[t - 1];
+          cz[t] = cz[t - 1];
+        }
+        lo[t] = key;
+        cx[t] = x;
+        cy[t] = y;
+        cz[t] = z;
+      }
+  return k;
+}
+
+// One lane per (query, slot): eight slots per query, each a merged interval
+// of the query's cubes.  REFINE: one lane per cube (unmerged); a cube
+// holding more than refine_min keys is split once, its children that meet
+// the box forming at most four runs of consecutive children in key order
+// (four slots per cube, 32 per query), each found by two searches inside the
+// cube's index range.  The reported ids and their order do not change.
+template <int SEARCH, bool REFINE>
 __global__ __launch_bounds__(256) void ranges_search3(
     const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, StreeView sv,
-    uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
+    uint32_t refine_min, uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total) {
   const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   const uint64_t j = g >> 3;
   const int r = (int)(g & 7);
-  uint64_t b0 = 0, e0 = 0;
+  uint64_t B[4] = {0, 0, 0, 0}, E[4] = {0, 0, 0, 0};
   uint32_t fb = 0;
   bool bad = false;
   if (j < m) {
     const double qx = q[3 * j], qy = q[3 * j + 1], qz = q[3 * j + 2], d = delta[j];
     if (!(finite(qx) && finite(qy) && finite(qz) && finite(d) && d >= 0.0)) {
       bad = true;
-    } else {
+    } else if (!REFINE) {
       uint64_t lo[8], hi[8];
       const int nr = query_ranges3(qx, qy, qz, d, lo, hi);
-      if (r < nr) find_range<SEARCH>(keys, n, lv, sv, lo[r], hi[r], b0, e0, fb);
+      if (r < nr) find_range<SEARCH>(keys, n, lv, sv, lo[r], hi[r], B[0], E[0], fb);
+    } else {
+      uint64_t lo[8];
+      uint32_t cx[8], cy[8], cz[8];
+      int64_t b[6];
+      int L = 0;
+      const int nr = query_cubes3(qx, qy, qz, d, lo, cx, cy, cz, &L, b);
+      if (r < nr) {
+        const uint64_t span = L >= 21 ? (1ull << 63) - 1 : (1ull << (3 * L)) - 1;
+        find_range<SEARCH>(keys, n, lv, sv, lo[r], lo[r] | span, B[0], E[0], fb);
+        if (E[0] - B[0] > refine_min && L >= 1 && L < 21) {
+          const int Lc = L - 1;
+          const uint64_t cspan = (1ull << (3 * Lc)) - 1;
+          const int64_t hs = (int64_t)1 << Lc;
+          uint32_t meet = 0;   // bit c: child c (x + 2y + 4z) meets the box
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int64_t x0 = (int64_t)(2 * cx[r] + (c & 1)) << Lc;
+            const int64_t y0 = (int64_t)(2 * cy[r] + ((c >> 1) & 1)) << Lc;
+            const int64_t z0 = (int64_t)(2 * cz[r] + (c >> 2)) << Lc;
+            const bool in = x0 <= b[1] && x0 + hs - 1 >= b[0] && y0 <= b[3] &&
+                            y0 + hs - 1 >= b[2] && z0 <= b[5] && z0 + hs - 1 >= b[4];
+            meet |= (uint32_t)in << c;
+          }
+          if (meet != 0xFFu) {
+            // Runs of consecutive children: the k-th run starts at the k-th
+            // set bit of `st` and ends at the k-th set bit of `en`.
+            const uint64_t pb = B[0], pe = E[0];
+            uint32_t st = meet & ~(meet << 1);
+            uint32_t en = meet & ~(meet >> 1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              if (st) {
+                const int c0 = __builtin_ctz(st), c1 = __builtin_ctz(en);
+                st &= st - 1;
+                en &= en - 1;
+                const uint64_t klo = lo[r] | ((uint64_t)c0 << (3 * Lc));
+                const uint64_t khi = lo[r] | ((uint64_t)c1 << (3 * Lc)) | cspan;
+                search_within(keys, pb, pe, klo, khi, B[k], E[k]);
+              } else {
+                B[k] = E[k] = 0;
+              }
+            }
+          }
+        }
+      }
     }
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&counters[2], kErrInvalidQuery);
   __shared__ unsigned long long s_c[4];
-  unsigned long long wc = e0 - b0;
+  unsigned long long wc = (E[0] - B[0]) + (E[1] - B[1]) + (E[2] - B[2]) + (E[3] - B[3]);
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) wc += __shfl_xor(wc, o, 64);
   if (lane_id() == 0) s_c[threadIdx.x >> 6] = wc;
@@ -598,9 +686,18 @@ __global__ __launch_bounds__(256) void ranges_search3(
     if (t) atomicAdd(cand_total, t);
   }
   if (j < m) {
-    slot_begin[g] = (uint32_t)b0;
-    slot_count[g] = (uint32_t)(e0 - b0);
-    slot_rows[g] = (uint32_t)((e0 - b0 + 63) >> 6);
+    if (!REFINE) {
+      slot_begin[g] = (uint32_t)B[0];
+      slot_count[g] = (uint32_t)(E[0] - B[0]);
+      slot_rows[g] = (uint32_t)((E[0] - B[0] + 63) >> 6);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        slot_begin[4 * g + t] = (uint32_t)B[t];
+        slot_count[4 * g + t] = (uint32_t)(E[t] - B[t]);
+        slot_rows[4 * g + t] = (uint32_t)((E[t] - B[t] + 63) >> 6);
+      }
+    }
   }
 }
 
@@ -979,14 +1076,14 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) 
   return hipGetLastError();
 }
 
-size_t query_scratch_bytes(uint64_t m) {
-  const uint64_t nseg = 8 * m;   // room for the refined layout (eight slots per query)
+size_t query_scratch_bytes(uint64_t m, uint32_t slots) {
+  const uint64_t nseg = slots * m;
   return align256(nseg * 4) * 3 + align256((nseg + 1) * 8) + scan_scratch_bytes(nseg) +
          align256(64) + align256(4 * m * 8);
 }
 
-void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs) {
-  const uint64_t nseg = 8 * m;
+void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slots) {
+  const uint64_t nseg = slots * m;
   char* p = (char*)base;
   qs->slot_begin = (uint32_t*)p;  p += align256(nseg * 4);
   qs->slot_count = (uint32_t*)p;  p += align256(nseg * 4);
@@ -1083,23 +1180,30 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
 constexpr uint64_t kCompactGrid = 4096;
 
 hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
-                          uint64_t n, const StreeView* sview, QueryScratch& qs, hipStream_t s) {
+                          uint64_t n, bool refine, uint32_t refine_min, const StreeView* sview,
+                          QueryScratch& qs, hipStream_t s) {
   if (m == 0) return hipSuccess;
   hipError_t e;
   if ((e = fill_u32(qs.counters, 0, 16, s)) != hipSuccess) return e;
-  qs.ss = 3;
+  qs.ss = refine ? 5 : 3;
   const uint32_t blocks = (uint32_t)((8 * m + 255) / 256);
   unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
   const LearnedView lv{};
+  const StreeView sv = sview ? *sview : StreeView{};
   {
     ProfScope ps(sview ? "ranges_stree3" : "ranges_search3", s);
-    if (sview)
-      ranges_search3<2><<<blocks, 256, 0, s>>>(q, delta, m, keys, n, lv, *sview, qs.slot_begin,
-                                               qs.slot_count, qs.slot_rows, qs.counters, cand);
-    else
-      ranges_search3<0><<<blocks, 256, 0, s>>>(q, delta, m, keys, n, lv, StreeView{},
-                                               qs.slot_begin, qs.slot_count, qs.slot_rows,
-                                               qs.counters, cand);
+#define SFC_R3(S, R)                                                                         \
+  ranges_search3<S, R><<<blocks, 256, 0, s>>>(q, delta, m, keys, n, lv, sv, refine_min,      \
+                                              qs.slot_begin, qs.slot_count, qs.slot_rows,    \
+                                              qs.counters, cand)
+    if (sview) {
+      if (refine) SFC_R3(2, true);
+      else SFC_R3(2, false);
+    } else {
+      if (refine) SFC_R3(0, true);
+      else SFC_R3(0, false);
+    }
+#undef SFC_R3
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return scan_excl(qs.slot_rows, qs.row_off, m << qs.ss, nullptr, qs.scan_tmp, s);

@@ -44,11 +44,12 @@ def test_keys_and_sorted_arrays(n):
     assert np.array_equal(x.cpu().numpy(), ox)
 
 
+@pytest.mark.parametrize("refine", [False, True])
 @pytest.mark.parametrize("search", [sfc.BINARY, sfc.STREE])
 @pytest.mark.parametrize("metric", [sfc.L2, sfc.LINF])
-def test_clustered_queries(metric, search):
+def test_clustered_queries(metric, search, refine):
     wl = workload.clustered3(n=200_000, m=20_000, seed=91)
-    idx = sfc.Index(dev(wl.points), M3, search=search, metric=metric)
+    idx = sfc.Index(dev(wl.points), M3, search=search, metric=metric, refine=refine)
     ref = check(idx, wl.points, wl.queries, wl.delta, LINF if metric == sfc.LINF else L2)
     assert ref[1].size > 200_000
 
@@ -57,8 +58,9 @@ def test_clustered_queries(metric, search):
 def test_adversarial_edges(metric):
     pts, qs, ds = _adversarial3(np.random.default_rng(92 + metric))
     for search in (sfc.BINARY, sfc.STREE):
-        idx = sfc.Index(dev(pts), M3, search=search, metric=metric)
-        check(idx, pts, qs, ds, LINF if metric == sfc.LINF else L2)
+        for refine in (False, True):
+            idx = sfc.Index(dev(pts), M3, search=search, metric=metric, refine=refine)
+            check(idx, pts, qs, ds, LINF if metric == sfc.LINF else L2)
 
 
 def test_edge_cases():
@@ -67,8 +69,9 @@ def test_edge_cases():
     qs = np.array([[0.5, 0.5, 0.5], [-0.4, 0.5, 0.5], [1.5, 1.5, 1.5], pts[7], [0.2, 0.2, 0.2],
                    [2.0 ** 33 + 0.5, 0.5, 0.5]])
     ds = np.array([2.0, 0.3, 0.1, 0.0, 1e-300, 2.0 ** 33])
-    idx = sfc.Index(dev(pts), M3)
-    ref = check(idx, pts, qs, ds)
+    for refine in (False, True):
+        idx = sfc.Index(dev(pts), M3, refine=refine)
+        ref = check(idx, pts, qs, ds)
     assert ref[0][1] - ref[0][0] == 5000 and ref[0][3] - ref[0][2] == 0
     # the far query: points 2 quanta past the exact edge are found
     k = np.arange(8)
@@ -102,7 +105,7 @@ def test_domain_error_and_refused_options():
     with pytest.raises(sfc.DomainError):
         sfc.Index(dev(np.array([[0.5, 0.5, 1.0]])), M3)
     pts = dev(np.random.default_rng(95).random((500, 3)))
-    for kw in ({"search": sfc.LEARNED}, {"refine": True}, {"early_term": True},
+    for kw in ({"search": sfc.LEARNED}, {"early_term": True},
                {"set_off": [0, 200, 500]}):
         with pytest.raises(sfc.SfcError) as ei:
             sfc.Index(pts, M3, **kw)
@@ -121,7 +124,7 @@ def test_domain_error_and_refused_options():
 def test_graphs_3d():
     wl = workload.clustered3(n=80_000, m=6_000, seed=96)
     buf = dev(wl.points)
-    idx = sfc.Index(buf, M3, search=sfc.STREE)
+    idx = sfc.Index(buf, M3, search=sfc.STREE, refine=True)
     q, d = dev(wl.queries), dev(wl.delta)
     off, ids = idx.query(q, d)
     rows = idx.last_stats()["candidates"] // 64 + 8 * len(wl.queries)
@@ -140,3 +143,16 @@ def test_graphs_3d():
     gb.wait()
     check(idx, other, wl.queries, wl.delta)
     gb.close()
+
+
+def test_refinement_cuts_candidates_not_results():
+    """Splitting crowded cubes leaves the output (and its order) as it was
+    and removes most candidates."""
+    wl = workload.clustered3(n=300_000, m=20_000, seed=98)
+    plain = sfc.Index(dev(wl.points), M3)
+    refined = sfc.Index(dev(wl.points), M3, refine=True)
+    a = plain.query(dev(wl.queries), dev(wl.delta))
+    b = refined.query(dev(wl.queries), dev(wl.delta))
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    ca, cb = plain.last_stats()["candidates"], refined.last_stats()["candidates"]
+    assert cb < 0.6 * ca

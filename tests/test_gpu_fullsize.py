@@ -81,11 +81,12 @@ def test_full_size(full, search, refine, metric, early_term, queries):
 
 def test_full_size_3d():
     """Three dimensions at 2^24 points and 2^20 queries (the 3-D bench leg's
-    shape), static search tree: offsets, soundness of every report in the
+    shape), static search tree, refined cubes: offsets, soundness of every report in the
     3-D test's order, a sample against brute force."""
     wl = workload.clustered3(n=N, m=M)
     qs, ds = wl.queries, wl.delta
-    idx = sfc.Index(torch.as_tensor(wl.points).to(DEV), sfc.MORTON3, search=sfc.STREE)
+    idx = sfc.Index(torch.as_tensor(wl.points).to(DEV), sfc.MORTON3, search=sfc.STREE,
+                    refine=True)
     off, ids = idx.query(torch.as_tensor(qs).to(DEV), torch.as_tensor(ds).to(DEV))
     off = off.cpu().numpy().view(np.uint64).astype(np.int64)
     ids = ids.cpu().numpy().view(np.uint32)
