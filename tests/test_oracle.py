@@ -8,6 +8,7 @@ the bound of at most four cells), brute force on small inputs, and a closed
 form for the expected output size.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -53,9 +54,25 @@ def test_morton_each_bit_position():
         assert oracle.morton(x, y) == oracle.morton(x, 0) | oracle.morton(0, y)
 
 
-# The 4x4 corner, rows y = 3..0, drawn by hand from the two definitions.
-MORTON_4x4 = [[10, 11, 14, 15], [8, 9, 12, 13], [2, 3, 6, 7], [0, 1, 4, 5]]
-HILBERT_4x4 = [[5, 6, 9, 10], [4, 7, 8, 11], [3, 2, 13, 12], [0, 1, 14, 15]]
+def _golden_corner():
+    """The 4x4 corner's labels, worked by hand (tests/golden, with the
+    derivation and citations in the file's header)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "corner_4x4_labels.txt")
+    tables, cur = {}, None
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.isalpha():
+            cur = tables.setdefault(line, [])
+        else:
+            cur.append([int(v) for v in line.split()])
+    return tables
+
+
+_CORNER = _golden_corner()
+MORTON_4x4 = _CORNER["morton"]
+HILBERT_4x4 = _CORNER["hilbert"]
 
 
 @pytest.mark.parametrize("curve,table", [(MORTON, MORTON_4x4), (HILBERT, HILBERT_4x4)])
