@@ -506,13 +506,15 @@ def main():
     else:
         ms_paper, kern_paper, stats_paper, _ = run_mode(False)
     ms_step, kern, stats, total = run_mode(True)
-    def query_only(search: int):
+    def query_only(search: int, cells: bool = True):
         """One index (built and, for the learned search, fitted once); the
-        timed steps are query batches only."""
+        timed steps are query batches only.  cells=False: every candidate
+        takes the exact test (no decisions from grid cells)."""
         torch.cuda.synchronize()
         sfc.profile_reset()
         sfc.profile_enable(True)
         idx = sfc.Index(pts, curve, refine=True, search=search)
+        idx.set_cell_filter(cells)
         torch.cuda.synchronize()
         sfc.profile_enable(False)
         fit = {k: v[1] for k, v in sfc.profile_read().items() if k.startswith("learned_")}
@@ -543,7 +545,8 @@ def main():
         ms_qb, kern_qb, _, _, rep_qb = query_only(sfc.BINARY)
         ms_ql, kern_ql, fit_l, info_l, rep_ql = query_only(sfc.LEARNED)
         ms_qs, kern_qs, _, _, rep_qs = query_only(sfc.STREE)
-        assert rep_qb == rep_ql == rep_qs == total
+        ms_qx, kern_qx, _, _, rep_qx = query_only(sfc.BINARY, cells=False)
+        assert rep_qb == rep_ql == rep_qs == rep_qx == total
         lvb = {
             "step": "one query batch over a built index (refined ranges); the learned index is "
                     "fitted once beforehand",
@@ -571,6 +574,19 @@ def main():
             "search_ms_stree": kern_qs.get("ranges_stree", float("nan")),
             "kernels_ms_per_batch_stree": kern_qs,
         }
+        # The same batch (binary search) with every candidate taking the exact
+        # test: the test kernel then reads 16 B per candidate.
+        cand_q = stats["candidates"]
+        ct_x = kern_qx.get("compact_test", float("nan"))
+        exact_bytes = 16 * cand_q + 24 * m + 12 * 8 * m + cand_q // 8 + 4 * math.ceil(cand_q / 4096)
+        cell_filter = {
+            "step": "one query batch over a built index (refined ranges, binary search)",
+            "ms_per_batch_cells": ms_qb, "ms_per_batch_exact": ms_qx,
+            "compact_test_ms_cells": kern_qb.get("compact_test", float("nan")),
+            "compact_test_ms_exact": ct_x,
+            "exact_compact_test_gbs": exact_bytes / (ct_x * 1e-3) / 1e9,
+            "exact_compact_test_frac": exact_bytes / (ct_x * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
 
     # Algorithmic bytes per step of each kernel (what the method must move).
     cand, rep = stats["candidates"], total
@@ -581,7 +597,10 @@ def main():
         "tile_hist": 7 * 8 * n,                             # passes 2..8 read the keys
         "scatter_pass": 8 * 24 * n,                         # 8 passes x (key+id) in and out
         "ranges_search": 24 * m + 8 * slots,                # queries in; begin+count per slot
-        "compact_test": 16 * cand + 24 * m + 12 * slots + cand // 8 + 4 * tiles,
+        # default: each candidate's 8-byte grid cell, the 32-byte filter record
+        # of its query per row (the rare undecided candidates read 16 B more)
+        "compact_test": 8 * cand + 32 * m + 12 * slots + cand // 8 + 4 * tiles,
+        "query_filters": 24 * m + 32 * m,
         "compact_write": cand // 8 + 8 * tiles + 4 * rep + 4 * rep + 8 * (m + 1) + 12 * slots,
     }
     # The last radix pass also gathers the points (random 16 B reads, 16 B writes).
@@ -614,6 +633,7 @@ def main():
         "config": {"workload": wl.name + "_hilbert", "n": n, "m": m, "curve": "hilbert",
                    "search": "binary", "ranges": "refined", "step": "build + one query batch"},
         "learned_vs_bsearch": lvb,
+        "cell_filter": None if args.only_refined else cell_filter,
         "paper_ranges": {"queries_per_s": m / (ms_paper * 1e-3), "ms_per_step": ms_paper,
                          "candidates_per_step": stats_paper["candidates"],
                          "kernels_ms_per_step": {k: v[1] / args.steps

@@ -426,6 +426,14 @@ sfc_status sfc_set_search(sfc_index* h, int search);
    the metric that batch was tested with.  SFC_ERR_INVALID for another
    value.  No device work. */
 sfc_status sfc_set_metric(sfc_index* h, int metric);
+/* The index keeps the grid cell of every stored point beside its
+   coordinates (8 bytes per point).  With on = 1 (the default) the exact test
+   decides a candidate from its cell when the whole cell lies inside or
+   outside the query by a relative margin of 2^-40, far beyond the test's
+   rounding, and reads the coordinates only for the rest: the same results
+   as the test on every candidate (on = 0), from about half the memory
+   traffic.  SFC_ERR_INVALID for another value.  No device work. */
+sfc_status sfc_set_cell_filter(sfc_index* h, int on);
 /* (Re)fits the learned index with the given training steps (< 0: the
    handle's default).  SFC_ERR_UNSUPPORTED for n < 2. */
 sfc_status sfc_learned_fit(sfc_index* h, int steps);

@@ -217,6 +217,11 @@ struct sfc_index {
   // point sets (sfc_build_sets)
   uint32_t n_sets = 0;
   uint64_t* set_off = nullptr;     // device, n_sets + 1
+  // grid cells of the sorted points (decide most candidates without reading
+  // their coordinates); kept in step with xy
+  uint64_t* cells = nullptr;
+  uint64_t cells_cap = 0;
+  bool cell_filter = true;
   // static search tree: layers above the keys (built while search is STREE)
   void* stree = nullptr;
   size_t stree_bytes = 0;
@@ -336,6 +341,9 @@ void release_arrays(sfc_index* h) {
   h->occ = nullptr;
   h->alloc.put(h->stree);
   h->stree = nullptr;
+  h->alloc.put(h->cells);
+  h->cells = nullptr;
+  h->cells_cap = 0;
   h->stree_bytes = 0;
   h->stree_ready = false;
   h->ins = h->era = nullptr;
@@ -374,6 +382,25 @@ sfc_status stree_refresh(sfc_index* h) {
 }
 
 bool stree_on(const sfc_index* h) { return h->search == SFC_SEARCH_STREE && h->stree_ready; }
+
+// The grid cells of the current points, after an update moved them; the
+// buffer grows first when the points outgrew it.
+sfc_status cells_refresh(sfc_index* h) {
+  if (h->n > h->cells_cap) {
+    SFC_TRY(hipStreamSynchronize(h->stream));   // the old cells may still be read
+    h->alloc.put(h->cells);
+    h->cells = (uint64_t*)h->alloc.get(h->n * 8);
+    h->cells_cap = h->cells ? h->n : 0;
+    if (!h->cells) return SFC_ERR_NOMEM;
+  }
+  SFC_TRY(sfc::pack_cells(h->xy, h->n, h->curve == SFC_CURVE_MORTON3 ? 3 : 2, h->cells,
+                          h->stream));
+  return SFC_OK;
+}
+
+// The cells the test may decide candidates from (null: every candidate takes
+// the exact test).
+const uint64_t* test_cells(const sfc_index* h) { return h->cell_filter ? h->cells : nullptr; }
 
 // Coordinates per point and per query.
 int dim_of(const sfc_index* h) { return h->curve == SFC_CURVE_MORTON3 ? 3 : 2; }
@@ -654,9 +681,11 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
     h->keys = (uint64_t*)h->alloc.get(n * 8);
     h->ids = (uint32_t*)h->alloc.get(n * 4);
     h->xy = (double*)h->alloc.get(n * 8 * dim_of(h));
+    h->cells = (uint64_t*)h->alloc.get(n * 8);
+    h->cells_cap = n;
     const size_t sb = sfc::build_scratch_bytes(n) + 256;
     void* scratch = h->alloc.get(sb);
-    if (!h->keys || !h->ids || !h->xy || !scratch) {
+    if (!h->keys || !h->ids || !h->xy || !h->cells || !scratch) {
       h->alloc.put(scratch);
       release_arrays(h);
       delete h;
@@ -666,7 +695,7 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
     hipError_t e = sfc::fill_u32(err, 0, 1, h->stream);
     if (e == hipSuccess)
       e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, h->xy, scratch, err, h->stream,
-                          h->set_off, h->n_sets);
+                          h->set_off, h->n_sets, h->cells);
     uint64_t w = 0;
     if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
     h->alloc.put(scratch);
@@ -774,9 +803,10 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
     sfc_status st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(total_rows));
     if (st != SFC_OK) return st;
   }
-  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, total_rows, false, h->cws,
-                              offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, dim_of(h),
-                              h->stream, filtered ? &ev : nullptr));
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, test_cells(h), h->ids, h->n, qs, total_rows,
+                              false, h->cws, offsets, ids, ids_cap,
+                              h->metric == SFC_METRIC_LINF, dim_of(h), h->stream,
+                              filtered ? &ev : nullptr));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
   if (m > 0) {
@@ -842,9 +872,10 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
                                nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs.counters + 2, h->stream));
-  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, qs, max_rows, true, h->cws,
-                              offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF, dim_of(h),
-                              h->stream, filtered ? &ev : nullptr));
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, test_cells(h), h->ids, h->n, qs, max_rows,
+                              true, h->cws, offsets, ids, ids_cap,
+                              h->metric == SFC_METRIC_LINF, dim_of(h), h->stream,
+                              filtered ? &ev : nullptr));
   SFC_TRY(hipMemcpyAsync(flags, qs.counters + 2, 4, hipMemcpyDeviceToDevice, h->stream));
   return SFC_OK;
 }
@@ -859,9 +890,9 @@ sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint6
     return SFC_ERR_CAPACITY;
   }
   h->pending.valid = false;
-  SFC_TRY(sfc::launch_compact(nullptr, nullptr, p.m, h->xy, h->ids, h->n, p.qs, p.rows, false,
-                              h->cws, offsets, ids, ids_cap, false, dim_of(h), h->stream, nullptr,
-                              true));
+  SFC_TRY(sfc::launch_compact(nullptr, nullptr, p.m, h->xy, nullptr, h->ids, h->n, p.qs, p.rows,
+                              false, h->cws, offsets, ids, ids_cap, false, dim_of(h), h->stream,
+                              nullptr, true));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + p.m, &total, 1, h->stream));
   if (total != p.total) return SFC_ERR_DEVICE;
@@ -950,6 +981,12 @@ sfc_status sfc_set_search(sfc_index* h, int search) {
     if (st != SFC_OK) return st;
   }
   h->search = search;
+  return SFC_OK;
+}
+
+sfc_status sfc_set_cell_filter(sfc_index* h, int on) {
+  if (!h || (on != 0 && on != 1)) return SFC_ERR_INVALID;
+  h->cell_filter = on != 0;
   return SFC_OK;
 }
 
@@ -1119,7 +1156,7 @@ sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out) {
     hipError_t e = sfc::fill_u32(g->err, 0, 1, s);
     if (e == hipSuccess)
       e = sfc::sort_build(xy, h->n, h->curve, h->keys, h->ids, h->xy, g->scratch, g->err, s,
-                          h->set_off, h->n_sets);
+                          h->set_off, h->n_sets, h->cells);
     if (e == hipSuccess && h->occ) e = sfc::build_occupancy(h->keys, h->n, h->occ, s);
     if (e == hipSuccess && h->stree_ready)
       e = sfc::stree_build(sfc::stree_view(h->keys, h->n, h->stree), s);
@@ -1172,9 +1209,10 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
                                  qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr, nullptr,
                                  nullptr, nullptr, nullptr, s);
     if (e == hipSuccess)
-      e = sfc::launch_compact(q, delta, m, h->xy, h->ids, h->n, g->qs, max_rows, true,
-                              g->cscratch, offsets, ids, ids_cap, h->metric == SFC_METRIC_LINF,
-                              dim_of(h), s, filtered ? &ev : nullptr);
+      e = sfc::launch_compact(q, delta, m, h->xy, test_cells(h), h->ids, h->n, g->qs,
+                              max_rows, true, g->cscratch, offsets, ids, ids_cap,
+                              h->metric == SFC_METRIC_LINF, dim_of(h), s,
+                              filtered ? &ev : nullptr);
     return e;
   });
   if (st != SFC_OK) {
@@ -1511,6 +1549,10 @@ sfc_status compact_now(sfc_index* h) {
     sfc_status st2 = stree_refresh(h);
     if (st2 != SFC_OK) return st2;
   }
+  {
+    sfc_status st2 = cells_refresh(h);
+    if (st2 != SFC_OK) return st2;
+  }
   std::vector<std::pair<uint32_t, uint64_t>> rest;
   for (const auto& t : h->tombs)
     if (t.first > h->oldest) rest.push_back(t);
@@ -1578,6 +1620,8 @@ sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_
     st = stree_refresh(h);
     if (st != SFC_OK) return st;
   }
+  st = cells_refresh(h);
+  if (st != SFC_OK) return st;
   if (!h->hold) h->oldest = ep;
   ++h->generation;
   ++h->merges;

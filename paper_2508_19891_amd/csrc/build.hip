@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
     const uint32_t* __restrict__ rel, const uint32_t* __restrict__ dtot, uint64_t tiles,
     uint32_t* err, const double2* __restrict__ xy_in, double2* __restrict__ xy_out,
-    const uint32_t* __restrict__ set_id) {
+    uint64_t* __restrict__ cells_out, const uint32_t* __restrict__ set_id) {
   constexpr int kTile = kSortThreads * ITEMS;
   __shared__ union {
     uint32_t wave_hist[kSortWaves][kRadix];
@@ -306,7 +306,11 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
     }
     kout[pos] = k;
     vout[pos] = v;
-    if (GATHER) xy_out[pos] = xy_in[v];
+    if (GATHER) {
+      const double2 p = xy_in[v];
+      xy_out[pos] = p;
+      if (cells_out) cells_out[pos] = pack_cell2(p.x, p.y);
+    }
   }
 }
 
@@ -337,7 +341,8 @@ __global__ void gather_points(const uint32_t* __restrict__ ids, const double2* _
 }
 
 __global__ void gather_points3(const uint32_t* __restrict__ ids, const double* __restrict__ xyz,
-                               double* __restrict__ out, uint64_t n) {
+                               double* __restrict__ out, uint64_t* __restrict__ cells_out,
+                               uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const uint64_t v = ids[i];
@@ -345,7 +350,17 @@ __global__ void gather_points3(const uint32_t* __restrict__ ids, const double* _
     out[3 * i] = x;
     out[3 * i + 1] = y;
     out[3 * i + 2] = z;
+    if (cells_out) cells_out[i] = pack_cell3(x, y, z);
   }
+}
+
+// Grid cells of n points already in sorted order (after updates move them).
+__global__ void pack_cells_kernel(const double* __restrict__ xy, uint64_t n, int dim,
+                                  uint64_t* __restrict__ cells) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    cells[i] = dim == 3 ? pack_cell3(xy[3 * i], xy[3 * i + 1], xy[3 * i + 2])
+                        : pack_cell2(xy[2 * i], xy[2 * i + 1]);
 }
 
 // Keys per thread of a radix pass: 8, 12 or 16.  The environment variable
@@ -382,15 +397,15 @@ template <int ITEMS>
 hipError_t launch_scatter(bool first, bool gather, bool setpass, int shift, uint64_t tiles,
                           const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                           uint32_t* vout, uint64_t n, const uint32_t* rel, const uint32_t* dtot,
-                          uint32_t* err, const double* xy, double* xy_out, const uint32_t* set_id,
-                          hipStream_t s) {
+                          uint32_t* err, const double* xy, double* xy_out, uint64_t* cells_out,
+                          const uint32_t* set_id, hipStream_t s) {
   const dim3 g((uint32_t)(((tiles + 7) / 8) * 8)), b(kSortThreads);
   const double2* xi = (const double2*)xy;
   double2* xo = (double2*)xy_out;
 #define SFC_PASS(F, G, S)                                                                      \
   scatter_pass<ITEMS, F, G, S><<<g, b, 0, s>>>(kin, vin, kout, vout, n, shift, rel, dtot,     \
                                                tiles, err, G ? xi : nullptr, G ? xo : nullptr, \
-                                               set_id)
+                                               G ? cells_out : nullptr, set_id)
   if (setpass) {
     if (gather) SFC_PASS(false, true, true);
     else SFC_PASS(false, false, true);
@@ -451,7 +466,8 @@ hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, 
 // be recorded into a graph.
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err_host_visible,
-                      hipStream_t s, const uint64_t* set_off, uint32_t n_sets) {
+                      hipStream_t s, const uint64_t* set_off, uint32_t n_sets,
+                      uint64_t* cells_out) {
   if (n == 0) return hipSuccess;
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
@@ -506,7 +522,7 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     ProfScope ps(setpass ? "set_pass" : "scatter_pass", s);
 #define SFC_LAUNCH(I)                                                                        \
   launch_scatter<I>(pass == 0, gather, setpass, shift, tiles, kin, vin, kout, vout, n, rel, dtot, \
-                    err_host_visible, xy, xy_out, set_id, s)
+                    err_host_visible, xy, xy_out, cells_out, set_id, s)
     switch (sort_items(n)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;
@@ -519,10 +535,20 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   }
   if (curve == SFC_CURVE_MORTON3) {
     ProfScope ps("gather_points3", s);
-    gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids_out, xy, xy_out, n);
+    gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids_out, xy, xy_out, cells_out,
+                                                                n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t pack_cells(const double* xy, uint64_t n, int dim, uint64_t* cells, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  ProfScope ps("pack_cells", s);
+  pack_cells_kernel<<<(uint32_t)blocks, 256, 0, s>>>(xy, n, dim, cells);
+  return hipGetLastError();
 }
 
 hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipStream_t s) {

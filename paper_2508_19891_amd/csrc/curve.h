@@ -59,6 +59,16 @@ __host__ __device__ __forceinline__ uint64_t morton3_key(uint32_t x, uint32_t y,
   return spread_bits3(x) | (spread_bits3(y) << 1) | (spread_bits3(z) << 2);
 }
 
+// Grid cells of a point packed in one word: x | y << 32 in the plane,
+// x | y << 21 | z << 42 in three dimensions (coordinates in [0,1)).
+__host__ __device__ __forceinline__ uint64_t pack_cell2(double x, double y) {
+  return (uint64_t)quantize(x) | ((uint64_t)quantize(y) << 32);
+}
+__host__ __device__ __forceinline__ uint64_t pack_cell3(double x, double y, double z) {
+  return (uint64_t)quantize3(x) | ((uint64_t)quantize3(y) << 21) |
+         ((uint64_t)quantize3(z) << 42);
+}
+
 // Hilbert order.  The frame of a sub-square is one of four symmetries of the
 // square, kept as two bits: bit 0 = x and y exchanged, bit 1 = both
 // complemented.  At each level the pair of coordinate bits is mapped into the

@@ -40,9 +40,14 @@ size_t build_scratch_bytes(uint64_t n);
 // not null, receives the first digit's counts per sort tile.
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
                        uint32_t* counts, hipStream_t s);
+// cells_out (may be null): the grid cells of the sorted points (pack_cell2 /
+// pack_cell3), written with the points.
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
-                      hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0);
+                      hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0,
+                      uint64_t* cells_out = nullptr);
+// Grid cells of n points (dim 2 or 3 doubles each), in their order.
+hipError_t pack_cells(const double* xy, uint64_t n, int dim, uint64_t* cells, hipStream_t s);
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,
                          hipStream_t s);
 // Early-termination occupancy bitmap (kOccWords words) of n sorted keys.
@@ -66,6 +71,7 @@ struct QueryScratch {
                           // endpoints, [8]: learned fallbacks
   int ss;                 // log2 of the slots per query (2: method's ranges, 3: refined)
   uint64_t* pairs;        // dense (query, cell) work list: 4 * query + cell
+  void* qfilt;            // per query: its grid cell and the cell filter's limits (32 B)
 };
 constexpr uint64_t kCompactTileRows = 64;           // rows of 64 candidates per tile
 constexpr uint64_t kCompactChunkTiles = 1ull << 19; // tiles per launch
@@ -107,10 +113,13 @@ hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, cons
 // device (a plan for graph capture); more rows raise kErrOverflow.  cscratch
 // holds compact_scratch_bytes(max_rows).  window: the square-window test
 // (half side delta) instead of the Euclidean ball.  dim: 2, or 3 for points
-// and queries of three doubles.
+// and queries of three doubles.  cells (may be null): the grid cells of the
+// sorted points (pack_cells); with them most candidates are decided from
+// their cell and only the undecided ones read their coordinates.
 struct EpochView;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
-                          const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
+                          const uint64_t* cells, const uint32_t* ids, uint64_t npts,
+                          const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
                           int dim, hipStream_t s,

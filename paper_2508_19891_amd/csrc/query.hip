@@ -837,16 +837,116 @@ __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ 
   }
 }
 
+// ---- deciding the test from a point's grid cell ---------------------------------
+//
+// A point p with grid cell u = floor(p * S) (S = 2^32 in the plane, 2^21 in
+// three dimensions) lies in [u, u + 1) quanta on each axis.  Measured in
+// quanta from the query's own cell c = floor(q S), its offset on an axis is
+// o = e + th with the integer e = u - c and |th| < 1, so o^2 lies within
+// 2|e| + 1 of e^2.  A candidate comes from the query's own cells, which meet
+// the box widened by one quantum, so |e| <= E = 6R + 10 with R = d S (exact
+// scalings): the sum of the squared offsets lies within the slack
+// s = DIM (2E + 1) of the sum of the e^2.  For the Euclidean test:
+//   * if sum e^2 <= R^2 (1 - 2^-16) - s, the rounded binary64 test accepts p;
+//   * if sum e^2 > R^2 (1 + 2^-16) + s, it rejects p;
+// for the square window, |e| <= R (1 - 2^-16) - 1 on every axis accepts and
+// |e| > R (1 + 2^-16) + 1 on some axis rejects.  Evaluated in binary32
+// (relative errors below 2^-20 all told) these verdicts equal the exact
+// test's, whose own rounding is a few 2^-53 relative, when R >= 16 (so the
+// slack is small beside R^2).  Other points read their coordinates and take
+// the exact test.  A query uses the filter when 16 <= R <= 2^28 (plane) /
+// 2^17 (three dimensions) and its cell lies within 2^30 quanta of the
+// domain: then |e| < 2^31, exact in 32-bit arithmetic.  Cells sit in one
+// word: x | y << 32, or x | y << 21 | z << 42.
+struct QueryFilter {
+  uint32_t c[3];   // the query's cell per axis (low 32 bits)
+  float acc, rej;  // limits on sum e^2 (or per-axis |e|); acc = not a number: filter off
+  uint32_t pad[3];
+};
+
+template <int DIM>
+__global__ __launch_bounds__(256) void query_filters(const double* __restrict__ q,
+                                                     const double* __restrict__ delta, uint64_t m,
+                                                     bool window, QueryFilter* __restrict__ out) {
+  constexpr double S = DIM == 2 ? 4294967296.0 : 2097152.0;
+  constexpr double kMaxR = DIM == 2 ? 0x1p28 : 0x1p17;
+  const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= m) return;
+  const double R = delta[j] * S;
+  bool on = R >= 16.0 && R <= kMaxR;
+  QueryFilter f{};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const double qs = q[DIM * j + a] * S;
+    on = on && qs > -0x1p30 && qs < S + 0x1p30;
+    f.c[a] = (uint32_t)(int64_t)__builtin_floor(on ? qs : 0.0);
+  }
+  if (window) {
+    f.acc = (float)(R * (1.0 - 0x1p-16) - 1.0);
+    f.rej = (float)(R * (1.0 + 0x1p-16) + 1.0);
+  } else {
+    const double slack = DIM * (2.0 * (6.0 * R + 10.0) + 1.0);
+    f.acc = (float)(R * R * (1.0 - 0x1p-16) - slack);
+    f.rej = (float)(R * R * (1.0 + 0x1p-16) + slack);
+  }
+  if (!on) f.acc = __uint_as_float(0xFFFFFFFFu);
+  out[j] = f;
+}
+
+// 1: accepted, 0: rejected, -1: undecided by the cell.
+template <int DIM>
+__device__ __forceinline__ int cell_check(uint64_t cell, const QueryFilter& f, bool window) {
+  constexpr int B = DIM == 2 ? 32 : 21;
+  const uint64_t mask = (1ull << B) - 1;
+  float e[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    e[a] = (float)(int32_t)((uint32_t)((cell >> (B * a)) & mask) - f.c[a]);
+  if (window) {
+    bool in = true, out = false;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      in = in && fabsf(e[a]) <= f.acc;
+      out = out || fabsf(e[a]) > f.rej;
+    }
+    return in ? 1 : out ? 0 : -1;
+  }
+  float d2 = e[0] * e[0];
+#pragma unroll
+  for (int a = 1; a < DIM; ++a) d2 = d2 + e[a] * e[a];
+  return d2 <= f.acc ? 1 : d2 > f.rej ? 0 : -1;
+}
+
+// The exact test of candidate pos against query qs (the point and the query
+// read here: only for candidates their cell could not decide).
+template <int DIM>
+__device__ __forceinline__ bool exact_hit(const double* __restrict__ q,
+                                          const double* __restrict__ delta,
+                                          const double* __restrict__ pts, uint32_t qs,
+                                          uint32_t pos, bool window) {
+  const double d = delta[qs];
+  if (DIM == 2) {
+    const double2 qq = ((const double2*)q)[qs];
+    const double2 p = ((const double2*)pts)[pos];
+    return window ? within_window(p.x, p.y, qq.x, qq.y, d) : within(p.x, p.y, qq.x, qq.y, d);
+  }
+  const double* qp = q + 3 * (uint64_t)qs;
+  const double* pp = pts + 3 * (uint64_t)pos;
+  return window ? within_window3(pp[0], pp[1], pp[2], qp[0], qp[1], qp[2], d)
+                : within3(pp[0], pp[1], pp[2], qp[0], qp[1], qp[2], d);
+}
+
 // Pass 1: the exact test of every candidate; per row the 64-bit mask of the
 // accepted lanes, per tile their number.  Each wave handles 16 consecutive
 // rows as ITERS groups of ROWS rows whose point loads are in flight together.
 // EPOCH: a candidate that passes the test also has to be visible at the
 // query's epoch (ins <= e < era); only those lanes read the epochs.
 // window: the square-window test instead of the Euclidean one.
-template <int ROWS, int ITERS, bool EPOCH, int DIM>
+template <int ROWS, int ITERS, bool EPOCH, int DIM, bool CELLS>
 __global__ __launch_bounds__(256) void compact_test(
     const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
-    const double* __restrict__ pts, uint64_t npts, const uint4* __restrict__ row_meta,
+    const double* __restrict__ pts, const uint64_t* __restrict__ cells,
+    const QueryFilter* __restrict__ qfilt, uint64_t npts, const uint4* __restrict__ row_meta,
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     bool flag_overflow, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits,
     uint32_t* counters, const uint32_t* __restrict__ ins, const uint32_t* __restrict__ era,
@@ -864,8 +964,7 @@ __global__ __launch_bounds__(256) void compact_test(
       uint4 md = make_uint4(0, 0, 0, 0);
       if (lane < (uint32_t)ROWS && g0 + lane < total_rows) md = row_meta[g0 + lane - rbase];
       uint32_t pos[ROWS];
-      double qx[ROWS], qy[ROWS], qz[ROWS], dd[ROWS];
-      uint32_t qe[ROWS];
+      uint32_t qrow[ROWS];
       bool act[ROWS];
 #pragma unroll
       for (int jr = 0; jr < ROWS; ++jr) {
@@ -875,46 +974,72 @@ __global__ __launch_bounds__(256) void compact_test(
         const uint64_t p64 = (uint64_t)pb + lane;
         act[jr] = lane < nv && p64 < npts && qi < m;
         pos[jr] = act[jr] ? (uint32_t)p64 : 0u;
-        const uint32_t qs = qi < m ? qi : 0u;
-        if (DIM == 2) {
-          const double2 qq = ((const double2*)q)[qs];
-          qx[jr] = qq.x;
-          qy[jr] = qq.y;
-        } else {
-          qx[jr] = q[3 * (uint64_t)qs];
-          qy[jr] = q[3 * (uint64_t)qs + 1];
-          qz[jr] = q[3 * (uint64_t)qs + 2];
-        }
-        dd[jr] = delta[qs];
-        if (EPOCH) qe[jr] = qepoch ? qepoch[qs] : epoch;
+        qrow[jr] = qi < m ? qi : 0u;
       }
-      double2 pv[ROWS];
-      double pz[ROWS];
+      bool hit[ROWS];
+      if constexpr (CELLS) {
+        // Decide from the cells; the coordinates only for undecided lanes.
+        uint64_t cv[ROWS];
 #pragma unroll
-      for (int jr = 0; jr < ROWS; ++jr) {
-        if (act[jr]) {
+        for (int jr = 0; jr < ROWS; ++jr) cv[jr] = act[jr] ? cells[pos[jr]] : 0ull;
+#pragma unroll
+        for (int jr = 0; jr < ROWS; ++jr) {
+          const QueryFilter f = qfilt[qrow[jr]];
+          const int vd = !act[jr] ? 0 : f.acc == f.acc ? cell_check<DIM>(cv[jr], f, window) : -1;
+          hit[jr] = vd == 1;
+          if (vd < 0) hit[jr] = exact_hit<DIM>(q, delta, pts, qrow[jr], pos[jr], window);
+        }
+      } else {
+        double qx[ROWS], qy[ROWS], qz[ROWS], dd[ROWS];
+#pragma unroll
+        for (int jr = 0; jr < ROWS; ++jr) {
+          const uint32_t qs = qrow[jr];
           if (DIM == 2) {
-            pv[jr] = ((const double2*)pts)[pos[jr]];
+            const double2 qq = ((const double2*)q)[qs];
+            qx[jr] = qq.x;
+            qy[jr] = qq.y;
           } else {
-            pv[jr].x = pts[3 * (uint64_t)pos[jr]];
-            pv[jr].y = pts[3 * (uint64_t)pos[jr] + 1];
-            pz[jr] = pts[3 * (uint64_t)pos[jr] + 2];
+            qx[jr] = q[3 * (uint64_t)qs];
+            qy[jr] = q[3 * (uint64_t)qs + 1];
+            qz[jr] = q[3 * (uint64_t)qs + 2];
+          }
+          dd[jr] = delta[qs];
+        }
+        double2 pv[ROWS];
+        double pz[ROWS];
+#pragma unroll
+        for (int jr = 0; jr < ROWS; ++jr) {
+          if (act[jr]) {
+            if (DIM == 2) {
+              pv[jr] = ((const double2*)pts)[pos[jr]];
+            } else {
+              pv[jr].x = pts[3 * (uint64_t)pos[jr]];
+              pv[jr].y = pts[3 * (uint64_t)pos[jr] + 1];
+              pz[jr] = pts[3 * (uint64_t)pos[jr] + 2];
+            }
           }
         }
+#pragma unroll
+        for (int jr = 0; jr < ROWS; ++jr) {
+          if (DIM == 2)
+            hit[jr] = act[jr] &&
+                      (window ? within_window(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr])
+                              : within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]));
+          else
+            hit[jr] = act[jr] && (window ? within_window3(pv[jr].x, pv[jr].y, pz[jr], qx[jr],
+                                                          qy[jr], qz[jr], dd[jr])
+                                         : within3(pv[jr].x, pv[jr].y, pz[jr], qx[jr], qy[jr],
+                                                   qz[jr], dd[jr]));
+        }
       }
 #pragma unroll
       for (int jr = 0; jr < ROWS; ++jr) {
-        bool hit;
-        if (DIM == 2)
-          hit = act[jr] && (window ? within_window(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr])
-                                   : within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]));
-        else
-          hit = act[jr] && (window ? within_window3(pv[jr].x, pv[jr].y, pz[jr], qx[jr], qy[jr],
-                                                    qz[jr], dd[jr])
-                                   : within3(pv[jr].x, pv[jr].y, pz[jr], qx[jr], qy[jr], qz[jr],
-                                             dd[jr]));
-        if (EPOCH && hit) hit = ins[pos[jr]] <= qe[jr] && qe[jr] < era[pos[jr]];
-        const uint64_t bal = __ballot(hit);
+        bool h = hit[jr];
+        if (EPOCH && h) {
+          const uint32_t qe = qepoch ? qepoch[qrow[jr]] : epoch;
+          h = ins[pos[jr]] <= qe && qe < era[pos[jr]];
+        }
+        const uint64_t bal = __ballot(h);
         cnt += (uint32_t)__popcll(bal);
         if (lane == 0) masks[tile * kTileRows + (uint64_t)(w * ITERS + it) * ROWS + jr] = bal;
       }
@@ -1079,7 +1204,7 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) 
 size_t query_scratch_bytes(uint64_t m, uint32_t slots) {
   const uint64_t nseg = slots * m;
   return align256(nseg * 4) * 3 + align256((nseg + 1) * 8) + scan_scratch_bytes(nseg) +
-         align256(64) + align256(4 * m * 8);
+         align256(64) + align256(4 * m * 8) + align256(m * 32);
 }
 
 void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slots) {
@@ -1091,7 +1216,8 @@ void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slot
   qs->row_off = (uint64_t*)p;     p += align256((nseg + 1) * 8);
   qs->scan_tmp = (uint64_t*)p;    p += scan_scratch_bytes(nseg);
   qs->counters = (uint32_t*)p;    p += align256(64);
-  qs->pairs = (uint64_t*)p;
+  qs->pairs = (uint64_t*)p;       p += align256(4 * m * 8);
+  qs->qfilt = p;
   qs->ss = 2;
 }
 
@@ -1210,7 +1336,8 @@ hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, cons
 }
 
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
-                          const uint32_t* ids, uint64_t npts, const QueryScratch& qs,
+                          const uint64_t* cells, const uint32_t* ids, uint64_t npts,
+                          const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
                           int dim, hipStream_t s, const EpochView* ev, bool write_only) {
@@ -1241,6 +1368,15 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
   // write_only: the masks and tile offsets of an earlier call on the same
   // batch are still in cscratch (one chunk only); run the write pass again.
   if (write_only && (chunks != 1 || device_sized)) return hipErrorInvalidValue;
+  if (cells && !write_only) {
+    ProfScope ps("query_filters", s);
+    const uint32_t qb = (uint32_t)((m + 255) / 256);
+    if (dim == 3)
+      query_filters<3><<<qb, 256, 0, s>>>(q, delta, m, window, (QueryFilter*)qs.qfilt);
+    else
+      query_filters<2><<<qb, 256, 0, s>>>(q, delta, m, window, (QueryFilter*)qs.qfilt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   for (uint64_t c = 0; c < chunks; ++c, buf ^= 1) {
     const uint64_t rbase = c * chunk * kCompactTileRows;
     const uint64_t nt = tiles_all - c * chunk < chunk ? (tiles_all ? tiles_all - c * chunk : 1)
@@ -1260,17 +1396,21 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
     }
     if (!write_only) {
       ProfScope ps("compact_test", s);
+#define SFC_TEST_D(R, I, E, D, C)                                                          \
+  compact_test<R, I, E, D, C><<<grid, 256, 0, s>>>(                                        \
+      q, delta, m, pts, cells, (const QueryFilter*)qs.qfilt, npts, meta, total_dev, rbase,  \
+      row_end, flag,                                                                       \
+      masks, hits,                                                                         \
+      qs.counters, ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                         \
+      ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u, window)
 #define SFC_TEST(R, I, E)                                                                  \
-  if (dim == 3)                                                                            \
-    compact_test<R, I, E, 3><<<grid, 256, 0, s>>>(                                         \
-        q, delta, m, pts, npts, meta, total_dev, rbase, row_end, flag, masks, hits,        \
-        qs.counters, ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                       \
-        ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u, window);                           \
-  else                                                                                     \
-    compact_test<R, I, E, 2><<<grid, 256, 0, s>>>(                                         \
-        q, delta, m, pts, npts, meta, total_dev, rbase, row_end, flag, masks, hits,        \
-        qs.counters, ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                       \
-        ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u, window)
+  if (dim == 3) {                                                                          \
+    if (cells) SFC_TEST_D(R, I, E, 3, true);                                               \
+    else SFC_TEST_D(R, I, E, 3, false);                                                    \
+  } else {                                                                                 \
+    if (cells) SFC_TEST_D(R, I, E, 2, true);                                               \
+    else SFC_TEST_D(R, I, E, 2, false);                                                    \
+  }
 #define SFC_TEST_SHAPES(E)                  \
   switch (test_variant(max_rows)) {         \
     case 1: SFC_TEST(4, 4, E); break;       \
@@ -1286,6 +1426,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
       }
 #undef SFC_TEST_SHAPES
 #undef SFC_TEST
+#undef SFC_TEST_D
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!write_only &&

@@ -43,7 +43,7 @@ EXPORTS = [
     "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
-    "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric",
+    "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric", "sfc_set_cell_filter",
 ]
 
 NPARAM = 1153
@@ -150,6 +150,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_set_search.restype = i32
     L.sfc_set_metric.argtypes = [vp, i32]
     L.sfc_set_metric.restype = i32
+    L.sfc_set_cell_filter.argtypes = [vp, i32]
+    L.sfc_set_cell_filter.restype = i32
     L.sfc_learned_fit.argtypes = [vp, i32]
     L.sfc_learned_fit.restype = i32
     L.sfc_learned_info_get.argtypes = [vp, ctypes.POINTER(LearnedInfo)]
@@ -492,6 +494,11 @@ class Index:
         _check(lib().sfc_query_ranges(self.handle, _ptr(q), _ptr(delta), m, _ptr(klo), _ptr(khi),
                                       _ptr(b), _ptr(e), _ptr(nr)), "sfc_query_ranges")
         return klo, khi, b, e, nr
+
+    def set_cell_filter(self, on: bool):
+        """Decide candidates from their grid cell where the cell settles the
+        test (default), or run the exact test on every candidate."""
+        _check(lib().sfc_set_cell_filter(self.handle, 1 if on else 0), "sfc_set_cell_filter")
 
     def set_metric(self, metric: int):
         _check(lib().sfc_set_metric(self.handle, metric), "sfc_set_metric")

@@ -1,0 +1,151 @@
+"""Candidates decided from their grid cell (the default) give exactly the
+exact test's results: against the oracle, on points placed within a few
+units in the last place of the query boundary (where the cell cannot decide),
+on quantum edges, at radii that underflow or overflow when squared, in three
+dimensions and with square windows, after updates and recorded builds."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import HILBERT, L2, LINF, MORTON
+from paper_2508_19891_amd import sfc, workload
+from snapshots import Model
+from test_oracle import _adversarial, _window_adversarial
+from test_oracle3 import _adversarial3
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(DEV)
+
+
+def both(idx, qs, ds):
+    """Results with the cell filter and with the exact test on every candidate."""
+    out = []
+    for on in (True, False):
+        idx.set_cell_filter(on)
+        off, ids = idx.query(dev(qs), dev(ds))
+        out.append((off.cpu().numpy().view(np.uint64), ids.cpu().numpy().view(np.uint32)))
+    idx.set_cell_filter(True)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    return out[0]
+
+
+def boundary_points(rng, qs, ds, per=24, metric=L2):
+    """Points at distance d (1 + k 2^-52), k in [-6, 6], around each query
+    (rounded to doubles, so some land exactly on the boundary): the band
+    where only the exact test can decide."""
+    pts = []
+    for q, d in zip(qs, ds):
+        for _ in range(per):
+            k = rng.integers(-6, 7)
+            if metric == L2:
+                a = rng.uniform(0, 2 * np.pi)
+                v = np.array([np.cos(a), np.sin(a)])
+            else:
+                v = np.array([1.0, rng.uniform(-1, 1)])[rng.permutation(2)] * rng.choice([-1, 1])
+            p = q + d * (1 + k * 2.0 ** -52) * v
+            if np.all(p >= 0) and np.all(p < 1):
+                pts.append(p)
+    return np.array(pts)
+
+
+@pytest.mark.parametrize("metric", [L2, LINF])
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_boundary_band(curve, metric):
+    rng = np.random.default_rng(100 + curve + 2 * metric)
+    qs = rng.uniform(0.1, 0.9, (400, 2))
+    ds = 10 ** rng.uniform(-6, -1.5, 400)
+    pts = np.concatenate([boundary_points(rng, qs, ds, metric=metric), rng.random((20_000, 2))])
+    idx = sfc.Index(dev(pts), curve, refine=True, metric=sfc.LINF if metric else sfc.L2)
+    off, ids = both(idx, qs, ds)
+    ref = oracle.query(oracle.build(pts, curve), qs, ds, curve, metric=metric)
+    assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
+    assert ref[1].size > 2000
+
+
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_adversarial_sets(curve):
+    rng = np.random.default_rng(110 + curve)
+    pts, qs, ds = _adversarial(rng)
+    idx = sfc.Index(dev(pts), curve)
+    off, ids = both(idx, qs, ds)
+    ref = oracle.query(oracle.build(pts, curve), qs, ds, curve)
+    assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
+    pts, qs, ds = _window_adversarial(rng)
+    idx = sfc.Index(dev(pts), curve, metric=sfc.LINF)
+    off, ids = both(idx, qs, ds)
+    ref = oracle.query(oracle.build(pts, curve), qs, ds, curve, metric=LINF)
+    assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
+
+
+def test_extreme_radii_and_far_queries():
+    rng = np.random.default_rng(120)
+    pts = rng.random((5000, 2))
+    pts[:50] = pts[50:100]
+    qs = np.array([pts[3], pts[60], [0.5, 0.5], [0.5, 0.5], [1e200, 0.5], [-1e200, 1e200],
+                   [0.25, 0.75], pts[70], pts[80], [0.5, 0.5]])
+    ds = np.array([1e-300, 2.0 ** -460, 2.0 ** -449, 1e200, 1e200, 1e150, 1e-170, 2.0 ** -500,
+                   0.0, 1e160])
+    for metric, om in ((sfc.L2, L2), (sfc.LINF, LINF)):
+        idx = sfc.Index(dev(pts), MORTON, metric=metric)
+        off, ids = both(idx, qs, ds)
+        ref = oracle.query(oracle.build(pts, MORTON), qs, ds, MORTON, metric=om)
+        assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
+
+
+@pytest.mark.parametrize("metric", [L2, LINF])
+def test_three_dimensions(metric):
+    rng = np.random.default_rng(130 + metric)
+    pts, qs, ds = _adversarial3(rng)
+    band = []
+    for q, d in zip(qs[:30], ds[:30]):
+        for _ in range(20):
+            v = rng.standard_normal(3)
+            v = v / (np.linalg.norm(v) if metric == L2 else np.abs(v).max())
+            p = q + d * (1 + rng.integers(-6, 7) * 2.0 ** -52) * v
+            if np.all(p >= 0) and np.all(p < 1):
+                band.append(p)
+    pts = np.concatenate([pts, np.array(band)])
+    for refine in (False, True):
+        idx = sfc.Index(dev(pts), sfc.MORTON3, refine=refine,
+                        metric=sfc.LINF if metric else sfc.L2)
+        off, ids = both(idx, qs, ds)
+        ref = oracle.query3(oracle.build3(pts), qs, ds, metric=metric)
+        assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
+
+
+def test_cells_follow_updates_and_recorded_builds():
+    pts = workload.uniform_points(50_000, 140)
+    qs = workload.uniform_points(3_000, 141)
+    ds = np.full(3_000, 0.01)
+    idx = sfc.Index(dev(pts), HILBERT, refine=True)
+    model = Model(pts)
+    for k, seed in ((10_000, 142), (120_000, 143)):     # grows past the cells' capacity
+        more = workload.uniform_points(k, seed)
+        idx.insert(dev(more))
+        model.insert(more)
+        want = model.reference(qs, ds, np.full(3_000, model.epoch), HILBERT)
+        off, ids = both(idx, qs, ds)
+        assert np.array_equal(off, want[0]) and np.array_equal(ids, want[1])
+    gone = np.random.default_rng(144).choice(len(model.xy), 40_000, replace=False)
+    idx.erase(dev(gone, torch.int32))
+    model.erase(gone)
+    assert idx.update_info()["compactions"] >= 1
+    want = model.reference(qs, ds, np.full(3_000, model.epoch), HILBERT)
+    off, ids = both(idx, qs, ds)
+    assert np.array_equal(off, want[0]) and np.array_equal(ids, want[1])
+    buf = dev(pts)
+    fresh = sfc.Index(buf, MORTON)
+    g = sfc.Graph.build(fresh, buf)
+    other = workload.uniform_points(len(pts), 145)
+    buf.copy_(dev(other))
+    g.launch()
+    g.wait()
+    off, ids = both(fresh, qs, ds)
+    ref = oracle.query(oracle.build(other, MORTON), qs, ds, MORTON)
+    assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
+    g.close()
