@@ -432,7 +432,9 @@ sfc_status sfc_set_metric(sfc_index* h, int metric);
    outside the query by a relative margin of 2^-40, far beyond the test's
    rounding, and reads the coordinates only for the rest: the same results
    as the test on every candidate (on = 0), from about half the memory
-   traffic.  SFC_ERR_INVALID for another value.  No device work. */
+   traffic.  An index drops its cells at its first insert or erase (its
+   queries then test every candidate exactly).  SFC_ERR_INVALID for another
+   value.  No device work. */
 sfc_status sfc_set_cell_filter(sfc_index* h, int on);
 /* (Re)fits the learned index with the given training steps (< 0: the
    handle's default).  SFC_ERR_UNSUPPORTED for n < 2. */

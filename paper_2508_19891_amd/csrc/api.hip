@@ -220,7 +220,6 @@ struct sfc_index {
   // grid cells of the sorted points (decide most candidates without reading
   // their coordinates); kept in step with xy
   uint64_t* cells = nullptr;
-  uint64_t cells_cap = 0;
   bool cell_filter = true;
   // static search tree: layers above the keys (built while search is STREE)
   void* stree = nullptr;
@@ -335,6 +334,7 @@ void release_arrays(sfc_index* h) {
   h->alloc.put(h->spare.xy);
   h->alloc.put(h->spare.ins);
   h->alloc.put(h->spare.era);
+  h->alloc.put(h->spare.cells);
   h->alloc.put(h->key_of);
   h->alloc.put(h->upd_word);
   h->alloc.put(h->occ);
@@ -343,7 +343,6 @@ void release_arrays(sfc_index* h) {
   h->stree = nullptr;
   h->alloc.put(h->cells);
   h->cells = nullptr;
-  h->cells_cap = 0;
   h->stree_bytes = 0;
   h->stree_ready = false;
   h->ins = h->era = nullptr;
@@ -369,10 +368,12 @@ void release_arrays(sfc_index* h) {
 sfc_status stree_refresh(sfc_index* h) {
   const size_t need = sfc::stree_bytes(h->n);
   if (need > h->stree_bytes) {
+    // room for a quarter more keys, so that a stream of inserts rarely grows it
+    const size_t room = sfc::stree_bytes(h->n + h->n / 4);
     SFC_TRY(hipStreamSynchronize(h->stream));   // the old layers may still be read
     h->alloc.put(h->stree);
-    h->stree = h->alloc.get(need);
-    h->stree_bytes = h->stree ? need : 0;
+    h->stree = h->alloc.get(room);
+    h->stree_bytes = h->stree ? room : 0;
     h->stree_ready = false;
     if (!h->stree) return SFC_ERR_NOMEM;
   }
@@ -382,21 +383,6 @@ sfc_status stree_refresh(sfc_index* h) {
 }
 
 bool stree_on(const sfc_index* h) { return h->search == SFC_SEARCH_STREE && h->stree_ready; }
-
-// The grid cells of the current points, after an update moved them; the
-// buffer grows first when the points outgrew it.
-sfc_status cells_refresh(sfc_index* h) {
-  if (h->n > h->cells_cap) {
-    SFC_TRY(hipStreamSynchronize(h->stream));   // the old cells may still be read
-    h->alloc.put(h->cells);
-    h->cells = (uint64_t*)h->alloc.get(h->n * 8);
-    h->cells_cap = h->cells ? h->n : 0;
-    if (!h->cells) return SFC_ERR_NOMEM;
-  }
-  SFC_TRY(sfc::pack_cells(h->xy, h->n, h->curve == SFC_CURVE_MORTON3 ? 3 : 2, h->cells,
-                          h->stream));
-  return SFC_OK;
-}
 
 // The cells the test may decide candidates from (null: every candidate takes
 // the exact test).
@@ -682,7 +668,6 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
     h->ids = (uint32_t*)h->alloc.get(n * 4);
     h->xy = (double*)h->alloc.get(n * 8 * dim_of(h));
     h->cells = (uint64_t*)h->alloc.get(n * 8);
-    h->cells_cap = n;
     const size_t sb = sfc::build_scratch_bytes(n) + 256;
     void* scratch = h->alloc.get(sb);
     if (!h->keys || !h->ids || !h->xy || !h->cells || !scratch) {
@@ -1439,6 +1424,11 @@ sfc_status ensure_dynamic(sfc_index* h) {
   h->key_of = key_of;
   h->key_of_cap = kc;
   h->upd_word = word;
+  // An index that takes updates drops the grid cells: every merge and
+  // compaction rewrites the whole run, and carrying the cells would add a
+  // fifth of its traffic; its queries test every candidate exactly.
+  h->alloc.put(h->cells);
+  h->cells = nullptr;
   return SFC_OK;
 }
 
@@ -1452,6 +1442,7 @@ sfc_status ensure_spare(sfc_index* h, uint64_t need) {
   h->alloc.put(r.xy);
   h->alloc.put(r.ins);
   h->alloc.put(r.era);
+  h->alloc.put(r.cells);
   r = sfc::Run{};
   h->spare_cap = 0;
   const uint64_t c = need + need / 4;
@@ -1466,6 +1457,7 @@ sfc_status ensure_spare(sfc_index* h, uint64_t need) {
     h->alloc.put(r.xy);
     h->alloc.put(r.ins);
     h->alloc.put(r.era);
+    h->alloc.put(r.cells);
     r = sfc::Run{};
     return SFC_ERR_NOMEM;
   }
@@ -1501,6 +1493,7 @@ sfc::Run current_run(const sfc_index* h) {
   r.xy = h->xy;
   r.ins = h->ins;
   r.era = h->era;
+  r.cells = h->cells;
   return r;
 }
 
@@ -1510,6 +1503,7 @@ void swap_runs(sfc_index* h) {
   std::swap(h->xy, h->spare.xy);
   std::swap(h->ins, h->spare.ins);
   std::swap(h->era, h->spare.era);
+  std::swap(h->cells, h->spare.cells);
   std::swap(h->cap, h->spare_cap);
 }
 
@@ -1549,10 +1543,7 @@ sfc_status compact_now(sfc_index* h) {
     sfc_status st2 = stree_refresh(h);
     if (st2 != SFC_OK) return st2;
   }
-  {
-    sfc_status st2 = cells_refresh(h);
-    if (st2 != SFC_OK) return st2;
-  }
+
   std::vector<std::pair<uint32_t, uint64_t>> rest;
   for (const auto& t : h->tombs)
     if (t.first > h->oldest) rest.push_back(t);
@@ -1620,8 +1611,6 @@ sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_
     st = stree_refresh(h);
     if (st != SFC_OK) return st;
   }
-  st = cells_refresh(h);
-  if (st != SFC_OK) return st;
   if (!h->hold) h->oldest = ep;
   ++h->generation;
   ++h->merges;

@@ -354,15 +354,6 @@ __global__ void gather_points3(const uint32_t* __restrict__ ids, const double* _
   }
 }
 
-// Grid cells of n points already in sorted order (after updates move them).
-__global__ void pack_cells_kernel(const double* __restrict__ xy, uint64_t n, int dim,
-                                  uint64_t* __restrict__ cells) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    cells[i] = dim == 3 ? pack_cell3(xy[3 * i], xy[3 * i + 1], xy[3 * i + 2])
-                        : pack_cell2(xy[2 * i], xy[2 * i + 1]);
-}
-
 // Keys per thread of a radix pass: 8, 12 or 16.  The environment variable
 // SFC_SORT_ITEMS overrides; else the autotuner's choice for this size; else 16.
 int sort_items(uint64_t n) {
@@ -540,15 +531,6 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
-}
-
-hipError_t pack_cells(const double* xy, uint64_t n, int dim, uint64_t* cells, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  uint64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  ProfScope ps("pack_cells", s);
-  pack_cells_kernel<<<(uint32_t)blocks, 256, 0, s>>>(xy, n, dim, cells);
-  return hipGetLastError();
 }
 
 hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipStream_t s) {

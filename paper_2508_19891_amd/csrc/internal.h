@@ -46,8 +46,6 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
                       hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0,
                       uint64_t* cells_out = nullptr);
-// Grid cells of n points (dim 2 or 3 doubles each), in their order.
-hipError_t pack_cells(const double* xy, uint64_t n, int dim, uint64_t* cells, hipStream_t s);
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,
                          hipStream_t s);
 // Early-termination occupancy bitmap (kOccWords words) of n sorted keys.
@@ -114,8 +112,8 @@ hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, cons
 // holds compact_scratch_bytes(max_rows).  window: the square-window test
 // (half side delta) instead of the Euclidean ball.  dim: 2, or 3 for points
 // and queries of three doubles.  cells (may be null): the grid cells of the
-// sorted points (pack_cells); with them most candidates are decided from
-// their cell and only the undecided ones read their coordinates.
+// sorted points (pack_cell2 / pack_cell3); with them most candidates are
+// decided from their cell and only the undecided ones read their coordinates.
 struct EpochView;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const uint64_t* cells, const uint32_t* ids, uint64_t npts,
@@ -143,6 +141,7 @@ struct Run {
   double* xy = nullptr;
   uint32_t* ins = nullptr;
   uint32_t* era = nullptr;
+  uint64_t* cells = nullptr;   // grid cells of the points (pack_cell2) if kept (may be null)
 };
 // Which stored entries a query sees: those with ins <= e < era, e = the
 // query's epoch (qepoch[j], or `epoch` when qepoch is null).  ins == null:

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "curve.h"
 #include "internal.h"
 
 namespace sfc {
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(kThreads) void merge_stored(
     const double2* __restrict__ xy, const uint32_t* __restrict__ ins,
     const uint32_t* __restrict__ era, uint64_t n, const uint64_t* __restrict__ bkeys, uint64_t k,
     uint64_t* __restrict__ okeys, uint32_t* __restrict__ oids, double2* __restrict__ oxy,
-    uint32_t* __restrict__ oins, uint32_t* __restrict__ oera) {
+    uint32_t* __restrict__ oins, uint32_t* __restrict__ oera, uint64_t* __restrict__ ocells) {
   __shared__ uint64_t s_br[2];
   const uint64_t t0 = (uint64_t)blockIdx.x * kMergeTile;
   const uint64_t t1 = t0 + kMergeTile < n ? t0 + kMergeTile : n;
@@ -78,11 +79,13 @@ __global__ __launch_bounds__(kThreads) void merge_stored(
   for (uint64_t i = t0 + threadIdx.x; i < t1; i += kThreads) {
     const uint64_t key = keys[i];
     const uint64_t o = i + lower_bound_u64(bkeys, b0, b1, key);
+    const double2 p = xy[i];
     okeys[o] = key;
     oids[o] = ids[i];
-    oxy[o] = xy[i];
+    oxy[o] = p;
     oins[o] = ins[i];
     oera[o] = era[i];
+    if (ocells) ocells[o] = pack_cell2(p.x, p.y);
   }
 }
 
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void merge_batch(
     const uint32_t* __restrict__ bids, const double2* __restrict__ bxy, uint64_t k,
     uint32_t id_base, uint32_t epoch, uint64_t* __restrict__ okeys, uint32_t* __restrict__ oids,
     double2* __restrict__ oxy, uint32_t* __restrict__ oins, uint32_t* __restrict__ oera,
-    uint64_t* __restrict__ key_of) {
+    uint64_t* __restrict__ ocells, uint64_t* __restrict__ key_of) {
   const uint64_t j = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
   if (j >= k) return;
   const uint32_t lid = bids[j];
@@ -102,11 +105,13 @@ __global__ __launch_bounds__(kThreads) void merge_batch(
   const uint64_t key = bkeys[j];
   const uint64_t o = j + upper_bound_u64(keys, 0, n, key);
   const uint32_t id = id_base + lid;
+  const double2 p = bxy[j];
   okeys[o] = key;
   oids[o] = id;
-  oxy[o] = bxy[j];
+  oxy[o] = p;
   oins[o] = epoch;
   oera[o] = kLiveEpoch;
+  if (ocells) ocells[o] = pack_cell2(p.x, p.y);
   key_of[id] = key;
 }
 
@@ -179,7 +184,8 @@ __global__ __launch_bounds__(kThreads) void compact_scatter(
     const uint32_t* __restrict__ era, uint64_t n, uint32_t oldest,
     const uint64_t* __restrict__ block_off, uint64_t* __restrict__ okeys,
     uint32_t* __restrict__ oids, double2* __restrict__ oxy, uint32_t* __restrict__ oins,
-    uint32_t* __restrict__ oera) {
+    uint32_t* __restrict__ oera, const uint64_t* __restrict__ cells,
+    uint64_t* __restrict__ ocells) {
   __shared__ uint32_t s_w[kThreads / 64];
   const uint32_t w = threadIdx.x >> 6;
   const uint64_t base = (uint64_t)blockIdx.x * kCompactBlock;
@@ -203,6 +209,7 @@ __global__ __launch_bounds__(kThreads) void compact_scatter(
       oxy[o] = xy[i];
       oins[o] = ins[i];
       oera[o] = era[i];
+      if (ocells) ocells[o] = cells[i];
     }
     out += total;
     __syncthreads();
@@ -236,7 +243,7 @@ hipError_t merge_runs(const Run& stored, uint64_t n, const uint64_t* bkeys, cons
     ProfScope ps("merge_stored", s);
     merge_stored<<<grid_for(n, kMergeTile), kThreads, 0, s>>>(
         stored.keys, stored.ids, (const double2*)stored.xy, stored.ins, stored.era, n, bkeys, k,
-        out.keys, out.ids, (double2*)out.xy, out.ins, out.era);
+        out.keys, out.ids, (double2*)out.xy, out.ins, out.era, out.cells);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -244,7 +251,7 @@ hipError_t merge_runs(const Run& stored, uint64_t n, const uint64_t* bkeys, cons
     ProfScope ps("merge_batch", s);
     merge_batch<<<grid_for(k, kThreads), kThreads, 0, s>>>(
         stored.keys, n, bkeys, bids, (const double2*)bxy, k, id_base, epoch, out.keys, out.ids,
-        (double2*)out.xy, out.ins, out.era, key_of);
+        (double2*)out.xy, out.ins, out.era, out.cells, key_of);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -290,7 +297,7 @@ hipError_t compact_entries(const Run& stored, uint64_t n, uint32_t oldest, const
   if ((e = scan_excl(kept, off, nb, nullptr, tmp, s)) != hipSuccess) return e;
   compact_scatter<<<(uint32_t)nb, kThreads, 0, s>>>(
       stored.keys, stored.ids, (const double2*)stored.xy, stored.ins, stored.era, n, oldest, off,
-      out.keys, out.ids, (double2*)out.xy, out.ins, out.era);
+      out.keys, out.ids, (double2*)out.xy, out.ins, out.era, stored.cells, out.cells);
   return hipGetLastError();
 }
 
