@@ -67,6 +67,10 @@ def cpu_baseline(wl, curve: int, m_sample: int):
     t0 = time.perf_counter()
     off, _ = oracle.query(idx, qs, ds, curve, nthreads=threads)
     t_query = time.perf_counter() - t0
+    m1 = max(1, m_sample // 8)   # one thread: an eighth of the sample
+    t0 = time.perf_counter()
+    oracle.query(idx, qs[:m1], ds[:m1], curve, nthreads=1)
+    t_query1 = time.perf_counter() - t0
     m = wl.queries.shape[0]
     t_step = t_build + t_query * (m / m_sample)
     return {
@@ -78,6 +82,8 @@ def cpu_baseline(wl, curve: int, m_sample: int):
                    f"({t_build:.2f} s) + the first {m_sample} of {m} queries on {threads} "
                    f"threads ({t_query:.2f} s, scaled x{m / m_sample:g})"),
         "reported_sample": int(off[-1]),
+        "queries_per_s_1_thread": m1 / t_query1,
+        "queries_per_s_all_threads": m_sample / t_query,
     }
 
 
@@ -152,7 +158,9 @@ def learned_large_bench(args, sfc, workload, torch):
     """The learned-index shape: 2^26 clustered points, Morton keys, 2^22
     uniform queries with delta = sqrt(10 / (pi n)) (about 10 reports each at
     unit density); query batches over one built index, binary vs learned
-    search, the learned fit timed once."""
+    search (and the static search tree), the learned fit timed once.  A
+    secondary batch draws the queries from the points' mixture (same delta,
+    a few hundred reports each)."""
     dev = torch.device("cuda:0")
     wl = workload.clustered_uniform_queries(n=1 << 26, m=1 << 22, curve=sfc.MORTON)
     n, m = wl.points.shape[0], wl.queries.shape[0]
@@ -160,9 +168,10 @@ def learned_large_bench(args, sfc, workload, torch):
     pts = torch.as_tensor(wl.points).to(dev)
     q = torch.as_tensor(wl.queries).to(dev)
     d = torch.as_tensor(wl.delta).to(dev)
+    qm = torch.as_tensor(workload.clustered_points(m, 4003, workload.make_mixture(503))).to(dev)
     offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
     out = {"workload": wl.name + "_morton", "n": n, "m": m}
-    reps = []
+    reps, reps_m = [], []
     for name, search in (("bsearch", sfc.BINARY), ("learned", sfc.LEARNED),
                          ("stree", sfc.STREE)):
         torch.cuda.synchronize()
@@ -201,14 +210,30 @@ def learned_large_bench(args, sfc, workload, torch):
             out[name]["model"] = {k: info[k] for k in ("leaves_nonempty", "max_leaf", "pieces",
                                                        "mean_window", "max_window", "search_steps",
                                                        "fallbacks_last")}
+        del out_ids
+        # Secondary: queries from the mixture.
+        _, ids0 = idx.query(qm, d)
+        out_ids = torch.empty(ids0.numel() + 1024, dtype=torch.int32, device=dev)
+        reps_m.append(int(ids0.numel()))
+        del ids0
+        idx.query(qm, d, out_ids=out_ids, out_offsets=offsets)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            idx.query(qm, d, out_ids=out_ids, out_offsets=offsets)
+        torch.cuda.synchronize()
+        ms_m = (time.perf_counter() - t0) / args.steps * 1e3
+        out[name]["mixture_q"] = {"ms_per_batch": ms_m, "queries_per_s": m / (ms_m * 1e-3),
+                                  "reported_pts_per_s": reps_m[-1] / (ms_m * 1e-3)}
         idx.close()
         del out_ids
-    assert reps[0] == reps[1] == reps[2]
+    assert reps[0] == reps[1] == reps[2] and reps_m[0] == reps_m[1] == reps_m[2]
     out["reported_per_batch"] = reps[0]
+    out["reported_per_batch_mixture_q"] = reps_m[0]
     out["speedup_batch"] = out["bsearch"]["ms_per_batch"] / out["learned"]["ms_per_batch"]
     out["speedup_search"] = out["bsearch"]["search_ms"] / out["learned"]["search_ms"]
     out["speedup_search_stree"] = out["bsearch"]["search_ms"] / out["stree"]["search_ms"]
-    del pts, q, d
+    del pts, q, d, qm
     torch.cuda.empty_cache()
     return out
 
@@ -431,7 +456,7 @@ def main():
                     help="skip the paper's square-window sweep")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the insert/erase/query serving measurement")
-    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-n-log2", type=int, default=25)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (counter calibration)")
@@ -454,6 +479,21 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("copy probe: 3 x 2^30 B device-to-device")
+
+    # The attainable HBM rate: a plain device-to-device copy of 2^30 bytes
+    # (2^31 bytes moved per copy), timed over 10 copies.
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    log(f"device copy: {copy_gbs:.0f} GB/s")
 
     n, m = 1 << args.n_log2, 1 << args.m_log2
     curve = sfc.HILBERT
@@ -653,6 +693,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "copy_gbs": copy_gbs,   # attainable: a plain device copy on this GPU
         },
         "kernels_algorithmic_gbs": kern_gbs,
     }

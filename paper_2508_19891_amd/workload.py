@@ -19,8 +19,10 @@ Generators are numpy PCG64 streams; every function takes an explicit seed.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -39,12 +41,27 @@ class Mixture:
     frac: float
 
     def density(self, q: np.ndarray) -> np.ndarray:
-        """Analytic density of the (unclamped) mixture at the rows of q."""
+        """Analytic density of the (unclamped) mixture at the rows of q
+        (evaluated in slices of rows, each row as a whole)."""
         q = np.asarray(q, np.float64)
         k = self.centres.shape[0]
-        d2 = ((q[:, None, :] - self.centres[None, :, :]) ** 2).sum(-1)
-        g = np.exp(-d2 / (2.0 * self.sigma ** 2)) / (2.0 * math.pi * self.sigma ** 2)
-        return (1.0 - self.frac) + (self.frac / k) * g.sum(1)
+        out = np.empty(q.shape[0])
+        step = 1 << 16
+
+        def part(a):
+            qa = q[a:a + step]
+            d2 = ((qa[:, None, :] - self.centres[None, :, :]) ** 2).sum(-1)
+            g = np.exp(-d2 / (2.0 * self.sigma ** 2)) / (2.0 * math.pi * self.sigma ** 2)
+            out[a:a + step] = (1.0 - self.frac) + (self.frac / k) * g.sum(1)
+
+        starts = range(0, q.shape[0], step)
+        if q.shape[0] <= 4 * step:
+            for a in starts:
+                part(a)
+        else:   # numpy releases the interpreter lock inside these operations
+            with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(part, starts))
+        return out
 
     def sample(self, n: int, rng: np.random.Generator) -> np.ndarray:
         nc = (int(round(self.frac * 1000)) * n) // 1000   # floor(frac * n)
