@@ -16,9 +16,10 @@
 //   compact_test   a block tests its tiles' candidates (64-lane rows) with
 //                  the exact distance test and counts the hits per tile;
 //                  the hit counts are scanned on the device.
-//   compact_write  the same tiles again: reported ids at the scanned
-//                  positions, in candidate order, and the CSR offsets of the
-//                  queries.
+//   compact_write  the same tiles again, one lane per reported id: the ids at
+//                  the scanned positions, in candidate order, and every
+//                  row's output position.
+//   query_offsets  the CSR offset of every query, from its first row.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -1059,27 +1060,33 @@ __global__ __launch_bounds__(256) void compact_test(
 // row order (= curve order per query), and the absolute output position of
 // every row of the tile (row_pre, chunk-relative index; the entry one past a
 // tile's last row is the next tile's first, and the one at the batch's last
-// row + 1 is the total).
-template <int ROWS, int ITERS>
-__global__ __launch_bounds__(256) void compact_write(
+// row + 1 is the total).  Output-driven: one lane per reported id rather than
+// one per candidate (about a quarter of the candidates are reported).  Output
+// o of a tile lies in the row r with pre[r] <= o < pre[r + 1] (found by
+// binary search over the tile's 65 prefix counts in LDS), at the
+// (o - pre[r])-th set bit of the row's mask (found by halving the mask by
+// population counts); its id is read at the row's first candidate position
+// plus that bit.  Writes are contiguous; a tile with few hits costs few
+// lanes.
+__global__ __launch_bounds__(256) void compact_write_out(
     const uint32_t* __restrict__ ids, uint64_t npts, const uint4* __restrict__ row_meta,
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     const uint64_t* __restrict__ masks, const uint64_t* __restrict__ tile_off,
     uint64_t* __restrict__ row_pre, uint32_t* __restrict__ out_ids, uint64_t cap, bool whole) {
   __shared__ uint64_t s_mask[kTileRows];
   __shared__ uint32_t s_pre[kTileRows + 1];
-  const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  __shared__ uint32_t s_base[kTileRows];
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
   const uint64_t total_rows = total_all < row_end ? total_all : row_end;
   const uint64_t ntiles = total_rows > rbase ? (total_rows - rbase + kTileRows - 1) / kTileRows : 0;
-  const uint64_t below = lanemask_lt();
-  // whole: this launch covers every row, so tile_off[ntiles] is the batch's
-  // total; an output larger than cap then leaves out_ids untouched (the
-  // offsets are still written).
   const bool write_ids = !whole || ntiles == 0 || tile_off[ntiles] <= cap;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t trow0 = rbase + tile * kTileRows;
-    if (tid < kTileRows) s_mask[tid] = masks[tile * kTileRows + tid];
+    if (tid < kTileRows) {
+      s_mask[tid] = masks[tile * kTileRows + tid];
+      s_base[tid] = trow0 + tid < total_rows ? row_meta[trow0 + tid - rbase].x : 0u;
+    }
     __syncthreads();
     if (tid < 64) {   // exclusive scan of the row counts (one wave)
       const uint32_t v = (uint32_t)__popcll(s_mask[tid]);
@@ -1096,26 +1103,32 @@ __global__ __launch_bounds__(256) void compact_write(
     const uint64_t prefix = tile_off[tile];
     if (tid <= kTileRows && trow0 + tid <= total_rows)
       row_pre[tile * kTileRows + tid] = prefix + s_pre[tid];
-    const uint64_t wrow0 = trow0 + (uint64_t)w * kWaveRows;
-    for (int it = 0; it < ITERS; ++it) {
-      const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;
-      const int ri0 = (w * ITERS + it) * ROWS;
-      uint32_t pbase = 0;
-      if (lane < (uint32_t)ROWS && g0 + lane < total_rows) pbase = row_meta[g0 + lane - rbase].x;
-      uint32_t idv[ROWS];
-      uint64_t opos[ROWS];
-      bool act[ROWS];
+    const uint32_t hits = s_pre[kTileRows];
+    if (write_ids) {
+      for (uint32_t o = tid; o < hits; o += 256) {
+        uint32_t r = 0;   // last row with s_pre[r] <= o
 #pragma unroll
-      for (int jr = 0; jr < ROWS; ++jr) {
-        const uint64_t mask = s_mask[ri0 + jr];
-        const uint64_t p64 = (uint64_t)__builtin_amdgcn_readlane(pbase, jr) + lane;
-        act[jr] = ((mask >> lane) & 1ull) && p64 < npts;
-        opos[jr] = prefix + s_pre[ri0 + jr] + (uint64_t)__popcll(mask & below);
-        idv[jr] = act[jr] ? ids[p64] : 0u;
+        for (uint32_t step = 32; step >= 1; step >>= 1)
+          if (s_pre[r + step] <= o) r += step;
+        uint32_t k = o - s_pre[r];
+        uint64_t mk = s_mask[r];
+        uint32_t bit = 0;
+#pragma unroll
+        for (uint32_t w = 32; w >= 1; w >>= 1) {
+          const uint64_t low = mk & ((1ull << w) - 1);
+          const uint32_t c = (uint32_t)__popcll(low);
+          if (k >= c) {
+            k -= c;
+            bit += w;
+            mk >>= w;
+          } else {
+            mk = low;
+          }
+        }
+        const uint64_t p64 = (uint64_t)s_base[r] + bit;
+        const uint64_t opos = prefix + o;
+        if (p64 < npts && opos < cap) out_ids[opos] = ids[p64];
       }
-#pragma unroll
-      for (int jr = 0; jr < ROWS; ++jr)
-        if (write_ids && act[jr] && opos[jr] < cap) out_ids[opos[jr]] = idv[jr];
     }
     __syncthreads();
   }
@@ -1434,11 +1447,10 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
       return e;
     {
       ProfScope ps("compact_write", s);
-      // Eight rows per group, two groups per wave: measured fastest of the
-      // shapes 16x1, 8x2, 4x4, 2x8, 1x16 (0.77 ms vs 0.99 ms for 4x4 at
-      // 10^7 rows); more id loads in flight per wave.
-      compact_write<8, 2><<<grid, 256, 0, s>>>(ids, npts, meta, total_dev, rbase, row_end, masks,
-                                               toff[buf], rpre, out_ids, cap, chunks == 1);
+      // One lane per output (0.64 ms at 1.7e8 outputs from 6.3e8 candidates;
+      // the candidate-driven version with eight-row groups took 0.72 ms).
+      compact_write_out<<<grid, 256, 0, s>>>(ids, npts, meta, total_dev, rbase, row_end, masks,
+                                             toff[buf], rpre, out_ids, cap, chunks == 1);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {
