@@ -895,15 +895,15 @@ __global__ __launch_bounds__(256) void query_filters(const double* __restrict__ 
 }
 
 // 1: accepted, 0: rejected, -1: undecided by the cell.
-template <int DIM>
-__device__ __forceinline__ int cell_check(uint64_t cell, const QueryFilter& f, bool window) {
+template <int DIM, bool WINDOW>
+__device__ __forceinline__ int cell_check(uint64_t cell, const QueryFilter& f) {
   constexpr int B = DIM == 2 ? 32 : 21;
   const uint64_t mask = (1ull << B) - 1;
   float e[DIM];
 #pragma unroll
   for (int a = 0; a < DIM; ++a)
     e[a] = (float)(int32_t)((uint32_t)((cell >> (B * a)) & mask) - f.c[a]);
-  if (window) {
+  if (WINDOW) {
     bool in = true, out = false;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -943,7 +943,7 @@ __device__ __forceinline__ bool exact_hit(const double* __restrict__ q,
 // EPOCH: a candidate that passes the test also has to be visible at the
 // query's epoch (ins <= e < era); only those lanes read the epochs.
 // window: the square-window test instead of the Euclidean one.
-template <int ROWS, int ITERS, bool EPOCH, int DIM, bool CELLS>
+template <int ROWS, int ITERS, bool EPOCH, int DIM, bool CELLS, bool WINDOW>
 __global__ __launch_bounds__(256) void compact_test(
     const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const double* __restrict__ pts, const uint64_t* __restrict__ cells,
@@ -951,7 +951,7 @@ __global__ __launch_bounds__(256) void compact_test(
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     bool flag_overflow, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits,
     uint32_t* counters, const uint32_t* __restrict__ ins, const uint32_t* __restrict__ era,
-    const uint32_t* __restrict__ qepoch, uint32_t epoch, bool window) {
+    const uint32_t* __restrict__ qepoch, uint32_t epoch) {
   __shared__ uint32_t s_cnt[4];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
@@ -980,15 +980,21 @@ __global__ __launch_bounds__(256) void compact_test(
       bool hit[ROWS];
       if constexpr (CELLS) {
         // Decide from the cells; the coordinates only for undecided lanes.
+        // The rows' filter records (uniform loads) and cells are all
+        // requested before any is used.
+        QueryFilter qf[ROWS];
+#pragma unroll
+        for (int jr = 0; jr < ROWS; ++jr) qf[jr] = qfilt[qrow[jr]];
         uint64_t cv[ROWS];
 #pragma unroll
         for (int jr = 0; jr < ROWS; ++jr) cv[jr] = act[jr] ? cells[pos[jr]] : 0ull;
 #pragma unroll
         for (int jr = 0; jr < ROWS; ++jr) {
-          const QueryFilter f = qfilt[qrow[jr]];
-          const int vd = !act[jr] ? 0 : f.acc == f.acc ? cell_check<DIM>(cv[jr], f, window) : -1;
+          const QueryFilter& f = qf[jr];
+          const int vd =
+              !act[jr] ? 0 : f.acc == f.acc ? cell_check<DIM, WINDOW>(cv[jr], f) : -1;
           hit[jr] = vd == 1;
-          if (vd < 0) hit[jr] = exact_hit<DIM>(q, delta, pts, qrow[jr], pos[jr], window);
+          if (vd < 0) hit[jr] = exact_hit<DIM>(q, delta, pts, qrow[jr], pos[jr], WINDOW);
         }
       } else {
         double qx[ROWS], qy[ROWS], qz[ROWS], dd[ROWS];
@@ -1024,10 +1030,10 @@ __global__ __launch_bounds__(256) void compact_test(
         for (int jr = 0; jr < ROWS; ++jr) {
           if (DIM == 2)
             hit[jr] = act[jr] &&
-                      (window ? within_window(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr])
+                      (WINDOW ? within_window(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr])
                               : within(pv[jr].x, pv[jr].y, qx[jr], qy[jr], dd[jr]));
           else
-            hit[jr] = act[jr] && (window ? within_window3(pv[jr].x, pv[jr].y, pz[jr], qx[jr],
+            hit[jr] = act[jr] && (WINDOW ? within_window3(pv[jr].x, pv[jr].y, pz[jr], qx[jr],
                                                           qy[jr], qz[jr], dd[jr])
                                          : within3(pv[jr].x, pv[jr].y, pz[jr], qx[jr], qy[jr],
                                                    qz[jr], dd[jr]));
@@ -1409,13 +1415,16 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
     }
     if (!write_only) {
       ProfScope ps("compact_test", s);
-#define SFC_TEST_D(R, I, E, D, C)                                                          \
-  compact_test<R, I, E, D, C><<<grid, 256, 0, s>>>(                                        \
+#define SFC_TEST_W(R, I, E, D, C, W)                                                       \
+  compact_test<R, I, E, D, C, W><<<grid, 256, 0, s>>>(                                     \
       q, delta, m, pts, cells, (const QueryFilter*)qs.qfilt, npts, meta, total_dev, rbase,  \
       row_end, flag,                                                                       \
       masks, hits,                                                                         \
       qs.counters, ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                         \
-      ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u, window)
+      ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u)
+#define SFC_TEST_D(R, I, E, D, C)                                                          \
+  if (window) SFC_TEST_W(R, I, E, D, C, true);                                             \
+  else SFC_TEST_W(R, I, E, D, C, false)
 #define SFC_TEST(R, I, E)                                                                  \
   if (dim == 3) {                                                                          \
     if (cells) SFC_TEST_D(R, I, E, 3, true);                                               \
@@ -1440,6 +1449,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
 #undef SFC_TEST_SHAPES
 #undef SFC_TEST
 #undef SFC_TEST_D
+#undef SFC_TEST_W
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!write_only &&
