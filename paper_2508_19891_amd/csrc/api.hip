@@ -200,7 +200,8 @@ struct sfc_index {
   uint64_t n = 0;
   uint64_t* keys = nullptr;
   uint32_t* ids = nullptr;
-  double* xy = nullptr;
+  double* xy = nullptr;        // points in sorted order: gathered when first needed
+  double* xy_in = nullptr;     // points in input order (until the sorted copy exists)
   void* ws = nullptr;          // query scratch (grow-only)
   size_t ws_bytes = 0;
   void* cws = nullptr;         // compaction scratch (grow-only)
@@ -319,6 +320,8 @@ void release_arrays(sfc_index* h) {
   h->alloc.put(h->keys);
   h->alloc.put(h->ids);
   h->alloc.put(h->xy);
+  h->alloc.put(h->xy_in);
+  h->xy_in = nullptr;
   h->alloc.put(h->ws);
   h->alloc.put(h->cws);
   h->cws = nullptr;
@@ -388,8 +391,35 @@ bool stree_on(const sfc_index* h) { return h->search == SFC_SEARCH_STREE && h->s
 // the exact test).
 const uint64_t* test_cells(const sfc_index* h) { return h->cell_filter ? h->cells : nullptr; }
 
+
 // Coordinates per point and per query.
 int dim_of(const sfc_index* h) { return h->curve == SFC_CURVE_MORTON3 ? 3 : 2; }
+
+// The points in sorted order, gathered from the input-order copy the first
+// time something needs them (a view of them, updates, a test without cells);
+// the input-order copy is released then.
+sfc_status ensure_sorted_xy(sfc_index* h) {
+  if (h->xy || h->n == 0) return SFC_OK;
+  double* xy = (double*)h->alloc.get(h->n * 8 * dim_of(h));
+  if (!xy) return SFC_ERR_NOMEM;
+  hipError_t e = sfc::gather_sorted(h->ids, h->xy_in, xy, h->n, dim_of(h), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->alloc.put(xy);
+    return from_hip(e);
+  }
+  h->xy = xy;
+  h->alloc.put(h->xy_in);
+  h->xy_in = nullptr;
+  return SFC_OK;
+}
+
+// What the test pass of a query batch reads: without cells it tests every
+// candidate on the sorted points.
+sfc_status points_for_test(sfc_index* h) {
+  return test_cells(h) ? SFC_OK : ensure_sorted_xy(h);
+}
 
 // Query slots per query the scratch must hold (three dimensions refined:
 // four runs for each of eight cubes).
@@ -666,11 +696,11 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
   if (n > 0) {
     h->keys = (uint64_t*)h->alloc.get(n * 8);
     h->ids = (uint32_t*)h->alloc.get(n * 4);
-    h->xy = (double*)h->alloc.get(n * 8 * dim_of(h));
+    h->xy_in = (double*)h->alloc.get(n * 8 * dim_of(h));
     h->cells = (uint64_t*)h->alloc.get(n * 8);
     const size_t sb = sfc::build_scratch_bytes(n) + 256;
     void* scratch = h->alloc.get(sb);
-    if (!h->keys || !h->ids || !h->xy || !h->cells || !scratch) {
+    if (!h->keys || !h->ids || !h->xy_in || !h->cells || !scratch) {
       h->alloc.put(scratch);
       release_arrays(h);
       delete h;
@@ -679,8 +709,8 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
     uint32_t* err = (uint32_t*)((char*)scratch + sb - 256);
     hipError_t e = sfc::fill_u32(err, 0, 1, h->stream);
     if (e == hipSuccess)
-      e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, h->xy, scratch, err, h->stream,
-                          h->set_off, h->n_sets, h->cells);
+      e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, nullptr, scratch, err, h->stream,
+                          h->set_off, h->n_sets, h->cells, h->xy_in);
     uint64_t w = 0;
     if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
     h->alloc.put(scratch);
@@ -770,6 +800,10 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
   if (!h || !offsets || !total_out || (m > 0 && (!q || !delta)) || (ids_cap > 0 && !ids))
     return SFC_ERR_INVALID;
   if (m > (1ull << 36)) return SFC_ERR_INVALID;
+  {
+    sfc_status st = points_for_test(h);
+    if (st != SFC_OK) return st;
+  }
   sfc::QueryScratch qs{};
   uint64_t total_rows = 0, total_cand = 0;
   sfc::EpochView ev;
@@ -788,8 +822,8 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
     sfc_status st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(total_rows));
     if (st != SFC_OK) return st;
   }
-  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, test_cells(h), h->ids, h->n, qs, total_rows,
-                              false, h->cws, offsets, ids, ids_cap,
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->xy_in, test_cells(h), h->ids, h->n, qs,
+                              total_rows, false, h->cws, offsets, ids, ids_cap,
                               h->metric == SFC_METRIC_LINF, dim_of(h), h->stream,
                               filtered ? &ev : nullptr));
   uint64_t total = 0;
@@ -836,7 +870,8 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
   if (h->n_sets) return SFC_ERR_UNSUPPORTED;
   h->pending.valid = false;
   // Growing a scratch buffer waits for the work queued on it first.
-  sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m, slots_of(h)));
+  sfc_status st = points_for_test(h);
+  if (st == SFC_OK) st = ensure_ws(h, sfc::query_scratch_bytes(m, slots_of(h)));
   if (st == SFC_OK) st = grow(h, &h->cws, &h->cws_bytes, sfc::compact_scratch_bytes(max_rows));
   if (st != SFC_OK) return st;
   sfc::QueryScratch qs{};
@@ -857,8 +892,8 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
                                nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs.counters + 2, h->stream));
-  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, test_cells(h), h->ids, h->n, qs, max_rows,
-                              true, h->cws, offsets, ids, ids_cap,
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->xy_in, test_cells(h), h->ids, h->n, qs,
+                              max_rows, true, h->cws, offsets, ids, ids_cap,
                               h->metric == SFC_METRIC_LINF, dim_of(h), h->stream,
                               filtered ? &ev : nullptr));
   SFC_TRY(hipMemcpyAsync(flags, qs.counters + 2, 4, hipMemcpyDeviceToDevice, h->stream));
@@ -875,9 +910,9 @@ sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint6
     return SFC_ERR_CAPACITY;
   }
   h->pending.valid = false;
-  SFC_TRY(sfc::launch_compact(nullptr, nullptr, p.m, h->xy, nullptr, h->ids, h->n, p.qs, p.rows,
-                              false, h->cws, offsets, ids, ids_cap, false, dim_of(h), h->stream,
-                              nullptr, true));
+  SFC_TRY(sfc::launch_compact(nullptr, nullptr, p.m, h->xy, h->xy_in, nullptr, h->ids, h->n,
+                              p.qs, p.rows, false, h->cws, offsets, ids, ids_cap, false, dim_of(h),
+                              h->stream, nullptr, true));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + p.m, &total, 1, h->stream));
   if (total != p.total) return SFC_ERR_DEVICE;
@@ -918,6 +953,11 @@ uint64_t sfc_size(const sfc_index* h) { return h ? h->n : 0; }
 sfc_status sfc_index_view(const sfc_index* h, const uint64_t** keys, const uint32_t** ids,
                           const double** xy, uint64_t* n) {
   if (!h) return SFC_ERR_INVALID;
+  if (xy) {
+    // Filling the sorted copy on first use does not change what the index holds.
+    sfc_status st = ensure_sorted_xy(const_cast<sfc_index*>(h));
+    if (st != SFC_OK) return st;
+  }
   if (keys) *keys = h->keys;
   if (ids) *ids = h->ids;
   if (xy) *xy = h->xy;
@@ -930,8 +970,10 @@ sfc_status sfc_index_copy(const sfc_index* h, uint64_t* keys, uint32_t* ids, dou
   if (h->n == 0) return SFC_OK;
   if (keys) SFC_TRY(hipMemcpyAsync(keys, h->keys, h->n * 8, hipMemcpyDeviceToDevice, h->stream));
   if (ids) SFC_TRY(hipMemcpyAsync(ids, h->ids, h->n * 4, hipMemcpyDeviceToDevice, h->stream));
-  if (xy)
+  if (xy && h->xy)
     SFC_TRY(hipMemcpyAsync(xy, h->xy, h->n * 8 * dim_of(h), hipMemcpyDeviceToDevice, h->stream));
+  else if (xy)
+    SFC_TRY(sfc::gather_sorted(h->ids, h->xy_in, xy, h->n, dim_of(h), h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
   return SFC_OK;
 }
@@ -1141,7 +1183,7 @@ sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out) {
     hipError_t e = sfc::fill_u32(g->err, 0, 1, s);
     if (e == hipSuccess)
       e = sfc::sort_build(xy, h->n, h->curve, h->keys, h->ids, h->xy, g->scratch, g->err, s,
-                          h->set_off, h->n_sets, h->cells);
+                          h->set_off, h->n_sets, h->cells, h->xy_in);
     if (e == hipSuccess && h->occ) e = sfc::build_occupancy(h->keys, h->n, h->occ, s);
     if (e == hipSuccess && h->stree_ready)
       e = sfc::stree_build(sfc::stree_view(h->keys, h->n, h->stree), s);
@@ -1161,6 +1203,10 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
   if (!h || !out || !offsets || m == 0 || !q || !delta || (ids_cap > 0 && !ids)) return SFC_ERR_INVALID;
   if (qset && h->n_sets == 0) return SFC_ERR_INVALID;
   if (max_rows == 0 || max_rows > (1ull << 40)) return SFC_ERR_INVALID;
+  {
+    sfc_status st = points_for_test(h);
+    if (st != SFC_OK) return st;
+  }
   sfc_graph* g = new (std::nothrow) sfc_graph();
   if (!g) return SFC_ERR_NOMEM;
   g->h = h;
@@ -1194,8 +1240,8 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
                                  qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr, nullptr,
                                  nullptr, nullptr, nullptr, s);
     if (e == hipSuccess)
-      e = sfc::launch_compact(q, delta, m, h->xy, test_cells(h), h->ids, h->n, g->qs,
-                              max_rows, true, g->cscratch, offsets, ids, ids_cap,
+      e = sfc::launch_compact(q, delta, m, h->xy, h->xy_in, test_cells(h), h->ids, h->n,
+                              g->qs, max_rows, true, g->cscratch, offsets, ids, ids_cap,
                               h->metric == SFC_METRIC_LINF, dim_of(h), s,
                               filtered ? &ev : nullptr);
     return e;
@@ -1394,6 +1440,10 @@ namespace {
 // live) and the id -> key table, before the first update.
 sfc_status ensure_dynamic(sfc_index* h) {
   if (h->ins) return SFC_OK;
+  {
+    sfc_status st = ensure_sorted_xy(h);   // merges move the sorted points
+    if (st != SFC_OK) return st;
+  }
   const uint64_t c = h->cap ? h->cap : 1;
   const uint64_t kc = h->next_id > 1024 ? h->next_id : 1024;
   uint32_t* ins = (uint32_t*)h->alloc.get(c * 4);

@@ -71,7 +71,8 @@ template <int CURVE>
 __global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ xy, uint64_t n,
                                                    uint32_t tile_len, uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ err,
-                                                   uint32_t* __restrict__ counts, uint64_t tiles) {
+                                                   uint32_t* __restrict__ counts, uint64_t tiles,
+                                                   double2* __restrict__ xy_copy) {
   __shared__ uint32_t h[kSortWaves][kRadix];
   __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
   for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ 
   bool bad = false;
   for (uint64_t i = base + threadIdx.x; i < end; i += 256) {
     const double2 p = xy[i];
+    if (xy_copy) xy_copy[i] = p;
     uint64_t key = 0;
     if (in_unit(p.x) && in_unit(p.y)) {
       const uint32_t ux = quantize(p.x), uy = quantize(p.y);
@@ -103,7 +105,8 @@ __global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ 
 __global__ __launch_bounds__(256) void keygen3_tiles(const double* __restrict__ xyz, uint64_t n,
                                                     uint32_t tile_len, uint64_t* __restrict__ keys,
                                                     uint32_t* __restrict__ err,
-                                                    uint32_t* __restrict__ counts, uint64_t tiles) {
+                                                    uint32_t* __restrict__ counts, uint64_t tiles,
+                                                    double* __restrict__ xyz_copy) {
   __shared__ uint32_t h[kSortWaves][kRadix];
   for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
   __syncthreads();
@@ -113,6 +116,11 @@ __global__ __launch_bounds__(256) void keygen3_tiles(const double* __restrict__ 
   bool bad = false;
   for (uint64_t i = base + threadIdx.x; i < end; i += 256) {
     const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    if (xyz_copy) {
+      xyz_copy[3 * i] = x;
+      xyz_copy[3 * i + 1] = y;
+      xyz_copy[3 * i + 2] = z;
+    }
     uint64_t key = 0;
     if (in_unit(x) && in_unit(y) && in_unit(z)) {
       key = morton3_key(quantize3(x), quantize3(y), quantize3(z));
@@ -204,7 +212,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
     const uint32_t* __restrict__ rel, const uint32_t* __restrict__ dtot, uint64_t tiles,
     uint32_t* err, const double2* __restrict__ xy_in, double2* __restrict__ xy_out,
-    uint64_t* __restrict__ cells_out, const uint32_t* __restrict__ set_id) {
+    uint64_t* __restrict__ cells_out, int cell_curve, const uint32_t* __restrict__ set_id) {
   constexpr int kTile = kSortThreads * ITEMS;
   __shared__ union {
     uint32_t wave_hist[kSortWaves][kRadix];
@@ -310,6 +318,8 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
       const double2 p = xy_in[v];
       xy_out[pos] = p;
       if (cells_out) cells_out[pos] = pack_cell2(p.x, p.y);
+    } else if (cells_out) {
+      cells_out[pos] = cell_of_key(cell_curve, k);   // the key holds the cell
     }
   }
 }
@@ -389,14 +399,14 @@ hipError_t launch_scatter(bool first, bool gather, bool setpass, int shift, uint
                           const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                           uint32_t* vout, uint64_t n, const uint32_t* rel, const uint32_t* dtot,
                           uint32_t* err, const double* xy, double* xy_out, uint64_t* cells_out,
-                          const uint32_t* set_id, hipStream_t s) {
+                          int cell_curve, const uint32_t* set_id, hipStream_t s) {
   const dim3 g((uint32_t)(((tiles + 7) / 8) * 8)), b(kSortThreads);
   const double2* xi = (const double2*)xy;
   double2* xo = (double2*)xy_out;
 #define SFC_PASS(F, G, S)                                                                      \
   scatter_pass<ITEMS, F, G, S><<<g, b, 0, s>>>(kin, vin, kout, vout, n, shift, rel, dtot,     \
                                                tiles, err, G ? xi : nullptr, G ? xo : nullptr, \
-                                               G ? cells_out : nullptr, set_id)
+                                               cells_out, cell_curve, set_id)
   if (setpass) {
     if (gather) SFC_PASS(false, true, true);
     else SFC_PASS(false, false, true);
@@ -432,19 +442,19 @@ size_t build_scratch_bytes(uint64_t n) {
 }
 
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
-                       uint32_t* counts, hipStream_t s) {
+                       uint32_t* counts, hipStream_t s, double* xy_copy) {
   if (n == 0) return hipSuccess;
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
   ProfScope ps("keygen_tiles", s);
   if (curve == SFC_CURVE_MORTON3)
-    keygen3_tiles<<<(uint32_t)tiles, 256, 0, s>>>(xy, n, tile, keys, err, counts, tiles);
+    keygen3_tiles<<<(uint32_t)tiles, 256, 0, s>>>(xy, n, tile, keys, err, counts, tiles, xy_copy);
   else if (curve == SFC_CURVE_HILBERT)
-    keygen_tiles<SFC_CURVE_HILBERT><<<(uint32_t)tiles, 256, 0, s>>>((const double2*)xy, n, tile,
-                                                                    keys, err, counts, tiles);
+    keygen_tiles<SFC_CURVE_HILBERT><<<(uint32_t)tiles, 256, 0, s>>>(
+        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy);
   else
-    keygen_tiles<SFC_CURVE_MORTON><<<(uint32_t)tiles, 256, 0, s>>>((const double2*)xy, n, tile,
-                                                                   keys, err, counts, tiles);
+    keygen_tiles<SFC_CURVE_MORTON><<<(uint32_t)tiles, 256, 0, s>>>(
+        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy);
   return hipGetLastError();
 }
 
@@ -458,7 +468,7 @@ hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, 
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err_host_visible,
                       hipStream_t s, const uint64_t* set_off, uint32_t n_sets,
-                      uint64_t* cells_out) {
+                      uint64_t* cells_out, double* xy_copy) {
   if (n == 0) return hipSuccess;
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
@@ -478,7 +488,7 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   auto out_is_final = [&](int pass) { return ((passes - 1 - pass) & 1) == 0; };
   uint64_t* keys_first = out_is_final(0) ? keys_b : keys_out;
 
-  hipError_t e = launch_keys(xy, n, curve, keys_first, err_host_visible, counts, s);
+  hipError_t e = launch_keys(xy, n, curve, keys_first, err_host_visible, counts, s, xy_copy);
   if (e != hipSuccess) return e;
   if (sp > 0) {
     ProfScope ps("set_prep", s);
@@ -493,8 +503,12 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     uint32_t* vout = fin ? ids_out : ids_b;
     const bool setpass = pass >= kDigits;
     const int shift = setpass ? 8 * (pass - kDigits) : 8 * pass;
-    // The points travel with the last pass (in 3-D they are gathered after it).
-    const bool gather = pass == passes - 1 && curve != SFC_CURVE_MORTON3;
+    // With xy_out the points travel with the last pass (in 3-D they are
+    // gathered after it); else the last pass writes each element's cell,
+    // decoded from its key.
+    const bool last = pass == passes - 1;
+    const bool gather = last && xy_out && curve != SFC_CURVE_MORTON3;
+    uint64_t* pass_cells = last && !(xy_out && curve == SFC_CURVE_MORTON3) ? cells_out : nullptr;
     if (pass > 0) {
       ProfScope ps("tile_hist", s);
       if (setpass)
@@ -513,7 +527,7 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     ProfScope ps(setpass ? "set_pass" : "scatter_pass", s);
 #define SFC_LAUNCH(I)                                                                        \
   launch_scatter<I>(pass == 0, gather, setpass, shift, tiles, kin, vin, kout, vout, n, rel, dtot, \
-                    err_host_visible, xy, xy_out, cells_out, set_id, s)
+                    err_host_visible, xy, xy_out, pass_cells, curve, set_id, s)
     switch (sort_items(n)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;
@@ -524,7 +538,7 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     kin = kout;
     vin = vout;
   }
-  if (curve == SFC_CURVE_MORTON3) {
+  if (curve == SFC_CURVE_MORTON3 && xy_out) {
     ProfScope ps("gather_points3", s);
     gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids_out, xy, xy_out, cells_out,
                                                                 n);
@@ -543,12 +557,15 @@ hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipS
   return hipGetLastError();
 }
 
-hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,
+hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n, int dim,
                          hipStream_t s) {
   if (n == 0) return hipSuccess;
   ProfScope ps("gather_points", s);
-  gather_points<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids, (const double2*)xy,
-                                                             (double2*)out, n);
+  if (dim == 3)
+    gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids, xy, out, nullptr, n);
+  else
+    gather_points<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids, (const double2*)xy,
+                                                               (double2*)out, n);
   return hipGetLastError();
 }
 

@@ -59,6 +59,72 @@ __host__ __device__ __forceinline__ uint64_t morton3_key(uint32_t x, uint32_t y,
   return spread_bits3(x) | (spread_bits3(y) << 1) | (spread_bits3(z) << 2);
 }
 
+// Inverse of spread_bits: the even bits of x, packed.
+__host__ __device__ __forceinline__ uint32_t compact_bits(uint64_t x) {
+  x &= 0x5555555555555555ull;
+  x = (x | (x >> 1)) & 0x3333333333333333ull;
+  x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+  return (uint32_t)x;
+}
+
+// Inverse of spread_bits3: every third bit of x, packed (21 bits).
+__host__ __device__ __forceinline__ uint32_t compact_bits3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x | (x >> 2)) & 0x10C30C30C30C30C3ull;
+  x = (x | (x >> 4)) & 0x100F00F00F00F00Full;
+  x = (x | (x >> 8)) & 0x001F0000FF0000FFull;
+  x = (x | (x >> 16)) & 0x001F00000000FFFFull;
+  x = (x | (x >> 32)) & 0x00000000001FFFFFull;
+  return (uint32_t)x;
+}
+
+// The grid cell (x, y) whose Hilbert label is key: the levels from the
+// bottom up, each undoing the frame the cell's quadrant imposed (the inverse
+// of the quadrant-rotation construction, whose orientation hilbert_key_lut
+// follows).
+__host__ __device__ __forceinline__ void hilbert_decode(uint64_t key, uint32_t& x, uint32_t& y) {
+  uint32_t cx = 0, cy = 0;
+  uint64_t t = key;
+  for (int b = 0; b < 32; ++b) {
+    const uint32_t s = 1u << b;
+    const uint32_t rx = (uint32_t)(t >> 1) & 1u;
+    const uint32_t ry = (uint32_t)(t ^ rx) & 1u;
+    if (ry == 0) {
+      if (rx == 1) {
+        cx = s - 1 - cx;
+        cy = s - 1 - cy;
+      }
+      const uint32_t tmp = cx;
+      cx = cy;
+      cy = tmp;
+    }
+    cx += s * rx;
+    cy += s * ry;
+    t >>= 2;
+  }
+  x = cx;
+  y = cy;
+}
+
+// Packed grid cell (as pack_cell2 / pack_cell3) of the point whose key is
+// `key` on `curve`: the key holds the cell exactly.
+__host__ __device__ __forceinline__ uint64_t cell_of_key(int curve, uint64_t key) {
+  if (curve == 2)   // SFC_CURVE_MORTON3
+    return (uint64_t)compact_bits3(key) | ((uint64_t)compact_bits3(key >> 1) << 21) |
+           ((uint64_t)compact_bits3(key >> 2) << 42);
+  uint32_t x, y;
+  if (curve == 1) {   // SFC_CURVE_HILBERT
+    hilbert_decode(key, x, y);
+  } else {
+    x = compact_bits(key);
+    y = compact_bits(key >> 1);
+  }
+  return (uint64_t)x | ((uint64_t)y << 32);
+}
+
 // Grid cells of a point packed in one word: x | y << 32 in the plane,
 // x | y << 21 | z << 42 in three dimensions (coordinates in [0,1)).
 __host__ __device__ __forceinline__ uint64_t pack_cell2(double x, double y) {

@@ -39,14 +39,17 @@ size_t build_scratch_bytes(uint64_t n);
 // Keys of n points (err: device word, kErrDomain is or-ed in); counts, if
 // not null, receives the first digit's counts per sort tile.
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
-                       uint32_t* counts, hipStream_t s);
-// cells_out (may be null): the grid cells of the sorted points (pack_cell2 /
-// pack_cell3), written with the points.
+                       uint32_t* counts, hipStream_t s, double* xy_copy = nullptr);
+// xy_out (may be null): the points in sorted order.  cells_out (may be
+// null): the grid cells of the sorted points (pack_cell2 / pack_cell3),
+// decoded from the keys (or taken from the points when they are gathered).
+// xy_copy (may be null): a copy of the input points in input order.
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
                       hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0,
-                      uint64_t* cells_out = nullptr);
-hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n,
+                      uint64_t* cells_out = nullptr, double* xy_copy = nullptr);
+// out[i] = xy[ids[i]] for points of dim (2 or 3) doubles.
+hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n, int dim,
                          hipStream_t s);
 // Early-termination occupancy bitmap (kOccWords words) of n sorted keys.
 hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipStream_t s);
@@ -113,11 +116,13 @@ hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, cons
 // (half side delta) instead of the Euclidean ball.  dim: 2, or 3 for points
 // and queries of three doubles.  cells (may be null): the grid cells of the
 // sorted points (pack_cell2 / pack_cell3); with them most candidates are
-// decided from their cell and only the undecided ones read their coordinates.
+// decided from their cell and only the undecided ones read their coordinates,
+// from pts (the sorted points) when not null, else from pts_in (input order)
+// through their ids.  Without cells pts must not be null.
 struct EpochView;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
-                          const uint64_t* cells, const uint32_t* ids, uint64_t npts,
-                          const QueryScratch& qs,
+                          const double* pts_in, const uint64_t* cells, const uint32_t* ids,
+                          uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
                           int dim, hipStream_t s,

@@ -860,8 +860,8 @@ __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ 
 // domain: then |e| < 2^31, exact in 32-bit arithmetic.  Cells sit in one
 // word: x | y << 32, or x | y << 21 | z << 42.
 struct QueryFilter {
-  uint32_t c[3];   // the query's cell per axis (low 32 bits)
   float acc, rej;  // limits on sum e^2 (or per-axis |e|); acc = not a number: filter off
+  uint32_t c[3];   // the query's cell per axis (low 32 bits)
   uint32_t pad[3];
 };
 
@@ -919,20 +919,23 @@ __device__ __forceinline__ int cell_check(uint64_t cell, const QueryFilter& f) {
 }
 
 // The exact test of candidate pos against query qs (the point and the query
-// read here: only for candidates their cell could not decide).
+// read here: only for candidates their cell could not decide).  The point
+// is src[pos] (sorted points), or src[via[pos]] (input order, via = ids).
 template <int DIM>
 __device__ __forceinline__ bool exact_hit(const double* __restrict__ q,
                                           const double* __restrict__ delta,
-                                          const double* __restrict__ pts, uint32_t qs,
+                                          const double* __restrict__ src,
+                                          const uint32_t* __restrict__ via, uint32_t qs,
                                           uint32_t pos, bool window) {
   const double d = delta[qs];
+  const uint64_t at = via ? via[pos] : pos;
   if (DIM == 2) {
     const double2 qq = ((const double2*)q)[qs];
-    const double2 p = ((const double2*)pts)[pos];
+    const double2 p = ((const double2*)src)[at];
     return window ? within_window(p.x, p.y, qq.x, qq.y, d) : within(p.x, p.y, qq.x, qq.y, d);
   }
   const double* qp = q + 3 * (uint64_t)qs;
-  const double* pp = pts + 3 * (uint64_t)pos;
+  const double* pp = src + 3 * at;
   return window ? within_window3(pp[0], pp[1], pp[2], qp[0], qp[1], qp[2], d)
                 : within3(pp[0], pp[1], pp[2], qp[0], qp[1], qp[2], d);
 }
@@ -946,7 +949,8 @@ __device__ __forceinline__ bool exact_hit(const double* __restrict__ q,
 template <int ROWS, int ITERS, bool EPOCH, int DIM, bool CELLS, bool WINDOW>
 __global__ __launch_bounds__(256) void compact_test(
     const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
-    const double* __restrict__ pts, const uint64_t* __restrict__ cells,
+    const double* __restrict__ pts, const uint32_t* __restrict__ via,
+    const uint64_t* __restrict__ cells,
     const QueryFilter* __restrict__ qfilt, uint64_t npts, const uint4* __restrict__ row_meta,
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
     bool flag_overflow, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits,
@@ -982,9 +986,17 @@ __global__ __launch_bounds__(256) void compact_test(
         // Decide from the cells; the coordinates only for undecided lanes.
         // The rows' filter records (uniform loads) and cells are all
         // requested before any is used.
+        // (the plane needs the record's first 16 bytes: limits and x, y)
         QueryFilter qf[ROWS];
 #pragma unroll
-        for (int jr = 0; jr < ROWS; ++jr) qf[jr] = qfilt[qrow[jr]];
+        for (int jr = 0; jr < ROWS; ++jr) {
+          const uint4 a = ((const uint4*)qfilt)[2 * (uint64_t)qrow[jr]];
+          qf[jr].acc = __uint_as_float(a.x);
+          qf[jr].rej = __uint_as_float(a.y);
+          qf[jr].c[0] = a.z;
+          qf[jr].c[1] = a.w;
+          qf[jr].c[2] = DIM == 3 ? qfilt[qrow[jr]].c[2] : 0u;
+        }
         uint64_t cv[ROWS];
 #pragma unroll
         for (int jr = 0; jr < ROWS; ++jr) cv[jr] = act[jr] ? cells[pos[jr]] : 0ull;
@@ -994,7 +1006,8 @@ __global__ __launch_bounds__(256) void compact_test(
           const int vd =
               !act[jr] ? 0 : f.acc == f.acc ? cell_check<DIM, WINDOW>(cv[jr], f) : -1;
           hit[jr] = vd == 1;
-          if (vd < 0) hit[jr] = exact_hit<DIM>(q, delta, pts, qrow[jr], pos[jr], WINDOW);
+          if (vd < 0)
+            hit[jr] = exact_hit<DIM>(q, delta, pts, via, qrow[jr], pos[jr], WINDOW);
         }
       } else {
         double qx[ROWS], qy[ROWS], qz[ROWS], dd[ROWS];
@@ -1355,8 +1368,8 @@ hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, cons
 }
 
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
-                          const uint64_t* cells, const uint32_t* ids, uint64_t npts,
-                          const QueryScratch& qs,
+                          const double* pts_in, const uint64_t* cells, const uint32_t* ids,
+                          uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
                           int dim, hipStream_t s, const EpochView* ev, bool write_only) {
@@ -1417,10 +1430,10 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
       ProfScope ps("compact_test", s);
 #define SFC_TEST_W(R, I, E, D, C, W)                                                       \
   compact_test<R, I, E, D, C, W><<<grid, 256, 0, s>>>(                                     \
-      q, delta, m, pts, cells, (const QueryFilter*)qs.qfilt, npts, meta, total_dev, rbase,  \
-      row_end, flag,                                                                       \
-      masks, hits,                                                                         \
-      qs.counters, ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                         \
+      q, delta, m, pts ? pts : pts_in, pts ? nullptr : ids, cells,                         \
+      (const QueryFilter*)qs.qfilt, npts, meta,                                            \
+      total_dev, rbase, row_end, flag, masks, hits, qs.counters,                           \
+      ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                                      \
       ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u)
 #define SFC_TEST_D(R, I, E, D, C)                                                          \
   if (window) SFC_TEST_W(R, I, E, D, C, true);                                             \
