@@ -436,6 +436,12 @@ sfc_status sfc_set_metric(sfc_index* h, int metric);
    queries then test every candidate exactly).  SFC_ERR_INVALID for another
    value.  No device work. */
 sfc_status sfc_set_cell_filter(sfc_index* h, int on);
+/* Copies the grid cells of the sorted points (device, count >= sfc_size
+   words): x | y << 32 per point, or x | y << 21 | z << 42 in three
+   dimensions (x, y, z the cell coordinates, floor(v * 2^32) or
+   floor(v * 2^21)).  SFC_ERR_UNSUPPORTED once the index dropped them (after
+   its first update).  Synchronises the stream. */
+sfc_status sfc_cells_copy(const sfc_index* h, uint64_t* out, uint64_t count);
 /* (Re)fits the learned index with the given training steps (< 0: the
    handle's default).  SFC_ERR_UNSUPPORTED for n < 2. */
 sfc_status sfc_learned_fit(sfc_index* h, int steps);

@@ -978,6 +978,15 @@ sfc_status sfc_index_copy(const sfc_index* h, uint64_t* keys, uint32_t* ids, dou
   return SFC_OK;
 }
 
+sfc_status sfc_cells_copy(const sfc_index* h, uint64_t* out, uint64_t count) {
+  if (!h || (count > 0 && !out) || count < h->n) return SFC_ERR_INVALID;
+  if (!h->cells) return SFC_ERR_UNSUPPORTED;
+  if (h->n == 0) return SFC_OK;
+  SFC_TRY(hipMemcpyAsync(out, h->cells, h->n * 8, hipMemcpyDeviceToDevice, h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  return SFC_OK;
+}
+
 sfc_status sfc_occupancy_copy(const sfc_index* h, uint32_t* out, uint64_t words) {
   if (!h || (words > 0 && !out)) return SFC_ERR_INVALID;
   if (!h->occ) return SFC_ERR_UNSUPPORTED;

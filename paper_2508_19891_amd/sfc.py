@@ -44,6 +44,7 @@ EXPORTS = [
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
     "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric", "sfc_set_cell_filter",
+    "sfc_cells_copy",
 ]
 
 NPARAM = 1153
@@ -152,6 +153,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_set_metric.restype = i32
     L.sfc_set_cell_filter.argtypes = [vp, i32]
     L.sfc_set_cell_filter.restype = i32
+    L.sfc_cells_copy.argtypes = [vp, vp, u64]
+    L.sfc_cells_copy.restype = i32
     L.sfc_learned_fit.argtypes = [vp, i32]
     L.sfc_learned_fit.restype = i32
     L.sfc_learned_info_get.argtypes = [vp, ctypes.POINTER(LearnedInfo)]
@@ -499,6 +502,12 @@ class Index:
         """Decide candidates from their grid cell where the cell settles the
         test (default), or run the exact test on every candidate."""
         _check(lib().sfc_set_cell_filter(self.handle, 1 if on else 0), "sfc_set_cell_filter")
+
+    def cells(self) -> torch.Tensor:
+        """Grid cells of the sorted points (int64 bits of the packed words)."""
+        out = torch.empty(max(self.size(), 1), dtype=torch.int64, device=self.device)
+        _check(lib().sfc_cells_copy(self.handle, _ptr(out), out.numel()), "sfc_cells_copy")
+        return out[:self.size()]
 
     def set_metric(self, metric: int):
         _check(lib().sfc_set_metric(self.handle, metric), "sfc_set_metric")

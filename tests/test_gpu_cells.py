@@ -149,3 +149,36 @@ def test_cells_follow_updates_and_recorded_builds():
     ref = oracle.query(oracle.build(other, MORTON), qs, ds, MORTON)
     assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
     g.close()
+
+
+@pytest.mark.parametrize("curve", [MORTON, HILBERT, sfc.MORTON3])
+def test_cells_decoded_from_keys(curve):
+    """The grid cells the build decodes from the sorted keys (Morton
+    de-interleave, Hilbert inverse, 3-D de-interleave) equal the quantized
+    coordinates of the points the oracle's construction puts at each
+    position, and are dropped (refused) once the index is updated."""
+    rng = np.random.default_rng(7 + curve)
+    n = 300_001
+    if curve == sfc.MORTON3:
+        pts = rng.random((n, 3))
+        pts[:64] = 1 - 2.0 ** -53   # top quantum of every axis
+        pts[64:128] = 0.0
+        _, ids, s = oracle.build3(pts)
+        q = np.floor(s * 2.0 ** 21).astype(np.uint64)   # exact: scaling by 2^21
+        want = q[:, 0] | (q[:, 1] << np.uint64(21)) | (q[:, 2] << np.uint64(42))
+    else:
+        pts = rng.random((n, 2))
+        pts[:64] = 1 - 2.0 ** -53
+        pts[64:128] = 0.0
+        _, ids, s = oracle.build(pts, curve)
+        ux, uy = oracle.quantize(s)
+        want = ux.astype(np.uint64) | (uy.astype(np.uint64) << np.uint64(32))
+    idx = sfc.Index(dev(pts), curve=curve)
+    got = idx.cells().cpu().numpy().view(np.uint64)
+    _, gids, _ = idx.sorted_arrays()
+    assert np.array_equal(gids.cpu().numpy().view(np.uint32), ids)
+    assert np.array_equal(got, want)
+    if curve != sfc.MORTON3:
+        idx.insert(dev(rng.random((10, 2))))
+        with pytest.raises(sfc.SfcError):
+            idx.cells()
