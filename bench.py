@@ -633,7 +633,7 @@ def main():
     tiles = math.ceil(cand / 4096)
     slots = 8 * m   # refined layout: eight slots (begin u32, count u32, offset u64) per query
     algo = {
-        "keygen_tiles": 16 * n + 8 * n,                     # points in, keys out
+        "keygen_tiles": 16 * n + 8 * n + 16 * n,            # points in, keys and input-order copy out
         "tile_hist": 7 * 8 * n,                             # passes 2..8 read the keys
         "scatter_pass": 8 * 24 * n,                         # 8 passes x (key+id) in and out
         "ranges_search": 24 * m + 8 * slots,                # queries in; begin+count per slot
@@ -643,8 +643,8 @@ def main():
         "query_filters": 24 * m + 32 * m,
         "compact_write": cand // 8 + 8 * tiles + 4 * rep + 4 * rep + 8 * (m + 1) + 12 * slots,
     }
-    # The last radix pass also gathers the points (random 16 B reads, 16 B writes).
-    algo["scatter_pass"] += 32 * n
+    # The last radix pass also writes each point's 8-byte grid cell.
+    algo["scatter_pass"] += 8 * n
     kern_gbs = {}
     for k, b in algo.items():
         if k in kern:
