@@ -630,12 +630,13 @@ def main():
 
     # Algorithmic bytes per step of each kernel (what the method must move).
     cand, rep = stats["candidates"], total
+    passes = round(kern["scatter_pass"][0] / args.steps)   # radix passes per build
     tiles = math.ceil(cand / 4096)
     slots = 8 * m   # refined layout: eight slots (begin u32, count u32, offset u64) per query
     algo = {
         "keygen_tiles": 16 * n + 8 * n + 16 * n,            # points in, keys and input-order copy out
-        "tile_hist": 7 * 8 * n,                             # passes 2..8 read the keys
-        "scatter_pass": 8 * 24 * n,                         # 8 passes x (key+id) in and out
+        "tile_hist": (passes - 1) * 8 * n,                  # passes 2.. read the keys
+        "scatter_pass": passes * 24 * n,                    # (key+id) in and out per pass
         "ranges_search": 24 * m + 8 * slots,                # queries in; begin+count per slot
         # default: each candidate's 8-byte grid cell, the 32-byte filter record
         # of its query per row (the rare undecided candidates read 16 B more)
@@ -643,8 +644,12 @@ def main():
         "query_filters": 24 * m + 32 * m,
         "compact_write": cand // 8 + 8 * tiles + 4 * rep + 4 * rep + 8 * (m + 1) + 12 * slots,
     }
-    # The last radix pass also writes each point's 8-byte grid cell.
-    algo["scatter_pass"] += 8 * n
+    if "chunk_sort" in kern:
+        # Chunks of equal top key bits: (key+id) in and out, the grid cell out.
+        algo["chunk_sort"] = 12 * n + 12 * n + 8 * n
+    else:
+        # The last radix pass also writes each point's 8-byte grid cell.
+        algo["scatter_pass"] += 8 * n
     kern_gbs = {}
     for k, b in algo.items():
         if k in kern:
@@ -654,7 +659,8 @@ def main():
     launches_per_step = d_launch / args.steps
     bytes_per_launch = algo[dom] / launches_per_step
     achieved = bytes_per_launch / (d_ms / d_launch * 1e-3) / 1e9
-    traffic = load_traffic(dom, "build.hip" if dom in ("keygen_tiles", "tile_hist", "digit_scan", "scatter_pass")
+    traffic = load_traffic(dom, "build.hip" if dom in ("keygen_tiles", "tile_hist", "digit_scan", "scatter_pass",
+                                                       "chunk_sort")
                            else "query.hip")
 
     line = {
@@ -682,7 +688,8 @@ def main():
         "reported_per_step": rep,
         "candidates_per_step": cand,
         "candidates_per_report": cand / max(rep, 1),
-        "build_ms_per_step": sum(kern[k][1] for k in ("keygen_tiles", "tile_hist", "digit_scan", "scatter_pass")
+        "build_ms_per_step": sum(kern[k][1] for k in ("keygen_tiles", "tile_hist", "digit_scan", "scatter_pass",
+                                                      "chunk_sort")
                                  if k in kern) / args.steps,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items()},
         "roofline": {

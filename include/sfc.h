@@ -455,6 +455,13 @@ sfc_status sfc_learned_params(const sfc_index* h, float* params);
    process (0 or more than 2^19 restores 2^19), so that the multi-chunk path
    can be checked on small inputs.  Results do not depend on it. */
 sfc_status sfc_debug_chunk_tiles(uint64_t tiles);
+/* Test hook of the construction's sort (process-wide).  force_plain 1: every
+   build uses the plain eight-pass radix sort; 0: builds without point sets
+   first order the keys by their top 32 bits and sort chunks of equal top
+   bits in LDS, falling back to the plain sort when a run of equal top bits
+   is too long (results are the same either way); negative: unchanged.
+   *last_fallback (may be null) receives 1 if the last build fell back. */
+sfc_status sfc_debug_sort_path(int force_plain, int* last_fallback);
 /* Leaf of each key (device keys[count]) by evaluating the router network
    (direct) and through the tabulation the queries use (table); both device
    uint32[count].  For checking that the two agree.  SFC_ERR_UNSUPPORTED

@@ -18,6 +18,11 @@
 #include "learned.h"
 #include "sfc.h"
 
+// Test switches of the construction's sort (process-wide): always the plain
+// radix sort, and whether the last build fell back to it.
+static std::atomic<bool> g_force_plain_sort{false};
+static std::atomic<int> g_last_sort_fallback{0};
+
 // ---- caching device allocator -----------------------------------------------
 
 namespace sfc {
@@ -708,11 +713,27 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
     }
     uint32_t* err = (uint32_t*)((char*)scratch + sb - 256);
     hipError_t e = sfc::fill_u32(err, 0, 1, h->stream);
+    // Without point sets the chunked sort runs first; a run of equal top key
+    // bits too long for it is reported in the error word (read here anyway),
+    // and the plain sort then builds the arrays again.
+    const bool chunked = !h->set_off && !g_force_plain_sort;
     if (e == hipSuccess)
-      e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, nullptr, scratch, err, h->stream,
-                          h->set_off, h->n_sets, h->cells, h->xy_in);
+      e = chunked ? sfc::sort_build_chunked(xy, n, h->curve, h->keys, h->ids, scratch, err,
+                                            h->stream, h->cells, h->xy_in)
+                  : sfc::sort_build(xy, n, h->curve, h->keys, h->ids, nullptr, scratch, err,
+                                    h->stream, h->set_off, h->n_sets, h->cells, h->xy_in);
     uint64_t w = 0;
     if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
+    g_last_sort_fallback = 0;
+    if (e == hipSuccess && chunked && ((uint32_t)w & sfc::kErrOversized) &&
+        !((uint32_t)w & sfc::kErrDomain)) {
+      g_last_sort_fallback = 1;
+      e = sfc::fill_u32(err, 0, 1, h->stream);
+      if (e == hipSuccess)
+        e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, nullptr, scratch, err, h->stream,
+                            nullptr, 0, h->cells, h->xy_in);
+      if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
+    }
     h->alloc.put(scratch);
     sfc_status st = SFC_OK;
     if (e != hipSuccess) {
@@ -1035,6 +1056,12 @@ sfc_status sfc_set_metric(sfc_index* h, int metric) {
 sfc_status sfc_learned_fit(sfc_index* h, int steps) {
   if (!h) return SFC_ERR_INVALID;
   return fit_learned(h, steps);
+}
+
+sfc_status sfc_debug_sort_path(int force_plain, int* last_fallback) {
+  if (force_plain >= 0) g_force_plain_sort = force_plain != 0;
+  if (last_fallback) *last_fallback = g_last_sort_fallback;
+  return SFC_OK;
 }
 
 sfc_status sfc_debug_chunk_tiles(uint64_t tiles) {

@@ -66,13 +66,14 @@ __device__ __forceinline__ void store_tile_counts(uint32_t (*h)[kRadix], uint32_
 }
 
 // One workgroup per sort tile of tile_len input points: quantise, key, write
-// keys; with counts != null also the tile's counts of the first digit.
+// keys; with counts != null also the tile's counts of the first digit (the
+// byte at count_shift).
 template <int CURVE>
 __global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ xy, uint64_t n,
                                                    uint32_t tile_len, uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ err,
                                                    uint32_t* __restrict__ counts, uint64_t tiles,
-                                                   double2* __restrict__ xy_copy) {
+                                                   double2* __restrict__ xy_copy, int count_shift) {
   __shared__ uint32_t h[kSortWaves][kRadix];
   __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
   for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ 
       bad = true;
     }
     keys[i] = key;
-    if (counts) atomicAdd(&h[w][key & 255u], 1u);
+    if (counts) atomicAdd(&h[w][(key >> count_shift) & 255u], 1u);
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(err, kErrDomain);
   if (counts) store_tile_counts(h, counts, tiles, blockIdx.x);
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) void keygen3_tiles(const double* __restrict__ 
                                                     uint32_t tile_len, uint64_t* __restrict__ keys,
                                                     uint32_t* __restrict__ err,
                                                     uint32_t* __restrict__ counts, uint64_t tiles,
-                                                    double* __restrict__ xyz_copy) {
+                                                    double* __restrict__ xyz_copy, int count_shift) {
   __shared__ uint32_t h[kSortWaves][kRadix];
   for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
   __syncthreads();
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(256) void keygen3_tiles(const double* __restrict__ 
       bad = true;
     }
     keys[i] = key;
-    if (counts) atomicAdd(&h[w][key & 255u], 1u);
+    if (counts) atomicAdd(&h[w][(key >> count_shift) & 255u], 1u);
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(err, kErrDomain);
   if (counts) store_tile_counts(h, counts, tiles, blockIdx.x);
@@ -255,7 +256,11 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
 
   // Rank within the wave, in (item, lane) order: lanes holding the same digit
   // are found with eight ballots; the lowest of them bumps the wave's counter.
-  volatile uint32_t* wh = sm.wave_hist[w];
+  // (The counters are indexed in the shared array itself, so that the
+  // accesses stay LDS instructions; a wave's LDS accesses complete in order,
+  // and the compiler keeps each slot's read after the previous slot's write,
+  // which may alias it.)
+  uint32_t* wh = sm.wave_hist[w];
   const uint64_t below_mask = lanemask_lt();
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
@@ -394,6 +399,282 @@ __global__ void fill_set_ids(const uint64_t* __restrict__ set_off, uint32_t n_se
   set_id[i] = lo - 1;
 }
 
+
+// ---- chunked construction: four passes over the top 32 bits, then LDS ----
+//
+// After four stable passes over the key bytes at bits 32..63 the keys are
+// ordered by their top 32 bits, and each run of equal top bits (a quadtree
+// cell of side 2^-16, or an octree cell of side about 2^-10.3; one or two
+// keys on average at the sizes here) only needs its own order by the
+// remaining bits.  The array is cut into chunks of whole runs: chunk c spans
+// [b(c), b(c + 1)), b(c) the first run start at or after c * kChunkStride
+// (b = n past the end).  A chunk of up to kChunkCap keys (always so when no
+// run is longer than kChunkCap - kChunkStride) is sorted by one workgroup in
+// LDS and written back in place with each key's grid cell: when every run in
+// it has at most kShortRun keys, each key's place in its run is counted
+// directly (keys of its run that are smaller, or equal and earlier); else
+// the whole chunk takes stable LSD passes over the bytes that vary within
+// it.  Sorting inside a chunk leaves the top bits at every position
+// unchanged.  A longer chunk raises kErrOversized and writes nothing; the
+// caller then runs the plain sort instead.
+constexpr int kTopShift = 32;
+constexpr int kTopPasses = 4;
+constexpr uint64_t kChunkStride = 2048;
+constexpr uint32_t kChunkCap = 6144;
+constexpr uint32_t kShortRun = 64;
+constexpr int kChunkWaves = 8;
+constexpr int kChunkThreads = kChunkWaves * kWave;
+constexpr int kChunkSlots = kChunkCap / kChunkThreads;   // items per lane at capacity
+
+// Entry c (one wave per stride of kChunkStride positions): the first run
+// start in [c * kChunkStride, (c + 1) * kChunkStride) (a position p with
+// p == 0 or top bits differing from p - 1's), ~0 if the stride has none;
+// entry `chunks` is n.
+__global__ __launch_bounds__(256) void chunk_firsts(const uint64_t* __restrict__ keys, uint64_t n,
+                                                    uint64_t chunks, uint64_t* __restrict__ first) {
+  const uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t l = lane_id();
+  if (c > chunks) return;
+  if (c == chunks) {
+    if (l == 0) first[c] = n;
+    return;
+  }
+  const uint64_t base = c * kChunkStride;
+  uint64_t found = ~0ull;
+  // Eight rows of 64 positions per round, their loads all in flight.
+  for (uint32_t g = 0; g < kChunkStride / kWave && found == ~0ull; g += 8) {
+    uint64_t m[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint64_t p = base + (uint64_t)(g + j) * kWave + l;
+      bool hit = false;
+      if (p < n) hit = p == 0 || (keys[p] >> kTopShift) != (keys[p - 1] >> kTopShift);
+      m[j] = __ballot(hit);
+    }
+#pragma unroll
+    for (int j = 7; j >= 0; --j)
+      if (m[j] != 0)
+        found = base + (uint64_t)(g + j) * kWave + (uint64_t)(__ffsll((unsigned long long)m[j]) - 1);
+  }
+  if (l == 0) first[c] = found;
+}
+
+// b(c) from the strides' first run starts: the first entry of
+// first[c .. c + kChunkLook] that is not ~0 (entries past `chunks` are n),
+// or ~0 when none is (the run through c * kChunkStride is longer than a
+// chunk can hold).
+constexpr int kChunkLook = (int)(kChunkCap / kChunkStride);
+__device__ __forceinline__ uint64_t chunk_bound(const uint64_t* first, uint64_t chunks, uint64_t n,
+                                                uint64_t c) {
+  for (int j = 0; j <= kChunkLook; ++j) {
+    const uint64_t v = c + j <= chunks ? first[c + j] : n;
+    if (v != ~0ull) return v;
+  }
+  return ~0ull;
+}
+
+__global__ __launch_bounds__(kChunkThreads) void chunk_sort(
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ ids, uint64_t n,
+    const uint64_t* __restrict__ first, uint64_t chunks, uint64_t* __restrict__ cells_out,
+    int cell_curve, uint32_t* err) {
+  __shared__ union {
+    uint32_t wave_hist[kChunkWaves][kRadix];
+    struct {
+      uint64_t k[kChunkCap];
+      uint32_t v[kChunkCap];
+    } st;
+  } sm;
+  __shared__ uint32_t s_local[kRadix];
+  __shared__ uint32_t s_tmp[kChunkWaves];
+  __shared__ uint64_t s_bound[2];
+  __shared__ uint32_t s_vary[2];
+  __shared__ uint32_t s_long;
+  __shared__ uint16_t s_inv[1024];   // inverse Hilbert table for the cells
+
+  const uint32_t tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const uint64_t c = blockIdx.x;
+  if (cells_out && cell_curve == SFC_CURVE_HILBERT)
+    for (uint32_t i = tid; i < 1024; i += kChunkThreads) s_inv[i] = kHilbertInvLutConst.v[i];
+  if (tid == 0) {
+    s_bound[0] = chunk_bound(first, chunks, n, c);
+    s_bound[1] = chunk_bound(first, chunks, n, c + 1);
+    s_vary[0] = 0;
+    s_vary[1] = 0;
+    s_long = 0;
+  }
+  __syncthreads();
+  const uint64_t start = s_bound[0], end = s_bound[1];
+  if (start == ~0ull || end == ~0ull || end - start > kChunkCap) {
+    if (tid == 0) atomicOr(err, kErrOversized);
+    return;   // the whole workgroup
+  }
+  if (end <= start) return;
+  const uint32_t len = (uint32_t)(end - start);
+
+  // The chunk into LDS in position order (coalesced).
+  for (uint32_t j = tid; j < len; j += kChunkThreads) {
+    sm.st.k[j] = keys[start + j];
+    sm.st.v[j] = ids[start + j];
+  }
+  __syncthreads();
+
+  // The bytes that vary within the chunk, and whether a run is longer than
+  // kShortRun (the keys being ordered by their top bits, a run holds more
+  // than kShortRun keys exactly when some key has the top bits of the key
+  // kShortRun places before it).
+  const uint64_t k0 = sm.st.k[0];
+  uint64_t vary = 0;
+  bool is_long = false;
+  for (uint32_t j = tid; j < len; j += kChunkThreads) {
+    const uint64_t kj = sm.st.k[j];
+    vary |= kj ^ k0;
+    if (j >= kShortRun && (sm.st.k[j - kShortRun] >> kTopShift) == (kj >> kTopShift)) is_long = true;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) vary |= __shfl_xor(vary, o, 64);
+  const bool wave_long = __ballot(is_long) != 0;
+  if (l == 0) {
+    if (vary != 0) {
+      atomicOr(&s_vary[0], (uint32_t)vary);
+      atomicOr(&s_vary[1], (uint32_t)(vary >> 32));
+    }
+    if (wave_long) atomicOr(&s_long, 1u);
+  }
+  __syncthreads();
+
+  if (s_long == 0) {
+    // Every run is short: a key's place is its run's start plus the number
+    // of keys of the run before it in (key, position) order.  Keys move only
+    // within their run, so the writes stay nearly contiguous.
+    for (uint32_t j = tid; j < len; j += kChunkThreads) {
+      const uint64_t kj = sm.st.k[j];
+      const uint64_t t = kj >> kTopShift;
+      uint32_t b = j;
+      while (b > 0 && (sm.st.k[b - 1] >> kTopShift) == t) --b;
+      uint32_t r = 0;
+      for (uint32_t q = b; q < len; ++q) {
+        const uint64_t kq = sm.st.k[q];
+        if ((kq >> kTopShift) != t) break;
+        r += (kq < kj || (kq == kj && q < j)) ? 1u : 0u;
+      }
+      const uint64_t dst = start + b + r;
+      keys[dst] = kj;
+      ids[dst] = sm.st.v[j];
+      if (cells_out) cells_out[dst] = cell_of_key_lut(cell_curve, kj, s_inv);
+    }
+    return;
+  } else {
+    // Stable LSD passes over the bytes that vary within the chunk.  Each
+    // wave holds a contiguous stretch of `slots` rows of 64 positions, so
+    // that (wave, slot, lane) order is position order.
+    const uint32_t slots = (len + kChunkThreads - 1) / kChunkThreads;
+    const uint32_t wbase = w * slots * kWave;
+    const uint64_t vmask = (uint64_t)s_vary[0] | ((uint64_t)s_vary[1] << 32);
+    uint64_t key[kChunkSlots];
+    uint32_t val[kChunkSlots];
+#pragma unroll
+    for (int i = 0; i < kChunkSlots; ++i) {
+      key[i] = ~0ull;   // padding sorts after every key of the chunk
+      val[i] = 0xFFFFFFFFu;
+      const uint32_t pos = wbase + i * kWave + l;
+      if (i < (int)slots && pos < len) {
+        key[i] = sm.st.k[pos];
+        val[i] = sm.st.v[pos];
+      }
+    }
+    __syncthreads();   // the items are in registers before the histograms reuse LDS
+    const uint64_t below_mask = lanemask_lt();
+    for (int shift = 0; shift < 64; shift += 8) {
+      if (((vmask >> shift) & 255u) == 0) continue;   // the byte is the same for every key
+      uint32_t* wh = sm.wave_hist[w];
+      for (uint32_t i = l; i < kRadix; i += kWave) wh[i] = 0;
+      uint32_t dig[kChunkSlots], rank[kChunkSlots];
+#pragma unroll
+      for (int i = 0; i < kChunkSlots; ++i) {
+        if (i >= (int)slots) continue;
+        const uint32_t dg = (uint32_t)(key[i] >> shift) & 255u;
+        uint64_t match = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const bool bit = (dg >> b) & 1u;
+          const uint64_t bal = __ballot(bit);
+          match &= bit ? bal : ~bal;
+        }
+        const uint32_t cnt = (uint32_t)__popcll(match);
+        const uint32_t below = (uint32_t)__popcll(match & below_mask);
+        const uint32_t pre = wh[dg];
+        if (below == 0) wh[dg] = pre + cnt;
+        dig[i] = dg;
+        rank[i] = pre + below;
+      }
+      __syncthreads();
+      // Digit d (threads 0..255): per-wave exclusive bases and the chunk's
+      // exclusive count of smaller digits.
+      if (tid < kRadix) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < kChunkWaves; ++ww) {
+          const uint32_t cw = sm.wave_hist[ww][tid];
+          sm.wave_hist[ww][tid] = tot;
+          tot += cw;
+        }
+        uint32_t x = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(x, o, 64);
+          if (l >= (uint32_t)o) x += y;
+        }
+        if (l == 63) s_tmp[w] = x;
+        s_local[tid] = x - tot;
+      }
+      __syncthreads();
+      uint32_t lpos[kChunkSlots];
+      {
+        const uint32_t add1 = s_tmp[0], add2 = add1 + s_tmp[1], add3 = add2 + s_tmp[2];
+#pragma unroll
+        for (int i = 0; i < kChunkSlots; ++i) {
+          if (i >= (int)slots) continue;
+          const uint32_t dg = dig[i], q = dg >> 6;
+          const uint32_t wadd = q == 0 ? 0u : (q == 1 ? add1 : (q == 2 ? add2 : add3));
+          lpos[i] = s_local[dg] + wadd + sm.wave_hist[w][dg] + rank[i];
+        }
+      }
+      __syncthreads();   // every histogram read is done before the items overwrite it
+#pragma unroll
+      for (int i = 0; i < kChunkSlots; ++i) {
+        if (i >= (int)slots) continue;
+        sm.st.k[lpos[i]] = key[i];
+        sm.st.v[lpos[i]] = val[i];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kChunkSlots; ++i) {
+        if (i >= (int)slots) continue;
+        const uint32_t pos = wbase + i * kWave + l;
+        key[i] = sm.st.k[pos];
+        val[i] = sm.st.v[pos];
+      }
+      __syncthreads();   // every item is read back before the next pass's histograms
+    }
+#pragma unroll
+    for (int i = 0; i < kChunkSlots; ++i) {
+      if (i >= (int)slots) continue;
+      const uint32_t pos = wbase + i * kWave + l;
+      sm.st.k[pos] = key[i];
+      sm.st.v[pos] = val[i];
+    }
+    __syncthreads();
+  }
+
+  // Out in position order: consecutive lanes, consecutive words.
+  for (uint32_t j = tid; j < len; j += kChunkThreads) {
+    const uint64_t k = sm.st.k[j];
+    keys[start + j] = k;
+    ids[start + j] = sm.st.v[j];
+    if (cells_out) cells_out[start + j] = cell_of_key_lut(cell_curve, k, s_inv);
+  }
+}
+
 template <int ITEMS>
 hipError_t launch_scatter(bool first, bool gather, bool setpass, int shift, uint64_t tiles,
                           const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
@@ -442,19 +723,20 @@ size_t build_scratch_bytes(uint64_t n) {
 }
 
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
-                       uint32_t* counts, hipStream_t s, double* xy_copy) {
+                       uint32_t* counts, hipStream_t s, double* xy_copy, int count_shift) {
   if (n == 0) return hipSuccess;
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
   ProfScope ps("keygen_tiles", s);
   if (curve == SFC_CURVE_MORTON3)
-    keygen3_tiles<<<(uint32_t)tiles, 256, 0, s>>>(xy, n, tile, keys, err, counts, tiles, xy_copy);
+    keygen3_tiles<<<(uint32_t)tiles, 256, 0, s>>>(xy, n, tile, keys, err, counts, tiles, xy_copy,
+                                                  count_shift);
   else if (curve == SFC_CURVE_HILBERT)
     keygen_tiles<SFC_CURVE_HILBERT><<<(uint32_t)tiles, 256, 0, s>>>(
-        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy);
+        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy, count_shift);
   else
     keygen_tiles<SFC_CURVE_MORTON><<<(uint32_t)tiles, 256, 0, s>>>(
-        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy);
+        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy, count_shift);
   return hipGetLastError();
 }
 
@@ -545,6 +827,75 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
+                              uint32_t* ids_out, void* scratch, uint32_t* err, hipStream_t s,
+                              uint64_t* cells_out, double* xy_copy) {
+  if (n == 0) return hipSuccess;
+  const uint32_t tile = (uint32_t)sort_tile(n);
+  const uint64_t tiles = (n + tile - 1) / tile;
+  const uint64_t cells = tiles * kRadix;
+  char* p = (char*)scratch;
+  uint64_t* keys_b = (uint64_t*)p;      p += align256(n * 8);
+  uint32_t* ids_b = (uint32_t*)p;       p += align256(n * 4);
+  uint32_t* counts = (uint32_t*)p;      p += align256(cells * 4);
+  uint32_t* rel = (uint32_t*)p;         p += align256(cells * 4);
+  uint32_t* dtot = (uint32_t*)p;
+
+  // The passes alternate between the output and the scratch buffer so that
+  // the last one lands in the output, where the chunks are then sorted in
+  // place.
+  auto final_pass = [](int pass) { return ((kTopPasses - 1 - pass) & 1) == 0; };
+  uint64_t* keys_first = final_pass(0) ? keys_b : keys_out;
+  hipError_t e = launch_keys(xy, n, curve, keys_first, err, counts, s, xy_copy, kTopShift);
+  if (e != hipSuccess) return e;
+  const uint64_t* kin = keys_first;
+  const uint32_t* vin = nullptr;
+  for (int pass = 0; pass < kTopPasses; ++pass) {
+    const bool fin = final_pass(pass);
+    uint64_t* kout = fin ? keys_out : keys_b;
+    uint32_t* vout = fin ? ids_out : ids_b;
+    const int shift = kTopShift + 8 * pass;
+    if (pass > 0) {
+      ProfScope ps("tile_hist", s);
+      tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, nullptr, counts,
+                                                       tiles);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+      ProfScope ps("digit_scan", s);
+      digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    ProfScope ps("scatter_pass", s);
+#define SFC_LAUNCH(I)                                                                     \
+  launch_scatter<I>(pass == 0, false, false, shift, tiles, kin, vin, kout, vout, n, rel, dtot, \
+                    err, xy, nullptr, nullptr, curve, nullptr, s)
+    switch (sort_items(n)) {
+      case 16: e = SFC_LAUNCH(16); break;
+      case 12: e = SFC_LAUNCH(12); break;
+      default: e = SFC_LAUNCH(8); break;
+    }
+#undef SFC_LAUNCH
+    if (e != hipSuccess) return e;
+    kin = kout;
+    vin = vout;
+  }
+  // The strides' first run starts go to the tile counts, free after the last
+  // pass (tiles * 256 words hold more than chunks + 1 entries).
+  const uint64_t chunks = (n + kChunkStride - 1) / kChunkStride;
+  if ((chunks + 1) * 8 > cells * 4) return hipErrorInvalidValue;
+  uint64_t* first = (uint64_t*)counts;
+  {
+    ProfScope ps("chunk_firsts", s);
+    chunk_firsts<<<(uint32_t)((chunks + 1 + 3) / 4), 256, 0, s>>>(keys_out, n, chunks, first);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  ProfScope ps("chunk_sort", s);
+  chunk_sort<<<(uint32_t)chunks, kChunkThreads, 0, s>>>(keys_out, ids_out, n, first, chunks,
+                                                         cells_out, curve, err);
+  return hipGetLastError();
 }
 
 hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipStream_t s) {

@@ -19,6 +19,7 @@ constexpr uint32_t kErrInvalidQuery = 2u;
 constexpr uint32_t kErrLookback = 4u;   // reserved (no kernel waits on another)
 constexpr uint32_t kErrInternal = 8u;   // an index outside its array (never expected)
 constexpr uint32_t kErrOverflow = 16u;  // more candidate rows than a fixed plan holds
+constexpr uint32_t kErrOversized = 32u; // a run of equal top key bits too long for the chunked sort
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 

@@ -196,4 +196,50 @@ __host__ __device__ __forceinline__ uint64_t hilbert_key_lut(const uint16_t* lut
   return key;
 }
 
+// The inverse table: index (frame << 8) | 8 key bits, entry
+// (frame' << 8) | (4 x bits << 4) | (4 y bits) (the forward table is a
+// bijection of the 256 (x, y) nibble pairs onto the 256 digit bytes in
+// every frame).
+constexpr HilbertLut make_hilbert_inv_lut() {
+  const HilbertLut fwd = make_hilbert_lut();
+  HilbertLut t{};
+  for (int f0 = 0; f0 < 4; ++f0)
+    for (int xy = 0; xy < 256; ++xy) {
+      const int e = fwd.v[(f0 << 8) | xy];
+      t.v[(f0 << 8) | (e & 0xFF)] = (uint16_t)((e & 0x300) | xy);
+    }
+  return t;
+}
+
+namespace {
+__constant__ HilbertLut kHilbertInvLutConst = make_hilbert_inv_lut();
+}  // namespace
+
+// cell_of_key with the Hilbert labels decoded through the inverse table.
+__host__ __device__ __forceinline__ void hilbert_decode_lut(const uint16_t* inv, uint64_t key,
+                                                            uint32_t& x, uint32_t& y);
+__host__ __device__ __forceinline__ uint64_t cell_of_key_lut(int curve, uint64_t key,
+                                                             const uint16_t* inv) {
+  if (curve != 1) return cell_of_key(curve, key);   // not SFC_CURVE_HILBERT
+  uint32_t x, y;
+  hilbert_decode_lut(inv, key, x, y);
+  return (uint64_t)x | ((uint64_t)y << 32);
+}
+
+// hilbert_decode through the inverse table: eight steps of four levels,
+// most significant first, starting in the identity frame.
+__host__ __device__ __forceinline__ void hilbert_decode_lut(const uint16_t* inv, uint64_t key,
+                                                            uint32_t& x, uint32_t& y) {
+  uint32_t f = 0, cx = 0, cy = 0;
+#pragma unroll
+  for (int s = 56; s >= 0; s -= 8) {
+    const uint32_t e = inv[(f << 8) | ((uint32_t)(key >> s) & 0xFFu)];
+    cx = (cx << 4) | ((e >> 4) & 15u);
+    cy = (cy << 4) | (e & 15u);
+    f = e >> 8;
+  }
+  x = cx;
+  y = cy;
+}
+
 }  // namespace sfc

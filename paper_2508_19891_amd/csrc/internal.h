@@ -39,7 +39,8 @@ size_t build_scratch_bytes(uint64_t n);
 // Keys of n points (err: device word, kErrDomain is or-ed in); counts, if
 // not null, receives the first digit's counts per sort tile.
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
-                       uint32_t* counts, hipStream_t s, double* xy_copy = nullptr);
+                       uint32_t* counts, hipStream_t s, double* xy_copy = nullptr,
+                       int count_shift = 0);
 // xy_out (may be null): the points in sorted order.  cells_out (may be
 // null): the grid cells of the sorted points (pack_cell2 / pack_cell3),
 // decoded from the keys (or taken from the points when they are gathered).
@@ -48,6 +49,14 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
                       hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0,
                       uint64_t* cells_out = nullptr, double* xy_copy = nullptr);
+// sort_build without point sets or xy_out, by four radix passes over the
+// top 32 key bits and an LDS sort of each chunk of whole runs of equal top
+// bits (same results).  A run too long for a chunk raises kErrOversized in
+// *err, and the arrays are then unspecified: run sort_build instead.  Same
+// scratch as sort_build.
+hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
+                              uint32_t* ids_out, void* scratch, uint32_t* err, hipStream_t s,
+                              uint64_t* cells_out, double* xy_copy);
 // out[i] = xy[ids[i]] for points of dim (2 or 3) doubles.
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n, int dim,
                          hipStream_t s);

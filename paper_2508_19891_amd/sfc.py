@@ -44,7 +44,7 @@ EXPORTS = [
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
     "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric", "sfc_set_cell_filter",
-    "sfc_cells_copy",
+    "sfc_cells_copy", "sfc_debug_sort_path",
 ]
 
 NPARAM = 1153
@@ -184,6 +184,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_autotune_build.restype = i32
     L.sfc_autotune_query.argtypes = [vp, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(i32), vp]
     L.sfc_autotune_query.restype = i32
+    L.sfc_debug_sort_path.argtypes = [i32, ctypes.POINTER(i32)]
+    L.sfc_debug_sort_path.restype = i32
     L.sfc_debug_chunk_tiles.argtypes = [u64]
     L.sfc_debug_chunk_tiles.restype = i32
     L.sfc_insert.argtypes = [vp, vp, u64, vp]
@@ -616,6 +618,15 @@ class Graph:
 def debug_chunk_tiles(tiles: int):
     """Test hook: compaction chunk size in tiles of 64 rows (0 = default)."""
     _check(lib().sfc_debug_chunk_tiles(tiles), "sfc_debug_chunk_tiles")
+
+
+def debug_sort_path(force_plain: int = -1) -> int:
+    """Test hook: force_plain 1 makes every build use the plain radix sort, 0
+    restores the chunked sort (-1 leaves it); returns 1 if the last build fell
+    back from the chunked sort to the plain one."""
+    fell = ctypes.c_int(0)
+    _check(lib().sfc_debug_sort_path(force_plain, ctypes.byref(fell)), "sfc_debug_sort_path")
+    return fell.value
 
 
 def autotune_build(xy: torch.Tensor, curve: int = MORTON, set_off=None):
