@@ -38,6 +38,31 @@ def kernel_source_hash(name: str) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
+# Kernels whose algorithmic bytes the bench states (candidates for the
+# roofline's dominant kernel).
+ROOFLINE_KERNELS = ("keygen_tiles", "tile_hist", "scatter_pass", "chunk_sort", "ranges_search",
+                    "compact_test", "query_filters", "compact_write")
+
+
+def timed_calls(fn, steps: int):
+    """(ms per call of fn, timed without events, {kernel: (launches, ms)} of
+    the same number of calls repeated with HIP events around every launch,
+    which add gaps between kernels)."""
+    torch.cuda.synchronize()
+    sfc.profile_reset()
+    sfc.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    sfc.profile_enable(False)
+    kern = sfc.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3, kern
+
+
 def load_traffic(kernel: str, source: str):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summary (its 'traffic: kernel bytes source hash' lines), or None if the
@@ -187,16 +212,9 @@ def learned_large_bench(args, sfc, workload, torch):
         del ids0
         for _ in range(max(1, args.warmup)):
             idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
-        torch.cuda.synchronize()
-        sfc.profile_reset()
-        sfc.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / args.steps * 1e3
-        sfc.profile_enable(False)
-        kern = {k: v[1] / args.steps for k, v in sfc.profile_read().items()}
+        ms, kern = timed_calls(lambda: idx.query(q, d, out_ids=out_ids, out_offsets=offsets),
+                               args.steps)
+        kern = {k: v[1] / args.steps for k, v in kern.items()}
         out[name] = {"ms_per_batch": ms, "queries_per_s": m / (ms * 1e-3),
                      "search_ms": kern.get({sfc.BINARY: "ranges_search", sfc.LEARNED:
                                             "ranges_learned", sfc.STREE: "ranges_stree"}[search]),
@@ -259,20 +277,12 @@ def early_term_bench(args, sfc, workload, torch, pts_c2):
         rep = int(ids0.numel())
         for _ in range(max(1, args.warmup)):
             idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
-        torch.cuda.synchronize()
-        sfc.profile_reset()
-        sfc.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / args.steps * 1e3
-        sfc.profile_enable(False)
+        ms, kern = timed_calls(lambda: idx.query(q, d, out_ids=out_ids, out_offsets=offsets),
+                               args.steps)
         st = idx.last_stats()
         out[name] = {"ms_per_batch": ms, "queries_per_s": m / (ms * 1e-3), "reported": rep,
                      "candidates": st["candidates"], "cells_pruned": st["pruned"],
-                     "kernels_ms_per_batch": {k: v[1] / args.steps
-                                              for k, v in sfc.profile_read().items()}}
+                     "kernels_ms_per_batch": {k: v[1] / args.steps for k, v in kern.items()}}
         idx.close()
     assert out["plain"]["reported"] == out["early_term"]["reported"]
     out["speedup_batch"] = out["plain"]["ms_per_batch"] / out["early_term"]["ms_per_batch"]
@@ -365,17 +375,8 @@ def three_d_bench(args, sfc, workload, torch):
 
         for _ in range(max(1, args.warmup)):
             step().close()
-        torch.cuda.synchronize()
-        sfc.profile_reset()
-        sfc.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ix = step()
-            ix.close()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / args.steps * 1e3
-        sfc.profile_enable(False)
-        kern = {k: v[1] / args.steps for k, v in sfc.profile_read().items()}
+        ms, kern = timed_calls(lambda: step().close(), args.steps)
+        kern = {k: v[1] / args.steps for k, v in kern.items()}
         ix = sfc.Index(pts, sfc.MORTON3, search=search, refine=refine)
         ix.query(q, d, out_ids=out_ids, out_offsets=offsets)
         cand = ix.last_stats()["candidates"]
@@ -526,26 +527,41 @@ def main():
         for i in range(args.warmup):
             step()
             log(f"warmup {i + 1}/{args.warmup}")
+        # Per-kernel breakdown: the same steps with HIP events around every
+        # launch (the events add gaps between kernels, so these steps are
+        # not the timed ones).
         torch.cuda.synchronize()
         sfc.profile_reset()
         sfc.profile_enable(True)
+        for i in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        sfc.profile_enable(False)
+        kern = sfc.profile_read()
+        dom = max((k for k in ROOFLINE_KERNELS if k in kern), key=lambda k: kern[k][1])
+        # Timed steps: events only around the dominant kernel's launches.
+        sfc.profile_reset()
+        sfc.profile_only(dom)
+        sfc.profile_enable(True)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
             step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sfc.profile_enable(False)
-        kern = sfc.profile_read()
+        sfc.profile_only(None)
+        kern_dom = sfc.profile_read()
         log(f"timed {args.steps} steps in {dt:.3f} s")
         if linfo is not None:
             stats = dict(stats, learned=linfo)
-        return dt / args.steps * 1e3, kern, stats, total
+        return dt / args.steps * 1e3, kern, stats, total, (dom, kern_dom.get(dom))
 
     if args.only_refined:
         ms_paper, kern_paper, stats_paper = float("nan"), {}, {"candidates": None}
     else:
-        ms_paper, kern_paper, stats_paper, _ = run_mode(False)
-    ms_step, kern, stats, total = run_mode(True)
+        ms_paper, kern_paper, stats_paper, _, _ = run_mode(False)
+    ms_step, kern, stats, total, (dom_timed, dom_kern) = run_mode(True)
     def query_only(search: int, cells: bool = True):
         """One index (built and, for the learned search, fitted once); the
         timed steps are query batches only.  cells=False: every candidate
@@ -563,16 +579,9 @@ def main():
         del ids0
         for _ in range(max(1, args.warmup)):
             idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
-        torch.cuda.synchronize()
-        sfc.profile_reset()
-        sfc.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            idx.query(q, d, out_ids=out_ids, out_offsets=offsets)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps * 1e3
-        sfc.profile_enable(False)
-        kern_q = {k: v[1] / args.steps for k, v in sfc.profile_read().items()}
+        dt, kern_q = timed_calls(lambda: idx.query(q, d, out_ids=out_ids, out_offsets=offsets),
+                                 args.steps)
+        kern_q = {k: v[1] / args.steps for k, v in kern_q.items()}
         info = idx.learned_info() if search == sfc.LEARNED else None
         rep_q = idx.last_stats()["reported"]
         idx.close()
@@ -654,8 +663,10 @@ def main():
     for k, b in algo.items():
         if k in kern:
             kern_gbs[k] = b / (kern[k][1] / args.steps * 1e-3) / 1e9
-    dom = max((k for k in algo if k in kern), key=lambda k: kern[k][1])
-    d_launch, d_ms = kern[dom]
+    # The dominant kernel (by time in the profiled steps) and its launches
+    # timed by HIP events inside the timed steps.
+    dom = dom_timed
+    d_launch, d_ms = dom_kern if dom_kern else kern[dom]
     launches_per_step = d_launch / args.steps
     bytes_per_launch = algo[dom] / launches_per_step
     achieved = bytes_per_launch / (d_ms / d_launch * 1e-3) / 1e9

@@ -493,6 +493,10 @@ void sfc_free(sfc_index* h);
  * Returns the number of distinct kernels seen (which may exceed max).
  */
 void sfc_profile_enable(int on);
+/* Restricts the timing to the launches of one kernel (name as reported by
+   sfc_profile_read; host string, copied), so that the others run without
+   events between them; NULL or "" times every kernel again. */
+void sfc_profile_only(const char* name);
 void sfc_profile_reset(void);
 int sfc_profile_read(const char** names, uint64_t* launches, double* ms,
                      int max);

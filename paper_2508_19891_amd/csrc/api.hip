@@ -96,6 +96,7 @@ namespace {
 struct ProfState {
   std::mutex mu;
   bool on = false;
+  std::string only;   // non-empty: time only the launches of this kernel
   struct Pending {
     const char* name;
     hipEvent_t a, b;
@@ -127,6 +128,7 @@ ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s) {
   ProfState& P = prof();
   std::lock_guard<std::mutex> g(P.mu);
   if (!P.on || g_capturing.load() > 0) return;
+  if (!P.only.empty() && P.only != n) return;
   hipEvent_t e = take_event(P);
   if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
 }
@@ -1430,6 +1432,12 @@ void sfc_profile_enable(int on) {
   sfc::ProfState& P = sfc::prof();
   std::lock_guard<std::mutex> g(P.mu);
   P.on = on != 0;
+}
+
+void sfc_profile_only(const char* name) {
+  sfc::ProfState& P = sfc::prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.only = name ? name : "";
 }
 
 void sfc_profile_reset(void) {

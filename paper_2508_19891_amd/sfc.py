@@ -36,6 +36,7 @@ EXPORTS = [
     "sfc_default_options", "sfc_status_string", "sfc_build", "sfc_query_batch", "sfc_size",
     "sfc_index_view", "sfc_index_copy", "sfc_keys", "sfc_query_ranges",
     "sfc_last_query_stats", "sfc_free", "sfc_profile_enable", "sfc_profile_reset",
+    "sfc_profile_only",
     "sfc_profile_read", "sfc_pool_trim", "sfc_set_search", "sfc_learned_fit",
     "sfc_learned_info_get", "sfc_learned_params", "sfc_learned_grad",
     "sfc_learned_shrink_windows", "sfc_build_sets", "sfc_query_sets", "sfc_graph_build",
@@ -141,6 +142,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_free.restype = None
     L.sfc_profile_enable.argtypes = [i32]
     L.sfc_profile_enable.restype = None
+    L.sfc_profile_only.argtypes = [ctypes.c_char_p]
+    L.sfc_profile_only.restype = None
     L.sfc_profile_reset.argtypes = []
     L.sfc_profile_reset.restype = None
     L.sfc_profile_read.argtypes = [vp, vp, vp, i32]
@@ -702,6 +705,11 @@ def learned_grad(params, x, t):
 
 def profile_enable(on: bool = True):
     lib().sfc_profile_enable(1 if on else 0)
+
+
+def profile_only(name: str | None):
+    """Time only the launches of kernel `name` (None: every kernel)."""
+    lib().sfc_profile_only(name.encode() if name else None)
 
 
 def profile_reset():
