@@ -451,7 +451,8 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
                                 h->stream));
   else
     SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                               h->refine_min, learned ? &lv : nullptr,
+                               h->refine_min, h->metric == SFC_METRIC_L2,
+                               learned ? &lv : nullptr,
                                stree_on(h) ? &sv : nullptr, h->occ, qset,
                                qset ? h->set_off : nullptr, h->n_sets, *qs, dbg_lo, dbg_hi, dbg_b,
                                dbg_e, dbg_nr, h->stream));
@@ -910,7 +911,8 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
                                 h->stream));
   else
     SFC_TRY(sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                               h->refine_min, learned ? &lv : nullptr,
+                               h->refine_min, h->metric == SFC_METRIC_L2,
+                               learned ? &lv : nullptr,
                                stree_on(h) ? &sv : nullptr, h->occ, nullptr, nullptr, 0, qs,
                                nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
   if (qepoch)
@@ -1273,7 +1275,8 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
                                 stree_on(h) ? &sv : nullptr, g->qs,
                                   s)
             : sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
-                                 h->refine_min, learned ? &lv : nullptr,
+                                 h->refine_min, h->metric == SFC_METRIC_L2,
+                                 learned ? &lv : nullptr,
                                  stree_on(h) ? &sv : nullptr, h->occ, qset,
                                  qset ? h->set_off : nullptr, h->n_sets, g->qs, nullptr, nullptr,
                                  nullptr, nullptr, nullptr, s);

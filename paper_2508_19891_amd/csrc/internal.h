@@ -96,7 +96,9 @@ void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slot
 size_t compact_scratch_bytes(uint64_t total_rows);
 
 // Ranges and searches per query slot, then the scan of candidate counts into
-// segment offsets; optionally records the ranges (dbg_* may be null).
+// segment offsets; optionally records the ranges (dbg_* may be null).  ball:
+// the Euclidean metric (the refinement may then also drop sub-cells outside
+// the disc).
 // lview non-null: searches go through the learned index; else sview
 // non-null: through the static search tree (both only without point sets).
 // occ non-null: cells whose occupancy bit is clear are skipped (early
@@ -104,7 +106,7 @@ size_t compact_scratch_bytes(uint64_t total_rows);
 // qset/set_off non-null: query j searches only set qset[j] (positions
 // [set_off[s], set_off[s+1]) of the sorted arrays).
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
-                         uint64_t n, int curve, bool refine, uint32_t refine_min,
+                         uint64_t n, int curve, bool refine, uint32_t refine_min, bool ball,
                          const LearnedView* lview, const StreeView* sview, const uint32_t* occ,
                          const uint32_t* qset, const uint64_t* set_off, uint32_t n_sets,
                          QueryScratch& qs, uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b,

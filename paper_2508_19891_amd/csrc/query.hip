@@ -287,22 +287,65 @@ __device__ __forceinline__ void find_range(const uint64_t* __restrict__ keys, ui
   e = khi == ~0ull ? n : r2[1];
 }
 
+// Hilbert frame (as in hilbert_key_lut: bit 0 axes exchanged, bit 1 both
+// complemented) of the cell whose key prefix holds `digits` digits: digit 0
+// exchanges the axes and digit 3 exchanges and complements them, and frames
+// compose by xor, so the frame is the parity of the count of digits 0 or 3
+// and the parity of the count of digits 3.
+__device__ __forceinline__ uint32_t hilbert_frame(uint64_t prefix, int digits) {
+  const uint64_t lowbits = 0x5555555555555555ull & ((1ull << (2 * digits)) - 1);
+  const uint32_t c03 = (uint32_t)__popcll(~(prefix ^ (prefix >> 1)) & lowbits) & 1u;
+  const uint32_t c3 = (uint32_t)__popcll(prefix & (prefix >> 1) & lowbits) & 1u;
+  return c03 | (c3 << 1);
+}
+
+// Rank along the curve of sub-cell (a, b) (offsets in cells D levels down,
+// D = 1 or 2) within a cell of Hilbert frame f.
+template <int CURVE>
+__device__ __forceinline__ uint32_t sub_rank(const uint16_t* lut, uint32_t f, uint32_t a,
+                                             uint32_t b, int D) {
+  if (CURVE == SFC_CURVE_HILBERT) {
+    const uint32_t sh = 4 - D;   // the offsets as the top bits of 4-level nibbles
+    return (lut[(f << 8) | ((a << sh) << 4) | (b << sh)] & 0xFFu) >> (8 - 2 * D);
+  }
+  return D == 2 ? (a & 1u) | ((b & 1u) << 1) | ((a >> 1) << 2) | ((b >> 1) << 3) : a | (b << 1);
+}
+
+// Whether the disc of radius d about (qx, qy) may hold a point that the
+// exact test accepts within the grid rectangle [x0, x1) x [y0, y1) (grid
+// units of 2^-32): false only when the rectangle's distance from the centre,
+// squared, exceeds d^2 by a relative 2^-40, far beyond the few units in the
+// last place by which the exact test's binary64 arithmetic can err.  Radii
+// below 2^-400 (whose squares approach the subnormal range) keep every
+// rectangle.
+__device__ __forceinline__ bool disc_meets(double qx, double qy, double d, int64_t x0, int64_t x1,
+                                           int64_t y0, int64_t y1) {
+  if (!(d >= 0x1p-400)) return true;
+  const double s = 0x1p-32;
+  const double ex = fmax(0.0, fmax((double)x0 * s - qx, qx - (double)x1 * s));
+  const double ey = fmax(0.0, fmax((double)y0 * s - qy, qy - (double)y1 * s));
+  return !(ex * ex + ey * ey > d * d * (1.0 + 0x1p-40));
+}
+
 // One lane per (query, slot).
 //   REFINE = false: four slots per query, slot r holds the r-th merged key
 //     range of cells(Q) and its index range (the method as stated: at most
 //     four ranges, two binary searches each).
 //   REFINE = true: eight slots per query, lane r handles the r-th cell of
 //     cells(Q) (by key).  After the two searches of the cell, a cell holding
-//     more than refine_min points is split once: its four children meet the
-//     box or not, the children that do are merged into at most two key runs
-//     (consecutive children in key order), and each run is located by two
-//     searches inside the cell's index range.  Only points outside the box
-//     are dropped, so the reported set and its order are unchanged.
+//     more than refine_min points is split two levels down (one for a cell
+//     of level 1): its sixteen sub-cells meet the box or not (ball: and the
+//     disc), the kept ones form at most two key runs (consecutive sub-cells
+//     in key order; beyond two, the gaps other than the widest are closed),
+//     and each run is located by two searches inside the cell's index range.
+//     Only points that the exact test rejects are dropped, so the reported
+//     set and its order are unchanged.
 template <int CURVE, bool REFINE, int SEARCH>
 __global__ __launch_bounds__(256) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, StreeView sv,
-    uint32_t refine_min, const uint32_t* __restrict__ occ, const uint64_t* __restrict__ pairs,
+    uint32_t refine_min, bool ball, const uint32_t* __restrict__ occ,
+    const uint64_t* __restrict__ pairs,
     const uint64_t* __restrict__ pair_total, const uint32_t* __restrict__ qset,
     const uint64_t* __restrict__ set_off, uint32_t n_sets, uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
@@ -383,42 +426,55 @@ __global__ __launch_bounds__(256) void ranges_search(
         e0 += base;
         ends += 2;
         if (e0 - b0 > refine_min && L >= 1 && L < 32) {
-          // Children at level L-1 that meet the box, in key order.
-          const int Lc = L - 1;
-          const uint64_t cspan = (1ull << (2 * Lc)) - 1;
-          uint64_t clo[4];
-          int nc = 0;
-          for (uint32_t dx = 0; dx < 2; ++dx) {
-            for (uint32_t dy = 0; dy < 2; ++dy) {
-              const int64_t x0 = (int64_t)((2 * cx[r] + dx) << Lc);
-              const int64_t y0 = (int64_t)((2 * cy[r] + dy) << Lc);
-              const int64_t x1 = x0 + ((int64_t)1 << Lc) - 1, y1 = y0 + ((int64_t)1 << Lc) - 1;
-              if (x1 < box[0] || x0 > box[1] || y1 < box[2] || y0 > box[3]) continue;
-              const uint64_t key =
-                  cell_key<CURVE>(lut, (uint32_t)x0, (uint32_t)y0) & ~cspan;
-              int t = nc++;
-              for (; t > 0 && clo[t - 1] > key; --t) clo[t] = clo[t - 1];
-              clo[t] = key;
+          // The cell's sub-cells D levels down that meet the box (and, with
+          // the Euclidean metric, the disc), as a mask over their order
+          // along the curve; at most two runs of them are searched, the
+          // widest gap of dropped sub-cells between the first and the last
+          // kept one staying open.
+          const int D = L >= 2 ? 2 : 1;
+          const int Ls = L - D;
+          const uint32_t per = 1u << D;
+          const uint32_t f = CURVE == SFC_CURVE_HILBERT ? hilbert_frame(lo[r] >> (2 * L), 32 - L)
+                                                        : 0u;
+          uint32_t mask = 0;
+          for (uint32_t a = 0; a < per; ++a) {
+            for (uint32_t bb = 0; bb < per; ++bb) {
+              const int64_t x0 = (int64_t)(((uint64_t)cx[r] * per + a) << Ls);
+              const int64_t y0 = (int64_t)(((uint64_t)cy[r] * per + bb) << Ls);
+              const int64_t x1 = x0 + ((int64_t)1 << Ls), y1 = y0 + ((int64_t)1 << Ls);
+              if (x1 - 1 < box[0] || x0 > box[1] || y1 - 1 < box[2] || y0 > box[3]) continue;
+              if (ball && !disc_meets(qq.x, qq.y, d, x0, x1, y0, y1)) continue;
+              mask |= 1u << sub_rank<CURVE>(lut, f, a, bb, D);
             }
           }
-          // Runs of consecutive children (at most two of four).
-          uint64_t rlo[2] = {0, 0}, rhi[2] = {0, 0};
-          int nrun = 0;
-          for (int t = 0; t < nc; ++t) {
-            if (nrun > 0 && rhi[nrun - 1] + 1 == clo[t]) {
-              rhi[nrun - 1] = clo[t] | cspan;
-            } else {
-              rlo[nrun] = clo[t];
-              rhi[nrun] = clo[t] | cspan;
-              ++nrun;
+          const uint32_t full = D == 2 ? 0xFFFFu : 0xFu;
+          if (mask == 0) {
+            e0 = b0;   // no point of the cell can be reported
+          } else if (mask != full) {
+            const int first = __builtin_ctz(mask), last = 31 - __builtin_clz(mask);
+            int gap_at = 0, gap_len = 0;   // widest run of dropped sub-cells inside
+            for (int i = first; i <= last;) {
+              if ((mask >> i) & 1u) {
+                ++i;
+                continue;
+              }
+              int j = i;
+              while (!((mask >> j) & 1u)) ++j;
+              if (j - i > gap_len) {
+                gap_len = j - i;
+                gap_at = i;
+              }
+              i = j;
             }
-          }
-          if (nrun == 1 && rlo[0] == lo[r] && rhi[0] == hi[r]) {
-            // every child meets the box: keep the cell's range
-          } else {
+            const int sh = 2 * Ls;
+            const uint64_t base = lo[r];
+            const int end0 = gap_len ? gap_at - 1 : last;
             const uint64_t pb = b0, pe = e0;
-            search_within(keys, pb, pe, rlo[0], rhi[0], b0, e0);
-            if (nrun > 1) search_within(keys, pb, pe, rlo[1], rhi[1], b1, e1);
+            search_within(keys, pb, pe, base | ((uint64_t)first << sh),
+                          base | ((((uint64_t)end0 + 1) << sh) - 1), b0, e0);
+            if (gap_len)
+              search_within(keys, pb, pe, base | ((uint64_t)(gap_at + gap_len) << sh),
+                            base | ((((uint64_t)last + 1) << sh) - 1), b1, e1);
           }
         }
       }
@@ -1263,7 +1319,7 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
 }
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
-                         uint64_t n, int curve, bool refine, uint32_t refine_min,
+                         uint64_t n, int curve, bool refine, uint32_t refine_min, bool ball,
                          const LearnedView* lview, const StreeView* sview, const uint32_t* occ,
                          const uint32_t* qset, const uint64_t* set_off, uint32_t n_sets,
                          QueryScratch& qs, uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b,
@@ -1308,7 +1364,7 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
     ProfScope ps(learned ? "ranges_learned" : stree ? "ranges_stree" : "ranges_search", s);
 #define SFC_RANGES(C, R, S)                                                                  \
   ranges_search<C, R, S><<<blocks, 256, 0, s>>>(                                              \
-      (const double2*)q, delta, m, keys, n, lv, sv, refine_min, dbg_lo ? nullptr : occ,       \
+      (const double2*)q, delta, m, keys, n, lv, sv, refine_min, ball, dbg_lo ? nullptr : occ, \
       pairs, pair_total, qset, set_off, n_sets, qs.slot_begin,                                \
       qs.slot_count, qs.slot_rows, qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr)
 #define SFC_RANGES_R(C, R)                      \
