@@ -48,6 +48,10 @@ def timed_calls(fn, steps: int):
     """(ms per call of fn, timed without events, {kernel: (launches, ms)} of
     the same number of calls repeated with HIP events around every launch,
     which add gaps between kernels)."""
+    import torch
+
+    from paper_2508_19891_amd import sfc
+
     torch.cuda.synchronize()
     sfc.profile_reset()
     sfc.profile_enable(True)

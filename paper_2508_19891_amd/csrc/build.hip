@@ -135,6 +135,38 @@ __global__ __launch_bounds__(256) void keygen3_tiles(const double* __restrict__ 
   if (counts) store_tile_counts(h, counts, tiles, blockIdx.x);
 }
 
+// Keys of query centres for ordering a batch: as keygen_tiles, with the
+// coordinates clamped into [0, 1) (queries may lie anywhere, NaN becomes 0)
+// and no domain check.
+template <int CURVE>
+__global__ __launch_bounds__(256) void query_keys_tiles(const double2* __restrict__ q, uint64_t m,
+                                                       uint32_t tile_len,
+                                                       uint64_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ counts,
+                                                       uint64_t tiles, int count_shift) {
+  __shared__ uint32_t h[kSortWaves][kRadix];
+  __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
+  for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
+  if (CURVE == SFC_CURVE_HILBERT)
+    for (int i = threadIdx.x; i < 1024; i += 256) lut[i] = kHilbertLutConst.v[i];
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * tile_len;
+  const uint64_t end = base + tile_len < m ? base + tile_len : m;
+  const uint32_t w = threadIdx.x >> 6;
+  constexpr double kBelowOne = 1.0 - 0x1p-53;
+  for (uint64_t i = base + threadIdx.x; i < end; i += 256) {
+    const double2 p = q[i];
+    const double x = p.x >= 0.0 ? (p.x < 1.0 ? p.x : kBelowOne) : 0.0;
+    const double y = p.y >= 0.0 ? (p.y < 1.0 ? p.y : kBelowOne) : 0.0;
+    const uint32_t ux = quantize(x), uy = quantize(y);
+    const uint64_t key =
+        CURVE == SFC_CURVE_HILBERT ? hilbert_key_lut(lut, ux, uy) : morton_key(ux, uy);
+    keys[i] = key;
+    atomicAdd(&h[w][(key >> count_shift) & 255u], 1u);
+  }
+  store_tile_counts(h, counts, tiles, blockIdx.x);
+}
+
 // Digit of an element in a pass: a byte of the key, or (SETPASS) a byte of
 // the point set the element's id belongs to.  Padding (id 0xFFFFFFFF) takes
 // digit 255 so that it sorts last.
@@ -896,6 +928,60 @@ hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t*
   chunk_sort<<<(uint32_t)chunks, kChunkThreads, 0, s>>>(keys_out, ids_out, n, first, chunks,
                                                          cells_out, curve, err);
   return hipGetLastError();
+}
+
+size_t order_scratch_bytes(uint64_t m) {
+  const uint64_t tiles = (m + sort_tile(m) - 1) / sort_tile(m);
+  return 2 * align256(m * 8) + align256(m * 4) + 2 * align256(tiles * kRadix * 4) +
+         align256(kRadix * 4);
+}
+
+hipError_t order_queries(const double* q, uint64_t m, int curve, uint32_t* perm, void* scratch,
+                         uint32_t* err, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const uint32_t tile = (uint32_t)sort_tile(m);
+  const uint64_t tiles = (m + tile - 1) / tile;
+  char* p = (char*)scratch;
+  uint64_t* keys_a = (uint64_t*)p;   p += align256(m * 8);
+  uint64_t* keys_b = (uint64_t*)p;   p += align256(m * 8);
+  uint32_t* ids_b = (uint32_t*)p;    p += align256(m * 4);
+  uint32_t* counts = (uint32_t*)p;   p += align256(tiles * kRadix * 4);
+  uint32_t* rel = (uint32_t*)p;      p += align256(tiles * kRadix * 4);
+  uint32_t* dtot = (uint32_t*)p;
+  ProfScope ps("query_order", s);
+  hipError_t e;
+  if (curve == SFC_CURVE_HILBERT)
+    query_keys_tiles<SFC_CURVE_HILBERT><<<(uint32_t)tiles, 256, 0, s>>>(
+        (const double2*)q, m, tile, keys_a, counts, tiles, 48);
+  else
+    query_keys_tiles<SFC_CURVE_MORTON><<<(uint32_t)tiles, 256, 0, s>>>(
+        (const double2*)q, m, tile, keys_a, counts, tiles, 48);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // Two stable passes over the top 16 bits: ids from positions, then perm.
+  for (int pass = 0; pass < 2; ++pass) {
+    const int shift = 48 + 8 * pass;
+    const uint64_t* kin = pass == 0 ? keys_a : keys_b;
+    uint64_t* kout = pass == 0 ? keys_b : keys_a;
+    uint32_t* vout = pass == 0 ? ids_b : perm;
+    if (pass > 0) {
+      tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, ids_b, m, tile, shift, nullptr, counts,
+                                                       tiles);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+#define SFC_LAUNCH(I)                                                                      \
+  launch_scatter<I>(pass == 0, false, false, shift, tiles, kin, ids_b, kout, vout, m, rel, dtot, \
+                    err, nullptr, nullptr, nullptr, curve, nullptr, s)
+    switch (sort_items(m)) {
+      case 16: e = SFC_LAUNCH(16); break;
+      case 12: e = SFC_LAUNCH(12); break;
+      default: e = SFC_LAUNCH(8); break;
+    }
+#undef SFC_LAUNCH
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipStream_t s) {

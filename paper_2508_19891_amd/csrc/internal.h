@@ -60,6 +60,12 @@ hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t*
 // out[i] = xy[ids[i]] for points of dim (2 or 3) doubles.
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n, int dim,
                          hipStream_t s);
+// Order of a batch of m queries (centres clamped into the square) by the
+// top 16 bits of their curve keys, stable: perm[i] = the i-th query in that
+// order.  scratch holds order_scratch_bytes(m); err: device error word.
+size_t order_scratch_bytes(uint64_t m);
+hipError_t order_queries(const double* q, uint64_t m, int curve, uint32_t* perm, void* scratch,
+                         uint32_t* err, hipStream_t s);
 // Early-termination occupancy bitmap (kOccWords words) of n sorted keys.
 hipError_t build_occupancy(const uint64_t* keys, uint64_t n, uint32_t* occ, hipStream_t s);
 
@@ -82,6 +88,8 @@ struct QueryScratch {
   int ss;                 // log2 of the slots per query (2: method's ranges, 3: refined)
   uint64_t* pairs;        // dense (query, cell) work list: 4 * query + cell
   void* qfilt;            // per query: its grid cell and the cell filter's limits (32 B)
+  uint32_t* perm;         // queries in curve order (the search's lane order)
+  void* order_scratch;    // order_scratch_bytes(m)
 };
 constexpr uint64_t kCompactTileRows = 64;           // rows of 64 candidates per tile
 constexpr uint64_t kCompactChunkTiles = 1ull << 19; // tiles per launch

@@ -349,6 +349,7 @@ __global__ __launch_bounds__(256) void ranges_search(
     const uint64_t* __restrict__ pair_total, const uint32_t* __restrict__ qset,
     const uint64_t* __restrict__ set_off, uint32_t n_sets, uint32_t* __restrict__ slot_begin, uint32_t* __restrict__ slot_count,
     uint32_t* __restrict__ slot_rows, uint32_t* counters, unsigned long long* cand_total,
+    const uint32_t* __restrict__ perm,
     uint64_t* __restrict__ dbg_lo, uint64_t* __restrict__ dbg_hi, uint64_t* __restrict__ dbg_b,
     uint64_t* __restrict__ dbg_e, uint32_t* __restrict__ dbg_nr) {
   constexpr bool LEARNED = SEARCH == 1;
@@ -371,9 +372,12 @@ __global__ __launch_bounds__(256) void ranges_search(
     r = (int)(pr & 3);
     sidx = pr;
   } else {
-    j = g >> 2;
+    // perm non-null: the queries in curve order, so that the searches of a
+    // workgroup meet in the same lines of the key array.
+    const uint64_t jj = g >> 2;
+    j = perm && jj < m ? perm[jj] : jj;
     r = (int)(g & 3);
-    sidx = g;
+    sidx = 4 * j + (uint64_t)r;
   }
 
   uint64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0, klo = 0, khi = 0;
@@ -1292,7 +1296,8 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) 
 size_t query_scratch_bytes(uint64_t m, uint32_t slots) {
   const uint64_t nseg = slots * m;
   return align256(nseg * 4) * 3 + align256((nseg + 1) * 8) + scan_scratch_bytes(nseg) +
-         align256(64) + align256(4 * m * 8) + align256(m * 32);
+         align256(64) + align256(4 * m * 8) + align256(m * 32) + align256(m * 4) +
+         order_scratch_bytes(m);
 }
 
 void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slots) {
@@ -1305,7 +1310,9 @@ void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slot
   qs->scan_tmp = (uint64_t*)p;    p += scan_scratch_bytes(nseg);
   qs->counters = (uint32_t*)p;    p += align256(64);
   qs->pairs = (uint64_t*)p;       p += align256(4 * m * 8);
-  qs->qfilt = p;
+  qs->qfilt = p;                  p += align256(m * 32);
+  qs->perm = (uint32_t*)p;        p += align256(m * 4);
+  qs->order_scratch = p;
   qs->ss = 2;
 }
 
@@ -1317,6 +1324,9 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
          align256(tiles * kTileRows * 16) + align256((tiles * kTileRows + 1) * 8) +
          scan_scratch_bytes(tiles);
 }
+
+// Batches from this size on are ordered along the curve before the search.
+constexpr uint64_t kOrderMin = 1u << 14;
 
 hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                          uint64_t n, int curve, bool refine, uint32_t refine_min, bool ball,
@@ -1360,13 +1370,22 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
     pairs = qs.pairs;
     pair_total = (const uint64_t*)total;
   }
+  // Large batches over the whole array are searched in curve order.
+  const uint32_t* perm = nullptr;
+  if (!dense && !dbg_lo && !qset && m >= kOrderMin) {
+    if ((e = order_queries(q, m, curve, qs.perm, qs.order_scratch, qs.counters + 2, s)) !=
+        hipSuccess)
+      return e;
+    perm = qs.perm;
+  }
   {
     ProfScope ps(learned ? "ranges_learned" : stree ? "ranges_stree" : "ranges_search", s);
 #define SFC_RANGES(C, R, S)                                                                  \
   ranges_search<C, R, S><<<blocks, 256, 0, s>>>(                                              \
       (const double2*)q, delta, m, keys, n, lv, sv, refine_min, ball, dbg_lo ? nullptr : occ, \
       pairs, pair_total, qset, set_off, n_sets, qs.slot_begin,                                \
-      qs.slot_count, qs.slot_rows, qs.counters, cand, dbg_lo, dbg_hi, dbg_b, dbg_e, dbg_nr)
+      qs.slot_count, qs.slot_rows, qs.counters, cand, perm, dbg_lo, dbg_hi, dbg_b, dbg_e,     \
+      dbg_nr)
 #define SFC_RANGES_R(C, R)                      \
   if (learned) SFC_RANGES(C, R, 1);             \
   else if (stree) SFC_RANGES(C, R, 2);          \
