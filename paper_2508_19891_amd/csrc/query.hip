@@ -776,7 +776,7 @@ __global__ __launch_bounds__(256) void cells_pack(
     const uint32_t* __restrict__ occ, const uint32_t* __restrict__ qset, uint32_t n_sets,
     uint64_t* __restrict__ pairs, unsigned long long* pair_total, uint32_t* __restrict__ slot_begin,
     uint32_t* __restrict__ slot_count, uint32_t* __restrict__ slot_rows, uint32_t* counters,
-    unsigned long long* pruned_total) {
+    unsigned long long* pruned_total, const uint32_t* __restrict__ perm) {
   __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
   __shared__ uint32_t s_cnt[4];
   __shared__ uint32_t s_pr[4];
@@ -784,7 +784,10 @@ __global__ __launch_bounds__(256) void cells_pack(
   if (CURVE == SFC_CURVE_HILBERT)
     for (int i = threadIdx.x; i < 1024; i += 256) lut[i] = kHilbertLutConst.v[i];
   __syncthreads();
-  const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  // perm non-null: queries in curve order, so that the listed pairs (and
+  // the searches that follow them) are too.
+  const uint64_t jj = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t j = perm && jj < m ? perm[jj] : jj;
   uint32_t nr = 0, pr = 0;
   bool bad = false;
   if (j < m) {
@@ -1351,13 +1354,22 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   unsigned long long* total = (unsigned long long*)(qs.counters + 14);   // cleared above
   const uint64_t* pairs = nullptr;
   const uint64_t* pair_total = nullptr;
+  // Large batches over the whole array are searched in curve order (with
+  // early termination: listed in that order).
+  const uint32_t* perm = nullptr;
+  if (!dbg_lo && !qset && m >= kOrderMin) {
+    if ((e = order_queries(q, m, curve, qs.perm, qs.order_scratch, qs.counters + 2, s)) !=
+        hipSuccess)
+      return e;
+    perm = qs.perm;
+  }
   if (dense) {
     const uint32_t qb = (uint32_t)((m + 255) / 256);
     ProfScope ps("cells_pack", s);
 #define SFC_CELLS(C, R)                                                                    \
   cells_pack<C, R><<<qb, 256, 0, s>>>((const double2*)q, delta, m, occ, qset, n_sets,       \
                                       qs.pairs, total, qs.slot_begin, qs.slot_count,        \
-                                      qs.slot_rows, qs.counters, cand + 3)
+                                      qs.slot_rows, qs.counters, cand + 3, perm)
     if (curve == SFC_CURVE_HILBERT) {
       if (refine) SFC_CELLS(SFC_CURVE_HILBERT, true);
       else SFC_CELLS(SFC_CURVE_HILBERT, false);
@@ -1370,22 +1382,14 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
     pairs = qs.pairs;
     pair_total = (const uint64_t*)total;
   }
-  // Large batches over the whole array are searched in curve order.
-  const uint32_t* perm = nullptr;
-  if (!dense && !dbg_lo && !qset && m >= kOrderMin) {
-    if ((e = order_queries(q, m, curve, qs.perm, qs.order_scratch, qs.counters + 2, s)) !=
-        hipSuccess)
-      return e;
-    perm = qs.perm;
-  }
   {
     ProfScope ps(learned ? "ranges_learned" : stree ? "ranges_stree" : "ranges_search", s);
 #define SFC_RANGES(C, R, S)                                                                  \
   ranges_search<C, R, S><<<blocks, 256, 0, s>>>(                                              \
       (const double2*)q, delta, m, keys, n, lv, sv, refine_min, ball, dbg_lo ? nullptr : occ, \
       pairs, pair_total, qset, set_off, n_sets, qs.slot_begin,                                \
-      qs.slot_count, qs.slot_rows, qs.counters, cand, perm, dbg_lo, dbg_hi, dbg_b, dbg_e,     \
-      dbg_nr)
+      qs.slot_count, qs.slot_rows, qs.counters, cand, dense ? nullptr : perm, dbg_lo, dbg_hi, \
+      dbg_b, dbg_e, dbg_nr)
 #define SFC_RANGES_R(C, R)                      \
   if (learned) SFC_RANGES(C, R, 1);             \
   else if (stree) SFC_RANGES(C, R, 2);          \
