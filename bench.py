@@ -83,9 +83,10 @@ def load_traffic(kernel: str, source: str):
 
 
 def cpu_baseline(wl, curve: int, m_sample: int):
-    """The oracle timed on the host: full construction (single thread) and a
-    bounded sample of the queries (contiguous slices over the host threads);
-    the query time is scaled to the full batch."""
+    """The oracle timed on the host: full construction (single thread) and
+    the first m_sample queries (by default the whole batch; contiguous slices
+    over the host threads), the query time scaled to the full batch when the
+    sample is smaller; the single-thread rate on an eighth of the sample."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
@@ -108,8 +109,10 @@ def cpu_baseline(wl, curve: int, m_sample: int):
         "cores": threads,
         "kind": "oracle",
         "sample": (f"oracle build of all {wl.points.shape[0]} points on 1 thread "
-                   f"({t_build:.2f} s) + the first {m_sample} of {m} queries on {threads} "
-                   f"threads ({t_query:.2f} s, scaled x{m / m_sample:g})"),
+                   f"({t_build:.2f} s) + " +
+                   (f"all {m} queries" if m_sample == m else f"the first {m_sample} of {m} queries")
+                   + f" on {threads} threads ({t_query:.2f} s"
+                   + (")" if m_sample == m else f", scaled x{m / m_sample:g})")),
         "reported_sample": int(off[-1]),
         "queries_per_s_1_thread": m1 / t_query1,
         "queries_per_s_all_threads": m_sample / t_query,
@@ -447,7 +450,7 @@ def main():
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--m-log2", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=17)
+    ap.add_argument("--cpu-sample-log2", type=int, default=20)
     ap.add_argument("--only-refined", action="store_true",
                     help="time only the refined range mode (for profiler runs)")
     ap.add_argument("--no-batched", action="store_true",
