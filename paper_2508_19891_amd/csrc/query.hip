@@ -1143,13 +1143,11 @@ __global__ __launch_bounds__(256) void compact_test(
 // every row of the tile (row_pre, chunk-relative index; the entry one past a
 // tile's last row is the next tile's first, and the one at the batch's last
 // row + 1 is the total).  Output-driven: one lane per reported id rather than
-// one per candidate (about a quarter of the candidates are reported).  Output
-// o of a tile lies in the row r with pre[r] <= o < pre[r + 1] (found by
-// binary search over the tile's 65 prefix counts in LDS), at the
-// (o - pre[r])-th set bit of the row's mask (found by halving the mask by
-// population counts); its id is read at the row's first candidate position
-// plus that bit.  Writes are contiguous; a tile with few hits costs few
-// lanes.
+// one per candidate.  The waves first map every output o of the tile to its
+// row and its candidate within the row (two byte maps in LDS, written by the
+// lanes whose bit is set); the output's id is then read at the row's first
+// candidate position plus that candidate.  Writes are contiguous; a tile
+// with few hits costs few lanes.
 __global__ __launch_bounds__(256) void compact_write_out(
     const uint32_t* __restrict__ ids, uint64_t npts, const uint4* __restrict__ row_meta,
     const uint64_t* __restrict__ total_rows_dev, uint64_t rbase, uint64_t row_end,
@@ -1158,7 +1156,10 @@ __global__ __launch_bounds__(256) void compact_write_out(
   __shared__ uint64_t s_mask[kTileRows];
   __shared__ uint32_t s_pre[kTileRows + 1];
   __shared__ uint32_t s_base[kTileRows];
-  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  __shared__ uint8_t s_row[kTileRows * 64];   // output o of the tile: its row
+  __shared__ uint8_t s_bit[kTileRows * 64];   // and its candidate within the row
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint64_t below = lanemask_lt();
   const uint64_t total_all = *total_rows_dev;
   const uint64_t total_rows = total_all < row_end ? total_all : row_end;
   const uint64_t ntiles = total_rows > rbase ? (total_rows - rbase + kTileRows - 1) / kTileRows : 0;
@@ -1187,27 +1188,22 @@ __global__ __launch_bounds__(256) void compact_write_out(
       row_pre[tile * kTileRows + tid] = prefix + s_pre[tid];
     const uint32_t hits = s_pre[kTileRows];
     if (write_ids) {
-      for (uint32_t o = tid; o < hits; o += 256) {
-        uint32_t r = 0;   // last row with s_pre[r] <= o
-#pragma unroll
-        for (uint32_t step = 32; step >= 1; step >>= 1)
-          if (s_pre[r + step] <= o) r += step;
-        uint32_t k = o - s_pre[r];
-        uint64_t mk = s_mask[r];
-        uint32_t bit = 0;
-#pragma unroll
-        for (uint32_t w = 32; w >= 1; w >>= 1) {
-          const uint64_t low = mk & ((1ull << w) - 1);
-          const uint32_t c = (uint32_t)__popcll(low);
-          if (k >= c) {
-            k -= c;
-            bit += w;
-            mk >>= w;
-          } else {
-            mk = low;
-          }
+      // Each wave maps the outputs of 16 rows (lane l of row r, if its bit
+      // is set, is output s_pre[r] + the set bits below it), then every
+      // output finds its row and candidate with one read of each map.
+      for (uint32_t k = 0; k < kTileRows / 4; ++k) {
+        const uint32_t r = wv * (kTileRows / 4) + k;
+        const uint64_t mk = s_mask[r];
+        if ((mk >> lane) & 1ull) {
+          const uint32_t o = s_pre[r] + (uint32_t)__popcll(mk & below);
+          s_row[o] = (uint8_t)r;
+          s_bit[o] = (uint8_t)lane;
         }
-        const uint64_t p64 = (uint64_t)s_base[r] + bit;
+      }
+      __syncthreads();
+      for (uint32_t o = tid; o < hits; o += 256) {
+        const uint32_t r = s_row[o];
+        const uint64_t p64 = (uint64_t)s_base[r] + s_bit[o];
         const uint64_t opos = prefix + o;
         if (p64 < npts && opos < cap) out_ids[opos] = ids[p64];
       }
