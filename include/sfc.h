@@ -198,6 +198,16 @@ sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta,
  * sfc_retire: epochs below `epoch` (<= current) are no longer queried.
  */
 sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_out);
+/* Inserts `runs` consecutive batches (1 <= runs <= 65536) with one sort and
+   one merge, with the same result as sfc_insert on each batch in order:
+   run_off (host, runs + 1 offsets into xy, run_off[0] = 0, non-decreasing)
+   delimits them; xy (device, run_off[runs] points, interleaved) holds them;
+   run r's points get the ids that follow the previous runs' and are
+   inserted at epoch e + 1 + r (e the current epoch), and the epoch advances
+   by `runs`, an empty run included.  ids_out as sfc_insert.  SFC_ERR_DOMAIN
+   leaves h unchanged. */
+sfc_status sfc_insert_runs(sfc_index* h, const double* xy, const uint64_t* run_off, uint32_t runs,
+                           uint32_t* ids_out);
 sfc_status sfc_erase(sfc_index* h, const uint32_t* ids, uint64_t k, uint64_t* erased_out);
 sfc_status sfc_query_epochs(sfc_index* h, const double* q, const double* delta,
                             const uint32_t* qepoch, uint64_t m, uint64_t* offsets,

@@ -21,6 +21,8 @@
 // Test switches of the construction's sort (process-wide): always the plain
 // radix sort, and whether the last build fell back to it.
 static std::atomic<bool> g_force_plain_sort{false};
+// Most batches one sfc_insert_runs call takes.
+constexpr uint32_t kMaxInsertRuns = 1u << 16;
 static std::atomic<int> g_last_sort_fallback{0};
 
 // ---- caching device allocator -----------------------------------------------
@@ -1661,33 +1663,47 @@ sfc_status maybe_compact(sfc_index* h) {
 
 extern "C" {
 
-sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_out) {
-  if (!h || (k > 0 && !xy)) return SFC_ERR_INVALID;
-  if (h->n_sets || dim_of(h) == 3) return SFC_ERR_UNSUPPORTED;
-  if (k == 0) return SFC_OK;
+namespace {
+
+// Inserts `runs` consecutive batches of xy (host offsets run_off, runs + 1
+// of them) as one sort and one merge; run r's points are inserted at epoch
+// h->epoch + 1 + r, and the index's epoch advances by `runs`.
+sfc_status insert_impl(sfc_index* h, const double* xy, uint64_t k, const uint64_t* run_off,
+                       uint32_t runs, uint32_t* ids_out) {
+  if (k == 0 && runs <= 1) return SFC_OK;
   if ((uint64_t)h->next_id + k > 0xFFFFFFFEull) return SFC_ERR_INVALID;
-  if (h->epoch >= 0xFFFFFFFEu) return SFC_ERR_UNSUPPORTED;
+  if ((uint64_t)h->epoch + runs >= 0xFFFFFFFEull) return SFC_ERR_UNSUPPORTED;
+  if (k == 0) {   // runs of no points: the epochs still advance
+    h->epoch += runs;
+    if (!h->hold) h->oldest = h->epoch;
+    return SFC_OK;
+  }
   sfc_status st = ensure_dynamic(h);
   if (st == SFC_OK) st = ensure_key_of(h, (uint64_t)h->next_id + k);
   if (st == SFC_OK) st = ensure_spare(h, h->n + k);
   if (st != SFC_OK) return st;
   const size_t sb = sfc::build_scratch_bytes(k) + 256;
-  char* batch = (char*)h->alloc.get(align256(k * 8) + align256(k * 4) + align256(k * 16) + sb);
+  const size_t rb = runs > 1 ? align256((runs + 1) * 8) : 0;
+  char* batch =
+      (char*)h->alloc.get(align256(k * 8) + align256(k * 4) + align256(k * 16) + sb + rb);
   if (!batch) return SFC_ERR_NOMEM;
   uint64_t* bkeys = (uint64_t*)batch;
   uint32_t* bids = (uint32_t*)(batch + align256(k * 8));
   double* bxy = (double*)(batch + align256(k * 8) + align256(k * 4));
   void* scratch = batch + align256(k * 8) + align256(k * 4) + align256(k * 16);
   uint32_t* err = (uint32_t*)((char*)scratch + sb - 256);
+  uint64_t* roff = runs > 1 ? (uint64_t*)((char*)scratch + sb) : nullptr;
   const uint32_t ep = h->epoch + 1;
   // Sort the batch, merge it into the spare run; the swap happens only when
   // the batch's coordinates were all in the domain.
   hipError_t e = sfc::fill_u32(err, 0, 1, h->stream);
+  if (e == hipSuccess && roff)
+    e = hipMemcpyAsync(roff, run_off, (runs + 1) * 8, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess)
     e = sfc::sort_build(xy, k, h->curve, bkeys, bids, bxy, scratch, err, h->stream);
   if (e == hipSuccess)
     e = sfc::merge_runs(current_run(h), h->n, bkeys, bids, bxy, k, h->next_id, ep, h->spare,
-                        h->key_of, h->stream);
+                        h->key_of, h->stream, roff, runs > 1 ? runs : 0);
   if (e == hipSuccess && ids_out) e = sfc::fill_iota(ids_out, k, h->next_id, h->stream);
   uint64_t w = 0;
   if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
@@ -1701,20 +1717,42 @@ sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_
   swap_runs(h);
   h->n += k;
   h->next_id += (uint32_t)k;
-  h->epoch = ep;
-  h->max_ins = ep;
+  h->epoch = ep + (runs > 1 ? runs - 1 : 0);
+  h->max_ins = h->epoch;
   if (h->occ) SFC_TRY(sfc::build_occupancy(h->keys, h->n, h->occ, h->stream));
   if (h->stree_ready) {
     st = stree_refresh(h);
     if (st != SFC_OK) return st;
   }
-  if (!h->hold) h->oldest = ep;
+  if (!h->hold) h->oldest = h->epoch;
   ++h->generation;
   ++h->merges;
   const uint64_t compactions = h->compactions;
   st = maybe_compact(h);   // a compaction refits the learned leaves itself
   if (st == SFC_OK && h->compactions == compactions) st = refit_leaves(h);
   return st;
+}
+
+}  // namespace
+
+sfc_status sfc_insert(sfc_index* h, const double* xy, uint64_t k, uint32_t* ids_out) {
+  if (!h || (k > 0 && !xy)) return SFC_ERR_INVALID;
+  if (h->n_sets || dim_of(h) == 3) return SFC_ERR_UNSUPPORTED;
+  if (k == 0) return SFC_OK;
+  const uint64_t off[2] = {0, k};
+  return insert_impl(h, xy, k, off, 1, ids_out);
+}
+
+sfc_status sfc_insert_runs(sfc_index* h, const double* xy, const uint64_t* run_off, uint32_t runs,
+                           uint32_t* ids_out) {
+  if (!h || !run_off || runs == 0 || runs > kMaxInsertRuns || run_off[0] != 0)
+    return SFC_ERR_INVALID;
+  for (uint32_t r = 0; r < runs; ++r)
+    if (run_off[r + 1] < run_off[r]) return SFC_ERR_INVALID;
+  const uint64_t k = run_off[runs];
+  if (k > 0 && !xy) return SFC_ERR_INVALID;
+  if (h->n_sets || dim_of(h) == 3) return SFC_ERR_UNSUPPORTED;
+  return insert_impl(h, xy, k, run_off, runs, ids_out);
 }
 
 sfc_status sfc_erase(sfc_index* h, const uint32_t* ids, uint64_t k, uint64_t* erased_out) {

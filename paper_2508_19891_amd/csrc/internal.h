@@ -177,10 +177,13 @@ struct EpochView {
   uint32_t epoch = 0;
 };
 // Merges the stored run (n entries) with a sorted batch (k entries, local
-// ids bids) into `out` (n + k entries).
+// ids bids) into `out` (n + k entries).  The batch's entries are inserted at
+// `epoch`; with run_off (device, runs + 1 offsets of local ids, run_off[0] =
+// 0), those of run r at epoch + r.
 hipError_t merge_runs(const Run& stored, uint64_t n, const uint64_t* bkeys, const uint32_t* bids,
                       const double* bxy, uint64_t k, uint32_t id_base, uint32_t epoch,
-                      const Run& out, uint64_t* key_of, hipStream_t s);
+                      const Run& out, uint64_t* key_of, hipStream_t s,
+                      const uint64_t* run_off = nullptr, uint32_t runs = 0);
 hipError_t record_keys(const uint64_t* keys, const uint32_t* ids, uint64_t n, uint64_t* key_of,
                        hipStream_t s);
 hipError_t erase_entries(const uint32_t* del, uint64_t k, uint32_t next_id, const uint64_t* key_of,

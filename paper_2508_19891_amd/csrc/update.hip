@@ -90,12 +90,15 @@ __global__ __launch_bounds__(kThreads) void merge_stored(
 }
 
 // Batch element j (sorted, local id bids[j]) goes to j + #{stored keys <=
-// its key}; it gets the id id_base + bids[j], the insert epoch `epoch`, and
-// its key is recorded under its id for later erasure.
+// its key}; it gets the id id_base + bids[j], the insert epoch `epoch` (with
+// run offsets: epoch + the index of the run holding its local id, runs
+// inserted one after another), and its key is recorded under its id for
+// later erasure.
 __global__ __launch_bounds__(kThreads) void merge_batch(
     const uint64_t* __restrict__ keys, uint64_t n, const uint64_t* __restrict__ bkeys,
     const uint32_t* __restrict__ bids, const double2* __restrict__ bxy, uint64_t k,
-    uint32_t id_base, uint32_t epoch, uint64_t* __restrict__ okeys, uint32_t* __restrict__ oids,
+    uint32_t id_base, uint32_t epoch, const uint64_t* __restrict__ run_off, uint32_t runs,
+    uint64_t* __restrict__ okeys, uint32_t* __restrict__ oids,
     double2* __restrict__ oxy, uint32_t* __restrict__ oins, uint32_t* __restrict__ oera,
     uint64_t* __restrict__ ocells, uint64_t* __restrict__ key_of) {
   const uint64_t j = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -106,10 +109,24 @@ __global__ __launch_bounds__(kThreads) void merge_batch(
   const uint64_t o = j + upper_bound_u64(keys, 0, n, key);
   const uint32_t id = id_base + lid;
   const double2 p = bxy[j];
+  uint32_t ep = epoch;
+  if (run_off) {   // last run r with run_off[r] <= lid
+    uint32_t lo = 0, len = runs;
+    while (len > 0) {
+      const uint32_t h = len >> 1;
+      if (run_off[lo + h] <= lid) {
+        lo += h + 1;
+        len -= h + 1;
+      } else {
+        len = h;
+      }
+    }
+    ep = epoch + (lo - 1);
+  }
   okeys[o] = key;
   oids[o] = id;
   oxy[o] = p;
-  oins[o] = epoch;
+  oins[o] = ep;
   oera[o] = kLiveEpoch;
   if (ocells) ocells[o] = pack_cell2(p.x, p.y);
   key_of[id] = key;
@@ -238,7 +255,8 @@ uint32_t grid_for(uint64_t count, uint64_t per_block) {
 
 hipError_t merge_runs(const Run& stored, uint64_t n, const uint64_t* bkeys, const uint32_t* bids,
                       const double* bxy, uint64_t k, uint32_t id_base, uint32_t epoch,
-                      const Run& out, uint64_t* key_of, hipStream_t s) {
+                      const Run& out, uint64_t* key_of, hipStream_t s, const uint64_t* run_off,
+                      uint32_t runs) {
   if (n > 0) {
     ProfScope ps("merge_stored", s);
     merge_stored<<<grid_for(n, kMergeTile), kThreads, 0, s>>>(
@@ -250,8 +268,8 @@ hipError_t merge_runs(const Run& stored, uint64_t n, const uint64_t* bkeys, cons
   if (k > 0) {
     ProfScope ps("merge_batch", s);
     merge_batch<<<grid_for(k, kThreads), kThreads, 0, s>>>(
-        stored.keys, n, bkeys, bids, (const double2*)bxy, k, id_base, epoch, out.keys, out.ids,
-        (double2*)out.xy, out.ins, out.era, out.cells, key_of);
+        stored.keys, n, bkeys, bids, (const double2*)bxy, k, id_base, epoch, run_off, runs,
+        out.keys, out.ids, (double2*)out.xy, out.ins, out.era, out.cells, key_of);
     return hipGetLastError();
   }
   return hipSuccess;

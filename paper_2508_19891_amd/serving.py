@@ -2,7 +2,8 @@
 
 Requests arrive in stream order at their arrival times.  Each tick takes
 the requests that have arrived (at most ``max_tick`` of them), applies the
-inserts and erases one by one in stream order, and answers the queries of
+inserts and erases in stream order (consecutive inserts together, as one
+sort and one merge that gives each its own epoch), and answers the queries of
 all of them in one batch, each query at the epoch it was admitted at (the
 epoch after the updates that arrived before it), so that batching never
 changes an answer.  Epochs older than every query still running are
@@ -83,6 +84,34 @@ class Run:
         return self.done - self.arrival
 
 
+class _Inserts:
+    """Insert requests of a tick not yet applied: consecutive ones (their
+    points are consecutive slices of the insert pool) go to the index as one
+    sfc_insert_runs call, one sort and one merge, with the epochs and ids
+    they would get one by one.  Applied before an erase and before the
+    tick's queries are answered."""
+
+    def __init__(self, index, pools):
+        self.index, self.pools, self.reqs = index, pools, []
+
+    def add(self, r: int, a: int, k: int):
+        if self.reqs and self.reqs[-1][1] + self.reqs[-1][2] != a:
+            raise ValueError("insert requests must take consecutive pool slices")
+        self.reqs.append((r, a, k))
+
+    def flush(self) -> list:
+        if not self.reqs:
+            return []
+        a0 = self.reqs[0][1]
+        off = [0]
+        for _, _, k in self.reqs:
+            off.append(off[-1] + k)
+        self.index.insert_runs(self.pools.inserts[a0:a0 + off[-1]], off, want_ids=False)
+        done = [r for r, _, _ in self.reqs]
+        self.reqs = []
+        return done
+
+
 def serve(index: sfc.Index, trace: ServingTrace, pools: Pools, rate: float = float("inf"),
           max_tick: int = 16, record: bool = False, out_ids: torch.Tensor | None = None,
           slots: int = 0, slot_queries: int = 1 << 20, slot_ids: int = 1 << 26,
@@ -117,18 +146,22 @@ def serve(index: sfc.Index, trace: ServingTrace, pools: Pools, rate: float = flo
         j = int(np.searchsorted(arrival, now, side="right"))
         j = min(max(j, i + 1), i + max_tick)
         pending = []
+        inserts = _Inserts(index, pools)
         for r in range(i, j):
             a, k = int(trace.start[r]), int(trace.size[r])
             if trace.kind[r] == QUERY:
                 pending.append((r, epoch))
             elif trace.kind[r] == INSERT:
-                index.insert(pools.inserts[a:a + k], want_ids=False)
+                inserts.add(r, a, k)
                 epoch += 1
-                done[r] = time.perf_counter() - t0
             else:
+                for ri in inserts.flush():
+                    done[ri] = time.perf_counter() - t0
                 index.erase(pools.erase_ids[a:a + k])
                 epoch += 1
                 done[r] = time.perf_counter() - t0
+        for ri in inserts.flush():
+            done[ri] = time.perf_counter() - t0
         if pending:
             qs, ds, es = [], [], []
             for r, e in pending:
@@ -235,18 +268,22 @@ def _serve_async(index, trace, pools, rate, max_tick, record, nslots, slot_queri
         j = int(np.searchsorted(arrival, now, side="right"))
         j = min(max(j, i + 1), i + max_tick)
         pending = []
+        inserts = _Inserts(index, pools)
         for r in range(i, j):
             a, k = int(trace.start[r]), int(trace.size[r])
             if trace.kind[r] == QUERY:
                 pending.append((r, epoch, k))
             elif trace.kind[r] == INSERT:
-                index.insert(pools.inserts[a:a + k], want_ids=False)
+                inserts.add(r, a, k)
                 epoch += 1
-                done[r] = time.perf_counter() - t0
             else:
+                for ri in inserts.flush():
+                    done[ri] = time.perf_counter() - t0
                 index.erase(pools.erase_ids[a:a + k])
                 epoch += 1
                 done[r] = time.perf_counter() - t0
+        for ri in inserts.flush():
+            done[ri] = time.perf_counter() - t0
         # an update waits for all queued work, so slots may have finished
         reap(False)
         while pending:

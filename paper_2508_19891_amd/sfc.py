@@ -45,7 +45,7 @@ EXPORTS = [
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
     "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric", "sfc_set_cell_filter",
-    "sfc_cells_copy", "sfc_debug_sort_path",
+    "sfc_cells_copy", "sfc_debug_sort_path", "sfc_insert_runs",
 ]
 
 NPARAM = 1153
@@ -193,6 +193,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_debug_chunk_tiles.restype = i32
     L.sfc_insert.argtypes = [vp, vp, u64, vp]
     L.sfc_insert.restype = i32
+    L.sfc_insert_runs.argtypes = [vp, vp, ctypes.POINTER(u64), u32, vp]
+    L.sfc_insert_runs.restype = i32
     L.sfc_erase.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
     L.sfc_erase.restype = i32
     L.sfc_query_epochs.argtypes = [vp, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(u64)]
@@ -463,6 +465,23 @@ class Index:
         k = xy.shape[0]
         ids = torch.empty(k, dtype=torch.int32, device=self.device) if want_ids else None
         _check(lib().sfc_insert(self.handle, _ptr(xy), k, _ptr(ids)), "sfc_insert")
+        return ids
+
+    def insert_runs(self, xy: torch.Tensor, run_off, want_ids: bool = True):
+        """Inserts consecutive batches xy[run_off[r]:run_off[r+1]] as if by one
+        insert call each, in order (one sort, one merge); returns the ids
+        (int32 tensor) or None."""
+        xy = _dev(xy, torch.float64, "xy")
+        if xy.ndim != 2 or xy.shape[1] != self.dim:
+            raise ValueError(f"xy must have shape (k, {self.dim})")
+        off = [int(v) for v in run_off]
+        if len(off) < 2 or off[-1] != xy.shape[0]:
+            raise ValueError("run_off must end at the number of points")
+        arr = (ctypes.c_uint64 * len(off))(*off)
+        ids = (torch.empty(xy.shape[0], dtype=torch.int32, device=self.device)
+               if want_ids else None)
+        _check(lib().sfc_insert_runs(self.handle, _ptr(xy), arr, len(off) - 1, _ptr(ids)),
+               "sfc_insert_runs")
         return ids
 
     def erase(self, ids: torch.Tensor) -> int:
