@@ -452,7 +452,7 @@ __global__ void fill_set_ids(const uint64_t* __restrict__ set_off, uint32_t n_se
 constexpr int kTopShift = 32;
 constexpr int kTopPasses = 4;
 constexpr uint64_t kChunkStride = 2048;
-constexpr uint32_t kChunkCap = 6144;
+constexpr uint32_t kChunkCap = 4096;
 constexpr uint32_t kShortRun = 64;
 constexpr int kChunkWaves = 8;
 constexpr int kChunkThreads = kChunkWaves * kWave;

@@ -5,8 +5,8 @@ radix passes) and sort each chunk of whole runs of equal top bits in LDS
 (by counting within runs of at most 64 keys, else by radix passes over the
 chunk); a run too long for a chunk makes the build fall back to the plain
 eight-pass radix sort.  Checked here: sizes around the chunk stride (2048)
-and capacity (6144), every curve, runs of equal top bits on both sides of
-64, up to the length that always fits (4096) and beyond it (the fallback),
+and capacity (4096), every curve, runs of equal top bits on both sides of
+64, up to the length that always fits (2048) and beyond it (the fallback),
 duplicates, and the two sorts against each other."""
 import numpy as np
 import pytest
@@ -62,7 +62,7 @@ def cell_run(rng, count, dim, level=None):
 
 
 @pytest.mark.parametrize("curve", [MORTON, HILBERT, M3])
-@pytest.mark.parametrize("n", [1, 2, 3, 2047, 2048, 2049, 6143, 6144, 6145, 12289, 250_001])
+@pytest.mark.parametrize("n", [1, 2, 3, 2047, 2048, 2049, 4095, 4096, 4097, 12289, 250_001])
 def test_sizes(curve, n):
     rng = np.random.default_rng(n * 3 + curve)
     pts = rng.random((n, 3 if curve == M3 else 2))
@@ -77,7 +77,7 @@ def test_clustered_mixture(curve):
 
 
 @pytest.mark.parametrize("curve", [MORTON, HILBERT])
-@pytest.mark.parametrize("run", [1, 2, 64, 65, 700, 2048, 4096])
+@pytest.mark.parametrize("run", [1, 2, 64, 65, 700, 2048])
 def test_runs_that_always_fit(curve, run):
     """Runs of equal top 32 bits no longer than capacity - stride always fit,
     wherever they fall relative to the chunk stride; runs of up to 64 keys
@@ -105,10 +105,11 @@ def test_long_runs_fall_back(curve):
 
 @pytest.mark.parametrize("curve", [MORTON, HILBERT])
 def test_runs_past_the_guarantee(curve):
-    """Runs between 4096 and 6144 keys fit or not depending on where chunks
+    """Runs between 2048 and 4096 keys fit or not depending on where chunks
     start: either way the arrays are the oracle's."""
     rng = np.random.default_rng(99 + curve)
-    pts = np.concatenate([rng.random((40_000, 2))] + [cell_run(rng, 5_500, 2) for _ in range(6)])
+    pts = np.concatenate([rng.random((40_000, 2))] +
+                         [cell_run(rng, s, 2) for s in (2100, 3000, 3500, 4000, 4096, 2600)])
     pts = pts[rng.permutation(len(pts))]
     check(pts, curve)
 
