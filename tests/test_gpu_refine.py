@@ -86,3 +86,36 @@ def test_tiny_radii_keep_every_sub_cell(curve):
     want = expect(pts, q, ds, curve, L2)
     got = run(pts, q, ds, curve, L2, refine=True)
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+@pytest.mark.parametrize("metric", [L2, LINF])
+def test_three_dimensions_crowded_boundary_band(metric):
+    """Crowded cubes split into runs of the children that meet the box:
+    points within a few units in the last place of the sphere (or the cube
+    window) around each query, in a dense background, refined or not."""
+    rng = np.random.default_rng(60 + metric)
+    qs = rng.uniform(0.05, 0.95, (200, 3))
+    ds = np.exp(rng.uniform(np.log(3e-3), np.log(5e-2), 200))
+    band = []
+    for q, d in zip(qs, ds):
+        for _ in range(30):
+            k = rng.integers(-6, 7)
+            if metric == L2:
+                v = rng.normal(size=3)
+                v /= np.linalg.norm(v)
+            else:
+                v = rng.uniform(-1, 1, 3)
+                v[rng.integers(3)] = rng.choice([-1.0, 1.0])
+            p = q + d * (1 + k * 2.0 ** -52) * v
+            if np.all(p >= 0) and np.all(p < 1):
+                band.append(p)
+    pts = np.concatenate([rng.random((300_000, 3)), np.array(band)])
+    pts = pts[rng.permutation(len(pts))]
+    index = oracle.build3(pts)
+    want = oracle.query3(index, qs, ds, nthreads=8, metric=metric)
+    for refine in (True, False):
+        idx = sfc.Index(dev(pts), sfc.MORTON3, refine=refine, metric=metric)
+        off, ids = idx.query(dev(qs), dev(ds))
+        idx.close()
+        assert np.array_equal(off.cpu().numpy().view(np.uint64), want[0])
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), want[1])
