@@ -461,7 +461,7 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs->counters + 2, h->stream));
   uint64_t* pin = sfc::pinned_scratch();
-  SFC_TRY(hipMemcpyAsync(pin, qs->row_off + (m << qs->ss), 8, hipMemcpyDeviceToHost, h->stream));
+  SFC_TRY(hipMemcpyAsync(pin, qs->row_off + m, 8, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 48, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
   const uint32_t err = ((const uint32_t*)(pin + 1))[2];

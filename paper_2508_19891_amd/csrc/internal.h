@@ -81,7 +81,7 @@ struct QueryScratch {
   uint32_t* slot_begin;   // per query slot: first sorted index of its range
   uint32_t* slot_count;   // per query slot: its number of candidates
   uint32_t* slot_rows;    // per query slot: rows of 64 candidates
-  uint64_t* row_off;      // exclusive scan of slot_rows (+ total at the end)
+  uint64_t* row_off;      // per query: its first row (+ the total at [m])
   uint64_t* scan_tmp;     // scan partials
   uint32_t* counters;     // [2] error word; u64 at [4]: candidates, [6]: learned
                           // endpoints, [8]: learned fallbacks
@@ -89,6 +89,7 @@ struct QueryScratch {
   uint64_t* pairs;        // dense (query, cell) work list: 4 * query + cell
   void* qfilt;            // per query: its grid cell and the cell filter's limits (32 B)
   uint32_t* perm;         // queries in curve order (the search's lane order)
+  uint32_t* qrows;        // per query: the rows of its slots
   void* order_scratch;    // order_scratch_bytes(m)
 };
 constexpr uint64_t kCompactTileRows = 64;           // rows of 64 candidates per tile

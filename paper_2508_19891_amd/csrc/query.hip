@@ -861,22 +861,46 @@ constexpr int kTileRows = 4 * kRows * kIters;             // 64 rows per tile
 constexpr uint64_t kWaveRows = (uint64_t)kRows * kIters;  // rows per wave
 static_assert(kCompactTileRows == (uint64_t)kTileRows, "tile shape");
 
+// Rows of each query: the sum over its 2^ss slots (the scan that follows
+// gives every query its first row).
+__global__ __launch_bounds__(256) void query_rows(const uint32_t* __restrict__ slot_rows,
+                                                  uint64_t m, int ss, uint32_t* __restrict__ qrows) {
+  const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= m) return;
+  uint32_t t = 0;
+  for (uint32_t k = 0; k < (1u << ss); ++k) t += slot_rows[(j << ss) + k];
+  qrows[j] = t;
+}
+
 // Row descriptors of a launch's rows [rbase, rend): for row r of slot s,
 // (first sorted index of the row, number of valid lanes, query index).  One
-// block per 256 slots; the block's rows are spread over its threads and each
-// finds its slot by a binary search in LDS.
+// block per 256 slots (whole queries: 2^ss slots each); a slot's first row is
+// its query's first row (row_off, one entry per query) plus the rows of the
+// query's earlier slots.  The block's rows are spread over its threads and
+// each finds its slot by a binary search in LDS.
 __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ row_off,
+                                                   const uint32_t* __restrict__ slot_rows,
                                                    const uint32_t* __restrict__ slot_begin,
                                                    const uint32_t* __restrict__ slot_count,
                                                    uint64_t nseg, int ss, uint64_t rbase,
                                                    uint64_t row_end, uint4* __restrict__ row_meta) {
   __shared__ uint64_t st[257];
-  const uint64_t total = row_off[nseg];
+  __shared__ uint32_t sr[256];
+  const uint64_t m = nseg >> ss;
+  const uint64_t total = row_off[m];
   const uint64_t rend = total < row_end ? total : row_end;
   const uint64_t s0 = (uint64_t)blockIdx.x * 256;
   const uint32_t tid = threadIdx.x;
-  st[tid] = row_off[s0 + tid < nseg ? s0 + tid : nseg];
-  if (tid == 0) st[256] = row_off[s0 + 256 < nseg ? s0 + 256 : nseg];
+  sr[tid] = s0 + tid < nseg ? slot_rows[s0 + tid] : 0u;
+  __syncthreads();
+  if (s0 + tid < nseg) {
+    uint64_t off = row_off[(s0 + tid) >> ss];
+    for (uint32_t t = tid & ~((1u << ss) - 1); t < tid; ++t) off += sr[t];
+    st[tid] = off;
+  } else {
+    st[tid] = total;
+  }
+  if (tid == 0) st[256] = s0 + 256 < nseg ? row_off[(s0 + 256) >> ss] : total;
   __syncthreads();
   const uint64_t r0 = st[0] > rbase ? st[0] : rbase;
   const uint64_t r1 = st[256] < rend ? st[256] : rend;
@@ -1213,7 +1237,7 @@ __global__ __launch_bounds__(256) void compact_write_out(
 }
 
 // The CSR offsets of the queries whose first row lies in this chunk: query
-// j's offset is the output position of row row_off[j << ss] (a query with no
+// j's offset is the output position of row row_off[j] (a query with no
 // rows takes the position of the next row, trailing ones the total).  One
 // thread per query; the chunk owns rows [rbase, rend) below the total and,
 // if the total falls in (rbase, rend], the total itself.
@@ -1226,7 +1250,7 @@ __global__ __launch_bounds__(256) void query_offsets(
   const bool owns_total = total == 0 ? rbase == 0 : (rbase < total && total <= rend);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= m; j += stride) {
-    uint64_t r = row_off[j << ss];
+    uint64_t r = row_off[j];
     if (r > total) r = total;   // past the capacity (flagged as overflow)
     if (r == total) {
       if (owns_total) offsets[j] = total == 0 ? 0 : row_pre[r - rbase];
@@ -1296,7 +1320,7 @@ size_t query_scratch_bytes(uint64_t m, uint32_t slots) {
   const uint64_t nseg = slots * m;
   return align256(nseg * 4) * 3 + align256((nseg + 1) * 8) + scan_scratch_bytes(nseg) +
          align256(64) + align256(4 * m * 8) + align256(m * 32) + align256(m * 4) +
-         order_scratch_bytes(m);
+         order_scratch_bytes(m) + align256(m * 4);
 }
 
 void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slots) {
@@ -1311,6 +1335,7 @@ void query_scratch_carve(void* base, uint64_t m, QueryScratch* qs, uint32_t slot
   qs->pairs = (uint64_t*)p;       p += align256(4 * m * 8);
   qs->qfilt = p;                  p += align256(m * 32);
   qs->perm = (uint32_t*)p;        p += align256(m * 4);
+  qs->qrows = (uint32_t*)p;       p += align256(m * 4);
   qs->order_scratch = p;
   qs->ss = 2;
 }
@@ -1322,6 +1347,18 @@ size_t compact_scratch_bytes(uint64_t total_rows) {
   return align256(tiles * kTileRows * 8) + align256(tiles * 4) + 2 * align256((tiles + 1) * 8) +
          align256(tiles * kTileRows * 16) + align256((tiles * kTileRows + 1) * 8) +
          scan_scratch_bytes(tiles);
+}
+
+// Every query's first row (row_off[j], and the total at row_off[m]): its
+// slots' rows summed, then scanned over the queries.
+hipError_t scan_query_rows(QueryScratch& qs, uint64_t m, hipStream_t s) {
+  {
+    ProfScope ps("scan", s);
+    query_rows<<<(uint32_t)((m + 255) / 256), 256, 0, s>>>(qs.slot_rows, m, qs.ss, qs.qrows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return scan_excl(qs.qrows, qs.row_off, m, nullptr, qs.scan_tmp, s);
 }
 
 // Batches from this size on are ordered along the curve before the search.
@@ -1406,7 +1443,7 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
 #undef SFC_RANGES
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return scan_excl(qs.slot_rows, qs.row_off, m << qs.ss, nullptr, qs.scan_tmp, s);
+  return scan_query_rows(qs, m, s);
 }
 
 // Blocks of the compaction kernels (grid-stride over tiles beyond this).
@@ -1439,7 +1476,7 @@ hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, cons
 #undef SFC_R3
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return scan_excl(qs.slot_rows, qs.row_off, m << qs.ss, nullptr, qs.scan_tmp, s);
+  return scan_query_rows(qs, m, s);
 }
 
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
@@ -1451,7 +1488,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
   hipError_t e;
   if (m == 0) return fill_u64(offsets, 0, 1, s);
   const uint64_t nseg = m << qs.ss;
-  const uint64_t* total_dev = qs.row_off + nseg;
+  const uint64_t* total_dev = qs.row_off + m;
   // Rows are processed in chunks of at most kCompactChunkTiles tiles.
   // Host-sized: max_rows is the exact number of rows.  Device-sized: max_rows
   // is a capacity; each kernel reads the row count on the device, chunks past
@@ -1498,7 +1535,8 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
     if (!write_only) {
       ProfScope ps("expand_rows", s);
       expand_rows<<<(uint32_t)((nseg + 255) / 256), 256, 0, s>>>(
-          qs.row_off, qs.slot_begin, qs.slot_count, nseg, qs.ss, rbase, row_end, meta);
+          qs.row_off, qs.slot_rows, qs.slot_begin, qs.slot_count, nseg, qs.ss, rbase, row_end,
+          meta);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!write_only) {
