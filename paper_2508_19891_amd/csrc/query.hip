@@ -133,8 +133,12 @@ __device__ int query_ranges(const uint16_t* lut, double qx, double qy, double d,
   const uint32_t cx0 = (uint32_t)(lx >> L), cx1 = (uint32_t)(hx >> L);
   const uint32_t cy0 = (uint32_t)(ly >> L), cy1 = (uint32_t)(hy >> L);
   int k = 0;
-  for (uint32_t cx = cx0; cx <= cx1; ++cx) {
-    for (uint32_t cy = cy0; cy <= cy1; ++cy) {
+  // Offsets within the box (at most one cell per axis past the first): a
+  // coordinate loop ending at cx1 inclusive would wrap at 2^32 - 1, the
+  // single cell of a box clamped to the last grid column and row.
+  for (uint32_t ax = 0; ax <= cx1 - cx0; ++ax) {
+    for (uint32_t ay = 0; ay <= cy1 - cy0; ++ay) {
+      const uint32_t cx = cx0 + ax, cy = cy0 + ay;
       const uint64_t key = cell_key<CURVE>(lut, cx << L, cy << L) & ~span;
       if (occ && !cell_occupied(occ, L, key)) {
         ++*pruned;
@@ -228,8 +232,12 @@ __device__ int query_cells(const uint16_t* lut, double qx, double qy, double d, 
   }
   const uint64_t span = (1ull << (2 * L)) - 1;
   int k = 0;
-  for (uint32_t x = (uint32_t)(lx >> L); x <= (uint32_t)(hx >> L); ++x) {
-    for (uint32_t y = (uint32_t)(ly >> L); y <= (uint32_t)(hy >> L); ++y) {
+  const uint32_t x0 = (uint32_t)(lx >> L), y0 = (uint32_t)(ly >> L);
+  const uint32_t nx = (uint32_t)(hx >> L) - x0, ny = (uint32_t)(hy >> L) - y0;
+  // Offsets within the box, as in query_ranges (no wrap at 2^32 - 1).
+  for (uint32_t ax = 0; ax <= nx; ++ax) {
+    for (uint32_t ay = 0; ay <= ny; ++ay) {
+      const uint32_t x = x0 + ax, y = y0 + ay;
       const uint64_t key = cell_key<CURVE>(lut, x << L, y << L) & ~span;
       if (occ && !cell_occupied(occ, L, key)) {
         ++*pruned;

@@ -119,3 +119,30 @@ def test_three_dimensions_crowded_boundary_band(metric):
         idx.close()
         assert np.array_equal(off.cpu().numpy().view(np.uint64), want[0])
         assert np.array_equal(ids.cpu().numpy().view(np.uint32), want[1])
+
+
+TOP = 1 - 2.0 ** -53
+
+
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_far_corner_last_cell(curve):
+    """Queries at and just past the square's far corner with tiny radii: their
+    widened boxes clamp to the single last grid cell (2^32 - 1, 2^32 - 1),
+    whose cell loop must stop there; every search, refined or not, with early
+    termination and square windows."""
+    rng = np.random.default_rng(70 + curve)
+    pts = np.concatenate([rng.random((5000, 2)),
+                          [[TOP, TOP]] * 3 + [[TOP, 0.5], [0.5, TOP], [TOP, TOP - 2.0 ** -40]]])
+    qs = np.array([[1.0, 1.0], [1.0, 1.0], [1.0, 1.0], [1.0 + 2.0 ** -33, 1.0], [1.0, TOP],
+                   [TOP, 1.0], [1.5, 1.5], [1.0, 0.5], [0.3, 0.6]])
+    ds = np.array([0.0, 2.0 ** -40, 2.0 ** -30, 2.0 ** -35, 2.0 ** -45, 0.0, 0.1, 1e-12, 0.01])
+    for metric in (L2, LINF):
+        want = expect(pts, qs, ds, curve, metric)
+        combos = [dict(refine=rf, early_term=et) for rf in (False, True) for et in (False, True)]
+        combos += [dict(refine=True, search=sfc.LEARNED), dict(refine=True, search=sfc.STREE)]
+        for kw in combos:
+            idx = sfc.Index(dev(pts), curve, metric=metric, **kw)
+            off, ids = idx.query(dev(qs), dev(ds))
+            idx.close()
+            assert np.array_equal(off.cpu().numpy().view(np.uint64), want[0]), kw
+            assert np.array_equal(ids.cpu().numpy().view(np.uint32), want[1]), kw

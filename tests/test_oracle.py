@@ -459,6 +459,30 @@ def test_far_query_large_radius_widening(curve):
     assert np.array_equal(oracle.canonical(*got), oracle.canonical(*ref))
 
 
+TOP = 1 - 2.0 ** -53
+# Queries at and just past the far corner of the square: their widened boxes
+# clamp to the single last grid cell (2^32 - 1, 2^32 - 1), at level 0.
+CORNER_PTS = np.array([[TOP, TOP]] * 3 + [[TOP, 0.5], [0.5, TOP], [TOP, TOP - 2.0 ** -40]])
+CORNER_Q = np.array([[1.0, 1.0], [1.0, 1.0], [1.0, 1.0], [1.0 + 2.0 ** -33, 1.0], [1.0, TOP],
+                     [TOP, 1.0], [1.5, 1.5], [1.0, 0.5]])
+CORNER_D = np.array([0.0, 2.0 ** -40, 2.0 ** -30, 2.0 ** -35, 2.0 ** -45, 0.0, 0.1, 1e-12])
+
+
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_far_corner_single_last_cell(curve):
+    """The box of a query at (1, 1) with a tiny radius is the last grid cell
+    alone; the three copies of (TOP, TOP) lie 2^-52.5 away, inside radii
+    2^-40 and 2^-30 and outside 0 and 2^-45."""
+    assert oracle.box(1.0, 1.0, 0.0) == (M32, M32, M32, M32)
+    assert len(oracle.ranges(1.0, 1.0, 0.0, curve)) == 1
+    rng = np.random.default_rng(5 + curve)
+    pts = np.concatenate([rng.random((2000, 2)), CORNER_PTS])
+    ref = oracle.brute(pts, CORNER_Q, CORNER_D)
+    assert np.diff(ref[0].astype(np.int64)).tolist() == [0, 3, 4, 0, 3, 0, 0, 1]
+    got = oracle.query(oracle.build(pts, curve), CORNER_Q, CORNER_D, curve)
+    assert np.array_equal(oracle.canonical(*got), oracle.canonical(*ref))
+
+
 # ---- square windows (the experiments' queries, Sec. 4) ---------------------------------------
 
 LINF = oracle.LINF
