@@ -231,30 +231,50 @@ __device__ int query_cells(const uint16_t* lut, double qx, double qy, double d, 
     return 1;
   }
   const uint64_t span = (1ull << (2 * L)) - 1;
-  int k = 0;
   const uint32_t x0 = (uint32_t)(lx >> L), y0 = (uint32_t)(ly >> L);
   const uint32_t nx = (uint32_t)(hx >> L) - x0, ny = (uint32_t)(hy >> L) - y0;
-  // Offsets within the box, as in query_ranges (no wrap at 2^32 - 1).
-  for (uint32_t ax = 0; ax <= nx; ++ax) {
-    for (uint32_t ay = 0; ay <= ny; ++ay) {
-      const uint32_t x = x0 + ax, y = y0 + ay;
-      const uint64_t key = cell_key<CURVE>(lut, x << L, y << L) & ~span;
-      if (occ && !cell_occupied(occ, L, key)) {
+  // The at most 2 x 2 cells at offsets (i >> 1, i & 1) within the box (no
+  // coordinate loop that could wrap at 2^32 - 1), absent or pruned ones
+  // keyed 2^64 - 1, then sorted by a fixed network of compare-exchanges on
+  // (key, offset index): every array index is static, so the cells stay in
+  // registers.  A present key equals 2^64 - 1 only at level 0, where the box
+  // is one cell (index 0) and no exchange moves it on a tie.
+  uint64_t key[4];
+  uint32_t id[4];
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    id[i] = (uint32_t)i;
+    key[i] = ~0ull;
+    if ((uint32_t)(i >> 1) <= nx && (uint32_t)(i & 1) <= ny) {
+      const uint64_t kk = cell_key<CURVE>(lut, (x0 + (uint32_t)(i >> 1)) << L,
+                                          (y0 + (uint32_t)(i & 1)) << L) & ~span;
+      if (occ && !cell_occupied(occ, L, kk)) {
         ++*pruned;
-        continue;
+      } else {
+        key[i] = kk;
+        ++k;
       }
-      int j = k++;
-      for (; j > 0 && lo[j - 1] > key; --j) {
-        lo[j] = lo[j - 1];
-        hi[j] = hi[j - 1];
-        cx[j] = cx[j - 1];
-        cy[j] = cy[j - 1];
-      }
-      lo[j] = key;
-      hi[j] = key | span;
-      cx[j] = x;
-      cy[j] = y;
     }
+  }
+  constexpr int kNet[5][2] = {{0, 1}, {2, 3}, {0, 2}, {1, 3}, {1, 2}};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const int a = kNet[c][0], b = kNet[c][1];
+    const bool sw = key[a] > key[b];
+    const uint64_t ka = key[a], kb = key[b];
+    const uint32_t ia = id[a], ib = id[b];
+    key[a] = sw ? kb : ka;
+    key[b] = sw ? ka : kb;
+    id[a] = sw ? ib : ia;
+    id[b] = sw ? ia : ib;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    lo[i] = key[i];
+    hi[i] = key[i] | span;
+    cx[i] = x0 + (id[i] >> 1);
+    cy[i] = y0 + (id[i] & 1u);
   }
   return k;
 }
@@ -348,10 +368,10 @@ __device__ __forceinline__ bool disc_meets(double qx, double qy, double d, int64
 //     and each run is located by two searches inside the cell's index range.
 //     Only points that the exact test rejects are dropped, so the reported
 //     set and its order are unchanged.
-// Five waves per SIMD (at most 102 registers; the refined variants spill a
-// few values held across the searches): the chains of dependent probes need
-// the extra waves in flight more than those values need registers (0.77 vs
-// 0.73 ms for a batch of 2^20 queries over 2^24 keys).
+// At least five waves per SIMD (at most 102 registers): the chains of
+// dependent probes need waves in flight.  The binary-search variants take 62
+// registers (eight waves) now that query_cells indexes its arrays statically;
+// the learned-index variants take 92.
 template <int CURVE, bool REFINE, int SEARCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void ranges_search(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
@@ -681,9 +701,9 @@ __device__ int query_cubes3(double qx, double qy, double qz, double d, uint64_t 
 // (four slots per cube, 32 per query), each found by two searches inside the
 // cube's index range.  The reported ids and their order do not change.
 template <int SEARCH, bool REFINE>
-// Five waves per SIMD, as ranges_search (the refined variants keep their
-// per-cube arrays in scratch then): 2.03 -> 1.89 ms binary, 1.67 -> 1.36 ms
-// with the static search tree, for 2^20 queries over 2^24 keys.
+// Five waves per SIMD (the refined variants then keep their per-cube arrays
+// in scratch): 2.03 -> 1.89 ms binary, 1.67 -> 1.36 ms with the static
+// search tree, for 2^20 queries over 2^24 keys.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void ranges_search3(
     const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, StreeView sv,
