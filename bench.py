@@ -88,7 +88,9 @@ def cpu_baseline(wl, curve: int, m_sample: int):
     over the host threads), the query time scaled to the full batch when the
     sample is smaller; the single-thread rate on an eighth of the sample."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    # every core this process may run on: the box's CPU share as its harness
+    # states it (OMP_NUM_THREADS), else the affinity mask
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
     idx = oracle.build(wl.points, curve)
     t_build = time.perf_counter() - t0
@@ -342,9 +344,9 @@ def paper_windows_bench(args, sfc, workload, torch):
                              "paper_cpu_s": paper_s[cname][i],
                              "paper_cpu_s_over_gpu_s": paper_s[cname][i] / (ms * 1e-3)})
                 del out_ids
-                log(f"windows {cname} refine={refine} side={side:g}: {ms:.3f} ms, "
-                    f"{total} reported")
             out[f"{cname}_{'refined' if refine else 'ranges'}"] = rows
+            log(f"windows {cname} refine={refine}: " +
+                " ".join(f"{r['ms_per_batch']:.3g}" for r in rows) + " ms")
             idx.close()
     del pts, q
     torch.cuda.empty_cache()
@@ -466,6 +468,8 @@ def main():
                     help="skip the insert/erase/query serving measurement")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-n-log2", type=int, default=25)
+    ap.add_argument("--detail-out", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="file that receives every leg's figures (empty: none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (counter calibration)")
     args = ap.parse_args()
@@ -479,14 +483,20 @@ def main():
     from paper_2508_19891_amd import sfc, workload
 
     if args.copy_probe:
-        # A plain copy kernel of known size: 2^30 bytes read and 2^30 written per launch.
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        # Counter calibration: kernels of known traffic per launch, three
+        # launches each -- a write-only fill of 2^30 bytes, a read-only sum
+        # over 2^30 bytes (one scalar written), and a copy of 2^30 bytes.
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")
         b = torch.empty_like(a)
+        for _ in range(3):
+            a.fill_(1.0)
+        for _ in range(3):
+            s = a.sum()
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        del a, b
-        log("copy probe: 3 x 2^30 B device-to-device")
+        del a, b, s
+        log("counter probe: 3 x fill, sum and copy of 2^30 B")
 
     # The attainable HBM rate: a plain device-to-device copy of 2^30 bytes
     # (2^31 bytes moved per copy), timed over 10 copies.
@@ -533,7 +543,6 @@ def main():
 
         for i in range(args.warmup):
             step()
-            log(f"warmup {i + 1}/{args.warmup}")
         # Per-kernel breakdown: the same steps with HIP events around every
         # launch (the events add gaps between kernels, so these steps are
         # not the timed ones).
@@ -550,25 +559,32 @@ def main():
         sfc.profile_reset()
         sfc.profile_only(dom)
         sfc.profile_enable(True)
+        # one event pair per step on the library's stream (torch's current
+        # stream): the median step beside the whole timed region's mean
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        ev[0].record()
         for i in range(args.steps):
             step()
+            ev[i + 1].record()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sfc.profile_enable(False)
         sfc.profile_only(None)
         kern_dom = sfc.profile_read()
+        per_step = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
         log(f"timed {args.steps} steps in {dt:.3f} s")
         if linfo is not None:
             stats = dict(stats, learned=linfo)
-        return dt / args.steps * 1e3, kern, stats, total, (dom, kern_dom.get(dom))
+        return (dt / args.steps * 1e3, kern, stats, total, (dom, kern_dom.get(dom)),
+                float(np.median(per_step)))
 
     if args.only_refined:
         ms_paper, kern_paper, stats_paper = float("nan"), {}, {"candidates": None}
     else:
-        ms_paper, kern_paper, stats_paper, _, _ = run_mode(False)
-    ms_step, kern, stats, total, (dom_timed, dom_kern) = run_mode(True)
+        ms_paper, kern_paper, stats_paper, _, _, _ = run_mode(False)
+    ms_step, kern, stats, total, (dom_timed, dom_kern), ms_median = run_mode(True)
     def query_only(search: int, cells: bool = True):
         """One index (built and, for the learned search, fitted once); the
         timed steps are query batches only.  cells=False: every candidate
@@ -681,21 +697,11 @@ def main():
                                                        "chunk_sort")
                            else "query.hip")
 
-    line = {
-        "metric": "queries/s + reported pts/s at n=2^24, learned vs bsearch index, % HBM peak",
-        "value": m / (ms_step * 1e-3),
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
+    detail = {
         "config": {"workload": wl.name + "_hilbert", "n": n, "m": m, "curve": "hilbert",
                    "search": "binary", "ranges": "refined", "step": "build + one query batch"},
+        "ms_per_step": ms_step,
+        "ms_per_step_median": ms_median,
         "learned_vs_bsearch": lvb,
         "cell_filter": None if args.only_refined else cell_filter,
         "paper_ranges": {"queries_per_s": m / (ms_paper * 1e-3), "ms_per_step": ms_paper,
@@ -706,50 +712,132 @@ def main():
         "reported_per_step": rep,
         "candidates_per_step": cand,
         "candidates_per_report": cand / max(rep, 1),
-        "build_ms_per_step": sum(kern[k][1] for k in ("keygen_tiles", "tile_hist", "digit_scan", "scatter_pass",
-                                                      "chunk_sort")
+        "build_ms_per_step": sum(kern[k][1] for k in ("keygen_tiles", "tile_hist", "digit_scan",
+                                                      "scatter_pass", "chunk_firsts", "chunk_sort")
                                  if k in kern) / args.steps,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items()},
-        "roofline": {
-            "kernel": dom,
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "copy_gbs": copy_gbs,   # attainable: a plain device copy on this GPU
-        },
+        "kernels_algorithmic_bytes_per_step": algo,
         "kernels_algorithmic_gbs": kern_gbs,
+        "copy_gbs": copy_gbs,
     }
+    # The dominant kernel's roofline on its own design's bytes, and on the
+    # scan bytes the method's description gives (16 B per candidate for the
+    # test pass plus 12 B per query: the coordinates of every candidate), for
+    # comparison; the latter can exceed 1 because the kernel decides most
+    # candidates from their 8-byte grid cell and never reads those bytes.
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "bytes_per_launch": bytes_per_launch, "copy_gbs": copy_gbs}
+    if dom == "compact_test":
+        survey_bytes = (16 * cand + 12 * m) / launches_per_step
+        roofline["frac_16B_per_candidate"] = (survey_bytes / (d_ms / d_launch * 1e-3) / 1e9
+                                              / HBM_PEAK_GBS)
+    detail["roofline"] = roofline
     if dom != "compact_test" and "compact_test" in kern:
-        # Another kernel dominates (at this shape the search, a chain of
-        # dependent probes): the scan's test pass, the main stream over the
-        # candidates, is reported beside it (timed by the HIP events of the
-        # profiled steps).
+        # Another kernel dominates: the scan's test pass, the main stream
+        # over the candidates, is reported beside it (timed by the HIP events
+        # of the profiled steps).
         c_launch, c_ms = kern["compact_test"]
         c_bytes = algo["compact_test"] / (c_launch / args.steps)
         c_gbs = c_bytes / (c_ms / c_launch * 1e-3) / 1e9
-        line["roofline_scan"] = {"kernel": "compact_test", "bound": "hbm", "achieved": c_gbs,
-                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": c_gbs / HBM_PEAK_GBS,
-                                 "traffic": load_traffic("compact_test", "query.hip")}
+        detail["roofline_scan"] = {"kernel": "compact_test", "bound": "hbm", "achieved": c_gbs,
+                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": c_gbs / HBM_PEAK_GBS,
+                                   "traffic": load_traffic("compact_test", "query.hip")}
     if not args.no_batched and not args.only_refined:
-        line["batched_sets"] = batched_sets_bench(args, sfc, workload, torch)
+        detail["batched_sets"] = batched_sets_bench(args, sfc, workload, torch)
     if not args.no_early_term and not args.only_refined:
-        line["early_termination"] = early_term_bench(args, sfc, workload, torch, pts)
+        detail["early_termination"] = early_term_bench(args, sfc, workload, torch, pts)
     if not args.no_windows and not args.only_refined:
-        line["paper_windows"] = paper_windows_bench(args, sfc, workload, torch)
+        detail["paper_windows"] = paper_windows_bench(args, sfc, workload, torch)
     if not args.no_3d and not args.only_refined:
-        line["three_d"] = three_d_bench(args, sfc, workload, torch)
+        detail["three_d"] = three_d_bench(args, sfc, workload, torch)
     if not args.no_learned_large and not args.only_refined:
-        line["learned_large"] = learned_large_bench(args, sfc, workload, torch)
+        detail["learned_large"] = learned_large_bench(args, sfc, workload, torch)
     if not args.no_serving and not args.only_refined:
-        line["serving"] = serving_bench(args, sfc, workload, torch)
+        detail["serving"] = serving_bench(args, sfc, workload, torch)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
-        line["cpu_baseline"] = cpu_baseline(wl, curve, min(m, 1 << args.cpu_sample_log2))
-    print(json.dumps(line), flush=True)
+        detail["cpu_baseline"] = cpu_baseline(wl, curve, min(m, 1 << args.cpu_sample_log2))
+
+    line = headline(args, detail, n, m, ms_step, ms_median)
+    if args.detail_out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail_out)), exist_ok=True)
+        with open(args.detail_out, "w") as f:
+            json.dump(detail, f, indent=1)
+        line["detail"] = os.path.relpath(os.path.abspath(args.detail_out), ROOT)
+    print(json.dumps(line, separators=(",", ":")), flush=True)
+
+
+def _r(v, digits: int = 4):
+    """A float rounded to `digits` significant digits (None stays None)."""
+    if v is None or not isinstance(v, float) or not math.isfinite(v):
+        return v
+    return float(f"{v:.{digits}g}")
+
+
+def headline(args, detail: dict, n: int, m: int, ms_step: float, ms_median: float) -> dict:
+    """The one JSON line the bench prints last: the metric, its workload,
+    the dominant kernel's roofline, the oracle's rate on the host, and short
+    summaries of the learned-versus-binary and early-termination legs (the
+    full figures go to the detail file)."""
+    rl = detail["roofline"]
+    out = {
+        "metric": "queries/s + reported pts/s at n=2^24, learned vs bsearch index, % HBM peak",
+        "value": _r(m / (ms_step * 1e-3), 6),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": _r(ms_step, 5),
+        "ms_per_step_median": _r(ms_median, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": detail["config"],
+        "reported_pts_per_s": _r(detail["reported_pts_per_s"]),
+        "candidates_per_report": _r(detail["candidates_per_report"]),
+        "build_ms": _r(detail["build_ms_per_step"]),
+        "roofline": {k: _r(v) for k, v in rl.items()},
+    }
+    if "roofline_scan" in detail:
+        rs = detail["roofline_scan"]
+        out["roofline_scan"] = {k: _r(rs[k]) for k in ("kernel", "achieved", "frac", "traffic")}
+    lvb = detail.get("learned_vs_bsearch")
+    if lvb:
+        s = {"n": n, "search_ms_learned": _r(lvb["search_ms_learned"]),
+             "search_ms_bsearch": _r(lvb["search_ms_bsearch"]),
+             "search_ms_stree": _r(lvb["search_ms_stree"]),
+             "ms_per_batch_learned": _r(lvb["ms_per_batch_learned"]),
+             "ms_per_batch_bsearch": _r(lvb["ms_per_batch_bsearch"]),
+             "fallbacks": lvb["model"].get("fallbacks_last")}
+        ll = detail.get("learned_large")
+        if ll:
+            s["large"] = {"n": ll["n"], "m": ll["m"],
+                          "search_ms_learned": _r(ll["learned"]["search_ms"]),
+                          "search_ms_bsearch": _r(ll["bsearch"]["search_ms"]),
+                          "ms_per_batch_learned": _r(ll["learned"]["ms_per_batch"]),
+                          "ms_per_batch_bsearch": _r(ll["bsearch"]["ms_per_batch"])}
+        out["learned_vs_bsearch"] = s
+    et = detail.get("early_termination")
+    if et:
+        out["early_termination"] = {"speedup_batch": _r(et["speedup_batch"]),
+                                    "ms_plain": _r(et["plain"]["ms_per_batch"]),
+                                    "ms_early_term": _r(et["early_term"]["ms_per_batch"])}
+    sv = detail.get("serving")
+    if sv:
+        q = sv["queued"]
+        out["serving"] = {"requests": q["saturation"]["requests"],
+                          "requests_per_s": _r(q["saturation"]["requests_per_s"]),
+                          "p50_ms_0.95": _r(q["load_0.95"]["p50_ms"]),
+                          "p99_ms_0.95": _r(q["load_0.95"]["p99_ms"])}
+    cb = detail.get("cpu_baseline")
+    if cb:
+        out["cpu_baseline"] = {"value": _r(cb["value"]), "unit": cb["unit"],
+                               "cores": cb["cores"], "kind": cb["kind"], "sample": cb["sample"]}
+    return out
 
 
 if __name__ == "__main__":

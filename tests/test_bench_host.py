@@ -52,3 +52,53 @@ def test_mixture_density_slices_equal_whole():
     d2 = ((q[:, None, :] - mix.centres[None, :, :]) ** 2).sum(-1)
     g = np.exp(-d2 / (2.0 * mix.sigma ** 2)) / (2.0 * math.pi * mix.sigma ** 2)
     assert np.array_equal(got, (1.0 - mix.frac) + (mix.frac / k) * g.sum(1))
+
+
+def test_headline_is_compact_and_complete():
+    """The bench's last stdout line stays a few KB (the record of a run keeps
+    only the tail of its output) and carries the contract's fields."""
+    import importlib.util
+    import json
+    import types
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    lvb = {"search_ms_learned": 0.5, "search_ms_bsearch": 0.53, "search_ms_stree": 0.52,
+           "ms_per_batch_learned": 1.9, "ms_per_batch_bsearch": 1.95,
+           "model": {"fallbacks_last": 0}}
+    big = {f"k{i}": list(range(50)) for i in range(200)}   # detail that must not leak in
+    load = {"requests": 10000, "requests_per_s": 4000.0, "p50_ms": 4.0, "p99_ms": 12.0}
+    detail = {
+        "config": {"workload": "clustered_n16777216_m1048576_hilbert", "n": 1 << 24,
+                   "m": 1 << 20, "curve": "hilbert", "search": "binary", "ranges": "refined",
+                   "step": "build + one query batch"},
+        "reported_pts_per_s": 6e10, "candidates_per_report": 2.14, "build_ms_per_step": 0.87,
+        "roofline": {"bound": "hbm", "kernel": "compact_test", "achieved": 4430.123456,
+                     "peak": 8000.0, "unit": "GB/s", "frac": 0.5537, "traffic": 3.48e9,
+                     "bytes_per_launch": 3.1e9, "copy_gbs": 4993.0,
+                     "frac_16B_per_candidate": 1.05},
+        "learned_vs_bsearch": lvb,
+        "learned_large": {"n": 1 << 26, "m": 1 << 22, "learned": {"search_ms": 0.9,
+                                                                 "ms_per_batch": 2.8},
+                          "bsearch": {"search_ms": 1.05, "ms_per_batch": 2.98}},
+        "early_termination": {"speedup_batch": 0.92, "plain": {"ms_per_batch": 0.65},
+                              "early_term": {"ms_per_batch": 0.70}},
+        "serving": {"queued": {"saturation": load, "load_0.95": load}},
+        "cpu_baseline": {"value": 2.8e5, "unit": "queries/s", "cores": 16, "kind": "oracle",
+                         "sample": "oracle build of all 16777216 points on 1 thread (3.09 s) + "
+                                   "all 1048576 queries on 16 threads (0.64 s)"},
+        "paper_windows": big,
+    }
+    args = types.SimpleNamespace(steps=20, warmup=5)
+    line = bench.headline(args, detail, 1 << 24, 1 << 20, 2.87, 2.85)
+    text = json.dumps(line, separators=(",", ":"))
+    assert len(text) <= 2048, len(text)
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+                "roofline", "cpu_baseline"):
+        assert key in line, key
+    for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert key in line["roofline"], key
+    for key in ("value", "unit", "cores", "kind", "sample"):
+        assert key in line["cpu_baseline"], key
+    assert line["learned_vs_bsearch"]["large"]["n"] == 1 << 26
