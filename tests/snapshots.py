@@ -1,8 +1,12 @@
 """Host record of an updated index for the GPU update and serving tests:
 which ids each epoch sees, and the oracle's answers over that snapshot."""
+import os
+
 import numpy as np
 
 import oracle
+
+THREADS = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
 
 LIVE = 0xFFFFFFFF
 
@@ -77,7 +81,7 @@ class Model:
                     per_q[j] = np.zeros(0, np.uint32)
                 continue
             off, idx = oracle.query(oracle.build(self.xy[ids], curve), qs[sel], ds[sel], curve,
-                                    nthreads=4, metric=metric)
+                                    nthreads=THREADS, metric=metric)
             for t, j in enumerate(sel):
                 per_q[j] = ids[idx[off[t]:off[t + 1]]].astype(np.uint32)
         offsets = np.zeros(m + 1, np.uint64)
