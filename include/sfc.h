@@ -56,7 +56,9 @@ typedef enum {
   SFC_ERR_NOMEM = -3,    /* a device allocation failed; state unchanged */
   SFC_ERR_CAPACITY = -4, /* output buffer too small; see sfc_query_batch */
   SFC_ERR_DEVICE = -5,   /* a HIP runtime error */
-  SFC_ERR_UNSUPPORTED = -6
+  SFC_ERR_UNSUPPORTED = -6,
+  SFC_ERR_SCRATCH = -7   /* the batch needs more than the fixed scratch of
+                            sfc_query_batch_static */
 } sfc_status;
 
 /* SFC_CURVE_MORTON3: points in [0,1)^3 (x, y, z interleaved, three doubles
@@ -159,6 +161,32 @@ sfc_status sfc_build(const double* xy, uint64_t n, const sfc_options* opt,
 sfc_status sfc_query_batch(sfc_index* h, const double* q, const double* delta,
                            uint64_t m, uint64_t* offsets, uint32_t* ids,
                            uint64_t ids_cap, uint64_t* total_out);
+
+/*
+ * sfc_query_batch without allocating: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results (offsets and
+ * ids bit for bit), errors and stream behaviour as sfc_query_batch, with
+ * these differences:
+ *   - its scratch is a fixed 64 MiB array inside the library, one per device
+ *     (held until the process ends); a batch whose query scratch (about 260
+ *     bytes per query) and compaction scratch (about 32 bytes per row of 64
+ *     candidates, e.g. 2^16 queries with 10^6 rows) exceed it returns
+ *     SFC_ERR_SCRATCH (offsets and ids unspecified);
+ *   - it calls no allocator (no hipMalloc, hipHostMalloc or pool request):
+ *     an index whose candidates must read the points in key order and whose
+ *     points are not gathered yet (cell filter off, before the first
+ *     sfc_query_batch) returns SFC_ERR_UNSUPPORTED;
+ *   - on SFC_ERR_CAPACITY offsets and *total_out are written, but the batch
+ *     is not kept for sfc_query_retry (rerun it with a larger ids buffer);
+ *   - every call on a device shares that device's scratch, which keeps the
+ *     last call's contents: two calls that overlap on one device (other
+ *     threads, other streams) race and give unspecified results.
+ * Point sets and query epochs are not taken (plain batches only).
+ */
+sfc_status sfc_query_batch_static(sfc_index* h, const double* q, const double* delta,
+                                  uint64_t m, uint64_t* offsets, uint32_t* ids,
+                                  uint64_t ids_cap, uint64_t* total_out);
 
 /*
  * Updates (the paper's dynamic variant: Section 2, implementation details,

@@ -436,6 +436,14 @@ uint32_t slots_of(const sfc_index* h) { return dim_of(h) == 3 && h->refine ? 32 
 
 // Runs ranges + searches + scan; on SFC_OK *total_rows holds the number of
 // candidate rows and *total_cand the number of candidates.
+// The same into query scratch at ws (query_scratch_bytes(m, slots_of(h))
+// bytes), reading the counts back through rb (host, 7 words).
+sfc_status run_ranges_into(sfc_index* h, void* ws, uint64_t* rb, const double* q,
+                           const double* delta, const uint32_t* qset, uint64_t m,
+                           sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
+                           uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
+                           uint32_t* dbg_nr, const uint32_t* qepoch);
+
 sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const uint32_t* qset,
                       uint64_t m, sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
                       uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
@@ -443,7 +451,18 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
   h->pending.valid = false;   // the scratch is about to be reused
   sfc_status st = ensure_ws(h, sfc::query_scratch_bytes(m, slots_of(h)));
   if (st != SFC_OK) return st;
-  sfc::query_scratch_carve(h->ws, m, qs, slots_of(h));
+  uint64_t* pin = sfc::pinned_scratch();
+  if (!pin) return SFC_ERR_NOMEM;
+  return run_ranges_into(h, h->ws, pin, q, delta, qset, m, qs, total_rows, total_cand, dbg_lo,
+                         dbg_hi, dbg_b, dbg_e, dbg_nr, qepoch);
+}
+
+sfc_status run_ranges_into(sfc_index* h, void* ws, uint64_t* rb, const double* q,
+                           const double* delta, const uint32_t* qset, uint64_t m,
+                           sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
+                           uint64_t* dbg_lo, uint64_t* dbg_hi, uint64_t* dbg_b, uint64_t* dbg_e,
+                           uint32_t* dbg_nr, const uint32_t* qepoch) {
+  sfc::query_scratch_carve(ws, m, qs, slots_of(h));
   const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted && !qset;
   const sfc::LearnedView lv = h->larr.view();
   const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
@@ -460,7 +479,7 @@ sfc_status run_ranges(sfc_index* h, const double* q, const double* delta, const 
                                dbg_e, dbg_nr, h->stream));
   if (qepoch)
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs->counters + 2, h->stream));
-  uint64_t* pin = sfc::pinned_scratch();
+  uint64_t* pin = rb;
   SFC_TRY(hipMemcpyAsync(pin, qs->row_off + m, 8, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 48, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
@@ -629,6 +648,7 @@ const char* sfc_status_string(sfc_status s) {
     case SFC_ERR_NOMEM: return "out of device memory";
     case SFC_ERR_CAPACITY: return "output buffer too small";
     case SFC_ERR_DEVICE: return "HIP device error";
+    case SFC_ERR_SCRATCH: return "batch needs more than the library's static scratch";
     case SFC_ERR_UNSUPPORTED: return "unsupported";
   }
   return "unknown status";
@@ -946,6 +966,97 @@ sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint6
   h->last.reported = total;
   *total_out = total;
   return SFC_OK;
+}
+
+}  // extern "C"
+
+// ---- query batches in the library's static scratch --------------------------
+
+namespace {
+
+// The scratch of sfc_query_batch_static: a fixed array in the library's code
+// object, one copy per device, held until the process ends.  Host code must
+// not pass the array's name to a kernel or a copy (in host code it names a
+// host-side stand-in): its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch.
+sfc_status static_scratch(void** out) {
+  int dev = 0;
+  SFC_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SFC_ERR_DEVICE;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    SFC_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return SFC_ERR_DEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SFC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sfc_status sfc_query_batch_static(sfc_index* h, const double* q, const double* delta, uint64_t m,
+                                  uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
+                                  uint64_t* total_out) {
+  if (!h || !offsets || !total_out || (m > 0 && (!q || !delta)) || (ids_cap > 0 && !ids))
+    return SFC_ERR_INVALID;
+  if (m > (1ull << 36)) return SFC_ERR_INVALID;
+  // The test pass reads the cells, or the points in key order: gathering
+  // those would allocate.
+  if (!test_cells(h) && !h->xy && h->n > 0) return SFC_ERR_UNSUPPORTED;
+  const size_t qbytes = align256(sfc::query_scratch_bytes(m, slots_of(h)));
+  if (qbytes > kStaticScratchBytes) return SFC_ERR_SCRATCH;
+  void* base = nullptr;
+  {
+    sfc_status st = static_scratch(&base);
+    if (st != SFC_OK) return st;
+  }
+  h->pending.valid = false;   // the handle's kept batch is not this one
+  sfc::QueryScratch qs{};
+  uint64_t total_rows = 0, total_cand = 0;
+  if (m > 0) {
+    uint64_t rb[7];
+    sfc_status st = run_ranges_into(h, base, rb, q, delta, nullptr, m, &qs, &total_rows,
+                                    &total_cand, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr);
+    if (st != SFC_OK) return st;
+  } else {
+    sfc::query_scratch_carve(base, 0, &qs, slots_of(h));
+  }
+  if (qbytes + sfc::compact_scratch_bytes(total_rows) > kStaticScratchBytes)
+    return SFC_ERR_SCRATCH;
+  sfc::EpochView ev;
+  const bool filtered = epoch_view(h, nullptr, &ev);
+  SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->xy_in, test_cells(h), h->ids, h->n, qs,
+                              total_rows, false, (char*)base + qbytes, offsets, ids, ids_cap,
+                              h->metric == SFC_METRIC_LINF, dim_of(h), h->stream,
+                              filtered ? &ev : nullptr));
+  uint64_t tail[3] = {0, 0, 0};   // the total, then the error word's doubleword
+  SFC_TRY(hipMemcpyAsync(&tail[0], offsets + m, 8, hipMemcpyDeviceToHost, h->stream));
+  if (m > 0)
+    SFC_TRY(hipMemcpyAsync(&tail[1], qs.counters, 16, hipMemcpyDeviceToHost, h->stream));
+  SFC_TRY(hipStreamSynchronize(h->stream));
+  if (m > 0 && (((const uint32_t*)&tail[1])[2] & (sfc::kErrLookback | sfc::kErrInternal)))
+    return SFC_ERR_DEVICE;
+  const uint64_t total = tail[0];
+  h->last.queries = m;
+  h->last.candidates = total_cand;
+  h->last.reported = total;
+  h->last.rows = total_rows;
+  h->last.pruned = m > 0 ? h->last_pruned : 0;
+  *total_out = total;
+  return total > ids_cap ? SFC_ERR_CAPACITY : SFC_OK;
 }
 
 sfc_status sfc_query_epochs(sfc_index* h, const double* q, const double* delta,

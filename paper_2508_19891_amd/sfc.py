@@ -22,6 +22,7 @@ SFC_ERR_NOMEM = -3
 SFC_ERR_CAPACITY = -4
 SFC_ERR_DEVICE = -5
 SFC_ERR_UNSUPPORTED = -6
+SFC_ERR_SCRATCH = -7   # more than sfc_query_batch_static's fixed scratch
 
 MORTON = 0
 HILBERT = 1
@@ -45,7 +46,7 @@ EXPORTS = [
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
     "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric", "sfc_set_cell_filter",
-    "sfc_cells_copy", "sfc_debug_sort_path", "sfc_insert_runs",
+    "sfc_cells_copy", "sfc_debug_sort_path", "sfc_insert_runs", "sfc_query_batch_static",
 ]
 
 NPARAM = 1153
@@ -126,6 +127,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_build.restype = i32
     L.sfc_query_batch.argtypes = [vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(u64)]
     L.sfc_query_batch.restype = i32
+    L.sfc_query_batch_static.argtypes = [vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(u64)]
+    L.sfc_query_batch_static.restype = i32
     L.sfc_size.argtypes = [vp]
     L.sfc_size.restype = u64
     L.sfc_index_view.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u64)]
@@ -365,6 +368,26 @@ class Index:
             raise CapacityError(st, "sfc_query_batch", int(total.value))
         _check(st, "sfc_query_batch")
         return offsets, out_ids[: int(total.value)]
+
+    def query_static(self, q: torch.Tensor, delta: torch.Tensor, out_ids: torch.Tensor,
+                     out_offsets: torch.Tensor):
+        """sfc_query_batch_static into caller buffers (the library's fixed
+        scratch, no allocation); returns (offsets, ids[:total])."""
+        q = _dev(q, torch.float64, "q")
+        delta = _dev(delta, torch.float64, "delta")
+        m = q.shape[0]
+        if q.ndim != 2 or q.shape[1] != self.dim or delta.shape != (m,):
+            raise ValueError(f"q must be (m, {self.dim}) and delta (m,)")
+        if out_offsets.numel() < m + 1:
+            raise ValueError("out_offsets must hold m + 1 entries")
+        total = ctypes.c_uint64(0)
+        st = lib().sfc_query_batch_static(self.handle, _ptr(q), _ptr(delta), m,
+                                          _ptr(out_offsets), _ptr(out_ids), out_ids.numel(),
+                                          ctypes.byref(total))
+        if st == SFC_ERR_CAPACITY:
+            raise CapacityError(st, "sfc_query_batch_static", int(total.value))
+        _check(st, "sfc_query_batch_static")
+        return out_offsets[: m + 1], out_ids[: int(total.value)]
 
     def _retry(self, offsets, total, rerun):
         """After SFC_ERR_CAPACITY: an ids buffer of the exact size, filled by
