@@ -407,7 +407,11 @@ def serving_bench(args, sfc, workload, torch):
     """Poisson stream of query / insert / erase batches (40/40/20, sizes
     2^U[10,16]) over 2^25 clustered points, Morton keys, learned search:
     first the saturation throughput (every request queued at time 0), then
-    arrivals at 0.5, 0.8 and 0.95 of it; p50/p99 from arrival to completion."""
+    arrivals at fractions of it; p50/p99 from arrival to completion.  Loops:
+    sync (each tick's batch answered before the next tick), queued (batches
+    queued on the index's stream into three output slots), overlap (batches
+    side by side on three streams with their own scratch, admitted against a
+    2 GiB budget)."""
     from paper_2508_19891_amd import serving
     dev = torch.device("cuda:0")
     trace = workload.serving_trace(n0=1 << args.serving_n_log2, requests=args.serving_requests)
@@ -417,25 +421,30 @@ def serving_bench(args, sfc, workload, torch):
     out_ids = torch.empty(1 << 26, dtype=torch.int32, device=dev)
     out = {"workload": trace.name, "curve": "morton", "search": "learned",
            "mix": "40% query, 40% insert, 20% erase batches of 2^U[10,16]"}
+    kw = {"sync": {}, "queued": {"slots": 3, "slot_queries": 1 << 20, "slot_ids": 1 << 27,
+                                 "slot_rows": 1 << 24},
+          "overlap": {"streams": 3, "budget_bytes": 2 << 30, "slot_queries": 1 << 17}}
 
-    def one(rate, slots):
+    def one(rate, mode):
         idx = sfc.Index(init, sfc.MORTON, search=sfc.LEARNED, refine=True)
         torch.cuda.synchronize()
-        run = serving.serve(idx, trace, pools, rate=rate, out_ids=out_ids, slots=slots,
-                            slot_queries=1 << 20, slot_ids=1 << 27, slot_rows=1 << 24)
+        run = serving.serve(idx, trace, pools, rate=rate, out_ids=out_ids, **kw[mode])
         s = serving.summarize(trace, run)
         s["compactions"] = idx.update_info()["compactions"]
+        if mode == "overlap":
+            s["max_batches_in_flight"] = run.max_batches
+            s["max_bytes_in_flight"] = run.max_in_flight
+            s["requeued"] = run.requeued
         idx.close()
         return s
 
-    # Each tick answered before the next (slots 0), and query batches queued
-    # into three slots while the next arrivals are admitted (slots 3).
-    for mode, slots in (("sync", 0), ("queued", 3)):
-        sat = one(float("inf"), slots)
+    for mode in args.serving_modes.split(","):
+        sat = one(float("inf"), mode)
         res = {"saturation": sat}
-        for f in (0.5, 0.8, 0.95):
+        log(f"serving ({mode}) saturation: {sat['requests_per_s']:.0f} requests/s")
+        for f in (float(x) for x in args.serving_loads.split(",") if x):
             rate = f * sat["requests_per_s"]
-            s = one(rate, slots)
+            s = one(rate, mode)
             s["offered_requests_per_s"] = rate
             res[f"load_{f}"] = s
             log(f"serving ({mode}) at {f} of saturation: p50 {s['p50_ms']:.2f} ms, "
@@ -466,7 +475,15 @@ def main():
                     help="skip the paper's square-window sweep")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the insert/erase/query serving measurement")
-    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-requests", type=int, default=10_000)
+    ap.add_argument("--serving-modes", default="sync,overlap",
+                    help="serving loops to time: sync (each tick answered before the next), "
+                         "queued (batches queued on the index's stream), overlap (batches side "
+                         "by side on their own streams, admitted by memory)")
+    ap.add_argument("--serving-loads", default="0.5,0.8,0.95",
+                    help="offered loads, as fractions of the saturation rate")
+    ap.add_argument("--serving-profile", action="store_true",
+                    help="run the serving leg even with --only-refined (for kernel traces)")
     ap.add_argument("--serving-n-log2", type=int, default=25)
     ap.add_argument("--detail-out", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
                     help="file that receives every leg's figures (empty: none)")
@@ -754,7 +771,7 @@ def main():
         detail["three_d"] = three_d_bench(args, sfc, workload, torch)
     if not args.no_learned_large and not args.only_refined:
         detail["learned_large"] = learned_large_bench(args, sfc, workload, torch)
-    if not args.no_serving and not args.only_refined:
+    if (not args.no_serving and not args.only_refined) or args.serving_profile:
         detail["serving"] = serving_bench(args, sfc, workload, torch)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
@@ -827,12 +844,14 @@ def headline(args, detail: dict, n: int, m: int, ms_step: float, ms_median: floa
                                     "ms_plain": _r(et["plain"]["ms_per_batch"]),
                                     "ms_early_term": _r(et["early_term"]["ms_per_batch"])}
     sv = detail.get("serving")
-    if sv:
-        q = sv["queued"]
-        out["serving"] = {"requests": q["saturation"]["requests"],
-                          "requests_per_s": _r(q["saturation"]["requests_per_s"]),
-                          "p50_ms_0.95": _r(q["load_0.95"]["p50_ms"]),
-                          "p99_ms_0.95": _r(q["load_0.95"]["p99_ms"])}
+    mode = next((k for k in ("overlap", "queued", "sync") if sv and k in sv), None)
+    if mode:
+        q = sv[mode]
+        out["serving"] = {"mode": mode, "requests": q["saturation"]["requests"],
+                          "requests_per_s": _r(q["saturation"]["requests_per_s"])}
+        if "load_0.95" in q:
+            out["serving"]["p50_ms_0.95"] = _r(q["load_0.95"]["p50_ms"])
+            out["serving"]["p99_ms_0.95"] = _r(q["load_0.95"]["p99_ms"])
     cb = detail.get("cpu_baseline")
     if cb:
         out["cpu_baseline"] = {"value": _r(cb["value"]), "unit": cb["unit"],

@@ -275,6 +275,35 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
                            uint64_t* offsets, uint32_t* ids, uint64_t ids_cap, uint32_t* flags);
 
 /*
+ * Query batches that run side by side (the serving setting of Sec. 2.1
+ * "Dynamic implementation", queries interleaved with updates): a batch on a
+ * stream of the caller's choosing, with its scratch in caller memory, so
+ * that several batches over one index are on the device at once.
+ *
+ * sfc_query_scratch_size: *bytes (host) = the scratch one batch of m
+ *   queries with at most max_rows candidate rows needs (about 260 bytes per
+ *   query and 32 per row).
+ * sfc_query_async_on: as sfc_query_async (same q, delta, qepoch, m,
+ *   max_rows, offsets, ids, ids_cap, flags and results), queued on `stream`
+ *   (hipStream_t) after the work already queued on the handle's stream,
+ *   with scratch (device, 256-byte aligned, scratch_bytes >= the size
+ *   above) owned by the call until `stream` has passed the batch.  Batches
+ *   on different streams with different scratch run concurrently.  The
+ *   batch only reads the index: every later call that rewrites or frees the
+ *   index's arrays (inserts, erases, compactions, fits, recorded
+ *   constructions, sfc_free) first makes the handle's stream wait for it, on
+ *   the device.  Errors: SFC_ERR_INVALID (arguments, scratch too small or
+ *   misaligned), SFC_ERR_UNSUPPORTED (point sets), SFC_ERR_NOMEM (the first
+ *   query of an index whose points were not yet gathered in key order).
+ */
+sfc_status sfc_query_scratch_size(const sfc_index* h, uint64_t m, uint64_t max_rows,
+                                  uint64_t* bytes);
+sfc_status sfc_query_async_on(sfc_index* h, void* stream, void* scratch, uint64_t scratch_bytes,
+                              const double* q, const double* delta, const uint32_t* qepoch,
+                              uint64_t m, uint64_t max_rows, uint64_t* offsets, uint32_t* ids,
+                              uint64_t ids_cap, uint32_t* flags);
+
+/*
  * Write pass of the last sfc_query_batch / sfc_query_sets / sfc_query_epochs
  * call on h that returned SFC_ERR_CAPACITY with its test results kept:
  * offsets (device, m+1) and ids (device, ids_cap) as in that call.  Valid

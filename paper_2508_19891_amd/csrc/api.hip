@@ -262,6 +262,11 @@ struct sfc_index {
     sfc::QueryScratch qs{};
   } pending;
   uint64_t merges = 0, compactions = 0;
+  // Query batches running on other streams (sfc_query_async_on) read the
+  // arrays above: the event recorded after each, until something that
+  // rewrites or frees the arrays has made the handle's stream wait for it.
+  std::vector<hipEvent_t> readers;
+  std::vector<hipEvent_t> idle_events;   // recorded-and-waited events for reuse
 };
 
 namespace {
@@ -282,6 +287,29 @@ sfc_status from_hip(hipError_t e) {
       return from_hip(_e);                         \
     }                                              \
   } while (0)
+
+// An event for ordering work across streams (no timing).
+hipError_t take_sync_event(sfc_index* h, hipEvent_t* out) {
+  if (!h->idle_events.empty()) {
+    *out = h->idle_events.back();
+    h->idle_events.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreateWithFlags(out, hipEventDisableTiming);
+}
+
+// Makes the handle's stream wait for every query batch still reading the
+// index on another stream (no host wait).  Called by everything that
+// rewrites or frees the index's arrays, before it does.
+hipError_t wait_readers(sfc_index* h) {
+  for (hipEvent_t e : h->readers) {
+    const hipError_t r = hipStreamWaitEvent(h->stream, e, 0);
+    if (r != hipSuccess) return r;
+    h->idle_events.push_back(e);
+  }
+  h->readers.clear();
+  return hipSuccess;
+}
 
 bool valid_options(const sfc_options& o) {
   if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT &&
@@ -378,6 +406,7 @@ void release_arrays(sfc_index* h) {
 // The static search tree's layers above the current keys, (re)built on the
 // handle's stream; the buffer grows first when the keys outgrew it.
 sfc_status stree_refresh(sfc_index* h) {
+  SFC_TRY(wait_readers(h));
   const size_t need = sfc::stree_bytes(h->n);
   if (need > h->stree_bytes) {
     // room for a quarter more keys, so that a stream of inserts rarely grows it
@@ -391,6 +420,31 @@ sfc_status stree_refresh(sfc_index* h) {
   }
   SFC_TRY(sfc::stree_build(sfc::stree_view(h->keys, h->n, h->stree), h->stream));
   h->stree_ready = true;
+  return SFC_OK;
+}
+
+// Grows the layer buffer to hold the layers of n keys; the current layers
+// are rebuilt into the new buffer, so the tree stays usable.
+sfc_status stree_reserve(sfc_index* h, uint64_t n) {
+  const size_t need = sfc::stree_bytes(n);
+  if (need <= h->stree_bytes) return SFC_OK;
+  SFC_TRY(wait_readers(h));   // the old layers are released below
+  const size_t room = sfc::stree_bytes(n + n / 4);
+  void* buf = h->alloc.get(room);
+  if (!buf) return SFC_ERR_NOMEM;
+  hipError_t e = hipSuccess;
+  if (h->stree_ready) {
+    e = sfc::stree_build(sfc::stree_view(h->keys, h->n, buf), h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->alloc.put(buf);
+    return from_hip(e);
+  }
+  h->alloc.put(h->stree);
+  h->stree = buf;
+  h->stree_bytes = room;
   return SFC_OK;
 }
 
@@ -409,6 +463,7 @@ int dim_of(const sfc_index* h) { return h->curve == SFC_CURVE_MORTON3 ? 3 : 2; }
 // the input-order copy is released then.
 sfc_status ensure_sorted_xy(sfc_index* h) {
   if (h->xy || h->n == 0) return SFC_OK;
+  SFC_TRY(wait_readers(h));   // the input-order copy is released below
   double* xy = (double*)h->alloc.get(h->n * 8 * dim_of(h));
   if (!xy) return SFC_ERR_NOMEM;
   hipError_t e = sfc::gather_sorted(h->ids, h->xy_in, xy, h->n, dim_of(h), h->stream);
@@ -571,6 +626,7 @@ sfc_status ensure_lmodel(sfc_index* h, uint64_t n) {
 
 sfc_status fit_learned(sfc_index* h, int steps) {
   if (h->n < 2) return SFC_ERR_UNSUPPORTED;
+  SFC_TRY(wait_readers(h));
   if (steps < 0) steps = h->learn_steps;
   if (!h->lparams) h->lparams = (float*)h->alloc.get(sfc::kParams * sizeof(float));
   if (!h->lparams) return SFC_ERR_NOMEM;
@@ -605,6 +661,7 @@ sfc_status fit_learned(sfc_index* h, int steps) {
 // search until the next fit.
 sfc_status refit_leaves(sfc_index* h) {
   if (!h->linfo.fitted) return SFC_OK;
+  SFC_TRY(wait_readers(h));
   if (h->n < 2) {
     h->linfo.fitted = 0;
     return SFC_OK;
@@ -947,6 +1004,81 @@ sfc_status sfc_query_async(sfc_index* h, const double* q, const double* delta,
   return SFC_OK;
 }
 
+sfc_status sfc_query_scratch_size(const sfc_index* h, uint64_t m, uint64_t max_rows,
+                                  uint64_t* bytes) {
+  if (!h || !bytes || m == 0 || m > (1ull << 36) || max_rows == 0 || max_rows > (1ull << 40))
+    return SFC_ERR_INVALID;
+  *bytes = align256(sfc::query_scratch_bytes(m, slots_of(h))) + sfc::compact_scratch_bytes(max_rows);
+  return SFC_OK;
+}
+
+sfc_status sfc_query_async_on(sfc_index* h, void* stream, void* scratch, uint64_t scratch_bytes,
+                              const double* q, const double* delta, const uint32_t* qepoch,
+                              uint64_t m, uint64_t max_rows, uint64_t* offsets, uint32_t* ids,
+                              uint64_t ids_cap, uint32_t* flags) {
+  if (!h || !offsets || !flags || !scratch || m == 0 || !q || !delta || (ids_cap > 0 && !ids))
+    return SFC_ERR_INVALID;
+  if (m > (1ull << 36) || max_rows == 0 || max_rows > (1ull << 40)) return SFC_ERR_INVALID;
+  if (((uintptr_t)scratch & 255) != 0) return SFC_ERR_INVALID;
+  if (h->n_sets) return SFC_ERR_UNSUPPORTED;
+  const size_t qbytes = align256(sfc::query_scratch_bytes(m, slots_of(h)));
+  if (scratch_bytes < qbytes + sfc::compact_scratch_bytes(max_rows)) return SFC_ERR_INVALID;
+  sfc_status st = points_for_test(h);   // a first gather of the points, on h's stream
+  if (st != SFC_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // After the work already queued on the handle's stream (an update's last
+  // kernels).
+  hipEvent_t ready = nullptr, done = nullptr;
+  SFC_TRY(take_sync_event(h, &ready));
+  h->idle_events.push_back(ready);   // reusable once the wait below is queued
+  SFC_TRY(hipEventRecord(ready, h->stream));
+  SFC_TRY(hipStreamWaitEvent(s, ready, 0));
+  SFC_TRY(take_sync_event(h, &done));
+  sfc::QueryScratch qs{};
+  sfc::query_scratch_carve(scratch, m, &qs, slots_of(h));
+  const bool learned = h->search == SFC_SEARCH_LEARNED && h->linfo.fitted;
+  const sfc::LearnedView lv = h->larr.view();
+  const sfc::StreeView sv = sfc::stree_view(h->keys, h->n, h->stree);
+  sfc::EpochView ev;
+  const bool filtered = epoch_view(h, qepoch, &ev);
+  hipError_t e =
+      dim_of(h) == 3
+          ? sfc::launch_ranges3(q, delta, m, h->keys, h->n, h->refine != 0, h->refine_min,
+                                stree_on(h) ? &sv : nullptr, qs, s)
+          : sfc::launch_ranges(q, delta, m, h->keys, h->n, h->curve, h->refine != 0,
+                               h->refine_min, h->metric == SFC_METRIC_L2,
+                               learned ? &lv : nullptr, stree_on(h) ? &sv : nullptr, h->occ,
+                               nullptr, nullptr, 0, qs, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, s);
+  if (e == hipSuccess && qepoch)
+    e = sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs.counters + 2, s);
+  if (e == hipSuccess)
+    e = sfc::launch_compact(q, delta, m, h->xy, h->xy_in, test_cells(h), h->ids, h->n, qs,
+                            max_rows, true, (char*)scratch + qbytes, offsets, ids, ids_cap,
+                            h->metric == SFC_METRIC_LINF, dim_of(h), s, filtered ? &ev : nullptr);
+  if (e == hipSuccess) e = hipMemcpyAsync(flags, qs.counters + 2, 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(done, s);
+  if (e != hipSuccess) {
+    h->idle_events.push_back(done);
+    (void)hipGetLastError();
+    return from_hip(e);
+  }
+  // Later writers of the index wait for this batch (finished batches are
+  // dropped from the list first).
+  for (size_t i = 0; i < h->readers.size();) {
+    if (hipEventQuery(h->readers[i]) == hipSuccess) {
+      h->idle_events.push_back(h->readers[i]);
+      h->readers[i] = h->readers.back();
+      h->readers.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  (void)hipGetLastError();   // hipEventQuery's not-ready status
+  h->readers.push_back(done);
+  return SFC_OK;
+}
+
 sfc_status sfc_query_retry(sfc_index* h, uint64_t* offsets, uint32_t* ids, uint64_t ids_cap,
                            uint64_t* total_out) {
   if (!h || !offsets || !total_out || (ids_cap > 0 && !ids)) return SFC_ERR_INVALID;
@@ -1189,6 +1321,7 @@ sfc_status sfc_debug_chunk_tiles(uint64_t tiles) {
 sfc_status sfc_learned_shrink_windows(sfc_index* h) {
   if (!h) return SFC_ERR_INVALID;
   if (!h->linfo.fitted) return SFC_ERR_UNSUPPORTED;
+  SFC_TRY(wait_readers(h));
   if (h->lstats_stale) {
     SFC_TRY(leaf_stats(h));
     h->lstats_stale = false;
@@ -1411,6 +1544,7 @@ sfc_status sfc_graph_query(sfc_index* h, const double* q, const double* delta,
 sfc_status sfc_graph_launch(sfc_graph* g) {
   if (!g || !g->exec) return SFC_ERR_INVALID;
   if (g->generation != g->h->generation) return SFC_ERR_INVALID;   // recorded before an update
+  if (g->kind == 0) SFC_TRY(wait_readers(g->h));
   SFC_TRY(hipGraphLaunch(g->exec, g->h->stream));
   return SFC_OK;
 }
@@ -1539,7 +1673,9 @@ sfc_status sfc_autotune_query(sfc_index* h, const double* q, const double* delta
 
 void sfc_free(sfc_index* h) {
   if (!h) return;
+  (void)wait_readers(h);
   (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->idle_events) (void)hipEventDestroy(e);
   release_arrays(h);
   delete h;
 }
@@ -1728,6 +1864,7 @@ uint64_t droppable(const sfc_index* h) {
 sfc_status compact_now(sfc_index* h) {
   const uint64_t drop = droppable(h);
   if (drop == 0) return SFC_OK;
+  SFC_TRY(wait_readers(h));
   const uint64_t keep = h->n - drop;
   // Room for every stored entry: the device's count decides what is written.
   sfc_status st = ensure_spare(h, h->n);
@@ -1764,9 +1901,14 @@ sfc_status compact_now(sfc_index* h) {
 }
 
 // Compacts once the droppable tombstones reach a tenth of the stored entries.
+// A compaction that finds no memory is put off to a later update: the
+// tombstones stay (queries skip them), so nothing the caller sees changes.
 sfc_status maybe_compact(sfc_index* h) {
   const uint64_t d = droppable(h);
-  if (d > 0 && d * 10 >= h->n) return compact_now(h);
+  if (d > 0 && d * 10 >= h->n) {
+    const sfc_status st = compact_now(h);
+    return st == SFC_ERR_NOMEM ? SFC_OK : st;
+  }
   return SFC_OK;
 }
 
@@ -1789,9 +1931,15 @@ sfc_status insert_impl(sfc_index* h, const double* xy, uint64_t k, const uint64_
     if (!h->hold) h->oldest = h->epoch;
     return SFC_OK;
   }
+  SFC_TRY(wait_readers(h));
   sfc_status st = ensure_dynamic(h);
   if (st == SFC_OK) st = ensure_key_of(h, (uint64_t)h->next_id + k);
   if (st == SFC_OK) st = ensure_spare(h, h->n + k);
+  // The learned leaves and the search tree of n + k keys get their memory
+  // now, so that nothing after the merge allocates: a failed allocation
+  // leaves the index as it was.
+  if (st == SFC_OK && h->linfo.fitted) st = ensure_lmodel(h, h->n + k);
+  if (st == SFC_OK && h->stree_ready) st = stree_reserve(h, h->n + k);
   if (st != SFC_OK) return st;
   const size_t sb = sfc::build_scratch_bytes(k) + 256;
   const size_t rb = runs > 1 ? align256((runs + 1) * 8) : 0;
@@ -1874,6 +2022,7 @@ sfc_status sfc_erase(sfc_index* h, const uint32_t* ids, uint64_t k, uint64_t* er
     return SFC_OK;
   }
   if (h->epoch >= 0xFFFFFFFEu) return SFC_ERR_UNSUPPORTED;
+  SFC_TRY(wait_readers(h));
   sfc_status st = ensure_dynamic(h);
   if (st != SFC_OK) return st;
   const uint32_t ep = h->epoch + 1;

@@ -11,16 +11,26 @@ retired, which lets the index drop the tombstones no query can see any
 more.  All GPU work runs in the library; this loop only slices the request
 pools and keeps the clock.
 
-Two modes:
-  * ``slots = 0``: each tick's query batch is answered before the next tick
-    starts (sfc_query_epochs).
+Three modes:
+  * ``slots = 0, streams = 0``: each tick's query batch is answered before
+    the next tick starts (sfc_query_epochs).
   * ``slots = k > 0``: query batches are queued without waiting
-    (sfc_query_async) into k preallocated output slots; while they run, the
-    loop admits the next arrivals and queues their work behind them, and a
-    batch's requests complete when its slot's event has passed.  A tick with
-    queries waits only for a free slot (admission as slots free up).  A batch
-    that outgrew its slot is answered again synchronously into larger
-    buffers.
+    (sfc_query_async) into k preallocated output slots on the index's own
+    stream; while they run, the loop admits the next arrivals and queues
+    their work behind them, and a batch's requests complete when its slot's
+    event has passed.  A tick with queries waits only for a free slot.
+  * ``streams = k > 0``: query batches run side by side on k streams
+    (sfc_query_async_on), each with its own scratch and outputs allocated
+    when it is admitted.  Admission is by memory: a batch is admitted while
+    the bytes of the batches in flight plus its own stay within
+    ``budget_bytes`` and a stream is free; otherwise the loop first waits for
+    the oldest batch.  An allocation that fails (the device, or the library
+    reporting SFC_ERR_NOMEM) puts the batch back at the head of the queue
+    until a batch in flight has freed its memory.  Updates run on the
+    index's stream; the library makes them wait, on the device, for the
+    batches still reading the index.
+A batch that outgrew its output (rows or ids) is answered again
+synchronously into larger buffers.
 """
 from __future__ import annotations
 
@@ -79,6 +89,9 @@ class Run:
     ticks: int
     seconds: float
     outputs: dict             # request -> (offsets, ids) on the host, if recorded
+    max_in_flight: int = 0    # side-by-side mode: most bytes admitted at once
+    max_batches: int = 0      # side-by-side mode: most batches in flight at once
+    requeued: int = 0         # side-by-side mode: batches put back for want of memory
 
     def latency(self) -> np.ndarray:
         return self.done - self.arrival
@@ -115,9 +128,18 @@ class _Inserts:
 def serve(index: sfc.Index, trace: ServingTrace, pools: Pools, rate: float = float("inf"),
           max_tick: int = 16, record: bool = False, out_ids: torch.Tensor | None = None,
           slots: int = 0, slot_queries: int = 1 << 20, slot_ids: int = 1 << 26,
-          slot_rows: int = 1 << 24) -> Run:
+          slot_rows: int = 1 << 24, streams: int = 0, budget_bytes: int = 2 << 30,
+          rows_per_query: int = 48, ids_per_query: int = 1200, alloc=None) -> Run:
     """Runs the trace with Poisson arrivals at ``rate`` requests/s (inf: all
-    at time 0) and returns arrival and completion times per request."""
+    at time 0) and returns arrival and completion times per request.
+
+    streams > 0: batches of at most slot_queries queries run side by side,
+    each sized for rows_per_query candidate rows and ids_per_query ids per
+    query, admitted against budget_bytes; alloc(nbytes) -> uint8 device
+    tensor (default torch.empty) provides their memory."""
+    if streams > 0:
+        return _serve_overlap(index, trace, pools, rate, max_tick, record, streams, budget_bytes,
+                              slot_queries, rows_per_query, ids_per_query, alloc)
     if slots > 0:
         return _serve_async(index, trace, pools, rate, max_tick, record, slots, slot_queries,
                             slot_ids, slot_rows)
@@ -325,6 +347,188 @@ def _serve_async(index, trace, pools, rate, max_tick, record, nslots, slot_queri
     index.retire(epoch)
     seconds = time.perf_counter() - t0
     return Run(arrival, done, admitted, ticks, seconds, outputs)
+
+
+class _Batch:
+    """One admitted query batch of the side-by-side mode: its requests, its
+    stream, and the memory it holds until it completes."""
+
+    def __init__(self, members, q, d, e, stream, nbytes):
+        self.members, self.q, self.d, self.e = members, q, d, e
+        self.stream, self.nbytes = stream, nbytes
+        self.event = torch.cuda.Event(enable_timing=True)
+        self.scratch = self.offsets = self.ids = self.flags = None
+        self.max_rows = 0
+
+
+def _serve_overlap(index, trace, pools, rate, max_tick, record, nstreams, budget, max_batch,
+                   rows_per_query, ids_per_query, alloc) -> Run:
+    R = len(trace.kind)
+    arrival = np.zeros(R) if not np.isfinite(rate) else np.cumsum(trace.gaps) / rate
+    done = np.zeros(R)
+    admitted = np.full(R, -1, np.int64)
+    outputs = {}
+    index.hold_epochs(True)
+    epoch = index.update_info()["epoch"]
+    dev = pools.queries.device
+    if alloc is None:
+        def alloc(nbytes):
+            return torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+    free = list(streams)
+    busy = []                      # batches in launch order
+    in_flight = [0]
+    stats = {"max_in_flight": 0, "max_batches": 0, "requeued": 0}
+    start = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+
+    def finish(b: _Batch):
+        b.event.synchronize()
+        t_done = start.elapsed_time(b.event) * 1e-3
+        m = sum(k for _, _, k in b.members)
+        flags = int(b.flags[0].item())
+        total = int(b.offsets[m].item()) if flags == 0 else -1
+        if flags != 0 or total > b.ids.numel():
+            if flags & ~16:
+                raise sfc.SfcError(sfc.SFC_ERR_INVALID, f"query batch flags {flags}")
+            off, ids = index.query_epochs(b.q, b.d, b.e)   # outgrew its outputs
+            t_done = time.perf_counter() - t0
+        else:
+            off, ids = b.offsets[:m + 1], b.ids[:total]
+        base = 0
+        if record:
+            off_h = off.cpu().numpy()
+            ids_h = ids.cpu().numpy()
+        for r, e_r, k in b.members:
+            done[r] = t_done
+            admitted[r] = e_r
+            if record:
+                o = off_h[base:base + k + 1]
+                outputs[r] = (o - o[0], ids_h[o[0]:o[-1]].copy())
+            base += k
+        in_flight[0] -= b.nbytes
+        free.append(b.stream)
+
+    def reap(block: bool):
+        while busy and (block or busy[0].event.query()):
+            finish(busy.pop(0))
+            block = False
+
+    def launch(take) -> bool:
+        """Admits one batch: False when its memory could not be had (the
+        caller waits for a batch in flight and tries again)."""
+        m = sum(k for _, _, k in take)
+        max_rows = rows_per_query * m + 1024
+        ids_cap = ids_per_query * m
+        scratch_bytes = index.query_scratch_bytes(m, max_rows)
+        nbytes = scratch_bytes + 8 * (m + 1) + 4 * ids_cap + 256 + m * (16 + 8 + 4)
+        while busy and (not free or in_flight[0] + nbytes > budget):
+            reap(True)                 # admission by memory and streams
+        try:
+            qs, ds, es = [], [], []
+            for r, e, k in take:
+                a = int(trace.start[r])
+                qs.append(pools.queries[a:a + k])
+                ds.append(pools.delta[a:a + k])
+                es.append(torch.full((k,), e, dtype=torch.int32, device=dev))
+            q = torch.cat(qs) if len(qs) > 1 else qs[0]
+            d = torch.cat(ds) if len(ds) > 1 else ds[0]
+            e = torch.cat(es) if len(es) > 1 else es[0]
+            b = _Batch(take, q, d, e, free[0], nbytes)
+            b.max_rows = max_rows
+            b.scratch = alloc(scratch_bytes)
+            out = alloc(8 * (m + 1) + 4 * ids_cap + 256)
+            b.offsets = out[:8 * (m + 1)].view(torch.int64)
+            b.ids = out[8 * (m + 1):8 * (m + 1) + 4 * ids_cap].view(torch.int32)
+            b.flags = out[-256:].view(torch.int32)
+            b.flags.zero_()
+        except torch.cuda.OutOfMemoryError:
+            return False
+        if b.scratch is None or b.scratch.numel() < scratch_bytes:
+            return False               # the caller's allocator had no memory
+        b.stream.wait_stream(torch.cuda.current_stream())
+        try:
+            index.query_async_on(b.stream, b.scratch, q, d, e, max_rows, b.offsets, b.ids,
+                                 b.flags)
+        except sfc.SfcError as err:
+            if err.status != sfc.SFC_ERR_NOMEM:
+                raise
+            return False
+        b.event.record(b.stream)
+        free.pop(0)
+        busy.append(b)
+        in_flight[0] += nbytes
+        stats["max_in_flight"] = max(stats["max_in_flight"], in_flight[0])
+        stats["max_batches"] = max(stats["max_batches"], len(busy))
+        return True
+
+    ticks = 0
+    i = 0
+    alone_failures = 0
+    while i < R:
+        reap(False)
+        now = time.perf_counter() - t0
+        if arrival[i] > now and busy:
+            reap(True)                 # nothing arrived yet: wait for the oldest batch
+            continue
+        if arrival[i] > now:
+            wait = arrival[i] - now
+            if wait > 2e-3:
+                time.sleep(wait - 1e-3)
+            while time.perf_counter() - t0 < arrival[i]:
+                pass
+            now = time.perf_counter() - t0
+        j = int(np.searchsorted(arrival, now, side="right"))
+        j = min(max(j, i + 1), i + max_tick)
+        pending = []
+        inserts = _Inserts(index, pools)
+        for r in range(i, j):
+            a, k = int(trace.start[r]), int(trace.size[r])
+            if trace.kind[r] == QUERY:
+                pending.append((r, epoch, k))
+            elif trace.kind[r] == INSERT:
+                inserts.add(r, a, k)
+                epoch += 1
+            else:
+                for ri in inserts.flush():
+                    done[ri] = time.perf_counter() - t0
+                index.erase(pools.erase_ids[a:a + k])
+                epoch += 1
+                done[r] = time.perf_counter() - t0
+        for ri in inserts.flush():
+            done[ri] = time.perf_counter() - t0
+        reap(False)
+        while pending:
+            take, m = [], 0
+            while pending and (not take or m + pending[0][2] <= max_batch):
+                take.append(pending.pop(0))
+                m += take[-1][2]
+            if launch(take):
+                alone_failures = 0
+                continue
+            # requeue: after a batch in flight frees its memory, or, with none
+            # in flight, once more after the device is idle
+            pending[:0] = take
+            stats["requeued"] += 1
+            if busy:
+                reap(True)
+            else:
+                alone_failures += 1
+                if alone_failures > 1:
+                    raise sfc.SfcError(sfc.SFC_ERR_NOMEM, "a query batch found no memory "
+                                       "with nothing in flight")
+                torch.cuda.synchronize()
+        oldest = min([e for b in busy for _, e, _ in b.members], default=epoch)
+        index.retire(oldest)
+        ticks += 1
+        i = j
+    while busy:
+        reap(True)
+    index.retire(epoch)
+    seconds = time.perf_counter() - t0
+    return Run(arrival, done, admitted, ticks, seconds, outputs, **stats)
 
 
 def summarize(trace: ServingTrace, run: Run) -> dict:

@@ -47,6 +47,7 @@ EXPORTS = [
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
     "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric", "sfc_set_cell_filter",
     "sfc_cells_copy", "sfc_debug_sort_path", "sfc_insert_runs", "sfc_query_batch_static",
+    "sfc_query_scratch_size", "sfc_query_async_on",
 ]
 
 NPARAM = 1153
@@ -81,6 +82,11 @@ class Options(ctypes.Structure):
         ("early_term", ctypes.c_int),
         ("metric", ctypes.c_int),
     ]
+
+
+# sfc_options.alloc / release: device memory hooks (alloc returns NULL on failure).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class LearnedInfo(ctypes.Structure):
@@ -216,6 +222,10 @@ def lib() -> ctypes.CDLL:
     L.sfc_query_retry.restype = i32
     L.sfc_query_async.argtypes = [vp, vp, vp, vp, u64, u64, vp, vp, u64, vp]
     L.sfc_query_async.restype = i32
+    L.sfc_query_scratch_size.argtypes = [vp, u64, u64, ctypes.POINTER(u64)]
+    L.sfc_query_scratch_size.restype = i32
+    L.sfc_query_async_on.argtypes = [vp, vp, vp, u64, vp, vp, vp, u64, u64, vp, vp, u64, vp]
+    L.sfc_query_async_on.restype = i32
     L.sfc_occupancy_copy.argtypes = [vp, vp, u64]
     L.sfc_occupancy_copy.restype = i32
     _lib = L
@@ -271,11 +281,13 @@ class Index:
 
     def __init__(self, xy: torch.Tensor, curve: int = MORTON, search: int = BINARY,
                  refine: bool = False, learn_steps: int = -1, set_off=None,
-                 early_term: bool = False, metric: int = L2):
+                 early_term: bool = False, metric: int = L2, allocator=None):
         """set_off (host sequence of n_sets + 1 offsets): build independent
         point sets with sfc_build_sets; query them with query_sets.  metric:
         L2 (ball of radius delta) or LINF (square window of half side
-        delta)."""
+        delta).  allocator: an object with alloc(nbytes) -> device address
+        (0 on failure) and release(address), used for every device
+        allocation of the index (sfc_options.alloc / release)."""
         xy = _dev(xy, torch.float64, "xy")
         self.dim = 3 if curve == MORTON3 else 2
         if xy.ndim != 2 or xy.shape[1] != self.dim:
@@ -290,6 +302,12 @@ class Index:
         opt.early_term = 1 if early_term else 0
         opt.metric = metric
         opt.stream = current_stream_handle()
+        self._hooks = None
+        if allocator is not None:
+            self._hooks = (ALLOC_FN(lambda nbytes, ctx: allocator.alloc(nbytes) or None),
+                           RELEASE_FN(lambda ptr, ctx: allocator.release(ptr)))
+            opt.alloc = ctypes.cast(self._hooks[0], ctypes.c_void_p)
+            opt.release = ctypes.cast(self._hooks[1], ctypes.c_void_p)
         h = ctypes.c_void_p()
         if set_off is None:
             _check(L.sfc_build(_ptr(xy), xy.shape[0], ctypes.byref(opt), ctypes.byref(h)),
@@ -472,6 +490,29 @@ class Index:
         _check(lib().sfc_query_async(self.handle, _ptr(q), _ptr(delta), _ptr(qepoch), q.shape[0],
                                      max_rows, _ptr(out_offsets), _ptr(out_ids), out_ids.numel(),
                                      _ptr(flags)), "sfc_query_async")
+
+    def query_scratch_bytes(self, m: int, max_rows: int) -> int:
+        """Scratch bytes of one sfc_query_async_on batch."""
+        b = ctypes.c_uint64(0)
+        _check(lib().sfc_query_scratch_size(self.handle, m, max_rows, ctypes.byref(b)),
+               "sfc_query_scratch_size")
+        return int(b.value)
+
+    def query_async_on(self, stream: torch.cuda.Stream, scratch: torch.Tensor, q: torch.Tensor,
+                       delta: torch.Tensor, qepoch: torch.Tensor | None, max_rows: int,
+                       out_offsets: torch.Tensor, out_ids: torch.Tensor, flags: torch.Tensor):
+        """Queues a batch on `stream` with its own scratch (sfc_query_async_on)
+        and returns at once; the caller keeps every tensor alive until the
+        stream has passed the batch."""
+        q = _dev(q, torch.float64, "q")
+        delta = _dev(delta, torch.float64, "delta")
+        if qepoch is not None:
+            qepoch = _dev(qepoch, torch.int32, "qepoch")
+        _check(lib().sfc_query_async_on(self.handle, ctypes.c_void_p(stream.cuda_stream),
+                                        _ptr(scratch), scratch.numel() * scratch.element_size(),
+                                        _ptr(q), _ptr(delta), _ptr(qepoch), q.shape[0], max_rows,
+                                        _ptr(out_offsets), _ptr(out_ids), out_ids.numel(),
+                                        _ptr(flags)), "sfc_query_async_on")
 
     def occupancy(self) -> torch.Tensor:
         """The early-termination bitmap (int32 words)."""

@@ -83,7 +83,7 @@ def test_headline_is_compact_and_complete():
                           "bsearch": {"search_ms": 1.05, "ms_per_batch": 2.98}},
         "early_termination": {"speedup_batch": 0.92, "plain": {"ms_per_batch": 0.65},
                               "early_term": {"ms_per_batch": 0.70}},
-        "serving": {"queued": {"saturation": load, "load_0.95": load}},
+        "serving": {"overlap": {"saturation": load, "load_0.95": load}},
         "cpu_baseline": {"value": 2.8e5, "unit": "queries/s", "cores": 16, "kind": "oracle",
                          "sample": "oracle build of all 16777216 points on 1 thread (3.09 s) + "
                                    "all 1048576 queries on 16 threads (0.64 s)"},

@@ -83,3 +83,73 @@ def test_queued_batches_that_outgrow_their_slot_are_answered_again():
     for r, (off, ids) in ref.outputs.items():
         assert np.array_equal(run.outputs[r][0], off) and np.array_equal(run.outputs[r][1], ids)
     assert (run.latency() > 0).all()
+
+
+class _FailSome:
+    """uint8 device buffers; the calls numbered in `fail` raise the device's
+    out-of-memory error instead."""
+
+    def __init__(self, fail):
+        self.fail, self.calls = set(fail), 0
+
+    def __call__(self, nbytes):
+        self.calls += 1
+        if self.calls in self.fail:
+            raise torch.cuda.OutOfMemoryError("injected")
+        return torch.empty(nbytes, dtype=torch.uint8, device=DEV)
+
+
+@pytest.mark.parametrize("curve,search", [(MORTON, sfc.LEARNED), (HILBERT, sfc.STREE)])
+def test_side_by_side_batches_equal_snapshot_oracle(curve, search):
+    """Query batches on three streams at once, admitted by memory, with
+    some of their allocations failing (put back and admitted again): every
+    request equals the oracle over the snapshot of its epoch."""
+    trace = workload.serving_trace(n0=20_000, requests=90, seed=7, curve=curve,
+                                   log2_size=(6, 11))
+    pools = serving.Pools.upload(trace, DEV)
+    init = torch.as_tensor(trace.initial).to(DEV)
+    idx = sfc.Index(init, curve, search=search, refine=True)
+    per_query = 8 * 48 + 8 + 4 * 1200 + 28 + 300     # scratch estimate + outputs + inputs
+    budget = 3 * 600 * per_query + (4 << 20)
+    alloc = _FailSome({4, 11, 23, 40})
+    run = serving.serve(idx, trace, pools, record=True, streams=3, budget_bytes=budget,
+                        slot_queries=600, alloc=alloc)
+    assert run.max_batches >= 2          # batches were on the device together
+    assert run.requeued >= 3             # and the failed allocations were admitted again
+    assert run.max_in_flight <= budget
+    model = Model(trace.initial, hold=True)
+    expect_epoch = {}
+    for r in range(len(trace.kind)):
+        a, k = int(trace.start[r]), int(trace.size[r])
+        if trace.kind[r] == workload.INSERT:
+            model.insert(trace.inserts[a:a + k])
+        elif trace.kind[r] == workload.ERASE:
+            model.erase(trace.erase_ids[a:a + k])
+        else:
+            expect_epoch[r] = model.epoch
+    for r, e in expect_epoch.items():
+        assert run.admitted[r] == e
+        a, k = int(trace.start[r]), int(trace.size[r])
+        want = model.reference(trace.queries[a:a + k], trace.delta[a:a + k], np.full(k, e), curve)
+        off, ids = run.outputs[r]
+        assert np.array_equal(off.view(np.uint64), want[0]), r
+        assert np.array_equal(ids.view(np.uint32), want[1]), r
+    idx.close()
+
+
+def test_side_by_side_budget_limits_batches_in_flight():
+    """A budget below the memory of any batch: each batch is admitted alone
+    (never two in flight), with the same answers as the synchronous loop."""
+    trace = workload.serving_trace(n0=20_000, requests=40, seed=9, log2_size=(6, 10))
+    pools = serving.Pools.upload(trace, DEV)
+    init = torch.as_tensor(trace.initial).to(DEV)
+    ref_idx = sfc.Index(init, MORTON, refine=True)
+    ref = serving.serve(ref_idx, trace, pools, record=True)
+    idx = sfc.Index(init, MORTON, refine=True)
+    m = 64                                   # the smallest request of the trace
+    one = idx.query_scratch_bytes(m, 48 * m + 1024) + 8 * (m + 1) + 4 * 1200 * m - 1
+    run = serving.serve(idx, trace, pools, record=True, streams=4, budget_bytes=one,
+                        slot_queries=300)
+    assert run.max_batches == 1
+    for r, (off, ids) in ref.outputs.items():
+        assert np.array_equal(run.outputs[r][0], off) and np.array_equal(run.outputs[r][1], ids)
