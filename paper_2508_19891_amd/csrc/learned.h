@@ -8,17 +8,28 @@
 // std::lower_bound over the keys.
 //
 // The router is evaluated in two equivalent ways.  Training and the fit
-// evaluate the network itself.  Queries read its tabulation: the router is
-// monotone in its 24-bit input X, so leaf(X) is a step function, fully
-// described by the first input of every leaf (xb); a table over the top 16
-// bits of X brackets the leaf and a short search in xb finds it.  Both give
-// the same leaf for every X (the table is built from the same device
-// function).
+// evaluate the network itself.  The fit also reads its tabulation: the
+// router is monotone in its 24-bit input X, so leaf(X) is a step function,
+// fully described by the first input of every leaf (xb); a table over the
+// top 16 bits of X brackets the leaf and a short search in xb finds it.
+// Both give the same leaf for every X (the table is built from the same
+// device function).
+//
+// The leaves are contiguous key runs and their pieces tile the sorted array
+// in key order, so the pieces' first keys fk are sorted and the piece a key
+// k lands in is simply the last one with fk < k: a query finds it through a
+// table over the top 20 key bits (the number of pieces whose first key lies
+// below each 20-bit prefix) and a scan of the few first keys that share k's
+// prefix, without evaluating the router.  Each piece's window covers every
+// key from its first key up to the next piece's first key, so the lower
+// bound of any k lies in the window of that piece.
 //
 // On the GPU the cost of a lower bound is its chain of dependent loads, so
-// the searches below end in a scan of at most 16 sorted entries whose loads
-// are independent of each other: a binary search over a few hundred keys
-// takes about eight dependent probes, the scan one round trip.
+// the searches below end in a scan of a few sorted entries (16 for one
+// bound, 4 for each of two bounds searched in lockstep, where registers
+// decide how many waves run) whose loads are independent of each other: a
+// binary search over a few hundred keys takes about eight dependent probes,
+// the scan one round trip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,6 +55,8 @@ constexpr uint32_t kPiece = 256;      // keys per piece (the last piece of a lea
 constexpr int kXBits = 24;            // router input: the top 24 key bits
 constexpr int kRouteBits = 16;        // leaf bracket table over the top 16 input bits
 constexpr uint32_t kRouteSlots = 1u << kRouteBits;
+constexpr int kDirectBits = 20;       // piece table over the top 20 key bits
+constexpr uint32_t kDirectSlots = 1u << kDirectBits;
 
 struct PieceRec {
   double s;          // ranks per key unit from the piece's first key
@@ -58,6 +71,8 @@ struct LearnedView {
                         // lp[kLeaves] = (n, number of pieces)
   const uint64_t* fk;   // first key of each piece
   const PieceRec* pr;   // model and window of each piece
+  const uint32_t* ps;   // pieces + 1: first key index of each piece (ps[pieces] = n)
+  const uint32_t* dt;   // kDirectSlots + 1: pieces whose first key is below t << 44
 };
 
 // The same arrays, writable, as the fit carves them from one allocation.
@@ -67,8 +82,10 @@ struct LearnedArrays {
   uint2* lp = nullptr;
   uint64_t* fk = nullptr;
   PieceRec* pr = nullptr;
+  uint32_t* ps = nullptr;
+  uint32_t* dt = nullptr;
   uint32_t max_pieces = 0;
-  __host__ __device__ LearnedView view() const { return LearnedView{xb, rt, lp, fk, pr}; }
+  __host__ __device__ LearnedView view() const { return LearnedView{xb, rt, lp, fk, pr, ps, dt}; }
 };
 
 // Router input: the top 24 bits of the key as a float in [0, 1) (exact, so
@@ -174,33 +191,25 @@ __device__ __forceinline__ int64_t piece_predict(double s, uint64_t fk, uint64_t
 __device__ __forceinline__ uint64_t learned_lower_bound(const uint64_t* __restrict__ keys,
                                                        uint64_t n, const LearnedView& v,
                                                        uint64_t k, bool* fell_back) {
-  // Keys of lower leaves are < k and keys of higher leaves > k (monotone
-  // routing), so the lower bound lies in [S, E].
-  const uint32_t l = route(v, (uint32_t)(k >> 40));
-  const uint2 a = v.lp[l], b = v.lp[l + 1];
-  uint64_t S = a.x, E = b.x;
-  E = E > n ? n : E;   // keeps every probe inside the array should the fit be stale
-  S = S > E ? E : S;
-  uint64_t r = S;
-  if (E > S) {
-    // The last piece whose first key is < k brackets the lower bound in
-    // (R, Rn]; no such piece means keys[S] >= k, so the bound is S.
-    const uint32_t p0 = a.y, p1 = b.y > a.y ? b.y : a.y;
-    const uint32_t c = (uint32_t)lower_bound_scan(v.fk, p0, p1, k);
-    if (c > p0) {
-      const uint32_t j = c - 1;
-      uint64_t R = S + (uint64_t)(j - p0) * kPiece;
-      R = R < E ? R : E - 1;
-      const uint64_t Rn = R + kPiece < E ? R + kPiece : E;
-      const PieceRec pc = v.pr[j];
-      const int64_t p = piece_predict(pc.s, v.fk[j], R, Rn, k);
-      int64_t wlo = p + pc.elo, whi = p + pc.ehi;
-      wlo = wlo < (int64_t)(R + 1) ? (int64_t)(R + 1) : wlo;
-      whi = whi > (int64_t)Rn ? (int64_t)Rn : whi;
-      if (whi < wlo) whi = wlo;
-      r = lower_bound_scan(keys, (uint64_t)wlo, (uint64_t)whi, k);
-    }
+  // The pieces whose first key is below k: all those below k's 20-bit
+  // prefix, and some of those that share it.
+  const uint32_t t = (uint32_t)(k >> (64 - kDirectBits));
+  const uint32_t c = (uint32_t)lower_bound_scan(v.fk, v.dt[t], v.dt[t + 1], k);
+  uint64_t r = 0;   // no piece starts below k: keys[0] >= k
+  if (c > 0) {
+    // Piece c - 1 holds keys [R, Rn); its window covers every k in
+    // (fk, first key of the next piece], so the lower bound is in (R, Rn].
+    const uint32_t j = c - 1;
+    const uint64_t R = v.ps[j], Rn = v.ps[j + 1];
+    const PieceRec pc = v.pr[j];
+    const int64_t p = piece_predict(pc.s, v.fk[j], R, Rn, k);
+    int64_t wlo = p + pc.elo, whi = p + pc.ehi;
+    wlo = wlo < (int64_t)(R + 1) ? (int64_t)(R + 1) : wlo;
+    whi = whi > (int64_t)Rn ? (int64_t)Rn : whi;
+    if (whi < wlo) whi = wlo;
+    r = lower_bound_scan(keys, (uint64_t)wlo, (uint64_t)whi, k);
   }
+  r = r > n ? n : r;   // keeps the check inside the array should the model be stale
   const bool ok = (r == 0 || keys[r - 1] < k) && (r == n || keys[r] >= k);
   *fell_back = !ok;
   return ok ? r : lower_bound_in(keys, 0, n, k);
@@ -211,7 +220,7 @@ __device__ __forceinline__ uint64_t learned_lower_bound(const uint64_t* __restri
 // keeps two independent loads in flight at every step (as the interleaved
 // binary searches of the plain path do), which halves the dependent latency.
 
-constexpr int kScan2 = 8;   // entries scanned at the end of each search
+constexpr int kScan2 = 4;   // entries scanned at the end of each search
 
 // Lower bounds of k[i] in [lo[i], hi[i]) of the sorted array a, for i = 0, 1.
 __device__ __forceinline__ void lower_bound_scan_pair(const uint64_t* __restrict__ a,
@@ -257,54 +266,24 @@ __device__ __forceinline__ void lower_bound_scan_pair(const uint64_t* __restrict
 __device__ __forceinline__ uint32_t learned_lower_bound_pair(const uint64_t* __restrict__ keys,
                                                             uint64_t n, const LearnedView& v,
                                                             const uint64_t k[2], uint64_t r[2]) {
-  // Route: bracket from the table, then the short search in xb.
-  uint32_t X[2], lo[2], hi[2];
+  // The pieces below each key: the prefix table's bracket, then a scan of
+  // the first keys that share the prefix.
+  uint64_t c[2], chi[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    X[i] = (uint32_t)(k[i] >> 40);
-    const uint32_t t = X[i] >> (kXBits - kRouteBits);
-    lo[i] = v.rt[t];
-    hi[i] = v.rt[t + 1];
+    const uint32_t t = (uint32_t)(k[i] >> (64 - kDirectBits));
+    c[i] = v.dt[t];
+    chi[i] = v.dt[t + 1];
   }
-  while (lo[0] < hi[0] || lo[1] < hi[1]) {
-    uint32_t mid[2], x[2] = {0, 0};
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      mid[i] = (lo[i] + hi[i] + 1) >> 1;
-      if (lo[i] < hi[i]) x[i] = v.xb[mid[i]];
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      if (lo[i] < hi[i]) {
-        if (x[i] <= X[i]) lo[i] = mid[i];
-        else hi[i] = mid[i] - 1;
-      }
-    }
-  }
-  // Leaves and their piece ranges.
-  uint64_t S[2], E[2], plo[2], phi[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const uint2 a = v.lp[lo[i]], b = v.lp[lo[i] + 1];
-    E[i] = b.x > n ? n : b.x;
-    S[i] = a.x > E[i] ? E[i] : a.x;
-    plo[i] = a.y;
-    phi[i] = E[i] > S[i] ? (b.y > a.y ? b.y : a.y) : a.y;   // no pieces for an empty leaf
-  }
-  const uint64_t p0[2] = {plo[0], plo[1]};
-  lower_bound_scan_pair(v.fk, plo, phi, k);
+  lower_bound_scan_pair(v.fk, c, chi, k);
   // The bracketing piece, its prediction and window.
   uint64_t wlo[2], whi[2];
-  bool searched[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    searched[i] = plo[i] > p0[i];
-    wlo[i] = whi[i] = S[i];
-    if (searched[i]) {
-      const uint64_t j = plo[i] - 1;
-      uint64_t R = S[i] + (j - p0[i]) * kPiece;
-      R = R < E[i] ? R : E[i] - 1;
-      const uint64_t Rn = R + kPiece < E[i] ? R + kPiece : E[i];
+    wlo[i] = whi[i] = 0;
+    if (c[i] > 0) {
+      const uint64_t j = c[i] - 1;
+      const uint64_t R = v.ps[j], Rn = v.ps[j + 1];
       const PieceRec pc = v.pr[j];
       const int64_t p = piece_predict(pc.s, v.fk[j], R, Rn, k[i]);
       int64_t a = p + pc.elo, b = p + pc.ehi;
@@ -320,7 +299,7 @@ __device__ __forceinline__ uint32_t learned_lower_bound_pair(const uint64_t* __r
   uint64_t below[2], at[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    r[i] = wlo[i];
+    r[i] = wlo[i] > n ? n : wlo[i];
     below[i] = r[i] > 0 ? keys[r[i] - 1] : 0;
     at[i] = r[i] < n ? keys[r[i]] : 0;
   }

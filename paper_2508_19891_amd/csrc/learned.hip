@@ -334,19 +334,20 @@ __global__ __launch_bounds__(256) void learned_piece_offsets(uint2* __restrict__
 }
 
 // One wave per piece j of leaf l: keys[R..Rn), R = lb[l] + (j - po[l]) * kPiece.
-// A query key k picks the last piece of its leaf with first key < k, so the
-// piece receives k in (keys[R], kmax] (kmax: the next piece's first key, or
-// the largest key routed to the leaf), and the lower bound lies in (R, Rn].
+// The pieces of all leaves tile the sorted keys in order, so a query key k
+// picks the last piece whose first key is < k: the piece receives k in
+// (keys[R], kmax] (kmax: the next piece's first key, keys[Rn], or the
+// largest key for the last piece), and the lower bound lies in (R, Rn].
 // For i in (R, Rn) the keys in (keys[i-1], keys[i]] have lower bound i (when
 // keys[i-1] < keys[i]); the keys in (keys[Rn-1], kmax] have lower bound Rn.
 // The prediction is monotone in k, so each interval's extremes of
 // (bound - prediction) are at its ends.
 __global__ __launch_bounds__(256) void learned_pieces(const uint64_t* __restrict__ keys,
-                                                      uint64_t n, const uint32_t* __restrict__ xb,
-                                                      const uint2* __restrict__ lp,
+                                                      uint64_t n, const uint2* __restrict__ lp,
                                                       uint32_t max_pieces,
                                                       uint64_t* __restrict__ fk,
-                                                      PieceRec* __restrict__ pr) {
+                                                      PieceRec* __restrict__ pr,
+                                                      uint32_t* __restrict__ ps) {
 #pragma clang fp contract(off)
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -365,15 +366,10 @@ __global__ __launch_bounds__(256) void learned_pieces(const uint64_t* __restrict
   const uint64_t Rn = R + kPiece < E ? R + kPiece : E;
   const bool last = j + 1 >= lp[l + 1].y;
   const uint64_t f = keys[R];
-  uint64_t kmax;
-  double span;
-  if (!last) {
-    kmax = keys[Rn];
-    span = (double)(kmax - f);
-  } else {
-    kmax = xb[l + 1] >= (1u << kXBits) ? ~0ull : ((uint64_t)xb[l + 1] << (64 - kXBits)) - 1;
-    span = (double)(keys[E - 1] - f) + 1.0;
-  }
+  const uint64_t kmax = Rn < n ? keys[Rn] : ~0ull;
+  // the slope spans the piece's own keys (to the next piece's first key
+  // inside the leaf)
+  const double span = !last ? (double)(kmax - f) : (double)(keys[E - 1] - f) + 1.0;
   const double sl = span > 0.0 ? (double)(Rn - R) / span : 0.0;
   int64_t emin = INT64_MAX, emax = INT64_MIN;
   for (uint64_t i = R + 1 + lane; i <= Rn; i += 64) {
@@ -402,7 +398,25 @@ __global__ __launch_bounds__(256) void learned_pieces(const uint64_t* __restrict
     rec.ehi = emin > emax ? 0 : (int32_t)emax;
     fk[j] = f;
     pr[j] = rec;
+    ps[j] = (uint32_t)R;
   }
+}
+
+// dt[t] = the number of pieces whose first key is below t << 44 (t < 2^20),
+// dt[2^20] = the number of pieces; ps[pieces] = n.
+__global__ __launch_bounds__(256) void learned_direct(const uint64_t* __restrict__ fk,
+                                                      const uint2* __restrict__ lp, uint64_t n,
+                                                      uint32_t* __restrict__ ps,
+                                                      uint32_t* __restrict__ dt) {
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t > kDirectSlots) return;
+  const uint32_t np = lp[kLeaves].y;
+  if (t == kDirectSlots) {
+    dt[t] = np;
+    ps[np] = (uint32_t)n;
+    return;
+  }
+  dt[t] = (uint32_t)lower_bound_in(fk, 0, np, (uint64_t)t << (64 - kDirectBits));
 }
 
 hipError_t fit_pieces(const uint64_t* keys, uint64_t n, const LearnedArrays& a, uint32_t max_pieces,
@@ -417,8 +431,10 @@ hipError_t fit_pieces(const uint64_t* keys, uint64_t n, const LearnedArrays& a, 
   }
   {
     ProfScope ps("learned_pieces", s);
-    learned_pieces<<<(max_pieces + 3) / 4, 256, 0, s>>>(keys, n, a.xb, a.lp, max_pieces, a.fk,
-                                                        a.pr);
+    learned_pieces<<<(max_pieces + 3) / 4, 256, 0, s>>>(keys, n, a.lp, max_pieces, a.fk, a.pr,
+                                                        a.ps);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    learned_direct<<<(kDirectSlots + 1 + 255) / 256, 256, 0, s>>>(a.fk, a.lp, n, a.ps, a.dt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -433,7 +449,8 @@ uint32_t learned_max_pieces(uint64_t n) { return (uint32_t)(n / kPiece + kLeaves
 size_t learned_model_bytes(uint64_t n) {
   const uint64_t np = learned_max_pieces(n);
   return align256((kLeaves + 1) * 4) + align256((kRouteSlots + 1) * 4) +
-         align256((kLeaves + 1) * 8) + align256(np * 8) + align256(np * sizeof(PieceRec));
+         align256((kLeaves + 1) * 8) + align256(np * 8) + align256(np * sizeof(PieceRec)) +
+         align256((np + 1) * 4) + align256((kDirectSlots + 1) * 4);
 }
 
 LearnedArrays learned_carve(void* base, uint64_t n) {
@@ -444,7 +461,9 @@ LearnedArrays learned_carve(void* base, uint64_t n) {
   a.rt = (uint32_t*)p;   p += align256((kRouteSlots + 1) * 4);
   a.lp = (uint2*)p;      p += align256((kLeaves + 1) * 8);
   a.fk = (uint64_t*)p;   p += align256(np * 8);
-  a.pr = (PieceRec*)p;
+  a.pr = (PieceRec*)p;   p += align256(np * sizeof(PieceRec));
+  a.ps = (uint32_t*)p;   p += align256((np + 1) * 4);
+  a.dt = (uint32_t*)p;
   a.max_pieces = (uint32_t)np;
   return a;
 }

@@ -569,7 +569,8 @@ __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ 
 // domain: then |e| < 2^31, exact in 32-bit arithmetic.  Cells sit in one
 // word: x | y << 32, or x | y << 21 | z << 42.
 struct QueryFilter {
-  float acc, rej;  // limits on sum e^2 (or per-axis |e|); acc = not a number: filter off
+  float acc, rej;  // limits on sum e^2 (or per-axis |e|); filter off: acc = not a number
+                   // and rej = +inf, so that neither comparison decides a candidate
   uint32_t c[3];   // the query's cell per axis (low 32 bits)
   uint32_t pad[3];
 };
@@ -599,7 +600,10 @@ __global__ __launch_bounds__(256) void query_filters(const double* __restrict__ 
     f.acc = (float)(R * R * (1.0 - 0x1p-16) - slack);
     f.rej = (float)(R * R * (1.0 + 0x1p-16) + slack);
   }
-  if (!on) f.acc = __uint_as_float(0xFFFFFFFFu);
+  if (!on) {   // undecided for every candidate: the exact test decides
+    f.acc = __uint_as_float(0xFFFFFFFFu);
+    f.rej = __builtin_inff();
+  }
   out[j] = f;
 }
 
@@ -708,15 +712,22 @@ __global__ __launch_bounds__(256) void compact_test(
         }
         uint64_t cv[ROWS];
 #pragma unroll
-        for (int jr = 0; jr < ROWS; ++jr) cv[jr] = act[jr] ? cells[pos[jr]] : 0ull;
+        for (int jr = 0; jr < ROWS; ++jr) cv[jr] = cells[pos[jr]];   // pos 0 when inactive
+        bool und[ROWS];
+        bool any = false;
 #pragma unroll
         for (int jr = 0; jr < ROWS; ++jr) {
-          const QueryFilter& f = qf[jr];
-          const int vd =
-              !act[jr] ? 0 : f.acc == f.acc ? cell_check<DIM, WINDOW>(cv[jr], f) : -1;
+          const int vd = act[jr] ? cell_check<DIM, WINDOW>(cv[jr], qf[jr]) : 0;
           hit[jr] = vd == 1;
-          if (vd < 0)
-            hit[jr] = exact_hit<DIM>(q, delta, pts, via, qrow[jr], pos[jr], WINDOW);
+          und[jr] = vd < 0;
+          any = any || und[jr];
+        }
+        // The candidates their cells leave undecided (rare) take the exact
+        // test, behind one branch for the whole group.
+        if (__ballot(any) != 0) {
+#pragma unroll
+          for (int jr = 0; jr < ROWS; ++jr)
+            if (und[jr]) hit[jr] = exact_hit<DIM>(q, delta, pts, via, qrow[jr], pos[jr], WINDOW);
         }
       } else {
         double qx[ROWS], qy[ROWS], qz[ROWS], dd[ROWS];

@@ -11,6 +11,7 @@
 //   keys[n], q[2m] (f64), delta[m] (f64),
 //   search 1 (learned): xb[4097] u32, rt[65537] u32, lp[4097] (u32 x2),
 //     npieces, fk[npieces], pr[npieces] (f64 slope, i32 elo, i32 ehi),
+//     ps[npieces + 1] u32, dt[2^20 + 1] u32,
 //   with_occ: occ[words] u32 preceded by words.
 // Output: for each query and each of its 4 lanes, (b0, e0, b1, e1) u64 and
 // then nr (u32 per query) -- the same slots the kernel writes.
@@ -112,6 +113,7 @@ int main(int argc, char** argv) {
   std::vector<uint2> lp;
   std::vector<uint64_t> fk;
   std::vector<PieceRec> pr;
+  std::vector<uint32_t> ps, dt;
   LearnedView lv{};
   if (search == 1) {
     xb = take<uint32_t>(f, kLeaves + 1);
@@ -120,7 +122,9 @@ int main(int argc, char** argv) {
     const uint64_t np = take<uint64_t>(f, 1)[0];
     fk = take<uint64_t>(f, np);
     pr = take<PieceRec>(f, np);
-    lv = LearnedView{xb.data(), rt.data(), lp.data(), fk.data(), pr.data()};
+    ps = take<uint32_t>(f, np + 1);
+    dt = take<uint32_t>(f, kDirectSlots + 1);
+    lv = LearnedView{xb.data(), rt.data(), lp.data(), fk.data(), pr.data(), ps.data(), dt.data()};
   }
   std::vector<uint32_t> occ;
   if (with_occ) {

@@ -23,7 +23,7 @@ SRC = os.path.join(ROOT, "tests", "cpu", "lane_check.cpp")
 CSRC = os.path.join(ROOT, "paper_2508_19891_amd", "csrc")
 ROCM_INCLUDE = "/opt/rocm/include"
 
-LEAVES, ROUTE_SLOTS, PIECE = 4096, 1 << 16, 256
+LEAVES, ROUTE_SLOTS, PIECE, DIRECT_BITS = 4096, 1 << 16, 256, 20
 
 
 @pytest.fixture(scope="module")
@@ -42,9 +42,11 @@ def harness(tmp_path_factory):
 def learned_model(keys, rng, empty_frac=0.1):
     """Arrays of a learned index over sorted keys in the library's layout:
     router boundaries at key quantiles (input X = key >> 40), its bracket
-    table, leaves cut into pieces of 256 keys, and per piece a slope and the
-    exact window of (lower bound - prediction) over the stored keys; a
-    fraction of pieces get an empty window instead."""
+    table, leaves cut into pieces of 256 keys, per piece its first index, a
+    slope and the exact window of (lower bound - prediction) over the
+    stored keys up to the next piece's first key, and the table of how many
+    pieces start below each 20-bit key prefix; a fraction of pieces get an
+    empty window instead."""
     n = len(keys)
     X = (keys >> np.uint64(40)).astype(np.int64)
     inner = np.floor(np.quantile(X, np.arange(1, LEAVES) / LEAVES)).astype(np.int64)
@@ -63,6 +65,10 @@ def learned_model(keys, rng, empty_frac=0.1):
     E = S[leaf_of_piece + 1]
     Rn = np.minimum(R + PIECE, E)
     fk = keys[R]
+    ps = np.concatenate([R, [n]]).astype(np.uint32)
+    prefix = np.arange((1 << DIRECT_BITS) + 1, dtype=np.uint64) << np.uint64(64 - DIRECT_BITS)
+    dt = np.searchsorted(fk, prefix[:-1], side="left")
+    dt = np.concatenate([dt, [npieces]]).astype(np.uint32)
     last = keys[Rn - 1]
     span = (last - fk).astype(np.float64)
     slope = np.where(span > 0, (Rn - R).astype(np.float64) / np.maximum(span, 1.0), 0.0)
@@ -87,7 +93,7 @@ def learned_model(keys, rng, empty_frac=0.1):
     pr = np.zeros(npieces, dtype=[("s", "<f8"), ("elo", "<i4"), ("ehi", "<i4")])
     pr["s"], pr["elo"], pr["ehi"] = slope, err_lo, err_hi
     del idx
-    return xb, rt, lp, fk.astype(np.uint64), pr
+    return xb, rt, lp, fk.astype(np.uint64), pr, ps, dt
 
 
 def occupancy_bits(keys):
@@ -111,13 +117,15 @@ def run_harness(exe, tmp_path, keys, q, d, curve, refine, search, model=None, oc
         np.ascontiguousarray(q, np.float64).tofile(f)
         np.ascontiguousarray(d, np.float64).tofile(f)
         if search == 1:
-            xb, rt, lp, fk, pr = model
+            xb, rt, lp, fk, pr, ps, dt = model
             xb.tofile(f)
             rt.tofile(f)
             lp.tofile(f)
             np.array([len(fk)], np.uint64).tofile(f)
             fk.tofile(f)
             pr.tofile(f)
+            ps.tofile(f)
+            dt.tofile(f)
         if occ is not None:
             np.array([len(occ)], np.uint64).tofile(f)
             occ.tofile(f)
