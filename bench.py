@@ -423,7 +423,8 @@ def serving_bench(args, sfc, workload, torch):
            "mix": "40% query, 40% insert, 20% erase batches of 2^U[10,16]"}
     kw = {"sync": {}, "queued": {"slots": 3, "slot_queries": 1 << 20, "slot_ids": 1 << 27,
                                  "slot_rows": 1 << 24},
-          "overlap": {"streams": 3, "budget_bytes": 2 << 30, "slot_queries": 1 << 17}}
+          "overlap": {"streams": 3, "budget_bytes": 2 << 30,
+                      "slot_queries": 1 << args.serving_batch_log2}}
 
     def one(rate, mode):
         idx = sfc.Index(init, sfc.MORTON, search=sfc.LEARNED, refine=True)
@@ -482,6 +483,8 @@ def main():
                          "by side on their own streams, admitted by memory)")
     ap.add_argument("--serving-loads", default="0.5,0.8,0.95",
                     help="offered loads, as fractions of the saturation rate")
+    ap.add_argument("--serving-batch-log2", type=int, default=17,
+                    help="overlap loop: most queries in one batch (log2)")
     ap.add_argument("--serving-profile", action="store_true",
                     help="run the serving leg even with --only-refined (for kernel traces)")
     ap.add_argument("--serving-n-log2", type=int, default=25)

@@ -821,13 +821,29 @@ __global__ __launch_bounds__(256) void compact_write_out(
   const uint64_t total_rows = total_all < row_end ? total_all : row_end;
   const uint64_t ntiles = total_rows > rbase ? (total_rows - rbase + kTileRows - 1) / kTileRows : 0;
   const bool write_ids = !whole || ntiles == 0 || tile_off[ntiles] <= cap;
+  // The next tile's masks and first positions are loaded while this tile is
+  // written (one row per thread of the first wave).
+  uint64_t nx_mask = 0;
+  uint32_t nx_base = 0;
+  uint64_t nx_off = 0;
+  auto fetch = [&](uint64_t t) {
+    const uint64_t r0 = rbase + t * kTileRows;
+    if (t < ntiles && tid < kTileRows) {
+      nx_mask = masks[t * kTileRows + tid];
+      nx_base = r0 + tid < total_rows ? row_meta[r0 + tid - rbase].x : 0u;
+    }
+    if (t < ntiles) nx_off = tile_off[t];
+  };
+  fetch(blockIdx.x);
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t trow0 = rbase + tile * kTileRows;
     if (tid < kTileRows) {
-      s_mask[tid] = masks[tile * kTileRows + tid];
-      s_base[tid] = trow0 + tid < total_rows ? row_meta[trow0 + tid - rbase].x : 0u;
+      s_mask[tid] = nx_mask;
+      s_base[tid] = nx_base;
     }
+    const uint64_t prefix = nx_off;
     __syncthreads();
+    fetch(tile + gridDim.x);
     if (tid < 64) {   // exclusive scan of the row counts (one wave)
       const uint32_t v = (uint32_t)__popcll(s_mask[tid]);
       uint32_t x = v;
@@ -840,7 +856,6 @@ __global__ __launch_bounds__(256) void compact_write_out(
       if (tid == 63) s_pre[kTileRows] = x;
     }
     __syncthreads();
-    const uint64_t prefix = tile_off[tile];
     if (tid <= kTileRows && trow0 + tid <= total_rows)
       row_pre[tile * kTileRows + tid] = prefix + s_pre[tid];
     const uint32_t hits = s_pre[kTileRows];
@@ -1081,7 +1096,7 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
 }
 
 // Blocks of the compaction kernels (grid-stride over tiles beyond this).
-constexpr uint64_t kCompactGrid = 4096;
+constexpr uint64_t kCompactGrid = 8192;
 
 hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, const uint64_t* keys,
                           uint64_t n, bool refine, uint32_t refine_min, const StreeView* sview,
