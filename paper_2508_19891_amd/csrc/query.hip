@@ -383,25 +383,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void r
   }
 }
 
-// The cells of every query that survive early termination, as a dense work
-// list of (query, cell) pairs (4 * query + cell) for the search.  One thread
-// per query; a block's pairs are contiguous, at a base taken with one atomic
-// on the list's length, so the list's order across blocks varies from run to
-// run -- the search writes each pair's results to the pair's own slots, so
-// results do not depend on it.  The slots of cells a query does not have are
-// cleared here; invalid queries (and bad set indices) raise the flag and list
-// no cell.
+// The cells of every query that survive early termination, as (query, cell)
+// pairs (4 * query + cell) for the search.  One thread per query; block b
+// lists its pairs at the start of its own region pairs[1024 b ..] and its
+// counts of pairs and of pruned cells in blk_cnt[b] and blk_pruned[b]
+// (pack_scan and pack_move then make the list dense, in query order).  No
+// atomic on a shared word: one per block, from every block of the grid,
+// serialises across the XCDs.  The slots of cells a query does not have are
+// cleared here; invalid queries (and bad set indices) raise the flag and
+// list no cell.
 template <int CURVE, bool REFINE>
 __global__ __launch_bounds__(256) void cells_pack(
     const double2* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint32_t* __restrict__ occ, const uint32_t* __restrict__ qset, uint32_t n_sets,
-    uint64_t* __restrict__ pairs, unsigned long long* pair_total, uint32_t* __restrict__ slot_begin,
-    uint32_t* __restrict__ slot_count, uint32_t* __restrict__ slot_rows, uint32_t* counters,
-    unsigned long long* pruned_total, const uint32_t* __restrict__ perm) {
+    uint64_t* __restrict__ pairs, uint32_t* __restrict__ blk_cnt,
+    uint32_t* __restrict__ slot_rows, uint32_t* counters,
+    uint32_t* __restrict__ blk_pruned, const uint32_t* __restrict__ perm) {
   __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
   __shared__ uint32_t s_cnt[4];
   __shared__ uint32_t s_pr[4];
-  __shared__ unsigned long long s_base;
   if (CURVE == SFC_CURVE_HILBERT)
     for (int i = threadIdx.x; i < 1024; i += 256) lut[i] = kHilbertLutConst.v[i];
   __syncthreads();
@@ -430,19 +430,13 @@ __global__ __launch_bounds__(256) void cells_pack(
         nr = (uint32_t)query_ranges<CURVE>(lut, qq.x, qq.y, d, lo, hi, occ, &pr);
       }
     }
-    for (uint32_t r = nr; r < 4; ++r) {
-      if (!REFINE) {
-        slot_begin[4 * j + r] = 0;
-        slot_count[4 * j + r] = 0;
-        slot_rows[4 * j + r] = 0;
-      } else {
-        for (uint32_t h = 0; h < 2; ++h) {
-          slot_begin[8 * j + 2 * r + h] = 0;
-          slot_count[8 * j + 2 * r + h] = 0;
-          slot_rows[8 * j + 2 * r + h] = 0;
-        }
-      }
-    }
+    // The rows of every slot of the query start at zero (one 16- or 32-byte
+    // store); the search then writes the slots of the listed cells.  The
+    // row scan and the row expansion read a slot's first index and count
+    // only when it has rows, so those need no clearing.
+    uint4* sr = (uint4*)(slot_rows + (REFINE ? 8 : 4) * j);
+    sr[0] = make_uint4(0, 0, 0, 0);
+    if (REFINE) sr[1] = make_uint4(0, 0, 0, 0);
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&counters[2], kErrInvalidQuery);
   // Block-exclusive offsets of the cell counts: wave prefix, then waves.
@@ -461,14 +455,65 @@ __global__ __launch_bounds__(256) void cells_pack(
   uint32_t before = 0;
   for (uint32_t w = 0; w < wv; ++w) before += s_cnt[w];
   if (threadIdx.x == 0) {
-    const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-    s_base = tot ? atomicAdd(pair_total, (unsigned long long)tot) : 0;
-    const uint32_t p = s_pr[0] + s_pr[1] + s_pr[2] + s_pr[3];
-    if (p) atomicAdd(pruned_total, (unsigned long long)p);
+    blk_cnt[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    blk_pruned[blockIdx.x] = s_pr[0] + s_pr[1] + s_pr[2] + s_pr[3];
   }
-  __syncthreads();
-  const uint64_t o = s_base + before + inc - nr;
+  const uint64_t o = (uint64_t)blockIdx.x * 1024 + before + inc - nr;
   for (uint32_t r = 0; r < nr; ++r) pairs[o + r] = 4 * j + r;
+}
+
+// One workgroup: the exclusive scan of the blocks' pair counts (blk_pre, and
+// the list's length in *pair_total) and the sum of their pruned cells.
+__global__ __launch_bounds__(1024) void pack_scan(const uint32_t* __restrict__ blk_cnt,
+                                                  const uint32_t* __restrict__ blk_pruned,
+                                                  uint32_t nblk, uint32_t* __restrict__ blk_pre,
+                                                  unsigned long long* pair_total,
+                                                  unsigned long long* pruned_total) {
+  __shared__ uint32_t s_w[16];
+  __shared__ unsigned long long s_p[16];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t carry = 0;
+  unsigned long long pruned = 0;
+  for (uint32_t b0 = 0; b0 < nblk; b0 += 1024) {
+    const uint32_t b = b0 + tid;
+    const uint32_t v = b < nblk ? blk_cnt[b] : 0u;
+    pruned += b < nblk ? blk_pruned[b] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) s_w[wv] = x;
+    __syncthreads();
+    uint32_t before = carry;
+    for (uint32_t w = 0; w < wv; ++w) before += s_w[w];
+    if (b < nblk) blk_pre[b] = before + x - v;
+    uint32_t all = 0;
+    for (uint32_t w = 0; w < 16; ++w) all += s_w[w];
+    carry += all;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) pruned += __shfl_xor(pruned, o, 64);
+  if (lane == 0) s_p[wv] = pruned;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long p = 0;
+    for (int w = 0; w < 16; ++w) p += s_p[w];
+    *pair_total = carry;
+    *pruned_total = p;
+  }
+}
+
+// Block b moves its region's pairs to their place in the dense list.
+__global__ __launch_bounds__(256) void pack_move(const uint64_t* __restrict__ pairs_in,
+                                                 const uint32_t* __restrict__ blk_cnt,
+                                                 const uint32_t* __restrict__ blk_pre,
+                                                 uint64_t* __restrict__ pairs_out) {
+  const uint32_t c = blk_cnt[blockIdx.x], at = blk_pre[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < c; i += 256)
+    pairs_out[at + i] = pairs_in[(uint64_t)blockIdx.x * 1024 + i];
 }
 
 // The candidates are laid out in rows of 64: each query slot (segment) s
@@ -1047,11 +1092,18 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   }
   if (dense) {
     const uint32_t qb = (uint32_t)((m + 255) / 256);
+    // Until the row scan (after the search) fills them: the row offsets hold
+    // each block's region of pairs (4m entries at most), and the query row
+    // counts the blocks' counts, pruned cells and exclusive prefixes.
+    uint64_t* regions = qs.row_off;
+    uint32_t* blk_cnt = qs.qrows;
+    uint32_t* blk_pruned = qs.qrows + qb;
+    uint32_t* blk_pre = qs.qrows + 2 * (uint64_t)qb;
     ProfScope ps("cells_pack", s);
 #define SFC_CELLS(C, R)                                                                    \
   cells_pack<C, R><<<qb, 256, 0, s>>>((const double2*)q, delta, m, occ, qset, n_sets,       \
-                                      qs.pairs, total, qs.slot_begin, qs.slot_count,        \
-                                      qs.slot_rows, qs.counters, cand + 3, perm)
+                                      regions, blk_cnt, qs.slot_rows, qs.counters,          \
+                                      blk_pruned, perm)
     if (curve == SFC_CURVE_HILBERT) {
       if (refine) SFC_CELLS(SFC_CURVE_HILBERT, true);
       else SFC_CELLS(SFC_CURVE_HILBERT, false);
@@ -1060,6 +1112,10 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
       else SFC_CELLS(SFC_CURVE_MORTON, false);
     }
 #undef SFC_CELLS
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    pack_scan<<<1, 1024, 0, s>>>(blk_cnt, blk_pruned, qb, blk_pre, total, cand + 3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    pack_move<<<qb, 256, 0, s>>>(regions, blk_cnt, blk_pre, qs.pairs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     pairs = qs.pairs;
     pair_total = (const uint64_t*)total;
