@@ -295,6 +295,34 @@ def early_term_bench(args, sfc, workload, torch, pts_c2):
         idx.close()
     assert out["plain"]["reported"] == out["early_term"]["reported"]
     out["speedup_batch"] = out["plain"]["ms_per_batch"] / out["early_term"]["ms_per_batch"]
+    # The paper's own empty and sparse queries: 10^7 normal points, 10^6
+    # uniform square windows of small sides, Hilbert, refined ranges.
+    nw, mw = 10_000_000, 1_000_000
+    wl = workload.square_windows(n=nw, m=mw, side=1e-7, points="normal")
+    pw = torch.as_tensor(wl.points).to(dev)
+    qw = torch.as_tensor(wl.queries).to(dev)
+    offw = torch.empty(mw + 1, dtype=torch.int64, device=dev)
+    rows = []
+    for side in (1e-7, 1e-5, 1e-4):
+        dw = torch.full((mw,), side / 2, dtype=torch.float64, device=dev)
+        res = {"side": side}
+        for name, et in (("plain", False), ("early_term", True)):
+            idx = sfc.Index(pw, sfc.HILBERT, refine=True, early_term=et, metric=sfc.LINF)
+            _, ids0 = idx.query(qw, dw)
+            ow = torch.empty(ids0.numel() + 1024, dtype=torch.int32, device=dev)
+            res["reported"] = int(ids0.numel())
+            for _ in range(max(1, args.warmup)):
+                idx.query(qw, dw, out_ids=ow, out_offsets=offw)
+            ms, _ = timed_calls(lambda: idx.query(qw, dw, out_ids=ow, out_offsets=offw),
+                                args.steps)
+            res[f"ms_{name}"] = ms
+            idx.close()
+        res["speedup_batch"] = res["ms_plain"] / res["ms_early_term"]
+        rows.append(res)
+    out["paper_windows"] = {"workload": f"normal_n{nw}_uniformq_m{mw}_square_windows_hilbert",
+                            "sides": rows}
+    del pw, qw
+    torch.cuda.empty_cache()
     return out
 
 
@@ -846,6 +874,9 @@ def headline(args, detail: dict, n: int, m: int, ms_step: float, ms_median: floa
         out["early_termination"] = {"speedup_batch": _r(et["speedup_batch"]),
                                     "ms_plain": _r(et["plain"]["ms_per_batch"]),
                                     "ms_early_term": _r(et["early_term"]["ms_per_batch"])}
+        if "paper_windows" in et:
+            out["early_termination"]["speedup_windows"] = {
+                f"{r['side']:g}": _r(r["speedup_batch"], 3) for r in et["paper_windows"]["sides"]}
     sv = detail.get("serving")
     mode = next((k for k in ("overlap", "queued", "sync") if sv and k in sv), None)
     if mode:

@@ -459,9 +459,11 @@ sfc_status sfc_occupancy_copy(const sfc_index* h, uint32_t* out, uint64_t words)
  * prediction) over every query key that can reach it.  A lower bound
  * searches that window, is checked against its neighbours, and falls back to
  * a full binary search if the check fails, so results equal plain binary
- * search for any model.  Queries evaluate the router through its exact
- * tabulation (the first input of every leaf, found by evaluating the
- * network), which gives the same leaf for every key.
+ * search for any model.  The pieces of all leaves tile the sorted keys in
+ * key order, so a query takes the last piece whose first key is below its
+ * key, found through a table of how many pieces start below each 20-bit
+ * key prefix (the router itself, and its exact tabulation, serve the fit);
+ * each piece's window covers every key up to the next piece's first key.
  * The router is trained on the GPU (Adam, mean squared error to rank/n over
  * 2^16 evenly spaced sorted keys, batches of 128), starting from ramps
  * placed at the sample quantiles.

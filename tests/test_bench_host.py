@@ -82,7 +82,10 @@ def test_headline_is_compact_and_complete():
                                                                  "ms_per_batch": 2.8},
                           "bsearch": {"search_ms": 1.05, "ms_per_batch": 2.98}},
         "early_termination": {"speedup_batch": 0.92, "plain": {"ms_per_batch": 0.65},
-                              "early_term": {"ms_per_batch": 0.70}},
+                              "early_term": {"ms_per_batch": 0.70},
+                              "paper_windows": {"sides": [{"side": 1e-7, "speedup_batch": 1.2},
+                                                          {"side": 1e-5, "speedup_batch": 1.1},
+                                                          {"side": 1e-4, "speedup_batch": 1.15}]}},
         "serving": {"overlap": {"saturation": load, "load_0.95": load}},
         "cpu_baseline": {"value": 2.8e5, "unit": "queries/s", "cores": 16, "kind": "oracle",
                          "sample": "oracle build of all 16777216 points on 1 thread (3.09 s) + "
