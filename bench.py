@@ -432,8 +432,9 @@ def three_d_bench(args, sfc, workload, torch):
 
 
 def serving_bench(args, sfc, workload, torch):
-    """Poisson stream of query / insert / erase batches (40/40/20, sizes
-    2^U[10,16]) over 2^25 clustered points, Morton keys, learned search:
+    """Poisson stream of query / insert / erase batches (40/40/20 unless
+    --serving-mix says otherwise, sizes 2^U[10,16]) over 2^25 clustered
+    points, Morton keys, learned search:
     first the saturation throughput (every request queued at time 0), then
     arrivals at fractions of it; p50/p99 from arrival to completion.  Loops:
     sync (each tick's batch answered before the next tick), queued (batches
@@ -442,13 +443,16 @@ def serving_bench(args, sfc, workload, torch):
     2 GiB budget)."""
     from paper_2508_19891_amd import serving
     dev = torch.device("cuda:0")
-    trace = workload.serving_trace(n0=1 << args.serving_n_log2, requests=args.serving_requests)
+    mix = tuple(float(x) for x in args.serving_mix.split(","))
+    trace = workload.serving_trace(n0=1 << args.serving_n_log2, requests=args.serving_requests,
+                                   mix=mix)
     log(f"serving: n0={len(trace.initial)}, {len(trace.kind)} requests")
     pools = serving.Pools.upload(trace, dev)
     init = torch.as_tensor(trace.initial).to(dev)
     out_ids = torch.empty(1 << 26, dtype=torch.int32, device=dev)
     out = {"workload": trace.name, "curve": "morton", "search": "learned",
-           "mix": "40% query, 40% insert, 20% erase batches of 2^U[10,16]"}
+           "mix": (f"{100 * mix[0]:.0f}% query, {100 * mix[1]:.0f}% insert, "
+                   f"{100 * mix[2]:.0f}% erase batches of 2^U[10,16]")}
     kw = {"sync": {}, "queued": {"slots": 3, "slot_queries": 1 << 20, "slot_ids": 1 << 27,
                                  "slot_rows": 1 << 24},
           "overlap": {"streams": 3, "budget_bytes": 2 << 30,
@@ -516,6 +520,8 @@ def main():
     ap.add_argument("--serving-profile", action="store_true",
                     help="run the serving leg even with --only-refined (for kernel traces)")
     ap.add_argument("--serving-n-log2", type=int, default=25)
+    ap.add_argument("--serving-mix", default="0.4,0.4,0.2",
+                    help="fractions of query, insert and erase requests in the serving trace")
     ap.add_argument("--detail-out", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
                     help="file that receives every leg's figures (empty: none)")
     ap.add_argument("--copy-probe", action="store_true",

@@ -372,8 +372,8 @@ void sfc_graph_free(sfc_graph* g);   /* NULL-safe; waits for h's stream */
  * HIP events and records the fastest for the size bucket (floor(log2)) of
  * that data; later calls of this process with sizes in the same bucket use
  * it.  Results are identical for every shape.
- * sfc_autotune_build: keys per thread of the radix passes (8, 12, 16; 3 timed
- *   builds each; ms[3], *best = the chosen count).  set_off/n_sets as in
+ * sfc_autotune_build: keys of a radix tile per 256 (8, 12, 16, 20, 24; 3
+ *   timed builds each; ms[5], *best = the chosen count).  set_off/n_sets as in
  *   sfc_build_sets, or NULL/0.
  * sfc_autotune_query: row groups of the exact-test kernel (5 shapes, 3 timed
  *   batches each; ms[5], *best = the chosen shape index), for the bucket of
@@ -385,6 +385,17 @@ sfc_status sfc_autotune_build(const double* xy, uint64_t n, const uint64_t* set_
 sfc_status sfc_autotune_query(sfc_index* h, const double* q, const double* delta,
                               const uint32_t* qset, uint64_t m, uint64_t* offsets,
                               uint32_t* ids, uint64_t ids_cap, int* best, double* ms);
+
+/* Pins a launch shape for the size bucket (floor(log2)) of `size`, as the
+ * autotuner records one: what = SFC_TUNE_SORT_ITEMS (keys of a radix tile per
+ * 256: 8, 12, 16, 20 or 24; size = points of the build) or
+ * SFC_TUNE_TEST_SHAPE (the exact-test kernel's row groups, 0..4; size = the
+ * batch's candidate rows); value -1 removes the pin, so that the default
+ * applies again.  Results are identical for every shape.  SFC_ERR_INVALID
+ * for another `what` or value. */
+#define SFC_TUNE_SORT_ITEMS 0
+#define SFC_TUNE_TEST_SHAPE 1
+sfc_status sfc_tune_pin(int what, uint64_t size, int value);
 
 /* Number of points currently reported by queries (live points). */
 uint64_t sfc_size(const sfc_index* h);

@@ -1609,15 +1609,15 @@ extern "C" {
 sfc_status sfc_autotune_build(const double* xy, uint64_t n, const uint64_t* set_off,
                               uint32_t n_sets, const sfc_options* opt, int* best, double* ms) {
   if (n == 0 || !xy) return SFC_ERR_INVALID;
-  static const int kItems[3] = {8, 12, 16};
+  static const int kItems[5] = {8, 12, 16, 20, 24};
   sfc_options o;
   sfc_default_options(&o);
   if (opt) o = *opt;
   o.search = SFC_SEARCH_BINARY;
-  double t[3] = {0, 0, 0};
+  double t[5] = {0, 0, 0, 0, 0};
   int pick = 16;
   double tb = 1e30;
-  for (int v = 0; v < 3; ++v) {
+  for (int v = 0; v < 5; ++v) {
     sfc::set_tuned(sfc::kTuneSortItems, n, kItems[v]);
     sfc_status st = time_ms((hipStream_t)o.stream, 3, [&] {
       sfc_index* h = nullptr;
@@ -1633,7 +1633,7 @@ sfc_status sfc_autotune_build(const double* xy, uint64_t n, const uint64_t* set_
   }
   sfc::set_tuned(sfc::kTuneSortItems, n, pick);
   if (best) *best = pick;
-  if (ms) for (int v = 0; v < 3; ++v) ms[v] = t[v];
+  if (ms) for (int v = 0; v < 5; ++v) ms[v] = t[v];
   return SFC_OK;
 }
 
@@ -1669,6 +1669,21 @@ sfc_status sfc_autotune_query(sfc_index* h, const double* q, const double* delta
   if (best) *best = pick;
   if (ms) for (int v = 0; v < 5; ++v) ms[v] = t[v];
   return SFC_OK;
+}
+
+sfc_status sfc_tune_pin(int what, uint64_t size, int value) {
+  if (what == SFC_TUNE_SORT_ITEMS) {
+    if (value != -1 && value != 8 && value != 12 && value != 16 && value != 20 && value != 24)
+      return SFC_ERR_INVALID;
+    sfc::set_tuned(sfc::kTuneSortItems, size, value);
+    return SFC_OK;
+  }
+  if (what == SFC_TUNE_TEST_SHAPE) {
+    if (value < -1 || value > 4) return SFC_ERR_INVALID;
+    sfc::set_tuned(sfc::kTuneTestShape, size, value);
+    return SFC_OK;
+  }
+  return SFC_ERR_INVALID;
 }
 
 void sfc_free(sfc_index* h) {

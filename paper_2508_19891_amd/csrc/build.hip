@@ -84,18 +84,32 @@ __global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ 
   const uint64_t end = base + tile_len < n ? base + tile_len : n;
   const uint32_t w = threadIdx.x >> 6;
   bool bad = false;
-  for (uint64_t i = base + threadIdx.x; i < end; i += 256) {
-    const double2 p = xy[i];
-    if (xy_copy) xy_copy[i] = p;
-    uint64_t key = 0;
-    if (in_unit(p.x) && in_unit(p.y)) {
-      const uint32_t ux = quantize(p.x), uy = quantize(p.y);
-      key = CURVE == SFC_CURVE_HILBERT ? hilbert_key_lut(lut, ux, uy) : morton_key(ux, uy);
-    } else {
-      bad = true;
+  // Eight points in flight per thread: positions past the tile load its last
+  // point (no branch around the loads) and are then skipped.
+  constexpr int kBatch = 8;
+  for (uint64_t i0 = base + threadIdx.x; i0 < end; i0 += 256 * kBatch) {
+    double2 pb[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const uint64_t i = i0 + 256u * j;
+      pb[j] = xy[i < end ? i : end - 1];
     }
-    keys[i] = key;
-    if (counts) atomicAdd(&h[w][(key >> count_shift) & 255u], 1u);
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const uint64_t i = i0 + 256u * j;
+      if (i >= end) continue;
+      const double2 p = pb[j];
+      if (xy_copy) xy_copy[i] = p;
+      uint64_t key = 0;
+      if (in_unit(p.x) && in_unit(p.y)) {
+        const uint32_t ux = quantize(p.x), uy = quantize(p.y);
+        key = CURVE == SFC_CURVE_HILBERT ? hilbert_key_lut(lut, ux, uy) : morton_key(ux, uy);
+      } else {
+        bad = true;
+      }
+      keys[i] = key;
+      if (counts) atomicAdd(&h[w][(key >> count_shift) & 255u], 1u);
+    }
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(err, kErrDomain);
   if (counts) store_tile_counts(h, counts, tiles, blockIdx.x);
@@ -190,10 +204,23 @@ __global__ __launch_bounds__(256) void tile_hist(const uint64_t* __restrict__ ki
   const uint64_t base = (uint64_t)blockIdx.x * tile_len;
   const uint64_t end = base + tile_len < n ? base + tile_len : n;
   const uint32_t w = threadIdx.x >> 6;
-  for (uint64_t i = base + threadIdx.x; i < end; i += 256) {
-    const uint32_t d = SETPASS ? pass_digit<true>(0, vin[i], shift, set_id)
-                               : pass_digit<false>(kin[i], 0, shift, set_id);
-    atomicAdd(&h[w][d], 1u);
+  // Eight loads in flight per thread before the counts are taken.
+  constexpr int kBatch = 8;
+  for (uint64_t i0 = base + threadIdx.x; i0 < end; i0 += 256 * kBatch) {
+    // Positions past the tile load its last element (no branch around the
+    // loads) and are not counted.
+    uint32_t dg[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const uint64_t i = i0 + 256u * j;
+      const uint64_t ic = i < end ? i : end - 1;
+      const uint32_t d = SETPASS ? pass_digit<true>(0, vin[ic], shift, set_id)
+                                 : pass_digit<false>(kin[ic], 0, shift, set_id);
+      dg[j] = i < end ? d : (uint32_t)kRadix;
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j)
+      if (dg[j] < (uint32_t)kRadix) atomicAdd(&h[w][dg[j]], 1u);
   }
   store_tile_counts(h, counts, tiles, blockIdx.x);
 }
@@ -209,10 +236,17 @@ __global__ __launch_bounds__(256) void digit_scan(const uint32_t* __restrict__ c
   uint32_t carry = 0;
   for (uint64_t b = 0; b < tiles; b += 256 * 16) {
     const uint64_t f = b + (uint64_t)threadIdx.x * 16;
+    // Sixteen loads in flight: entries past the end load the last one (no
+    // branch around the loads) and count as zero.
     uint32_t v[16], sum = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      v[i] = f + i < tiles ? c[f + i] : 0u;
+      const uint64_t j = f + i < tiles ? f + i : tiles - 1;
+      v[i] = c[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (f + i >= tiles) v[i] = 0u;
       sum += v[i];
     }
     const uint32_t excl = block_excl_scan256(sum, s_tmp);
@@ -238,17 +272,27 @@ __device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t tiles) {
   return (b & 7) * per + (b >> 3);
 }
 
-// One stable pass of the LSD radix sort over the digit pass_digit(...).
+// Threads of a scatter workgroup: eight waves share one tile, each holding a
+// quarter of what a four-wave histogram workgroup covers per thread.
+constexpr int kScatterWaves = 8;
+constexpr int kScatterThreads = kScatterWaves * kWave;
+
+// One stable pass of the LSD radix sort over the digit pass_digit(...).  The
+// tile holds kSortThreads * ITEMS keys (the histogram kernels' tile); each of
+// the kScatterThreads threads ranks ITEMS * kSortThreads / kScatterThreads of
+// them.
 template <int ITEMS, bool FIRST, bool GATHER, bool SETPASS>
-__global__ __launch_bounds__(kSortThreads) void scatter_pass(
+__global__ __launch_bounds__(kScatterThreads) void scatter_pass(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
     const uint32_t* __restrict__ rel, const uint32_t* __restrict__ dtot, uint64_t tiles,
     uint32_t* err, const double2* __restrict__ xy_in, double2* __restrict__ xy_out,
     uint64_t* __restrict__ cells_out, int cell_curve, const uint32_t* __restrict__ set_id) {
   constexpr int kTile = kSortThreads * ITEMS;
+  constexpr int IT = kTile / kScatterThreads;
+  static_assert(IT * kScatterThreads == kTile, "tile must split over the scatter threads");
   __shared__ union {
-    uint32_t wave_hist[kSortWaves][kRadix];
+    uint32_t wave_hist[kScatterWaves][kRadix];
     struct {
       uint64_t k[kTile];
       uint32_t v[kTile];
@@ -256,20 +300,21 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
   } sm;
   __shared__ uint32_t s_local[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
-  __shared__ uint32_t s_tmp[kSortWaves];
+  __shared__ uint32_t s_tmp[kScatterWaves];
 
   const uint64_t tile = xcd_tile(blockIdx.x, tiles);
   if (tile >= tiles) return;   // the whole workgroup: no barrier is skipped by part of it
   const uint32_t tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  for (uint32_t i = tid; i < kSortWaves * kRadix; i += kSortThreads) (&sm.wave_hist[0][0])[i] = 0;
+  for (uint32_t i = tid; i < kScatterWaves * kRadix; i += kScatterThreads)
+    (&sm.wave_hist[0][0])[i] = 0;
   const uint64_t base = tile * kTile;
-  const uint64_t wbase = base + (uint64_t)w * (kWave * ITEMS);
+  const uint64_t wbase = base + (uint64_t)w * (kWave * IT);
 
-  uint64_t key[ITEMS];
-  uint32_t val[ITEMS];
-  uint32_t rank[ITEMS];
+  uint64_t key[IT];
+  uint32_t val[IT];
+  uint32_t rank[IT];
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
+  for (int i = 0; i < IT; ++i) {
     const uint64_t idx = wbase + (uint64_t)i * kWave + l;
     if (idx < n) {
       key[i] = kin[idx];
@@ -279,11 +324,12 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
       val[i] = 0xFFFFFFFFu;
     }
   }
-  // This tile's offset within each digit's bucket and the digit totals (read
-  // early, used after the ranking).
+  // Threads d < 256: this tile's offset within digit d's bucket and the
+  // digit's total (read early, used after the ranking).
   const uint32_t d = tid;
-  const uint32_t rl = rel[(uint64_t)d * tiles + tile];
-  const uint32_t dt = dtot[d];
+  const bool digit_thread = d < (uint32_t)kRadix;
+  const uint32_t rl = digit_thread ? rel[(uint64_t)d * tiles + tile] : 0u;
+  const uint32_t dt = digit_thread ? dtot[d] : 0u;
   __syncthreads();
 
   // Rank within the wave, in (item, lane) order: lanes holding the same digit
@@ -295,7 +341,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
   uint32_t* wh = sm.wave_hist[w];
   const uint64_t below_mask = lanemask_lt();
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
+  for (int i = 0; i < IT; ++i) {
     const uint32_t dg = pass_digit<SETPASS>(key[i], val[i], shift, set_id);
     uint64_t match = ~0ull;
 #pragma unroll
@@ -312,36 +358,42 @@ __global__ __launch_bounds__(kSortThreads) void scatter_pass(
   }
   __syncthreads();
 
-  // Thread d: tile count of digit d and per-wave exclusive bases.
+  // Thread d: tile count of digit d and per-wave exclusive bases.  The scans
+  // run over the first four waves (one thread per digit); the other waves
+  // pass zeros and take part only in the barriers.
   uint32_t tot = 0;
+  if (digit_thread) {
 #pragma unroll
-  for (int ww = 0; ww < kSortWaves; ++ww) {
-    const uint32_t c = sm.wave_hist[ww][d];
-    sm.wave_hist[ww][d] = tot;
-    tot += c;
+    for (int ww = 0; ww < kScatterWaves; ++ww) {
+      const uint32_t c = sm.wave_hist[ww][d];
+      sm.wave_hist[ww][d] = tot;
+      tot += c;
+    }
   }
   const uint32_t local = block_excl_scan256(tot, s_tmp);
   const uint32_t dbase = block_excl_scan256(dt, s_tmp);
-  s_local[d] = local;
-  s_gbase[d] = dbase + rl - local;
+  if (digit_thread) {
+    s_local[d] = local;
+    s_gbase[d] = dbase + rl - local;
+  }
   __syncthreads();
 
-  uint32_t lpos[ITEMS];
+  uint32_t lpos[IT];
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
+  for (int i = 0; i < IT; ++i) {
     const uint32_t dd = pass_digit<SETPASS>(key[i], val[i], shift, set_id);
     lpos[i] = s_local[dd] + sm.wave_hist[w][dd] + rank[i];
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
+  for (int i = 0; i < IT; ++i) {
     sm.st.k[lpos[i]] = key[i];
     sm.st.v[lpos[i]] = val[i];
   }
   __syncthreads();
 
   const uint32_t valid = (uint32_t)((n - base) < (uint64_t)kTile ? (n - base) : (uint64_t)kTile);
-  for (uint32_t j = tid; j < valid; j += kSortThreads) {
+  for (uint32_t j = tid; j < valid; j += kScatterThreads) {
     const uint64_t k = sm.st.k[j];
     const uint32_t v = sm.st.v[j];
     const uint32_t pos = s_gbase[pass_digit<SETPASS>(k, v, shift, set_id)] + j;
@@ -401,15 +453,19 @@ __global__ void gather_points3(const uint32_t* __restrict__ ids, const double* _
   }
 }
 
-// Keys per thread of a radix pass: 8, 12 or 16.  The environment variable
-// SFC_SORT_ITEMS overrides; else the autotuner's choice for this size; else 16.
+// Keys of a radix tile per histogram thread (the tile is 256 times this): 8,
+// 12, 16, 20 or 24.  The environment variable SFC_SORT_ITEMS overrides; else
+// the autotuner's choice for this size; else 24 from 2^23 keys on (tiles of
+// 6144 keys, two scatter workgroups per CU; at 2^24 keys the build takes
+// 0.81 ms against 0.84 with 4096-key tiles) and 16 below.
 int sort_items(uint64_t n) {
   static const int env = [] {
     const char* e = std::getenv("SFC_SORT_ITEMS");
     return e ? std::atoi(e) : 0;
   }();
-  int k = env ? env : tuned(kTuneSortItems, n);
-  return (k == 8 || k == 12) ? k : 16;
+  const int k = env ? env : tuned(kTuneSortItems, n);
+  if (k == 8 || k == 12 || k == 16 || k == 20 || k == 24) return k;
+  return n >= (1ull << 23) ? 24 : 16;
 }
 uint64_t sort_tile(uint64_t n) { return (uint64_t)kSortThreads * sort_items(n); }
 
@@ -543,10 +599,27 @@ __global__ __launch_bounds__(kChunkThreads) void chunk_sort(
   if (end <= start) return;
   const uint32_t len = (uint32_t)(end - start);
 
-  // The chunk into LDS in position order (coalesced).
-  for (uint32_t j = tid; j < len; j += kChunkThreads) {
-    sm.st.k[j] = keys[start + j];
-    sm.st.v[j] = ids[start + j];
+  // The chunk into LDS in position order (coalesced), every load of a lane
+  // in flight at once: slots past the chunk load its last entry and are not
+  // stored.
+  {
+    uint64_t kb[kChunkSlots];
+    uint32_t vb[kChunkSlots];
+#pragma unroll
+    for (int t = 0; t < kChunkSlots; ++t) {
+      const uint32_t j = tid + (uint32_t)t * kChunkThreads;
+      const uint64_t g = start + (j < len ? j : len - 1);
+      kb[t] = keys[g];
+      vb[t] = ids[g];
+    }
+#pragma unroll
+    for (int t = 0; t < kChunkSlots; ++t) {
+      const uint32_t j = tid + (uint32_t)t * kChunkThreads;
+      if (j < len) {
+        sm.st.k[j] = kb[t];
+        sm.st.v[j] = vb[t];
+      }
+    }
   }
   __syncthreads();
 
@@ -713,7 +786,7 @@ hipError_t launch_scatter(bool first, bool gather, bool setpass, int shift, uint
                           uint32_t* vout, uint64_t n, const uint32_t* rel, const uint32_t* dtot,
                           uint32_t* err, const double* xy, double* xy_out, uint64_t* cells_out,
                           int cell_curve, const uint32_t* set_id, hipStream_t s) {
-  const dim3 g((uint32_t)(((tiles + 7) / 8) * 8)), b(kSortThreads);
+  const dim3 g((uint32_t)(((tiles + 7) / 8) * 8)), b(kScatterThreads);
   const double2* xi = (const double2*)xy;
   double2* xo = (double2*)xy_out;
 #define SFC_PASS(F, G, S)                                                                      \
@@ -845,6 +918,8 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     switch (sort_items(n)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;
+      case 20: e = SFC_LAUNCH(20); break;
+      case 24: e = SFC_LAUNCH(24); break;
       default: e = SFC_LAUNCH(8); break;
     }
 #undef SFC_LAUNCH
@@ -907,6 +982,8 @@ hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t*
     switch (sort_items(n)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;
+      case 20: e = SFC_LAUNCH(20); break;
+      case 24: e = SFC_LAUNCH(24); break;
       default: e = SFC_LAUNCH(8); break;
     }
 #undef SFC_LAUNCH
@@ -976,6 +1053,8 @@ hipError_t order_queries(const double* q, uint64_t m, int curve, uint32_t* perm,
     switch (sort_items(m)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;
+      case 20: e = SFC_LAUNCH(20); break;
+      case 24: e = SFC_LAUNCH(24); break;
       default: e = SFC_LAUNCH(8); break;
     }
 #undef SFC_LAUNCH

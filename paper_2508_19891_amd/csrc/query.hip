@@ -714,6 +714,7 @@ __global__ __launch_bounds__(256) void compact_test(
     bool flag_overflow, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_hits,
     uint32_t* counters, const uint32_t* __restrict__ ins, const uint32_t* __restrict__ era,
     const uint32_t* __restrict__ qepoch, uint32_t epoch) {
+  static_assert(ROWS * ITERS == (int)kWaveRows, "a wave's groups cover its rows");
   __shared__ uint32_t s_cnt[4];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
@@ -722,18 +723,21 @@ __global__ __launch_bounds__(256) void compact_test(
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t wrow0 = rbase + tile * kTileRows + (uint64_t)w * kWaveRows;
     uint32_t cnt = 0;
+    // The records of the wave's rows, one per lane, in one load.
+    uint4 mdw = make_uint4(0, 0, 0, 0);
+    if (lane < (uint32_t)kWaveRows && wrow0 + lane < total_rows)
+      mdw = row_meta[wrow0 + lane - rbase];
+#pragma unroll
     for (int it = 0; it < ITERS; ++it) {
-      const uint64_t g0 = wrow0 + (uint64_t)it * ROWS;   // first row of the group
-      uint4 md = make_uint4(0, 0, 0, 0);
-      if (lane < (uint32_t)ROWS && g0 + lane < total_rows) md = row_meta[g0 + lane - rbase];
+      const uint4 md = mdw;   // rows it * ROWS .. it * ROWS + ROWS - 1 of the wave
       uint32_t pos[ROWS];
       uint32_t qrow[ROWS];
       bool act[ROWS];
 #pragma unroll
       for (int jr = 0; jr < ROWS; ++jr) {
-        const uint32_t pb = __builtin_amdgcn_readlane(md.x, jr);
-        const uint32_t nv = __builtin_amdgcn_readlane(md.y, jr);
-        const uint32_t qi = __builtin_amdgcn_readlane(md.z, jr);
+        const uint32_t pb = __builtin_amdgcn_readlane(md.x, it * ROWS + jr);
+        const uint32_t nv = __builtin_amdgcn_readlane(md.y, it * ROWS + jr);
+        const uint32_t qi = __builtin_amdgcn_readlane(md.z, it * ROWS + jr);
         const uint64_t p64 = (uint64_t)pb + lane;
         act[jr] = lane < nv && p64 < npts && qi < m;
         pos[jr] = act[jr] ? (uint32_t)p64 : 0u;

@@ -42,7 +42,7 @@ EXPORTS = [
     "sfc_learned_info_get", "sfc_learned_params", "sfc_learned_grad",
     "sfc_learned_shrink_windows", "sfc_build_sets", "sfc_query_sets", "sfc_graph_build",
     "sfc_graph_query", "sfc_graph_launch", "sfc_graph_wait", "sfc_graph_free",
-    "sfc_autotune_build", "sfc_autotune_query", "sfc_debug_chunk_tiles",
+    "sfc_autotune_build", "sfc_autotune_query", "sfc_tune_pin", "sfc_debug_chunk_tiles",
     "sfc_insert", "sfc_erase", "sfc_query_epochs", "sfc_hold_epochs", "sfc_retire",
     "sfc_compact", "sfc_update_info_get", "sfc_learned_route", "sfc_query_retry",
     "sfc_query_async", "sfc_occupancy_copy", "sfc_set_metric", "sfc_set_cell_filter",
@@ -196,6 +196,8 @@ def lib() -> ctypes.CDLL:
     L.sfc_autotune_build.restype = i32
     L.sfc_autotune_query.argtypes = [vp, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(i32), vp]
     L.sfc_autotune_query.restype = i32
+    L.sfc_tune_pin.argtypes = [i32, u64, i32]
+    L.sfc_tune_pin.restype = i32
     L.sfc_debug_sort_path.argtypes = [i32, ctypes.POINTER(i32)]
     L.sfc_debug_sort_path.restype = i32
     L.sfc_debug_chunk_tiles.argtypes = [u64]
@@ -726,13 +728,24 @@ def autotune_build(xy: torch.Tensor, curve: int = MORTON, set_off=None):
     opt.curve = curve
     opt.stream = current_stream_handle()
     best = ctypes.c_int(0)
-    ms = (ctypes.c_double * 3)()
+    ms = (ctypes.c_double * 5)()
     so = None if set_off is None else np.ascontiguousarray(set_off, np.uint64)
     _check(L.sfc_autotune_build(_ptr(xy), xy.shape[0],
                                 None if so is None else so.ctypes.data_as(ctypes.c_void_p),
                                 0 if so is None else len(so) - 1, ctypes.byref(opt),
                                 ctypes.byref(best), ms), "sfc_autotune_build")
-    return best.value, dict(zip((8, 12, 16), list(ms)))
+    return best.value, dict(zip((8, 12, 16, 20, 24), list(ms)))
+
+
+TUNE_SORT_ITEMS = 0
+TUNE_TEST_SHAPE = 1
+
+
+def tune_pin(what: int, size: int, value: int) -> None:
+    """Pins a launch shape for the size bucket of `size` (TUNE_SORT_ITEMS:
+    8, 12, 16, 20 or 24 keys of a radix tile per 256; TUNE_TEST_SHAPE: 0..4);
+    value -1 removes the pin."""
+    _check(lib().sfc_tune_pin(what, size, value), "sfc_tune_pin")
 
 
 def autotune_query(index: Index, q: torch.Tensor, delta: torch.Tensor,

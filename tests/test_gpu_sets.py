@@ -103,3 +103,17 @@ def test_query_sets_invalid_set():
     with pytest.raises(sfc.SfcError) as ei:
         idx.query_sets(dev(wl.queries), dev(wl.delta), dev(qset, torch.int32))
     assert ei.value.status == sfc.SFC_ERR_INVALID
+
+
+@pytest.mark.parametrize("items", [8, 16, 24])
+def test_sets_at_each_tile_size(items):
+    """The set passes of the plain sort at several radix tile sizes (pinned
+    for the batch's total size): the same per-set CSR as the oracle."""
+    wl = workload.batched_uneven(n_sets=24, log2_n=(6, 15), log2_m=(2, 8), curve=MORTON,
+                                 seed=40 + items)
+    n = len(wl.points)
+    sfc.tune_pin(sfc.TUNE_SORT_ITEMS, n, items)
+    try:
+        check_sets(wl, MORTON, refine=True).close()
+    finally:
+        sfc.tune_pin(sfc.TUNE_SORT_ITEMS, n, -1)

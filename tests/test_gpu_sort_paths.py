@@ -130,3 +130,28 @@ def test_plain_and_chunked_agree():
         sfc.debug_sort_path(0)
     for a, b in zip(out[0], out[1]):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("items", [8, 12, 16, 20, 24])
+def test_tile_sizes(items):
+    """Every radix tile size (pinned for the build's size, as the autotuner
+    records one) gives the oracle's arrays through both sorts; 250 001 points
+    leave a ragged last tile at each size (tiles of 256 x items keys)."""
+    n = 250_001
+    mix = workload.make_mixture(items, k=8, sigma=0.003, frac=0.8)
+    pts = workload.clustered_points(n, items + 1, mix)
+    sfc.tune_pin(sfc.TUNE_SORT_ITEMS, n, items)
+    try:
+        for force in (0, 1):
+            sfc.debug_sort_path(force)
+            check(pts, HILBERT)
+    finally:
+        sfc.debug_sort_path(0)
+        sfc.tune_pin(sfc.TUNE_SORT_ITEMS, n, -1)
+
+
+def test_tune_pin_rejects_unknown_shapes():
+    for what, value in ((sfc.TUNE_SORT_ITEMS, 10), (sfc.TUNE_SORT_ITEMS, 32),
+                        (sfc.TUNE_TEST_SHAPE, 5), (7, 0)):
+        with pytest.raises(sfc.SfcError):
+            sfc.tune_pin(what, 1000, value)
