@@ -439,8 +439,8 @@ def serving_bench(args, sfc, workload, torch):
     arrivals at fractions of it; p50/p99 from arrival to completion.  Loops:
     sync (each tick's batch answered before the next tick), queued (batches
     queued on the index's stream into three output slots), overlap (batches
-    side by side on three streams with their own scratch, admitted against a
-    2 GiB budget)."""
+    side by side on three streams, each keeping its scratch and outputs for
+    400 ids per query, admitted against a 2 GiB budget)."""
     from paper_2508_19891_amd import serving
     dev = torch.device("cuda:0")
     mix = tuple(float(x) for x in args.serving_mix.split(","))
@@ -455,7 +455,7 @@ def serving_bench(args, sfc, workload, torch):
                    f"{100 * mix[2]:.0f}% erase batches of 2^U[10,16]")}
     kw = {"sync": {}, "queued": {"slots": 3, "slot_queries": 1 << 20, "slot_ids": 1 << 27,
                                  "slot_rows": 1 << 24},
-          "overlap": {"streams": 3, "budget_bytes": 2 << 30,
+          "overlap": {"streams": 3, "budget_bytes": 2 << 30, "ids_per_query": 400,
                       "slot_queries": 1 << args.serving_batch_log2}}
 
     def one(rate, mode):

@@ -700,7 +700,10 @@ __device__ __forceinline__ bool exact_hit(const double* __restrict__ q,
 
 // Pass 1: the exact test of every candidate; per row the 64-bit mask of the
 // accepted lanes, per tile their number.  Each wave handles 16 consecutive
-// rows as ITERS groups of ROWS rows whose point loads are in flight together.
+// rows as ITERS groups of ROWS rows whose point loads are in flight together,
+// writes its 16 masks with one store (lane j: row j) and adds its count to
+// the tile's (zeroed before the launch), so that the waves of a workgroup
+// never wait for each other.
 // EPOCH: a candidate that passes the test also has to be visible at the
 // query's epoch (ins <= e < era); only those lanes read the epochs.
 // window: the square-window test instead of the Euclidean one.
@@ -715,7 +718,6 @@ __global__ __launch_bounds__(256) void compact_test(
     uint32_t* counters, const uint32_t* __restrict__ ins, const uint32_t* __restrict__ era,
     const uint32_t* __restrict__ qepoch, uint32_t epoch) {
   static_assert(ROWS * ITERS == (int)kWaveRows, "a wave's groups cover its rows");
-  __shared__ uint32_t s_cnt[4];
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint64_t total_all = *total_rows_dev;
   const uint64_t total_rows = total_all < row_end ? total_all : row_end;
@@ -723,6 +725,7 @@ __global__ __launch_bounds__(256) void compact_test(
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t wrow0 = rbase + tile * kTileRows + (uint64_t)w * kWaveRows;
     uint32_t cnt = 0;
+    uint64_t mrow = 0;   // lane j < 16: the mask of the wave's row j
     // The records of the wave's rows, one per lane, in one load.
     uint4 mdw = make_uint4(0, 0, 0, 0);
     if (lane < (uint32_t)kWaveRows && wrow0 + lane < total_rows)
@@ -830,13 +833,12 @@ __global__ __launch_bounds__(256) void compact_test(
         }
         const uint64_t bal = __ballot(h);
         cnt += (uint32_t)__popcll(bal);
-        if (lane == 0) masks[tile * kTileRows + (uint64_t)(w * ITERS + it) * ROWS + jr] = bal;
+        if (lane == (uint32_t)(it * ROWS + jr)) mrow = bal;
       }
     }
-    if (lane == 0) s_cnt[w] = cnt;
-    __syncthreads();
-    if (tid == 0) tile_hits[tile] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-    __syncthreads();
+    if (lane < (uint32_t)kWaveRows)
+      masks[tile * kTileRows + (uint64_t)w * kWaveRows + lane] = mrow;
+    if (lane == 0 && cnt) atomicAdd(&tile_hits[tile], cnt);
   }
   if (blockIdx.x == 0 && tid == 0) {
     counters[12] = (uint32_t)ntiles;   // tile count for the scan that follows
@@ -1249,6 +1251,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!write_only) {
+      if ((e = fill_u32(hits, 0, nt, s)) != hipSuccess) return e;
       ProfScope ps("compact_test", s);
 #define SFC_TEST_W(R, I, E, D, C, W)                                                       \
   compact_test<R, I, E, D, C, W><<<grid, 256, 0, s>>>(                                     \

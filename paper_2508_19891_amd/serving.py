@@ -20,15 +20,19 @@ Three modes:
     their work behind them, and a batch's requests complete when its slot's
     event has passed.  A tick with queries waits only for a free slot.
   * ``streams = k > 0``: query batches run side by side on k streams
-    (sfc_query_async_on), each with its own scratch and outputs allocated
-    when it is admitted.  Admission is by memory: a batch is admitted while
-    the bytes of the batches in flight plus its own stay within
-    ``budget_bytes`` and a stream is free; otherwise the loop first waits for
-    the oldest batch.  An allocation that fails (the device, or the library
-    reporting SFC_ERR_NOMEM) puts the batch back at the head of the queue
-    until a batch in flight has freed its memory.  Updates run on the
-    index's stream; the library makes them wait, on the device, for the
-    batches still reading the index.
+    (sfc_query_async_on), each with its own scratch and outputs: a stream
+    keeps them for its next batch and allocates larger ones only when a
+    batch needs more.  Admission is by memory: a batch is admitted while the
+    memory the loop holds (the streams' buffers and the batches' inputs)
+    plus what the batch adds stays within ``budget_bytes`` and a stream is
+    free; idle streams first give their buffers back, then the loop waits
+    for the oldest batch.  An allocation that fails (the device, or the
+    library reporting SFC_ERR_NOMEM) puts the batch back at the head of the
+    queue until a batch in flight has finished.  A batch's queries and radii
+    are views of the request pools (consecutive query requests take
+    consecutive slices).  Updates run on the index's stream; the library
+    makes them wait, on the device, for the batches still reading the
+    index.
 A batch that outgrew its output (rows or ids) is answered again
 synchronously into larger buffers.
 """
@@ -89,12 +93,34 @@ class Run:
     ticks: int
     seconds: float
     outputs: dict             # request -> (offsets, ids) on the host, if recorded
-    max_in_flight: int = 0    # side-by-side mode: most bytes admitted at once
+    max_in_flight: int = 0    # side-by-side mode: most batch memory held at once (bytes)
     max_batches: int = 0      # side-by-side mode: most batches in flight at once
     requeued: int = 0         # side-by-side mode: batches put back for want of memory
 
     def latency(self) -> np.ndarray:
         return self.done - self.arrival
+
+
+def _batch_inputs(trace, pools, members, dev):
+    """Queries, radii and query epochs of a batch's requests (r, epoch, k) in
+    order: consecutive query requests take consecutive slices of the pools,
+    so the batch is one view of each; one fill when they share an epoch."""
+    starts = [int(trace.start[r]) for r, _, _ in members]
+    sizes = [k for _, _, k in members]
+    m = sum(sizes)
+    if all(starts[t + 1] == starts[t] + sizes[t] for t in range(len(members) - 1)):
+        q = pools.queries[starts[0]:starts[0] + m]
+        d = pools.delta[starts[0]:starts[0] + m]
+    else:
+        q = torch.cat([pools.queries[a:a + k] for a, k in zip(starts, sizes)])
+        d = torch.cat([pools.delta[a:a + k] for a, k in zip(starts, sizes)])
+    eps = [e for _, e, _ in members]
+    if all(x == eps[0] for x in eps):
+        e = torch.full((m,), eps[0], dtype=torch.int32, device=dev)
+    else:
+        e = torch.cat([torch.full((k,), x, dtype=torch.int32, device=dev)
+                       for x, k in zip(eps, sizes)])
+    return q, d, e
 
 
 class _Inserts:
@@ -129,17 +155,22 @@ def serve(index: sfc.Index, trace: ServingTrace, pools: Pools, rate: float = flo
           max_tick: int = 16, record: bool = False, out_ids: torch.Tensor | None = None,
           slots: int = 0, slot_queries: int = 1 << 20, slot_ids: int = 1 << 26,
           slot_rows: int = 1 << 24, streams: int = 0, budget_bytes: int = 2 << 30,
-          rows_per_query: int = 48, ids_per_query: int = 1200, alloc=None) -> Run:
+          rows_per_query: int = 48, ids_per_query: int = 1200, alloc=None,
+          keep_buffers: bool = True) -> Run:
     """Runs the trace with Poisson arrivals at ``rate`` requests/s (inf: all
     at time 0) and returns arrival and completion times per request.
 
     streams > 0: batches of at most slot_queries queries run side by side,
     each sized for rows_per_query candidate rows and ids_per_query ids per
     query, admitted against budget_bytes; alloc(nbytes) -> uint8 device
-    tensor (default torch.empty) provides their memory."""
+    tensor (default torch.empty) provides their memory.  With keep_buffers
+    each stream keeps its scratch and output buffers for its next batch
+    (allocating only when a batch needs more) and the kept bytes count
+    against the budget; idle streams give theirs back when a batch needs
+    the room.  Without it every batch allocates and frees its own."""
     if streams > 0:
         return _serve_overlap(index, trace, pools, rate, max_tick, record, streams, budget_bytes,
-                              slot_queries, rows_per_query, ids_per_query, alloc)
+                              slot_queries, rows_per_query, ids_per_query, alloc, keep_buffers)
     if slots > 0:
         return _serve_async(index, trace, pools, rate, max_tick, record, slots, slot_queries,
                             slot_ids, slot_rows)
@@ -185,15 +216,8 @@ def serve(index: sfc.Index, trace: ServingTrace, pools: Pools, rate: float = flo
         for ri in inserts.flush():
             done[ri] = time.perf_counter() - t0
         if pending:
-            qs, ds, es = [], [], []
-            for r, e in pending:
-                a, k = int(trace.start[r]), int(trace.size[r])
-                qs.append(pools.queries[a:a + k])
-                ds.append(pools.delta[a:a + k])
-                es.append(torch.full((k,), e, dtype=torch.int32, device=dev))
-            q = qs[0] if len(qs) == 1 else torch.cat(qs)
-            d = ds[0] if len(ds) == 1 else torch.cat(ds)
-            e = es[0] if len(es) == 1 else torch.cat(es)
+            q, d, e = _batch_inputs(trace, pools,
+                                    [(r, e, int(trace.size[r])) for r, e in pending], dev)
             try:
                 off, ids = index.query_epochs(q, d, e, out_ids=out_ids)
             except sfc.CapacityError as err:
@@ -319,15 +343,7 @@ def _serve_async(index, trace, pools, rate, max_tick, record, nslots, slot_queri
             if not take:               # a single request larger than a slot
                 take.append(pending.pop(0))
                 m = take[0][2]
-            qs, ds, es = [], [], []
-            for r, e, k in take:
-                a = int(trace.start[r])
-                qs.append(pools.queries[a:a + k])
-                ds.append(pools.delta[a:a + k])
-                es.append(torch.full((k,), e, dtype=torch.int32, device=dev))
-            q = torch.cat(qs) if len(qs) > 1 else qs[0]
-            d = torch.cat(ds) if len(ds) > 1 else ds[0]
-            e = torch.cat(es) if len(es) > 1 else es[0]
+            q, d, e = _batch_inputs(trace, pools, take, dev)
             slot.members = take
             slot.batch = (q, d, e)
             slot.busy = True
@@ -362,7 +378,7 @@ class _Batch:
 
 
 def _serve_overlap(index, trace, pools, rate, max_tick, record, nstreams, budget, max_batch,
-                   rows_per_query, ids_per_query, alloc) -> Run:
+                   rows_per_query, ids_per_query, alloc, keep_buffers) -> Run:
     R = len(trace.kind)
     arrival = np.zeros(R) if not np.isfinite(rate) else np.cumsum(trace.gaps) / rate
     done = np.zeros(R)
@@ -377,12 +393,25 @@ def _serve_overlap(index, trace, pools, rate, max_tick, record, nstreams, budget
     streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
     free = list(streams)
     busy = []                      # batches in launch order
-    in_flight = [0]
+    # Each stream's scratch and output buffers, kept between its batches
+    # (keep_buffers) and replaced by larger ones when a batch needs more.
+    # held: bytes of those buffers plus the query epochs of the batches in
+    # flight; admission keeps it within the budget.
+    kept = {}
+    held = [0]
     stats = {"max_in_flight": 0, "max_batches": 0, "requeued": 0}
     start = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
+
+    def kept_bytes(st) -> int:
+        k = kept.get(st)
+        return 0 if k is None else k[0].numel() + k[1].numel()
+
+    def drop(st):
+        held[0] -= kept_bytes(st)
+        kept.pop(st, None)
 
     def finish(b: _Batch):
         b.event.synchronize()
@@ -408,7 +437,10 @@ def _serve_overlap(index, trace, pools, rate, max_tick, record, nstreams, budget
                 o = off_h[base:base + k + 1]
                 outputs[r] = (o - o[0], ids_h[o[0]:o[-1]].copy())
             base += k
-        in_flight[0] -= b.nbytes
+        held[0] -= b.nbytes
+        b.offsets = b.ids = b.flags = b.scratch = None
+        if not keep_buffers:
+            drop(b.stream)
         free.append(b.stream)
 
     def reap(block: bool):
@@ -423,31 +455,52 @@ def _serve_overlap(index, trace, pools, rate, max_tick, record, nstreams, budget
         max_rows = rows_per_query * m + 1024
         ids_cap = ids_per_query * m
         scratch_bytes = index.query_scratch_bytes(m, max_rows)
-        nbytes = scratch_bytes + 8 * (m + 1) + 4 * ids_cap + 256 + m * (16 + 8 + 4)
-        while busy and (not free or in_flight[0] + nbytes > budget):
-            reap(True)                 # admission by memory and streams
+        out_bytes = 256 + 8 * (m + 1) + 4 * ids_cap
+        in_bytes = 4 * m               # the query epochs (queries and radii are pool views)
+
+        def fits_kept(st) -> bool:
+            k = kept.get(st)
+            return k is not None and k[0].numel() >= scratch_bytes and k[1].numel() >= out_bytes
+
+        def adds(st) -> int:           # bytes held more once the batch runs on st
+            if fits_kept(st):
+                return in_bytes
+            return scratch_bytes + out_bytes + in_bytes - kept_bytes(st)
+
+        while True:                    # admission by memory and streams
+            if free:
+                if held[0] + adds(free[0]) <= budget:
+                    break
+                for st in free[1:]:    # idle streams give their buffers back first
+                    drop(st)
+                if held[0] + adds(free[0]) <= budget:
+                    break
+            if not busy:               # alone: admitted whatever it needs
+                break
+            reap(True)
+        st = free[0]
         try:
-            qs, ds, es = [], [], []
-            for r, e, k in take:
-                a = int(trace.start[r])
-                qs.append(pools.queries[a:a + k])
-                ds.append(pools.delta[a:a + k])
-                es.append(torch.full((k,), e, dtype=torch.int32, device=dev))
-            q = torch.cat(qs) if len(qs) > 1 else qs[0]
-            d = torch.cat(ds) if len(ds) > 1 else ds[0]
-            e = torch.cat(es) if len(es) > 1 else es[0]
-            b = _Batch(take, q, d, e, free[0], nbytes)
+            q, d, e = _batch_inputs(trace, pools, take, dev)
+            if not fits_kept(st):
+                drop(st)
+                scratch = alloc(scratch_bytes)
+                if scratch is None or scratch.numel() < scratch_bytes:
+                    return False       # the caller's allocator had no memory
+                out = alloc(out_bytes)
+                if out is None or out.numel() < out_bytes:
+                    return False
+                kept[st] = (scratch, out)
+                held[0] += scratch.numel() + out.numel()
+            scratch, out = kept[st]
+            b = _Batch(take, q, d, e, st, in_bytes)
             b.max_rows = max_rows
-            b.scratch = alloc(scratch_bytes)
-            out = alloc(8 * (m + 1) + 4 * ids_cap + 256)
-            b.offsets = out[:8 * (m + 1)].view(torch.int64)
-            b.ids = out[8 * (m + 1):8 * (m + 1) + 4 * ids_cap].view(torch.int32)
-            b.flags = out[-256:].view(torch.int32)
+            b.scratch = scratch
+            b.flags = out[:256].view(torch.int32)
+            b.offsets = out[256:256 + 8 * (m + 1)].view(torch.int64)
+            b.ids = out[256 + 8 * (m + 1):256 + 8 * (m + 1) + 4 * ids_cap].view(torch.int32)
             b.flags.zero_()
         except torch.cuda.OutOfMemoryError:
             return False
-        if b.scratch is None or b.scratch.numel() < scratch_bytes:
-            return False               # the caller's allocator had no memory
         b.stream.wait_stream(torch.cuda.current_stream())
         try:
             index.query_async_on(b.stream, b.scratch, q, d, e, max_rows, b.offsets, b.ids,
@@ -459,8 +512,8 @@ def _serve_overlap(index, trace, pools, rate, max_tick, record, nstreams, budget
         b.event.record(b.stream)
         free.pop(0)
         busy.append(b)
-        in_flight[0] += nbytes
-        stats["max_in_flight"] = max(stats["max_in_flight"], in_flight[0])
+        held[0] += in_bytes
+        stats["max_in_flight"] = max(stats["max_in_flight"], held[0])
         stats["max_batches"] = max(stats["max_batches"], len(busy))
         return True
 
@@ -519,6 +572,8 @@ def _serve_overlap(index, trace, pools, rate, max_tick, record, nstreams, budget
                 if alone_failures > 1:
                     raise sfc.SfcError(sfc.SFC_ERR_NOMEM, "a query batch found no memory "
                                        "with nothing in flight")
+                for st in list(kept):  # nothing runs: every stream's buffers go back
+                    drop(st)
                 torch.cuda.synchronize()
         oldest = min([e for b in busy for _, e, _ in b.members], default=epoch)
         index.retire(oldest)

@@ -99,11 +99,19 @@ class _FailSome:
         return torch.empty(nbytes, dtype=torch.uint8, device=DEV)
 
 
-@pytest.mark.parametrize("curve,search", [(MORTON, sfc.LEARNED), (HILBERT, sfc.STREE)])
-def test_side_by_side_batches_equal_snapshot_oracle(curve, search):
+@pytest.mark.parametrize("curve,search,keep", [(MORTON, sfc.LEARNED, False),
+                                               (HILBERT, sfc.STREE, False),
+                                               (MORTON, sfc.BINARY, True),
+                                               (HILBERT, sfc.LEARNED, True)])
+def test_side_by_side_batches_equal_snapshot_oracle(curve, search, keep):
     """Query batches on three streams at once, admitted by memory, with
     some of their allocations failing (put back and admitted again): every
-    request equals the oracle over the snapshot of its epoch."""
+    request equals the oracle over the snapshot of its epoch.  With kept
+    buffers the streams allocate only for their first batches and for
+    larger ones, so the failures are placed among the first allocations:
+    the out buffer of each of the first three allocating batches (one
+    failure apart, so that two never come in a row with nothing in
+    flight)."""
     trace = workload.serving_trace(n0=20_000, requests=90, seed=7, curve=curve,
                                    log2_size=(6, 11))
     pools = serving.Pools.upload(trace, DEV)
@@ -111,9 +119,9 @@ def test_side_by_side_batches_equal_snapshot_oracle(curve, search):
     idx = sfc.Index(init, curve, search=search, refine=True)
     per_query = 8 * 48 + 8 + 4 * 1200 + 28 + 300     # scratch estimate + outputs + inputs
     budget = 3 * 600 * per_query + (4 << 20)
-    alloc = _FailSome({4, 11, 23, 40})
+    alloc = _FailSome({2, 6, 10} if keep else {4, 11, 23, 40})
     run = serving.serve(idx, trace, pools, record=True, streams=3, budget_bytes=budget,
-                        slot_queries=600, alloc=alloc)
+                        slot_queries=600, alloc=alloc, keep_buffers=keep)
     assert run.max_batches >= 2          # batches were on the device together
     assert run.requeued >= 3             # and the failed allocations were admitted again
     assert run.max_in_flight <= budget
