@@ -795,15 +795,20 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
     }
     uint32_t* err = (uint32_t*)((char*)scratch + sb - 256);
     hipError_t e = sfc::fill_u32(err, 0, 1, h->stream);
-    // Without point sets the chunked sort runs first; a run of equal top key
-    // bits too long for it is reported in the error word (read here anyway),
-    // and the plain sort then builds the arrays again.
-    const bool chunked = !h->set_off && !g_force_plain_sort;
+    // The chunked sort runs first (with point sets, followed by the passes
+    // over the set index); a run of equal top key bits too long for it is
+    // reported in the error word (read here anyway), and the plain sort then
+    // builds the arrays again.
+    const bool chunked = !g_force_plain_sort;
     if (e == hipSuccess)
-      e = chunked ? sfc::sort_build_chunked(xy, n, h->curve, h->keys, h->ids, scratch, err,
-                                            h->stream, h->cells, h->xy_in)
-                  : sfc::sort_build(xy, n, h->curve, h->keys, h->ids, nullptr, scratch, err,
-                                    h->stream, h->set_off, h->n_sets, h->cells, h->xy_in);
+      e = !chunked ? sfc::sort_build(xy, n, h->curve, h->keys, h->ids, nullptr, scratch, err,
+                                     h->stream, h->set_off, h->n_sets, h->cells, h->xy_in)
+          : h->set_off
+              ? sfc::sort_build_sets_chunked(xy, n, h->curve, h->keys, h->ids, nullptr, scratch,
+                                             err, h->stream, h->set_off, h->n_sets, h->cells,
+                                             h->xy_in, false)
+              : sfc::sort_build_chunked(xy, n, h->curve, h->keys, h->ids, scratch, err, h->stream,
+                                        h->cells, h->xy_in);
     uint64_t w = 0;
     if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
     g_last_sort_fallback = 0;
@@ -813,7 +818,7 @@ sfc_status build_impl(const double* xy, uint64_t n, const uint64_t* set_off_host
       e = sfc::fill_u32(err, 0, 1, h->stream);
       if (e == hipSuccess)
         e = sfc::sort_build(xy, n, h->curve, h->keys, h->ids, nullptr, scratch, err, h->stream,
-                            nullptr, 0, h->cells, h->xy_in);
+                            h->set_off, h->n_sets, h->cells, h->xy_in);
       if (e == hipSuccess) e = read_words(err, &w, 1, h->stream);
     }
     h->alloc.put(scratch);
@@ -1467,9 +1472,15 @@ sfc_status sfc_graph_build(sfc_index* h, const double* xy, sfc_graph** out) {
   g->err = (uint32_t*)((char*)g->scratch + sb - 256);
   sfc_status st = graph_capture(g, [&](hipStream_t s) {
     hipError_t e = sfc::fill_u32(g->err, 0, 1, s);
+    // The chunked sort with the plain one recorded behind it, which runs (on
+    // the device) only when a run was too long for the chunks.
     if (e == hipSuccess)
-      e = sfc::sort_build(xy, h->n, h->curve, h->keys, h->ids, h->xy, g->scratch, g->err, s,
-                          h->set_off, h->n_sets, h->cells, h->xy_in);
+      e = g_force_plain_sort
+              ? sfc::sort_build(xy, h->n, h->curve, h->keys, h->ids, h->xy, g->scratch, g->err,
+                                s, h->set_off, h->n_sets, h->cells, h->xy_in)
+              : sfc::sort_build_sets_chunked(xy, h->n, h->curve, h->keys, h->ids, h->xy,
+                                             g->scratch, g->err, s, h->set_off, h->n_sets,
+                                             h->cells, h->xy_in, true);
     if (e == hipSuccess && h->occ) e = sfc::build_occupancy(h->keys, h->n, h->occ, s);
     if (e == hipSuccess && h->stree_ready)
       e = sfc::stree_build(sfc::stree_view(h->keys, h->n, h->stree), s);

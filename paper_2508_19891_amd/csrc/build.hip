@@ -39,6 +39,13 @@ constexpr int kDigits = 8;
 constexpr int kSortWaves = 4;
 constexpr int kSortThreads = kSortWaves * kWave;
 
+// True when a kernel of a guarded sequence has nothing to do (SortGuard).
+// The word is read by every thread before any barrier: the whole workgroup
+// returns or none of it.
+__device__ __forceinline__ bool guard_skips(SortGuard g) {
+  return g.word && (((*g.word & kErrOversized) != 0u) != g.when_set);
+}
+
 // Exclusive scan of one uint32 per thread over a block of 256 threads.
 __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_tmp) {
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -73,7 +80,9 @@ __global__ __launch_bounds__(256) void keygen_tiles(const double2* __restrict__ 
                                                    uint32_t tile_len, uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ err,
                                                    uint32_t* __restrict__ counts, uint64_t tiles,
-                                                   double2* __restrict__ xy_copy, int count_shift) {
+                                                   double2* __restrict__ xy_copy, int count_shift,
+                                                   SortGuard guard) {
+  if (guard_skips(guard)) return;
   __shared__ uint32_t h[kSortWaves][kRadix];
   __shared__ uint16_t lut[CURVE == SFC_CURVE_HILBERT ? 1024 : 1];
   for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
@@ -121,7 +130,9 @@ __global__ __launch_bounds__(256) void keygen3_tiles(const double* __restrict__ 
                                                     uint32_t tile_len, uint64_t* __restrict__ keys,
                                                     uint32_t* __restrict__ err,
                                                     uint32_t* __restrict__ counts, uint64_t tiles,
-                                                    double* __restrict__ xyz_copy, int count_shift) {
+                                                    double* __restrict__ xyz_copy, int count_shift,
+                                                    SortGuard guard) {
+  if (guard_skips(guard)) return;
   __shared__ uint32_t h[kSortWaves][kRadix];
   for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
   __syncthreads();
@@ -197,7 +208,9 @@ __global__ __launch_bounds__(256) void tile_hist(const uint64_t* __restrict__ ki
                                                  const uint32_t* __restrict__ vin, uint64_t n,
                                                  uint32_t tile_len, int shift,
                                                  const uint32_t* __restrict__ set_id,
-                                                 uint32_t* __restrict__ counts, uint64_t tiles) {
+                                                 uint32_t* __restrict__ counts, uint64_t tiles,
+                                                 SortGuard guard) {
+  if (guard_skips(guard)) return;
   __shared__ uint32_t h[kSortWaves][kRadix];
   for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
   __syncthreads();
@@ -229,7 +242,8 @@ __global__ __launch_bounds__(256) void tile_hist(const uint64_t* __restrict__ ki
 // of tiles < t; dtot[d] = the digit's total.
 __global__ __launch_bounds__(256) void digit_scan(const uint32_t* __restrict__ counts,
                                                   uint64_t tiles, uint32_t* __restrict__ rel,
-                                                  uint32_t* __restrict__ dtot) {
+                                                  uint32_t* __restrict__ dtot, SortGuard guard) {
+  if (guard_skips(guard)) return;
   __shared__ uint32_t s_tmp[kSortWaves];
   const uint32_t* c = counts + (uint64_t)blockIdx.x * tiles;
   uint32_t* r = rel + (uint64_t)blockIdx.x * tiles;
@@ -287,7 +301,9 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_pass(
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
     const uint32_t* __restrict__ rel, const uint32_t* __restrict__ dtot, uint64_t tiles,
     uint32_t* err, const double2* __restrict__ xy_in, double2* __restrict__ xy_out,
-    uint64_t* __restrict__ cells_out, int cell_curve, const uint32_t* __restrict__ set_id) {
+    uint64_t* __restrict__ cells_out, int cell_curve, const uint32_t* __restrict__ set_id,
+    SortGuard guard) {
+  if (guard_skips(guard)) return;
   constexpr int kTile = kSortThreads * ITEMS;
   constexpr int IT = kTile / kScatterThreads;
   static_assert(IT * kScatterThreads == kTile, "tile must split over the scatter threads");
@@ -434,14 +450,16 @@ __global__ __launch_bounds__(256) void occupancy_mark(const uint64_t* __restrict
 }
 
 __global__ void gather_points(const uint32_t* __restrict__ ids, const double2* __restrict__ xy,
-                              double2* __restrict__ out, uint64_t n) {
+                              double2* __restrict__ out, uint64_t n, SortGuard guard) {
+  if (guard_skips(guard)) return;
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = xy[ids[i]];
 }
 
 __global__ void gather_points3(const uint32_t* __restrict__ ids, const double* __restrict__ xyz,
                                double* __restrict__ out, uint64_t* __restrict__ cells_out,
-                               uint64_t n) {
+                               uint64_t n, SortGuard guard) {
+  if (guard_skips(guard)) return;
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const uint64_t v = ids[i];
@@ -471,7 +489,8 @@ uint64_t sort_tile(uint64_t n) { return (uint64_t)kSortThreads * sort_items(n); 
 
 // Set id of every input position (sets are contiguous in the input).
 __global__ void fill_set_ids(const uint64_t* __restrict__ set_off, uint32_t n_sets, uint64_t n,
-                             uint32_t* __restrict__ set_id) {
+                             uint32_t* __restrict__ set_id, SortGuard guard) {
+  if (guard_skips(guard)) return;
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t lo = 0, len = n_sets + 1;   // last s with set_off[s] <= i
@@ -785,14 +804,15 @@ hipError_t launch_scatter(bool first, bool gather, bool setpass, int shift, uint
                           const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                           uint32_t* vout, uint64_t n, const uint32_t* rel, const uint32_t* dtot,
                           uint32_t* err, const double* xy, double* xy_out, uint64_t* cells_out,
-                          int cell_curve, const uint32_t* set_id, hipStream_t s) {
+                          int cell_curve, const uint32_t* set_id, SortGuard guard,
+                          hipStream_t s) {
   const dim3 g((uint32_t)(((tiles + 7) / 8) * 8)), b(kScatterThreads);
   const double2* xi = (const double2*)xy;
   double2* xo = (double2*)xy_out;
 #define SFC_PASS(F, G, S)                                                                      \
   scatter_pass<ITEMS, F, G, S><<<g, b, 0, s>>>(kin, vin, kout, vout, n, shift, rel, dtot,     \
                                                tiles, err, G ? xi : nullptr, G ? xo : nullptr, \
-                                               cells_out, cell_curve, set_id)
+                                               cells_out, cell_curve, set_id, guard)
   if (setpass) {
     if (gather) SFC_PASS(false, true, true);
     else SFC_PASS(false, false, true);
@@ -805,6 +825,46 @@ hipError_t launch_scatter(bool first, bool gather, bool setpass, int shift, uint
   }
 #undef SFC_PASS
   return hipGetLastError();
+}
+
+// One stable radix pass over the byte at `shift` of the keys (of the set
+// index with setpass): the tiles' digit counts (unless the key pass already
+// took them: counted), their scan over the tiles, and the scatter.
+hipError_t radix_pass(bool counted, bool first, bool gather, bool setpass, int shift, uint64_t n,
+                      const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
+                      uint32_t* counts, uint32_t* rel, uint32_t* dtot, uint32_t* err,
+                      const double* xy, double* xy_out, uint64_t* cells_out, int curve,
+                      const uint32_t* set_id, SortGuard guard, hipStream_t s) {
+  const uint32_t tile = (uint32_t)sort_tile(n);
+  const uint64_t tiles = (n + tile - 1) / tile;
+  hipError_t e;
+  if (!counted) {
+    ProfScope ps("tile_hist", s);
+    if (setpass)
+      tile_hist<true><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, set_id, counts,
+                                                      tiles, guard);
+    else
+      tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, set_id, counts,
+                                                       tiles, guard);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    ProfScope ps("digit_scan", s);
+    digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot, guard);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  ProfScope ps(setpass ? "set_pass" : "scatter_pass", s);
+#define SFC_LAUNCH(I)                                                                          \
+  launch_scatter<I>(first, gather, setpass, shift, tiles, kin, vin, kout, vout, n, rel, dtot, err, \
+                    xy, xy_out, cells_out, curve, set_id, guard, s)
+  switch (sort_items(n)) {
+    case 16: return SFC_LAUNCH(16);
+    case 12: return SFC_LAUNCH(12);
+    case 20: return SFC_LAUNCH(20);
+    case 24: return SFC_LAUNCH(24);
+    default: return SFC_LAUNCH(8);
+  }
+#undef SFC_LAUNCH
 }
 
 }  // namespace
@@ -828,20 +888,23 @@ size_t build_scratch_bytes(uint64_t n) {
 }
 
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
-                       uint32_t* counts, hipStream_t s, double* xy_copy, int count_shift) {
+                       uint32_t* counts, hipStream_t s, double* xy_copy, int count_shift,
+                       SortGuard guard) {
   if (n == 0) return hipSuccess;
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
   ProfScope ps("keygen_tiles", s);
   if (curve == SFC_CURVE_MORTON3)
     keygen3_tiles<<<(uint32_t)tiles, 256, 0, s>>>(xy, n, tile, keys, err, counts, tiles, xy_copy,
-                                                  count_shift);
+                                                  count_shift, guard);
   else if (curve == SFC_CURVE_HILBERT)
     keygen_tiles<SFC_CURVE_HILBERT><<<(uint32_t)tiles, 256, 0, s>>>(
-        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy, count_shift);
+        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy, count_shift,
+        guard);
   else
     keygen_tiles<SFC_CURVE_MORTON><<<(uint32_t)tiles, 256, 0, s>>>(
-        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy, count_shift);
+        (const double2*)xy, n, tile, keys, err, counts, tiles, (double2*)xy_copy, count_shift,
+        guard);
   return hipGetLastError();
 }
 
@@ -855,7 +918,7 @@ hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, 
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err_host_visible,
                       hipStream_t s, const uint64_t* set_off, uint32_t n_sets,
-                      uint64_t* cells_out, double* xy_copy) {
+                      uint64_t* cells_out, double* xy_copy, SortGuard guard) {
   if (n == 0) return hipSuccess;
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
@@ -875,11 +938,12 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   auto out_is_final = [&](int pass) { return ((passes - 1 - pass) & 1) == 0; };
   uint64_t* keys_first = out_is_final(0) ? keys_b : keys_out;
 
-  hipError_t e = launch_keys(xy, n, curve, keys_first, err_host_visible, counts, s, xy_copy);
+  hipError_t e = launch_keys(xy, n, curve, keys_first, err_host_visible, counts, s, xy_copy, 0,
+                             guard);
   if (e != hipSuccess) return e;
   if (sp > 0) {
     ProfScope ps("set_prep", s);
-    fill_set_ids<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(set_off, n_sets, n, set_id);
+    fill_set_ids<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(set_off, n_sets, n, set_id, guard);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const uint64_t* kin = keys_first;
@@ -896,33 +960,8 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     const bool last = pass == passes - 1;
     const bool gather = last && xy_out && curve != SFC_CURVE_MORTON3;
     uint64_t* pass_cells = last && !(xy_out && curve == SFC_CURVE_MORTON3) ? cells_out : nullptr;
-    if (pass > 0) {
-      ProfScope ps("tile_hist", s);
-      if (setpass)
-        tile_hist<true><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, set_id, counts,
-                                                        tiles);
-      else
-        tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, set_id, counts,
-                                                         tiles);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    {
-      ProfScope ps("digit_scan", s);
-      digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    ProfScope ps(setpass ? "set_pass" : "scatter_pass", s);
-#define SFC_LAUNCH(I)                                                                        \
-  launch_scatter<I>(pass == 0, gather, setpass, shift, tiles, kin, vin, kout, vout, n, rel, dtot, \
-                    err_host_visible, xy, xy_out, pass_cells, curve, set_id, s)
-    switch (sort_items(n)) {
-      case 16: e = SFC_LAUNCH(16); break;
-      case 12: e = SFC_LAUNCH(12); break;
-      case 20: e = SFC_LAUNCH(20); break;
-      case 24: e = SFC_LAUNCH(24); break;
-      default: e = SFC_LAUNCH(8); break;
-    }
-#undef SFC_LAUNCH
+    e = radix_pass(pass == 0, pass == 0, gather, setpass, shift, n, kin, vin, kout, vout, counts,
+                   rel, dtot, err_host_visible, xy, xy_out, pass_cells, curve, set_id, guard, s);
     if (e != hipSuccess) return e;
     kin = kout;
     vin = vout;
@@ -930,63 +969,36 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   if (curve == SFC_CURVE_MORTON3 && xy_out) {
     ProfScope ps("gather_points3", s);
     gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids_out, xy, xy_out, cells_out,
-                                                                n);
+                                                                n, guard);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
-                              uint32_t* ids_out, void* scratch, uint32_t* err, hipStream_t s,
-                              uint64_t* cells_out, double* xy_copy) {
-  if (n == 0) return hipSuccess;
+namespace {
+// The chunked sort with its buffers named: the sorted keys and ids land in
+// (kfin, ifin), (ktmp, itmp) serve as the other side of the passes.
+hipError_t chunked_core(const double* xy, uint64_t n, int curve, uint64_t* kfin, uint32_t* ifin,
+                        uint64_t* ktmp, uint32_t* itmp, uint32_t* counts, uint32_t* rel,
+                        uint32_t* dtot, uint32_t* err, hipStream_t s, uint64_t* cells_out,
+                        double* xy_copy) {
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
   const uint64_t cells = tiles * kRadix;
-  char* p = (char*)scratch;
-  uint64_t* keys_b = (uint64_t*)p;      p += align256(n * 8);
-  uint32_t* ids_b = (uint32_t*)p;       p += align256(n * 4);
-  uint32_t* counts = (uint32_t*)p;      p += align256(cells * 4);
-  uint32_t* rel = (uint32_t*)p;         p += align256(cells * 4);
-  uint32_t* dtot = (uint32_t*)p;
-
-  // The passes alternate between the output and the scratch buffer so that
-  // the last one lands in the output, where the chunks are then sorted in
-  // place.
+  // The passes alternate between the two sides so that the last one lands in
+  // (kfin, ifin), where the chunks are then sorted in place.
   auto final_pass = [](int pass) { return ((kTopPasses - 1 - pass) & 1) == 0; };
-  uint64_t* keys_first = final_pass(0) ? keys_b : keys_out;
+  uint64_t* keys_first = final_pass(0) ? ktmp : kfin;
   hipError_t e = launch_keys(xy, n, curve, keys_first, err, counts, s, xy_copy, kTopShift);
   if (e != hipSuccess) return e;
   const uint64_t* kin = keys_first;
   const uint32_t* vin = nullptr;
   for (int pass = 0; pass < kTopPasses; ++pass) {
     const bool fin = final_pass(pass);
-    uint64_t* kout = fin ? keys_out : keys_b;
-    uint32_t* vout = fin ? ids_out : ids_b;
-    const int shift = kTopShift + 8 * pass;
-    if (pass > 0) {
-      ProfScope ps("tile_hist", s);
-      tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, nullptr, counts,
-                                                       tiles);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    {
-      ProfScope ps("digit_scan", s);
-      digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    ProfScope ps("scatter_pass", s);
-#define SFC_LAUNCH(I)                                                                     \
-  launch_scatter<I>(pass == 0, false, false, shift, tiles, kin, vin, kout, vout, n, rel, dtot, \
-                    err, xy, nullptr, nullptr, curve, nullptr, s)
-    switch (sort_items(n)) {
-      case 16: e = SFC_LAUNCH(16); break;
-      case 12: e = SFC_LAUNCH(12); break;
-      case 20: e = SFC_LAUNCH(20); break;
-      case 24: e = SFC_LAUNCH(24); break;
-      default: e = SFC_LAUNCH(8); break;
-    }
-#undef SFC_LAUNCH
+    uint64_t* kout = fin ? kfin : ktmp;
+    uint32_t* vout = fin ? ifin : itmp;
+    e = radix_pass(pass == 0, pass == 0, false, false, kTopShift + 8 * pass, n, kin, vin, kout,
+                   vout, counts, rel, dtot, err, xy, nullptr, nullptr, curve, nullptr, {}, s);
     if (e != hipSuccess) return e;
     kin = kout;
     vin = vout;
@@ -998,13 +1010,93 @@ hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t*
   uint64_t* first = (uint64_t*)counts;
   {
     ProfScope ps("chunk_firsts", s);
-    chunk_firsts<<<(uint32_t)((chunks + 1 + 3) / 4), 256, 0, s>>>(keys_out, n, chunks, first);
+    chunk_firsts<<<(uint32_t)((chunks + 1 + 3) / 4), 256, 0, s>>>(kfin, n, chunks, first);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   ProfScope ps("chunk_sort", s);
-  chunk_sort<<<(uint32_t)chunks, kChunkThreads, 0, s>>>(keys_out, ids_out, n, first, chunks,
-                                                         cells_out, curve, err);
+  chunk_sort<<<(uint32_t)chunks, kChunkThreads, 0, s>>>(kfin, ifin, n, first, chunks, cells_out,
+                                                         curve, err);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
+                              uint32_t* ids_out, void* scratch, uint32_t* err, hipStream_t s,
+                              uint64_t* cells_out, double* xy_copy) {
+  if (n == 0) return hipSuccess;
+  const uint64_t cells = (n + sort_tile(n) - 1) / sort_tile(n) * kRadix;
+  char* p = (char*)scratch;
+  uint64_t* keys_b = (uint64_t*)p;      p += align256(n * 8);
+  uint32_t* ids_b = (uint32_t*)p;       p += align256(n * 4);
+  uint32_t* counts = (uint32_t*)p;      p += align256(cells * 4);
+  uint32_t* rel = (uint32_t*)p;         p += align256(cells * 4);
+  uint32_t* dtot = (uint32_t*)p;
+  return chunked_core(xy, n, curve, keys_out, ids_out, keys_b, ids_b, counts, rel, dtot, err, s,
+                      cells_out, xy_copy);
+}
+
+hipError_t sort_build_sets_chunked(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
+                                   uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
+                                   hipStream_t s, const uint64_t* set_off, uint32_t n_sets,
+                                   uint64_t* cells_out, double* xy_copy, bool fallback) {
+  if (n == 0) return hipSuccess;
+  const uint64_t cells = (n + sort_tile(n) - 1) / sort_tile(n) * kRadix;
+  char* p = (char*)scratch;
+  uint64_t* keys_b = (uint64_t*)p;      p += align256(n * 8);
+  uint32_t* ids_b = (uint32_t*)p;       p += align256(n * 4);
+  uint32_t* counts = (uint32_t*)p;      p += align256(cells * 4);
+  uint32_t* rel = (uint32_t*)p;         p += align256(cells * 4);
+  uint32_t* dtot = (uint32_t*)p;        p += align256(kRadix * 4);
+  uint32_t* set_id = (uint32_t*)p;
+  const int sp = set_off ? set_passes(n_sets) : 0;
+  // The chunked sort lands where the set passes, alternating sides, end in
+  // the output.
+  const bool odd = (sp & 1) != 0;
+  uint64_t* kc = odd ? keys_b : keys_out;
+  uint32_t* ic = odd ? ids_b : ids_out;
+  hipError_t e = chunked_core(xy, n, curve, kc, ic, odd ? keys_out : keys_b,
+                              odd ? ids_out : ids_b, counts, rel, dtot, err, s,
+                              sp ? nullptr : cells_out, xy_copy);
+  if (e != hipSuccess) return e;
+  // The set passes run only on a complete chunked sort.
+  const SortGuard when_sorted{err, false};
+  if (sp > 0) {
+    ProfScope ps("set_prep", s);
+    fill_set_ids<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(set_off, n_sets, n, set_id,
+                                                             when_sorted);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const uint64_t* kin = kc;
+  const uint32_t* vin = ic;
+  // With xy_out the points travel with the last set pass (in 3-D, or
+  // without sets, they are gathered after the sort).
+  const bool gather2 = xy_out && curve != SFC_CURVE_MORTON3;
+  for (int pass = 0; pass < sp; ++pass) {
+    const bool fin = ((sp - 1 - pass) & 1) == 0;
+    const bool last = pass == sp - 1;
+    uint64_t* kout = fin ? keys_out : keys_b;
+    uint32_t* vout = fin ? ids_out : ids_b;
+    e = radix_pass(false, false, last && gather2, true, 8 * pass, n, kin, vin, kout, vout, counts,
+                   rel, dtot, err, xy, xy_out, last ? cells_out : nullptr, curve, set_id,
+                   when_sorted, s);
+    if (e != hipSuccess) return e;
+    kin = kout;
+    vin = vout;
+  }
+  if (xy_out && (sp == 0 || !gather2)) {
+    ProfScope ps("gather_points", s);
+    if (curve == SFC_CURVE_MORTON3)
+      gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids_out, xy, xy_out, nullptr,
+                                                                  n, when_sorted);
+    else
+      gather_points<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(
+          ids_out, (const double2*)xy, (double2*)xy_out, n, when_sorted);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (!fallback) return hipSuccess;
+  // A run too long for a chunk: the plain sort, recorded here too, runs then.
+  return sort_build(xy, n, curve, keys_out, ids_out, xy_out, scratch, err, s, set_off, n_sets,
+                    cells_out, xy_copy, SortGuard{err, true});
 }
 
 size_t order_scratch_bytes(uint64_t m) {
@@ -1042,14 +1134,14 @@ hipError_t order_queries(const double* q, uint64_t m, int curve, uint32_t* perm,
     uint32_t* vout = pass == 0 ? ids_b : perm;
     if (pass > 0) {
       tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, ids_b, m, tile, shift, nullptr, counts,
-                                                       tiles);
+                                                       tiles, SortGuard{});
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot);
+    digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot, SortGuard{});
     if ((e = hipGetLastError()) != hipSuccess) return e;
 #define SFC_LAUNCH(I)                                                                      \
   launch_scatter<I>(pass == 0, false, false, shift, tiles, kin, ids_b, kout, vout, m, rel, dtot, \
-                    err, nullptr, nullptr, nullptr, curve, nullptr, s)
+                    err, nullptr, nullptr, nullptr, curve, nullptr, SortGuard{}, s)
     switch (sort_items(m)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;
@@ -1078,10 +1170,11 @@ hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uin
   if (n == 0) return hipSuccess;
   ProfScope ps("gather_points", s);
   if (dim == 3)
-    gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids, xy, out, nullptr, n);
+    gather_points3<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids, xy, out, nullptr, n,
+                                                                SortGuard{});
   else
     gather_points<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(ids, (const double2*)xy,
-                                                               (double2*)out, n);
+                                                               (double2*)out, n, SortGuard{});
   return hipGetLastError();
 }
 

@@ -36,11 +36,19 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s);
 
 // ---- construction (build.hip) ----
 size_t build_scratch_bytes(uint64_t n);
+// Run condition of a kernel sequence recorded beside an alternative one (a
+// recorded graph cannot branch on the host): with word != null each of its
+// kernels returns at once unless the kErrOversized bit of *word is set
+// (when_set) or clear (!when_set).
+struct SortGuard {
+  const uint32_t* word = nullptr;
+  bool when_set = true;
+};
 // Keys of n points (err: device word, kErrDomain is or-ed in); counts, if
 // not null, receives the first digit's counts per sort tile.
 hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, uint32_t* err,
                        uint32_t* counts, hipStream_t s, double* xy_copy = nullptr,
-                       int count_shift = 0);
+                       int count_shift = 0, SortGuard guard = SortGuard{});
 // xy_out (may be null): the points in sorted order.  cells_out (may be
 // null): the grid cells of the sorted points (pack_cell2 / pack_cell3),
 // decoded from the keys (or taken from the points when they are gathered).
@@ -48,7 +56,8 @@ hipError_t launch_keys(const double* xy, uint64_t n, int curve, uint64_t* keys, 
 hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                       uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
                       hipStream_t s, const uint64_t* set_off = nullptr, uint32_t n_sets = 0,
-                      uint64_t* cells_out = nullptr, double* xy_copy = nullptr);
+                      uint64_t* cells_out = nullptr, double* xy_copy = nullptr,
+                      SortGuard guard = {});
 // sort_build without point sets or xy_out, by four radix passes over the
 // top 32 key bits and an LDS sort of each chunk of whole runs of equal top
 // bits (same results).  A run too long for a chunk raises kErrOversized in
@@ -57,6 +66,20 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
 hipError_t sort_build_chunked(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
                               uint32_t* ids_out, void* scratch, uint32_t* err, hipStream_t s,
                               uint64_t* cells_out, double* xy_copy);
+// sort_build_chunked with point sets (set_off and n_sets as in sort_build;
+// none: the chunked sort alone): the chunked sort of all points by key, then
+// stable passes over the set index (so that the order is by set, key, id, as
+// sort_build's).  A run too
+// long for a chunk raises kErrOversized and the set passes do nothing; with
+// fallback the plain sort_build (with the sets) then runs on the device,
+// its kernels recorded after these and doing nothing unless the bit is set.
+// xy_out (may be null): the points in sorted order.  No host
+// synchronisation: the whole sequence can be recorded into a graph.  Same
+// scratch as sort_build.
+hipError_t sort_build_sets_chunked(const double* xy, uint64_t n, int curve, uint64_t* keys_out,
+                                   uint32_t* ids_out, double* xy_out, void* scratch, uint32_t* err,
+                                   hipStream_t s, const uint64_t* set_off, uint32_t n_sets,
+                                   uint64_t* cells_out, double* xy_copy, bool fallback);
 // out[i] = xy[ids[i]] for points of dim (2 or 3) doubles.
 hipError_t gather_sorted(const uint32_t* ids, const double* xy, double* out, uint64_t n, int dim,
                          hipStream_t s);

@@ -155,3 +155,71 @@ def test_tune_pin_rejects_unknown_shapes():
                         (sfc.TUNE_TEST_SHAPE, 5), (7, 0)):
         with pytest.raises(sfc.SfcError):
             sfc.tune_pin(what, 1000, value)
+
+
+def expected_sets(pts, curve, set_off):
+    """The oracle's sorted arrays set by set (ids are input positions)."""
+    ks, ids, xs = [], [], []
+    for s in range(len(set_off) - 1):
+        a, b = int(set_off[s]), int(set_off[s + 1])
+        if b == a:
+            continue
+        k, i, x = oracle.build(pts[a:b], curve)
+        ks.append(k)
+        ids.append(i.astype(np.uint64) + a)
+        xs.append(x)
+    return np.concatenate(ks), np.concatenate(ids).astype(np.uint32), np.concatenate(xs)
+
+
+def sets_with_long_run(seed, n=60_000, run=9_000):
+    """n uniform points in three sets, and the same with the first run points
+    moved into one cell of side 2^-16 (keys with equal top 32 bits: a run too
+    long for a chunk) inside the first set."""
+    rng = np.random.default_rng(seed)
+    fit = rng.random((n, 2))
+    long_run = fit.copy()
+    long_run[:run] = cell_run(rng, run, 2)
+    return fit, long_run, np.array([0, 20_000, 45_000, n], np.uint64)
+
+
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_sets_chunked_and_fallback(curve):
+    """Point sets take the chunked sort followed by a pass over the set index;
+    a run too long for a chunk sends the build to the plain sort with the
+    sets.  Both give the oracle's arrays set by set."""
+    fit, long_run, set_off = sets_with_long_run(31 + curve)
+    for pts, fell in ((fit, 0), (long_run, 1)):
+        idx = sfc.Index(dev(pts), curve=curve, set_off=set_off)
+        assert sfc.debug_sort_path(-1) == fell
+        keys, ids, xy = idx.sorted_arrays()
+        k, i, x = expected_sets(pts, curve, set_off)
+        assert np.array_equal(keys.cpu().numpy().view(np.uint64), k)
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), i)
+        assert np.array_equal(xy.cpu().numpy(), x)
+        idx.close()
+
+
+@pytest.mark.parametrize("sets", [False, True])
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_recorded_build_falls_back_on_the_device(curve, sets):
+    """A recorded build holds the chunked sort and, behind it, the plain one,
+    whose kernels do nothing unless a run was too long for a chunk.  Replays
+    on points that fit and on points that do not, written into the same
+    buffer between replays, all give the oracle's arrays."""
+    fit, long_run, set_off = sets_with_long_run(41 + curve)
+    if not sets:
+        set_off = np.array([0, len(fit)], np.uint64)
+    pts = dev(fit)
+    idx = sfc.Index(pts, curve, set_off=set_off if sets else None)
+    gb = sfc.Graph.build(idx, pts)
+    for rep, data in enumerate((long_run, fit, long_run, fit)):
+        pts.copy_(dev(data))
+        gb.launch()
+        gb.wait()
+        keys, ids, xy = idx.sorted_arrays()
+        k, i, x = expected_sets(data, curve, set_off)
+        assert np.array_equal(keys.cpu().numpy().view(np.uint64), k), rep
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), i), rep
+        assert np.array_equal(xy.cpu().numpy(), x), rep
+    gb.close()
+    idx.close()
