@@ -192,14 +192,50 @@ __global__ __launch_bounds__(256) void query_keys_tiles(const double2* __restric
   store_tile_counts(h, counts, tiles, blockIdx.x);
 }
 
+// Point sets whose offsets a set pass stages in LDS (one pass, the set found
+// by a binary search there); more sets read the set of every input position
+// from an array.
+constexpr uint32_t kLdsSets = 256;
+
+// The set of input position v: the last s with off[s] <= v (off: the n_sets
+// + 1 set offsets; a set that is empty shares its offset with the next one).
+__device__ __forceinline__ uint32_t set_of(const uint64_t* off, uint32_t n_sets, uint32_t v) {
+  uint32_t lo = 0, len = n_sets + 1;   // off[lo] <= v
+  while (len > 1) {
+    const uint32_t half = len >> 1;
+    if (off[lo + half] <= v) {
+      lo += half;
+      len -= half;
+    } else {
+      len = half;
+    }
+  }
+  return lo;
+}
+
 // Digit of an element in a pass: a byte of the key, or (SETPASS) a byte of
-// the point set the element's id belongs to.  Padding (id 0xFFFFFFFF) takes
-// digit 255 so that it sorts last.
+// the point set the element's id belongs to (from the offsets in LDS when
+// s_off is set, else from set_id).  Padding (id 0xFFFFFFFF) takes digit 255
+// so that it sorts last.
 template <bool SETPASS>
 __device__ __forceinline__ uint32_t pass_digit(uint64_t k, uint32_t v, int shift,
-                                               const uint32_t* __restrict__ set_id) {
+                                               const uint32_t* __restrict__ set_id,
+                                               const uint64_t* s_off = nullptr,
+                                               uint32_t n_sets = 0) {
   if (!SETPASS) return (uint32_t)(k >> shift) & 255u;
-  return v == 0xFFFFFFFFu ? 255u : (set_id[v] >> shift) & 255u;
+  if (v == 0xFFFFFFFFu) return 255u;
+  return ((s_off ? set_of(s_off, n_sets, v) : set_id[v]) >> shift) & 255u;
+}
+
+// With set_off (at most kLdsSets sets), a set pass's workgroup copies the set
+// offsets into LDS; the caller's barrier follows.
+template <bool SETPASS>
+__device__ __forceinline__ const uint64_t* stage_set_off(uint64_t* s_off,
+                                                         const uint64_t* __restrict__ set_off,
+                                                         uint32_t n_sets) {
+  if (!SETPASS || !set_off) return nullptr;
+  for (uint32_t i = threadIdx.x; i <= n_sets; i += blockDim.x) s_off[i] = set_off[i];
+  return s_off;
 }
 
 // The tile's digit counts for a pass.
@@ -209,10 +245,13 @@ __global__ __launch_bounds__(256) void tile_hist(const uint64_t* __restrict__ ki
                                                  uint32_t tile_len, int shift,
                                                  const uint32_t* __restrict__ set_id,
                                                  uint32_t* __restrict__ counts, uint64_t tiles,
-                                                 SortGuard guard) {
+                                                 const uint64_t* __restrict__ set_off,
+                                                 uint32_t n_sets, SortGuard guard) {
   if (guard_skips(guard)) return;
   __shared__ uint32_t h[kSortWaves][kRadix];
+  __shared__ uint64_t s_off_mem[SETPASS ? kLdsSets + 1 : 1];
   for (int i = threadIdx.x; i < kSortWaves * kRadix; i += 256) (&h[0][0])[i] = 0;
+  const uint64_t* s_off = stage_set_off<SETPASS>(s_off_mem, set_off, n_sets);
   __syncthreads();
   const uint64_t base = (uint64_t)blockIdx.x * tile_len;
   const uint64_t end = base + tile_len < n ? base + tile_len : n;
@@ -227,7 +266,7 @@ __global__ __launch_bounds__(256) void tile_hist(const uint64_t* __restrict__ ki
     for (int j = 0; j < kBatch; ++j) {
       const uint64_t i = i0 + 256u * j;
       const uint64_t ic = i < end ? i : end - 1;
-      const uint32_t d = SETPASS ? pass_digit<true>(0, vin[ic], shift, set_id)
+      const uint32_t d = SETPASS ? pass_digit<true>(0, vin[ic], shift, set_id, s_off, n_sets)
                                  : pass_digit<false>(kin[ic], 0, shift, set_id);
       dg[j] = i < end ? d : (uint32_t)kRadix;
     }
@@ -302,7 +341,7 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_pass(
     const uint32_t* __restrict__ rel, const uint32_t* __restrict__ dtot, uint64_t tiles,
     uint32_t* err, const double2* __restrict__ xy_in, double2* __restrict__ xy_out,
     uint64_t* __restrict__ cells_out, int cell_curve, const uint32_t* __restrict__ set_id,
-    SortGuard guard) {
+    const uint64_t* __restrict__ set_off, uint32_t n_sets, SortGuard guard) {
   if (guard_skips(guard)) return;
   constexpr int kTile = kSortThreads * ITEMS;
   constexpr int IT = kTile / kScatterThreads;
@@ -317,12 +356,14 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_pass(
   __shared__ uint32_t s_local[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_tmp[kScatterWaves];
+  __shared__ uint64_t s_off_mem[SETPASS ? kLdsSets + 1 : 1];
 
   const uint64_t tile = xcd_tile(blockIdx.x, tiles);
   if (tile >= tiles) return;   // the whole workgroup: no barrier is skipped by part of it
   const uint32_t tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   for (uint32_t i = tid; i < kScatterWaves * kRadix; i += kScatterThreads)
     (&sm.wave_hist[0][0])[i] = 0;
+  const uint64_t* s_off = stage_set_off<SETPASS>(s_off_mem, set_off, n_sets);
   const uint64_t base = tile * kTile;
   const uint64_t wbase = base + (uint64_t)w * (kWave * IT);
 
@@ -358,7 +399,7 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_pass(
   const uint64_t below_mask = lanemask_lt();
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
-    const uint32_t dg = pass_digit<SETPASS>(key[i], val[i], shift, set_id);
+    const uint32_t dg = pass_digit<SETPASS>(key[i], val[i], shift, set_id, s_off, n_sets);
     uint64_t match = ~0ull;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -397,7 +438,7 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_pass(
   uint32_t lpos[IT];
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
-    const uint32_t dd = pass_digit<SETPASS>(key[i], val[i], shift, set_id);
+    const uint32_t dd = pass_digit<SETPASS>(key[i], val[i], shift, set_id, s_off, n_sets);
     lpos[i] = s_local[dd] + sm.wave_hist[w][dd] + rank[i];
   }
   __syncthreads();
@@ -412,7 +453,7 @@ __global__ __launch_bounds__(kScatterThreads) void scatter_pass(
   for (uint32_t j = tid; j < valid; j += kScatterThreads) {
     const uint64_t k = sm.st.k[j];
     const uint32_t v = sm.st.v[j];
-    const uint32_t pos = s_gbase[pass_digit<SETPASS>(k, v, shift, set_id)] + j;
+    const uint32_t pos = s_gbase[pass_digit<SETPASS>(k, v, shift, set_id, s_off, n_sets)] + j;
     if (pos >= n || (GATHER && v >= n)) {   // cannot happen with consistent counts
       atomicOr(err, kErrInternal);
       continue;
@@ -804,15 +845,16 @@ hipError_t launch_scatter(bool first, bool gather, bool setpass, int shift, uint
                           const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                           uint32_t* vout, uint64_t n, const uint32_t* rel, const uint32_t* dtot,
                           uint32_t* err, const double* xy, double* xy_out, uint64_t* cells_out,
-                          int cell_curve, const uint32_t* set_id, SortGuard guard,
-                          hipStream_t s) {
+                          int cell_curve, const uint32_t* set_id, const uint64_t* set_off,
+                          uint32_t n_sets, SortGuard guard, hipStream_t s) {
   const dim3 g((uint32_t)(((tiles + 7) / 8) * 8)), b(kScatterThreads);
   const double2* xi = (const double2*)xy;
   double2* xo = (double2*)xy_out;
 #define SFC_PASS(F, G, S)                                                                      \
   scatter_pass<ITEMS, F, G, S><<<g, b, 0, s>>>(kin, vin, kout, vout, n, shift, rel, dtot,     \
                                                tiles, err, G ? xi : nullptr, G ? xo : nullptr, \
-                                               cells_out, cell_curve, set_id, guard)
+                                               cells_out, cell_curve, set_id, set_off,     \
+                                               n_sets, guard)
   if (setpass) {
     if (gather) SFC_PASS(false, true, true);
     else SFC_PASS(false, false, true);
@@ -834,7 +876,8 @@ hipError_t radix_pass(bool counted, bool first, bool gather, bool setpass, int s
                       const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
                       uint32_t* counts, uint32_t* rel, uint32_t* dtot, uint32_t* err,
                       const double* xy, double* xy_out, uint64_t* cells_out, int curve,
-                      const uint32_t* set_id, SortGuard guard, hipStream_t s) {
+                      const uint32_t* set_id, const uint64_t* set_off, uint32_t n_sets,
+                      SortGuard guard, hipStream_t s) {
   const uint32_t tile = (uint32_t)sort_tile(n);
   const uint64_t tiles = (n + tile - 1) / tile;
   hipError_t e;
@@ -842,10 +885,10 @@ hipError_t radix_pass(bool counted, bool first, bool gather, bool setpass, int s
     ProfScope ps("tile_hist", s);
     if (setpass)
       tile_hist<true><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, set_id, counts,
-                                                      tiles, guard);
+                                                      tiles, set_off, n_sets, guard);
     else
       tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, vin, n, tile, shift, set_id, counts,
-                                                       tiles, guard);
+                                                       tiles, nullptr, 0, guard);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   {
@@ -856,7 +899,7 @@ hipError_t radix_pass(bool counted, bool first, bool gather, bool setpass, int s
   ProfScope ps(setpass ? "set_pass" : "scatter_pass", s);
 #define SFC_LAUNCH(I)                                                                          \
   launch_scatter<I>(first, gather, setpass, shift, tiles, kin, vin, kout, vout, n, rel, dtot, err, \
-                    xy, xy_out, cells_out, curve, set_id, guard, s)
+                    xy, xy_out, cells_out, curve, set_id, set_off, n_sets, guard, s)
   switch (sort_items(n)) {
     case 16: return SFC_LAUNCH(16);
     case 12: return SFC_LAUNCH(12);
@@ -941,7 +984,10 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
   hipError_t e = launch_keys(xy, n, curve, keys_first, err_host_visible, counts, s, xy_copy, 0,
                              guard);
   if (e != hipSuccess) return e;
-  if (sp > 0) {
+  // Up to kLdsSets sets, the set passes find each element's set from the
+  // offsets (in LDS); more, from the set of every input position.
+  const uint64_t* lds_off = sp == 1 && n_sets <= kLdsSets ? set_off : nullptr;
+  if (sp > 0 && !lds_off) {
     ProfScope ps("set_prep", s);
     fill_set_ids<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(set_off, n_sets, n, set_id, guard);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -961,7 +1007,8 @@ hipError_t sort_build(const double* xy, uint64_t n, int curve, uint64_t* keys_ou
     const bool gather = last && xy_out && curve != SFC_CURVE_MORTON3;
     uint64_t* pass_cells = last && !(xy_out && curve == SFC_CURVE_MORTON3) ? cells_out : nullptr;
     e = radix_pass(pass == 0, pass == 0, gather, setpass, shift, n, kin, vin, kout, vout, counts,
-                   rel, dtot, err_host_visible, xy, xy_out, pass_cells, curve, set_id, guard, s);
+                   rel, dtot, err_host_visible, xy, xy_out, pass_cells, curve, set_id, lds_off,
+                   n_sets, guard, s);
     if (e != hipSuccess) return e;
     kin = kout;
     vin = vout;
@@ -998,7 +1045,8 @@ hipError_t chunked_core(const double* xy, uint64_t n, int curve, uint64_t* kfin,
     uint64_t* kout = fin ? kfin : ktmp;
     uint32_t* vout = fin ? ifin : itmp;
     e = radix_pass(pass == 0, pass == 0, false, false, kTopShift + 8 * pass, n, kin, vin, kout,
-                   vout, counts, rel, dtot, err, xy, nullptr, nullptr, curve, nullptr, {}, s);
+                   vout, counts, rel, dtot, err, xy, nullptr, nullptr, curve, nullptr, nullptr, 0,
+                   {}, s);
     if (e != hipSuccess) return e;
     kin = kout;
     vin = vout;
@@ -1060,7 +1108,8 @@ hipError_t sort_build_sets_chunked(const double* xy, uint64_t n, int curve, uint
   if (e != hipSuccess) return e;
   // The set passes run only on a complete chunked sort.
   const SortGuard when_sorted{err, false};
-  if (sp > 0) {
+  const uint64_t* lds_off = sp == 1 && n_sets <= kLdsSets ? set_off : nullptr;
+  if (sp > 0 && !lds_off) {
     ProfScope ps("set_prep", s);
     fill_set_ids<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(set_off, n_sets, n, set_id,
                                                              when_sorted);
@@ -1077,8 +1126,8 @@ hipError_t sort_build_sets_chunked(const double* xy, uint64_t n, int curve, uint
     uint64_t* kout = fin ? keys_out : keys_b;
     uint32_t* vout = fin ? ids_out : ids_b;
     e = radix_pass(false, false, last && gather2, true, 8 * pass, n, kin, vin, kout, vout, counts,
-                   rel, dtot, err, xy, xy_out, last ? cells_out : nullptr, curve, set_id,
-                   when_sorted, s);
+                   rel, dtot, err, xy, xy_out, last ? cells_out : nullptr, curve, set_id, lds_off,
+                   n_sets, when_sorted, s);
     if (e != hipSuccess) return e;
     kin = kout;
     vin = vout;
@@ -1134,14 +1183,14 @@ hipError_t order_queries(const double* q, uint64_t m, int curve, uint32_t* perm,
     uint32_t* vout = pass == 0 ? ids_b : perm;
     if (pass > 0) {
       tile_hist<false><<<(uint32_t)tiles, 256, 0, s>>>(kin, ids_b, m, tile, shift, nullptr, counts,
-                                                       tiles, SortGuard{});
+                                                       tiles, nullptr, 0, SortGuard{});
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     digit_scan<<<kRadix, 256, 0, s>>>(counts, tiles, rel, dtot, SortGuard{});
     if ((e = hipGetLastError()) != hipSuccess) return e;
 #define SFC_LAUNCH(I)                                                                      \
   launch_scatter<I>(pass == 0, false, false, shift, tiles, kin, ids_b, kout, vout, m, rel, dtot, \
-                    err, nullptr, nullptr, nullptr, curve, nullptr, SortGuard{}, s)
+                    err, nullptr, nullptr, nullptr, curve, nullptr, nullptr, 0, SortGuard{}, s)
     switch (sort_items(m)) {
       case 16: e = SFC_LAUNCH(16); break;
       case 12: e = SFC_LAUNCH(12); break;
