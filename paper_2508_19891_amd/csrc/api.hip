@@ -238,6 +238,7 @@ struct sfc_index {
   // early termination: occupancy bits of the quadtree nodes (null: off)
   uint32_t* occ = nullptr;
   uint64_t last_pruned = 0;
+  int last_coarse = -1;   // the last batch's ranges: some radius past the cell shift limit
   // updates (sfc_insert / sfc_erase); ins == null until the first update
   uint32_t* ins = nullptr;         // device, insert epoch per stored entry
   uint32_t* era = nullptr;         // device, erase epoch per stored entry
@@ -492,7 +493,7 @@ uint32_t slots_of(const sfc_index* h) { return dim_of(h) == 3 && h->refine ? 32 
 // Runs ranges + searches + scan; on SFC_OK *total_rows holds the number of
 // candidate rows and *total_cand the number of candidates.
 // The same into query scratch at ws (query_scratch_bytes(m, slots_of(h))
-// bytes), reading the counts back through rb (host, 7 words).
+// bytes), reading the counts back through rb (host, 8 words).
 sfc_status run_ranges_into(sfc_index* h, void* ws, uint64_t* rb, const double* q,
                            const double* delta, const uint32_t* qset, uint64_t m,
                            sfc::QueryScratch* qs, uint64_t* total_rows, uint64_t* total_cand,
@@ -536,7 +537,7 @@ sfc_status run_ranges_into(sfc_index* h, void* ws, uint64_t* rb, const double* q
     SFC_TRY(sfc::validate_epochs(qepoch, m, h->oldest, h->epoch, qs->counters + 2, h->stream));
   uint64_t* pin = rb;
   SFC_TRY(hipMemcpyAsync(pin, qs->row_off + m, 8, hipMemcpyDeviceToHost, h->stream));
-  SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 48, hipMemcpyDeviceToHost, h->stream));
+  SFC_TRY(hipMemcpyAsync(pin + 1, qs->counters, 56, hipMemcpyDeviceToHost, h->stream));
   SFC_TRY(hipStreamSynchronize(h->stream));
   const uint32_t err = ((const uint32_t*)(pin + 1))[2];
   if (err & sfc::kErrInvalidQuery) return SFC_ERR_INVALID;
@@ -546,6 +547,7 @@ sfc_status run_ranges_into(sfc_index* h, void* ws, uint64_t* rb, const double* q
   h->linfo.endpoints_last = learned ? pin[4] : 0;
   h->linfo.fallbacks_last = learned ? pin[5] : 0;
   h->last_pruned = pin[6];   // counters[10..11]
+  h->last_coarse = (pin[7] >> 32) != 0 ? 1 : 0;   // counters[13]: radii past the shift limit
   return SFC_OK;
 }
 
@@ -933,7 +935,7 @@ sfc_status query_impl(sfc_index* h, const double* q, const double* delta, const 
   SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->xy_in, test_cells(h), h->ids, h->n, qs,
                               total_rows, false, h->cws, offsets, ids, ids_cap,
                               h->metric == SFC_METRIC_LINF, dim_of(h), h->stream,
-                              filtered ? &ev : nullptr));
+                              filtered ? &ev : nullptr, false, m > 0 ? h->last_coarse : 0));
   uint64_t total = 0;
   SFC_TRY(read_words(offsets + m, &total, 1, h->stream));
   if (m > 0) {
@@ -1163,7 +1165,7 @@ sfc_status sfc_query_batch_static(sfc_index* h, const double* q, const double* d
   sfc::QueryScratch qs{};
   uint64_t total_rows = 0, total_cand = 0;
   if (m > 0) {
-    uint64_t rb[7];
+    uint64_t rb[8];
     sfc_status st = run_ranges_into(h, base, rb, q, delta, nullptr, m, &qs, &total_rows,
                                     &total_cand, nullptr, nullptr, nullptr, nullptr, nullptr,
                                     nullptr);
@@ -1178,7 +1180,7 @@ sfc_status sfc_query_batch_static(sfc_index* h, const double* q, const double* d
   SFC_TRY(sfc::launch_compact(q, delta, m, h->xy, h->xy_in, test_cells(h), h->ids, h->n, qs,
                               total_rows, false, (char*)base + qbytes, offsets, ids, ids_cap,
                               h->metric == SFC_METRIC_LINF, dim_of(h), h->stream,
-                              filtered ? &ev : nullptr));
+                              filtered ? &ev : nullptr, false, m > 0 ? h->last_coarse : 0));
   uint64_t tail[3] = {0, 0, 0};   // the total, then the error word's doubleword
   SFC_TRY(hipMemcpyAsync(&tail[0], offsets + m, 8, hipMemcpyDeviceToHost, h->stream));
   if (m > 0)

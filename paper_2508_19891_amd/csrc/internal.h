@@ -161,7 +161,10 @@ hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, cons
 // sorted points (pack_cell2 / pack_cell3); with them most candidates are
 // decided from their cell and only the undecided ones read their coordinates,
 // from pts (the sorted points) when not null, else from pts_in (input order)
-// through their ids.  Without cells pts must not be null.
+// through their ids.  Without cells pts must not be null.  coarse: whether
+// some radius of the batch lies above the cell filter's shift limit (the
+// flag that launch_ranges sets in the counters: 1, 0 when the caller read
+// it, -1 when not; with 0 the test pass takes its shortest form).
 struct EpochView;
 hipError_t launch_compact(const double* q, const double* delta, uint64_t m, const double* pts,
                           const double* pts_in, const uint64_t* cells, const uint32_t* ids,
@@ -169,7 +172,8 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
                           int dim, hipStream_t s,
-                          const EpochView* ev = nullptr, bool write_only = false);
+                          const EpochView* ev = nullptr, bool write_only = false,
+                          int coarse = -1);
 // Whether a batch of total_rows rows (host-sized) is compacted in one chunk:
 // then an output larger than the capacity leaves the ids untouched, and the
 // write pass can be rerun alone (write_only) for a larger buffer.

@@ -609,16 +609,40 @@ __global__ __launch_bounds__(256) void expand_rows(const uint64_t* __restrict__ 
 // (relative errors below 2^-20 all told) these verdicts equal the exact
 // test's, whose own rounding is a few 2^-53 relative, when R >= 16 (so the
 // slack is small beside R^2).  Other points read their coordinates and take
-// the exact test.  A query uses the filter when 16 <= R <= 2^28 (plane) /
-// 2^17 (three dimensions) and its cell lies within 2^30 quanta of the
-// domain: then |e| < 2^31, exact in 32-bit arithmetic.  Cells sit in one
-// word: x | y << 32, or x | y << 21 | z << 42.
+// the exact test.  A query uses the filter when R >= 16 and its cell lies
+// within 2^30 quanta of the domain.  Above R = 2^28 (plane) / 2^17 (three
+// dimensions) the cells are compared 2^k quanta wide (u >> k against
+// floor(q S 2^-k), k the smallest shift that brings R 2^-k to that limit,
+// at most 24): the same bounds hold there with R 2^-k for R, since the
+// shifted offsets again differ from the exact ones by less than one.  Then
+// |e| < 2^31, exact in 32-bit arithmetic.  Cells sit in one word: x | y << 32,
+// or x | y << 21 | z << 42.
 struct QueryFilter {
-  float acc, rej;  // limits on sum e^2 (or per-axis |e|); filter off: acc = not a number
-                   // and rej = +inf, so that neither comparison decides a candidate
-  uint32_t c[3];   // the query's cell per axis (low 32 bits)
-  uint32_t pad[3];
+  float acc, rej;   // limits on sum e^2 (or per-axis |e|); filter off: acc = not a number
+                    // and rej = +inf, so that neither comparison decides a candidate
+  uint32_t c[3];    // the query's cell per axis (low 32 bits), 2^shift quanta wide
+  uint32_t shift;   // cells are compared 2^shift quanta wide
+  uint32_t pad[2];
 };
+static_assert(sizeof(QueryFilter) == 32, "a record is 32 bytes");
+// The batch counter word that flag_coarse sets when some query may compare
+// coarser cells (the counters are cleared when the ranges are computed).
+constexpr int kShiftWord = 13;   // free: 2 errors, 4-11 statistics, 12 tiles, 14-15 total
+
+// Sets counters[kShiftWord] when some radius of the batch lies above the
+// filter's shift limit (delta S > limit): then the test pass reads the cell
+// shifts.  One atomic per workgroup that has such a radius.
+__global__ __launch_bounds__(256) void flag_coarse(const double* __restrict__ delta, uint64_t m,
+                                                   double S, double limit,
+                                                   uint32_t* __restrict__ counters) {
+  __shared__ uint32_t s_any;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < m && delta[j] * S > limit) s_any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && s_any) atomicOr(&counters[kShiftWord], 1u);
+}
 
 template <int DIM>
 __global__ __launch_bounds__(256) void query_filters(const double* __restrict__ q,
@@ -628,14 +652,18 @@ __global__ __launch_bounds__(256) void query_filters(const double* __restrict__ 
   constexpr double kMaxR = DIM == 2 ? 0x1p28 : 0x1p17;
   const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= m) return;
-  const double R = delta[j] * S;
-  bool on = R >= 16.0 && R <= kMaxR;
+  const double R0 = delta[j] * S;
+  int k = 0;
+  while (k < 24 && R0 > kMaxR * __builtin_ldexp(1.0, k)) ++k;
+  const double R = __builtin_ldexp(R0, -k);   // exact
+  bool on = R0 >= 16.0 && R <= kMaxR;
   QueryFilter f{};
+  f.shift = (uint32_t)k;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const double qs = q[DIM * j + a] * S;
     on = on && qs > -0x1p30 && qs < S + 0x1p30;
-    f.c[a] = (uint32_t)(int64_t)__builtin_floor(on ? qs : 0.0);
+    f.c[a] = (uint32_t)(int64_t)__builtin_floor(on ? __builtin_ldexp(qs, -k) : 0.0);
   }
   if (window) {
     f.acc = (float)(R * (1.0 - 0x1p-16) - 1.0);
@@ -648,19 +676,24 @@ __global__ __launch_bounds__(256) void query_filters(const double* __restrict__ 
   if (!on) {   // undecided for every candidate: the exact test decides
     f.acc = __uint_as_float(0xFFFFFFFFu);
     f.rej = __builtin_inff();
+    f.shift = 0;
   }
   out[j] = f;
 }
 
-// 1: accepted, 0: rejected, -1: undecided by the cell.
-template <int DIM, bool WINDOW>
+// 1: accepted, 0: rejected, -1: undecided by the cell.  SHIFTED: the cells
+// are compared f.shift bits coarser (else f.shift is 0).
+template <int DIM, bool WINDOW, bool SHIFTED>
 __device__ __forceinline__ int cell_check(uint64_t cell, const QueryFilter& f) {
   constexpr int B = DIM == 2 ? 32 : 21;
   const uint64_t mask = (1ull << B) - 1;
   float e[DIM];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a)
-    e[a] = (float)(int32_t)((uint32_t)((cell >> (B * a)) & mask) - f.c[a]);
+  for (int a = 0; a < DIM; ++a) {
+    uint32_t u = (uint32_t)((cell >> (B * a)) & mask);
+    if (SHIFTED) u >>= f.shift;
+    e[a] = (float)(int32_t)(u - f.c[a]);
+  }
   if (WINDOW) {
     bool in = true, out = false;
 #pragma unroll
@@ -707,7 +740,7 @@ __device__ __forceinline__ bool exact_hit(const double* __restrict__ q,
 // EPOCH: a candidate that passes the test also has to be visible at the
 // query's epoch (ins <= e < era); only those lanes read the epochs.
 // window: the square-window test instead of the Euclidean one.
-template <int ROWS, int ITERS, bool EPOCH, int DIM, bool CELLS, bool WINDOW>
+template <int ROWS, int ITERS, bool EPOCH, int DIM, bool CELLS, bool WINDOW, bool SHIFTS>
 __global__ __launch_bounds__(256) void compact_test(
     const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const double* __restrict__ pts, const uint32_t* __restrict__ via,
@@ -719,6 +752,8 @@ __global__ __launch_bounds__(256) void compact_test(
     const uint32_t* __restrict__ qepoch, uint32_t epoch) {
   static_assert(ROWS * ITERS == (int)kWaveRows, "a wave's groups cover its rows");
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  // SHIFTS: the batch may hold queries with coarser cells (flag_coarse)
+  const bool any_shifted = SHIFTS && CELLS && counters[kShiftWord] != 0u;
   const uint64_t total_all = *total_rows_dev;
   const uint64_t total_rows = total_all < row_end ? total_all : row_end;
   const uint64_t ntiles = total_rows > rbase ? (total_rows - rbase + kTileRows - 1) / kTileRows : 0;
@@ -751,7 +786,8 @@ __global__ __launch_bounds__(256) void compact_test(
         // Decide from the cells; the coordinates only for undecided lanes.
         // The rows' filter records (uniform loads) and cells are all
         // requested before any is used.
-        // (the plane needs the record's first 16 bytes: limits and x, y)
+        // (the plane needs the record's first 16 bytes: limits and x, y; the
+        // cell shifts only in a batch with coarser cells)
         QueryFilter qf[ROWS];
 #pragma unroll
         for (int jr = 0; jr < ROWS; ++jr) {
@@ -761,18 +797,32 @@ __global__ __launch_bounds__(256) void compact_test(
           qf[jr].c[0] = a.z;
           qf[jr].c[1] = a.w;
           qf[jr].c[2] = DIM == 3 ? qfilt[qrow[jr]].c[2] : 0u;
+          qf[jr].shift = 0;
         }
         uint64_t cv[ROWS];
 #pragma unroll
         for (int jr = 0; jr < ROWS; ++jr) cv[jr] = cells[pos[jr]];   // pos 0 when inactive
         bool und[ROWS];
         bool any = false;
+        // A batch with coarser cells (radii past the shift limit) takes the
+        // shifting check.
+        if (!any_shifted) {
 #pragma unroll
-        for (int jr = 0; jr < ROWS; ++jr) {
-          const int vd = act[jr] ? cell_check<DIM, WINDOW>(cv[jr], qf[jr]) : 0;
-          hit[jr] = vd == 1;
-          und[jr] = vd < 0;
-          any = any || und[jr];
+          for (int jr = 0; jr < ROWS; ++jr) {
+            const int vd = act[jr] ? cell_check<DIM, WINDOW, false>(cv[jr], qf[jr]) : 0;
+            hit[jr] = vd == 1;
+            und[jr] = vd < 0;
+            any = any || und[jr];
+          }
+        } else {
+#pragma unroll
+          for (int jr = 0; jr < ROWS; ++jr) {
+            qf[jr].shift = qfilt[qrow[jr]].shift;
+            const int vd = act[jr] ? cell_check<DIM, WINDOW, true>(cv[jr], qf[jr]) : 0;
+            hit[jr] = vd == 1;
+            und[jr] = vd < 0;
+            any = any || und[jr];
+          }
         }
         // The candidates their cells leave undecided (rare) take the exact
         // test, behind one branch for the whole group.
@@ -1074,6 +1124,9 @@ hipError_t launch_ranges(const double* q, const double* delta, uint64_t m, const
   const uint32_t blocks = (uint32_t)((4 * m + 255) / 256);
   hipError_t e;
   if ((e = fill_u32(qs.counters, 0, 16, s)) != hipSuccess) return e;
+  flag_coarse<<<(uint32_t)((m + 255) / 256), 256, 0, s>>>(delta, m, 4294967296.0, 0x1p28,
+                                                           qs.counters);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if (dbg_lo) refine = false;   // the inspected ranges are the method's merged ranges
   qs.ss = refine ? 3 : 2;
   const bool learned = lview != nullptr && qset == nullptr;
@@ -1166,6 +1219,9 @@ hipError_t launch_ranges3(const double* q, const double* delta, uint64_t m, cons
   if (m == 0) return hipSuccess;
   hipError_t e;
   if ((e = fill_u32(qs.counters, 0, 16, s)) != hipSuccess) return e;
+  flag_coarse<<<(uint32_t)((m + 255) / 256), 256, 0, s>>>(delta, m, 2097152.0, 0x1p17,
+                                                           qs.counters);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   qs.ss = refine ? 5 : 3;
   const uint32_t blocks = (uint32_t)((8 * m + 255) / 256);
   unsigned long long* cand = (unsigned long long*)(qs.counters + 4);
@@ -1195,9 +1251,13 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
                           uint64_t npts, const QueryScratch& qs,
                           uint64_t max_rows, bool device_sized, void* cscratch,
                           uint64_t* offsets, uint32_t* out_ids, uint64_t cap, bool window,
-                          int dim, hipStream_t s, const EpochView* ev, bool write_only) {
+                          int dim, hipStream_t s, const EpochView* ev, bool write_only,
+                          int coarse) {
   hipError_t e;
   if (m == 0) return fill_u64(offsets, 0, 1, s);
+  // Whether the test pass may meet queries with coarser cells: known (0, 1)
+  // when the caller read the batch's flag, else (-1) the pass reads it.
+  const bool shifts = coarse != 0;
   const uint64_t nseg = m << qs.ss;
   const uint64_t* total_dev = qs.row_off + m;
   // Rows are processed in chunks of at most kCompactChunkTiles tiles.
@@ -1253,13 +1313,16 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
     if (!write_only) {
       if ((e = fill_u32(hits, 0, nt, s)) != hipSuccess) return e;
       ProfScope ps("compact_test", s);
-#define SFC_TEST_W(R, I, E, D, C, W)                                                       \
-  compact_test<R, I, E, D, C, W><<<grid, 256, 0, s>>>(                                     \
+#define SFC_TEST_K(R, I, E, D, C, W, K)                                                    \
+  compact_test<R, I, E, D, C, W, K><<<grid, 256, 0, s>>>(                                  \
       q, delta, m, pts ? pts : pts_in, pts ? nullptr : ids, cells,                         \
       (const QueryFilter*)qs.qfilt, npts, meta,                                            \
       total_dev, rbase, row_end, flag, masks, hits, qs.counters,                           \
       ev ? ev->ins : nullptr, ev ? ev->era : nullptr,                                      \
       ev ? ev->qepoch : nullptr, ev ? ev->epoch : 0u)
+#define SFC_TEST_W(R, I, E, D, C, W)                                                       \
+  if (C && shifts) SFC_TEST_K(R, I, E, D, C, W, C);                                        \
+  else SFC_TEST_K(R, I, E, D, C, W, false)
 #define SFC_TEST_D(R, I, E, D, C)                                                          \
   if (window) SFC_TEST_W(R, I, E, D, C, true);                                             \
   else SFC_TEST_W(R, I, E, D, C, false)
@@ -1288,6 +1351,7 @@ hipError_t launch_compact(const double* q, const double* delta, uint64_t m, cons
 #undef SFC_TEST
 #undef SFC_TEST_D
 #undef SFC_TEST_W
+#undef SFC_TEST_K
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!write_only &&

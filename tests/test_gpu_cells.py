@@ -82,6 +82,44 @@ def test_adversarial_sets(curve):
     assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
 
 
+@pytest.mark.parametrize("metric", [L2, LINF])
+@pytest.mark.parametrize("curve", [MORTON, HILBERT])
+def test_large_radii_compare_coarser_cells(curve, metric):
+    """Radii from 2^-5 to 1.5 (2^27 to 6.4e9 quanta): above 2^28 quanta the
+    cells are compared 2^k quanta wide; with points in the boundary band of
+    every query, the filter's results equal the exact test's and the
+    oracle's."""
+    rng = np.random.default_rng(150 + curve + 2 * metric)
+    qs = rng.uniform(0.0, 1.0, (160, 2))
+    ds = 2.0 ** rng.uniform(-5, 0.6, 160)
+    pts = np.concatenate([boundary_points(rng, qs, ds, per=12, metric=metric),
+                          rng.random((6_000, 2))])
+    idx = sfc.Index(dev(pts), curve, refine=True, metric=sfc.LINF if metric else sfc.L2)
+    off, ids = both(idx, qs, ds)
+    ref = oracle.query(oracle.build(pts, curve), qs, ds, curve, metric=metric)
+    assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
+
+
+@pytest.mark.parametrize("metric", [L2, LINF])
+def test_large_radii_three_dimensions(metric):
+    rng = np.random.default_rng(160 + metric)
+    qs = rng.uniform(0.0, 1.0, (80, 3))
+    ds = 2.0 ** rng.uniform(-5, 0.3, 80)
+    band = []
+    for q, d in zip(qs, ds):
+        for _ in range(12):
+            v = rng.standard_normal(3)
+            v = v / (np.linalg.norm(v) if metric == L2 else np.abs(v).max())
+            p = q + d * (1 + rng.integers(-6, 7) * 2.0 ** -52) * v
+            if np.all(p >= 0) and np.all(p < 1):
+                band.append(p)
+    pts = np.concatenate([np.array(band).reshape(-1, 3), rng.random((4_000, 3))])
+    idx = sfc.Index(dev(pts), sfc.MORTON3, refine=True, metric=sfc.LINF if metric else sfc.L2)
+    off, ids = both(idx, qs, ds)
+    ref = oracle.query3(oracle.build3(pts), qs, ds, metric=metric)
+    assert np.array_equal(off, ref[0]) and np.array_equal(ids, ref[1])
+
+
 def test_extreme_radii_and_far_queries():
     rng = np.random.default_rng(120)
     pts = rng.random((5000, 2))

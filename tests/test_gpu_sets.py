@@ -117,3 +117,15 @@ def test_sets_at_each_tile_size(items):
         check_sets(wl, MORTON, refine=True).close()
     finally:
         sfc.tune_pin(sfc.TUNE_SORT_ITEMS, n, -1)
+
+
+@pytest.mark.parametrize("n_sets,log2_m", [(40, (8, 11)), (300, (6, 9))])
+def test_large_batches_over_sets(n_sets, log2_m):
+    """Batches of 2^14 queries and more over point sets (past 256 sets too:
+    two passes over the set index in the build), with radii up to those of
+    the smallest sets (compared on coarser cells): the per-set CSR is the
+    oracle's."""
+    wl = workload.batched_uneven(n_sets=n_sets, log2_n=(4, 12), log2_m=log2_m, curve=HILBERT,
+                                 seed=60 + n_sets)
+    assert len(wl.queries) >= 1 << 14
+    check_sets(wl, HILBERT, refine=True).close()
