@@ -243,9 +243,27 @@ __device__ int query_ranges3(double qx, double qy, double qz, double d, uint64_t
 
 // The level-l cubes meeting the widened box, unmerged and sorted by key, with
 // their coordinates at level l (for the refinement); *L gets l, b the box.
-__device__ int query_cubes3(double qx, double qy, double qz, double d, uint64_t lo[8],
-                            uint32_t cx[8], uint32_t cy[8], uint32_t cz[8], int* L,
-                            int64_t b[6]) {
+__device__ __forceinline__ void cube_cas(uint64_t* lo, uint32_t* cx, uint32_t* cy, uint32_t* cz,
+                                         int i, int j) {
+  if (lo[j] < lo[i]) {
+    const uint64_t k = lo[i];
+    lo[i] = lo[j];
+    lo[j] = k;
+    uint32_t t = cx[i];
+    cx[i] = cx[j];
+    cx[j] = t;
+    t = cy[i];
+    cy[i] = cy[j];
+    cy[j] = t;
+    t = cz[i];
+    cz[i] = cz[j];
+    cz[j] = t;
+  }
+}
+
+__device__ __forceinline__ int query_cubes3(double qx, double qy, double qz, double d,
+                                            uint64_t lo[8], uint32_t cx[8], uint32_t cy[8],
+                                            uint32_t cz[8], int* L, int64_t b[6]) {
   if (!axis_box3(qx, d, b[0], b[1]) || !axis_box3(qy, d, b[2], b[3]) ||
       !axis_box3(qz, d, b[4], b[5]))
     return 0;
@@ -260,23 +278,35 @@ __device__ int query_cubes3(double qx, double qy, double qz, double d, uint64_t 
     return 1;
   }
   *L = l;
+  // A box of side at most 2^l meets at most two level-l cells per axis: the
+  // eight candidates (x0 + dx, y0 + dy, z0 + dz), those outside the box keyed
+  // past every cube, then sorted by key with a fixed network (Batcher's
+  // odd-even merge, 19 exchanges), every array index static so that the
+  // arrays stay in registers.
+  const uint32_t x0 = (uint32_t)(b[0] >> l), x1 = (uint32_t)(b[1] >> l);
+  const uint32_t y0 = (uint32_t)(b[2] >> l), y1 = (uint32_t)(b[3] >> l);
+  const uint32_t z0 = (uint32_t)(b[4] >> l), z1 = (uint32_t)(b[5] >> l);
   int k = 0;
-  for (uint32_t x = (uint32_t)(b[0] >> l); x <= (uint32_t)(b[1] >> l); ++x)
-    for (uint32_t y = (uint32_t)(b[2] >> l); y <= (uint32_t)(b[3] >> l); ++y)
-      for (uint32_t z = (uint32_t)(b[4] >> l); z <= (uint32_t)(b[5] >> l); ++z) {
-        const uint64_t key = morton3_key(x << l, y << l, z << l);
-        int t = k++;
-        for (; t > 0 && lo[t - 1] > key; --t) {
-          lo[t] = lo[t - 1];
-          cx[t] = cx[t - 1];
-          cy[t] = cy[t - 1];
-          cz[t] = cz[t - 1];
-        }
-        lo[t] = key;
-        cx[t] = x;
-        cy[t] = y;
-        cz[t] = z;
-      }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const uint32_t x = x0 + (c & 1), y = y0 + ((c >> 1) & 1), z = z0 + (c >> 2);
+    const bool in = x <= x1 && y <= y1 && z <= z1;
+    lo[c] = in ? morton3_key(x << l, y << l, z << l) : ~0ull;
+    cx[c] = x;
+    cy[c] = y;
+    cz[c] = z;
+    k += in ? 1 : 0;
+  }
+  cube_cas(lo, cx, cy, cz, 0, 1); cube_cas(lo, cx, cy, cz, 2, 3);
+  cube_cas(lo, cx, cy, cz, 4, 5); cube_cas(lo, cx, cy, cz, 6, 7);
+  cube_cas(lo, cx, cy, cz, 0, 2); cube_cas(lo, cx, cy, cz, 1, 3);
+  cube_cas(lo, cx, cy, cz, 4, 6); cube_cas(lo, cx, cy, cz, 5, 7);
+  cube_cas(lo, cx, cy, cz, 1, 2); cube_cas(lo, cx, cy, cz, 5, 6);
+  cube_cas(lo, cx, cy, cz, 0, 4); cube_cas(lo, cx, cy, cz, 1, 5);
+  cube_cas(lo, cx, cy, cz, 2, 6); cube_cas(lo, cx, cy, cz, 3, 7);
+  cube_cas(lo, cx, cy, cz, 2, 4); cube_cas(lo, cx, cy, cz, 3, 5);
+  cube_cas(lo, cx, cy, cz, 1, 2); cube_cas(lo, cx, cy, cz, 3, 4);
+  cube_cas(lo, cx, cy, cz, 5, 6);
   return k;
 }
 
@@ -287,9 +317,10 @@ __device__ int query_cubes3(double qx, double qy, double qz, double d, uint64_t 
 // (four slots per cube, 32 per query), each found by two searches inside the
 // cube's index range.  The reported ids and their order do not change.
 template <int SEARCH, bool REFINE>
-// Five waves per SIMD (the refined variants then keep their per-cube arrays
-// in scratch): 2.03 -> 1.89 ms binary, 1.67 -> 1.36 ms with the static
-// search tree, for 2^20 queries over 2^24 keys.
+// Five waves per SIMD or more (the cubes sorted by a fixed network, so that
+// their arrays stay in registers): 1.71 ms binary, 1.16 ms with the static
+// search tree for 2^20 queries over 2^24 keys, against 1.89 and 1.39 ms with
+// the arrays in scratch memory.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void ranges_search3(
     const double* __restrict__ q, const double* __restrict__ delta, uint64_t m,
     const uint64_t* __restrict__ keys, uint64_t n, LearnedView lv, StreeView sv,
@@ -308,16 +339,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void r
     } else if (!REFINE) {
       uint64_t lo[8], hi[8];
       const int nr = query_ranges3(qx, qy, qz, d, lo, hi);
-      if (r < nr) find_range<SEARCH>(keys, n, lv, sv, lo[r], hi[r], B[0], E[0], fb);
+      // The lane's range, taken with static indexes (a runtime index into
+      // the arrays would put them in scratch memory).
+      uint64_t mlo = 0, mhi = 0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c == r) {
+          mlo = lo[c];
+          mhi = hi[c];
+        }
+      if (r < nr) find_range<SEARCH>(keys, n, lv, sv, mlo, mhi, B[0], E[0], fb);
     } else {
       uint64_t lo[8];
       uint32_t cx[8], cy[8], cz[8];
       int64_t b[6];
       int L = 0;
       const int nr = query_cubes3(qx, qy, qz, d, lo, cx, cy, cz, &L, b);
+      // The lane's cube, taken with static indexes (a runtime index into the
+      // arrays would put them in scratch memory).
+      uint64_t mlo = 0;
+      uint32_t mx = 0, my = 0, mz = 0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c == r) {
+          mlo = lo[c];
+          mx = cx[c];
+          my = cy[c];
+          mz = cz[c];
+        }
       if (r < nr) {
         const uint64_t span = L >= 21 ? (1ull << 63) - 1 : (1ull << (3 * L)) - 1;
-        find_range<SEARCH>(keys, n, lv, sv, lo[r], lo[r] | span, B[0], E[0], fb);
+        find_range<SEARCH>(keys, n, lv, sv, mlo, mlo | span, B[0], E[0], fb);
         if (E[0] - B[0] > refine_min && L >= 1 && L < 21) {
           const int Lc = L - 1;
           const uint64_t cspan = (1ull << (3 * Lc)) - 1;
@@ -325,9 +377,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void r
           uint32_t meet = 0;   // bit c: child c (x + 2y + 4z) meets the box
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
-            const int64_t x0 = (int64_t)(2 * cx[r] + (c & 1)) << Lc;
-            const int64_t y0 = (int64_t)(2 * cy[r] + ((c >> 1) & 1)) << Lc;
-            const int64_t z0 = (int64_t)(2 * cz[r] + (c >> 2)) << Lc;
+            const int64_t x0 = (int64_t)(2 * mx + (c & 1)) << Lc;
+            const int64_t y0 = (int64_t)(2 * my + ((c >> 1) & 1)) << Lc;
+            const int64_t z0 = (int64_t)(2 * mz + (c >> 2)) << Lc;
             const bool in = x0 <= b[1] && x0 + hs - 1 >= b[0] && y0 <= b[3] &&
                             y0 + hs - 1 >= b[2] && z0 <= b[5] && z0 + hs - 1 >= b[4];
             meet |= (uint32_t)in << c;
@@ -344,8 +396,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void r
                 const int c0 = __builtin_ctz(st), c1 = __builtin_ctz(en);
                 st &= st - 1;
                 en &= en - 1;
-                const uint64_t klo = lo[r] | ((uint64_t)c0 << (3 * Lc));
-                const uint64_t khi = lo[r] | ((uint64_t)c1 << (3 * Lc)) | cspan;
+                const uint64_t klo = mlo | ((uint64_t)c0 << (3 * Lc));
+                const uint64_t khi = mlo | ((uint64_t)c1 << (3 * Lc)) | cspan;
                 search_within(keys, pb, pe, klo, khi, B[k], E[k]);
               } else {
                 B[k] = E[k] = 0;
