@@ -150,31 +150,6 @@ __device__ __forceinline__ uint64_t lower_bound_in(const uint64_t* __restrict__ 
   return lo;
 }
 
-// The same result: binary steps down to at most 16 entries, then one scan
-// that counts the entries < k (loads clamped into the range, all issued
-// before the compares).
-__device__ __forceinline__ uint64_t lower_bound_scan(const uint64_t* __restrict__ a, uint64_t lo,
-                                                     uint64_t hi, uint64_t k) {
-  uint64_t len = hi - lo;
-  while (len > 16) {
-    const uint64_t h = len >> 1;
-    if (a[lo + h] < k) {
-      lo += h + 1;
-      len -= h + 1;
-    } else {
-      len = h;
-    }
-  }
-  if (len == 0) return lo;
-  uint64_t v[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = a[lo + ((uint64_t)i < len ? (uint64_t)i : len - 1)];
-  uint32_t c = 0;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) c += ((uint64_t)i < len && v[i] < k) ? 1u : 0u;
-  return lo + c;
-}
-
 // The piece's rank prediction for a key k > fk: R + round(s * (k - fk)),
 // clamped to [R + 1, Rn] (the bracket the lower bound lies in).
 __device__ __forceinline__ int64_t piece_predict(double s, uint64_t fk, uint64_t R, uint64_t Rn,
@@ -184,35 +159,6 @@ __device__ __forceinline__ int64_t piece_predict(double s, uint64_t fk, uint64_t
   double p = (double)R + floor(s * u + 0.5);
   p = fmin(fmax(p, (double)(R + 1)), (double)Rn);
   return (int64_t)p;
-}
-
-// Lower bound of k through the learned index; *fell_back is set when the
-// check of the result failed and the full binary search answered.
-__device__ __forceinline__ uint64_t learned_lower_bound(const uint64_t* __restrict__ keys,
-                                                       uint64_t n, const LearnedView& v,
-                                                       uint64_t k, bool* fell_back) {
-  // The pieces whose first key is below k: all those below k's 20-bit
-  // prefix, and some of those that share it.
-  const uint32_t t = (uint32_t)(k >> (64 - kDirectBits));
-  const uint32_t c = (uint32_t)lower_bound_scan(v.fk, v.dt[t], v.dt[t + 1], k);
-  uint64_t r = 0;   // no piece starts below k: keys[0] >= k
-  if (c > 0) {
-    // Piece c - 1 holds keys [R, Rn); its window covers every k in
-    // (fk, first key of the next piece], so the lower bound is in (R, Rn].
-    const uint32_t j = c - 1;
-    const uint64_t R = v.ps[j], Rn = v.ps[j + 1];
-    const PieceRec pc = v.pr[j];
-    const int64_t p = piece_predict(pc.s, v.fk[j], R, Rn, k);
-    int64_t wlo = p + pc.elo, whi = p + pc.ehi;
-    wlo = wlo < (int64_t)(R + 1) ? (int64_t)(R + 1) : wlo;
-    whi = whi > (int64_t)Rn ? (int64_t)Rn : whi;
-    if (whi < wlo) whi = wlo;
-    r = lower_bound_scan(keys, (uint64_t)wlo, (uint64_t)whi, k);
-  }
-  r = r > n ? n : r;   // keeps the check inside the array should the model be stale
-  const bool ok = (r == 0 || keys[r - 1] < k) && (r == n || keys[r] >= k);
-  *fell_back = !ok;
-  return ok ? r : lower_bound_in(keys, 0, n, k);
 }
 
 // ---- two lower bounds in lockstep ------------------------------------------
@@ -246,12 +192,16 @@ __device__ __forceinline__ void lower_bound_scan_pair(const uint64_t* __restrict
       }
     }
   }
+  // Only the entries left are loaded (a lane's load of an entry it does not
+  // need costs as much as one it does).
   uint64_t v[2][kScan2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int t = 0; t < kScan2; ++t)
-      v[i][t] = len[i] ? a[lo[i] + ((uint64_t)t < len[i] ? (uint64_t)t : len[i] - 1)] : 0;
+    for (int t = 0; t < kScan2; ++t) {
+      v[i][t] = 0;
+      if ((uint64_t)t < len[i]) v[i][t] = a[lo[i] + t];
+    }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     uint32_t c = 0;
@@ -261,34 +211,59 @@ __device__ __forceinline__ void lower_bound_scan_pair(const uint64_t* __restrict
   }
 }
 
-// r[i] = lower bound of k[i] over keys[0, n) for i = 0, 1 (the same result as
-// learned_lower_bound); returns the number of checks that fell back.
+// r[i] = lower bound of k[i] over keys[0, n) for i = 0, 1 through the learned
+// index: the piece whose first key is the last one below k[i] (the prefix
+// table's bracket, then a scan of the first keys that share the prefix), its
+// prediction and window, a search of the window, and a check of the result
+// against its neighbours, which falls back to binary search over the whole
+// array when it fails.  Returns the number of checks that fell back.
 __device__ __forceinline__ uint32_t learned_lower_bound_pair(const uint64_t* __restrict__ keys,
                                                             uint64_t n, const LearnedView& v,
                                                             const uint64_t k[2], uint64_t r[2]) {
-  // The pieces below each key: the prefix table's bracket, then a scan of
-  // the first keys that share the prefix.
+  // The two keys of a range mostly share their prefix and their piece: the
+  // second key then takes the first one's loads.
   uint64_t c[2], chi[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const uint32_t t = (uint32_t)(k[i] >> (64 - kDirectBits));
-    c[i] = v.dt[t];
-    chi[i] = v.dt[t + 1];
+  const uint32_t t0 = (uint32_t)(k[0] >> (64 - kDirectBits));
+  const uint32_t t1 = (uint32_t)(k[1] >> (64 - kDirectBits));
+  c[0] = v.dt[t0];
+  chi[0] = v.dt[t0 + 1];
+  c[1] = c[0];
+  chi[1] = chi[0];
+  if (t1 != t0) {
+    c[1] = v.dt[t1];
+    chi[1] = v.dt[t1 + 1];
   }
   lower_bound_scan_pair(v.fk, c, chi, k);
   // The bracketing piece, its prediction and window.
+  uint64_t R[2] = {0, 0}, Rn[2] = {0, 0}, fkj[2] = {0, 0};
+  PieceRec pc[2] = {};
+  if (c[0] > 0) {
+    const uint64_t j = c[0] - 1;
+    R[0] = v.ps[j];
+    Rn[0] = v.ps[j + 1];
+    pc[0] = v.pr[j];
+    fkj[0] = v.fk[j];
+  }
+  R[1] = R[0];
+  Rn[1] = Rn[0];
+  pc[1] = pc[0];
+  fkj[1] = fkj[0];
+  if (c[1] > 0 && c[1] != c[0]) {
+    const uint64_t j = c[1] - 1;
+    R[1] = v.ps[j];
+    Rn[1] = v.ps[j + 1];
+    pc[1] = v.pr[j];
+    fkj[1] = v.fk[j];
+  }
   uint64_t wlo[2], whi[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     wlo[i] = whi[i] = 0;
     if (c[i] > 0) {
-      const uint64_t j = c[i] - 1;
-      const uint64_t R = v.ps[j], Rn = v.ps[j + 1];
-      const PieceRec pc = v.pr[j];
-      const int64_t p = piece_predict(pc.s, v.fk[j], R, Rn, k[i]);
-      int64_t a = p + pc.elo, b = p + pc.ehi;
-      a = a < (int64_t)(R + 1) ? (int64_t)(R + 1) : a;
-      b = b > (int64_t)Rn ? (int64_t)Rn : b;
+      const int64_t p = piece_predict(pc[i].s, fkj[i], R[i], Rn[i], k[i]);
+      int64_t a = p + pc[i].elo, b = p + pc[i].ehi;
+      a = a < (int64_t)(R[i] + 1) ? (int64_t)(R[i] + 1) : a;
+      b = b > (int64_t)Rn[i] ? (int64_t)Rn[i] : b;
       if (b < a) b = a;
       wlo[i] = (uint64_t)a;
       whi[i] = (uint64_t)b;

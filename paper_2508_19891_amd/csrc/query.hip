@@ -387,20 +387,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void r
           if (meet != 0xFFu) {
             // Runs of consecutive children: the k-th run starts at the k-th
             // set bit of `st` and ends at the k-th set bit of `en`.
+            // The runs lie in the cube's index range: searched there, one
+            // after the other (four runs in lockstep took longer).
             const uint64_t pb = B[0], pe = E[0];
             uint32_t st = meet & ~(meet << 1);
             uint32_t en = meet & ~(meet >> 1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
+              B[k] = E[k] = 0;
               if (st) {
                 const int c0 = __builtin_ctz(st), c1 = __builtin_ctz(en);
                 st &= st - 1;
                 en &= en - 1;
                 const uint64_t klo = mlo | ((uint64_t)c0 << (3 * Lc));
                 const uint64_t khi = mlo | ((uint64_t)c1 << (3 * Lc)) | cspan;
-                search_within(keys, pb, pe, klo, khi, B[k], E[k]);
-              } else {
-                B[k] = E[k] = 0;
+                uint64_t x, y;
+                search_pair(keys + pb, pe - pb, klo, khi, x, y);
+                B[k] = pb + x;
+                E[k] = pb + y;
               }
             }
           }

@@ -157,34 +157,124 @@ __device__ int query_ranges(const uint16_t* lut, double qx, double qy, double d,
   return r;
 }
 
-// b = first index with keys[i] >= klo; e = first index with keys[i] > khi.
-// The two searches are interleaved to keep two loads in flight.
-__device__ __forceinline__ void search_pair(const uint64_t* __restrict__ keys, uint64_t n,
-                                            uint64_t klo, uint64_t khi, uint64_t& b,
-                                            uint64_t& e) {
-  uint64_t bl = 0, blen = n, el = 0, elen = n;
-  while (blen > 0 || elen > 0) {
-    if (blen > 0) {
-      const uint64_t h = blen >> 1;
-      if (keys[bl + h] < klo) {
-        bl += h + 1;
-        blen -= h + 1;
-      } else {
-        blen = h;
-      }
+// For each of K key intervals [klo[i], khi[i]] whose use flag is set:
+// b[i] = first index with keys[idx] >= klo[i], e[i] = first index with
+// keys[idx] > khi[i], over keys[0, n) (chains with use[i] false hold no
+// result; use[0] must be set).  Every chain keeps only its base and halves one shared length
+// (the answer stays in [base, base + len]), so all chains, and all lanes
+// that search arrays of one size, probe in lockstep.  All chains start at
+// one base and keep sharing it while each probe lies below every key of the
+// intervals (all move) or above every key (none moves): such a step takes
+// one load and one pair of compares for all.  From the step at which they
+// part, each chain loads its own probe, all of them before any compare.
+// I is the index type (32 bits whenever n allows: fewer instructions per
+// step).
+template <typename I, int K>
+__device__ __forceinline__ void search_lockstep_t(const uint64_t* __restrict__ keys, I n,
+                                                  const uint64_t (&klo)[K],
+                                                  const uint64_t (&khi)[K],
+                                                  const bool (&use)[K], uint64_t (&ob)[K],
+                                                  uint64_t (&oe)[K]) {
+  uint64_t alo = ~0ull, ahi = 0;   // the keys' span over the used intervals
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    if (use[i]) {
+      const uint64_t l = klo[i] < khi[i] ? klo[i] : khi[i];
+      const uint64_t h = klo[i] < khi[i] ? khi[i] : klo[i];
+      alo = l < alo ? l : alo;
+      ahi = h > ahi ? h : ahi;
     }
-    if (elen > 0) {
-      const uint64_t h = elen >> 1;
-      if (keys[el + h] <= khi) {
-        el += h + 1;
-        elen -= h + 1;
+  }
+  I b[K], e[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    b[i] = 0;
+    e[i] = 0;
+  }
+  if (n != 0) {
+    I len = n;
+    bool shared = true;
+    for (;;) {
+      const I half = len >> 1;   // 0 at the last step: probe the base itself
+      const I step = len > 1 ? half : 1;
+      const uint64_t v0 = keys[b[0] + half];
+      uint64_t vb[K], ve[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        vb[i] = v0;
+        ve[i] = v0;
+      }
+      if (!shared) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          if (use[i]) {
+            if (i > 0) vb[i] = keys[b[i] + half];
+            ve[i] = keys[e[i] + half];
+          }
+        }
+      }
+      if (shared) {
+        const bool below = v0 < alo;
+        if (below || v0 > ahi) {
+          b[0] += below ? step : 0;
+        } else {
+          // The chains part at this probe: each takes its own side of it.
+          const I base = b[0];
+#pragma unroll
+          for (int i = 0; i < K; ++i) {
+            b[i] = base + (v0 < klo[i] ? step : 0);
+            e[i] = base + (v0 <= khi[i] ? step : 0);
+          }
+          shared = false;
+        }
       } else {
-        elen = h;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          if (use[i]) {
+            b[i] += vb[i] < klo[i] ? step : 0;
+            e[i] += ve[i] <= khi[i] ? step : 0;
+          }
+        }
+      }
+      if (len == 1) break;
+      len -= half;
+    }
+    if (shared) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        b[i] = b[0];
+        e[i] = b[0];
       }
     }
   }
-  b = bl;
-  e = el;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    ob[i] = b[i];
+    oe[i] = e[i];
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void search_lockstep(const uint64_t* __restrict__ keys, uint64_t n,
+                                                const uint64_t (&klo)[K],
+                                                const uint64_t (&khi)[K], const bool (&use)[K],
+                                                uint64_t (&b)[K], uint64_t (&e)[K]) {
+  if (n <= 0xFFFFFFFFull)
+    search_lockstep_t<uint32_t, K>(keys, (uint32_t)n, klo, khi, use, b, e);
+  else
+    search_lockstep_t<uint64_t, K>(keys, n, klo, khi, use, b, e);
+}
+
+// b = first index with keys[i] >= klo; e = first index with keys[i] > khi.
+__device__ __forceinline__ void search_pair(const uint64_t* __restrict__ keys, uint64_t n,
+                                            uint64_t klo, uint64_t khi, uint64_t& b,
+                                            uint64_t& e) {
+  const uint64_t kl[1] = {klo}, kh[1] = {khi};
+  const bool use[1] = {true};
+  uint64_t bb[1], ee[1];
+  search_lockstep<1>(keys, n, kl, kh, use, bb, ee);
+  b = bb[0];
+  e = ee[0];
 }
 
 // Cells of cells(Q) for the widened box of (qx, qy, d), unmerged and sorted
@@ -264,20 +354,10 @@ __device__ int query_cells(const uint16_t* lut, double qx, double qy, double d, 
   return k;
 }
 
-__device__ __forceinline__ void search_within(const uint64_t* __restrict__ keys, uint64_t b,
-                                              uint64_t e, uint64_t klo, uint64_t khi,
-                                              uint64_t& rb, uint64_t& re) {
-  uint64_t x, y;
-  search_pair(keys + b, e - b, klo, khi, x, y);
-  rb = b + x;
-  re = b + y;
-}
-
-// Index range [b, e) of the key interval [klo, khi]: two binary searches, or
-// the learned index (whose lower bounds are verified and fall back to binary
-// search, so the result is the same).  *fb counts the fallbacks.
-// Index range [b, e) of the key interval [klo, khi]: SEARCH 0 binary
-// search, 1 the learned index, 2 the static search tree.
+// Index range [b, e) of the key interval [klo, khi]: SEARCH 0 two binary
+// searches, 1 the learned index (whose lower bounds are verified and fall
+// back to binary search, so the result is the same; *fb counts the
+// fallbacks), 2 the static search tree.
 template <int SEARCH>
 __device__ __forceinline__ void find_range(const uint64_t* __restrict__ keys, uint64_t n,
                                            const LearnedView& lv, const StreeView& sv,
@@ -324,21 +404,99 @@ __device__ __forceinline__ uint32_t sub_rank(const uint16_t* lut, uint32_t f, ui
   return D == 2 ? (a & 1u) | ((b & 1u) << 1) | ((a >> 1) << 2) | ((b >> 1) << 3) : a | (b << 1);
 }
 
-// Whether the disc of radius d about (qx, qy) may hold a point that the
-// exact test accepts within the grid rectangle [x0, x1) x [y0, y1) (grid
-// units of 2^-32): false only when the rectangle's distance from the centre,
-// squared, exceeds d^2 by a relative 2^-40, far beyond the few units in the
-// last place by which the exact test's binary64 arithmetic can err.  Radii
-// below 2^-400 (whose squares approach the subnormal range) keep every
-// rectangle.
-__device__ __forceinline__ bool disc_meets(double qx, double qy, double d, int64_t x0, int64_t x1,
-                                           int64_t y0, int64_t y1) {
-  if (!(d >= 0x1p-400)) return true;
-  const double s = 0x1p-32;
-  const double ex = fmax(0.0, fmax((double)x0 * s - qx, qx - (double)x1 * s));
-  const double ey = fmax(0.0, fmax((double)y0 * s - qy, qy - (double)y1 * s));
-  return !(ex * ex + ey * ey > d * d * (1.0 + 0x1p-40));
-}
+// The refinement of a crowded cell of cells(Q) (level L, grid cell (cx, cy),
+// keys from lo): its sub-cells D levels down (D = 2, or 1 at level 1) that
+// meet the widened box, and with the Euclidean metric the disc, as a mask
+// over their order along the curve.  kind -1: nothing to refine (level 0 or
+// 32, or every sub-cell kept); 0: no sub-cell kept, no point of the cell can
+// be reported; 1 or 2: the kept sub-cells as that many key runs [lo0, hi0],
+// [lo1, hi1] (consecutive sub-cells in key order; beyond two runs the gaps
+// other than the widest are closed).  Unused runs repeat the cell's keys.
+struct CellRuns {
+  int kind;
+  uint64_t lo0, hi0, lo1, hi1;
+};
 
+template <int CURVE>
+__device__ __forceinline__ CellRuns cell_runs(const uint16_t* lut, uint64_t lo, uint64_t hi,
+                                              uint32_t cx, uint32_t cy, int L,
+                                              const int64_t (&box)[4], bool ball, double qx,
+                                              double qy, double d) {
+  CellRuns cr{-1, lo, hi, lo, hi};
+  if (L < 1 || L >= 32) return cr;
+  const int D = L >= 2 ? 2 : 1;
+  const int Ls = L - D;
+  const uint32_t per = 1u << D;
+  const uint32_t f = CURVE == SFC_CURVE_HILBERT ? hilbert_frame(lo >> (2 * L), 32 - L) : 0u;
+  // A sub-cell meets the box when its column and its row do.  With the
+  // Euclidean metric it is dropped when its distance from the centre,
+  // squared, exceeds d^2 by a relative 2^-40 (far beyond the few units in
+  // the last place by which the exact test's binary64 arithmetic can err);
+  // that distance is the column's and the row's, each taken once.  Radii
+  // below 2^-400 (whose squares approach the subnormal range) keep every
+  // sub-cell.
+  const bool disc = ball && d >= 0x1p-400;
+  const double s = 0x1p-32;
+  const double lim = d * d * (1.0 + 0x1p-40);
+  uint32_t colm = 0, rowm = 0;
+  double ex2[4], ey2[4];
+#pragma unroll
+  for (uint32_t a = 0; a < 4; ++a) {
+    ex2[a] = 0.0;
+    ey2[a] = 0.0;
+    if (a < per) {
+      const int64_t x0 = (int64_t)(((uint64_t)cx * per + a) << Ls);
+      const int64_t y0 = (int64_t)(((uint64_t)cy * per + a) << Ls);
+      const int64_t x1 = x0 + ((int64_t)1 << Ls), y1 = y0 + ((int64_t)1 << Ls);
+      colm |= (uint32_t)!(x1 - 1 < box[0] || x0 > box[1]) << a;
+      rowm |= (uint32_t)!(y1 - 1 < box[2] || y0 > box[3]) << a;
+      const double ex = fmax(0.0, fmax((double)x0 * s - qx, qx - (double)x1 * s));
+      const double ey = fmax(0.0, fmax((double)y0 * s - qy, qy - (double)y1 * s));
+      ex2[a] = ex * ex;
+      ey2[a] = ey * ey;
+    }
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (uint32_t a = 0; a < 4; ++a) {
+#pragma unroll
+    for (uint32_t bb = 0; bb < 4; ++bb) {
+      if (!((colm >> a) & (rowm >> bb) & 1u)) continue;
+      if (disc && ex2[a] + ey2[bb] > lim) continue;
+      mask |= 1u << sub_rank<CURVE>(lut, f, a, bb, D);
+    }
+  }
+  const uint32_t full = D == 2 ? 0xFFFFu : 0xFu;
+  if (mask == full) return cr;
+  if (mask == 0) {
+    cr.kind = 0;
+    return cr;
+  }
+  const int first = __builtin_ctz(mask), last = 31 - __builtin_clz(mask);
+  int gap_at = 0, gap_len = 0;   // widest run of dropped sub-cells inside
+  for (int i = first; i <= last;) {
+    if ((mask >> i) & 1u) {
+      ++i;
+      continue;
+    }
+    int j = i;
+    while (!((mask >> j) & 1u)) ++j;
+    if (j - i > gap_len) {
+      gap_len = j - i;
+      gap_at = i;
+    }
+    i = j;
+  }
+  const int sh = 2 * Ls;
+  const int end0 = gap_len ? gap_at - 1 : last;
+  cr.kind = gap_len ? 2 : 1;
+  cr.lo0 = lo | ((uint64_t)first << sh);
+  cr.hi0 = lo | ((((uint64_t)end0 + 1) << sh) - 1);
+  if (gap_len) {
+    cr.lo1 = lo | ((uint64_t)(gap_at + gap_len) << sh);
+    cr.hi1 = lo | ((((uint64_t)last + 1) << sh) - 1);
+  }
+  return cr;
+}
 
 }  // namespace sfc

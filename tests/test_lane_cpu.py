@@ -230,3 +230,23 @@ def test_lane_cell_corner_points(harness, tmp_path, curve, search):
           seed=3)
     check(harness, tmp_path, pts, np.concatenate(qs), np.concatenate(ds), curve, False, search,
           seed=3)
+
+
+def test_lockstep_search(tmp_path):
+    """The lockstep search of several key intervals (one shared chain while
+    the probes fall outside every interval, then one chain per bound), both
+    index widths, against std::lower_bound / std::upper_bound under the
+    sanitizers: every array length up to 300 and some around powers of two,
+    repeated keys, unused and empty intervals, keys at both ends of the
+    64-bit range."""
+    if not os.path.isdir(ROCM_INCLUDE):
+        pytest.skip("HIP headers not installed")
+    exe = str(tmp_path / "search_check")
+    subprocess.check_call([
+        "g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+        "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-ffp-contract=off",
+        "-D__HIP_PLATFORM_AMD__", "-I", ROCM_INCLUDE, "-I", CSRC,
+        "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "cpu", "search_check.cpp"),
+        "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
