@@ -564,8 +564,16 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     copy_gbs = 10 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, b
-    log(f"device copy: {copy_gbs:.0f} GB/s")
+    # And of a plain read-only stream: a sum over the same 2^30 bytes.
+    s = a.sum()
+    e0.record()
+    for _ in range(10):
+        s = a.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read_gbs = 10 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b, s
+    log(f"device copy: {copy_gbs:.0f} GB/s, read-only sum: {read_gbs:.0f} GB/s")
 
     n, m = 1 << args.n_log2, 1 << args.m_log2
     curve = sfc.HILBERT
@@ -773,15 +781,20 @@ def main():
         "kernels_algorithmic_bytes_per_step": algo,
         "kernels_algorithmic_gbs": kern_gbs,
         "copy_gbs": copy_gbs,
+        "read_gbs": read_gbs,
     }
     # The dominant kernel's roofline on its own design's bytes, and on the
     # scan bytes the method's description gives (16 B per candidate for the
     # test pass plus 12 B per query: the coordinates of every candidate), for
     # comparison; the latter can exceed 1 because the kernel decides most
     # candidates from their 8-byte grid cell and never reads those bytes.
+    # Beside them, the kernel's counted bytes over the same time (when the
+    # counters match its current source) and the rates of a plain read-only
+    # stream and a plain copy measured in this run.
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "bytes_per_launch": bytes_per_launch, "copy_gbs": copy_gbs}
+                "traffic_gbs": (traffic / (d_ms / d_launch * 1e-3) / 1e9) if traffic else None,
+                "bytes_per_launch": bytes_per_launch, "read_gbs": read_gbs, "copy_gbs": copy_gbs}
     if dom == "compact_test":
         survey_bytes = (16 * cand + 12 * m) / launches_per_step
         roofline["frac_16B_per_candidate"] = (survey_bytes / (d_ms / d_launch * 1e-3) / 1e9

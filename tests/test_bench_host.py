@@ -75,7 +75,8 @@ def test_headline_is_compact_and_complete():
         "reported_pts_per_s": 6e10, "candidates_per_report": 2.14, "build_ms_per_step": 0.87,
         "roofline": {"bound": "hbm", "kernel": "compact_test", "achieved": 4430.123456,
                      "peak": 8000.0, "unit": "GB/s", "frac": 0.5537, "traffic": 3.48e9,
-                     "bytes_per_launch": 3.1e9, "copy_gbs": 4993.0,
+                     "traffic_gbs": 6312.0, "bytes_per_launch": 3.1e9, "read_gbs": 6034.0,
+                     "copy_gbs": 4993.0,
                      "frac_16B_per_candidate": 1.05},
         "learned_vs_bsearch": lvb,
         "learned_large": {"n": 1 << 26, "m": 1 << 22, "learned": {"search_ms": 0.9,
