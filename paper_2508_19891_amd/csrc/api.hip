@@ -203,7 +203,7 @@ struct sfc_index {
   int search = SFC_SEARCH_BINARY;
   int refine = 0;
   int metric = SFC_METRIC_L2;   // exact test of the query batches
-  uint32_t refine_min = 32;
+  uint32_t refine_min = 64;   // a cell with more points is refined (measured best of 8 to 128)
   hipStream_t stream = nullptr;
   sfc::Allocator alloc;
   uint64_t n = 0;

@@ -1,6 +1,6 @@
 """The refined ranges report exactly the method's results.
 
-Crowded cells (more than 32 points) are split two levels down and their
+Crowded cells (more than 64 points) are split two levels down and their
 sub-cells kept when they meet the widened box and, for the Euclidean metric,
 the disc (with a relative margin of 2^-40 on the squared distance).  Checked
 against the oracle with every cell crowded: a dense background plus points
@@ -80,7 +80,7 @@ def test_tiny_radii_keep_every_sub_cell(curve):
     are split."""
     rng = np.random.default_rng(3 + curve)
     q = rng.uniform(0.2, 0.8, (8, 2))
-    pts = np.concatenate([np.repeat(q, 50, axis=0), rng.random((50_000, 2))])
+    pts = np.concatenate([np.repeat(q, 100, axis=0), rng.random((50_000, 2))])
     ds = np.array([0.0, 2.0 ** -401, 2.0 ** -400, 2.0 ** -399, 1e-300, 2.0 ** -40, 2.0 ** -33,
                    2.0 ** -31])
     want = expect(pts, q, ds, curve, L2)
