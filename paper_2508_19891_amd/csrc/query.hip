@@ -958,7 +958,7 @@ __global__ __launch_bounds__(256) void compact_test(
 // tile's last row is the next tile's first, and the one at the batch's last
 // row + 1 is the total).  Output-driven: one lane per reported id rather than
 // one per candidate.  The waves first map every output o of the tile to its
-// row and its candidate within the row (two byte maps in LDS, written by the
+// row and its candidate within the row (one 16-bit map in LDS, written by the
 // lanes whose bit is set); the output's id is then read at the row's first
 // candidate position plus that candidate.  Writes are contiguous; a tile
 // with few hits costs few lanes.
@@ -970,8 +970,8 @@ __global__ __launch_bounds__(256) void compact_write_out(
   __shared__ uint64_t s_mask[kTileRows];
   __shared__ uint32_t s_pre[kTileRows + 1];
   __shared__ uint32_t s_base[kTileRows];
-  __shared__ uint8_t s_row[kTileRows * 64];   // output o of the tile: its row
-  __shared__ uint8_t s_bit[kTileRows * 64];   // and its candidate within the row
+  // Output o of the tile: its row << 8 | its candidate within the row.
+  __shared__ uint16_t s_map[kTileRows * 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint64_t below = lanemask_lt();
   const uint64_t total_all = *total_rows_dev;
@@ -1025,14 +1025,13 @@ __global__ __launch_bounds__(256) void compact_write_out(
         const uint64_t mk = s_mask[r];
         if ((mk >> lane) & 1ull) {
           const uint32_t o = s_pre[r] + (uint32_t)__popcll(mk & below);
-          s_row[o] = (uint8_t)r;
-          s_bit[o] = (uint8_t)lane;
+          s_map[o] = (uint16_t)((r << 8) | lane);
         }
       }
       __syncthreads();
       for (uint32_t o = tid; o < hits; o += 256) {
-        const uint32_t r = s_row[o];
-        const uint64_t p64 = (uint64_t)s_base[r] + s_bit[o];
+        const uint32_t mp = s_map[o];
+        const uint64_t p64 = (uint64_t)s_base[mp >> 8] + (mp & 0xFFu);
         const uint64_t opos = prefix + o;
         if (p64 < npts && opos < cap) out_ids[opos] = ids[p64];
       }
